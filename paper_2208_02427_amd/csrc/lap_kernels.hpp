@@ -1,0 +1,187 @@
+// Internal interface between the liblap runtime and its gfx950 kernels.
+//
+// Data layout of a field on one level: element (i, j) at ptr[j * P + i] with
+// the pitch P a multiple of 64 elements and the base 256-byte aligned; the
+// perimeter (i = 0, m-1 or j = 0, n-1) holds Dirichlet data (zero on coarse
+// levels and for corrections).  Columns m..P-1 are padding.
+//
+// Stencil kernels are "streaming-window" kernels: one 64-lane wavefront owns
+// a window of 64*V consecutive columns (V per lane, one vector load per lane
+// and row) and a chunk of `ty` rows, marches down the chunk keeping a few
+// rows in registers, and exchanges the left/right neighbours of its lanes
+// with cross-lane shuffles.  Windows overlap by 4 columns (2 halo columns on
+// each side), so a wave needs no LDS and no barrier; the overlap re-reads
+// hit L2.  All kernels are out of place, so a wave's halo rows are never
+// being written by a neighbour.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lap {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kXcds = 8;          // MI355X: workgroups are dealt round-robin over 8 XCDs
+
+// Window geometry for V columns per lane: step between windows and the left
+// offset of window 0 (keeps every vector load V-aligned).
+__host__ __device__ constexpr int win_step(int V) { return 64 * V - 4; }
+__host__ __device__ constexpr int win_left(int V) { return V <= 2 ? 2 : V; }
+
+struct Tiling {
+    int V = 2;       // columns per lane
+    int ty = 64;     // rows per chunk (even)
+    int nwin = 0;    // windows across
+    int nchunk = 0;  // chunks down
+    int ntiles = 0;  // nwin * nchunk (one wavefront each)
+};
+
+inline Tiling make_tiling(int m, int n, int V, int ty) {
+    Tiling t;
+    t.V = V;
+    t.ty = ty;
+    const int S = win_step(V), H = win_left(V);
+    // outputs of window w: columns [w*S - H + 2, w*S - H + 64V - 2); need to reach m-2
+    int nw = 1;
+    while ((nw - 1) * S - H + 64 * V - 3 < m - 2) ++nw;
+    t.nwin = nw;
+    t.nchunk = (n - 2 + ty - 1) / ty;
+    if (t.nchunk < 1) t.nchunk = 1;
+    t.ntiles = t.nwin * t.nchunk;
+    return t;
+}
+
+// Blocks of 4 waves; the grid is padded to a multiple of the XCD count so
+// the XCD-aware remap below is a bijection.
+inline int blocks_for(const Tiling& t) {
+    int nb = (t.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    return ((nb + kXcds - 1) / kXcds) * kXcds;
+}
+
+// Kernel-side control block of one solve (device memory).
+struct Ctrl {
+    double r0;          // ||r_0||_2 of this solve
+    double rel;         // last ||r||_2 / r0
+    double res_l2;      // last ||r||_2
+    double res_inf;     // last max|r|
+    double tol;         // stopping tolerance
+    int32_t stop;       // 0: rel l2, 1: max-abs
+    int32_t max_iter;
+    int32_t iters;      // iterations completed on the iterate that was last tested
+    int32_t checks;     // number of norm finalisations so far in this solve
+    int32_t done;       // nonzero: stop; every kernel of the solve becomes a no-op
+    int32_t status;     // lap_status when done
+    int32_t step;       // iterations between two tests (SOR / ADI check interval)
+    int32_t pad;
+};
+
+// Flags of the red-black sweep.
+enum : int {
+    SW_F = 1,        // source / right-hand side present
+    SW_ZERO = 2,     // input is identically zero (u_in ignored)
+    SW_PROLONG = 4,  // input is u_in + P(ec)
+    SW_NORM = 8,     // accumulate residual norms of the input into partials
+};
+
+template <typename T>
+struct SweepArgs {
+    const T* uin;
+    T* uout;
+    const T* f;
+    const T* ec;        // coarse correction (SW_PROLONG)
+    double* partials;   // 2 doubles per tile (SW_NORM)
+    const Ctrl* ctrl;   // nullable: kernel returns at once if ctrl->done
+    int m, n, P;
+    int mc, nc, Pc;
+    T cx, cy, d, inv_d, omega;
+    Tiling tl;
+};
+
+template <typename T>
+struct RestrictArgs {
+    const T* u;
+    const T* f;
+    T* bc;
+    const Ctrl* ctrl;
+    int m, n, P;
+    int mc, nc, Pc;
+    T cx, cy, d;
+    Tiling tl;
+};
+
+template <typename T>
+struct ResidualArgs {
+    const T* u;
+    const T* f;
+    T* r;               // nullable
+    double* partials;   // nullable
+    const Ctrl* ctrl;
+    int m, n, P;
+    T cx, cy, d;
+    Tiling tl;
+};
+
+// FP64 defect correction: psi_out = psi_in + e (e nullable), r = f - L psi_out,
+// rhs = fl32(r) on the interior, norms of r.
+struct DefectArgs {
+    const double* psi_in;
+    double* psi_out;
+    const float* e;
+    const double* f;
+    float* rhs;
+    double* partials;
+    const Ctrl* ctrl;
+    int m, n, P;
+    double cx, cy, d;
+    Tiling tl;
+};
+
+template <typename T>
+struct CoarseArgs {
+    const T* u;         // boundary source (level 0) or nullptr (zero boundary)
+    const T* b;         // right-hand side (nullable = 0)
+    T* out;             // solution (interior written)
+    const double* minv; // (N x N) inverse of L_h on the interior unknowns, FP64, symmetric
+    const Ctrl* ctrl;
+    int m, n, P;
+    double cx, cy;
+};
+
+// ---- launchers (stencil_kernels.hip) ----
+template <typename T> hipError_t launch_sweep(const SweepArgs<T>& a, int flags, hipStream_t s);
+template <typename T> hipError_t launch_restrict(const RestrictArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_residual(const ResidualArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s);
+hipError_t launch_defect(const DefectArgs& a, hipStream_t s);
+// Sum the per-tile partials in a fixed order and run the stopping test.
+// mode 0: stopping test of a solve; mode 1: write norms only (out2 = {sum, max}).
+hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, double* out2, int mode,
+                           hipStream_t s);
+// Reset a control block for a new solve (stream-ordered, graph-safe).
+hipError_t launch_ctrl_init(Ctrl* ctrl, double tol, int stop, int max_iter, int step, hipStream_t s);
+// Gather the control blocks of a batch of grids into one array.
+hipError_t launch_gather_ctrl(Ctrl* const* src, Ctrl* dst, int count, hipStream_t s);
+// Copy interior of src into dst (FP64 fields of the same layout).
+hipError_t launch_copy(const double* src, double* dst, int m, int n, int P, const Ctrl* ctrl,
+                       hipStream_t s);
+
+// ---- ADI (adi_kernels.hip) ----
+struct LineArgs {
+    double* u;               // in place
+    const double* f;         // nullable
+    double* scratch;         // forward-sweep values, same layout as u
+    const double* cprime;    // c'_k of the constant-coefficient factorisation, k = 0..K-1
+    const double* piv;       // pivot_k (piv_0 = d)
+    const Ctrl* ctrl;
+    int m, n, P;
+    double cx, cy, d, omega;
+    double a_off;            // off-diagonal of the line matrix (-cx or -w cx, rows; -cy.. cols)
+    int form;                // 0 relax after, 1 relax inside
+    int parity;              // 1: odd lines, 0: even lines
+};
+hipError_t launch_adi_rows(const LineArgs& a, hipStream_t s);
+hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s);
+
+}  // namespace lap

@@ -1,0 +1,1574 @@
+// liblap runtime: device arena, grid hierarchies, solve drivers, hipGraph
+// replay of multigrid cycles, kernel timing, and the C ABI of include/lap.h.
+//
+// Stopping is decided on the device: the norm kernels feed a one-block
+// finalise kernel that updates a control block (Ctrl) and sets `done`; every
+// later kernel of the solve reads `done` first and exits at once.  The host
+// therefore enqueues cycles ahead and only polls the control block (copied
+// to pinned memory after each cycle) one cycle behind.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "lap_kernels.hpp"
+#include "../../include/lap.h"
+
+using namespace lap;
+
+// ====================================================================== errors
+namespace {
+thread_local std::string g_err;
+
+lap_status fail(lap_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(LAP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define HIPERR(expr)                              \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return e_;          \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int pitch_of(int m) { return (int)round_up((size_t)m, 64); }
+
+// ======================================================================= arena
+// First-fit sub-allocator over the caller's device buffer; adjacent free
+// blocks are merged on release.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> bytes
+    std::map<size_t, size_t> used_;   // offset -> bytes
+    size_t in_use = 0;
+
+    void init(void* p, size_t bytes) {
+        base = (char*)p;
+        size = bytes / kAlign * kAlign;
+        free_.clear();
+        used_.clear();
+        free_[0] = size;
+        in_use = 0;
+    }
+    void* alloc(size_t bytes) {
+        bytes = round_up(std::max<size_t>(bytes, 1), kAlign);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, sz = it->second;
+                free_.erase(it);
+                if (sz > bytes) free_[off + bytes] = sz - bytes;
+                used_[off] = bytes;
+                in_use += bytes;
+                return base + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(void* p) {
+        if (p == nullptr) return;
+        const size_t off = (size_t)((char*)p - base);
+        auto it = used_.find(off);
+        if (it == used_.end()) return;
+        size_t sz = it->second;
+        used_.erase(it);
+        in_use -= sz;
+        size_t start = off;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && nx->first == off + sz) {
+            sz += nx->second;
+            free_.erase(nx);
+        }
+        auto pv = free_.lower_bound(off);
+        if (pv != free_.begin()) {
+            --pv;
+            if (pv->first + pv->second == off) {
+                start = pv->first;
+                sz += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[start] = sz;
+    }
+    size_t largest_free() const {
+        size_t b = 0;
+        for (auto& kv : free_) b = std::max(b, kv.second);
+        return b;
+    }
+};
+
+struct LevelGeo {
+    int m, n, P;
+    double dx, dy;
+    size_t interior() const { return (size_t)(m - 2) * (size_t)(n - 2); }
+};
+
+template <typename T>
+struct LevelBufs {
+    T* u[2] = {nullptr, nullptr};
+    T* b = nullptr;
+};
+
+struct Coef {
+    double cx, cy, d, inv_d;
+};
+Coef coef(double dx, double dy) {
+    Coef c;
+    c.cx = 1.0 / (dx * dx);
+    c.cy = 1.0 / (dy * dy);
+    c.d = 2.0 * (c.cx + c.cy);
+    c.inv_d = 1.0 / c.d;
+    return c;
+}
+
+// Hierarchy plan: vertex coarsening while both sides are odd and stay >= 5.
+std::vector<LevelGeo> plan_levels(int m, int n, double dx, double dy) {
+    std::vector<LevelGeo> lv;
+    lv.push_back({m, n, pitch_of(m), dx, dy});
+    while (true) {
+        const LevelGeo& L = lv.back();
+        if ((L.m - 1) % 2 || (L.n - 1) % 2) break;
+        const int mc = (L.m - 1) / 2 + 1, nc = (L.n - 1) / 2 + 1;
+        if (mc < 5 || nc < 5) break;
+        lv.push_back({mc, nc, pitch_of(mc), 2.0 * L.dx, 2.0 * L.dy});
+    }
+    return lv;
+}
+
+// Inverse of L_h restricted to the interior unknowns (k = (j-1)(m-2)+(i-1))
+// of a small level, in FP64: Cholesky factorisation of the SPD matrix -L_h,
+// then column-by-column solves; returns L_h^{-1} = -(-L_h)^{-1}.
+bool coarse_inverse(int m, int n, double dx, double dy, std::vector<double>& out) {
+    const Coef c = coef(dx, dy);
+    const int mi = m - 2, ni = n - 2, N = mi * ni;
+    std::vector<double> A((size_t)N * N, 0.0);
+    for (int j = 0; j < ni; ++j)
+        for (int i = 0; i < mi; ++i) {
+            const int k = j * mi + i;
+            A[(size_t)k * N + k] = c.d;
+            if (i > 0) A[(size_t)k * N + k - 1] = -c.cx;
+            if (i < mi - 1) A[(size_t)k * N + k + 1] = -c.cx;
+            if (j > 0) A[(size_t)k * N + k - mi] = -c.cy;
+            if (j < ni - 1) A[(size_t)k * N + k + mi] = -c.cy;
+        }
+    // in-place Cholesky, lower triangle
+    for (int k = 0; k < N; ++k) {
+        double s = A[(size_t)k * N + k];
+        for (int p = 0; p < k; ++p) s -= A[(size_t)k * N + p] * A[(size_t)k * N + p];
+        if (!(s > 0.0)) return false;
+        const double lkk = std::sqrt(s);
+        A[(size_t)k * N + k] = lkk;
+        for (int r = k + 1; r < N; ++r) {
+            double t = A[(size_t)r * N + k];
+            for (int p = 0; p < k; ++p) t -= A[(size_t)r * N + p] * A[(size_t)k * N + p];
+            A[(size_t)r * N + k] = t / lkk;
+        }
+    }
+    out.assign((size_t)N * N, 0.0);
+    std::vector<double> y(N);
+    for (int col = 0; col < N; ++col) {
+        for (int r = 0; r < N; ++r) {
+            double t = (r == col) ? 1.0 : 0.0;
+            for (int p = 0; p < r; ++p) t -= A[(size_t)r * N + p] * y[p];
+            y[r] = t / A[(size_t)r * N + r];
+        }
+        for (int r = N - 1; r >= 0; --r) {
+            double t = y[r];
+            for (int p = r + 1; p < N; ++p) t -= A[(size_t)p * N + r] * y[p];
+            y[r] = t / A[(size_t)r * N + r];
+        }
+        for (int r = 0; r < N; ++r) out[(size_t)r * N + col] = -y[r];
+    }
+    return true;
+}
+
+enum KClass { KC_SWEEP = 0, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE,
+              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_COUNT };
+
+// Size classes for tilings, by interior node count.
+int size_class(size_t nint) {
+    if (nint < (1u << 14)) return 0;
+    if (nint < (1u << 18)) return 1;
+    if (nint < (1u << 22)) return 2;
+    return 3;
+}
+
+}  // namespace
+
+// ====================================================================== context
+struct lap_ctx {
+    Arena arena;
+    hipStream_t stream = nullptr;
+    bool timing = false;
+    struct Rec {
+        int cls;
+        bool fine;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    int64_t launches[KC_COUNT][2] = {};
+    double ms[KC_COUNT][2] = {};
+    double bytes[KC_COUNT][2] = {};
+    // tiling table: [size class][kernel class][dtype 0=f64,1=f32] -> (V, ty)
+    int tileV[4][KC_COUNT][2];
+    int tileTY[4][KC_COUNT][2];
+    std::vector<lap_grid*> grids;
+    std::map<std::string, std::vector<double>> inv_cache;
+    Ctrl* pinned = nullptr;        // 4 host slots
+    // batch readback: device pointer table, gathered control blocks, pinned copy
+    int batch_cap = 0;
+    Ctrl** batch_ptrs = nullptr;
+    Ctrl* batch_ctrl = nullptr;
+    Ctrl* batch_host = nullptr;
+    std::vector<Ctrl*> batch_ptrs_host;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+
+    hipEvent_t ev() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipError_t flush_recs() {
+        if (recs.empty()) return hipSuccess;
+        HIPERR(hipStreamSynchronize(stream));
+        for (auto& r : recs) {
+            float t = 0.f;
+            HIPERR(hipEventElapsedTime(&t, r.a, r.b));
+            for (int f = 0; f < 2; ++f) {
+                if (f == 1 && !r.fine) continue;
+                launches[r.cls][f] += 1;
+                ms[r.cls][f] += t;
+                bytes[r.cls][f] += r.bytes;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+        return hipSuccess;
+    }
+    template <typename F>
+    hipError_t timed(int cls, bool fine, double nbytes, F&& launch) {
+        if (!timing) return launch();
+        hipEvent_t a = ev(), b = ev();
+        if (a == nullptr || b == nullptr) return hipErrorOutOfMemory;
+        HIPERR(hipEventRecord(a, stream));
+        HIPERR(launch());
+        HIPERR(hipEventRecord(b, stream));
+        recs.push_back({cls, fine, nbytes, a, b});
+        if (recs.size() > 8192) return flush_recs();
+        return hipSuccess;
+    }
+    Tiling tiling(int m, int n, int cls, int dt) const {
+        const int sc = size_class((size_t)(m - 2) * (size_t)(n - 2));
+        return make_tiling(m, n, tileV[sc][cls][dt], tileTY[sc][cls][dt]);
+    }
+};
+
+// ========================================================================= grid
+struct lap_grid {
+    lap_ctx* ctx = nullptr;
+    int m = 0, n = 0, P = 0;
+    double dx = 0, dy = 0;
+    int flags = 0;
+    bool has_f = false;
+    std::vector<LevelGeo> geo;
+    double* psi[2] = {nullptr, nullptr};
+    double* f64 = nullptr;
+    std::vector<LevelBufs<double>> l64;
+    std::vector<LevelBufs<float>> l32;
+    double* minv = nullptr;
+    double* adi_scratch = nullptr;
+    double* adi_tab = nullptr;       // rows cprime, rows piv, cols cprime, cols piv (each maxK)
+    int adi_maxk = 0;
+    std::vector<double> adi_host;
+    Ctrl* ctrl = nullptr;
+    double* partials = nullptr;
+    int max_partials = 0;
+    double* norm_out = nullptr;
+    double last_r0 = -1.0;
+    double tol = 1e-10;
+    bool batch_started = false;
+    bool batch_done = false;
+    double batch_t0 = 0.0;
+    int step_idx = 0;                // next outer step of the running solve
+    int e_idx = 0;                   // buffer of the last FP32 correction (mixed)
+    lap_opts batch_opts{};
+    // graph cache
+    hipGraphExec_t graph = nullptr;
+    std::string graph_key;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+void* galloc(lap_grid* g, size_t bytes) {
+    void* p = g->ctx->arena.alloc(bytes);
+    if (p) g->allocs.push_back(p);
+    return p;
+}
+
+struct Footprint {
+    size_t bytes = 0;
+    void add(size_t b) { bytes += round_up(std::max<size_t>(b, 1), kAlign); }
+};
+
+size_t max_tiles(int m, int n) {
+    // the finest tiling any table entry may pick: V = 1, ty = 16
+    const Tiling t = make_tiling(m, n, 1, 16);
+    return (size_t)t.ntiles;
+}
+
+// Mirrors the allocations of lap_grid_create_ex.
+Footprint footprint(int m, int n, bool has_f, int flags) {
+    Footprint fp;
+    const auto lv = plan_levels(m, n, 1.0, 1.0);
+    const LevelGeo& L0 = lv[0];
+    const size_t f0 = (size_t)L0.n * L0.P;
+    fp.add(f0 * 8);
+    fp.add(f0 * 8);
+    if (has_f) fp.add(f0 * 8);
+    if (flags & LAP_ALLOC_FP64)
+        for (size_t l = 1; l < lv.size(); ++l)
+            for (int k = 0; k < 3; ++k) fp.add((size_t)lv[l].n * lv[l].P * 8);
+    if (flags & LAP_ALLOC_MIXED)
+        for (size_t l = 0; l < lv.size(); ++l)
+            for (int k = 0; k < 3; ++k) fp.add((size_t)lv[l].n * lv[l].P * 4);
+    if (flags & (LAP_ALLOC_FP64 | LAP_ALLOC_MIXED)) {
+        const size_t N = (size_t)(lv.back().m - 2) * (lv.back().n - 2);
+        fp.add(N * N * 8);
+    }
+    if (flags & LAP_ALLOC_ADI) {
+        fp.add(f0 * 8);
+        fp.add((size_t)4 * std::max(m, n) * 8);
+    }
+    fp.add(sizeof(Ctrl));
+    fp.add(max_tiles(m, n) * 16);
+    fp.add(16);
+    return fp;
+}
+
+lap_status check_ptr(const void* p, const char* what) {
+    if (p == nullptr) return fail(LAP_EINVAL, std::string(what) + " is NULL");
+    return LAP_OK;
+}
+
+// ------------------------------------------------------------- kernel enqueue
+double nint(const LevelGeo& L) { return (double)L.interior(); }
+
+template <typename T>
+struct HierView {
+    std::vector<T*> u0, u1, b;
+    bool zero_start0 = false;  // level 0 starts from zero (error equation) or holds the iterate
+};
+
+template <typename T> constexpr int dt_of() { return sizeof(T) == 8 ? 0 : 1; }
+
+template <typename T>
+SweepArgs<T> sweep_args(lap_grid* g, int l, const T* in, T* out, const T* f, const T* ec, double omega,
+                        bool norm) {
+    const LevelGeo& L = g->geo[l];
+    const Coef c = coef(L.dx, L.dy);
+    SweepArgs<T> a{};
+    a.uin = in;
+    a.uout = out;
+    a.f = f;
+    a.ec = ec;
+    a.partials = norm ? g->partials : nullptr;
+    a.ctrl = g->ctrl;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    if ((size_t)l + 1 < g->geo.size()) {
+        a.mc = g->geo[l + 1].m;
+        a.nc = g->geo[l + 1].n;
+        a.Pc = g->geo[l + 1].P;
+    }
+    a.cx = (T)c.cx;
+    a.cy = (T)c.cy;
+    a.d = (T)c.d;
+    a.inv_d = (T)c.inv_d;
+    a.omega = (T)omega;
+    a.tl = g->ctx->tiling(L.m, L.n, ec ? KC_SWEEP_PROLONG : KC_SWEEP, dt_of<T>());
+    return a;
+}
+
+template <typename T>
+hipError_t enq_sweep(lap_grid* g, int l, const T* in, T* out, const T* f, const T* ec, double omega, int flags) {
+    SweepArgs<T> a = sweep_args<T>(g, l, in, out, f, ec, omega, (flags & SW_NORM) != 0);
+    const LevelGeo& L = g->geo[l];
+    double per = (flags & SW_ZERO) ? 1.0 : 2.0;
+    if (flags & SW_F) per += 1.0;
+    if (flags & SW_PROLONG) per += 0.25;
+    const int cls = (flags & SW_PROLONG) ? KC_SWEEP_PROLONG : KC_SWEEP;
+    return g->ctx->timed(cls, l == 0, per * sizeof(T) * nint(L),
+                         [&]() { return launch_sweep<T>(a, flags, g->ctx->stream); });
+}
+
+hipError_t enq_finalize(lap_grid* g, int ntiles) {
+    return g->ctx->timed(KC_FINALIZE, false, 16.0 * ntiles, [&]() {
+        return launch_finalize(g->partials, ntiles, g->ctrl, nullptr, 0, g->ctx->stream);
+    });
+}
+
+template <typename T>
+hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc) {
+    const LevelGeo& L = g->geo[l];
+    const LevelGeo& C = g->geo[l + 1];
+    const Coef c = coef(L.dx, L.dy);
+    RestrictArgs<T> a{};
+    a.u = u;
+    a.f = f;
+    a.bc = bc;
+    a.ctrl = g->ctrl;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    a.mc = C.m;
+    a.nc = C.n;
+    a.Pc = C.P;
+    a.cx = (T)c.cx;
+    a.cy = (T)c.cy;
+    a.d = (T)c.d;
+    a.tl = g->ctx->tiling(L.m, L.n, KC_RESTRICT, dt_of<T>());
+    const double per = (u ? 1.0 : 0.0) + (f ? 1.0 : 0.0) + 0.25;
+    return g->ctx->timed(KC_RESTRICT, l == 0, per * sizeof(T) * nint(L),
+                         [&]() { return launch_restrict<T>(a, g->ctx->stream); });
+}
+
+template <typename T>
+hipError_t enq_coarse(lap_grid* g, int l, const T* ubnd, const T* b, T* out) {
+    const LevelGeo& L = g->geo[l];
+    const Coef c = coef(L.dx, L.dy);
+    CoarseArgs<T> a{};
+    a.u = ubnd;
+    a.b = b;
+    a.out = out;
+    a.minv = g->minv;
+    a.ctrl = g->ctrl;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    a.cx = c.cx;
+    a.cy = c.cy;
+    return g->ctx->timed(KC_COARSE, l == 0, 2.0 * sizeof(T) * nint(L),
+                         [&]() { return launch_coarse<T>(a, g->ctx->stream); });
+}
+
+template <typename T>
+hipError_t enq_residual_norm(lap_grid* g, int l, const T* u, const T* f) {
+    const LevelGeo& L = g->geo[l];
+    const Coef c = coef(L.dx, L.dy);
+    ResidualArgs<T> a{};
+    a.u = u;
+    a.f = f;
+    a.r = nullptr;
+    a.partials = g->partials;
+    a.ctrl = g->ctrl;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    a.cx = (T)c.cx;
+    a.cy = (T)c.cy;
+    a.d = (T)c.d;
+    a.tl = g->ctx->tiling(L.m, L.n, KC_RESIDUAL, dt_of<T>());
+    HIPERR(g->ctx->timed(KC_RESIDUAL, l == 0, (f ? 2.0 : 1.0) * sizeof(T) * nint(L),
+                         [&]() { return launch_residual<T>(a, g->ctx->stream); }));
+    return enq_finalize(g, a.tl.ntiles);
+}
+
+// One V-cycle on level l of hierarchy H.  Level 0 either holds the iterate in
+// u0[0] (FP64 multigrid: the result returns to u0[0] since nu1+nu2 is even)
+// or starts from zero (error equation).  Returns the buffer index (0/1)
+// that holds the level's result.
+template <typename T>
+hipError_t enq_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm, int& res_idx) {
+    const int L = (int)g->geo.size();
+    const bool zero_start = (l > 0) || H.zero_start0;
+    T* U[2] = {H.u0[l], H.u1[l]};
+    const T* b = H.b[l];
+    if (l == L - 1) {
+        if (norm && !zero_start) HIPERR(enq_residual_norm<T>(g, l, U[0], b));
+        HIPERR(enq_coarse<T>(g, l, zero_start ? nullptr : U[0], b, U[0]));
+        res_idx = 0;
+        return hipSuccess;
+    }
+    const int fb = b ? SW_F : 0;
+    int cur = 0;
+    bool have_u = !zero_start;
+    if (norm && !zero_start && o.nu1 == 0) HIPERR(enq_residual_norm<T>(g, l, U[0], b));
+    for (int k = 0; k < o.nu1; ++k) {
+        if (!have_u) {
+            HIPERR(enq_sweep<T>(g, l, nullptr, U[0], b, nullptr, o.omega, SW_ZERO | fb));
+            cur = 0;
+            have_u = true;
+        } else {
+            const bool nk = norm && !zero_start && k == 0;
+            HIPERR(enq_sweep<T>(g, l, U[cur], U[1 - cur], b, nullptr, o.omega, fb | (nk ? SW_NORM : 0)));
+            if (nk) HIPERR(enq_finalize(g, g->ctx->tiling(g->geo[l].m, g->geo[l].n, KC_SWEEP, dt_of<T>()).ntiles));
+            cur = 1 - cur;
+        }
+    }
+    HIPERR(enq_restrict<T>(g, l, have_u ? U[cur] : nullptr, b, H.b[l + 1]));
+    int cres = 0;
+    HIPERR(enq_vcycle<T>(g, H, l + 1, o, false, cres));
+    const T* ec = (cres == 0 ? H.u0[l + 1] : H.u1[l + 1]);
+    for (int k = 0; k < o.nu2; ++k) {
+        if (k == 0) {
+            HIPERR(enq_sweep<T>(g, l, have_u ? U[cur] : nullptr, U[have_u ? 1 - cur : 0], b, ec, o.omega,
+                                SW_PROLONG | fb));
+            cur = have_u ? 1 - cur : 0;
+            have_u = true;
+        } else {
+            HIPERR(enq_sweep<T>(g, l, U[cur], U[1 - cur], b, nullptr, o.omega, fb));
+            cur = 1 - cur;
+        }
+    }
+    res_idx = cur;
+    return hipSuccess;
+}
+
+HierView<double> view64(lap_grid* g) {
+    HierView<double> H;
+    const int L = (int)g->geo.size();
+    H.u0.resize(L);
+    H.u1.resize(L);
+    H.b.resize(L);
+    H.u0[0] = g->psi[0];
+    H.u1[0] = g->psi[1];
+    H.b[0] = g->f64;
+    for (int l = 1; l < L; ++l) {
+        H.u0[l] = g->l64[l].u[0];
+        H.u1[l] = g->l64[l].u[1];
+        H.b[l] = g->l64[l].b;
+    }
+    H.zero_start0 = false;
+    return H;
+}
+
+HierView<float> view32(lap_grid* g) {
+    HierView<float> H;
+    const int L = (int)g->geo.size();
+    H.u0.resize(L);
+    H.u1.resize(L);
+    H.b.resize(L);
+    for (int l = 0; l < L; ++l) {
+        H.u0[l] = g->l32[l].u[0];
+        H.u1[l] = g->l32[l].u[1];
+        H.b[l] = g->l32[l].b;
+    }
+    H.zero_start0 = true;
+    return H;
+}
+
+hipError_t enq_defect(lap_grid* g, int in_idx, const float* e) {
+    const LevelGeo& L = g->geo[0];
+    const Coef c = coef(L.dx, L.dy);
+    DefectArgs a{};
+    a.psi_in = g->psi[in_idx];
+    a.psi_out = g->psi[1 - in_idx];
+    a.e = e;
+    a.f = g->f64;
+    a.rhs = g->l32[0].b;
+    a.partials = g->partials;
+    a.ctrl = g->ctrl;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    a.cx = c.cx;
+    a.cy = c.cy;
+    a.d = c.d;
+    a.tl = g->ctx->tiling(L.m, L.n, KC_DEFECT, 0);
+    const double per = 8.0 + (e ? 4.0 : 0.0) + (g->f64 ? 8.0 : 0.0) + 8.0 + 4.0;
+    HIPERR(g->ctx->timed(KC_DEFECT, true, per * nint(L), [&]() { return launch_defect(a, g->ctx->stream); }));
+    return enq_finalize(g, a.tl.ntiles);
+}
+
+// Buffer (0/1) in which a zero-start V-cycle leaves its level result.
+int vcycle_result_index(const lap_opts& o) {
+    const int pre = o.nu1 >= 1 ? o.nu1 : 0;   // first pre-sweep writes buffer 0, each further one flips
+    const int flips = (pre >= 1 ? pre - 1 + 1 : 0) + (o.nu2 - 1);
+    return flips % 2;
+}
+
+// One outer step of the mixed loop: defect correction (adds the previous
+// FP32 correction, forms the FP64 residual, tests it), then one FP32
+// V-cycle on the error equation.
+hipError_t enq_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int& e_idx) {
+    const float* e = first ? nullptr : (e_idx == 0 ? g->l32[0].u[0] : g->l32[0].u[1]);
+    HIPERR(enq_defect(g, in_idx, e));
+    HierView<float> H = view32(g);
+    return enq_vcycle<float>(g, H, 0, o, false, e_idx);
+}
+
+// ------------------------------------------------------------------ ADI
+void adi_factor(double b, double a, double c, int K, double* cp, double* piv) {
+    if (K <= 0) return;
+    cp[0] = c / b;
+    piv[0] = b;
+    for (int k = 1; k < K; ++k) {
+        piv[k] = b - a * cp[k - 1];
+        cp[k] = c / piv[k];
+    }
+}
+
+hipError_t enq_adi_iteration(lap_grid* g, const lap_opts& o) {
+    const LevelGeo& L = g->geo[0];
+    const Coef c = coef(L.dx, L.dy);
+    const int mk = g->adi_maxk;
+    LineArgs a{};
+    a.u = g->psi[0];
+    a.f = g->f64;
+    a.scratch = g->adi_scratch;
+    a.ctrl = g->ctrl;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    a.cx = c.cx;
+    a.cy = c.cy;
+    a.d = c.d;
+    a.omega = o.omega;
+    a.form = o.adi_form;
+    const double per = (g->f64 ? 48.0 : 40.0) * 0.5 * nint(L);
+    a.cprime = g->adi_tab;
+    a.piv = g->adi_tab + mk;
+    a.a_off = o.adi_form == 0 ? -c.cx : -o.omega * c.cx;
+    for (int par : {1, 0}) {
+        a.parity = par;
+        HIPERR(g->ctx->timed(KC_ADI_ROWS, true, per, [&]() { return launch_adi_rows(a, g->ctx->stream); }));
+    }
+    a.cprime = g->adi_tab + 2 * mk;
+    a.piv = g->adi_tab + 3 * mk;
+    a.a_off = o.adi_form == 0 ? -c.cy : -o.omega * c.cy;
+    for (int par : {1, 0}) {
+        a.parity = par;
+        HIPERR(g->ctx->timed(KC_ADI_COLS, true, per, [&]() { return launch_adi_cols(a, g->ctx->stream); }));
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------- driver
+lap_status init_ctrl(lap_grid* g, const lap_opts& o, int step) {
+    HIPCHK(launch_ctrl_init(g->ctrl, o.tol, o.stop, o.max_iter, step, g->ctx->stream));
+    return LAP_OK;
+}
+
+// Enqueue steps until the device says done; poll one step behind.
+lap_status drive(lap_grid* g, int max_steps, const std::function<hipError_t(int)>& step, Ctrl& out) {
+    lap_ctx* c = g->ctx;
+    int polled = -1;
+    for (int s = 0; s < max_steps; ++s) {
+        hipError_t e = step(s);
+        if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+        HIPCHK(hipMemcpyAsync(&c->pinned[s & 1], g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipEventRecord(c->poll_ev[s & 1], c->stream));
+        if (s >= 1) {
+            HIPCHK(hipEventSynchronize(c->poll_ev[(s - 1) & 1]));
+            polled = s - 1;
+            if (c->pinned[(s - 1) & 1].done) break;
+        }
+    }
+    (void)polled;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(&c->pinned[2], g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    out = c->pinned[2];
+    return LAP_OK;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+lap_status finish(lap_grid* g, const lap_opts& o, const Ctrl& h, double t0, lap_info* info) {
+    lap_status st = (lap_status)h.status;
+    if (!h.done) st = LAP_ENOTCONV;
+    if (o.tol <= 0.0 && st == LAP_ENOTCONV) st = LAP_OK;
+    g->last_r0 = h.r0;
+    if (info) {
+        info->iterations = h.iters;
+        info->status = st;
+        info->rel_res_l2 = h.rel;
+        info->res_l2 = h.res_l2;
+        info->res_linf = h.res_inf;
+        info->res0_l2 = h.r0;
+        info->seconds = now_s() - t0;
+    }
+    if (st == LAP_ENOTCONV) g_err = "max_iter reached before the stopping rule held";
+    if (st == LAP_EDIVERGED) g_err = "residual diverged (NaN/Inf or growth by 1e6)";
+    return st;
+}
+
+lap_status validate_opts(lap_grid* g, const lap_opts& o) {
+    if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(LAP_EINVAL, "omega must lie in (0, 2)");
+    if (o.max_iter < 0) return fail(LAP_EINVAL, "max_iter must be >= 0");
+    if (!(o.tol >= 0.0)) return fail(LAP_EINVAL, "tol must be >= 0");
+    if (o.stop != LAP_STOP_REL_L2 && o.stop != LAP_STOP_RES_INF) return fail(LAP_EINVAL, "unknown stopping rule");
+    if (o.method != LAP_SOR_RB && o.method != LAP_ADI && o.method != LAP_MG)
+        return fail(LAP_EINVAL, "unknown method");
+    if (o.precision != LAP_FP64 && o.precision != LAP_MIXED) return fail(LAP_EINVAL, "unknown precision");
+    if (o.precision == LAP_MIXED && o.method != LAP_MG) return fail(LAP_EINVAL, "LAP_MIXED needs LAP_MG");
+    if (o.method == LAP_MG) {
+        if (o.nu1 < 0 || o.nu2 < 1) return fail(LAP_EINVAL, "multigrid needs nu1 >= 0 and nu2 >= 1");
+        if ((o.nu1 + o.nu2) % 2) return fail(LAP_EINVAL, "multigrid needs nu1 + nu2 even");
+        if (o.precision == LAP_FP64 && !(g->flags & LAP_ALLOC_FP64)) return fail(LAP_EINVAL, "grid has no FP64 hierarchy");
+        if (o.precision == LAP_MIXED && !(g->flags & LAP_ALLOC_MIXED)) return fail(LAP_EINVAL, "grid has no mixed hierarchy");
+    }
+    if (o.method == LAP_ADI) {
+        if (!(g->flags & LAP_ALLOC_ADI)) return fail(LAP_EINVAL, "grid has no ADI scratch");
+        if (o.adi_form != 0 && o.adi_form != 1) return fail(LAP_EINVAL, "unknown ADI form");
+        if (o.adi_form == 1) {
+            const Coef c = coef(g->dx, g->dy);
+            if (o.omega >= 1.0 + std::min(c.cy / c.cx, c.cx / c.cy))
+                return fail(LAP_EINVAL, "relaxation inside the line system needs omega < 1 + beta^2 in both directions");
+        }
+    }
+    if (o.check_every < 1) return fail(LAP_EINVAL, "check_every must be >= 1");
+    return LAP_OK;
+}
+
+// ------------------------------------------------------------------ methods
+// Every method is (prepare, step, fixup): prepare resets the control block
+// and builds per-solve tables / graphs; step s enqueues one outer iteration
+// whose first kernels test the current iterate; fixup moves the tested
+// iterate (the solution) into psi[0] once the device reports done.
+
+int max_steps(const lap_opts& o) {
+    switch (o.method) {
+        case LAP_MG: return o.max_iter + 1;
+        default: return (o.max_iter + o.check_every - 1) / o.check_every + 1;
+    }
+}
+
+hipError_t capture(lap_grid* g, const char* key, const std::function<hipError_t()>& body) {
+    lap_ctx* c = g->ctx;
+    if (g->graph != nullptr && g->graph_key == key) return hipSuccess;
+    if (g->graph) {
+        HIPERR(hipGraphExecDestroy(g->graph));
+        g->graph = nullptr;
+    }
+    HIPERR(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = body();
+    hipGraph_t tmp = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->stream, &tmp);
+    if (e != hipSuccess) return e;
+    if (e2 != hipSuccess) return e2;
+    e = hipGraphInstantiate(&g->graph, tmp, nullptr, nullptr, 0);
+    hipGraphDestroy(tmp);
+    if (e == hipSuccess) g->graph_key = key;
+    return e;
+}
+
+bool use_graph(lap_grid* g, const lap_opts& o) {
+    return o.use_graph && g->ctx->stream != nullptr && !g->ctx->timing && o.method == LAP_MG;
+}
+
+lap_status prepare(lap_grid* g, const lap_opts& o) {
+    const int step = (o.method == LAP_MG) ? 1 : o.check_every;
+    lap_status st = init_ctrl(g, o, step);
+    if (st != LAP_OK) return st;
+    g->step_idx = 0;
+    g->e_idx = vcycle_result_index(o);
+    if (o.method == LAP_ADI) {
+        const Coef c = coef(g->dx, g->dy);
+        const int mk = g->adi_maxk;
+        g->adi_host.assign((size_t)4 * mk, 0.0);
+        const double wx = o.adi_form == 0 ? c.cx : o.omega * c.cx;
+        const double wy = o.adi_form == 0 ? c.cy : o.omega * c.cy;
+        adi_factor(c.d, -wx, -wx, g->m - 2, g->adi_host.data(), g->adi_host.data() + mk);
+        adi_factor(c.d, -wy, -wy, g->n - 2, g->adi_host.data() + 2 * mk, g->adi_host.data() + 3 * mk);
+        HIPCHK(hipMemcpyAsync(g->adi_tab, g->adi_host.data(), (size_t)4 * mk * 8, hipMemcpyHostToDevice,
+                              g->ctx->stream));
+    }
+    if (use_graph(g, o)) {
+        char key[128];
+        hipError_t e;
+        if (o.precision == LAP_FP64) {
+            snprintf(key, sizeof key, "mg64:%d:%d:%.17g", o.nu1, o.nu2, o.omega);
+            e = capture(g, key, [&]() {
+                HierView<double> H = view64(g);
+                int ri = 0;
+                return enq_vcycle<double>(g, H, 0, o, true, ri);
+            });
+        } else {
+            // two outer steps (psi[1] -> psi[0] -> psi[1]); step 0 runs without the graph
+            snprintf(key, sizeof key, "mixed:%d:%d:%.17g", o.nu1, o.nu2, o.omega);
+            e = capture(g, key, [&]() {
+                int ei = vcycle_result_index(o);
+                HIPERR(enq_mixed_step(g, o, 1, false, ei));
+                return enq_mixed_step(g, o, 0, false, ei);
+            });
+        }
+        if (e != hipSuccess) return fail(LAP_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    return LAP_OK;
+}
+
+// Enqueue outer step number g->step_idx (then advance it).
+hipError_t step(lap_grid* g, const lap_opts& o) {
+    const int s = g->step_idx++;
+    lap_ctx* c = g->ctx;
+    const bool graph = use_graph(g, o);
+    switch (o.method) {
+        case LAP_MG:
+            if (o.precision == LAP_FP64) {
+                if (graph) return hipGraphLaunch(g->graph, c->stream);
+                HierView<double> H = view64(g);
+                int ri = 0;
+                return enq_vcycle<double>(g, H, 0, o, true, ri);
+            } else {
+                // step s reads psi[s % 2]; the graph covers the pair (odd s, even s)
+                if (s == 0) return enq_mixed_step(g, o, 0, true, g->e_idx);
+                if (graph) {
+                    if (s % 2 == 1) {
+                        g->step_idx++;   // the graph also runs step s + 1
+                        return hipGraphLaunch(g->graph, c->stream);
+                    }
+                }
+                return enq_mixed_step(g, o, s % 2, false, g->e_idx);
+            }
+        case LAP_SOR_RB: {
+            const int fb = g->f64 ? SW_F : 0;
+            const int ntl = c->tiling(g->m, g->n, KC_SWEEP, 0).ntiles;
+            for (int k = 0; k < o.check_every; ++k) {
+                const int cur = (s * o.check_every + k) % 2;
+                HIPERR(enq_sweep<double>(g, 0, g->psi[cur], g->psi[1 - cur], g->f64, nullptr, o.omega,
+                                         fb | (k == 0 ? SW_NORM : 0)));
+                if (k == 0) HIPERR(enq_finalize(g, ntl));
+            }
+            return hipSuccess;
+        }
+        case LAP_ADI:
+            HIPERR(enq_residual_norm<double>(g, 0, g->psi[0], g->f64));
+            for (int k = 0; k < o.check_every; ++k) HIPERR(enq_adi_iteration(g, o));
+            return hipSuccess;
+    }
+    return hipErrorInvalidValue;
+}
+
+// The tested iterate is the solution; bring it to psi[0] and make psi[1] equal.
+lap_status fixup(lap_grid* g, const lap_opts& o, const Ctrl& h) {
+    lap_ctx* c = g->ctx;
+    const size_t bytes = (size_t)g->n * g->P * 8;
+    int where = 0;
+    if (o.method == LAP_SOR_RB) where = h.iters % 2;
+    if (o.method == LAP_MG && o.precision == LAP_MIXED) where = h.checks % 2;
+    if (where == 1) HIPCHK(hipMemcpyAsync(g->psi[0], g->psi[1], bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (o.method == LAP_ADI) HIPCHK(hipMemcpyAsync(g->psi[1], g->psi[0], bytes, hipMemcpyDeviceToDevice, c->stream));
+    return LAP_OK;
+}
+
+lap_status solve_one(lap_grid* g, const lap_opts& o, lap_info* info) {
+    const double t0 = now_s();
+    lap_status st = prepare(g, o);
+    if (st != LAP_OK) return st;
+    Ctrl h{};
+    st = drive(g, max_steps(o) + 1, [&](int) -> hipError_t { return step(g, o); }, h);
+    if (st != LAP_OK) return st;
+    st = fixup(g, o, h);
+    if (st != LAP_OK) return st;
+    HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    return finish(g, o, h, t0, info);
+}
+
+void default_tilings(lap_ctx* c) {
+    for (int sc = 0; sc < 4; ++sc)
+        for (int k = 0; k < KC_COUNT; ++k) {
+            c->tileV[sc][k][0] = 2;
+            c->tileTY[sc][k][0] = sc <= 1 ? 16 : 64;
+            c->tileV[sc][k][1] = 4;
+            c->tileTY[sc][k][1] = sc <= 1 ? 16 : 64;
+        }
+}
+
+}  // namespace
+
+// =========================================================================== ABI
+extern "C" {
+
+const char* lap_last_error(void) { return g_err.c_str(); }
+const char* lap_version(void) { return "liblap 0.1 (gfx950)"; }
+
+void lap_opts_default(lap_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->method = LAP_MG;
+    o->precision = LAP_FP64;
+    o->omega = 1.0;
+    o->tol = 1e-10;
+    o->max_iter = 100;
+    o->stop = LAP_STOP_REL_L2;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->check_every = 1;
+    o->adi_form = LAP_ADI_RELAX_AFTER;
+    o->use_graph = 1;
+}
+
+lap_status lap_ctx_create(void* dev_arena, size_t arena_bytes, void* hip_stream, lap_ctx** out) {
+    if (!out) return fail(LAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!dev_arena) return fail(LAP_EINVAL, "arena is NULL");
+    if (((uintptr_t)dev_arena) % kAlign) return fail(LAP_EINVAL, "arena must be 256-byte aligned");
+    if (arena_bytes < (1u << 20)) return fail(LAP_EINVAL, "arena must hold at least 1 MiB");
+    lap_ctx* c = new (std::nothrow) lap_ctx();
+    if (!c) return fail(LAP_ENOMEM, "host allocation failed");
+    c->arena.init(dev_arena, arena_bytes);
+    c->stream = (hipStream_t)hip_stream;
+    default_tilings(c);
+    if (hipHostMalloc((void**)&c->pinned, 4 * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(LAP_EHIP, "hipHostMalloc of the control slots failed");
+    }
+    for (int k = 0; k < 2; ++k)
+        if (hipEventCreateWithFlags(&c->poll_ev[k], hipEventDisableTiming) != hipSuccess) {
+            delete c;
+            return fail(LAP_EHIP, "hipEventCreate failed");
+        }
+    *out = c;
+    return LAP_OK;
+}
+
+lap_status lap_grid_destroy(lap_grid* g);
+
+lap_status lap_ctx_destroy(lap_ctx* c) {
+    if (!c) return LAP_OK;
+    hipStreamSynchronize(c->stream);
+    while (!c->grids.empty()) lap_grid_destroy(c->grids.back());
+    for (auto& r : c->recs) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (auto e : c->pool) hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k)
+        if (c->poll_ev[k]) hipEventDestroy(c->poll_ev[k]);
+    if (c->pinned) hipHostFree(c->pinned);
+    if (c->batch_host) hipHostFree(c->batch_host);
+    delete c;
+    return LAP_OK;
+}
+
+lap_status lap_ctx_usage(lap_ctx* c, size_t* used, size_t* largest_free) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    if (used) *used = c->arena.in_use;
+    if (largest_free) *largest_free = c->arena.largest_free();
+    return LAP_OK;
+}
+
+lap_status lap_ctx_set_timing(lap_ctx* c, int32_t on) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    c->timing = on != 0;
+    return LAP_OK;
+}
+
+lap_status lap_ctx_reset_stats(lap_ctx* c) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    HIPCHK(c->flush_recs());
+    std::memset(c->launches, 0, sizeof c->launches);
+    std::memset(c->ms, 0, sizeof c->ms);
+    std::memset(c->bytes, 0, sizeof c->bytes);
+    return LAP_OK;
+}
+
+lap_status lap_ctx_kernel_stats(lap_ctx* c, int32_t cls, int32_t fine_only, int64_t* launches, double* ms,
+                                double* bytes) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    if (cls < 0 || cls >= KC_COUNT) return fail(LAP_EINVAL, "unknown kernel class");
+    HIPCHK(c->flush_recs());
+    const int f = fine_only ? 1 : 0;
+    if (launches) *launches = c->launches[cls][f];
+    if (ms) *ms = c->ms[cls][f];
+    if (bytes) *bytes = c->bytes[cls][f];
+    return LAP_OK;
+}
+
+size_t lap_grid_footprint(int32_t m, int32_t n, int32_t flags) {
+    if (m < 3 || n < 3) return 0;
+    return footprint(m, n, true, flags).bytes;
+}
+
+lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, double dy, const double* psi0,
+                              const double* source, int32_t flags, lap_grid** out) {
+    if (!out) return fail(LAP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    if (m < 3 || n < 3) return fail(LAP_EINVAL, "m and n must be >= 3");
+    if (!(dx > 0.0) || !(dy > 0.0) || !std::isfinite(dx) || !std::isfinite(dy))
+        return fail(LAP_EINVAL, "dx and dy must be positive and finite");
+    if (check_ptr(psi0, "psi0") != LAP_OK) return LAP_EINVAL;
+    if (flags <= 0 || flags > LAP_ALLOC_ALL) return fail(LAP_EINVAL, "bad allocation flags");
+    auto lv = plan_levels(m, n, dx, dy);
+    if (flags == LAP_ALLOC_ALL && lv.back().interior() > 1024)
+        flags = LAP_ALLOC_ADI;   // "everything the grid supports": no multigrid on this size
+    const bool mg = (flags & (LAP_ALLOC_FP64 | LAP_ALLOC_MIXED)) != 0;
+    if (mg && lv.back().interior() > 1024)
+        return fail(LAP_EINVAL, "coarsest multigrid level has more than 1024 interior nodes; use sizes c*2^k+1");
+    const Footprint fp = footprint(m, n, source != nullptr, flags);
+    if (fp.bytes > c->arena.largest_free()) return fail(LAP_ENOMEM, "arena cannot hold the grid");
+
+    lap_grid* g = new (std::nothrow) lap_grid();
+    if (!g) return fail(LAP_ENOMEM, "host allocation failed");
+    g->ctx = c;
+    g->m = m;
+    g->n = n;
+    g->dx = dx;
+    g->dy = dy;
+    g->flags = flags;
+    g->geo = lv;
+    g->P = lv[0].P;
+    g->has_f = source != nullptr;
+    const size_t f0 = (size_t)n * g->P;
+    const int L = (int)lv.size();
+    bool ok = true;
+    auto A = [&](size_t bytes) -> void* {
+        void* p = galloc(g, bytes);
+        if (!p) ok = false;
+        return p;
+    };
+    g->psi[0] = (double*)A(f0 * 8);
+    g->psi[1] = (double*)A(f0 * 8);
+    if (source) g->f64 = (double*)A(f0 * 8);
+    g->l64.resize(L);
+    g->l32.resize(L);
+    if (flags & LAP_ALLOC_FP64)
+        for (int l = 1; l < L; ++l) {
+            const size_t sz = (size_t)lv[l].n * lv[l].P * 8;
+            g->l64[l].u[0] = (double*)A(sz);
+            g->l64[l].u[1] = (double*)A(sz);
+            g->l64[l].b = (double*)A(sz);
+        }
+    if (flags & LAP_ALLOC_MIXED)
+        for (int l = 0; l < L; ++l) {
+            const size_t sz = (size_t)lv[l].n * lv[l].P * 4;
+            g->l32[l].u[0] = (float*)A(sz);
+            g->l32[l].u[1] = (float*)A(sz);
+            g->l32[l].b = (float*)A(sz);
+        }
+    std::vector<double> inv;
+    if (mg) {
+        const LevelGeo& C = lv.back();
+        char key[96];
+        snprintf(key, sizeof key, "%d:%d:%.17g:%.17g", C.m, C.n, C.dx, C.dy);
+        auto it = c->inv_cache.find(key);
+        if (it == c->inv_cache.end()) {
+            if (!coarse_inverse(C.m, C.n, C.dx, C.dy, inv)) {
+                lap_grid_destroy(g);
+                return fail(LAP_EINVAL, "coarse operator factorisation failed");
+            }
+            c->inv_cache[key] = inv;
+        } else {
+            inv = it->second;
+        }
+        g->minv = (double*)A(inv.size() * 8);
+    }
+    if (flags & LAP_ALLOC_ADI) {
+        g->adi_scratch = (double*)A(f0 * 8);
+        g->adi_maxk = std::max(m, n);
+        g->adi_tab = (double*)A((size_t)4 * g->adi_maxk * 8);
+    }
+    g->ctrl = (Ctrl*)A(sizeof(Ctrl));
+    g->max_partials = (int)max_tiles(m, n);
+    g->partials = (double*)A((size_t)g->max_partials * 16);
+    g->norm_out = (double*)A(16);
+    if (!ok) {
+        for (void* p : g->allocs) c->arena.release(p);
+        delete g;
+        return fail(LAP_ENOMEM, "arena exhausted");
+    }
+    hipStream_t s = c->stream;
+    for (void* p : g->allocs) {
+        // zero every buffer (padding included) so no kernel ever reads garbage
+        const size_t off = (size_t)((char*)p - c->arena.base);
+        const size_t sz = c->arena.used_[off];
+        if (hipMemsetAsync(p, 0, sz, s) != hipSuccess) {
+            lap_grid_destroy(g);
+            return fail(LAP_EHIP, "hipMemsetAsync failed");
+        }
+    }
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipMemcpy2DAsync(g->psi[k], (size_t)g->P * 8, psi0, (size_t)m * 8, (size_t)m * 8, n,
+                             hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && source)
+        e = hipMemcpy2DAsync(g->f64, (size_t)g->P * 8, source, (size_t)m * 8, (size_t)m * 8, n,
+                             hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && mg) e = hipMemcpyAsync(g->minv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // inv (host) must outlive the copy
+    if (e != hipSuccess) {
+        lap_grid_destroy(g);
+        return fail(LAP_EHIP, std::string("grid upload: ") + hipGetErrorString(e));
+    }
+    c->grids.push_back(g);
+    *out = g;
+    return LAP_OK;
+}
+
+lap_status lap_grid_create(lap_ctx* c, int32_t m, int32_t n, double dx, double dy, const double* psi0,
+                           const double* source, lap_grid** out) {
+    return lap_grid_create_ex(c, m, n, dx, dy, psi0, source, LAP_ALLOC_ALL, out);
+}
+
+lap_status lap_grid_destroy(lap_grid* g) {
+    if (!g) return LAP_OK;
+    lap_ctx* c = g->ctx;
+    hipStreamSynchronize(c->stream);
+    if (g->graph) hipGraphExecDestroy(g->graph);
+    for (void* p : g->allocs) c->arena.release(p);
+    auto it = std::find(c->grids.begin(), c->grids.end(), g);
+    if (it != c->grids.end()) c->grids.erase(it);
+    delete g;
+    return LAP_OK;
+}
+
+lap_status lap_grid_read(lap_grid* g, double* dst) {
+    if (!g) return fail(LAP_EINVAL, "grid is NULL");
+    if (!dst) return fail(LAP_EINVAL, "dst is NULL");
+    HIPCHK(hipMemcpy2DAsync(dst, (size_t)g->m * 8, g->psi[0], (size_t)g->P * 8, (size_t)g->m * 8, g->n,
+                            hipMemcpyDeviceToDevice, g->ctx->stream));
+    return LAP_OK;
+}
+
+lap_status lap_grid_write(lap_grid* g, const double* src) {
+    if (!g) return fail(LAP_EINVAL, "grid is NULL");
+    if (!src) return fail(LAP_EINVAL, "src is NULL");
+    for (int k = 0; k < 2; ++k)
+        HIPCHK(hipMemcpy2DAsync(g->psi[k], (size_t)g->P * 8, src, (size_t)g->m * 8, (size_t)g->m * 8, g->n,
+                                hipMemcpyDeviceToDevice, g->ctx->stream));
+    g->batch_started = false;
+    return LAP_OK;
+}
+
+lap_status lap_grid_levels(lap_grid* g, int32_t* nl) {
+    if (!g || !nl) return fail(LAP_EINVAL, "NULL argument");
+    *nl = (int32_t)g->geo.size();
+    return LAP_OK;
+}
+
+lap_status lap_grid_level_shape(lap_grid* g, int32_t l, int32_t* m, int32_t* n) {
+    if (!g || !m || !n) return fail(LAP_EINVAL, "NULL argument");
+    if (l < 0 || l >= (int)g->geo.size()) return fail(LAP_EINVAL, "level out of range");
+    *m = g->geo[l].m;
+    *n = g->geo[l].n;
+    return LAP_OK;
+}
+
+lap_status lap_solve_ex(lap_grid* g, const lap_opts* o, lap_info* info) {
+    if (!g || !o) return fail(LAP_EINVAL, "NULL argument");
+    lap_status st = validate_opts(g, *o);
+    if (st != LAP_OK) return st;
+    return solve_one(g, *o, info);
+}
+
+lap_status lap_solve(lap_grid* g, int32_t method, double omega, double tol, int32_t max_iter, int32_t precision,
+                     lap_info* info) {
+    lap_opts o;
+    lap_opts_default(&o);
+    o.method = method;
+    o.omega = omega;
+    o.tol = tol;
+    o.max_iter = max_iter;
+    o.precision = precision;
+    return lap_solve_ex(g, &o, info);
+}
+
+lap_status lap_residual_ex(lap_grid* g, double* l2, double* linf) {
+    if (!g) return fail(LAP_EINVAL, "grid is NULL");
+    const LevelGeo& L = g->geo[0];
+    const Coef c = coef(L.dx, L.dy);
+    ResidualArgs<double> a{};
+    a.u = g->psi[0];
+    a.f = g->f64;
+    a.partials = g->partials;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    a.cx = c.cx;
+    a.cy = c.cy;
+    a.d = c.d;
+    a.tl = g->ctx->tiling(L.m, L.n, KC_RESIDUAL, 0);
+    HIPCHK(launch_residual<double>(a, g->ctx->stream));
+    HIPCHK(launch_finalize(g->partials, a.tl.ntiles, nullptr, g->norm_out, 1, g->ctx->stream));
+    double h[2];
+    HIPCHK(hipMemcpyAsync(h, g->norm_out, 16, hipMemcpyDeviceToHost, g->ctx->stream));
+    HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    if (l2) *l2 = std::sqrt(h[0]);
+    if (linf) *linf = h[1];
+    return LAP_OK;
+}
+
+lap_status lap_residual(lap_grid* g, double* l2_rel, double* linf) {
+    double l2 = 0.0;
+    lap_status st = lap_residual_ex(g, &l2, linf);
+    if (st != LAP_OK) return st;
+    if (l2_rel) *l2_rel = (g->last_r0 > 0.0) ? l2 / g->last_r0 : (l2 > 0.0 ? 1.0 : 0.0);
+    return LAP_OK;
+}
+
+lap_status lap_grid_set_tol(lap_grid* g, double tol) {
+    if (!g) return fail(LAP_EINVAL, "grid is NULL");
+    if (!(tol >= 0.0)) return fail(LAP_EINVAL, "tol must be >= 0");
+    g->tol = tol;
+    return LAP_OK;
+}
+
+lap_status lap_grid_reset(lap_grid* g) {
+    if (!g) return fail(LAP_EINVAL, "grid is NULL");
+    g->batch_started = false;
+    return LAP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------- op level
+static lap_status op_check(int32_t dtype, int32_t m, int32_t n, int32_t ld, double dx, double dy) {
+    if (dtype != 0 && dtype != 1) return fail(LAP_EINVAL, "dtype must be 0 (FP64) or 1 (FP32)");
+    if (m < 3 || n < 3) return fail(LAP_EINVAL, "m and n must be >= 3");
+    if (ld < m || ld % 64) return fail(LAP_EINVAL, "ld must be >= m and a multiple of 64");
+    if (!(dx > 0.0) || !(dy > 0.0)) return fail(LAP_EINVAL, "dx and dy must be positive");
+    return LAP_OK;
+}
+static bool aligned(const void* p) { return ((uintptr_t)p % kAlign) == 0; }
+
+static const int kOpV[2] = {2, 4};
+static const int kOpTY = 32;
+
+template <typename T>
+static lap_status op_sweep(int32_t m, int32_t n, int32_t ld, double dx, double dy, double omega, const void* u_in,
+                           const void* f, const void* ec, int32_t ldc, void* u_out, hipStream_t s) {
+    const Coef c = coef(dx, dy);
+    SweepArgs<T> a{};
+    a.uin = (const T*)u_in;
+    a.uout = (T*)u_out;
+    a.f = (const T*)f;
+    a.ec = (const T*)ec;
+    a.m = m;
+    a.n = n;
+    a.P = ld;
+    a.mc = (m - 1) / 2 + 1;
+    a.nc = (n - 1) / 2 + 1;
+    a.Pc = ldc;
+    a.cx = (T)c.cx;
+    a.cy = (T)c.cy;
+    a.d = (T)c.d;
+    a.inv_d = (T)c.inv_d;
+    a.omega = (T)omega;
+    a.tl = make_tiling(m, n, kOpV[dt_of<T>()], kOpTY);
+    int flags = (f ? SW_F : 0);
+    if (!u_in && !ec) flags |= SW_ZERO;
+    if (ec) flags |= SW_PROLONG;
+    HIPCHK(launch_sweep<T>(a, flags, s));
+    return LAP_OK;
+}
+
+extern "C" lap_status lap_op_rb_sweep(int32_t dtype, int32_t m, int32_t n, int32_t ld, double dx, double dy, double omega,
+                           const void* u_in, const void* f, const void* ec, int32_t ldc, void* u_out, void* stream) {
+    lap_status st = op_check(dtype, m, n, ld, dx, dy);
+    if (st != LAP_OK) return st;
+    if (!(omega > 0.0 && omega < 2.0)) return fail(LAP_EINVAL, "omega must lie in (0, 2)");
+    if (!u_out) return fail(LAP_EINVAL, "u_out is NULL");
+    if (!aligned(u_out) || (u_in && !aligned(u_in)) || (f && !aligned(f)) || (ec && !aligned(ec)))
+        return fail(LAP_EINVAL, "pointers must be 256-byte aligned");
+    if (ec) {
+        if (m % 2 == 0 || n % 2 == 0) return fail(LAP_EINVAL, "prolongation needs odd m and n");
+        if (ldc < (m - 1) / 2 + 1 || ldc % 64) return fail(LAP_EINVAL, "bad ldc");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    return dtype == 0 ? op_sweep<double>(m, n, ld, dx, dy, omega, u_in, f, ec, ldc, u_out, s)
+                      : op_sweep<float>(m, n, ld, dx, dy, omega, u_in, f, ec, ldc, u_out, s);
+}
+
+extern "C" size_t lap_op_work_bytes(int32_t m, int32_t n) {
+    if (m < 3 || n < 3) return 0;
+    const size_t part = round_up((size_t)make_tiling(m, n, 1, 16).ntiles * 16, kAlign);
+    const size_t line = round_up((size_t)n * pitch_of(m) * 8, kAlign) + round_up((size_t)2 * std::max(m, n) * 8, kAlign);
+    return std::max(part, line);
+}
+
+template <typename T>
+static lap_status op_residual(int32_t m, int32_t n, int32_t ld, double dx, double dy, const void* u, const void* f,
+                              void* r, double* norms, void* work, hipStream_t s) {
+    const Coef c = coef(dx, dy);
+    ResidualArgs<T> a{};
+    a.u = (const T*)u;
+    a.f = (const T*)f;
+    a.r = (T*)r;
+    a.partials = norms ? (double*)work : nullptr;
+    a.m = m;
+    a.n = n;
+    a.P = ld;
+    a.cx = (T)c.cx;
+    a.cy = (T)c.cy;
+    a.d = (T)c.d;
+    a.tl = make_tiling(m, n, kOpV[dt_of<T>()], kOpTY);
+    HIPCHK(launch_residual<T>(a, s));
+    if (norms) HIPCHK(launch_finalize((double*)work, a.tl.ntiles, nullptr, norms, 1, s));
+    return LAP_OK;
+}
+
+extern "C" lap_status lap_op_residual(int32_t dtype, int32_t m, int32_t n, int32_t ld, double dx, double dy, const void* u,
+                           const void* f, void* r, double* norms, void* work, void* stream) {
+    lap_status st = op_check(dtype, m, n, ld, dx, dy);
+    if (st != LAP_OK) return st;
+    if (!u) return fail(LAP_EINVAL, "u is NULL");
+    if (norms && !work) return fail(LAP_EINVAL, "norms need a work buffer");
+    if (!aligned(u) || (f && !aligned(f)) || (r && !aligned(r))) return fail(LAP_EINVAL, "pointers must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    return dtype == 0 ? op_residual<double>(m, n, ld, dx, dy, u, f, r, norms, work, s)
+                      : op_residual<float>(m, n, ld, dx, dy, u, f, r, norms, work, s);
+}
+
+template <typename T>
+static lap_status op_restrict(int32_t m, int32_t n, int32_t ld, double dx, double dy, const void* u, const void* f,
+                              void* bc, int32_t ldc, hipStream_t s) {
+    const Coef c = coef(dx, dy);
+    RestrictArgs<T> a{};
+    a.u = (const T*)u;
+    a.f = (const T*)f;
+    a.bc = (T*)bc;
+    a.m = m;
+    a.n = n;
+    a.P = ld;
+    a.mc = (m - 1) / 2 + 1;
+    a.nc = (n - 1) / 2 + 1;
+    a.Pc = ldc;
+    a.cx = (T)c.cx;
+    a.cy = (T)c.cy;
+    a.d = (T)c.d;
+    a.tl = make_tiling(m, n, kOpV[dt_of<T>()], kOpTY);
+    HIPCHK(launch_restrict<T>(a, s));
+    return LAP_OK;
+}
+
+extern "C" lap_status lap_op_restrict(int32_t dtype, int32_t m, int32_t n, int32_t ld, double dx, double dy, const void* u,
+                           const void* f, void* bc, int32_t ldc, void* stream) {
+    lap_status st = op_check(dtype, m, n, ld, dx, dy);
+    if (st != LAP_OK) return st;
+    if (m % 2 == 0 || n % 2 == 0 || m < 5 || n < 5) return fail(LAP_EINVAL, "restriction needs odd m, n >= 5");
+    if (!bc) return fail(LAP_EINVAL, "bc is NULL");
+    if (ldc < (m - 1) / 2 + 1 || ldc % 64) return fail(LAP_EINVAL, "bad ldc");
+    if ((u && !aligned(u)) || (f && !aligned(f)) || !aligned(bc)) return fail(LAP_EINVAL, "pointers must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    return dtype == 0 ? op_restrict<double>(m, n, ld, dx, dy, u, f, bc, ldc, s)
+                      : op_restrict<float>(m, n, ld, dx, dy, u, f, bc, ldc, s);
+}
+
+extern "C" lap_status lap_op_adi_half(int32_t dtype, int32_t m, int32_t n, int32_t ld, double dx, double dy, double omega,
+                           int32_t dir, int32_t form, void* u, const void* f, void* work, void* stream) {
+    lap_status st = op_check(dtype, m, n, ld, dx, dy);
+    if (st != LAP_OK) return st;
+    if (dtype != 0) return fail(LAP_EINVAL, "ADI lines are FP64 only");
+    if (!(omega > 0.0 && omega < 2.0)) return fail(LAP_EINVAL, "omega must lie in (0, 2)");
+    if (dir != 0 && dir != 1) return fail(LAP_EINVAL, "dir must be 0 (rows) or 1 (columns)");
+    if (form != 0 && form != 1) return fail(LAP_EINVAL, "unknown form");
+    if (!u || !work) return fail(LAP_EINVAL, "u and work are required");
+    if (!aligned(u) || (f && !aligned(f)) || !aligned(work)) return fail(LAP_EINVAL, "pointers must be 256-byte aligned");
+    if (ld != pitch_of(m)) return fail(LAP_EINVAL, "ADI needs ld = m rounded up to 64");
+    const Coef c = coef(dx, dy);
+    const double cl = dir == 0 ? c.cx : c.cy;
+    if (form == 1 && omega >= 1.0 + (dir == 0 ? c.cy / c.cx : c.cx / c.cy))
+        return fail(LAP_EINVAL, "relaxation inside the line system needs omega < 1 + beta^2");
+    const int K = dir == 0 ? m - 2 : n - 2;
+    std::vector<double> tab(2 * (size_t)K);
+    const double wl = form == 0 ? cl : omega * cl;
+    adi_factor(c.d, -wl, -wl, K, tab.data(), tab.data() + K);
+    // tables live at the end of the work buffer
+    char* wbase = (char*)work;
+    double* scratch = (double*)wbase;
+    double* dtab = (double*)(wbase + round_up((size_t)n * ld * 8, kAlign));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(dtab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    LineArgs a{};
+    a.u = (double*)u;
+    a.f = (const double*)f;
+    a.scratch = scratch;
+    a.cprime = dtab;
+    a.piv = dtab + K;
+    a.m = m;
+    a.n = n;
+    a.P = ld;
+    a.cx = c.cx;
+    a.cy = c.cy;
+    a.d = c.d;
+    a.omega = omega;
+    a.form = form;
+    a.a_off = -wl;
+    for (int par : {1, 0}) {
+        a.parity = par;
+        HIPCHK(dir == 0 ? launch_adi_rows(a, s) : launch_adi_cols(a, s));
+    }
+    return LAP_OK;
+}
+
+// ------------------------------------------------------------------ batches
+namespace {
+
+lap_status batch_reserve(lap_ctx* c, int count) {
+    if (count <= c->batch_cap) return LAP_OK;
+    int cap = std::max(count, 2 * c->batch_cap);
+    if (c->batch_ptrs) c->arena.release(c->batch_ptrs);
+    if (c->batch_ctrl) c->arena.release(c->batch_ctrl);
+    if (c->batch_host) hipHostFree(c->batch_host);
+    c->batch_ptrs = (Ctrl**)c->arena.alloc((size_t)cap * sizeof(Ctrl*));
+    c->batch_ctrl = (Ctrl*)c->arena.alloc((size_t)cap * sizeof(Ctrl));
+    c->batch_host = nullptr;
+    c->batch_cap = 0;
+    if (!c->batch_ptrs || !c->batch_ctrl) return fail(LAP_ENOMEM, "arena cannot hold the batch tables");
+    HIPCHK(hipHostMalloc((void**)&c->batch_host, (size_t)cap * sizeof(Ctrl), hipHostMallocDefault));
+    c->batch_cap = cap;
+    return LAP_OK;
+}
+
+// Read the control blocks of `gs` (one gather kernel, one copy, one sync).
+lap_status batch_read(lap_ctx* c, const std::vector<lap_grid*>& gs, std::vector<Ctrl>& out) {
+    const int n = (int)gs.size();
+    out.resize(n);
+    if (n == 0) return LAP_OK;
+    lap_status st = batch_reserve(c, n);
+    if (st != LAP_OK) return st;
+    c->batch_ptrs_host.resize(n);
+    for (int k = 0; k < n; ++k) c->batch_ptrs_host[k] = gs[k]->ctrl;
+    HIPCHK(hipMemcpyAsync(c->batch_ptrs, c->batch_ptrs_host.data(), (size_t)n * sizeof(Ctrl*),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(launch_gather_ctrl(c->batch_ptrs, c->batch_ctrl, n, c->stream));
+    HIPCHK(hipMemcpyAsync(c->batch_host, c->batch_ctrl, (size_t)n * sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::memcpy(out.data(), c->batch_host, (size_t)n * sizeof(Ctrl));
+    return LAP_OK;
+}
+
+}  // namespace
+
+extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_t count, const lap_opts* o,
+                                      lap_info* infos) {
+    if (!c || !o || (count > 0 && !grids)) return fail(LAP_EINVAL, "NULL argument");
+    if (count < 0) return fail(LAP_EINVAL, "count must be >= 0");
+    const double t0 = now_s();
+    for (int k = 0; k < count; ++k) {
+        if (!grids[k] || grids[k]->ctx != c) return fail(LAP_EINVAL, "grid does not belong to this context");
+        lap_status st = validate_opts(grids[k], *o);
+        if (st != LAP_OK) return st;
+    }
+    for (int k = 0; k < count; ++k) {
+        lap_status st = prepare(grids[k], *o);
+        if (st != LAP_OK) return st;
+    }
+    std::vector<lap_grid*> active(grids, grids + count);
+    std::vector<Ctrl> hs;
+    std::map<lap_grid*, Ctrl> final_ctrl;
+    const int rounds = max_steps(*o) + 1;
+    for (int r = 0; r < rounds && !active.empty(); ++r) {
+        for (lap_grid* g : active) {
+            hipError_t e = step(g, *o);
+            if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+        }
+        lap_status st = batch_read(c, active, hs);
+        if (st != LAP_OK) return st;
+        std::vector<lap_grid*> next;
+        for (size_t k = 0; k < active.size(); ++k) {
+            if (hs[k].done)
+                final_ctrl[active[k]] = hs[k];
+            else
+                next.push_back(active[k]);
+        }
+        active.swap(next);
+    }
+    lap_status worst = LAP_OK;
+    for (int k = 0; k < count; ++k) {
+        lap_grid* g = grids[k];
+        Ctrl h{};
+        auto it = final_ctrl.find(g);
+        if (it != final_ctrl.end()) h = it->second;
+        lap_status st = fixup(g, *o, h);
+        if (st != LAP_OK) return st;
+        st = finish(g, *o, h, t0, infos ? &infos[k] : nullptr);
+        if (st != LAP_OK && worst == LAP_OK) worst = st;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return worst;
+}
+
+extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t count, int32_t precision,
+                                     int32_t* done_host, lap_info* infos) {
+    if (!c || (count > 0 && (!grids || !done_host))) return fail(LAP_EINVAL, "NULL argument");
+    if (precision != LAP_FP64 && precision != LAP_MIXED) return fail(LAP_EINVAL, "unknown precision");
+    const double t0 = now_s();
+    std::vector<lap_grid*> active;
+    for (int k = 0; k < count; ++k) {
+        lap_grid* g = grids[k];
+        if (!g || g->ctx != c) return fail(LAP_EINVAL, "grid does not belong to this context");
+        done_host[k] = 0;
+        if (g->batch_started && g->batch_done) {
+            done_host[k] = 1;
+            continue;
+        }
+        if (!g->batch_started) {
+            lap_opts o;
+            lap_opts_default(&o);
+            o.method = LAP_MG;
+            o.precision = precision;
+            o.tol = g->tol;
+            o.max_iter = 1000;
+            lap_status st = validate_opts(g, o);
+            if (st != LAP_OK) return st;
+            st = prepare(g, o);
+            if (st != LAP_OK) return st;
+            g->batch_opts = o;
+            g->batch_started = true;
+            g->batch_done = false;
+            g->batch_t0 = t0;
+        }
+        active.push_back(g);
+    }
+    for (lap_grid* g : active) {
+        // one outer step per tick: launch directly (a mixed graph spans two steps)
+        lap_opts o = g->batch_opts;
+        o.use_graph = (o.precision == LAP_FP64) ? o.use_graph : 0;
+        hipError_t e = step(g, o);
+        if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    std::vector<Ctrl> hs;
+    lap_status st = batch_read(c, active, hs);
+    if (st != LAP_OK) return st;
+    lap_status worst = LAP_OK;
+    for (size_t k = 0; k < active.size(); ++k) {
+        lap_grid* g = active[k];
+        const int idx = (int)(std::find(grids, grids + count, g) - grids);
+        if (hs[k].done) {
+            g->batch_done = true;
+            done_host[idx] = 1;
+            st = fixup(g, g->batch_opts, hs[k]);
+            if (st != LAP_OK) return st;
+            st = finish(g, g->batch_opts, hs[k], g->batch_t0, infos ? &infos[idx] : nullptr);
+            if (st != LAP_OK && worst == LAP_OK) worst = st;
+        } else if (infos) {
+            infos[idx].iterations = hs[k].iters;
+            infos[idx].status = LAP_ENOTCONV;
+            infos[idx].rel_res_l2 = hs[k].rel;
+            infos[idx].res_l2 = hs[k].res_l2;
+            infos[idx].res_linf = hs[k].res_inf;
+            infos[idx].res0_l2 = hs[k].r0;
+            infos[idx].seconds = now_s() - g->batch_t0;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return worst;
+}

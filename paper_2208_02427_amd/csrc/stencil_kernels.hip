@@ -1,0 +1,692 @@
+// gfx950 stencil kernels of the multigrid / red-black SOR path.
+//
+//  k_sweep     one red-black SOR sweep (both colours) in a single HBM pass,
+//              optionally from a zero start, with the bilinear prolongation
+//              of a coarse correction folded into its input, and/or with the
+//              residual norms of its input accumulated on the way
+//              (SOR: Eq. (7); colour ordering: (i+j) even first).
+//  k_restrict  residual r = f - L_h u (Eqs. (11)-(12)) fused with 9-point
+//              full weighting onto the coarse right-hand side.
+//  k_residual  residual with optional store and norms.
+//  k_defect    FP64 defect correction: psi += e32, r = f - L_h psi, rhs32 = fl32(r).
+//  k_coarse    exact solve on the coarsest level with a precomputed inverse.
+//  k_finalize  fixed-order reduction of per-tile norm partials + stopping test.
+//
+// All arithmetic is written with explicit fma() and the file is compiled
+// with -ffp-contract=off, so every tiling (V, ty) produces bitwise identical
+// fields.  Per-node expression trees:
+//   t   = (fma(cy, S+N, cx*(W+E)) - f) * inv_d
+//   u'  = fma(omega, t - u, u)
+//   L u = fma(-d, C, fma(cy, S+N, cx*(W+E)));   r = f - L u
+#include "lap_kernels.hpp"
+
+namespace lap {
+
+// ------------------------------------------------------------------ helpers
+template <typename T, int V> struct VecT;
+template <> struct VecT<double, 1> { using type = double; };
+template <> struct VecT<double, 2> { using type = double __attribute__((ext_vector_type(2))); };
+template <> struct VecT<double, 4> { using type = double __attribute__((ext_vector_type(4))); };
+template <> struct VecT<float, 1> { using type = float; };
+template <> struct VecT<float, 2> { using type = float __attribute__((ext_vector_type(2))); };
+template <> struct VecT<float, 4> { using type = float __attribute__((ext_vector_type(4))); };
+
+template <typename T, int V>
+__device__ __forceinline__ void ldv(T (&x)[V], const T* p) {
+    using VT = typename VecT<T, V>::type;
+    VT v = *reinterpret_cast<const VT*>(p);
+    if constexpr (V == 1) {
+        x[0] = v;
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) x[e] = v[e];
+    }
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void stv(T* p, const T (&x)[V]) {
+    using VT = typename VecT<T, V>::type;
+    VT v;
+    if constexpr (V == 1) {
+        v = x[0];
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = x[e];
+    }
+    *reinterpret_cast<VT*>(p) = v;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void zero(T (&x)[V]) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) x[e] = T(0);
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void copy(T (&dst)[V], const T (&src)[V]) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) dst[e] = src[e];
+}
+
+// Workgroups are dealt to the XCDs round-robin; give XCD x the contiguous
+// tile range [x*per, (x+1)*per) so neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int per = nb / kXcds;
+    return (b % kXcds) * per + (b / kXcds);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Per-lane column bookkeeping of one window.
+template <int V>
+struct Cols {
+    int ws, i0;
+    bool vin;                 // whole vector inside [0, P)
+    bool cint[V];             // interior column
+    bool cout[V];             // interior and inside this window's output range
+    bool all_out;
+    __device__ __forceinline__ Cols(int win, int lane, int m, int P) {
+        ws = win * win_step(V) - win_left(V);
+        i0 = ws + lane * V;
+        vin = (i0 >= 0) && (i0 + V <= P);
+        all_out = true;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int i = i0 + e;
+            cint[e] = (i >= 1) && (i <= m - 2);
+            cout[e] = cint[e] && (i >= ws + 2) && (i < ws + 64 * V - 2);
+            all_out = all_out && cout[e];
+        }
+    }
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void load_row(T (&x)[V], const T* base, int j, int n, int P, int i0, bool vin) {
+    if (base != nullptr && vin && j >= 0 && j < n)
+        ldv<T, V>(x, base + (size_t)j * P + i0);
+    else
+        zero<T, V>(x);
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void store_row(T* base, const T (&x)[V], int j, int P, const Cols<V>& c) {
+    T* p = base + (size_t)j * P + c.i0;
+    if (c.vin && c.all_out) {
+        stv<T, V>(p, x);
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (c.cout[e]) p[e] = x[e];
+    }
+}
+
+// Add the bilinear interpolation of the coarse correction ec to fine row j.
+template <typename T, int V>
+__device__ __forceinline__ void add_prolong(T (&x)[V], const T* ec, int Pc, int j, int n, int i0, int m) {
+    if (j < 0 || j >= n) return;
+    const int J = j >> 1, t = j & 1;
+    const T* r0 = ec + (size_t)J * Pc;
+    const T* r1 = r0 + Pc;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const int i = i0 + e;
+        if (i < 0 || i >= m) continue;
+        const int I = i >> 1, s = i & 1;
+        T p;
+        const T e00 = r0[I];
+        if (!s && !t) {
+            p = e00;
+        } else if (s && !t) {
+            p = (e00 + r0[I + 1]) * T(0.5);
+        } else if (!s && t) {
+            p = (e00 + r1[I]) * T(0.5);
+        } else {
+            p = ((e00 + r0[I + 1]) + (r1[I] + r1[I + 1])) * T(0.25);
+        }
+        x[e] = x[e] + p;
+    }
+}
+
+// ------------------------------------------------------------ red-black sweep
+template <typename T, int V, int FL>
+__device__ __forceinline__ void sweep_load(T (&x)[V], const SweepArgs<T>& A, int j, const Cols<V>& c) {
+    if constexpr (FL & SW_ZERO) {
+        zero<T, V>(x);
+    } else {
+        load_row<T, V>(x, A.uin, j, A.n, A.P, c.i0, c.vin);
+        if constexpr (FL & SW_PROLONG) add_prolong<T, V>(x, A.ec, A.Pc, j, A.n, c.i0, A.m);
+    }
+}
+
+template <typename T, int V, int FL>
+__device__ __forceinline__ void sweep_loadf(T (&x)[V], const SweepArgs<T>& A, int j, const Cols<V>& c) {
+    if constexpr (FL & SW_F)
+        load_row<T, V>(x, A.f, j, A.n, A.P, c.i0, c.vin);
+    else
+        zero<T, V>(x);
+}
+
+// State carried down the rows of one window (registers).
+template <typename T, int V>
+struct SweepRegs {
+    T a[V], b[V], c[V], d[V];   // rows j-2 (final), j-1 (red done), j (old -> red), j+1 (old)
+    T fb[V], fc[V], fd[V];      // f at rows j-1, j, j+1
+    T dn[V], fdn[V];            // prefetched row j+2
+    T bo[V];                    // old row j-1 (norm of the input)
+    double s2, mx;
+};
+
+template <typename T, int V, int FL, int JP>
+__device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V>& R, const Cols<V>& c,
+                                           int j, int j0, int j1, int ipar) {
+    // rotate in the prefetched row j+1, prefetch row j+2
+    copy<T, V>(R.d, R.dn);
+    copy<T, V>(R.fd, R.fdn);
+    if (j <= j1) {
+        sweep_load<T, V, FL>(R.dn, A, j + 2, c);
+        sweep_loadf<T, V, FL>(R.fdn, A, j + 2, c);
+    }
+    const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
+
+    // old row j: neighbours across lanes
+    const T cW = __shfl_up(R.c[V - 1], 1);
+    const T cE = __shfl_down(R.c[0], 1);
+
+    if constexpr (FL & SW_NORM) {
+        if (j >= j0 && j <= j1) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                if (!c.cout[e]) continue;
+                const T W = e > 0 ? R.c[e - 1] : cW;
+                const T E = e < V - 1 ? R.c[e + 1] : cE;
+                const T L = fma(-A.d, R.c[e], fma(cy, R.bo[e] + R.d[e], cx * (W + E)));
+                const double r = (double)(R.fc[e] - L);
+                R.s2 = fma(r, r, R.s2);
+                R.mx = fmax(R.mx, fabs(r));
+            }
+        }
+        copy<T, V>(R.bo, R.c);
+    }
+
+    const bool rj = (j >= 1) && (j <= A.n - 2);
+    const bool rjm = (j - 1 >= 1) && (j - 1 <= A.n - 2);
+
+    // colour 0 ((i+j) even) on row j from old colour-1 neighbours
+    if (rj) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
+            if (!upd || !c.cint[e]) continue;
+            const T W = e > 0 ? R.c[e - 1] : cW;
+            const T E = e < V - 1 ? R.c[e + 1] : cE;
+            const T t = (fma(cy, R.b[e] + R.d[e], cx * (W + E)) - R.fc[e]) * inv_d;
+            R.c[e] = fma(om, t - R.c[e], R.c[e]);
+        }
+    }
+    // colour 1 on row j-1 ((i+j-1) odd) from the new colour-0 values
+    const T bW = __shfl_up(R.b[V - 1], 1);
+    const T bE = __shfl_down(R.b[0], 1);
+    if (rjm) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
+            if (!upd || !c.cint[e]) continue;
+            const T W = e > 0 ? R.b[e - 1] : bW;
+            const T E = e < V - 1 ? R.b[e + 1] : bE;
+            const T t = (fma(cy, R.a[e] + R.c[e], cx * (W + E)) - R.fb[e]) * inv_d;
+            R.b[e] = fma(om, t - R.b[e], R.b[e]);
+        }
+    }
+    if (j - 1 >= j0 && j - 1 <= j1) store_row<T, V>(A.uout, R.b, j - 1, A.P, c);
+
+    copy<T, V>(R.a, R.b);
+    copy<T, V>(R.b, R.c);
+    copy<T, V>(R.c, R.d);
+    copy<T, V>(R.fb, R.fc);
+    copy<T, V>(R.fc, R.fd);
+}
+
+template <typename T, int V, int FL>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
+    if (A.ctrl != nullptr && A.ctrl->done) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
+    if (tile >= A.tl.ntiles) return;
+    const int lane = threadIdx.x & 63;
+    const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
+    const Cols<V> c(win, lane, A.m, A.P);
+    const int j0 = 1 + chunk * A.tl.ty;          // odd
+    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
+    const int ipar = c.i0 & 1;
+
+    SweepRegs<T, V> R;
+    R.s2 = 0.0;
+    R.mx = 0.0;
+    zero<T, V>(R.a);
+    zero<T, V>(R.fb);
+    sweep_load<T, V, FL>(R.b, A, j0 - 2, c);
+    sweep_load<T, V, FL>(R.c, A, j0 - 1, c);
+    sweep_loadf<T, V, FL>(R.fc, A, j0 - 1, c);
+    sweep_load<T, V, FL>(R.dn, A, j0, c);
+    sweep_loadf<T, V, FL>(R.fdn, A, j0, c);
+    if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.b);
+
+    for (int j = j0 - 1; j <= j1 + 1; j += 2) {   // j0 - 1 is even
+        sweep_step<T, V, FL, 0>(A, R, c, j, j0, j1, ipar);
+        if (j + 1 <= j1 + 1) sweep_step<T, V, FL, 1>(A, R, c, j + 1, j0, j1, ipar);
+    }
+    if constexpr (FL & SW_NORM) {
+        const double s = wave_sum(R.s2);
+        const double mx = wave_max(R.mx);
+        if (lane == 0) {
+            A.partials[2 * tile] = s;
+            A.partials[2 * tile + 1] = mx;
+        }
+    }
+}
+
+template <typename T, int V>
+static hipError_t launch_sweep_v(const SweepArgs<T>& a, int flags, hipStream_t s) {
+    const dim3 grid(blocks_for(a.tl)), block(kBlock);
+    switch (flags) {
+        case 0: k_sweep<T, V, 0><<<grid, block, 0, s>>>(a); break;
+        case SW_F: k_sweep<T, V, SW_F><<<grid, block, 0, s>>>(a); break;
+        case SW_ZERO | SW_F: k_sweep<T, V, SW_ZERO | SW_F><<<grid, block, 0, s>>>(a); break;
+        case SW_ZERO: k_sweep<T, V, SW_ZERO><<<grid, block, 0, s>>>(a); break;
+        case SW_PROLONG: k_sweep<T, V, SW_PROLONG><<<grid, block, 0, s>>>(a); break;
+        case SW_PROLONG | SW_F: k_sweep<T, V, SW_PROLONG | SW_F><<<grid, block, 0, s>>>(a); break;
+        case SW_NORM: k_sweep<T, V, SW_NORM><<<grid, block, 0, s>>>(a); break;
+        case SW_NORM | SW_F: k_sweep<T, V, SW_NORM | SW_F><<<grid, block, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T>& a, int flags, hipStream_t s) {
+    switch (a.tl.V) {
+        case 1: return launch_sweep_v<T, 1>(a, flags, s);
+        case 2: return launch_sweep_v<T, 2>(a, flags, s);
+        case 4: return launch_sweep_v<T, 4>(a, flags, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, hipStream_t);
+
+// ------------------------------------------------- residual + full weighting
+template <typename T, int V>
+__device__ __forceinline__ void residual_row(T (&r)[V], const T (&um)[V], const T (&uc)[V], const T (&up)[V],
+                                             const T (&f)[V], bool rowint, const Cols<V>& c, T cx, T cy, T d) {
+    const T W0 = __shfl_up(uc[V - 1], 1);
+    const T E0 = __shfl_down(uc[0], 1);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const T W = e > 0 ? uc[e - 1] : W0;
+        const T E = e < V - 1 ? uc[e + 1] : E0;
+        const T L = fma(-d, uc[e], fma(cy, um[e] + up[e], cx * (W + E)));
+        r[e] = (rowint && c.cint[e]) ? (f[e] - L) : T(0);
+    }
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void k_restrict(RestrictArgs<T> A) {
+    if (A.ctrl != nullptr && A.ctrl->done) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
+    if (tile >= A.tl.ntiles) return;
+    const int lane = threadIdx.x & 63;
+    const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
+    const Cols<V> c(win, lane, A.m, A.P);
+    const int j0 = 1 + chunk * A.tl.ty;
+    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
+
+    T um[V], uc[V], up[V], un[V], fr[V], fn[V];
+    T r2[V], r1[V], r0[V];
+    zero<T, V>(r2);
+    zero<T, V>(r1);
+    load_row<T, V>(um, A.u, j0 - 1, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(uc, A.u, j0, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(un, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(fn, A.f, j0, A.n, A.P, c.i0, c.vin);
+
+    for (int j = j0; j <= j1 + 1; ++j) {
+        copy<T, V>(up, un);
+        copy<T, V>(fr, fn);
+        if (j <= j1) {
+            load_row<T, V>(un, A.u, j + 2, A.n, A.P, c.i0, c.vin);
+            load_row<T, V>(fn, A.f, j + 1, A.n, A.P, c.i0, c.vin);
+        }
+        residual_row<T, V>(r0, um, uc, up, fr, (j >= 1) && (j <= A.n - 2), c, A.cx, A.cy, A.d);
+        if ((j & 1) && j >= j0 + 2) {
+            const int J = (j - 1) >> 1;               // coarse row at fine row j-1
+            const T w2 = __shfl_up(r2[V - 1], 1), w1 = __shfl_up(r1[V - 1], 1), w0 = __shfl_up(r0[V - 1], 1);
+            const T e2 = __shfl_down(r2[0], 1), e1 = __shfl_down(r1[0], 1), e0 = __shfl_down(r0[0], 1);
+            if (J >= 1 && J <= A.nc - 2) {
+                T* brow = A.bc + (size_t)J * A.Pc;
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int i = c.i0 + e;
+                    if ((i & 1) || !c.cout[e]) continue;
+                    const int I = i >> 1;
+                    if (I < 1 || I > A.mc - 2) continue;
+                    const T C = r1[e];
+                    const T W = e > 0 ? r1[e - 1] : w1;
+                    const T E = e < V - 1 ? r1[e + 1] : e1;
+                    const T S = r2[e], N = r0[e];
+                    const T SW = e > 0 ? r2[e - 1] : w2;
+                    const T SE = e < V - 1 ? r2[e + 1] : e2;
+                    const T NW = e > 0 ? r0[e - 1] : w0;
+                    const T NE = e < V - 1 ? r0[e + 1] : e0;
+                    const T v = (fma(T(4), C, T(2) * ((W + E) + (S + N))) + ((SW + SE) + (NW + NE))) * T(0.0625);
+                    brow[I] = v;
+                }
+            }
+        }
+        copy<T, V>(r2, r1);
+        copy<T, V>(r1, r0);
+        copy<T, V>(um, uc);
+        copy<T, V>(uc, up);
+    }
+}
+
+template <typename T>
+hipError_t launch_restrict(const RestrictArgs<T>& a, hipStream_t s) {
+    const dim3 grid(blocks_for(a.tl)), block(kBlock);
+    switch (a.tl.V) {
+        case 1: k_restrict<T, 1><<<grid, block, 0, s>>>(a); break;
+        case 2: k_restrict<T, 2><<<grid, block, 0, s>>>(a); break;
+        case 4: k_restrict<T, 4><<<grid, block, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_restrict<double>(const RestrictArgs<double>&, hipStream_t);
+template hipError_t launch_restrict<float>(const RestrictArgs<float>&, hipStream_t);
+
+// ------------------------------------------------------------------ residual
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs<T> A) {
+    if (A.ctrl != nullptr && A.ctrl->done) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
+    if (tile >= A.tl.ntiles) return;
+    const int lane = threadIdx.x & 63;
+    const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
+    const Cols<V> c(win, lane, A.m, A.P);
+    const int j0 = 1 + chunk * A.tl.ty;
+    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
+
+    T um[V], uc[V], up[V], un[V], fr[V], fn[V], r[V];
+    double s2 = 0.0, mx = 0.0;
+    load_row<T, V>(um, A.u, j0 - 1, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(uc, A.u, j0, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(un, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(fn, A.f, j0, A.n, A.P, c.i0, c.vin);
+    for (int j = j0; j <= j1; ++j) {
+        copy<T, V>(up, un);
+        copy<T, V>(fr, fn);
+        if (j < j1) {
+            load_row<T, V>(un, A.u, j + 2, A.n, A.P, c.i0, c.vin);
+            load_row<T, V>(fn, A.f, j + 1, A.n, A.P, c.i0, c.vin);
+        }
+        residual_row<T, V>(r, um, uc, up, fr, true, c, A.cx, A.cy, A.d);
+        if (A.r != nullptr) store_row<T, V>(A.r, r, j, A.P, c);
+        if (A.partials != nullptr) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                if (!c.cout[e]) continue;
+                const double v = (double)r[e];
+                s2 = fma(v, v, s2);
+                mx = fmax(mx, fabs(v));
+            }
+        }
+        copy<T, V>(um, uc);
+        copy<T, V>(uc, up);
+    }
+    if (A.partials != nullptr) {
+        const double s = wave_sum(s2);
+        const double m2 = wave_max(mx);
+        if (lane == 0) {
+            A.partials[2 * tile] = s;
+            A.partials[2 * tile + 1] = m2;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_residual(const ResidualArgs<T>& a, hipStream_t s) {
+    const dim3 grid(blocks_for(a.tl)), block(kBlock);
+    switch (a.tl.V) {
+        case 1: k_residual<T, 1><<<grid, block, 0, s>>>(a); break;
+        case 2: k_residual<T, 2><<<grid, block, 0, s>>>(a); break;
+        case 4: k_residual<T, 4><<<grid, block, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_residual<double>(const ResidualArgs<double>&, hipStream_t);
+template hipError_t launch_residual<float>(const ResidualArgs<float>&, hipStream_t);
+
+// ---------------------------------------------------- FP64 defect correction
+template <int V>
+__device__ __forceinline__ void defect_load(double (&x)[V], const DefectArgs& A, int j, const Cols<V>& c) {
+    load_row<double, V>(x, A.psi_in, j, A.n, A.P, c.i0, c.vin);
+    if (A.e != nullptr && c.vin && j >= 0 && j < A.n) {
+        float ev[V];
+        ldv<float, V>(ev, A.e + (size_t)j * A.P + c.i0);
+#pragma unroll
+        for (int e = 0; e < V; ++e) x[e] = x[e] + (double)ev[e];
+    }
+}
+
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_defect(DefectArgs A) {
+    if (A.ctrl != nullptr && A.ctrl->done) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
+    if (tile >= A.tl.ntiles) return;
+    const int lane = threadIdx.x & 63;
+    const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
+    const Cols<V> c(win, lane, A.m, A.P);
+    const int j0 = 1 + chunk * A.tl.ty;
+    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
+
+    double um[V], uc[V], up[V], un[V], fr[V], fn[V], r[V];
+    float r32[V];
+    double s2 = 0.0, mx = 0.0;
+    defect_load<V>(um, A, j0 - 1, c);
+    defect_load<V>(uc, A, j0, c);
+    defect_load<V>(un, A, j0 + 1, c);
+    load_row<double, V>(fn, A.f, j0, A.n, A.P, c.i0, c.vin);
+    for (int j = j0; j <= j1; ++j) {
+        copy<double, V>(up, un);
+        copy<double, V>(fr, fn);
+        if (j < j1) {
+            defect_load<V>(un, A, j + 2, c);
+            load_row<double, V>(fn, A.f, j + 1, A.n, A.P, c.i0, c.vin);
+        }
+        residual_row<double, V>(r, um, uc, up, fr, true, c, A.cx, A.cy, A.d);
+        if (A.psi_out != A.psi_in || A.e != nullptr) store_row<double, V>(A.psi_out, uc, j, A.P, c);
+#pragma unroll
+        for (int e = 0; e < V; ++e) r32[e] = (float)r[e];
+        store_row<float, V>(A.rhs, r32, j, A.P, c);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            if (!c.cout[e]) continue;
+            s2 = fma(r[e], r[e], s2);
+            mx = fmax(mx, fabs(r[e]));
+        }
+        copy<double, V>(um, uc);
+        copy<double, V>(uc, up);
+    }
+    const double s = wave_sum(s2);
+    const double m2 = wave_max(mx);
+    if (lane == 0) {
+        A.partials[2 * tile] = s;
+        A.partials[2 * tile + 1] = m2;
+    }
+}
+
+hipError_t launch_defect(const DefectArgs& a, hipStream_t s) {
+    const dim3 grid(blocks_for(a.tl)), block(kBlock);
+    switch (a.tl.V) {
+        case 1: k_defect<1><<<grid, block, 0, s>>>(a); break;
+        case 2: k_defect<2><<<grid, block, 0, s>>>(a); break;
+        case 4: k_defect<4><<<grid, block, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- coarsest level
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse(CoarseArgs<T> A) {
+    if (A.ctrl != nullptr && A.ctrl->done) return;
+    __shared__ double rhs[1024];
+    const int mi = A.m - 2, ni = A.n - 2, N = mi * ni;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const int i = 1 + k % mi, j = 1 + k / mi;
+        double v = A.b != nullptr ? (double)A.b[(size_t)j * A.P + i] : 0.0;
+        if (A.u != nullptr) {   // Dirichlet values of the perimeter move to the right-hand side
+            if (i == 1) v -= A.cx * (double)A.u[(size_t)j * A.P];
+            if (i == A.m - 2) v -= A.cx * (double)A.u[(size_t)j * A.P + A.m - 1];
+            if (j == 1) v -= A.cy * (double)A.u[i];
+            if (j == A.n - 2) v -= A.cy * (double)A.u[(size_t)(A.n - 1) * A.P + i];
+        }
+        rhs[k] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        double x = 0.0;
+        for (int l = 0; l < N; ++l) x = fma(A.minv[(size_t)l * N + k], rhs[l], x);
+        const int i = 1 + k % mi, j = 1 + k / mi;
+        A.out[(size_t)j * A.P + i] = (T)x;
+    }
+}
+
+template <typename T>
+hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s) {
+    if ((a.m - 2) * (a.n - 2) > 1024) return hipErrorInvalidValue;
+    k_coarse<T><<<1, kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+template hipError_t launch_coarse<double>(const CoarseArgs<double>&, hipStream_t);
+template hipError_t launch_coarse<float>(const CoarseArgs<float>&, hipStream_t);
+
+// ------------------------------------------------------------ norm finalise
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* partials, int ntiles, Ctrl* ctrl,
+                                                     double* out2, int mode) {
+    if (mode == 0 && ctrl->done) return;
+    __shared__ double ss[kBlock], sm[kBlock];
+    double s = 0.0, mx = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += kBlock) {
+        s += partials[2 * t];
+        mx = fmax(mx, partials[2 * t + 1]);
+    }
+    ss[threadIdx.x] = s;
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            ss[threadIdx.x] += ss[threadIdx.x + w];
+            sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double sum = ss[0], m = sm[0];
+    if (mode == 1) {
+        out2[0] = sum;
+        out2[1] = m;
+        return;
+    }
+    const double res = sqrt(sum);
+    if (ctrl->checks == 0) ctrl->r0 = res;
+    const double r0 = ctrl->r0;
+    ctrl->res_l2 = res;
+    ctrl->res_inf = m;
+    ctrl->rel = r0 > 0.0 ? res / r0 : 0.0;
+    ctrl->checks += 1;
+    const double q = ctrl->stop == 0 ? ctrl->rel : m;
+    if (!isfinite(res) || !isfinite(m) || (r0 > 0.0 && res > 1e6 * r0)) {
+        ctrl->done = 1;
+        ctrl->status = -4;   // LAP_EDIVERGED
+    } else if (q < ctrl->tol || res == 0.0) {
+        ctrl->done = 1;
+        ctrl->status = 0;
+    } else if (ctrl->iters >= ctrl->max_iter) {
+        ctrl->done = 1;
+        ctrl->status = -3;   // LAP_ENOTCONV
+    } else {
+        ctrl->iters += ctrl->step > 0 ? ctrl->step : 1;
+    }
+}
+
+__global__ void k_ctrl_init(Ctrl* c, double tol, int stop, int max_iter, int step) {
+    c->r0 = 0.0;
+    c->rel = 0.0;
+    c->res_l2 = 0.0;
+    c->res_inf = 0.0;
+    c->tol = tol;
+    c->stop = stop;
+    c->max_iter = max_iter;
+    c->iters = 0;
+    c->checks = 0;
+    c->done = 0;
+    c->status = 0;
+    c->step = step;
+    c->pad = 0;
+}
+
+hipError_t launch_ctrl_init(Ctrl* ctrl, double tol, int stop, int max_iter, int step, hipStream_t s) {
+    k_ctrl_init<<<1, 1, 0, s>>>(ctrl, tol, stop, max_iter, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, double* out2, int mode,
+                           hipStream_t s) {
+    k_finalize<<<1, kBlock, 0, s>>>(partials, ntiles, ctrl, out2, mode);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ ctrl gather
+__global__ void k_gather_ctrl(Ctrl* const* src, Ctrl* dst, int count) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) dst[k] = *src[k];
+}
+
+hipError_t launch_gather_ctrl(Ctrl* const* src, Ctrl* dst, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_gather_ctrl<<<(count + 255) / 256, 256, 0, s>>>(src, dst, count);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------- copy
+__global__ __launch_bounds__(kBlock) void k_copy(const double* src, double* dst, int m, int n, int P,
+                                                 const Ctrl* ctrl) {
+    if (ctrl != nullptr && ctrl->done) return;
+    const size_t total = (size_t)n * P;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
+hipError_t launch_copy(const double* src, double* dst, int m, int n, int P, const Ctrl* ctrl, hipStream_t s) {
+    const size_t total = (size_t)n * P;
+    int nb = (int)((total + kBlock - 1) / kBlock);
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    k_copy<<<nb, kBlock, 0, s>>>(src, dst, m, n, P, ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace lap
