@@ -58,6 +58,12 @@ def run_gpu(args):
     arena = 12 << 30 if N > 4097 else 4 << 30
     ctx = lap.Context(arena_bytes=arena, device=dev)
     out = {}
+    # autotune the tilings of every size class the hierarchy visits (setup, untimed)
+    tune = []
+    if not args.no_tune:
+        for tn in (N, 2049, 257, 65):
+            tune.append(ctx.autotune(tn, tn, reps=3))
+    out["autotune"] = tune
 
     # ---------------------------------------------------------------- headline
     p = W.square_problem(N, seed=2)
@@ -204,6 +210,7 @@ def main():
     ap.add_argument("--size", type=int, default=8193)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--no-tune", action="store_true", help="default tilings, no autotuning")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs each grid on a single MI355X "
@@ -233,7 +240,7 @@ def main():
         "rel_res": out["rel_res"],
         "roofline": out["roofline"],
     }
-    for k in ("mixed", "sor", "mg_4097", "kernels_fine"):
+    for k in ("mixed", "sor", "mg_4097", "kernels_fine", "autotune"):
         if k in out:
             line[k] = out[k]
     if not args.no_cpu:

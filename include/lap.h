@@ -142,6 +142,27 @@ lap_status lap_ctx_kernel_stats(lap_ctx* ctx, int32_t kernel_class, int32_t fine
                                 int64_t* launches, double* device_ms, double* alg_bytes);
 lap_status lap_ctx_reset_stats(lap_ctx* ctx);
 
+/* Tilings of the stencil kernels.  Each kernel class (as numbered above) has,
+ * per dtype (0 FP64, 1 FP32) and per size class of the level (0: fewer than
+ * 2^14 interior nodes, 1: < 2^18, 2: < 2^22, 3: larger; lap_size_class), a
+ * tiling: V columns per lane (1, 2 or 4) and chunks of ty rows (even, >= 16),
+ * or ty = 0 for chunks sized so a launch has about target_waves wavefronts.
+ * Every tiling produces bitwise identical fields; only speed differs. */
+int32_t lap_size_class(int32_t m, int32_t n);
+lap_status lap_ctx_set_tiling(lap_ctx* ctx, int32_t kernel_class, int32_t dtype, int32_t size_class,
+                              int32_t V, int32_t ty, int32_t target_waves);
+lap_status lap_ctx_get_tiling(lap_ctx* ctx, int32_t kernel_class, int32_t dtype, int32_t size_class,
+                              int32_t* V, int32_t* ty, int32_t* target_waves);
+
+/* Autotuner: time every candidate tiling (V in {1,2,4}; ty in {16,32,64,128};
+ * auto with 1 or 2 device wave rounds) of the sweep, sweep+prolongation,
+ * residual+restriction, residual and defect kernels on scratch buffers of an
+ * m x n level (odd m, n >= 5; carved from the arena and released), keep the
+ * fastest per kernel class and dtype for that size class, and write a JSON
+ * report of the choices into `report` (host buffer of report_bytes, may be
+ * NULL).  `reps` timed launches per candidate.  Synchronises the stream. */
+lap_status lap_autotune(lap_ctx* ctx, int32_t m, int32_t n, int32_t reps, char* report, size_t report_bytes);
+
 /* ------------------------------------------------------------------ grids */
 
 /* Arena bytes a grid of m x n takes with the hierarchies of `alloc_flags`

@@ -11,6 +11,7 @@ Fields are torch float64 tensors of shape (n, m) on the GPU, indexed [j, i]
 from __future__ import annotations
 
 import ctypes
+import json
 
 from . import _native as N
 from ._native import (LAP_SOR_RB, LAP_ADI, LAP_MG, LAP_FP64, LAP_MIXED, LAP_STOP_REL_L2,  # noqa: F401
@@ -120,6 +121,33 @@ class Context:
                                           ctypes.byref(ms), ctypes.byref(b)))
         return {"launches": n.value, "device_ms": ms.value, "alg_bytes": b.value}
 
+    # ------------------------------------------------------------ tilings
+    def autotune(self, m: int, n: int, reps: int = 5) -> dict:
+        """Time every candidate tiling of the stencil kernels on an m x n level
+        and keep the fastest for its size class; returns the report."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._enter()
+        st = lib().lap_autotune(self.handle, int(m), int(n), int(reps), buf, len(buf))
+        self._leave()
+        _check(st)
+        return json.loads(buf.value.decode())
+
+    def apply_tuning(self, report: dict):
+        """Re-apply the choices of an autotune report (e.g. loaded from JSON)."""
+        sc = int(report["size_class"])
+        for e in report["best"]:
+            self.set_tiling(e["class"], 0 if e["dtype"] == "f64" else 1, sc, e["V"], e["ty"], e["target_waves"])
+
+    def set_tiling(self, cls, dtype, size_class, V, ty, target_waves=0):
+        _check(lib().lap_ctx_set_tiling(self.handle, int(cls), int(dtype), int(size_class), int(V), int(ty),
+                                        int(target_waves)))
+
+    def get_tiling(self, cls, dtype, size_class):
+        v, t, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lap_ctx_get_tiling(self.handle, int(cls), int(dtype), int(size_class), ctypes.byref(v),
+                                        ctypes.byref(t), ctypes.byref(w)))
+        return v.value, t.value, w.value
+
     def grid(self, psi0, f=None, dx=1.0, dy=1.0, alloc=LAP_ALLOC_ALL) -> "Grid":
         return Grid(self, psi0, f, dx, dy, alloc)
 
@@ -145,6 +173,10 @@ class Context:
         self._leave()
         _check(st, allow=(N.LAP_ENOTCONV, N.LAP_EDIVERGED))
         return [bool(d) for d in done], [i.as_dict() for i in infos]
+
+
+def size_class(m: int, n: int) -> int:
+    return int(lib().lap_size_class(int(m), int(n)))
 
 
 def footprint(m: int, n: int, alloc=LAP_ALLOC_ALL) -> int:

@@ -79,6 +79,10 @@ SIGNATURES = {
     "lap_op_restrict": (_S, [c_int32, c_int32, c_int32, c_int32, c_double, c_double, _P, _P, _P, c_int32, _P]),
     "lap_op_adi_half": (_S, [c_int32, c_int32, c_int32, c_int32, c_double, c_double, c_double, c_int32,
                              c_int32, _P, _P, _P, _P]),
+    "lap_size_class": (c_int32, [c_int32, c_int32]),
+    "lap_ctx_set_tiling": (_S, [_P, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
+    "lap_ctx_get_tiling": (_S, [_P, c_int32, c_int32, c_int32, _PS(c_int32), _PS(c_int32), _PS(c_int32)]),
+    "lap_autotune": (_S, [_P, c_int32, c_int32, c_int32, c_char_p, c_size_t]),
     "lap_last_error": (c_char_p, []),
     "lap_version": (c_char_p, []),
 }

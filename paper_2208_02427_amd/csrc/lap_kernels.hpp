@@ -38,16 +38,29 @@ struct Tiling {
     int ntiles = 0;  // nwin * nchunk (one wavefront each)
 };
 
-inline Tiling make_tiling(int m, int n, int V, int ty) {
+// Tiling of an m x n level with V columns per lane.  ty > 0: chunks of ty
+// rows.  ty == 0: size the chunks so the launch has about `target` waves
+// (one full occupancy round of the device when target = its wave capacity),
+// which avoids a nearly empty last round.  Chunks are never shorter than 16
+// rows, which bounds the number of tiles (and norm partials) of a level.
+inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0) {
     Tiling t;
     t.V = V;
-    t.ty = ty;
     const int S = win_step(V), H = win_left(V);
     // outputs of window w: columns [w*S - H + 2, w*S - H + 64V - 2); need to reach m-2
     int nw = 1;
     while ((nw - 1) * S - H + 64 * V - 3 < m - 2) ++nw;
     t.nwin = nw;
-    t.nchunk = (n - 2 + ty - 1) / ty;
+    const int rows = n - 2 > 0 ? n - 2 : 1;
+    if (ty <= 0) {
+        int chunks = target > 0 ? target / nw : 1;
+        if (chunks < 1) chunks = 1;
+        ty = (rows + chunks - 1) / chunks;
+        ty += ty & 1;
+        if (ty < 16) ty = 16;
+    }
+    t.ty = ty;
+    t.nchunk = (rows + ty - 1) / ty;
     if (t.nchunk < 1) t.nchunk = 1;
     t.ntiles = t.nwin * t.nchunk;
     return t;

@@ -226,7 +226,9 @@ struct lap_ctx {
     double bytes[KC_COUNT][2] = {};
     // tiling table: [size class][kernel class][dtype 0=f64,1=f32] -> (V, ty)
     int tileV[4][KC_COUNT][2];
-    int tileTY[4][KC_COUNT][2];
+    int tileTY[4][KC_COUNT][2];     // 0: auto (chunks sized for tileT waves)
+    int tileT[4][KC_COUNT][2];
+    int wave_cap = 8192;            // CUs x 32 wavefronts (read from the device)
     std::vector<lap_grid*> grids;
     std::map<std::string, std::vector<double>> inv_cache;
     Ctrl* pinned = nullptr;        // 4 host slots
@@ -280,7 +282,7 @@ struct lap_ctx {
     }
     Tiling tiling(int m, int n, int cls, int dt) const {
         const int sc = size_class((size_t)(m - 2) * (size_t)(n - 2));
-        return make_tiling(m, n, tileV[sc][cls][dt], tileTY[sc][cls][dt]);
+        return make_tiling(m, n, tileV[sc][cls][dt], tileTY[sc][cls][dt], tileT[sc][cls][dt]);
     }
 };
 
@@ -893,9 +895,11 @@ void default_tilings(lap_ctx* c) {
     for (int sc = 0; sc < 4; ++sc)
         for (int k = 0; k < KC_COUNT; ++k) {
             c->tileV[sc][k][0] = 2;
-            c->tileTY[sc][k][0] = sc <= 1 ? 16 : 64;
+            c->tileTY[sc][k][0] = 0;
+            c->tileT[sc][k][0] = c->wave_cap;
             c->tileV[sc][k][1] = 4;
-            c->tileTY[sc][k][1] = sc <= 1 ? 16 : 64;
+            c->tileTY[sc][k][1] = 0;
+            c->tileT[sc][k][1] = c->wave_cap;
         }
 }
 
@@ -933,6 +937,14 @@ lap_status lap_ctx_create(void* dev_arena, size_t arena_bytes, void* hip_stream,
     if (!c) return fail(LAP_ENOMEM, "host allocation failed");
     c->arena.init(dev_arena, arena_bytes);
     c->stream = (hipStream_t)hip_stream;
+    {
+        int dev = 0, cus = 0, tpm = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipDeviceGetAttribute(&tpm, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev) == hipSuccess &&
+            cus > 0 && tpm > 0)
+            c->wave_cap = cus * (tpm / kWave);
+    }
     default_tilings(c);
     if (hipHostMalloc((void**)&c->pinned, 4 * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -1527,6 +1539,7 @@ extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t
             o.precision = precision;
             o.tol = g->tol;
             o.max_iter = 1000;
+            o.use_graph = precision == LAP_FP64 ? 1 : 0;   // a mixed graph spans two outer steps
             lap_status st = validate_opts(g, o);
             if (st != LAP_OK) return st;
             st = prepare(g, o);
@@ -1540,9 +1553,7 @@ extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t
     }
     for (lap_grid* g : active) {
         // one outer step per tick: launch directly (a mixed graph spans two steps)
-        lap_opts o = g->batch_opts;
-        o.use_graph = (o.precision == LAP_FP64) ? o.use_graph : 0;
-        hipError_t e = step(g, o);
+        hipError_t e = step(g, g->batch_opts);
         if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     }
     std::vector<Ctrl> hs;
@@ -1571,4 +1582,215 @@ extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     return worst;
+}
+
+// ------------------------------------------------------------------ autotuner
+extern "C" int32_t lap_size_class(int32_t m, int32_t n) {
+    if (m < 3 || n < 3) return -1;
+    return size_class((size_t)(m - 2) * (size_t)(n - 2));
+}
+
+static lap_status tiling_args_ok(lap_ctx* c, int32_t cls, int32_t dtype, int32_t sc) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    if (cls < 0 || cls >= KC_COUNT) return fail(LAP_EINVAL, "unknown kernel class");
+    if (dtype != 0 && dtype != 1) return fail(LAP_EINVAL, "dtype must be 0 or 1");
+    if (sc < 0 || sc > 3) return fail(LAP_EINVAL, "size class must be 0..3");
+    return LAP_OK;
+}
+
+extern "C" lap_status lap_ctx_set_tiling(lap_ctx* c, int32_t cls, int32_t dtype, int32_t sc, int32_t V, int32_t ty,
+                                         int32_t target) {
+    lap_status st = tiling_args_ok(c, cls, dtype, sc);
+    if (st != LAP_OK) return st;
+    if (V != 1 && V != 2 && V != 4) return fail(LAP_EINVAL, "V must be 1, 2 or 4");
+    if (ty != 0 && (ty < 16 || ty % 2)) return fail(LAP_EINVAL, "ty must be 0 (auto) or an even number >= 16");
+    if (ty == 0 && target < 64) return fail(LAP_EINVAL, "auto tiling needs target_waves >= 64");
+    c->tileV[sc][cls][dtype] = V;
+    c->tileTY[sc][cls][dtype] = ty;
+    c->tileT[sc][cls][dtype] = ty == 0 ? target : 0;
+    return LAP_OK;
+}
+
+extern "C" lap_status lap_ctx_get_tiling(lap_ctx* c, int32_t cls, int32_t dtype, int32_t sc, int32_t* V, int32_t* ty,
+                                         int32_t* target) {
+    lap_status st = tiling_args_ok(c, cls, dtype, sc);
+    if (st != LAP_OK) return st;
+    if (V) *V = c->tileV[sc][cls][dtype];
+    if (ty) *ty = c->tileTY[sc][cls][dtype];
+    if (target) *target = c->tileT[sc][cls][dtype];
+    return LAP_OK;
+}
+
+namespace {
+struct TuneBufs {
+    void* u[2];
+    void* f;
+    void* ec;
+    void* bc;
+    void* rhs32;
+    void* e32;
+    double* partials;
+};
+
+template <typename T>
+hipError_t tune_launch(lap_ctx* c, int cls, const Tiling& t, int m, int n, int P, int Pc, const TuneBufs& B,
+                       int flags) {
+    const Coef k = coef(1.0 / (m - 1), 1.0 / (n - 1));
+    const int mc = (m - 1) / 2 + 1, nc = (n - 1) / 2 + 1;
+    if (cls == KC_SWEEP || cls == KC_SWEEP_PROLONG) {
+        SweepArgs<T> a{};
+        a.uin = (const T*)B.u[0];
+        a.uout = (T*)B.u[1];
+        a.f = (flags & SW_F) ? (const T*)B.f : nullptr;
+        a.ec = (const T*)B.ec;
+        a.partials = B.partials;
+        a.m = m; a.n = n; a.P = P; a.mc = mc; a.nc = nc; a.Pc = Pc;
+        a.cx = (T)k.cx; a.cy = (T)k.cy; a.d = (T)k.d; a.inv_d = (T)k.inv_d; a.omega = (T)1.0;
+        a.tl = t;
+        return launch_sweep<T>(a, flags | (cls == KC_SWEEP_PROLONG ? SW_PROLONG : 0), c->stream);
+    }
+    if (cls == KC_RESTRICT) {
+        RestrictArgs<T> a{};
+        a.u = (const T*)B.u[0]; a.f = (const T*)B.f; a.bc = (T*)B.bc;
+        a.m = m; a.n = n; a.P = P; a.mc = mc; a.nc = nc; a.Pc = Pc;
+        a.cx = (T)k.cx; a.cy = (T)k.cy; a.d = (T)k.d; a.tl = t;
+        return launch_restrict<T>(a, c->stream);
+    }
+    if (cls == KC_RESIDUAL) {
+        ResidualArgs<T> a{};
+        a.u = (const T*)B.u[0]; a.f = (const T*)B.f; a.partials = B.partials;
+        a.m = m; a.n = n; a.P = P; a.cx = (T)k.cx; a.cy = (T)k.cy; a.d = (T)k.d; a.tl = t;
+        return launch_residual<T>(a, c->stream);
+    }
+    if (cls == KC_DEFECT) {
+        DefectArgs a{};
+        a.psi_in = (const double*)B.u[0]; a.psi_out = (double*)B.u[1]; a.e = (const float*)B.e32;
+        a.f = (const double*)B.f; a.rhs = (float*)B.rhs32; a.partials = B.partials;
+        a.m = m; a.n = n; a.P = P; a.cx = k.cx; a.cy = k.cy; a.d = k.d; a.tl = t;
+        return launch_defect(a, c->stream);
+    }
+    return hipErrorInvalidValue;
+}
+}  // namespace
+
+extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t reps, char* report, size_t report_bytes) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    if (m < 5 || n < 5 || m % 2 == 0 || n % 2 == 0) return fail(LAP_EINVAL, "autotune needs odd m, n >= 5");
+    if (reps < 1) reps = 1;
+    const int sc = size_class((size_t)(m - 2) * (size_t)(n - 2));
+    const int P = pitch_of(m);
+    const int mc = (m - 1) / 2 + 1, nc = (n - 1) / 2 + 1, Pc = pitch_of(mc);
+    const size_t fine = (size_t)n * P * 8, coarse = (size_t)nc * Pc * 8;
+    std::vector<void*> held;
+    auto A = [&](size_t b) -> void* {
+        void* p = c->arena.alloc(b);
+        if (p) held.push_back(p);
+        return p;
+    };
+    TuneBufs B{};
+    B.u[0] = A(fine);
+    B.u[1] = A(fine);
+    B.f = A(fine);
+    B.ec = A(coarse);
+    B.bc = A(coarse);
+    B.rhs32 = A(fine / 2);
+    B.e32 = A(fine / 2);
+    B.partials = (double*)A((size_t)make_tiling(m, n, 1, 16).ntiles * 16);
+    auto release = [&]() {
+        hipStreamSynchronize(c->stream);
+        for (void* p : held) c->arena.release(p);
+    };
+    if (held.size() != 8) {
+        release();
+        return fail(LAP_ENOMEM, "arena cannot hold the autotune buffers");
+    }
+    for (void* p : held) {
+        const size_t off = (size_t)((char*)p - c->arena.base);
+        if (hipMemsetAsync(p, 0, c->arena.used_[off], c->stream) != hipSuccess) {
+            release();
+            return fail(LAP_EHIP, "hipMemsetAsync failed");
+        }
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        release();
+        return fail(LAP_EHIP, "hipEventCreate failed");
+    }
+    struct Cand { int V, ty, tgt; };
+    std::vector<Cand> cands;
+    for (int V : {1, 2, 4}) {
+        for (int ty : {16, 32, 64, 128}) cands.push_back({V, ty, 0});
+        cands.push_back({V, 0, c->wave_cap});
+        cands.push_back({V, 0, 2 * c->wave_cap});
+    }
+    std::string js = "{\"m\": " + std::to_string(m) + ", \"n\": " + std::to_string(n) + ", \"size_class\": " +
+                     std::to_string(sc) + ", \"wave_cap\": " + std::to_string(c->wave_cap) + ", \"best\": [";
+    const char* names[KC_COUNT] = {"sweep", "sweep_prolong", "restrict", "defect", "coarse", "finalize",
+                                   "adi_rows", "adi_cols", "residual"};
+    bool first = true;
+    lap_status result = LAP_OK;
+    for (int cls : {(int)KC_SWEEP, (int)KC_SWEEP_PROLONG, (int)KC_RESTRICT, (int)KC_RESIDUAL, (int)KC_DEFECT}) {
+        for (int dt = 0; dt < 2; ++dt) {
+            if (cls == KC_DEFECT && dt == 1) continue;
+            double best = 1e30;
+            Cand bc{2, 0, c->wave_cap};
+            for (const Cand& cd : cands) {
+                const Tiling t = make_tiling(m, n, cd.V, cd.ty, cd.tgt);
+                double total = 0.0;
+                for (int fl : {0, (int)SW_F}) {
+                    if (fl == 0 && cls != KC_SWEEP) continue;
+                    auto go = [&]() {
+                        return dt == 0 ? tune_launch<double>(c, cls, t, m, n, P, Pc, B, fl)
+                                       : tune_launch<float>(c, cls, t, m, n, P, Pc, B, fl);
+                    };
+                    hipError_t e = go();
+                    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+                    for (int r = 0; r < reps && e == hipSuccess; ++r) e = go();
+                    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e != hipSuccess) {
+                        result = fail(LAP_EHIP, std::string("autotune launch: ") + hipGetErrorString(e));
+                        break;
+                    }
+                    total += ms / reps;
+                }
+                if (result != LAP_OK) break;
+                if (total < best) {
+                    best = total;
+                    bc = cd;
+                }
+            }
+            if (result != LAP_OK) break;
+            c->tileV[sc][cls][dt] = bc.V;
+            c->tileTY[sc][cls][dt] = bc.ty;
+            c->tileT[sc][cls][dt] = bc.tgt;
+            char buf[256];
+            snprintf(buf, sizeof buf,
+                     "%s{\"kernel\": \"%s\", \"class\": %d, \"dtype\": \"%s\", \"V\": %d, \"ty\": %d, \"target_waves\": %d, "
+                     "\"ms\": %.5f}",
+                     first ? "" : ", ", names[cls], cls, dt == 0 ? "f64" : "f32", bc.V, bc.ty, bc.tgt, best);
+            js += buf;
+            first = false;
+        }
+        if (result != LAP_OK) break;
+    }
+    js += "]}";
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    release();
+    if (result != LAP_OK) return result;
+    // cached graphs hold the old tilings
+    for (lap_grid* g : c->grids)
+        if (g->graph) {
+            hipGraphExecDestroy(g->graph);
+            g->graph = nullptr;
+            g->graph_key.clear();
+        }
+    if (report && report_bytes > 0) {
+        std::strncpy(report, js.c_str(), report_bytes - 1);
+        report[report_bytes - 1] = 0;
+    }
+    return LAP_OK;
 }

@@ -181,6 +181,7 @@ struct SweepRegs {
     T a[V], b[V], c[V], d[V];   // rows j-2 (final), j-1 (red done), j (old -> red), j+1 (old)
     T fb[V], fc[V], fd[V];      // f at rows j-1, j, j+1
     T dn[V], fdn[V];            // prefetched row j+2
+    T dnn[V], fdnn[V];          // prefetched row j+3
     T bo[V];                    // old row j-1 (norm of the input)
     double s2, mx;
 };
@@ -188,12 +189,14 @@ struct SweepRegs {
 template <typename T, int V, int FL, int JP>
 __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V>& R, const Cols<V>& c,
                                            int j, int j0, int j1, int ipar) {
-    // rotate in the prefetched row j+1, prefetch row j+2
+    // rotate in the prefetched row j+1, prefetch row j+3 (two rows in flight)
     copy<T, V>(R.d, R.dn);
     copy<T, V>(R.fd, R.fdn);
-    if (j <= j1) {
-        sweep_load<T, V, FL>(R.dn, A, j + 2, c);
-        sweep_loadf<T, V, FL>(R.fdn, A, j + 2, c);
+    copy<T, V>(R.dn, R.dnn);
+    copy<T, V>(R.fdn, R.fdnn);
+    if (j + 3 <= j1 + 2) {
+        sweep_load<T, V, FL>(R.dnn, A, j + 3, c);
+        sweep_loadf<T, V, FL>(R.fdnn, A, j + 3, c);
     }
     const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
 
@@ -278,6 +281,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
     sweep_loadf<T, V, FL>(R.fc, A, j0 - 1, c);
     sweep_load<T, V, FL>(R.dn, A, j0, c);
     sweep_loadf<T, V, FL>(R.fdn, A, j0, c);
+    sweep_load<T, V, FL>(R.dnn, A, j0 + 1, c);
+    sweep_loadf<T, V, FL>(R.fdnn, A, j0 + 1, c);
     if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.b);
 
     for (int j = j0 - 1; j <= j1 + 1; j += 2) {   // j0 - 1 is even
