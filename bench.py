@@ -58,7 +58,8 @@ def run_gpu(args):
     arena = 12 << 30 if N > 4097 else 4 << 30
     ctx = lap.Context(arena_bytes=arena, device=dev)
     out = {}
-    # autotune the tilings of every size class the hierarchy visits (setup, untimed)
+    # autotune the tilings of every size class the hierarchy visits (setup,
+    # untimed); without it the Context keeps the shipped MI355X table
     tune = []
     if not args.no_tune:
         for tn in (N, 2049, 257, 65):
@@ -210,7 +211,7 @@ def main():
     ap.add_argument("--size", type=int, default=8193)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
-    ap.add_argument("--no-tune", action="store_true", help="default tilings, no autotuning")
+    ap.add_argument("--no-tune", action="store_true", help="keep the shipped tiling table, no autotuning")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs each grid on a single MI355X "

@@ -12,11 +12,15 @@ from __future__ import annotations
 
 import ctypes
 import json
+import os
 
 from . import _native as N
 from ._native import (LAP_SOR_RB, LAP_ADI, LAP_MG, LAP_FP64, LAP_MIXED, LAP_STOP_REL_L2,  # noqa: F401
                       LAP_STOP_RES_INF, LAP_ADI_RELAX_AFTER, LAP_ADI_RELAX_INSIDE, LAP_ALLOC_FP64,
                       LAP_ALLOC_MIXED, LAP_ALLOC_ADI, LAP_ALLOC_ALL, LapInfo, LapOpts)
+
+# tilings measured by the autotuner on MI355X (applied to every new Context)
+DEFAULT_TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 
 METHODS = {"sor": LAP_SOR_RB, "rb": LAP_SOR_RB, "adi": LAP_ADI, "mg": LAP_MG}
 PRECISIONS = {"fp64": LAP_FP64, "mixed": LAP_MIXED}
@@ -73,7 +77,7 @@ class Context:
     handed to lap_ctx_create.  Library work is ordered after the caller's
     current stream on entry and the current stream waits for it on exit."""
 
-    def __init__(self, arena_bytes: int = 1 << 30, device: str = "cuda:0"):
+    def __init__(self, arena_bytes: int = 1 << 30, device: str = "cuda:0", tuning: str | None = "default"):
         torch = _torch()
         self.device = torch.device(device)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
@@ -83,6 +87,12 @@ class Context:
                                     ctypes.byref(h)))
         self.handle = h
         self.grids = []
+        if tuning == "default":
+            tuning = DEFAULT_TUNING if os.path.exists(DEFAULT_TUNING) else None
+        if tuning:
+            with open(tuning) as fh:
+                for rep in json.load(fh)["reports"]:
+                    self.apply_tuning(rep)
 
     # stream ordering around library calls
     def _enter(self):

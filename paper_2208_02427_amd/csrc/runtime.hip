@@ -195,6 +195,8 @@ bool coarse_inverse(int m, int n, double dx, double dy, std::vector<double>& out
     return true;
 }
 
+enum Part { PART_ALL = 0, PART_HEAD = 1, PART_TAIL = 2 };
+
 enum KClass { KC_SWEEP = 0, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE,
               KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_COUNT };
 
@@ -503,31 +505,44 @@ hipError_t enq_residual_norm(lap_grid* g, int l, const T* u, const T* f) {
 // or starts from zero (error equation).  Returns the buffer index (0/1)
 // that holds the level's result.
 template <typename T>
-hipError_t enq_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm, int& res_idx) {
+hipError_t enq_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm, int& res_idx,
+                      int part = PART_ALL) {
+    // part (level 0 with norm only): PART_HEAD enqueues the stopping test of
+    // the incoming iterate (its first kernel + finalise), PART_TAIL the rest.
     const int L = (int)g->geo.size();
     const bool zero_start = (l > 0) || H.zero_start0;
+    const bool split = norm && !zero_start;
+    const bool head = !split || part != PART_TAIL;
+    const bool tail = !split || part != PART_HEAD;
     T* U[2] = {H.u0[l], H.u1[l]};
     const T* b = H.b[l];
     if (l == L - 1) {
-        if (norm && !zero_start) HIPERR(enq_residual_norm<T>(g, l, U[0], b));
-        HIPERR(enq_coarse<T>(g, l, zero_start ? nullptr : U[0], b, U[0]));
+        if (split && head) HIPERR(enq_residual_norm<T>(g, l, U[0], b));
+        if (tail) HIPERR(enq_coarse<T>(g, l, zero_start ? nullptr : U[0], b, U[0]));
         res_idx = 0;
         return hipSuccess;
     }
     const int fb = b ? SW_F : 0;
     int cur = 0;
     bool have_u = !zero_start;
-    if (norm && !zero_start && o.nu1 == 0) HIPERR(enq_residual_norm<T>(g, l, U[0], b));
+    if (split && o.nu1 == 0) {
+        if (head) HIPERR(enq_residual_norm<T>(g, l, U[0], b));
+        if (!tail) return hipSuccess;
+    }
     for (int k = 0; k < o.nu1; ++k) {
         if (!have_u) {
             HIPERR(enq_sweep<T>(g, l, nullptr, U[0], b, nullptr, o.omega, SW_ZERO | fb));
             cur = 0;
             have_u = true;
         } else {
-            const bool nk = norm && !zero_start && k == 0;
-            HIPERR(enq_sweep<T>(g, l, U[cur], U[1 - cur], b, nullptr, o.omega, fb | (nk ? SW_NORM : 0)));
-            if (nk) HIPERR(enq_finalize(g, g->ctx->tiling(g->geo[l].m, g->geo[l].n, KC_SWEEP, dt_of<T>()).ntiles));
+            const bool nk = split && k == 0;
+            if (!nk || head) {
+                HIPERR(enq_sweep<T>(g, l, U[cur], U[1 - cur], b, nullptr, o.omega, fb | (nk ? SW_NORM : 0)));
+                if (nk)
+                    HIPERR(enq_finalize(g, g->ctx->tiling(g->geo[l].m, g->geo[l].n, KC_SWEEP, dt_of<T>()).ntiles));
+            }
             cur = 1 - cur;
+            if (nk && !tail) return hipSuccess;
         }
     }
     HIPERR(enq_restrict<T>(g, l, have_u ? U[cur] : nullptr, b, H.b[l + 1]));
@@ -615,9 +630,13 @@ int vcycle_result_index(const lap_opts& o) {
 // One outer step of the mixed loop: defect correction (adds the previous
 // FP32 correction, forms the FP64 residual, tests it), then one FP32
 // V-cycle on the error equation.
-hipError_t enq_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int& e_idx) {
-    const float* e = first ? nullptr : (e_idx == 0 ? g->l32[0].u[0] : g->l32[0].u[1]);
-    HIPERR(enq_defect(g, in_idx, e));
+hipError_t enq_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int& e_idx,
+                          int part = PART_ALL) {
+    if (part != PART_TAIL) {
+        const float* e = first ? nullptr : (e_idx == 0 ? g->l32[0].u[0] : g->l32[0].u[1]);
+        HIPERR(enq_defect(g, in_idx, e));
+    }
+    if (part == PART_HEAD) return hipSuccess;
     HierView<float> H = view32(g);
     return enq_vcycle<float>(g, H, 0, o, false, e_idx);
 }
@@ -824,33 +843,34 @@ lap_status prepare(lap_grid* g, const lap_opts& o) {
     return LAP_OK;
 }
 
-// Enqueue outer step number g->step_idx (then advance it).
-hipError_t step(lap_grid* g, const lap_opts& o) {
-    const int s = g->step_idx++;
+// Enqueue outer step number g->step_idx.  PART_ALL enqueues the whole step
+// (and advances step_idx); PART_HEAD only its stopping test of the incoming
+// iterate, PART_TAIL the rest (and advances step_idx).
+hipError_t step(lap_grid* g, const lap_opts& o, int part = PART_ALL) {
+    const int s = g->step_idx;
+    if (part != PART_HEAD) g->step_idx++;
     lap_ctx* c = g->ctx;
-    const bool graph = use_graph(g, o);
+    const bool graph = use_graph(g, o) && part == PART_ALL;
     switch (o.method) {
         case LAP_MG:
             if (o.precision == LAP_FP64) {
                 if (graph) return hipGraphLaunch(g->graph, c->stream);
                 HierView<double> H = view64(g);
                 int ri = 0;
-                return enq_vcycle<double>(g, H, 0, o, true, ri);
+                return enq_vcycle<double>(g, H, 0, o, true, ri, part);
             } else {
                 // step s reads psi[s % 2]; the graph covers the pair (odd s, even s)
-                if (s == 0) return enq_mixed_step(g, o, 0, true, g->e_idx);
-                if (graph) {
-                    if (s % 2 == 1) {
-                        g->step_idx++;   // the graph also runs step s + 1
-                        return hipGraphLaunch(g->graph, c->stream);
-                    }
+                if (s == 0) return enq_mixed_step(g, o, 0, true, g->e_idx, part);
+                if (graph && s % 2 == 1) {
+                    g->step_idx++;   // the graph also runs step s + 1
+                    return hipGraphLaunch(g->graph, c->stream);
                 }
-                return enq_mixed_step(g, o, s % 2, false, g->e_idx);
+                return enq_mixed_step(g, o, s % 2, false, g->e_idx, part);
             }
         case LAP_SOR_RB: {
             const int fb = g->f64 ? SW_F : 0;
             const int ntl = c->tiling(g->m, g->n, KC_SWEEP, 0).ntiles;
-            for (int k = 0; k < o.check_every; ++k) {
+            for (int k = (part == PART_TAIL ? 1 : 0); k < (part == PART_HEAD ? 1 : o.check_every); ++k) {
                 const int cur = (s * o.check_every + k) % 2;
                 HIPERR(enq_sweep<double>(g, 0, g->psi[cur], g->psi[1 - cur], g->f64, nullptr, o.omega,
                                          fb | (k == 0 ? SW_NORM : 0)));
@@ -859,8 +879,9 @@ hipError_t step(lap_grid* g, const lap_opts& o) {
             return hipSuccess;
         }
         case LAP_ADI:
-            HIPERR(enq_residual_norm<double>(g, 0, g->psi[0], g->f64));
-            for (int k = 0; k < o.check_every; ++k) HIPERR(enq_adi_iteration(g, o));
+            if (part != PART_TAIL) HIPERR(enq_residual_norm<double>(g, 0, g->psi[0], g->f64));
+            if (part != PART_HEAD)
+                for (int k = 0; k < o.check_every; ++k) HIPERR(enq_adi_iteration(g, o));
             return hipSuccess;
     }
     return hipErrorInvalidValue;
@@ -878,12 +899,34 @@ lap_status fixup(lap_grid* g, const lap_opts& o, const Ctrl& h) {
     return LAP_OK;
 }
 
+// Measurement mode (kernel timing on): test the stopping rule synchronously
+// before the rest of each step, so no kernel is ever launched after the
+// device has decided to stop and every timed launch did its full work.
+lap_status drive_measured(lap_grid* g, const lap_opts& o, Ctrl& out) {
+    lap_ctx* c = g->ctx;
+    for (int s = 0; s <= max_steps(o); ++s) {
+        hipError_t e = step(g, o, PART_HEAD);
+        if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+        HIPCHK(hipMemcpyAsync(&c->pinned[2], g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->pinned[2].done) break;
+        e = step(g, o, PART_TAIL);
+        if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    out = c->pinned[2];
+    return LAP_OK;
+}
+
 lap_status solve_one(lap_grid* g, const lap_opts& o, lap_info* info) {
     const double t0 = now_s();
     lap_status st = prepare(g, o);
     if (st != LAP_OK) return st;
     Ctrl h{};
-    st = drive(g, max_steps(o) + 1, [&](int) -> hipError_t { return step(g, o); }, h);
+    if (g->ctx->timing)
+        st = drive_measured(g, o, h);
+    else
+        st = drive(g, max_steps(o) + 1, [&](int) -> hipError_t { return step(g, o); }, h);
     if (st != LAP_OK) return st;
     st = fixup(g, o, h);
     if (st != LAP_OK) return st;
