@@ -66,6 +66,24 @@ def run_gpu(args):
             tune.append(ctx.autotune(tn, tn, reps=3))
     out["autotune"] = tune
 
+    if args.copy_probe:
+        # achievable HBM bandwidth: plain copy of 1 GiB, several grid sizes
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        best = {}
+        for blocks in (1024, 2048, 4096, 8192):
+            lap.op_stream_copy(src, dst, blocks=blocks)
+            sync()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                lap.op_stream_copy(src, dst, blocks=blocks)
+            sync()
+            t = (time.perf_counter() - t0) / 10
+            best[blocks] = 2 * (1 << 30) / t / 1e9
+        out["copy_probe"] = {"bytes_per_launch": 2 * (1 << 30), "GB/s_by_blocks": best,
+                             "best_GB/s": max(best.values())}
+        del src, dst
+
     # ---------------------------------------------------------------- headline
     p = W.square_problem(N, seed=2)
     psi0 = torch.as_tensor(p.psi0, device=dev)
@@ -212,6 +230,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-tune", action="store_true", help="keep the shipped tiling table, no autotuning")
+    ap.add_argument("--copy-probe", action="store_true", help="also time a plain 1 GiB device copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs each grid on a single MI355X "
@@ -241,7 +260,7 @@ def main():
         "rel_res": out["rel_res"],
         "roofline": out["roofline"],
     }
-    for k in ("mixed", "sor", "mg_4097", "kernels_fine", "autotune"):
+    for k in ("copy_probe", "mixed", "sor", "mg_4097", "kernels_fine", "autotune"):
         if k in out:
             line[k] = out[k]
     if not args.no_cpu:

@@ -282,6 +282,12 @@ lap_status lap_op_adi_half(int32_t dtype, int32_t m, int32_t n, int32_t ld, doub
                            double omega, int32_t dir, int32_t form, void* u, const void* f,
                            void* work, void* stream);
 
+/* Plain streaming copy of `bytes` (a multiple of 16; 16-byte aligned
+ * pointers) from src to dst with `blocks` workgroups of 256 threads: the
+ * achievable-bandwidth reference for roofline figures and the calibration
+ * kernel for hardware byte counters.  Stream-ordered. */
+lap_status lap_op_stream_copy(const void* src, void* dst, size_t bytes, int32_t blocks, void* stream);
+
 /* ---------------------------------------------------------------- errors */
 const char* lap_last_error(void);
 /* Library version string. */

@@ -339,3 +339,9 @@ def op_adi_half(m, n, dx, dy, omega, direction, form, u, f=None):
     _check(lib().lap_op_adi_half(0, m, n, u.shape[1], float(dx), float(dy), float(omega), int(direction), int(form),
                                  _ptr(u), _ptr(f), _ptr(work), _stream()))
     torch.cuda.current_stream().synchronize()
+
+
+def op_stream_copy(src, dst, nbytes=None, blocks=2048):
+    """Plain device copy (the bandwidth reference kernel)."""
+    nbytes = int(nbytes if nbytes is not None else src.numel() * src.element_size())
+    _check(lib().lap_op_stream_copy(_ptr(src), _ptr(dst), nbytes, int(blocks), _stream()))

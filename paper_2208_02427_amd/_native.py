@@ -83,6 +83,7 @@ SIGNATURES = {
     "lap_ctx_set_tiling": (_S, [_P, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
     "lap_ctx_get_tiling": (_S, [_P, c_int32, c_int32, c_int32, _PS(c_int32), _PS(c_int32), _PS(c_int32)]),
     "lap_autotune": (_S, [_P, c_int32, c_int32, c_int32, c_char_p, c_size_t]),
+    "lap_op_stream_copy": (_S, [_P, _P, c_size_t, c_int32, _P]),
     "lap_last_error": (c_char_p, []),
     "lap_version": (c_char_p, []),
 }

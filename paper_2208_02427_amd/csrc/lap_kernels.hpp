@@ -176,6 +176,10 @@ hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, doubl
 hipError_t launch_ctrl_init(Ctrl* ctrl, double tol, int stop, int max_iter, int step, hipStream_t s);
 // Gather the control blocks of a batch of grids into one array.
 hipError_t launch_gather_ctrl(Ctrl* const* src, Ctrl* dst, int count, hipStream_t s);
+// Streaming copy of `bytes` (a multiple of 16) with `blocks` workgroups.
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks, hipStream_t s);
+// Dense m x n FP64 field (row pitch m) into pitched fields d0 and (if not NULL) d1.
+hipError_t launch_write_field(const double* src, double* d0, double* d1, int m, int n, int P, hipStream_t s);
 // Copy interior of src into dst (FP64 fields of the same layout).
 hipError_t launch_copy(const double* src, double* dst, int m, int n, int P, const Ctrl* ctrl,
                        hipStream_t s);

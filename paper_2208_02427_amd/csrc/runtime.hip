@@ -1158,13 +1158,8 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
             return fail(LAP_EHIP, "hipMemsetAsync failed");
         }
     }
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < 2 && e == hipSuccess; ++k)
-        e = hipMemcpy2DAsync(g->psi[k], (size_t)g->P * 8, psi0, (size_t)m * 8, (size_t)m * 8, n,
-                             hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && source)
-        e = hipMemcpy2DAsync(g->f64, (size_t)g->P * 8, source, (size_t)m * 8, (size_t)m * 8, n,
-                             hipMemcpyDeviceToDevice, s);
+    hipError_t e = launch_write_field(psi0, g->psi[0], g->psi[1], m, n, g->P, s);
+    if (e == hipSuccess && source) e = launch_write_field(source, g->f64, nullptr, m, n, g->P, s);
     if (e == hipSuccess && mg) e = hipMemcpyAsync(g->minv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // inv (host) must outlive the copy
     if (e != hipSuccess) {
@@ -1204,9 +1199,7 @@ lap_status lap_grid_read(lap_grid* g, double* dst) {
 lap_status lap_grid_write(lap_grid* g, const double* src) {
     if (!g) return fail(LAP_EINVAL, "grid is NULL");
     if (!src) return fail(LAP_EINVAL, "src is NULL");
-    for (int k = 0; k < 2; ++k)
-        HIPCHK(hipMemcpy2DAsync(g->psi[k], (size_t)g->P * 8, src, (size_t)g->m * 8, (size_t)g->m * 8, g->n,
-                                hipMemcpyDeviceToDevice, g->ctx->stream));
+    HIPCHK(launch_write_field(src, g->psi[0], g->psi[1], g->m, g->n, g->P, g->ctx->stream));
     g->batch_started = false;
     return LAP_OK;
 }
@@ -1835,5 +1828,15 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
         std::strncpy(report, js.c_str(), report_bytes - 1);
         report[report_bytes - 1] = 0;
     }
+    return LAP_OK;
+}
+
+// ------------------------------------------------------------- stream copy
+extern "C" lap_status lap_op_stream_copy(const void* src, void* dst, size_t bytes, int32_t blocks, void* stream) {
+    if (!src || !dst) return fail(LAP_EINVAL, "NULL pointer");
+    if (bytes % 16 || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
+        return fail(LAP_EINVAL, "bytes and pointers must be multiples of 16");
+    if (blocks < 1) return fail(LAP_EINVAL, "blocks must be >= 1");
+    HIPCHK(launch_stream_copy(src, dst, bytes, blocks, (hipStream_t)stream));
     return LAP_OK;
 }

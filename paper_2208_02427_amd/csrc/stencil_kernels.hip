@@ -18,6 +18,8 @@
 //   t   = (fma(cy, S+N, cx*(W+E)) - f) * inv_d
 //   u'  = fma(omega, t - u, u)
 //   L u = fma(-d, C, fma(cy, S+N, cx*(W+E)));   r = f - L u
+#include <algorithm>
+
 #include "lap_kernels.hpp"
 
 namespace lap {
@@ -129,41 +131,74 @@ __device__ __forceinline__ void store_row(T* base, const T (&x)[V], int j, int P
     }
 }
 
-// Add the bilinear interpolation of the coarse correction ec to fine row j.
+// Bilinear interpolation of a coarse correction, streamed with the fine rows.
+// A lane owning fine columns i0..i0+V-1 needs coarse columns I0 = i0>>1 ..
+// I0 + V2 (V2 = max(1, V/2)); it loads I0..I0+V2-1 with one vector load per
+// coarse row and takes column I0+V2 from the next lane.  The two coarse rows
+// J, J+1 around the current fine row stay in registers: fine rows arrive in
+// increasing order, so each coarse row is loaded once per wave.
 template <typename T, int V>
-__device__ __forceinline__ void add_prolong(T (&x)[V], const T* ec, int Pc, int j, int n, int i0, int m) {
-    if (j < 0 || j >= n) return;
-    const int J = j >> 1, t = j & 1;
-    const T* r0 = ec + (size_t)J * Pc;
-    const T* r1 = r0 + Pc;
+struct Prolong {
+    static constexpr int V2 = V >= 2 ? V / 2 : 1;
+    T lo[V2 + 1], hi[V2 + 1];   // coarse rows Jcur, Jcur+1 (entry V2 from the next lane)
+    int Jcur;
+    __device__ __forceinline__ void load_coarse(T (&x)[V2 + 1], const T* ec, int J, int nc, int Pc, int I0) {
+        T v[V2];
+        if (J >= 0 && J < nc && I0 >= 0 && I0 + V2 <= Pc)
+            ldv<T, V2>(v, ec + (size_t)J * Pc + I0);
+        else
+            zero<T, V2>(v);
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-        const int i = i0 + e;
-        if (i < 0 || i >= m) continue;
-        const int I = i >> 1, s = i & 1;
-        T p;
-        const T e00 = r0[I];
-        if (!s && !t) {
-            p = e00;
-        } else if (s && !t) {
-            p = (e00 + r0[I + 1]) * T(0.5);
-        } else if (!s && t) {
-            p = (e00 + r1[I]) * T(0.5);
-        } else {
-            p = ((e00 + r0[I + 1]) + (r1[I] + r1[I + 1])) * T(0.25);
-        }
-        x[e] = x[e] + p;
+        for (int q = 0; q < V2; ++q) x[q] = v[q];
+        x[V2] = __shfl_down(v[0], 1);
     }
-}
+    __device__ __forceinline__ void init(const T* ec, int j, int nc, int Pc, int i0) {
+        Jcur = j >> 1;
+        load_coarse(lo, ec, Jcur, nc, Pc, i0 >> 1);
+        load_coarse(hi, ec, Jcur + 1, nc, Pc, i0 >> 1);
+    }
+    // add P(ec) to fine row j (j non-decreasing between calls)
+    __device__ __forceinline__ void add(T (&x)[V], const T* ec, int j, int n, int nc, int Pc, int i0, int m) {
+        const int J = j >> 1;
+        while (Jcur < J) {   // at most one step per fine row
+#pragma unroll
+            for (int q = 0; q <= V2; ++q) lo[q] = hi[q];
+            ++Jcur;
+            load_coarse(hi, ec, Jcur + 1, nc, Pc, i0 >> 1);
+        }
+        if (j < 0 || j >= n) return;
+        const int t = j & 1;
+        const int I0 = i0 >> 1;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int i = i0 + e;
+            const int q = (i >> 1) - I0;           // 0..V2-1
+            const int s = i & 1;
+            const T e00 = lo[q], e10 = lo[q + 1], e01 = hi[q], e11 = hi[q + 1];
+            T p;
+            if (!s && !t) {
+                p = e00;
+            } else if (s && !t) {
+                p = (e00 + e10) * T(0.5);
+            } else if (!s && t) {
+                p = (e00 + e01) * T(0.5);
+            } else {
+                p = ((e00 + e10) + (e01 + e11)) * T(0.25);
+            }
+            if (i >= 0 && i < m) x[e] = x[e] + p;
+        }
+    }
+};
 
 // ------------------------------------------------------------ red-black sweep
 template <typename T, int V, int FL>
-__device__ __forceinline__ void sweep_load(T (&x)[V], const SweepArgs<T>& A, int j, const Cols<V>& c) {
+__device__ __forceinline__ void sweep_load(T (&x)[V], const SweepArgs<T>& A, int j, const Cols<V>& c,
+                                           Prolong<T, V>& pr) {
     if constexpr (FL & SW_ZERO) {
         zero<T, V>(x);
     } else {
         load_row<T, V>(x, A.uin, j, A.n, A.P, c.i0, c.vin);
-        if constexpr (FL & SW_PROLONG) add_prolong<T, V>(x, A.ec, A.Pc, j, A.n, c.i0, A.m);
+        if constexpr (FL & SW_PROLONG) pr.add(x, A.ec, j, A.n, A.nc, A.Pc, c.i0, A.m);
     }
 }
 
@@ -184,6 +219,7 @@ struct SweepRegs {
     T dnn[V], fdnn[V];          // prefetched row j+3
     T bo[V];                    // old row j-1 (norm of the input)
     double s2, mx;
+    Prolong<T, V> pr;           // coarse rows of a fused prolongation
 };
 
 template <typename T, int V, int FL, int JP>
@@ -195,7 +231,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
     copy<T, V>(R.dn, R.dnn);
     copy<T, V>(R.fdn, R.fdnn);
     if (j + 3 <= j1 + 2) {
-        sweep_load<T, V, FL>(R.dnn, A, j + 3, c);
+        sweep_load<T, V, FL>(R.dnn, A, j + 3, c, R.pr);
         sweep_loadf<T, V, FL>(R.fdnn, A, j + 3, c);
     }
     const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
@@ -276,12 +312,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
     R.mx = 0.0;
     zero<T, V>(R.a);
     zero<T, V>(R.fb);
-    sweep_load<T, V, FL>(R.b, A, j0 - 2, c);
-    sweep_load<T, V, FL>(R.c, A, j0 - 1, c);
+    if constexpr (FL & SW_PROLONG) R.pr.init(A.ec, j0 - 2, A.nc, A.Pc, c.i0);
+    sweep_load<T, V, FL>(R.b, A, j0 - 2, c, R.pr);
+    sweep_load<T, V, FL>(R.c, A, j0 - 1, c, R.pr);
     sweep_loadf<T, V, FL>(R.fc, A, j0 - 1, c);
-    sweep_load<T, V, FL>(R.dn, A, j0, c);
+    sweep_load<T, V, FL>(R.dn, A, j0, c, R.pr);
     sweep_loadf<T, V, FL>(R.fdn, A, j0, c);
-    sweep_load<T, V, FL>(R.dnn, A, j0 + 1, c);
+    sweep_load<T, V, FL>(R.dnn, A, j0 + 1, c, R.pr);
     sweep_loadf<T, V, FL>(R.fdnn, A, j0 + 1, c);
     if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.b);
 
@@ -355,22 +392,24 @@ __global__ __launch_bounds__(kBlock) void k_restrict(RestrictArgs<T> A) {
     const int j0 = 1 + chunk * A.tl.ty;
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
 
-    T um[V], uc[V], up[V], un[V], fr[V], fn[V];
+    T um[V], uc[V], up[V], q1[V], q2[V], fr[V], fq1[V], fq2[V];
     T r2[V], r1[V], r0[V];
     zero<T, V>(r2);
     zero<T, V>(r1);
     load_row<T, V>(um, A.u, j0 - 1, A.n, A.P, c.i0, c.vin);
     load_row<T, V>(uc, A.u, j0, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(un, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(fn, A.f, j0, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(q1, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(q2, A.u, j0 + 2, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(fq1, A.f, j0, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(fq2, A.f, j0 + 1, A.n, A.P, c.i0, c.vin);
 
-    for (int j = j0; j <= j1 + 1; ++j) {
-        copy<T, V>(up, un);
-        copy<T, V>(fr, fn);
-        if (j <= j1) {
-            load_row<T, V>(un, A.u, j + 2, A.n, A.P, c.i0, c.vin);
-            load_row<T, V>(fn, A.f, j + 1, A.n, A.P, c.i0, c.vin);
-        }
+    for (int j = j0; j <= j1 + 1; ++j) {   // rows j+1, j+2 (u) and j, j+1 (f) are in flight
+        copy<T, V>(up, q1);
+        copy<T, V>(fr, fq1);
+        copy<T, V>(q1, q2);
+        copy<T, V>(fq1, fq2);
+        if (j + 3 <= j1 + 2) load_row<T, V>(q2, A.u, j + 3, A.n, A.P, c.i0, c.vin);
+        if (j + 2 <= j1 + 1) load_row<T, V>(fq2, A.f, j + 2, A.n, A.P, c.i0, c.vin);
         residual_row<T, V>(r0, um, uc, up, fr, (j >= 1) && (j <= A.n - 2), c, A.cx, A.cy, A.d);
         if ((j & 1) && j >= j0 + 2) {
             const int J = (j - 1) >> 1;               // coarse row at fine row j-1
@@ -431,19 +470,21 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs<T> A) {
     const int j0 = 1 + chunk * A.tl.ty;
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
 
-    T um[V], uc[V], up[V], un[V], fr[V], fn[V], r[V];
+    T um[V], uc[V], up[V], q1[V], q2[V], fr[V], fq1[V], fq2[V], r[V];
     double s2 = 0.0, mx = 0.0;
     load_row<T, V>(um, A.u, j0 - 1, A.n, A.P, c.i0, c.vin);
     load_row<T, V>(uc, A.u, j0, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(un, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(fn, A.f, j0, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(q1, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(q2, A.u, j0 + 2, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(fq1, A.f, j0, A.n, A.P, c.i0, c.vin);
+    load_row<T, V>(fq2, A.f, j0 + 1, A.n, A.P, c.i0, c.vin);
     for (int j = j0; j <= j1; ++j) {
-        copy<T, V>(up, un);
-        copy<T, V>(fr, fn);
-        if (j < j1) {
-            load_row<T, V>(un, A.u, j + 2, A.n, A.P, c.i0, c.vin);
-            load_row<T, V>(fn, A.f, j + 1, A.n, A.P, c.i0, c.vin);
-        }
+        copy<T, V>(up, q1);
+        copy<T, V>(fr, fq1);
+        copy<T, V>(q1, q2);
+        copy<T, V>(fq1, fq2);
+        if (j + 3 <= j1 + 1) load_row<T, V>(q2, A.u, j + 3, A.n, A.P, c.i0, c.vin);
+        if (j + 2 <= j1) load_row<T, V>(fq2, A.f, j + 2, A.n, A.P, c.i0, c.vin);
         residual_row<T, V>(r, um, uc, up, fr, true, c, A.cx, A.cy, A.d);
         if (A.r != nullptr) store_row<T, V>(A.r, r, j, A.P, c);
         if (A.partials != nullptr) {
@@ -506,20 +547,22 @@ __global__ __launch_bounds__(kBlock) void k_defect(DefectArgs A) {
     const int j0 = 1 + chunk * A.tl.ty;
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
 
-    double um[V], uc[V], up[V], un[V], fr[V], fn[V], r[V];
+    double um[V], uc[V], up[V], q1[V], q2[V], fr[V], fq1[V], fq2[V], r[V];
     float r32[V];
     double s2 = 0.0, mx = 0.0;
     defect_load<V>(um, A, j0 - 1, c);
     defect_load<V>(uc, A, j0, c);
-    defect_load<V>(un, A, j0 + 1, c);
-    load_row<double, V>(fn, A.f, j0, A.n, A.P, c.i0, c.vin);
+    defect_load<V>(q1, A, j0 + 1, c);
+    defect_load<V>(q2, A, j0 + 2, c);
+    load_row<double, V>(fq1, A.f, j0, A.n, A.P, c.i0, c.vin);
+    load_row<double, V>(fq2, A.f, j0 + 1, A.n, A.P, c.i0, c.vin);
     for (int j = j0; j <= j1; ++j) {
-        copy<double, V>(up, un);
-        copy<double, V>(fr, fn);
-        if (j < j1) {
-            defect_load<V>(un, A, j + 2, c);
-            load_row<double, V>(fn, A.f, j + 1, A.n, A.P, c.i0, c.vin);
-        }
+        copy<double, V>(up, q1);
+        copy<double, V>(fr, fq1);
+        copy<double, V>(q1, q2);
+        copy<double, V>(fq1, fq2);
+        if (j + 3 <= j1 + 1) defect_load<V>(q2, A, j + 3, c);
+        if (j + 2 <= j1) load_row<double, V>(fq2, A.f, j + 2, A.n, A.P, c.i0, c.vin);
         residual_row<double, V>(r, um, uc, up, fr, true, c, A.cx, A.cy, A.d);
         if (A.psi_out != A.psi_in || A.e != nullptr) store_row<double, V>(A.psi_out, uc, j, A.P, c);
 #pragma unroll
@@ -673,6 +716,43 @@ __global__ void k_gather_ctrl(Ctrl* const* src, Ctrl* dst, int count) {
 hipError_t launch_gather_ctrl(Ctrl* const* src, Ctrl* dst, int count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     k_gather_ctrl<<<(count + 255) / 256, 256, 0, s>>>(src, dst, count);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- stream copy
+// Plain streaming copy (16-byte vectors, grid-stride): the achievable HBM
+// bandwidth reference for the roofline and the byte counter calibration.
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                        size_t nvec) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvec; k += stride) dst[k] = src[k];
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks, hipStream_t s) {
+    const size_t nvec = bytes / 16;
+    if (nvec == 0) return hipSuccess;
+    k_stream_copy<<<blocks, kBlock, 0, s>>>((const double2*)src, (double2*)dst, nvec);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- field upload/copy
+// Dense (m-pitched) FP64 field -> one or two pitched fields (perimeter included).
+__global__ __launch_bounds__(kBlock) void k_write_field(const double* __restrict__ src, double* __restrict__ d0,
+                                                        double* __restrict__ d1, int m, int n, int P) {
+    const size_t total = (size_t)m * n;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t j = k / (size_t)m, i = k - j * (size_t)m;
+        const double v = src[k];
+        d0[j * P + i] = v;
+        if (d1 != nullptr) d1[j * P + i] = v;
+    }
+}
+
+hipError_t launch_write_field(const double* src, double* d0, double* d1, int m, int n, int P, hipStream_t s) {
+    const size_t total = (size_t)m * n;
+    int nb = (int)std::min<size_t>((total + kBlock - 1) / kBlock, 8192);
+    if (nb < 1) nb = 1;
+    k_write_field<<<nb, kBlock, 0, s>>>(src, d0, d1, m, n, P);
     return hipGetLastError();
 }
 
