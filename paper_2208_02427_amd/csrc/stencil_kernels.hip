@@ -151,6 +151,12 @@ struct Prolong {
 #pragma unroll
         for (int q = 0; q < V2; ++q) x[q] = v[q];
         x[V2] = __shfl_down(v[0], 1);
+        // the last lane has no right neighbour, but its halo columns still need
+        // coarse column I0 + V2 (the sweep reads the window's last column)
+        if ((threadIdx.x & 63) == 63) {
+            const int I = I0 + V2;
+            x[V2] = (J >= 0 && J < nc && I >= 0 && I < Pc) ? ec[(size_t)J * Pc + I] : T(0);
+        }
     }
     __device__ __forceinline__ void init(const T* ec, int j, int nc, int Pc, int i0) {
         Jcur = j >> 1;
@@ -167,25 +173,31 @@ struct Prolong {
             load_coarse(hi, ec, Jcur + 1, nc, Pc, i0 >> 1);
         }
         if (j < 0 || j >= n) return;
-        const int t = j & 1;
-        const int I0 = i0 >> 1;
+        const bool t = (j & 1) != 0;                  // wave-uniform
+        // branch-free: every lane evaluates the same instructions; for even V
+        // the coarse index and the column parity of element e are compile-time
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             const int i = i0 + e;
-            const int q = (i >> 1) - I0;           // 0..V2-1
-            const int s = i & 1;
-            const T e00 = lo[q], e10 = lo[q + 1], e01 = hi[q], e11 = hi[q + 1];
-            T p;
-            if (!s && !t) {
-                p = e00;
-            } else if (s && !t) {
-                p = (e00 + e10) * T(0.5);
-            } else if (!s && t) {
-                p = (e00 + e01) * T(0.5);
+            T e00, e10, e01, e11;
+            bool s;
+            if constexpr (V % 2 == 0) {
+                s = (e & 1) != 0;
+                e00 = lo[e >> 1];
+                e10 = lo[(e >> 1) + 1];
+                e01 = hi[e >> 1];
+                e11 = hi[(e >> 1) + 1];
             } else {
-                p = ((e00 + e10) + (e01 + e11)) * T(0.25);
+                s = (i & 1) != 0;                      // V == 1: q = 0 for every lane
+                e00 = lo[0];
+                e10 = lo[1];
+                e01 = hi[0];
+                e11 = hi[1];
             }
-            if (i >= 0 && i < m) x[e] = x[e] + p;
+            const T p_even = t ? (e00 + e01) * T(0.5) : e00;
+            const T p_odd = t ? ((e00 + e10) + (e01 + e11)) * T(0.25) : (e00 + e10) * T(0.5);
+            const T p = s ? p_odd : p_even;
+            x[e] = (i >= 0 && i < m) ? x[e] + p : x[e];
         }
     }
 };
