@@ -25,9 +25,8 @@
 namespace lap {
 
 // ------------------------------------------------------------------ columns
-__global__ __launch_bounds__(kBlock) void k_adi_cols(LineArgs A) {
-    if (A.ctrl != nullptr && A.ctrl->done) return;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// Column line number t of the parity in A (no-op past the last line).
+static __device__ void adi_col_line(const LineArgs& A, int t) {
     const int i = (A.parity ? 1 : 2) + 2 * t;
     if (i > A.m - 2) return;
     const int K = A.n - 2;
@@ -63,6 +62,11 @@ __global__ __launch_bounds__(kBlock) void k_adi_cols(LineArgs A) {
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_adi_cols(LineArgs A) {
+    if (A.ctrl != nullptr && A.ctrl->done) return;
+    adi_col_line(A, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s) {
     const int first = a.parity ? 1 : 2;
     const int lines = a.m - 2 >= first ? (a.m - 2 - first) / 2 + 1 : 0;
@@ -73,16 +77,15 @@ hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------- rows
-constexpr int kRowTile = 64;
 
-__global__ __launch_bounds__(64) void k_adi_rows(LineArgs A) {
-    if (A.ctrl != nullptr && A.ctrl->done) return;
-    __shared__ double tile[kRowTile][kRowTile + 1];
-    __shared__ double told[kRowTile][kRowTile + 1];
+// Row lines 64*blk .. 64*blk+63 of the parity in A, one lane per line
+// (block of 64 threads; tile / told are LDS scratch of 64 x 65 doubles).
+static __device__ void adi_rows_block(const LineArgs& A, int blk, double (*tile)[kRowTile + 1],
+                               double (*told)[kRowTile + 1]) {
     const int lane = threadIdx.x;
     const int first = A.parity ? 1 : 2;
     const int nlines = A.n - 2 >= first ? (A.n - 2 - first) / 2 + 1 : 0;
-    const int line0 = blockIdx.x * kRowTile;
+    const int line0 = blk * kRowTile;
     const int mylines = min(kRowTile, nlines - line0);
     const int K = A.m - 2;
     const size_t P = (size_t)A.P;
@@ -153,12 +156,80 @@ __global__ __launch_bounds__(64) void k_adi_rows(LineArgs A) {
     }
 }
 
+__global__ __launch_bounds__(64) void k_adi_rows(LineArgs A) {
+    if (A.ctrl != nullptr && A.ctrl->done) return;
+    __shared__ double tile[kRowTile][kRowTile + 1];
+    __shared__ double told[kRowTile][kRowTile + 1];
+    adi_rows_block(A, blockIdx.x, tile, told);
+}
+
 hipError_t launch_adi_rows(const LineArgs& a, hipStream_t s) {
     const int first = a.parity ? 1 : 2;
     const int lines = a.n - 2 >= first ? (a.n - 2 - first) / 2 + 1 : 0;
     if (lines <= 0) return hipSuccess;
     const int nb = (lines + kRowTile - 1) / kRowTile;
     k_adi_rows<<<nb, kRowTile, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- merged batch launches
+__device__ __forceinline__ int find_item(const BatchItem* it, int count, int t) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (it[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ LineArgs line_args(const BatchItem& it) {
+    LineArgs a{};
+    a.u = (double*)it.out;
+    a.f = (const double*)it.f;
+    a.scratch = it.scratch;
+    a.cprime = it.cprime;
+    a.piv = it.piv;
+    a.ctrl = nullptr;
+    a.m = it.m;
+    a.n = it.n;
+    a.P = it.P;
+    a.cx = it.cx;
+    a.cy = it.cy;
+    a.d = it.d;
+    a.omega = it.omega;
+    a.a_off = it.a_off;
+    a.form = it.flags;
+    a.parity = it.parity;
+    return a;
+}
+
+// Row lines of all grids: one 64-lane block per 64-line block of a grid,
+// the grid loops over all (grid, line block) tiles.
+__global__ __launch_bounds__(64) void k_batch_adi_rows(const BatchItem* items, int count, int total) {
+    __shared__ double tile[kRowTile][kRowTile + 1];
+    __shared__ double told[kRowTile][kRowTile + 1];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const BatchItem& it = items[find_item(items, count, t)];
+        if (it.ctrl->done) continue;
+        adi_rows_block(line_args(it), t - it.tile0, tile, told);
+    }
+}
+
+// Column lines of all grids: one thread per line, 256 lines per tile.
+__global__ __launch_bounds__(kBlock) void k_batch_adi_cols(const BatchItem* items, int count, int total) {
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const BatchItem& it = items[find_item(items, count, t)];
+        if (it.ctrl->done) continue;
+        adi_col_line(line_args(it), (t - it.tile0) * kBlock + threadIdx.x);
+    }
+}
+
+hipError_t launch_batch_adi(int kind, const BatchItem* items, int count, int total, int blocks, hipStream_t s) {
+    if (total <= 0 || count <= 0) return hipSuccess;
+    if (kind == BK_ADI_ROWS)
+        k_batch_adi_rows<<<blocks, kRowTile, 0, s>>>(items, count, total);
+    else
+        k_batch_adi_cols<<<blocks, kBlock, 0, s>>>(items, count, total);
     return hipGetLastError();
 }
 

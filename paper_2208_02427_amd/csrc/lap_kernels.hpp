@@ -66,6 +66,12 @@ inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0) {
     return t;
 }
 
+// Fixed tiling of every kernel that produces norm partials (the first
+// pre-sweep with norms, residual norms, the FP64 defect correction): the
+// partial sums, and so the stopping decisions, then do not depend on the
+// tuning table or on whether the grid runs alone or inside a batch.
+inline Tiling norm_tiling(int m, int n) { return make_tiling(m, n, 1, 0, 16384); }
+
 // Blocks of 4 waves; the grid is padded to a multiple of the XCD count so
 // the XCD-aware remap below is a bijection.
 inline int blocks_for(const Tiling& t) {
@@ -198,7 +204,38 @@ struct LineArgs {
     int form;                // 0 relax after, 1 relax inside
     int parity;              // 1: odd lines, 0: even lines
 };
+constexpr int kRowTile = 64;   // row lines per ADI row block
 hipError_t launch_adi_rows(const LineArgs& a, hipStream_t s);
 hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s);
+
+// ---- merged ragged-batch launches (batch_kernels.hip) ----
+// One grid's share of a merged launch: the arguments of the single-grid
+// kernel plus its tiling and the offset of its first tile in the launch.
+struct BatchItem {
+    const void* in;          // sweep input / residual u / defect psi_in / coarse boundary source
+    void* out;               // sweep / coarse output, defect psi_out
+    const void* f;           // right-hand side
+    const void* ec;          // sweep: coarse correction; defect: FP32 correction
+    void* bc;                // restrict: coarse right-hand side; defect: FP32 rhs
+    const double* minv;      // coarse solve
+    double* partials;        // norm partials
+    Ctrl* ctrl;
+    double* scratch;         // ADI
+    const double* cprime;
+    const double* piv;
+    int m, n, P, mc, nc, Pc;
+    double cx, cy, d, inv_d, omega, a_off;
+    int V, ty, nwin, nchunk;
+    int ntiles, tile0;       // tiles (or line blocks) of this item; prefix offset in the launch
+    int flags;               // SW_F for sweeps; ADI relaxation form
+    int parity;              // ADI line parity
+};
+
+enum BatchKind { BK_SWEEP = 0, BK_RESTRICT, BK_COARSE, BK_FINALIZE, BK_RESNORM, BK_DEFECT, BK_ADI_ROWS, BK_ADI_COLS };
+// Launch one merged operation over `count` items (device array) covering
+// `total` tiles with a persistent grid of `blocks` workgroups.
+hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items, int count, int total, int blocks,
+                        hipStream_t s);
+hipError_t launch_batch_adi(int kind, const BatchItem* items, int count, int total, int blocks, hipStream_t s);
 
 }  // namespace lap

@@ -240,6 +240,9 @@ struct lap_ctx {
     Ctrl* batch_ctrl = nullptr;
     Ctrl* batch_host = nullptr;
     std::vector<Ctrl*> batch_ptrs_host;
+    // merged-launch plans of batches, by composition key (grid set, step parity, options)
+    struct Plan;
+    std::vector<std::pair<std::string, Plan*>> plans;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
 
     hipEvent_t ev() {
@@ -287,6 +290,10 @@ struct lap_ctx {
         return make_tiling(m, n, tileV[sc][cls][dt], tileTY[sc][cls][dt], tileT[sc][cls][dt]);
     }
 };
+
+namespace {
+void plans_clear(lap_ctx* c);   // batch plans (defined with the batch executor)
+}
 
 // ========================================================================= grid
 struct lap_grid {
@@ -412,7 +419,7 @@ SweepArgs<T> sweep_args(lap_grid* g, int l, const T* in, T* out, const T* f, con
     a.d = (T)c.d;
     a.inv_d = (T)c.inv_d;
     a.omega = (T)omega;
-    a.tl = g->ctx->tiling(L.m, L.n, ec ? KC_SWEEP_PROLONG : KC_SWEEP, dt_of<T>());
+    a.tl = norm ? norm_tiling(L.m, L.n) : g->ctx->tiling(L.m, L.n, ec ? KC_SWEEP_PROLONG : KC_SWEEP, dt_of<T>());
     return a;
 }
 
@@ -494,21 +501,70 @@ hipError_t enq_residual_norm(lap_grid* g, int l, const T* u, const T* f) {
     a.cx = (T)c.cx;
     a.cy = (T)c.cy;
     a.d = (T)c.d;
-    a.tl = g->ctx->tiling(L.m, L.n, KC_RESIDUAL, dt_of<T>());
-    HIPERR(g->ctx->timed(KC_RESIDUAL, l == 0, (f ? 2.0 : 1.0) * sizeof(T) * nint(L),
-                         [&]() { return launch_residual<T>(a, g->ctx->stream); }));
-    return enq_finalize(g, a.tl.ntiles);
+    a.tl = norm_tiling(L.m, L.n);
+    return g->ctx->timed(KC_RESIDUAL, l == 0, (f ? 2.0 : 1.0) * sizeof(T) * nint(L),
+                         [&]() { return launch_residual<T>(a, g->ctx->stream); });
+}
+
+// ---------------------------------------------------------------- op plans
+// A step of a method is first recorded as a list of operations, each with a
+// merge key; the single-grid executor launches them in order, and the batch
+// executor launches all grids' operations of one key as one merged launch.
+// Keys order a V-cycle top-aligned across grids of different depth: the
+// pre-smoothing and restriction of level l, then every grid's coarsest
+// solve, then the post-smoothing of level l from coarse to fine.
+enum OpKind { OP_SWEEP, OP_RESTRICT, OP_COARSE, OP_FINALIZE, OP_RESNORM, OP_DEFECT, OP_ADI_ROWS, OP_ADI_COLS };
+
+struct Op {
+    long key;
+    int kind;
+    int dt;          // 0 FP64, 1 FP32
+    int level;
+    int flags;       // sweep flags
+    const void* in;  // sweep input, restrict / residual u, defect psi_in, coarse boundary source
+    void* out;       // sweep / coarse output, defect psi_out
+    const void* f;   // right-hand side
+    const void* ec;  // sweep: coarse correction; defect: FP32 correction
+    void* bc;        // restrict: coarse right-hand side
+    double omega;
+    int parity;      // ADI line parity
+};
+
+constexpr long KEY_HEAD = 10;
+// (the stopping test's finalise must sit between the first and the second
+// pre-smoothing sweep: keys of a grid increase along its own operation order)
+inline long key_pre(int l, int k) { return 1000 + 100L * l + 2L * k; }
+inline long key_norm_fin(int l) { return 1000 + 100L * l + 1; }
+inline long key_restrict(int l) { return 1000 + 100L * l + 99; }
+constexpr long KEY_COARSE = 20000;
+inline long key_post(int l, int k) { return 30000 + 100L * (99 - l) + k; }
+
+template <typename T>
+void push_op(std::vector<Op>& ops, long key, int kind, int level, int flags, const void* in, void* out,
+             const void* f, const void* ec, void* bc, double omega, int parity = 0) {
+    Op op;
+    op.key = key;
+    op.kind = kind;
+    op.dt = dt_of<T>();
+    op.level = level;
+    op.flags = flags;
+    op.in = in;
+    op.out = out;
+    op.f = f;
+    op.ec = ec;
+    op.bc = bc;
+    op.omega = omega;
+    op.parity = parity;
+    ops.push_back(op);
 }
 
 // One V-cycle on level l of hierarchy H.  Level 0 either holds the iterate in
 // u0[0] (FP64 multigrid: the result returns to u0[0] since nu1+nu2 is even)
 // or starts from zero (error equation).  Returns the buffer index (0/1)
-// that holds the level's result.
+// that holds the level's result.  `part` (level 0 with a norm only):
+// PART_HEAD records the stopping test of the incoming iterate, PART_TAIL the rest.
 template <typename T>
-hipError_t enq_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm, int& res_idx,
-                      int part = PART_ALL) {
-    // part (level 0 with norm only): PART_HEAD enqueues the stopping test of
-    // the incoming iterate (its first kernel + finalise), PART_TAIL the rest.
+int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm, int part, std::vector<Op>& ops) {
     const int L = (int)g->geo.size();
     const bool zero_start = (l > 0) || H.zero_start0;
     const bool split = norm && !zero_start;
@@ -517,51 +573,58 @@ hipError_t enq_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, boo
     T* U[2] = {H.u0[l], H.u1[l]};
     const T* b = H.b[l];
     if (l == L - 1) {
-        if (split && head) HIPERR(enq_residual_norm<T>(g, l, U[0], b));
-        if (tail) HIPERR(enq_coarse<T>(g, l, zero_start ? nullptr : U[0], b, U[0]));
-        res_idx = 0;
-        return hipSuccess;
+        if (split && head) {
+            push_op<T>(ops, KEY_HEAD, OP_RESNORM, l, 0, U[0], nullptr, b, nullptr, nullptr, 0.0);
+            push_op<T>(ops, KEY_HEAD + 1, OP_FINALIZE, l, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0);
+        }
+        if (tail) push_op<T>(ops, KEY_COARSE, OP_COARSE, l, 0, zero_start ? nullptr : U[0], U[0], b, nullptr,
+                             nullptr, 0.0);
+        return 0;
     }
     const int fb = b ? SW_F : 0;
     int cur = 0;
     bool have_u = !zero_start;
     if (split && o.nu1 == 0) {
-        if (head) HIPERR(enq_residual_norm<T>(g, l, U[0], b));
-        if (!tail) return hipSuccess;
+        if (head) {
+            push_op<T>(ops, KEY_HEAD, OP_RESNORM, l, 0, U[0], nullptr, b, nullptr, nullptr, 0.0);
+            push_op<T>(ops, KEY_HEAD + 1, OP_FINALIZE, l, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0);
+        }
+        if (!tail) return 0;
     }
     for (int k = 0; k < o.nu1; ++k) {
         if (!have_u) {
-            HIPERR(enq_sweep<T>(g, l, nullptr, U[0], b, nullptr, o.omega, SW_ZERO | fb));
+            push_op<T>(ops, key_pre(l, k), OP_SWEEP, l, SW_ZERO | fb, nullptr, U[0], b, nullptr, nullptr, o.omega);
             cur = 0;
             have_u = true;
         } else {
             const bool nk = split && k == 0;
             if (!nk || head) {
-                HIPERR(enq_sweep<T>(g, l, U[cur], U[1 - cur], b, nullptr, o.omega, fb | (nk ? SW_NORM : 0)));
+                push_op<T>(ops, key_pre(l, k), OP_SWEEP, l, fb | (nk ? SW_NORM : 0), U[cur], U[1 - cur], b, nullptr,
+                           nullptr, o.omega);
                 if (nk)
-                    HIPERR(enq_finalize(g, g->ctx->tiling(g->geo[l].m, g->geo[l].n, KC_SWEEP, dt_of<T>()).ntiles));
+                    push_op<T>(ops, key_norm_fin(l), OP_FINALIZE, l, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               0.0);
             }
             cur = 1 - cur;
-            if (nk && !tail) return hipSuccess;
+            if (nk && !tail) return 0;
         }
     }
-    HIPERR(enq_restrict<T>(g, l, have_u ? U[cur] : nullptr, b, H.b[l + 1]));
-    int cres = 0;
-    HIPERR(enq_vcycle<T>(g, H, l + 1, o, false, cres));
+    push_op<T>(ops, key_restrict(l), OP_RESTRICT, l, 0, have_u ? U[cur] : nullptr, nullptr, b, nullptr, H.b[l + 1],
+               0.0);
+    const int cres = plan_vcycle<T>(g, H, l + 1, o, false, PART_ALL, ops);
     const T* ec = (cres == 0 ? H.u0[l + 1] : H.u1[l + 1]);
     for (int k = 0; k < o.nu2; ++k) {
         if (k == 0) {
-            HIPERR(enq_sweep<T>(g, l, have_u ? U[cur] : nullptr, U[have_u ? 1 - cur : 0], b, ec, o.omega,
-                                SW_PROLONG | fb));
+            push_op<T>(ops, key_post(l, k), OP_SWEEP, l, SW_PROLONG | fb, have_u ? U[cur] : nullptr,
+                       U[have_u ? 1 - cur : 0], b, ec, nullptr, o.omega);
             cur = have_u ? 1 - cur : 0;
             have_u = true;
         } else {
-            HIPERR(enq_sweep<T>(g, l, U[cur], U[1 - cur], b, nullptr, o.omega, fb));
+            push_op<T>(ops, key_post(l, k), OP_SWEEP, l, fb, U[cur], U[1 - cur], b, nullptr, nullptr, o.omega);
             cur = 1 - cur;
         }
     }
-    res_idx = cur;
-    return hipSuccess;
+    return cur;
 }
 
 HierView<double> view64(lap_grid* g) {
@@ -597,12 +660,12 @@ HierView<float> view32(lap_grid* g) {
     return H;
 }
 
-hipError_t enq_defect(lap_grid* g, int in_idx, const float* e) {
+hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const float* e) {
     const LevelGeo& L = g->geo[0];
     const Coef c = coef(L.dx, L.dy);
     DefectArgs a{};
-    a.psi_in = g->psi[in_idx];
-    a.psi_out = g->psi[1 - in_idx];
+    a.psi_in = psi_in;
+    a.psi_out = psi_out;
     a.e = e;
     a.f = g->f64;
     a.rhs = g->l32[0].b;
@@ -614,10 +677,9 @@ hipError_t enq_defect(lap_grid* g, int in_idx, const float* e) {
     a.cx = c.cx;
     a.cy = c.cy;
     a.d = c.d;
-    a.tl = g->ctx->tiling(L.m, L.n, KC_DEFECT, 0);
+    a.tl = norm_tiling(L.m, L.n);
     const double per = 8.0 + (e ? 4.0 : 0.0) + (g->f64 ? 8.0 : 0.0) + 8.0 + 4.0;
-    HIPERR(g->ctx->timed(KC_DEFECT, true, per * nint(L), [&]() { return launch_defect(a, g->ctx->stream); }));
-    return enq_finalize(g, a.tl.ntiles);
+    return g->ctx->timed(KC_DEFECT, true, per * nint(L), [&]() { return launch_defect(a, g->ctx->stream); });
 }
 
 // Buffer (0/1) in which a zero-start V-cycle leaves its level result.
@@ -630,15 +692,17 @@ int vcycle_result_index(const lap_opts& o) {
 // One outer step of the mixed loop: defect correction (adds the previous
 // FP32 correction, forms the FP64 residual, tests it), then one FP32
 // V-cycle on the error equation.
-hipError_t enq_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int& e_idx,
-                          int part = PART_ALL) {
+void plan_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int e_idx, int part,
+                     std::vector<Op>& ops) {
     if (part != PART_TAIL) {
         const float* e = first ? nullptr : (e_idx == 0 ? g->l32[0].u[0] : g->l32[0].u[1]);
-        HIPERR(enq_defect(g, in_idx, e));
+        push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, g->psi[in_idx], g->psi[1 - in_idx], g->f64, e,
+                        g->l32[0].b, 0.0);
+        push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0);
     }
-    if (part == PART_HEAD) return hipSuccess;
+    if (part == PART_HEAD) return;
     HierView<float> H = view32(g);
-    return enq_vcycle<float>(g, H, 0, o, false, e_idx);
+    plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops);
 }
 
 // ------------------------------------------------------------------ ADI
@@ -652,7 +716,7 @@ void adi_factor(double b, double a, double c, int K, double* cp, double* piv) {
     }
 }
 
-hipError_t enq_adi_iteration(lap_grid* g, const lap_opts& o) {
+LineArgs adi_args(lap_grid* g, double omega, int form, int dir, int parity) {
     const LevelGeo& L = g->geo[0];
     const Coef c = coef(L.dx, L.dy);
     const int mk = g->adi_maxk;
@@ -667,23 +731,63 @@ hipError_t enq_adi_iteration(lap_grid* g, const lap_opts& o) {
     a.cx = c.cx;
     a.cy = c.cy;
     a.d = c.d;
-    a.omega = o.omega;
-    a.form = o.adi_form;
-    const double per = (g->f64 ? 48.0 : 40.0) * 0.5 * nint(L);
-    a.cprime = g->adi_tab;
-    a.piv = g->adi_tab + mk;
-    a.a_off = o.adi_form == 0 ? -c.cx : -o.omega * c.cx;
-    for (int par : {1, 0}) {
-        a.parity = par;
-        HIPERR(g->ctx->timed(KC_ADI_ROWS, true, per, [&]() { return launch_adi_rows(a, g->ctx->stream); }));
+    a.omega = omega;
+    a.form = form;
+    a.parity = parity;
+    if (dir == 0) {
+        a.cprime = g->adi_tab;
+        a.piv = g->adi_tab + mk;
+        a.a_off = form == 0 ? -c.cx : -omega * c.cx;
+    } else {
+        a.cprime = g->adi_tab + 2 * mk;
+        a.piv = g->adi_tab + 3 * mk;
+        a.a_off = form == 0 ? -c.cy : -omega * c.cy;
     }
-    a.cprime = g->adi_tab + 2 * mk;
-    a.piv = g->adi_tab + 3 * mk;
-    a.a_off = o.adi_form == 0 ? -c.cy : -o.omega * c.cy;
-    for (int par : {1, 0}) {
-        a.parity = par;
-        HIPERR(g->ctx->timed(KC_ADI_COLS, true, per, [&]() { return launch_adi_cols(a, g->ctx->stream); }));
+    return a;
+}
+
+hipError_t enq_adi_half(lap_grid* g, double omega, int form, int dir, int parity) {
+    const LineArgs a = adi_args(g, omega, form, dir, parity);
+    const double per = (g->f64 ? 48.0 : 40.0) * 0.5 * nint(g->geo[0]);
+    if (dir == 0)
+        return g->ctx->timed(KC_ADI_ROWS, true, per, [&]() { return launch_adi_rows(a, g->ctx->stream); });
+    return g->ctx->timed(KC_ADI_COLS, true, per, [&]() { return launch_adi_cols(a, g->ctx->stream); });
+}
+
+// Launch one recorded operation of grid g.
+hipError_t exec_op(lap_grid* g, const Op& op) {
+    const int l = op.level;
+    switch (op.kind) {
+        case OP_SWEEP:
+            if (op.dt == 0)
+                return enq_sweep<double>(g, l, (const double*)op.in, (double*)op.out, (const double*)op.f,
+                                         (const double*)op.ec, op.omega, op.flags);
+            return enq_sweep<float>(g, l, (const float*)op.in, (float*)op.out, (const float*)op.f,
+                                    (const float*)op.ec, op.omega, op.flags);
+        case OP_RESTRICT:
+            if (op.dt == 0)
+                return enq_restrict<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.bc);
+            return enq_restrict<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.bc);
+        case OP_COARSE:
+            if (op.dt == 0)
+                return enq_coarse<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.out);
+            return enq_coarse<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.out);
+        case OP_FINALIZE:
+            return enq_finalize(g, norm_tiling(g->geo[0].m, g->geo[0].n).ntiles);
+        case OP_RESNORM:
+            return enq_residual_norm<double>(g, l, (const double*)op.in, (const double*)op.f);
+        case OP_DEFECT:
+            return enq_defect(g, (const double*)op.in, (double*)op.out, (const float*)op.ec);
+        case OP_ADI_ROWS:
+            return enq_adi_half(g, op.omega, op.flags, 0, op.parity);
+        case OP_ADI_COLS:
+            return enq_adi_half(g, op.omega, op.flags, 1, op.parity);
     }
+    return hipErrorInvalidValue;
+}
+
+hipError_t exec_ops(lap_grid* g, const std::vector<Op>& ops) {
+    for (const Op& op : ops) HIPERR(exec_op(g, op));
     return hipSuccess;
 }
 
@@ -826,16 +930,18 @@ lap_status prepare(lap_grid* g, const lap_opts& o) {
             snprintf(key, sizeof key, "mg64:%d:%d:%.17g", o.nu1, o.nu2, o.omega);
             e = capture(g, key, [&]() {
                 HierView<double> H = view64(g);
-                int ri = 0;
-                return enq_vcycle<double>(g, H, 0, o, true, ri);
+                std::vector<Op> ops;
+                plan_vcycle<double>(g, H, 0, o, true, PART_ALL, ops);
+                return exec_ops(g, ops);
             });
         } else {
             // two outer steps (psi[1] -> psi[0] -> psi[1]); step 0 runs without the graph
             snprintf(key, sizeof key, "mixed:%d:%d:%.17g", o.nu1, o.nu2, o.omega);
             e = capture(g, key, [&]() {
-                int ei = vcycle_result_index(o);
-                HIPERR(enq_mixed_step(g, o, 1, false, ei));
-                return enq_mixed_step(g, o, 0, false, ei);
+                std::vector<Op> ops;
+                plan_mixed_step(g, o, 1, false, g->e_idx, PART_ALL, ops);
+                plan_mixed_step(g, o, 0, false, g->e_idx, PART_ALL, ops);
+                return exec_ops(g, ops);
             });
         }
         if (e != hipSuccess) return fail(LAP_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -843,48 +949,64 @@ lap_status prepare(lap_grid* g, const lap_opts& o) {
     return LAP_OK;
 }
 
-// Enqueue outer step number g->step_idx.  PART_ALL enqueues the whole step
-// (and advances step_idx); PART_HEAD only its stopping test of the incoming
-// iterate, PART_TAIL the rest (and advances step_idx).
+// Record outer step s of grid g (SOR / ADI: one check block; MG: one cycle;
+// mixed: one defect correction + FP32 cycle).  PART_ALL records the whole
+// step, PART_HEAD only its stopping test of the incoming iterate, PART_TAIL
+// the rest.
+void plan_step(lap_grid* g, const lap_opts& o, int s, int part, std::vector<Op>& ops) {
+    switch (o.method) {
+        case LAP_MG:
+            if (o.precision == LAP_FP64) {
+                HierView<double> H = view64(g);
+                plan_vcycle<double>(g, H, 0, o, true, part, ops);
+            } else {
+                plan_mixed_step(g, o, s % 2, s == 0, g->e_idx, part, ops);
+            }
+            return;
+        case LAP_SOR_RB: {
+            const int fb = g->f64 ? SW_F : 0;
+            for (int k = (part == PART_TAIL ? 1 : 0); k < (part == PART_HEAD ? 1 : o.check_every); ++k) {
+                const int cur = (s * o.check_every + k) % 2;
+                push_op<double>(ops, key_pre(0, 0) + 2L * k, OP_SWEEP, 0, fb | (k == 0 ? SW_NORM : 0), g->psi[cur],
+                                g->psi[1 - cur], g->f64, nullptr, nullptr, o.omega);
+                if (k == 0)
+                    push_op<double>(ops, key_pre(0, 0) + 1, OP_FINALIZE, 0, 0, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr, 0.0);
+            }
+            return;
+        }
+        case LAP_ADI:
+            if (part != PART_TAIL) {
+                push_op<double>(ops, KEY_HEAD, OP_RESNORM, 0, 0, g->psi[0], nullptr, g->f64, nullptr, nullptr, 0.0);
+                push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                0.0);
+            }
+            if (part != PART_HEAD)
+                for (int k = 0; k < o.check_every; ++k)
+                    for (int q = 0; q < 4; ++q)
+                        push_op<double>(ops, 1000 + 4L * k + q, q < 2 ? OP_ADI_ROWS : OP_ADI_COLS, 0, o.adi_form,
+                                        nullptr, nullptr, nullptr, nullptr, nullptr, o.omega, (q % 2) ? 0 : 1);
+            return;
+    }
+}
+
+// Enqueue outer step number g->step_idx (single grid).  PART_HEAD does not
+// advance step_idx; PART_ALL and PART_TAIL do.
 hipError_t step(lap_grid* g, const lap_opts& o, int part = PART_ALL) {
     const int s = g->step_idx;
     if (part != PART_HEAD) g->step_idx++;
     lap_ctx* c = g->ctx;
     const bool graph = use_graph(g, o) && part == PART_ALL;
-    switch (o.method) {
-        case LAP_MG:
-            if (o.precision == LAP_FP64) {
-                if (graph) return hipGraphLaunch(g->graph, c->stream);
-                HierView<double> H = view64(g);
-                int ri = 0;
-                return enq_vcycle<double>(g, H, 0, o, true, ri, part);
-            } else {
-                // step s reads psi[s % 2]; the graph covers the pair (odd s, even s)
-                if (s == 0) return enq_mixed_step(g, o, 0, true, g->e_idx, part);
-                if (graph && s % 2 == 1) {
-                    g->step_idx++;   // the graph also runs step s + 1
-                    return hipGraphLaunch(g->graph, c->stream);
-                }
-                return enq_mixed_step(g, o, s % 2, false, g->e_idx, part);
-            }
-        case LAP_SOR_RB: {
-            const int fb = g->f64 ? SW_F : 0;
-            const int ntl = c->tiling(g->m, g->n, KC_SWEEP, 0).ntiles;
-            for (int k = (part == PART_TAIL ? 1 : 0); k < (part == PART_HEAD ? 1 : o.check_every); ++k) {
-                const int cur = (s * o.check_every + k) % 2;
-                HIPERR(enq_sweep<double>(g, 0, g->psi[cur], g->psi[1 - cur], g->f64, nullptr, o.omega,
-                                         fb | (k == 0 ? SW_NORM : 0)));
-                if (k == 0) HIPERR(enq_finalize(g, ntl));
-            }
-            return hipSuccess;
+    if (graph && o.method == LAP_MG) {
+        if (o.precision == LAP_FP64) return hipGraphLaunch(g->graph, c->stream);
+        if (s % 2 == 1) {               // the mixed graph covers steps s (odd) and s + 1
+            g->step_idx++;
+            return hipGraphLaunch(g->graph, c->stream);
         }
-        case LAP_ADI:
-            if (part != PART_TAIL) HIPERR(enq_residual_norm<double>(g, 0, g->psi[0], g->f64));
-            if (part != PART_HEAD)
-                for (int k = 0; k < o.check_every; ++k) HIPERR(enq_adi_iteration(g, o));
-            return hipSuccess;
     }
-    return hipErrorInvalidValue;
+    std::vector<Op> ops;
+    plan_step(g, o, s, part, ops);
+    return exec_ops(g, ops);
 }
 
 // The tested iterate is the solution; bring it to psi[0] and make psi[1] equal.
@@ -1008,6 +1130,7 @@ lap_status lap_ctx_destroy(lap_ctx* c) {
     if (!c) return LAP_OK;
     hipStreamSynchronize(c->stream);
     while (!c->grids.empty()) lap_grid_destroy(c->grids.back());
+    plans_clear(c);
     for (auto& r : c->recs) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
@@ -1180,6 +1303,7 @@ lap_status lap_grid_destroy(lap_grid* g) {
     if (!g) return LAP_OK;
     lap_ctx* c = g->ctx;
     hipStreamSynchronize(c->stream);
+    plans_clear(c);   // cached batch plans may point into this grid
     if (g->graph) hipGraphExecDestroy(g->graph);
     for (void* p : g->allocs) c->arena.release(p);
     auto it = std::find(c->grids.begin(), c->grids.end(), g);
@@ -1251,7 +1375,7 @@ lap_status lap_residual_ex(lap_grid* g, double* l2, double* linf) {
     a.cx = c.cx;
     a.cy = c.cy;
     a.d = c.d;
-    a.tl = g->ctx->tiling(L.m, L.n, KC_RESIDUAL, 0);
+    a.tl = norm_tiling(L.m, L.n);
     HIPCHK(launch_residual<double>(a, g->ctx->stream));
     HIPCHK(launch_finalize(g->partials, a.tl.ntiles, nullptr, g->norm_out, 1, g->ctx->stream));
     double h[2];
@@ -1467,7 +1591,265 @@ extern "C" lap_status lap_op_adi_half(int32_t dtype, int32_t m, int32_t n, int32
 }
 
 // ------------------------------------------------------------------ batches
+struct MergedLaunch {
+    int kind, dt, flags;     // BatchKind, dtype, step flags of a sweep
+    int cls;                 // kernel class for timing
+    bool fine;
+    int count, total, blocks;
+    size_t off;              // first item in the plan's item array
+    double bytes;            // algorithmic bytes of the launch
+};
+
+struct lap_ctx::Plan {
+    std::vector<MergedLaunch> launches;
+    std::vector<BatchItem> items;
+    BatchItem* dev = nullptr;
+    hipGraphExec_t graph = nullptr;
+};
+
 namespace {
+
+void plan_free(lap_ctx* c, lap_ctx::Plan* p) {
+    if (!p) return;
+    if (p->graph) hipGraphExecDestroy(p->graph);
+    if (p->dev) c->arena.release(p->dev);
+    delete p;
+}
+
+void plans_clear(lap_ctx* c) {
+    hipStreamSynchronize(c->stream);
+    for (auto& kv : c->plans) plan_free(c, kv.second);
+    c->plans.clear();
+}
+
+int batch_kind(int op_kind) {
+    switch (op_kind) {
+        case OP_SWEEP: return BK_SWEEP;
+        case OP_RESTRICT: return BK_RESTRICT;
+        case OP_COARSE: return BK_COARSE;
+        case OP_FINALIZE: return BK_FINALIZE;
+        case OP_RESNORM: return BK_RESNORM;
+        case OP_DEFECT: return BK_DEFECT;
+        case OP_ADI_ROWS: return BK_ADI_ROWS;
+        case OP_ADI_COLS: return BK_ADI_COLS;
+    }
+    return -1;
+}
+
+// Fill the item of grid g for operation op (tiling, geometry, coefficients).
+BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o) {
+    lap_ctx* c = g->ctx;
+    const LevelGeo& L = g->geo[op.level];
+    const Coef k = coef(L.dx, L.dy);
+    BatchItem it{};
+    it.in = op.in;
+    it.out = op.out;
+    it.f = op.f;
+    it.ec = op.ec;
+    it.bc = op.bc;
+    it.minv = g->minv;
+    it.partials = g->partials;
+    it.ctrl = g->ctrl;
+    it.m = L.m;
+    it.n = L.n;
+    it.P = L.P;
+    if ((size_t)op.level + 1 < g->geo.size()) {
+        it.mc = g->geo[op.level + 1].m;
+        it.nc = g->geo[op.level + 1].n;
+        it.Pc = g->geo[op.level + 1].P;
+    }
+    it.cx = k.cx;
+    it.cy = k.cy;
+    it.d = k.d;
+    it.inv_d = k.inv_d;
+    it.omega = op.omega;
+    it.flags = (op.kind == OP_SWEEP) ? (op.flags & SW_F) : 0;
+    Tiling t{};
+    switch (op.kind) {
+        case OP_SWEEP:
+            t = (op.flags & SW_NORM) ? norm_tiling(L.m, L.n)
+                                     : c->tiling(L.m, L.n, (op.flags & SW_PROLONG) ? KC_SWEEP_PROLONG : KC_SWEEP, op.dt);
+            break;
+        case OP_RESTRICT: t = c->tiling(L.m, L.n, KC_RESTRICT, op.dt); break;
+        case OP_RESNORM:
+        case OP_DEFECT:
+        case OP_FINALIZE: t = norm_tiling(g->geo[0].m, g->geo[0].n); break;
+        case OP_ADI_ROWS:
+        case OP_ADI_COLS: {
+            const LineArgs la = adi_args(g, op.omega, op.flags, op.kind == OP_ADI_ROWS ? 0 : 1, op.parity);
+            it.out = la.u;
+            it.f = la.f;
+            it.scratch = la.scratch;
+            it.cprime = la.cprime;
+            it.piv = la.piv;
+            it.a_off = la.a_off;
+            it.flags = op.flags;
+            it.parity = op.parity;
+            const int first = op.parity ? 1 : 2;
+            const int span = op.kind == OP_ADI_ROWS ? L.n - 2 : L.m - 2;
+            const int lines = span >= first ? (span - first) / 2 + 1 : 0;
+            const int per = op.kind == OP_ADI_ROWS ? kRowTile : kBlock;
+            t.ntiles = (lines + per - 1) / per;
+            break;
+        }
+        case OP_COARSE: t.ntiles = 1; break;
+    }
+    it.V = t.V;
+    it.ty = t.ty;
+    it.nwin = t.nwin;
+    it.nchunk = t.nchunk;
+    it.ntiles = t.ntiles;
+    return it;
+}
+
+double item_bytes(const Op& op, const BatchItem& it) {
+    const double n = (double)(it.m - 2) * (double)(it.n - 2);
+    const double sz = op.dt == 0 ? 8.0 : 4.0;
+    switch (op.kind) {
+        case OP_SWEEP: {
+            double per = (op.flags & SW_ZERO) ? 1.0 : 2.0;
+            if (op.flags & SW_F) per += 1.0;
+            if (op.flags & SW_PROLONG) per += 0.25;
+            return per * sz * n;
+        }
+        case OP_RESTRICT: return ((op.in ? 1.0 : 0.0) + (op.f ? 1.0 : 0.0) + 0.25) * sz * n;
+        case OP_RESNORM: return (op.f ? 16.0 : 8.0) * n;
+        case OP_DEFECT: return (8.0 + (op.ec ? 4.0 : 0.0) + (op.f ? 8.0 : 0.0) + 12.0) * n;
+        case OP_ADI_ROWS:
+        case OP_ADI_COLS: return (op.f ? 48.0 : 40.0) * 0.5 * n;
+        default: return 0.0;
+    }
+}
+
+int kclass_of(const Op& op) {
+    switch (op.kind) {
+        case OP_SWEEP: return (op.flags & SW_PROLONG) ? KC_SWEEP_PROLONG : KC_SWEEP;
+        case OP_RESTRICT: return KC_RESTRICT;
+        case OP_COARSE: return KC_COARSE;
+        case OP_FINALIZE: return KC_FINALIZE;
+        case OP_RESNORM: return KC_RESIDUAL;
+        case OP_DEFECT: return KC_DEFECT;
+        case OP_ADI_ROWS: return KC_ADI_ROWS;
+        case OP_ADI_COLS: return KC_ADI_COLS;
+    }
+    return KC_SWEEP;
+}
+
+// Build (or fetch) the merged-launch plan of one step of `gs`; steps[k] is
+// grid k's step number (its buffer parity).
+lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vector<int>& steps, const lap_opts& o,
+                    lap_ctx::Plan** out) {
+    std::string key;
+    {
+        char buf[96];
+        snprintf(buf, sizeof buf, "%d:%d:%d:%d:%d:%d:%.17g|", o.method, o.precision, o.nu1, o.nu2, o.check_every,
+                 o.adi_form, o.omega);
+        key = buf;
+        for (size_t k = 0; k < gs.size(); ++k) {
+            const int par = (o.method == LAP_MG && o.precision == LAP_MIXED)
+                                ? (steps[k] == 0 ? 2 : steps[k] % 2)
+                                : (o.method == LAP_SOR_RB ? (steps[k] * o.check_every) % 2 : 0);
+            snprintf(buf, sizeof buf, "%p:%d,", (void*)gs[k], par);
+            key += buf;
+        }
+    }
+    for (size_t k = 0; k < c->plans.size(); ++k)
+        if (c->plans[k].first == key) {
+            *out = c->plans[k].second;
+            return LAP_OK;
+        }
+    // group every grid's operations by merge key
+    std::map<long, std::vector<std::pair<lap_grid*, Op>>> groups;
+    for (size_t k = 0; k < gs.size(); ++k) {
+        std::vector<Op> ops;
+        plan_step(gs[k], o, steps[k], PART_ALL, ops);
+        for (size_t q = 1; q < ops.size(); ++q)
+            if (ops[q].key <= ops[q - 1].key)   // merging by key must keep each grid's own order
+                return fail(LAP_EINVAL, "internal error: operation keys out of order");
+        for (const Op& op : ops) groups[op.key].push_back({gs[k], op});
+    }
+    lap_ctx::Plan* p = new lap_ctx::Plan();
+    for (auto& kv : groups) {
+        auto& v = kv.second;
+        // one merged launch per (kind, dtype, step flags) inside a key (normally exactly one)
+        std::map<std::tuple<int, int, int>, std::vector<std::pair<lap_grid*, Op>>> sub;
+        for (auto& go : v) sub[std::make_tuple(go.second.kind, go.second.dt, go.second.flags & ~SW_F)].push_back(go);
+        for (auto& skv : sub) {
+            MergedLaunch L{};
+            L.kind = batch_kind(std::get<0>(skv.first));
+            L.dt = std::get<1>(skv.first);
+            L.flags = std::get<2>(skv.first);
+            L.off = p->items.size();
+            L.cls = kclass_of(skv.second[0].second);
+            L.fine = skv.second[0].second.level == 0;
+            int tile0 = 0;
+            for (auto& go : skv.second) {
+                BatchItem it = make_item(go.first, go.second, o);
+                it.tile0 = tile0;
+                if (L.kind != BK_COARSE && L.kind != BK_FINALIZE) tile0 += it.ntiles;
+                L.bytes += item_bytes(go.second, it);
+                p->items.push_back(it);
+            }
+            L.count = (int)skv.second.size();
+            L.total = tile0;
+            if (L.kind == BK_COARSE || L.kind == BK_FINALIZE) {
+                L.blocks = std::min(L.count, 2048);
+            } else if (L.kind == BK_ADI_ROWS || L.kind == BK_ADI_COLS) {
+                L.blocks = std::max(1, std::min(L.total, 4096));
+            } else {
+                int nb = (L.total + kWavesPerBlock - 1) / kWavesPerBlock;
+                nb = std::min(nb, 2 * c->wave_cap / kWavesPerBlock);
+                L.blocks = std::max(kXcds, (nb + kXcds - 1) / kXcds * kXcds);
+            }
+            p->launches.push_back(L);
+        }
+    }
+    p->dev = (BatchItem*)c->arena.alloc(p->items.size() * sizeof(BatchItem));
+    if (!p->dev) {
+        delete p;
+        return fail(LAP_ENOMEM, "arena cannot hold the batch plan");
+    }
+    if (hipMemcpyAsync(p->dev, p->items.data(), p->items.size() * sizeof(BatchItem), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess) {
+        plan_free(c, p);
+        return fail(LAP_EHIP, "plan upload failed");
+    }
+    if (c->plans.size() >= 8) {
+        hipStreamSynchronize(c->stream);
+        plan_free(c, c->plans.front().second);
+        c->plans.erase(c->plans.begin());
+    }
+    c->plans.push_back({key, p});
+    *out = p;
+    return LAP_OK;
+}
+
+hipError_t run_plan_launches(lap_ctx* c, lap_ctx::Plan* p) {
+    for (const MergedLaunch& L : p->launches)
+        HIPERR(c->timed(L.cls, L.fine, L.bytes, [&]() {
+            return launch_batch(L.kind, L.dt, L.flags, p->dev + L.off, L.count, L.total, L.blocks, c->stream);
+        }));
+    return hipSuccess;
+}
+
+// Enqueue a plan: replay its captured graph (captured on first use) or launch.
+hipError_t run_plan(lap_ctx* c, lap_ctx::Plan* p, bool graph) {
+    if (graph && c->stream != nullptr && !c->timing) {
+        if (!p->graph) {
+            HIPERR(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = run_plan_launches(c, p);
+            hipGraph_t tmp = nullptr;
+            hipError_t e2 = hipStreamEndCapture(c->stream, &tmp);
+            if (e != hipSuccess) return e;
+            if (e2 != hipSuccess) return e2;
+            e = hipGraphInstantiate(&p->graph, tmp, nullptr, nullptr, 0);
+            hipGraphDestroy(tmp);
+            HIPERR(e);
+        }
+        return hipGraphLaunch(p->graph, c->stream);
+    }
+    return run_plan_launches(c, p);
+}
 
 lap_status batch_reserve(lap_ctx* c, int count) {
     if (count <= c->batch_cap) return LAP_OK;
@@ -1512,23 +1894,34 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
     const double t0 = now_s();
     for (int k = 0; k < count; ++k) {
         if (!grids[k] || grids[k]->ctx != c) return fail(LAP_EINVAL, "grid does not belong to this context");
+        for (int q = 0; q < k; ++q)
+            if (grids[q] == grids[k]) return fail(LAP_EINVAL, "a grid appears twice in the batch");
         lap_status st = validate_opts(grids[k], *o);
         if (st != LAP_OK) return st;
     }
+    lap_opts po = *o;
+    po.use_graph = 0;   // per-grid graphs are not used; the merged plans have their own
     for (int k = 0; k < count; ++k) {
-        lap_status st = prepare(grids[k], *o);
+        lap_status st = prepare(grids[k], po);
         if (st != LAP_OK) return st;
     }
-    std::vector<lap_grid*> active(grids, grids + count);
+    // every grid stays in the plan until all are done (a finished grid's
+    // tiles exit at its control block), so the plans and graphs are reused
+    std::vector<lap_grid*> all(grids, grids + count);
+    std::vector<lap_grid*> active = all;
+    std::vector<int> steps(count, 0);
     std::vector<Ctrl> hs;
     std::map<lap_grid*, Ctrl> final_ctrl;
     const int rounds = max_steps(*o) + 1;
     for (int r = 0; r < rounds && !active.empty(); ++r) {
-        for (lap_grid* g : active) {
-            hipError_t e = step(g, *o);
-            if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
-        }
-        lap_status st = batch_read(c, active, hs);
+        lap_ctx::Plan* p = nullptr;
+        for (int k = 0; k < count; ++k) steps[k] = r;
+        lap_status st = get_plan(c, all, steps, *o, &p);
+        if (st != LAP_OK) return st;
+        hipError_t e = run_plan(c, p, o->use_graph != 0);
+        if (e != hipSuccess) return fail(LAP_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+        for (lap_grid* g : all) g->step_idx = r + 1;
+        st = batch_read(c, active, hs);
         if (st != LAP_OK) return st;
         std::vector<lap_grid*> next;
         for (size_t k = 0; k < active.size(); ++k) {
@@ -1560,37 +1953,48 @@ extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t
     if (precision != LAP_FP64 && precision != LAP_MIXED) return fail(LAP_EINVAL, "unknown precision");
     const double t0 = now_s();
     std::vector<lap_grid*> active;
+    std::vector<int> steps;
+    lap_opts o;
+    lap_opts_default(&o);
+    o.method = LAP_MG;
+    o.precision = precision;
+    o.max_iter = 1000;
+    o.use_graph = 1;
     for (int k = 0; k < count; ++k) {
         lap_grid* g = grids[k];
         if (!g || g->ctx != c) return fail(LAP_EINVAL, "grid does not belong to this context");
+        for (int q = 0; q < k; ++q)
+            if (grids[q] == g) return fail(LAP_EINVAL, "a grid appears twice in the batch");
         done_host[k] = 0;
         if (g->batch_started && g->batch_done) {
             done_host[k] = 1;
             continue;
         }
         if (!g->batch_started) {
-            lap_opts o;
-            lap_opts_default(&o);
-            o.method = LAP_MG;
-            o.precision = precision;
-            o.tol = g->tol;
-            o.max_iter = 1000;
-            o.use_graph = precision == LAP_FP64 ? 1 : 0;   // a mixed graph spans two outer steps
-            lap_status st = validate_opts(g, o);
+            lap_opts go = o;
+            go.tol = g->tol;
+            go.use_graph = 0;
+            lap_status st = validate_opts(g, go);
             if (st != LAP_OK) return st;
-            st = prepare(g, o);
+            st = prepare(g, go);
             if (st != LAP_OK) return st;
-            g->batch_opts = o;
+            g->batch_opts = go;
             g->batch_started = true;
             g->batch_done = false;
             g->batch_t0 = t0;
         }
         active.push_back(g);
+        steps.push_back(g->step_idx);
     }
-    for (lap_grid* g : active) {
-        // one outer step per tick: launch directly (a mixed graph spans two steps)
-        hipError_t e = step(g, g->batch_opts);
-        if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (!active.empty()) {
+        // the stopping tolerance lives in each grid's control block, so grids
+        // with different tolerances share one plan
+        lap_ctx::Plan* p = nullptr;
+        lap_status st = get_plan(c, active, steps, o, &p);
+        if (st != LAP_OK) return st;
+        hipError_t e = run_plan(c, p, true);
+        if (e != hipSuccess) return fail(LAP_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+        for (lap_grid* g : active) g->step_idx++;
     }
     std::vector<Ctrl> hs;
     lap_status st = batch_read(c, active, hs);
@@ -1817,7 +2221,8 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
     hipEventDestroy(e1);
     release();
     if (result != LAP_OK) return result;
-    // cached graphs hold the old tilings
+    // cached graphs and batch plans hold the old tilings
+    plans_clear(c);
     for (lap_grid* g : c->grids)
         if (g->graph) {
             hipGraphExecDestroy(g->graph);

@@ -20,291 +20,9 @@
 //   L u = fma(-d, C, fma(cy, S+N, cx*(W+E)));   r = f - L u
 #include <algorithm>
 
-#include "lap_kernels.hpp"
+#include "stencil_tiles.hpp"
 
 namespace lap {
-
-// ------------------------------------------------------------------ helpers
-template <typename T, int V> struct VecT;
-template <> struct VecT<double, 1> { using type = double; };
-template <> struct VecT<double, 2> { using type = double __attribute__((ext_vector_type(2))); };
-template <> struct VecT<double, 4> { using type = double __attribute__((ext_vector_type(4))); };
-template <> struct VecT<float, 1> { using type = float; };
-template <> struct VecT<float, 2> { using type = float __attribute__((ext_vector_type(2))); };
-template <> struct VecT<float, 4> { using type = float __attribute__((ext_vector_type(4))); };
-
-template <typename T, int V>
-__device__ __forceinline__ void ldv(T (&x)[V], const T* p) {
-    using VT = typename VecT<T, V>::type;
-    VT v = *reinterpret_cast<const VT*>(p);
-    if constexpr (V == 1) {
-        x[0] = v;
-    } else {
-#pragma unroll
-        for (int e = 0; e < V; ++e) x[e] = v[e];
-    }
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void stv(T* p, const T (&x)[V]) {
-    using VT = typename VecT<T, V>::type;
-    VT v;
-    if constexpr (V == 1) {
-        v = x[0];
-    } else {
-#pragma unroll
-        for (int e = 0; e < V; ++e) v[e] = x[e];
-    }
-    *reinterpret_cast<VT*>(p) = v;
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void zero(T (&x)[V]) {
-#pragma unroll
-    for (int e = 0; e < V; ++e) x[e] = T(0);
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void copy(T (&dst)[V], const T (&src)[V]) {
-#pragma unroll
-    for (int e = 0; e < V; ++e) dst[e] = src[e];
-}
-
-// Workgroups are dealt to the XCDs round-robin; give XCD x the contiguous
-// tile range [x*per, (x+1)*per) so neighbouring tiles share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int per = nb / kXcds;
-    return (b % kXcds) * per + (b / kXcds);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
-}
-
-// Per-lane column bookkeeping of one window.
-template <int V>
-struct Cols {
-    int ws, i0;
-    bool vin;                 // whole vector inside [0, P)
-    bool cint[V];             // interior column
-    bool cout[V];             // interior and inside this window's output range
-    bool all_out;
-    __device__ __forceinline__ Cols(int win, int lane, int m, int P) {
-        ws = win * win_step(V) - win_left(V);
-        i0 = ws + lane * V;
-        vin = (i0 >= 0) && (i0 + V <= P);
-        all_out = true;
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const int i = i0 + e;
-            cint[e] = (i >= 1) && (i <= m - 2);
-            cout[e] = cint[e] && (i >= ws + 2) && (i < ws + 64 * V - 2);
-            all_out = all_out && cout[e];
-        }
-    }
-};
-
-template <typename T, int V>
-__device__ __forceinline__ void load_row(T (&x)[V], const T* base, int j, int n, int P, int i0, bool vin) {
-    if (base != nullptr && vin && j >= 0 && j < n)
-        ldv<T, V>(x, base + (size_t)j * P + i0);
-    else
-        zero<T, V>(x);
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void store_row(T* base, const T (&x)[V], int j, int P, const Cols<V>& c) {
-    T* p = base + (size_t)j * P + c.i0;
-    if (c.vin && c.all_out) {
-        stv<T, V>(p, x);
-    } else {
-#pragma unroll
-        for (int e = 0; e < V; ++e)
-            if (c.cout[e]) p[e] = x[e];
-    }
-}
-
-// Bilinear interpolation of a coarse correction, streamed with the fine rows.
-// A lane owning fine columns i0..i0+V-1 needs coarse columns I0 = i0>>1 ..
-// I0 + V2 (V2 = max(1, V/2)); it loads I0..I0+V2-1 with one vector load per
-// coarse row and takes column I0+V2 from the next lane.  The two coarse rows
-// J, J+1 around the current fine row stay in registers: fine rows arrive in
-// increasing order, so each coarse row is loaded once per wave.
-template <typename T, int V>
-struct Prolong {
-    static constexpr int V2 = V >= 2 ? V / 2 : 1;
-    T lo[V2 + 1], hi[V2 + 1];   // coarse rows Jcur, Jcur+1 (entry V2 from the next lane)
-    int Jcur;
-    __device__ __forceinline__ void load_coarse(T (&x)[V2 + 1], const T* ec, int J, int nc, int Pc, int I0) {
-        T v[V2];
-        if (J >= 0 && J < nc && I0 >= 0 && I0 + V2 <= Pc)
-            ldv<T, V2>(v, ec + (size_t)J * Pc + I0);
-        else
-            zero<T, V2>(v);
-#pragma unroll
-        for (int q = 0; q < V2; ++q) x[q] = v[q];
-        x[V2] = __shfl_down(v[0], 1);
-        // the last lane has no right neighbour, but its halo columns still need
-        // coarse column I0 + V2 (the sweep reads the window's last column)
-        if ((threadIdx.x & 63) == 63) {
-            const int I = I0 + V2;
-            x[V2] = (J >= 0 && J < nc && I >= 0 && I < Pc) ? ec[(size_t)J * Pc + I] : T(0);
-        }
-    }
-    __device__ __forceinline__ void init(const T* ec, int j, int nc, int Pc, int i0) {
-        Jcur = j >> 1;
-        load_coarse(lo, ec, Jcur, nc, Pc, i0 >> 1);
-        load_coarse(hi, ec, Jcur + 1, nc, Pc, i0 >> 1);
-    }
-    // add P(ec) to fine row j (j non-decreasing between calls)
-    __device__ __forceinline__ void add(T (&x)[V], const T* ec, int j, int n, int nc, int Pc, int i0, int m) {
-        const int J = j >> 1;
-        while (Jcur < J) {   // at most one step per fine row
-#pragma unroll
-            for (int q = 0; q <= V2; ++q) lo[q] = hi[q];
-            ++Jcur;
-            load_coarse(hi, ec, Jcur + 1, nc, Pc, i0 >> 1);
-        }
-        if (j < 0 || j >= n) return;
-        const bool t = (j & 1) != 0;                  // wave-uniform
-        // branch-free: every lane evaluates the same instructions; for even V
-        // the coarse index and the column parity of element e are compile-time
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const int i = i0 + e;
-            T e00, e10, e01, e11;
-            bool s;
-            if constexpr (V % 2 == 0) {
-                s = (e & 1) != 0;
-                e00 = lo[e >> 1];
-                e10 = lo[(e >> 1) + 1];
-                e01 = hi[e >> 1];
-                e11 = hi[(e >> 1) + 1];
-            } else {
-                s = (i & 1) != 0;                      // V == 1: q = 0 for every lane
-                e00 = lo[0];
-                e10 = lo[1];
-                e01 = hi[0];
-                e11 = hi[1];
-            }
-            const T p_even = t ? (e00 + e01) * T(0.5) : e00;
-            const T p_odd = t ? ((e00 + e10) + (e01 + e11)) * T(0.25) : (e00 + e10) * T(0.5);
-            const T p = s ? p_odd : p_even;
-            x[e] = (i >= 0 && i < m) ? x[e] + p : x[e];
-        }
-    }
-};
-
-// ------------------------------------------------------------ red-black sweep
-template <typename T, int V, int FL>
-__device__ __forceinline__ void sweep_load(T (&x)[V], const SweepArgs<T>& A, int j, const Cols<V>& c,
-                                           Prolong<T, V>& pr) {
-    if constexpr (FL & SW_ZERO) {
-        zero<T, V>(x);
-    } else {
-        load_row<T, V>(x, A.uin, j, A.n, A.P, c.i0, c.vin);
-        if constexpr (FL & SW_PROLONG) pr.add(x, A.ec, j, A.n, A.nc, A.Pc, c.i0, A.m);
-    }
-}
-
-template <typename T, int V, int FL>
-__device__ __forceinline__ void sweep_loadf(T (&x)[V], const SweepArgs<T>& A, int j, const Cols<V>& c) {
-    if constexpr (FL & SW_F)
-        load_row<T, V>(x, A.f, j, A.n, A.P, c.i0, c.vin);
-    else
-        zero<T, V>(x);
-}
-
-// State carried down the rows of one window (registers).
-template <typename T, int V>
-struct SweepRegs {
-    T a[V], b[V], c[V], d[V];   // rows j-2 (final), j-1 (red done), j (old -> red), j+1 (old)
-    T fb[V], fc[V], fd[V];      // f at rows j-1, j, j+1
-    T dn[V], fdn[V];            // prefetched row j+2
-    T dnn[V], fdnn[V];          // prefetched row j+3
-    T bo[V];                    // old row j-1 (norm of the input)
-    double s2, mx;
-    Prolong<T, V> pr;           // coarse rows of a fused prolongation
-};
-
-template <typename T, int V, int FL, int JP>
-__device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V>& R, const Cols<V>& c,
-                                           int j, int j0, int j1, int ipar) {
-    // rotate in the prefetched row j+1, prefetch row j+3 (two rows in flight)
-    copy<T, V>(R.d, R.dn);
-    copy<T, V>(R.fd, R.fdn);
-    copy<T, V>(R.dn, R.dnn);
-    copy<T, V>(R.fdn, R.fdnn);
-    if (j + 3 <= j1 + 2) {
-        sweep_load<T, V, FL>(R.dnn, A, j + 3, c, R.pr);
-        sweep_loadf<T, V, FL>(R.fdnn, A, j + 3, c);
-    }
-    const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
-
-    // old row j: neighbours across lanes
-    const T cW = __shfl_up(R.c[V - 1], 1);
-    const T cE = __shfl_down(R.c[0], 1);
-
-    if constexpr (FL & SW_NORM) {
-        if (j >= j0 && j <= j1) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                if (!c.cout[e]) continue;
-                const T W = e > 0 ? R.c[e - 1] : cW;
-                const T E = e < V - 1 ? R.c[e + 1] : cE;
-                const T L = fma(-A.d, R.c[e], fma(cy, R.bo[e] + R.d[e], cx * (W + E)));
-                const double r = (double)(R.fc[e] - L);
-                R.s2 = fma(r, r, R.s2);
-                R.mx = fmax(R.mx, fabs(r));
-            }
-        }
-        copy<T, V>(R.bo, R.c);
-    }
-
-    const bool rj = (j >= 1) && (j <= A.n - 2);
-    const bool rjm = (j - 1 >= 1) && (j - 1 <= A.n - 2);
-
-    // colour 0 ((i+j) even) on row j from old colour-1 neighbours
-    if (rj) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
-            if (!upd || !c.cint[e]) continue;
-            const T W = e > 0 ? R.c[e - 1] : cW;
-            const T E = e < V - 1 ? R.c[e + 1] : cE;
-            const T t = (fma(cy, R.b[e] + R.d[e], cx * (W + E)) - R.fc[e]) * inv_d;
-            R.c[e] = fma(om, t - R.c[e], R.c[e]);
-        }
-    }
-    // colour 1 on row j-1 ((i+j-1) odd) from the new colour-0 values
-    const T bW = __shfl_up(R.b[V - 1], 1);
-    const T bE = __shfl_down(R.b[0], 1);
-    if (rjm) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
-            if (!upd || !c.cint[e]) continue;
-            const T W = e > 0 ? R.b[e - 1] : bW;
-            const T E = e < V - 1 ? R.b[e + 1] : bE;
-            const T t = (fma(cy, R.a[e] + R.c[e], cx * (W + E)) - R.fb[e]) * inv_d;
-            R.b[e] = fma(om, t - R.b[e], R.b[e]);
-        }
-    }
-    if (j - 1 >= j0 && j - 1 <= j1) store_row<T, V>(A.uout, R.b, j - 1, A.P, c);
-
-    copy<T, V>(R.a, R.b);
-    copy<T, V>(R.b, R.c);
-    copy<T, V>(R.c, R.d);
-    copy<T, V>(R.fb, R.fc);
-    copy<T, V>(R.fc, R.fd);
-}
 
 template <typename T, int V, int FL>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
@@ -312,40 +30,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
     if (tile >= A.tl.ntiles) return;
-    const int lane = threadIdx.x & 63;
-    const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
-    const Cols<V> c(win, lane, A.m, A.P);
-    const int j0 = 1 + chunk * A.tl.ty;          // odd
-    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
-    const int ipar = c.i0 & 1;
-
-    SweepRegs<T, V> R;
-    R.s2 = 0.0;
-    R.mx = 0.0;
-    zero<T, V>(R.a);
-    zero<T, V>(R.fb);
-    if constexpr (FL & SW_PROLONG) R.pr.init(A.ec, j0 - 2, A.nc, A.Pc, c.i0);
-    sweep_load<T, V, FL>(R.b, A, j0 - 2, c, R.pr);
-    sweep_load<T, V, FL>(R.c, A, j0 - 1, c, R.pr);
-    sweep_loadf<T, V, FL>(R.fc, A, j0 - 1, c);
-    sweep_load<T, V, FL>(R.dn, A, j0, c, R.pr);
-    sweep_loadf<T, V, FL>(R.fdn, A, j0, c);
-    sweep_load<T, V, FL>(R.dnn, A, j0 + 1, c, R.pr);
-    sweep_loadf<T, V, FL>(R.fdnn, A, j0 + 1, c);
-    if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.b);
-
-    for (int j = j0 - 1; j <= j1 + 1; j += 2) {   // j0 - 1 is even
-        sweep_step<T, V, FL, 0>(A, R, c, j, j0, j1, ipar);
-        if (j + 1 <= j1 + 1) sweep_step<T, V, FL, 1>(A, R, c, j + 1, j0, j1, ipar);
-    }
-    if constexpr (FL & SW_NORM) {
-        const double s = wave_sum(R.s2);
-        const double mx = wave_max(R.mx);
-        if (lane == 0) {
-            A.partials[2 * tile] = s;
-            A.partials[2 * tile + 1] = mx;
-        }
-    }
+    sweep_tile<T, V, FL>(A, tile, threadIdx.x & 63);
 }
 
 template <typename T, int V>
@@ -377,82 +62,13 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int flags, hipStream_t s) {
 template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, hipStream_t);
 template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, hipStream_t);
 
-// ------------------------------------------------- residual + full weighting
-template <typename T, int V>
-__device__ __forceinline__ void residual_row(T (&r)[V], const T (&um)[V], const T (&uc)[V], const T (&up)[V],
-                                             const T (&f)[V], bool rowint, const Cols<V>& c, T cx, T cy, T d) {
-    const T W0 = __shfl_up(uc[V - 1], 1);
-    const T E0 = __shfl_down(uc[0], 1);
-#pragma unroll
-    for (int e = 0; e < V; ++e) {
-        const T W = e > 0 ? uc[e - 1] : W0;
-        const T E = e < V - 1 ? uc[e + 1] : E0;
-        const T L = fma(-d, uc[e], fma(cy, um[e] + up[e], cx * (W + E)));
-        r[e] = (rowint && c.cint[e]) ? (f[e] - L) : T(0);
-    }
-}
-
 template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void k_restrict(RestrictArgs<T> A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
     if (tile >= A.tl.ntiles) return;
-    const int lane = threadIdx.x & 63;
-    const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
-    const Cols<V> c(win, lane, A.m, A.P);
-    const int j0 = 1 + chunk * A.tl.ty;
-    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
-
-    T um[V], uc[V], up[V], q1[V], q2[V], fr[V], fq1[V], fq2[V];
-    T r2[V], r1[V], r0[V];
-    zero<T, V>(r2);
-    zero<T, V>(r1);
-    load_row<T, V>(um, A.u, j0 - 1, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(uc, A.u, j0, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(q1, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(q2, A.u, j0 + 2, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(fq1, A.f, j0, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(fq2, A.f, j0 + 1, A.n, A.P, c.i0, c.vin);
-
-    for (int j = j0; j <= j1 + 1; ++j) {   // rows j+1, j+2 (u) and j, j+1 (f) are in flight
-        copy<T, V>(up, q1);
-        copy<T, V>(fr, fq1);
-        copy<T, V>(q1, q2);
-        copy<T, V>(fq1, fq2);
-        if (j + 3 <= j1 + 2) load_row<T, V>(q2, A.u, j + 3, A.n, A.P, c.i0, c.vin);
-        if (j + 2 <= j1 + 1) load_row<T, V>(fq2, A.f, j + 2, A.n, A.P, c.i0, c.vin);
-        residual_row<T, V>(r0, um, uc, up, fr, (j >= 1) && (j <= A.n - 2), c, A.cx, A.cy, A.d);
-        if ((j & 1) && j >= j0 + 2) {
-            const int J = (j - 1) >> 1;               // coarse row at fine row j-1
-            const T w2 = __shfl_up(r2[V - 1], 1), w1 = __shfl_up(r1[V - 1], 1), w0 = __shfl_up(r0[V - 1], 1);
-            const T e2 = __shfl_down(r2[0], 1), e1 = __shfl_down(r1[0], 1), e0 = __shfl_down(r0[0], 1);
-            if (J >= 1 && J <= A.nc - 2) {
-                T* brow = A.bc + (size_t)J * A.Pc;
-#pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    const int i = c.i0 + e;
-                    if ((i & 1) || !c.cout[e]) continue;
-                    const int I = i >> 1;
-                    if (I < 1 || I > A.mc - 2) continue;
-                    const T C = r1[e];
-                    const T W = e > 0 ? r1[e - 1] : w1;
-                    const T E = e < V - 1 ? r1[e + 1] : e1;
-                    const T S = r2[e], N = r0[e];
-                    const T SW = e > 0 ? r2[e - 1] : w2;
-                    const T SE = e < V - 1 ? r2[e + 1] : e2;
-                    const T NW = e > 0 ? r0[e - 1] : w0;
-                    const T NE = e < V - 1 ? r0[e + 1] : e0;
-                    const T v = (fma(T(4), C, T(2) * ((W + E) + (S + N))) + ((SW + SE) + (NW + NE))) * T(0.0625);
-                    brow[I] = v;
-                }
-            }
-        }
-        copy<T, V>(r2, r1);
-        copy<T, V>(r1, r0);
-        copy<T, V>(um, uc);
-        copy<T, V>(uc, up);
-    }
+    restrict_tile<T, V>(A, tile, threadIdx.x & 63);
 }
 
 template <typename T>
@@ -469,56 +85,13 @@ hipError_t launch_restrict(const RestrictArgs<T>& a, hipStream_t s) {
 template hipError_t launch_restrict<double>(const RestrictArgs<double>&, hipStream_t);
 template hipError_t launch_restrict<float>(const RestrictArgs<float>&, hipStream_t);
 
-// ------------------------------------------------------------------ residual
 template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs<T> A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
     if (tile >= A.tl.ntiles) return;
-    const int lane = threadIdx.x & 63;
-    const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
-    const Cols<V> c(win, lane, A.m, A.P);
-    const int j0 = 1 + chunk * A.tl.ty;
-    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
-
-    T um[V], uc[V], up[V], q1[V], q2[V], fr[V], fq1[V], fq2[V], r[V];
-    double s2 = 0.0, mx = 0.0;
-    load_row<T, V>(um, A.u, j0 - 1, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(uc, A.u, j0, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(q1, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(q2, A.u, j0 + 2, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(fq1, A.f, j0, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(fq2, A.f, j0 + 1, A.n, A.P, c.i0, c.vin);
-    for (int j = j0; j <= j1; ++j) {
-        copy<T, V>(up, q1);
-        copy<T, V>(fr, fq1);
-        copy<T, V>(q1, q2);
-        copy<T, V>(fq1, fq2);
-        if (j + 3 <= j1 + 1) load_row<T, V>(q2, A.u, j + 3, A.n, A.P, c.i0, c.vin);
-        if (j + 2 <= j1) load_row<T, V>(fq2, A.f, j + 2, A.n, A.P, c.i0, c.vin);
-        residual_row<T, V>(r, um, uc, up, fr, true, c, A.cx, A.cy, A.d);
-        if (A.r != nullptr) store_row<T, V>(A.r, r, j, A.P, c);
-        if (A.partials != nullptr) {
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                if (!c.cout[e]) continue;
-                const double v = (double)r[e];
-                s2 = fma(v, v, s2);
-                mx = fmax(mx, fabs(v));
-            }
-        }
-        copy<T, V>(um, uc);
-        copy<T, V>(uc, up);
-    }
-    if (A.partials != nullptr) {
-        const double s = wave_sum(s2);
-        const double m2 = wave_max(mx);
-        if (lane == 0) {
-            A.partials[2 * tile] = s;
-            A.partials[2 * tile + 1] = m2;
-        }
-    }
+    residual_tile<T, V>(A, tile, threadIdx.x & 63);
 }
 
 template <typename T>
@@ -535,66 +108,13 @@ hipError_t launch_residual(const ResidualArgs<T>& a, hipStream_t s) {
 template hipError_t launch_residual<double>(const ResidualArgs<double>&, hipStream_t);
 template hipError_t launch_residual<float>(const ResidualArgs<float>&, hipStream_t);
 
-// ---------------------------------------------------- FP64 defect correction
-template <int V>
-__device__ __forceinline__ void defect_load(double (&x)[V], const DefectArgs& A, int j, const Cols<V>& c) {
-    load_row<double, V>(x, A.psi_in, j, A.n, A.P, c.i0, c.vin);
-    if (A.e != nullptr && c.vin && j >= 0 && j < A.n) {
-        float ev[V];
-        ldv<float, V>(ev, A.e + (size_t)j * A.P + c.i0);
-#pragma unroll
-        for (int e = 0; e < V; ++e) x[e] = x[e] + (double)ev[e];
-    }
-}
-
 template <int V>
 __global__ __launch_bounds__(kBlock) void k_defect(DefectArgs A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
     if (tile >= A.tl.ntiles) return;
-    const int lane = threadIdx.x & 63;
-    const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
-    const Cols<V> c(win, lane, A.m, A.P);
-    const int j0 = 1 + chunk * A.tl.ty;
-    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
-
-    double um[V], uc[V], up[V], q1[V], q2[V], fr[V], fq1[V], fq2[V], r[V];
-    float r32[V];
-    double s2 = 0.0, mx = 0.0;
-    defect_load<V>(um, A, j0 - 1, c);
-    defect_load<V>(uc, A, j0, c);
-    defect_load<V>(q1, A, j0 + 1, c);
-    defect_load<V>(q2, A, j0 + 2, c);
-    load_row<double, V>(fq1, A.f, j0, A.n, A.P, c.i0, c.vin);
-    load_row<double, V>(fq2, A.f, j0 + 1, A.n, A.P, c.i0, c.vin);
-    for (int j = j0; j <= j1; ++j) {
-        copy<double, V>(up, q1);
-        copy<double, V>(fr, fq1);
-        copy<double, V>(q1, q2);
-        copy<double, V>(fq1, fq2);
-        if (j + 3 <= j1 + 1) defect_load<V>(q2, A, j + 3, c);
-        if (j + 2 <= j1) load_row<double, V>(fq2, A.f, j + 2, A.n, A.P, c.i0, c.vin);
-        residual_row<double, V>(r, um, uc, up, fr, true, c, A.cx, A.cy, A.d);
-        if (A.psi_out != A.psi_in || A.e != nullptr) store_row<double, V>(A.psi_out, uc, j, A.P, c);
-#pragma unroll
-        for (int e = 0; e < V; ++e) r32[e] = (float)r[e];
-        store_row<float, V>(A.rhs, r32, j, A.P, c);
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            if (!c.cout[e]) continue;
-            s2 = fma(r[e], r[e], s2);
-            mx = fmax(mx, fabs(r[e]));
-        }
-        copy<double, V>(um, uc);
-        copy<double, V>(uc, up);
-    }
-    const double s = wave_sum(s2);
-    const double m2 = wave_max(mx);
-    if (lane == 0) {
-        A.partials[2 * tile] = s;
-        A.partials[2 * tile + 1] = m2;
-    }
+    defect_tile<V>(A, tile, threadIdx.x & 63);
 }
 
 hipError_t launch_defect(const DefectArgs& a, hipStream_t s) {
@@ -608,30 +128,11 @@ hipError_t launch_defect(const DefectArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------- coarsest level
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse(CoarseArgs<T> A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     __shared__ double rhs[1024];
-    const int mi = A.m - 2, ni = A.n - 2, N = mi * ni;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-        const int i = 1 + k % mi, j = 1 + k / mi;
-        double v = A.b != nullptr ? (double)A.b[(size_t)j * A.P + i] : 0.0;
-        if (A.u != nullptr) {   // Dirichlet values of the perimeter move to the right-hand side
-            if (i == 1) v -= A.cx * (double)A.u[(size_t)j * A.P];
-            if (i == A.m - 2) v -= A.cx * (double)A.u[(size_t)j * A.P + A.m - 1];
-            if (j == 1) v -= A.cy * (double)A.u[i];
-            if (j == A.n - 2) v -= A.cy * (double)A.u[(size_t)(A.n - 1) * A.P + i];
-        }
-        rhs[k] = v;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-        double x = 0.0;
-        for (int l = 0; l < N; ++l) x = fma(A.minv[(size_t)l * N + k], rhs[l], x);
-        const int i = 1 + k % mi, j = 1 + k / mi;
-        A.out[(size_t)j * A.P + i] = (T)x;
-    }
+    coarse_block<T>(A, rhs);
 }
 
 template <typename T>
@@ -643,53 +144,11 @@ hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s) {
 template hipError_t launch_coarse<double>(const CoarseArgs<double>&, hipStream_t);
 template hipError_t launch_coarse<float>(const CoarseArgs<float>&, hipStream_t);
 
-// ------------------------------------------------------------ norm finalise
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* partials, int ntiles, Ctrl* ctrl,
                                                      double* out2, int mode) {
     if (mode == 0 && ctrl->done) return;
     __shared__ double ss[kBlock], sm[kBlock];
-    double s = 0.0, mx = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += kBlock) {
-        s += partials[2 * t];
-        mx = fmax(mx, partials[2 * t + 1]);
-    }
-    ss[threadIdx.x] = s;
-    sm[threadIdx.x] = mx;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            ss[threadIdx.x] += ss[threadIdx.x + w];
-            sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    const double sum = ss[0], m = sm[0];
-    if (mode == 1) {
-        out2[0] = sum;
-        out2[1] = m;
-        return;
-    }
-    const double res = sqrt(sum);
-    if (ctrl->checks == 0) ctrl->r0 = res;
-    const double r0 = ctrl->r0;
-    ctrl->res_l2 = res;
-    ctrl->res_inf = m;
-    ctrl->rel = r0 > 0.0 ? res / r0 : 0.0;
-    ctrl->checks += 1;
-    const double q = ctrl->stop == 0 ? ctrl->rel : m;
-    if (!isfinite(res) || !isfinite(m) || (r0 > 0.0 && res > 1e6 * r0)) {
-        ctrl->done = 1;
-        ctrl->status = -4;   // LAP_EDIVERGED
-    } else if (q < ctrl->tol || res == 0.0) {
-        ctrl->done = 1;
-        ctrl->status = 0;
-    } else if (ctrl->iters >= ctrl->max_iter) {
-        ctrl->done = 1;
-        ctrl->status = -3;   // LAP_ENOTCONV
-    } else {
-        ctrl->iters += ctrl->step > 0 ? ctrl->step : 1;
-    }
+    finalize_block(partials, ntiles, ctrl, out2, mode, ss, sm);
 }
 
 __global__ void k_ctrl_init(Ctrl* c, double tol, int stop, int max_iter, int step) {
