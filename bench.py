@@ -143,6 +143,8 @@ def run_gpu(args):
     out["final_res_l2"] = l2
     g.destroy()
 
+    if args.quick:
+        args.batch = args.serve = False
     if not args.quick:
         # ---------------------------------------------- mixed vs FP64 (bumps)
         pb = W.square_problem(N, seed=2, bumps=True, bump_seed=3)
@@ -201,8 +203,116 @@ def run_gpu(args):
         out["mg_4097"] = {"time_to_tol_s": t4, "cycles": i4["iterations"],
                           "GLUP/s": i4["iterations"] * lup_per_cycle(g4.levels()) / t4 / 1e9}
         g4.destroy()
+    if args.batch:
+        out["ragged_batch"] = run_batch_leg(args, ctx, torch, lap, dev)
+    if args.serve:
+        out["serving"] = run_serving_leg(args, ctx, torch, lap, dev)
     ctx.close()
     return out, levels
+
+
+def device_request(torch, req, dev):
+    """A serving request's inputs generated on the device (same recipe as
+    workloads.request_problem: U[0,1) boundary and 32 Gaussian bumps drawn
+    from the request's seed; the bumps are evaluated with torch)."""
+    rng = np.random.default_rng(req.seed)
+    m, n = req.m, req.n
+    h = 1.0 / (max(m, n) - 1)
+    psi0 = W.random_boundary(m, n, rng)
+    lx, ly = h * (m - 1), h * (n - 1)
+    amp = rng.standard_normal(32)
+    cx = rng.random(32) * lx
+    cy = rng.random(32) * ly
+    sig = rng.uniform(0.01, 0.1, 32) * max(lx, ly)
+    x = torch.arange(m, device=dev, dtype=torch.float64) * h
+    y = torch.arange(n, device=dev, dtype=torch.float64) * h
+    f = torch.zeros((n, m), device=dev, dtype=torch.float64)
+    for k in range(32):
+        gx = torch.exp(-((x - cx[k]) ** 2) / (2.0 * sig[k] ** 2))
+        gy = torch.exp(-((y - cy[k]) ** 2) / (2.0 * sig[k] ** 2))
+        f += amp[k] * torch.outer(gy, gx)
+    return torch.as_tensor(psi0, device=dev), f, h, h
+
+
+def run_batch_leg(args, ctx, torch, lap, dev):
+    """Ragged batch: 512 grids, m, n log-uniform in [33, 1025] (snapped to
+    c*2^k+1), aspect <= 3, beta in [0.5, 2], U[0,1) boundary, f = 0."""
+    count = args.batch_count
+    probs = W.ragged_batch(count=count, lo=33, hi=1025, seed=4)
+    grids = [ctx.grid(torch.as_tensor(p.psi0, device=dev), None, p.dx, p.dy,
+                      alloc=lap.LAP_ALLOC_MIXED | lap.LAP_ALLOC_ADI) for p in probs]
+    nodes = sum((p.m - 2) * (p.n - 2) for p in probs)
+    lpc = [lup_per_cycle(g.levels()) for g in grids]
+    out = {"grids": count, "interior_nodes": nodes}
+    # warm-up (plans, graphs), then timed batched mixed-precision multigrid
+    ctx.solve_batch(grids, method="mg", precision="mixed", tol=1e-10, max_iter=200)
+    for g, p in zip(grids, probs):
+        g.write(torch.as_tensor(p.psi0, device=dev))
+    sync()
+    t0 = time.perf_counter()
+    infos = ctx.solve_batch(grids, method="mg", precision="mixed", tol=1e-10, max_iter=200)
+    sync()
+    t = time.perf_counter() - t0
+    its = [i["iterations"] for i in infos]
+    out["mg_mixed"] = {"seconds": t, "GLUP/s": sum(k * l for k, l in zip(its, lpc)) / t / 1e9,
+                       "cycles_min": min(its), "cycles_max": max(its),
+                       "all_converged": all(i["status"] == 0 for i in infos),
+                       "solves_per_s": count / t}
+    # the same grids one at a time
+    for g, p in zip(grids, probs):
+        g.write(torch.as_tensor(p.psi0, device=dev))
+    sync()
+    t0 = time.perf_counter()
+    seq = [g.solve("mg", precision="mixed", tol=1e-10, max_iter=200) for g in grids]
+    sync()
+    ts = time.perf_counter() - t0
+    out["mg_mixed_one_at_a_time"] = {"seconds": ts, "speedup_of_batch": ts / t,
+                                     "same_iterations": [i["iterations"] for i in seq] == its}
+    # batched zebra ADI: fixed number of iterations (every interior node is
+    # updated twice per iteration: once by its row, once by its column)
+    for g, p in zip(grids, probs):
+        g.write(torch.as_tensor(p.psi0, device=dev))
+    nit = args.adi_iters
+    ctx.solve_batch(grids, method="adi", omega=1.0, tol=0.0, max_iter=2, check_every=2)
+    sync()
+    t0 = time.perf_counter()
+    ctx.solve_batch(grids, method="adi", omega=1.0, tol=0.0, max_iter=nit, check_every=nit)
+    sync()
+    ta = time.perf_counter() - t0
+    out["adi"] = {"iterations": nit, "seconds": ta, "line_updates_G/s": 2 * nit * nodes / ta / 1e9}
+    for g in grids:
+        g.destroy()
+    return out
+
+
+def run_serving_leg(args, ctx, torch, lap, dev):
+    """Poisson arrivals; m, n log-uniform in [17, 4097] snapped, beta = 1,
+    32-bump source, tol 1e-8 or 1e-10; continuous batching (mixed) vs
+    one-at-a-time FP64 solves."""
+    from paper_2208_02427_amd.serving import Job, Server, DeviceBackend, serve_sequential
+    res = {}
+    for rate in args.rates:
+        reqs = W.poisson_requests(rate, args.serve_count, seed=5, lo=17, hi=4097)
+        jobs = [Job(r.rid, r.arrival, r.m, r.n, r.tol, payload=device_request(torch, r, dev)) for r in reqs]
+        nodes = {j.rid: (j.m - 2) * (j.n - 2) for j in jobs}
+        sync()
+        stats = Server(DeviceBackend(ctx, precision="mixed"), max_active=256).run(jobs)
+        sm = stats.summary()
+        sm["GLUP/s"] = None
+        res[str(int(rate))] = {"batched_mixed": sm}
+        if rate in args.baseline_rates:
+            def solve_one(job):
+                psi0, f, dx, dy = job.payload
+                g = ctx.grid(psi0, f, dx, dy, alloc=lap.LAP_ALLOC_FP64)
+                info = g.solve("mg", precision="fp64", tol=job.tol, max_iter=100)
+                g.destroy()
+                return info
+            jobs2 = [Job(j.rid, r.arrival, j.m, j.n, j.tol, payload=j.payload) for j, r in zip(jobs, reqs)]
+            sync()
+            res[str(int(rate))]["one_at_a_time_fp64"] = serve_sequential(solve_one, jobs2).summary()
+        del jobs
+        torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline():
@@ -231,6 +341,13 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-tune", action="store_true", help="keep the shipped tiling table, no autotuning")
     ap.add_argument("--copy-probe", action="store_true", help="also time a plain 1 GiB device copy")
+    ap.add_argument("--no-batch", dest="batch", action="store_false", help="skip the ragged-batch leg")
+    ap.add_argument("--no-serve", dest="serve", action="store_false", help="skip the serving leg")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--adi-iters", type=int, default=20)
+    ap.add_argument("--serve-count", type=int, default=300)
+    ap.add_argument("--rates", type=float, nargs="*", default=[100, 300, 1000, 3000, 10000])
+    ap.add_argument("--baseline-rates", type=float, nargs="*", default=[100, 1000])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs each grid on a single MI355X "
@@ -260,7 +377,7 @@ def main():
         "rel_res": out["rel_res"],
         "roofline": out["roofline"],
     }
-    for k in ("copy_probe", "mixed", "sor", "mg_4097", "kernels_fine", "autotune"):
+    for k in ("copy_probe", "mixed", "sor", "mg_4097", "ragged_batch", "serving", "kernels_fine", "autotune"):
         if k in out:
             line[k] = out[k]
     if not args.no_cpu:

@@ -1,0 +1,215 @@
+"""Continuous-batching request loop for Poisson / Laplace solves.
+
+Policy (host side) over the library's tick primitive (lap_batch_step):
+
+* requests queue in arrival order;
+* at every tick, queued requests are admitted while their multigrid
+  hierarchy's HBM footprint (lap_grid_footprint) fits the context's largest
+  free arena block and the active set is below `max_active`; admission
+  copies the request's boundary data and source into a device-resident
+  hierarchy;
+* one tick advances every active grid by one outer step (one FP32 V-cycle
+  inside FP64 defect correction), all grids' operations of a level merged
+  into single launches; grids whose stopping rule holds leave the active set,
+  their solution is read back and their hierarchy returned to the arena, so
+  the next queued requests can join at the following tick;
+* latency of a request = time its result is readable - its arrival time.
+
+The backend is any object with footprint(m, n) -> bytes, free_bytes(),
+admit(request) -> handle, tick(handles) -> (done flags, infos), and
+retire(handle) -> result.  `DeviceBackend` drives liblap; tests drive the
+policy with a simulated backend on a virtual clock.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Job:
+    rid: int
+    arrival: float
+    m: int
+    n: int
+    tol: float
+    payload: object = None        # backend-specific input (device tensors, seeds, ...)
+    admitted: float | None = None
+    finished: float | None = None
+    iterations: int | None = None
+    status: int | None = None
+    result: object = None
+    handle: object = None
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+@dataclass
+class ServeStats:
+    jobs: list = field(default_factory=list)
+    ticks: int = 0
+    wall: float = 0.0
+    max_active: int = 0
+    busy_ticks: int = 0
+
+    def summary(self, lup_of=None):
+        lat = np.array([j.latency for j in self.jobs if j.latency is not None])
+        done = len(lat)
+        out = {
+            "requests": len(self.jobs),
+            "completed": done,
+            "solves_per_s": done / self.wall if self.wall > 0 else 0.0,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3) if done else None,
+            "p99_ms": float(np.percentile(lat, 99) * 1e3) if done else None,
+            "mean_ms": float(lat.mean() * 1e3) if done else None,
+            "ticks": self.ticks,
+            "max_active": self.max_active,
+            "wall_s": self.wall,
+            "failed": sum(1 for j in self.jobs if j.status not in (None, 0)),
+        }
+        if lup_of is not None and self.wall > 0:
+            out["GLUP/s"] = sum(lup_of(j) for j in self.jobs if j.finished is not None) / self.wall / 1e9
+        return out
+
+
+class Server:
+    """Continuous batching with admission by footprint."""
+
+    def __init__(self, backend, max_active: int = 512, clock=time.perf_counter):
+        self.backend = backend
+        self.max_active = max_active
+        self.clock = clock
+        self.queue: list[Job] = []
+        self.active: list[Job] = []
+
+    def submit(self, job: Job):
+        self.queue.append(job)
+
+    def _admit(self, now):
+        while self.queue and len(self.active) < self.max_active:
+            job = self.queue[0]
+            if job.arrival > now:
+                break
+            if self.backend.footprint(job.m, job.n) > self.backend.free_bytes():
+                break                       # wait for memory to free up (FIFO: no overtaking)
+            self.queue.pop(0)
+            job.handle = self.backend.admit(job)
+            job.admitted = self.clock()
+            self.active.append(job)
+
+    def tick(self, stats: ServeStats | None = None):
+        """Admit what fits, advance every active grid by one outer step,
+        retire the finished ones.  Returns the finished jobs."""
+        self._admit(self.clock())
+        if not self.active:
+            return []
+        done, infos = self.backend.tick([j.handle for j in self.active])
+        now = self.clock()
+        finished, still = [], []
+        for job, d, info in zip(self.active, done, infos):
+            if d:
+                job.result = self.backend.retire(job.handle)
+                job.finished = self.clock()
+                job.iterations = info.get("iterations")
+                job.status = info.get("status")
+                job.handle = None
+                finished.append(job)
+            else:
+                still.append(job)
+        self.active = still
+        if stats is not None:
+            stats.ticks += 1
+            stats.busy_ticks += 1
+            stats.max_active = max(stats.max_active, len(self.active) + len(finished))
+        del now
+        return finished
+
+    def run(self, jobs: list[Job], t0: float | None = None, idle_sleep: float = 0.0) -> ServeStats:
+        """Serve a whole stream: job.arrival is relative to the start."""
+        stats = ServeStats(jobs=list(jobs))
+        start = self.clock() if t0 is None else t0
+        pending = sorted(jobs, key=lambda j: j.arrival)
+        for j in pending:
+            j.arrival = start + j.arrival
+        k = 0
+        while k < len(pending) or self.queue or self.active:
+            now = self.clock()
+            while k < len(pending) and pending[k].arrival <= now:
+                self.submit(pending[k])
+                k += 1
+            if not self.active and not self.queue and k < len(pending):
+                # idle: wait for the next arrival
+                wait = pending[k].arrival - self.clock()
+                if wait > 0 and idle_sleep >= 0:
+                    self._sleep(wait)
+                continue
+            self.tick(stats)
+        stats.wall = self.clock() - start
+        for j in jobs:
+            j.arrival -= start
+            if j.finished is not None:
+                j.finished -= start
+        return stats
+
+    def _sleep(self, dt):
+        sleeper = getattr(self.backend, "sleep", None)
+        if sleeper is not None:
+            sleeper(dt)
+        else:
+            time.sleep(dt)
+
+
+def serve_sequential(backend_solve, jobs: list[Job], clock=time.perf_counter) -> ServeStats:
+    """Baseline: one request at a time in arrival order (FIFO), each solved
+    to its tolerance before the next starts."""
+    stats = ServeStats(jobs=list(jobs))
+    start = clock()
+    for job in sorted(jobs, key=lambda j: j.arrival):
+        now = clock() - start
+        if job.arrival > now:
+            time.sleep(job.arrival - now)
+        job.admitted = clock() - start
+        info = backend_solve(job)
+        job.finished = clock() - start
+        job.iterations = info.get("iterations")
+        job.status = info.get("status")
+    stats.wall = clock() - start
+    stats.ticks = len(jobs)
+    return stats
+
+
+class DeviceBackend:
+    """liblap backend: grids with the mixed-precision hierarchy only, ticks
+    through lap_batch_step.  job.payload = (psi0, f, dx, dy) device tensors."""
+
+    def __init__(self, ctx, precision: str = "mixed", keep_results: bool = False):
+        from . import LAP_ALLOC_MIXED, LAP_ALLOC_FP64
+        self.ctx = ctx
+        self.precision = precision
+        self.alloc = LAP_ALLOC_MIXED if precision == "mixed" else LAP_ALLOC_FP64
+        self.keep_results = keep_results
+
+    def footprint(self, m, n):
+        from . import footprint
+        return footprint(m, n, self.alloc)
+
+    def free_bytes(self):
+        return self.ctx.usage()[1]
+
+    def admit(self, job):
+        psi0, f, dx, dy = job.payload
+        g = self.ctx.grid(psi0, f, dx, dy, alloc=self.alloc)
+        g.set_tol(job.tol)
+        return g
+
+    def tick(self, grids):
+        return self.ctx.batch_step(grids, precision=self.precision)
+
+    def retire(self, g):
+        out = g.read() if self.keep_results else None
+        g.destroy()
+        return out

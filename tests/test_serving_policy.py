@@ -1,0 +1,124 @@
+"""The serving policy on a virtual clock with a simulated backend (CPU only):
+admission by footprint, FIFO order, continuous batching (requests join while
+others run), retirement, latency accounting, the sequential baseline."""
+import numpy as np
+
+import workloads as W
+from paper_2208_02427_amd.serving import Job, Server, ServeStats, serve_sequential
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class SimBackend:
+    """Each grid needs `cycles` ticks; a tick costs base + per-grid time on
+    the virtual clock; memory is a fixed pool."""
+
+    def __init__(self, clock, pool=10_000, tick_base=1e-3, per_grid=1e-4):
+        self.clock = clock
+        self.pool = pool
+        self.used = 0
+        self.tick_base = tick_base
+        self.per_grid = per_grid
+        self.admitted = []
+        self.max_used = 0
+        self.batches = []
+
+    def footprint(self, m, n):
+        return m * n
+
+    def free_bytes(self):
+        return self.pool - self.used
+
+    def admit(self, job):
+        self.used += self.footprint(job.m, job.n)
+        self.max_used = max(self.max_used, self.used)
+        self.admitted.append(job.rid)
+        return {"job": job, "left": job.payload}
+
+    def tick(self, handles):
+        self.batches.append(len(handles))
+        self.clock.t += self.tick_base + self.per_grid * len(handles)
+        done = []
+        for h in handles:
+            h["left"] -= 1
+            done.append(h["left"] <= 0)
+        return done, [{"iterations": h["job"].payload, "status": 0} for h in handles]
+
+    def retire(self, h):
+        self.used -= self.footprint(h["job"].m, h["job"].n)
+        return "result"
+
+    def sleep(self, dt):
+        self.clock.t += dt
+
+
+def jobs_from_stream(rate, count, seed=5, lo=17, hi=257):
+    reqs = W.poisson_requests(rate, count, seed=seed, lo=lo, hi=hi)
+    return [Job(r.rid, r.arrival, r.m, r.n, r.tol, payload=7 if r.tol < 1e-9 else 5) for r in reqs]
+
+
+def test_all_requests_complete_with_fifo_admission():
+    clk = Clock()
+    be = SimBackend(clk, pool=200_000)
+    jobs = jobs_from_stream(rate=2000.0, count=300)
+    stats = Server(be, max_active=64, clock=clk).run(jobs)
+    s = stats.summary()
+    assert s["completed"] == 300 and s["failed"] == 0
+    assert be.admitted == sorted(be.admitted)            # FIFO admission
+    assert be.max_used <= be.pool                         # never over the memory pool
+    assert max(be.batches) <= 64                          # never above max_active
+    assert all(j.latency >= 0 for j in jobs)
+    # continuous batching: grids are advanced together (batches > 1)
+    assert max(be.batches) > 1
+    # each job needed exactly its cycle count of ticks after admission
+    assert all(j.iterations == j.payload for j in jobs)
+
+
+def test_memory_pressure_defers_admission():
+    clk = Clock()
+    be = SimBackend(clk, pool=70_000)
+    jobs = [Job(k, 0.0, 257, 257, 1e-10, payload=3) for k in range(4)]   # 66k each: one at a time
+    stats = Server(be, clock=clk).run(jobs)
+    assert stats.summary()["completed"] == 4
+    assert max(be.batches) == 1 and be.max_used <= 70_000
+
+
+def test_requests_join_while_others_run():
+    clk = Clock()
+    be = SimBackend(clk, pool=10**9, tick_base=1e-3, per_grid=0.0)
+    jobs = [Job(0, 0.0, 33, 33, 1e-10, payload=10), Job(1, 0.0035, 33, 33, 1e-10, payload=2)]
+    Server(be, clock=clk).run(jobs)
+    # job 1 arrives during job 0's 4th tick, joins, and finishes first
+    assert jobs[1].finished < jobs[0].finished
+    assert 2 in be.batches
+
+
+def test_latency_grows_past_saturation():
+    res = {}
+    for rate in (100.0, 100000.0):
+        clk = Clock()
+        be = SimBackend(clk, pool=10**9, tick_base=1e-3, per_grid=2e-4)
+        jobs = jobs_from_stream(rate=rate, count=200)
+        res[rate] = Server(be, max_active=16, clock=clk).run(jobs).summary()
+    assert res[100000.0]["p99_ms"] > res[100.0]["p99_ms"]
+    assert res[100.0]["p50_ms"] < 20
+
+
+def test_sequential_baseline():
+    jobs = [Job(k, 0.0, 17, 17, 1e-8) for k in range(5)]
+    stats = serve_sequential(lambda j: {"iterations": 3, "status": 0}, jobs)
+    assert stats.summary()["completed"] == 5
+    assert [j.finished for j in jobs] == sorted(j.finished for j in jobs)
+
+
+def test_summary_percentiles():
+    st = ServeStats(jobs=[Job(k, 0.0, 3, 3, 1.0, finished=float(k + 1)) for k in range(100)], wall=100.0)
+    s = st.summary()
+    assert s["p50_ms"] == np.percentile(np.arange(1, 101), 50) * 1e3
+    assert s["solves_per_s"] == 1.0
