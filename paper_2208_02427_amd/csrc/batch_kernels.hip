@@ -160,6 +160,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_coarse(const BatchItem* items,
         A.b = (const T*)it.f;
         A.out = (T*)it.out;
         A.minv = it.minv;
+        A.work = it.cwork;
+        A.bw = it.cbw;
+        A.ifast = it.cifast;
         A.ctrl = nullptr;
         A.m = it.m;
         A.n = it.n;

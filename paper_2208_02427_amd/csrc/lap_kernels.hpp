@@ -162,10 +162,15 @@ struct CoarseArgs {
     const T* u;         // boundary source (level 0) or nullptr (zero boundary)
     const T* b;         // right-hand side (nullable = 0)
     T* out;             // solution (interior written)
-    const double* minv; // (N x N) inverse of L_h on the interior unknowns, FP64, symmetric
+    const double* minv; // dense: (N x N) inverse of L_h on the interior unknowns, FP64, symmetric
+                        // banded: Cholesky factor of -L_h, N rows of (bw + 1) entries, row k
+                        // holding L(k, k), L(k, k-1), ..., L(k, k-bw)
+    double* work;       // banded: N doubles of FP64 scratch
     const Ctrl* ctrl;
     int m, n, P;
     double cx, cy;
+    int bw;             // 0: dense inverse; > 0: banded Cholesky with this bandwidth
+    int ifast;          // banded ordering: 1 = i fastest, 0 = j fastest
 };
 
 // ---- launchers (stencil_kernels.hip) ----
@@ -208,6 +213,10 @@ constexpr int kRowTile = 64;   // row lines per ADI row block
 hipError_t launch_adi_rows(const LineArgs& a, hipStream_t s);
 hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s);
 
+// Coarsest levels with at most this many unknowns use a dense inverse (all
+// lanes in parallel); larger ones a banded Cholesky factor.
+constexpr int kDenseCoarseMax = 1024;
+
 // ---- merged ragged-batch launches (batch_kernels.hip) ----
 // One grid's share of a merged launch: the arguments of the single-grid
 // kernel plus its tiling and the offset of its first tile in the launch.
@@ -217,7 +226,9 @@ struct BatchItem {
     const void* f;           // right-hand side
     const void* ec;          // sweep: coarse correction; defect: FP32 correction
     void* bc;                // restrict: coarse right-hand side; defect: FP32 rhs
-    const double* minv;      // coarse solve
+    const double* minv;      // coarse solve (dense inverse or banded factor)
+    double* cwork;           // banded coarse solve scratch
+    int cbw, cifast;
     double* partials;        // norm partials
     Ctrl* ctrl;
     double* scratch;         // ADI

@@ -195,6 +195,60 @@ bool coarse_inverse(int m, int n, double dx, double dy, std::vector<double>& out
     return true;
 }
 
+// Coarsest-level factor of levels too large for the dense inverse: banded
+// Cholesky of -L_h with the unknowns ordered along the longer side, so the
+// bandwidth is the number of interior nodes across the shorter side.  Band
+// row k holds L(k, k), L(k, k-1), ..., L(k, k-bw).
+constexpr int kBandMax = 128;
+constexpr size_t kBandStorageMax = (size_t)8 << 20;   // doubles
+
+bool coarse_band(int m, int n, double dx, double dy, std::vector<double>& out, int& bw, int& ifast) {
+    const Coef c = coef(dx, dy);
+    const int mi = m - 2, ni = n - 2, N = mi * ni;
+    ifast = mi <= ni ? 1 : 0;
+    const int fast = ifast ? mi : ni;
+    const double cf = ifast ? c.cx : c.cy, cs = ifast ? c.cy : c.cx;
+    bw = fast;
+    const int W = bw + 1;
+    if (bw > kBandMax || (size_t)N * W > kBandStorageMax) return false;
+    auto Aval = [&](int k, int p) -> double {   // entries of -L_h, p <= k
+        if (p == k) return c.d;
+        if (k - p == 1 && (k % fast) != 0) return -cf;
+        if (k - p == fast) return -cs;
+        return 0.0;
+    };
+    out.assign((size_t)N * W, 0.0);
+    auto L = [&](int k, int p) -> double& { return out[(size_t)k * W + (k - p)]; };
+    for (int k = 0; k < N; ++k) {
+        const int p0 = k - bw > 0 ? k - bw : 0;
+        for (int j = p0; j < k; ++j) {
+            double v = Aval(k, j);
+            const int q0 = (j - bw > p0) ? j - bw : p0;
+            for (int p = q0; p < j; ++p) v -= L(k, p) * L(j, p);
+            L(k, j) = v / L(j, j);
+        }
+        double v = Aval(k, k);
+        for (int p = p0; p < k; ++p) v -= L(k, p) * L(k, p);
+        if (!(v > 0.0)) return false;
+        L(k, k) = std::sqrt(v);
+    }
+    return true;
+}
+
+bool coarse_ok(const LevelGeo& C) {
+    const size_t N = C.interior();
+    if (N <= (size_t)kDenseCoarseMax) return true;
+    const size_t fast = std::min(C.m, C.n) - 2;
+    return fast <= (size_t)kBandMax && N * (fast + 1) <= kBandStorageMax;
+}
+
+size_t coarse_bytes(const LevelGeo& C) {
+    const size_t N = C.interior();
+    if (N <= (size_t)kDenseCoarseMax) return N * N * 8;
+    const size_t fast = std::min(C.m, C.n) - 2;
+    return N * (fast + 1) * 8;
+}
+
 enum Part { PART_ALL = 0, PART_HEAD = 1, PART_TAIL = 2 };
 
 enum KClass { KC_SWEEP = 0, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE,
@@ -307,7 +361,9 @@ struct lap_grid {
     double* f64 = nullptr;
     std::vector<LevelBufs<double>> l64;
     std::vector<LevelBufs<float>> l32;
-    double* minv = nullptr;
+    double* minv = nullptr;          // dense inverse or banded factor of the coarsest level
+    double* coarse_work = nullptr;   // banded solve scratch
+    int coarse_bw = 0, coarse_ifast = 1;
     double* adi_scratch = nullptr;
     double* adi_tab = nullptr;       // rows cprime, rows piv, cols cprime, cols piv (each maxK)
     int adi_maxk = 0;
@@ -365,8 +421,8 @@ Footprint footprint(int m, int n, bool has_f, int flags) {
         for (size_t l = 0; l < lv.size(); ++l)
             for (int k = 0; k < 3; ++k) fp.add((size_t)lv[l].n * lv[l].P * 4);
     if (flags & (LAP_ALLOC_FP64 | LAP_ALLOC_MIXED)) {
-        const size_t N = (size_t)(lv.back().m - 2) * (lv.back().n - 2);
-        fp.add(N * N * 8);
+        fp.add(coarse_bytes(lv.back()));
+        if (lv.back().interior() > (size_t)kDenseCoarseMax) fp.add(lv.back().interior() * 8);
     }
     if (flags & LAP_ALLOC_ADI) {
         fp.add(f0 * 8);
@@ -475,6 +531,9 @@ hipError_t enq_coarse(lap_grid* g, int l, const T* ubnd, const T* b, T* out) {
     a.b = b;
     a.out = out;
     a.minv = g->minv;
+    a.work = g->coarse_work;
+    a.bw = g->coarse_bw;
+    a.ifast = g->coarse_ifast;
     a.ctrl = g->ctrl;
     a.m = L.m;
     a.n = L.n;
@@ -1194,11 +1253,11 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
     if (check_ptr(psi0, "psi0") != LAP_OK) return LAP_EINVAL;
     if (flags <= 0 || flags > LAP_ALLOC_ALL) return fail(LAP_EINVAL, "bad allocation flags");
     auto lv = plan_levels(m, n, dx, dy);
-    if (flags == LAP_ALLOC_ALL && lv.back().interior() > 1024)
+    if (flags == LAP_ALLOC_ALL && !coarse_ok(lv.back()))
         flags = LAP_ALLOC_ADI;   // "everything the grid supports": no multigrid on this size
     const bool mg = (flags & (LAP_ALLOC_FP64 | LAP_ALLOC_MIXED)) != 0;
-    if (mg && lv.back().interior() > 1024)
-        return fail(LAP_EINVAL, "coarsest multigrid level has more than 1024 interior nodes; use sizes c*2^k+1");
+    if (mg && !coarse_ok(lv.back()))
+        return fail(LAP_EINVAL, "coarsest multigrid level too large for its direct solve; use sizes c*2^k+1");
     const Footprint fp = footprint(m, n, source != nullptr, flags);
     if (fp.bytes > c->arena.largest_free()) return fail(LAP_ENOMEM, "arena cannot hold the grid");
 
@@ -1246,15 +1305,25 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
         char key[96];
         snprintf(key, sizeof key, "%d:%d:%.17g:%.17g", C.m, C.n, C.dx, C.dy);
         auto it = c->inv_cache.find(key);
+        int bw = 0, ifast = 1;
         if (it == c->inv_cache.end()) {
-            if (!coarse_inverse(C.m, C.n, C.dx, C.dy, inv)) {
+            const bool okf = C.interior() <= (size_t)kDenseCoarseMax ? coarse_inverse(C.m, C.n, C.dx, C.dy, inv)
+                                                                     : coarse_band(C.m, C.n, C.dx, C.dy, inv, bw, ifast);
+            if (!okf) {
                 lap_grid_destroy(g);
                 return fail(LAP_EINVAL, "coarse operator factorisation failed");
             }
             c->inv_cache[key] = inv;
         } else {
             inv = it->second;
+            if (C.interior() > (size_t)kDenseCoarseMax) {
+                ifast = C.m <= C.n ? 1 : 0;
+                bw = std::min(C.m, C.n) - 2;
+            }
         }
+        g->coarse_bw = bw;
+        g->coarse_ifast = ifast;
+        if (bw > 0) g->coarse_work = (double*)A(C.interior() * 8);
         g->minv = (double*)A(inv.size() * 8);
     }
     if (flags & LAP_ALLOC_ADI) {
@@ -1648,6 +1717,9 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o) {
     it.ec = op.ec;
     it.bc = op.bc;
     it.minv = g->minv;
+    it.cwork = g->coarse_work;
+    it.cbw = g->coarse_bw;
+    it.cifast = g->coarse_ifast;
     it.partials = g->partials;
     it.ctrl = g->ctrl;
     it.m = L.m;

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse(CoarseArgs<T> A) {
 
 template <typename T>
 hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s) {
-    if ((a.m - 2) * (a.n - 2) > 1024) return hipErrorInvalidValue;
+    if (a.bw == 0 && (a.m - 2) * (a.n - 2) > kDenseCoarseMax) return hipErrorInvalidValue;
     k_coarse<T><<<1, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }

@@ -509,23 +509,52 @@ __device__ __forceinline__ void defect_tile(const DefectArgs& A, int tile, int l
 template <typename T>
 __device__ __forceinline__ void coarse_block(const CoarseArgs<T>& A, double* rhs) {
     const int mi = A.m - 2, ni = A.n - 2, N = mi * ni;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-        const int i = 1 + k % mi, j = 1 + k / mi;
+    // right-hand side of the interior system; Dirichlet values of the
+    // perimeter (level 0 only) move to the right-hand side
+    auto rhs_at = [&](int i, int j) {
         double v = A.b != nullptr ? (double)A.b[(size_t)j * A.P + i] : 0.0;
-        if (A.u != nullptr) {   // Dirichlet values of the perimeter move to the right-hand side
+        if (A.u != nullptr) {
             if (i == 1) v -= A.cx * (double)A.u[(size_t)j * A.P];
             if (i == A.m - 2) v -= A.cx * (double)A.u[(size_t)j * A.P + A.m - 1];
             if (j == 1) v -= A.cy * (double)A.u[i];
             if (j == A.n - 2) v -= A.cy * (double)A.u[(size_t)(A.n - 1) * A.P + i];
         }
-        rhs[k] = v;
+        return v;
+    };
+    if (A.bw == 0) {
+        for (int k = threadIdx.x; k < N; k += blockDim.x) rhs[k] = rhs_at(1 + k % mi, 1 + k / mi);
+        __syncthreads();
+        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+            double x = 0.0;
+            for (int l = 0; l < N; ++l) x = fma(A.minv[(size_t)l * N + k], rhs[l], x);
+            const int i = 1 + k % mi, j = 1 + k / mi;
+            A.out[(size_t)j * A.P + i] = (T)x;
+        }
+        return;
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-        double x = 0.0;
-        for (int l = 0; l < N; ++l) x = fma(A.minv[(size_t)l * N + k], rhs[l], x);
-        const int i = 1 + k % mi, j = 1 + k / mi;
-        A.out[(size_t)j * A.P + i] = (T)x;
+    // banded Cholesky of -L_h (unknowns ordered along the longer side, so the
+    // bandwidth is the shorter interior side): (-L_h) x = -rhs by forward and
+    // back substitution, sequential along the ordering (one lane)
+    if (threadIdx.x != 0) return;
+    const int bw = A.bw, W = bw + 1;
+    const int fast = A.ifast ? mi : ni;
+    double* y = A.work;
+    for (int k = 0; k < N; ++k) {
+        const int a = k % fast, c = k / fast;
+        const int i = 1 + (A.ifast ? a : c), j = 1 + (A.ifast ? c : a);
+        double v = -rhs_at(i, j);
+        const int dmax = k < bw ? k : bw;
+        for (int d = 1; d <= dmax; ++d) v = fma(-A.minv[(size_t)k * W + d], y[k - d], v);
+        y[k] = v / A.minv[(size_t)k * W];
+    }
+    for (int k = N - 1; k >= 0; --k) {
+        double v = y[k];
+        const int dmax = (N - 1 - k) < bw ? (N - 1 - k) : bw;
+        for (int d = 1; d <= dmax; ++d) v = fma(-A.minv[(size_t)(k + d) * W + d], y[k + d], v);
+        y[k] = v / A.minv[(size_t)k * W];
+        const int a = k % fast, c = k / fast;
+        const int i = 1 + (A.ifast ? a : c), j = 1 + (A.ifast ? c : a);
+        A.out[(size_t)j * A.P + i] = (T)y[k];
     }
 }
 

@@ -213,3 +213,39 @@ def test_warm_start_continues():
     assert np.array_equal(g1.read().cpu().numpy(), g2.read().cpu().numpy())
     g1.destroy()
     g2.destroy()
+
+
+@pytest.mark.parametrize("m,n", [(6, 400), (401, 8)])
+def test_banded_coarse_solve_single_level(m, n):
+    """A grid that cannot coarsen and has more than 1024 unknowns: multigrid
+    is one banded-Cholesky direct solve, equal to the exact DST solution."""
+    say("banded single level", m, n)
+    psi, f, dx, dy = rand_problem(m, n, m * n, dx=0.01, dy=0.013, interior=False)
+    g = make_grid(psi, f, dx, dy)
+    assert g.levels() == [(m, n)]
+    info = g.solve("mg", tol=0.0, max_iter=1)
+    ex = direct.dst_solve(m, n, dx, dy, psi, f)
+    assert maxabs(g.read().cpu().numpy(), ex) <= 1e-10 * max(1.0, np.max(np.abs(ex)))
+    g.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_banded_coarse_in_vcycle(precision):
+    """9 x 1025 coarsens once to 5 x 513 (1533 unknowns, banded factor)."""
+    say("banded coarse vcycle", precision)
+    m, n = 9, 1025
+    psi, f, dx, dy = rand_problem(m, n, 77, dx=1 / 8, dy=1 / 1024, interior=False)
+    g = make_grid(psi, f, dx, dy)
+    assert g.levels() == [(9, 1025), (5, 513)]
+    lv = omg.hierarchy(m, n, dx, dy)
+    if precision == "fp64":
+        info = g.solve("mg", tol=0.0, max_iter=1)
+        ref = psi.copy()
+        omg.vcycle(lv, 0, ref, f)
+        assert maxabs(g.read().cpu().numpy(), ref) <= 1e-10 * max(1.0, np.max(np.abs(ref)))
+    info = g.solve("mg", precision=precision, tol=1e-10, max_iter=60)
+    assert info["status"] == 0
+    got = g.read().cpu().numpy()
+    r0 = ogrid.norm2(ogrid.residual(psi, f, dx, dy))
+    assert ogrid.norm2(ogrid.residual(got, f, dx, dy)) / r0 < 1e-10
+    g.destroy()
