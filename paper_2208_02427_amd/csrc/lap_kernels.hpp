@@ -215,7 +215,7 @@ hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s);
 
 // Coarsest levels with at most this many unknowns use a dense inverse (all
 // lanes in parallel); larger ones a banded Cholesky factor.
-constexpr int kDenseCoarseMax = 1024;
+constexpr int kDenseCoarseMax = 256;
 
 // ---- merged ragged-batch launches (batch_kernels.hip) ----
 // One grid's share of a merged launch: the arguments of the single-grid

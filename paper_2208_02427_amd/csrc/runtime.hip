@@ -1300,6 +1300,7 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
             g->l32[l].b = (float*)A(sz);
         }
     std::vector<double> inv;
+    const std::vector<double>* factor = nullptr;   // lives in the context's cache
     if (mg) {
         const LevelGeo& C = lv.back();
         char key[96];
@@ -1315,7 +1316,6 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
             }
             c->inv_cache[key] = inv;
         } else {
-            inv = it->second;
             if (C.interior() > (size_t)kDenseCoarseMax) {
                 ifast = C.m <= C.n ? 1 : 0;
                 bw = std::min(C.m, C.n) - 2;
@@ -1324,7 +1324,8 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
         g->coarse_bw = bw;
         g->coarse_ifast = ifast;
         if (bw > 0) g->coarse_work = (double*)A(C.interior() * 8);
-        g->minv = (double*)A(inv.size() * 8);
+        factor = &c->inv_cache[key];
+        g->minv = (double*)A(factor->size() * 8);
     }
     if (flags & LAP_ALLOC_ADI) {
         g->adi_scratch = (double*)A(f0 * 8);
@@ -1352,8 +1353,8 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
     }
     hipError_t e = launch_write_field(psi0, g->psi[0], g->psi[1], m, n, g->P, s);
     if (e == hipSuccess && source) e = launch_write_field(source, g->f64, nullptr, m, n, g->P, s);
-    if (e == hipSuccess && mg) e = hipMemcpyAsync(g->minv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);   // inv (host) must outlive the copy
+    if (e == hipSuccess && mg)
+        e = hipMemcpyAsync(g->minv, factor->data(), factor->size() * 8, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         lap_grid_destroy(g);
         return fail(LAP_EHIP, std::string("grid upload: ") + hipGetErrorString(e));
@@ -1674,6 +1675,7 @@ struct lap_ctx::Plan {
     std::vector<BatchItem> items;
     BatchItem* dev = nullptr;
     hipGraphExec_t graph = nullptr;
+    int uses = 0;
 };
 
 namespace {
@@ -1906,7 +1908,9 @@ hipError_t run_plan_launches(lap_ctx* c, lap_ctx::Plan* p) {
 
 // Enqueue a plan: replay its captured graph (captured on first use) or launch.
 hipError_t run_plan(lap_ctx* c, lap_ctx::Plan* p, bool graph) {
-    if (graph && c->stream != nullptr && !c->timing) {
+    // capture a plan only once it is reused (a serving tick's active set
+    // changes often; a fixed batch replays the same plans every cycle)
+    if (graph && ++p->uses >= 2 && c->stream != nullptr && !c->timing) {
         if (!p->graph) {
             HIPERR(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = run_plan_launches(c, p);

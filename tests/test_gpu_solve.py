@@ -234,7 +234,7 @@ def test_banded_coarse_in_vcycle(precision):
     """9 x 1025 coarsens once to 5 x 513 (1533 unknowns, banded factor)."""
     say("banded coarse vcycle", precision)
     m, n = 9, 1025
-    psi, f, dx, dy = rand_problem(m, n, 77, dx=1 / 8, dy=1 / 1024, interior=False)
+    psi, f, dx, dy = rand_problem(m, n, 77, dx=1 / 1024, dy=1 / 1024, interior=False)
     g = make_grid(psi, f, dx, dy)
     assert g.levels() == [(9, 1025), (5, 513)]
     lv = omg.hierarchy(m, n, dx, dy)
