@@ -37,6 +37,11 @@ import workloads as W  # noqa: E402
 
 METRIC = "GLUP/s + time to 1e-10 residual (FP32+FP64 refine vs FP64); p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the fine FP64 sweep (8193^2, f = 0) measured with
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by the counts of a 1 GiB
+# stream copy (profiles/sweep_fp64_8193_mg.md); valid for the tiling it was
+# taken with (V = 1, auto chunks for 16384 waves) and this kernel version.
+SWEEP_FINE_TRAFFIC = {(1, 0, 16384): 1.1096e9}
 
 
 def lup_per_cycle(levels, nu1=2, nu2=2):
@@ -128,9 +133,12 @@ def run_gpu(args):
 
     # roofline of the dominant kernel: FP64 red-black sweep on the finest level
     ach = sweep["alg_bytes"] / (sweep["device_ms"] / 1e3) / 1e9 if sweep["device_ms"] > 0 else 0.0
+    tiling = ctx.get_tiling(0, 0, lap.size_class(N, N))
     out["roofline"] = {
         "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(ach / HBM_PEAK_GBS, 4),
+        "traffic": SWEEP_FINE_TRAFFIC.get(tuple(tiling)) if N == 8193 else None,
+        "tiling": {"V": tiling[0], "ty": tiling[1], "target_waves": tiling[2]},
         "kernel": "k_sweep<double,V,0> (fused two-colour red-black sweep, finest level, f = 0)",
         "alg_bytes_per_launch": sweep["alg_bytes"] / max(1, sweep["launches"]),
         "avg_launch_ms": sweep["device_ms"] / max(1, sweep["launches"]),
