@@ -135,7 +135,9 @@ lap_status lap_ctx_usage(lap_ctx* ctx, size_t* used, size_t* largest_free);
  * nodes x bytes per node of that kernel).  Classes: 0 RB sweep, 1 RB sweep
  * with fused prolongation, 2 residual + full weighting, 3 defect correction
  * (FP64), 4 coarse solve, 5 norm finalise, 6 ADI row lines, 7 ADI column
- * lines, 8 residual.  `fine_only` selects the finest-level bucket.
+ * lines, 8 residual, 9 small-level subtree (one launch per sub-V-cycle; its
+ * bytes are the top level's right-hand side read and result written).
+ * `fine_only` selects the finest-level bucket.
  * lap_ctx_kernel_stats synchronises the stream. */
 lap_status lap_ctx_set_timing(lap_ctx* ctx, int32_t on);
 lap_status lap_ctx_kernel_stats(lap_ctx* ctx, int32_t kernel_class, int32_t fine_only,
@@ -153,6 +155,20 @@ lap_status lap_ctx_set_tiling(lap_ctx* ctx, int32_t kernel_class, int32_t dtype,
                               int32_t V, int32_t ty, int32_t target_waves);
 lap_status lap_ctx_get_tiling(lap_ctx* ctx, int32_t kernel_class, int32_t dtype, int32_t size_class,
                               int32_t* V, int32_t* ty, int32_t* target_waves);
+
+/* Small-level subtree (multigrid, section 2.3's V-cycle below a size): from
+ * the first zero-start level whose remaining hierarchy (u and b of every level
+ * below it, plus the coarsest right-hand side) fits one workgroup's LDS, the
+ * rest of the V-cycle (pre-smoothing, full weighting, coarsest solve,
+ * bilinear correction, post-smoothing on every level below) runs as ONE
+ * launch of one workgroup (per grid, in a batch) instead of five launches per
+ * level.  The result is bitwise the one of the multi-launch schedule.
+ * max_nodes caps the subtree's top level at m*n nodes: -1 (default) = any
+ * level that fits LDS, 0 = never use the subtree.  lap_ctx_get_subtree also
+ * reports the LDS bytes one workgroup may use on this device.  Changing the
+ * setting drops captured graphs and batch plans. */
+lap_status lap_ctx_set_subtree(lap_ctx* ctx, int64_t max_nodes);
+lap_status lap_ctx_get_subtree(lap_ctx* ctx, int64_t* max_nodes, int32_t* lds_bytes);
 
 /* Autotuner: time every candidate tiling (V in {1,2,4}; ty in {16,32,64,128};
  * auto with 1 or 2 device wave rounds) of the sweep, sweep+prolongation,

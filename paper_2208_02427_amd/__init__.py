@@ -158,6 +158,16 @@ class Context:
                                         ctypes.byref(t), ctypes.byref(w)))
         return v.value, t.value, w.value
 
+    def set_subtree(self, max_nodes=-1):
+        """Small-level subtree: -1 any level whose sub-V-cycle fits LDS, 0 off,
+        else the largest top level (m*n nodes) that may run as one launch."""
+        _check(lib().lap_ctx_set_subtree(self.handle, int(max_nodes)))
+
+    def get_subtree(self):
+        v, b = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().lap_ctx_get_subtree(self.handle, ctypes.byref(v), ctypes.byref(b)))
+        return v.value, b.value
+
     def grid(self, psi0, f=None, dx=1.0, dy=1.0, alloc=LAP_ALLOC_ALL) -> "Grid":
         return Grid(self, psi0, f, dx, dy, alloc)
 

@@ -173,12 +173,50 @@ struct CoarseArgs {
     int ifast;          // banded ordering: 1 = i fastest, 0 = j fastest
 };
 
+// The small-level tail of a V-cycle run by one workgroup with every level
+// resident in LDS: from a zero-start level (the subtree's top) down to the
+// coarsest and back (nu1 sweeps, full weighting, recursion, exact coarsest
+// solve, bilinear correction, nu2 sweeps).  Only the top level's right-hand
+// side is read from HBM and only its result is written back; the levels
+// below it are internal to one launch.
+constexpr int kMaxSub = 16;
+constexpr int kSubBlock = 1024;
+
+template <typename T>
+struct SubLevel {
+    int m, n;          // level size (LDS pitch m)
+    int ou, ob;        // LDS offsets (elements of T) of the level's u and b
+    T cx, cy, d, inv_d;
+};
+
+template <typename T>
+struct SubtreeArgs {
+    T* out;              // top-level result, HBM, pitch P (boundary written as 0)
+    const T* b;          // top-level right-hand side, HBM, pitch P (nullable = 0)
+    int P;
+    int nlev, nu1, nu2;
+    T omega;
+    int lds_elems;       // elements of T for all levels' u and b
+    int lds_bytes;       // dynamic LDS of the launch (levels + coarse rhs)
+    const double* minv;  // coarsest factor (dense inverse or band), see CoarseArgs
+    double* work;
+    int bw, ifast;
+    double ccx, ccy;     // coarsest-level coefficients in FP64
+    const Ctrl* ctrl;
+    SubLevel<T> lv[kMaxSub];
+};
+
 // ---- launchers (stencil_kernels.hip) ----
 template <typename T> hipError_t launch_sweep(const SweepArgs<T>& a, int flags, hipStream_t s);
 template <typename T> hipError_t launch_restrict(const RestrictArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_residual(const ResidualArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s);
 hipError_t launch_defect(const DefectArgs& a, hipStream_t s);
+template <typename T> hipError_t launch_subtree(const SubtreeArgs<T>& a, hipStream_t s);
+// merged subtree launch: one workgroup per item, items[k].sub -> SubtreeArgs<T> in device memory
+hipError_t launch_batch_subtree(int dt, const struct BatchItem* items, int count, int lds_bytes, hipStream_t s);
+// allow dynamic LDS up to `bytes` for the subtree kernels (once per device)
+hipError_t subtree_set_lds_limit(int bytes);
 // Sum the per-tile partials in a fixed order and run the stopping test.
 // mode 0: stopping test of a solve; mode 1: write norms only (out2 = {sum, max}).
 hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, double* out2, int mode,
@@ -240,9 +278,11 @@ struct BatchItem {
     int ntiles, tile0;       // tiles (or line blocks) of this item; prefix offset in the launch
     int flags;               // SW_F for sweeps; ADI relaxation form
     int parity;              // ADI line parity
+    const void* sub;         // BK_SUBTREE: device SubtreeArgs<T> of this grid
 };
 
-enum BatchKind { BK_SWEEP = 0, BK_RESTRICT, BK_COARSE, BK_FINALIZE, BK_RESNORM, BK_DEFECT, BK_ADI_ROWS, BK_ADI_COLS };
+enum BatchKind { BK_SWEEP = 0, BK_RESTRICT, BK_COARSE, BK_FINALIZE, BK_RESNORM, BK_DEFECT, BK_ADI_ROWS, BK_ADI_COLS,
+                 BK_SUBTREE };
 // Launch one merged operation over `count` items (device array) covering
 // `total` tiles with a persistent grid of `blocks` workgroups.
 hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items, int count, int total, int blocks,

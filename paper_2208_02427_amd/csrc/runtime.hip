@@ -252,7 +252,7 @@ size_t coarse_bytes(const LevelGeo& C) {
 enum Part { PART_ALL = 0, PART_HEAD = 1, PART_TAIL = 2 };
 
 enum KClass { KC_SWEEP = 0, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE,
-              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_COUNT };
+              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_COUNT };
 
 // Size classes for tilings, by interior node count.
 int size_class(size_t nint) {
@@ -285,6 +285,10 @@ struct lap_ctx {
     int tileTY[4][KC_COUNT][2];     // 0: auto (chunks sized for tileT waves)
     int tileT[4][KC_COUNT][2];
     int wave_cap = 8192;            // CUs x 32 wavefronts (read from the device)
+    // small-level subtree: LDS the device grants one workgroup, and the
+    // largest top level (nodes m*n) a subtree may start at (0: never)
+    int lds_max = 65536;
+    int64_t sub_max_nodes = -1;     // -1: any level whose subtree fits in LDS
     std::vector<lap_grid*> grids;
     std::map<std::string, std::vector<double>> inv_cache;
     Ctrl* pinned = nullptr;        // 4 host slots
@@ -446,7 +450,84 @@ template <typename T>
 struct HierView {
     std::vector<T*> u0, u1, b;
     bool zero_start0 = false;  // level 0 starts from zero (error equation) or holds the iterate
+    int sub_root = -1;         // level whose whole sub-V-cycle runs as one LDS-resident launch
 };
+
+// LDS bytes of a subtree rooted at level l: u and b of every level l..L-1
+// (pitch m), then the coarsest right-hand side in FP64 (dense coarsest solve)
+template <typename T>
+size_t subtree_lds(const std::vector<LevelGeo>& geo, int l) {
+    size_t e = 0;
+    for (size_t k = (size_t)l; k < geo.size(); ++k) e += 2 * (size_t)geo[k].m * (size_t)geo[k].n;
+    size_t bytes = (e * sizeof(T) + 7) / 8 * 8;
+    const size_t N = geo.back().interior();
+    if (N <= (size_t)kDenseCoarseMax) bytes += N * sizeof(double);
+    return bytes;
+}
+
+// First level at or below `lmin` from which the rest of the V-cycle fits one
+// workgroup's LDS (and the context's node limit); -1 if none.  The root must
+// have a level below it, and at most kMaxSub levels may take part.
+template <typename T>
+int subtree_root(const lap_grid* g, int lmin) {
+    const lap_ctx* c = g->ctx;
+    const int L = (int)g->geo.size();
+    if (c->sub_max_nodes == 0) return -1;
+    for (int l = std::max(lmin, L - kMaxSub); l < L - 1; ++l) {
+        const LevelGeo& G = g->geo[l];
+        if (c->sub_max_nodes > 0 && (int64_t)G.m * G.n > c->sub_max_nodes) continue;
+        if (subtree_lds<T>(g->geo, l) <= (size_t)c->lds_max) return l;
+    }
+    return -1;
+}
+
+// Arguments of the subtree rooted at level l (u -> out, right-hand side b).
+template <typename T>
+SubtreeArgs<T> subtree_args(const lap_grid* g, int l, T* out, const T* b, double omega, int nus) {
+    SubtreeArgs<T> a{};
+    const int L = (int)g->geo.size();
+    a.out = out;
+    a.b = b;
+    a.P = g->geo[l].P;
+    a.nlev = L - l;
+    a.nu1 = nus & 255;
+    a.nu2 = nus >> 8;
+    a.omega = (T)omega;
+    int off = 0;
+    for (int k = 0; k < a.nlev; ++k) {
+        const LevelGeo& G = g->geo[l + k];
+        const Coef c = coef(G.dx, G.dy);
+        SubLevel<T>& v = a.lv[k];
+        v.m = G.m;
+        v.n = G.n;
+        v.ou = off;
+        off += G.m * G.n;
+        v.ob = off;
+        off += G.m * G.n;
+        v.cx = (T)c.cx;
+        v.cy = (T)c.cy;
+        v.d = (T)c.d;
+        v.inv_d = (T)c.inv_d;
+    }
+    a.lds_elems = off;
+    a.lds_bytes = (int)subtree_lds<T>(g->geo, l);
+    a.minv = g->minv;
+    a.work = g->coarse_work;
+    a.bw = g->coarse_bw;
+    a.ifast = g->coarse_ifast;
+    const Coef cc = coef(g->geo.back().dx, g->geo.back().dy);
+    a.ccx = cc.cx;
+    a.ccy = cc.cy;
+    a.ctrl = g->ctrl;
+    return a;
+}
+
+template <typename T>
+hipError_t enq_subtree(lap_grid* g, int l, T* out, const T* b, double omega, int nus) {
+    const SubtreeArgs<T> a = subtree_args<T>(g, l, out, b, omega, nus);
+    const double bytes = 2.0 * sizeof(T) * g->geo[l].m * (double)g->geo[l].n;
+    return g->ctx->timed(KC_SUBTREE, false, bytes, [&]() { return launch_subtree<T>(a, g->ctx->stream); });
+}
 
 template <typename T> constexpr int dt_of() { return sizeof(T) == 8 ? 0 : 1; }
 
@@ -572,14 +653,15 @@ hipError_t enq_residual_norm(lap_grid* g, int l, const T* u, const T* f) {
 // Keys order a V-cycle top-aligned across grids of different depth: the
 // pre-smoothing and restriction of level l, then every grid's coarsest
 // solve, then the post-smoothing of level l from coarse to fine.
-enum OpKind { OP_SWEEP, OP_RESTRICT, OP_COARSE, OP_FINALIZE, OP_RESNORM, OP_DEFECT, OP_ADI_ROWS, OP_ADI_COLS };
+enum OpKind { OP_SWEEP, OP_RESTRICT, OP_COARSE, OP_FINALIZE, OP_RESNORM, OP_DEFECT, OP_ADI_ROWS, OP_ADI_COLS,
+              OP_SUBTREE };
 
 struct Op {
     long key;
     int kind;
     int dt;          // 0 FP64, 1 FP32
     int level;
-    int flags;       // sweep flags
+    int flags;       // sweep flags; subtree: nu1 | nu2 << 8
     const void* in;  // sweep input, restrict / residual u, defect psi_in, coarse boundary source
     void* out;       // sweep / coarse output, defect psi_out
     const void* f;   // right-hand side
@@ -617,6 +699,8 @@ void push_op(std::vector<Op>& ops, long key, int kind, int level, int flags, con
     ops.push_back(op);
 }
 
+int vcycle_result_index(const lap_opts& o);
+
 // One V-cycle on level l of hierarchy H.  Level 0 either holds the iterate in
 // u0[0] (FP64 multigrid: the result returns to u0[0] since nu1+nu2 is even)
 // or starts from zero (error equation).  Returns the buffer index (0/1)
@@ -631,6 +715,14 @@ int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm
     const bool tail = !split || part != PART_HEAD;
     T* U[2] = {H.u0[l], H.u1[l]};
     const T* b = H.b[l];
+    if (zero_start && l == H.sub_root && l < L - 1) {
+        // the whole sub-V-cycle in one launch; its result lands where the
+        // multi-launch schedule would leave it
+        const int ri = vcycle_result_index(o);
+        push_op<T>(ops, KEY_COARSE, OP_SUBTREE, l, o.nu1 | (o.nu2 << 8), nullptr, U[ri], b, nullptr, nullptr,
+                   o.omega);
+        return ri;
+    }
     if (l == L - 1) {
         if (split && head) {
             push_op<T>(ops, KEY_HEAD, OP_RESNORM, l, 0, U[0], nullptr, b, nullptr, nullptr, 0.0);
@@ -701,6 +793,7 @@ HierView<double> view64(lap_grid* g) {
         H.b[l] = g->l64[l].b;
     }
     H.zero_start0 = false;
+    H.sub_root = subtree_root<double>(g, 1);
     return H;
 }
 
@@ -716,6 +809,7 @@ HierView<float> view32(lap_grid* g) {
         H.b[l] = g->l32[l].b;
     }
     H.zero_start0 = true;
+    H.sub_root = subtree_root<float>(g, 0);
     return H;
 }
 
@@ -841,6 +935,10 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
             return enq_adi_half(g, op.omega, op.flags, 0, op.parity);
         case OP_ADI_COLS:
             return enq_adi_half(g, op.omega, op.flags, 1, op.parity);
+        case OP_SUBTREE:
+            if (op.dt == 0)
+                return enq_subtree<double>(g, l, (double*)op.out, (const double*)op.f, op.omega, op.flags);
+            return enq_subtree<float>(g, l, (float*)op.out, (const float*)op.f, op.omega, op.flags);
     }
     return hipErrorInvalidValue;
 }
@@ -1168,6 +1266,18 @@ lap_status lap_ctx_create(void* dev_arena, size_t arena_bytes, void* hip_stream,
             hipDeviceGetAttribute(&tpm, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev) == hipSuccess &&
             cus > 0 && tpm > 0)
             c->wave_cap = cus * (tpm / kWave);
+        int lds = 0, optin = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 0;
+        if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
+        lds = std::max(lds, optin);
+        if (lds > 0) {
+            if (subtree_set_lds_limit(lds) == hipSuccess) {
+                c->lds_max = lds;
+            } else {
+                (void)hipGetLastError();
+                c->lds_max = std::min(lds, 65536);
+            }
+        }
     }
     default_tilings(c);
     if (hipHostMalloc((void**)&c->pinned, 4 * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
@@ -1666,6 +1776,7 @@ struct MergedLaunch {
     int cls;                 // kernel class for timing
     bool fine;
     int count, total, blocks;
+    int lds;                 // subtree: dynamic LDS bytes (largest item)
     size_t off;              // first item in the plan's item array
     double bytes;            // algorithmic bytes of the launch
 };
@@ -1673,6 +1784,8 @@ struct MergedLaunch {
 struct lap_ctx::Plan {
     std::vector<MergedLaunch> launches;
     std::vector<BatchItem> items;
+    std::vector<unsigned char> subs;                 // SubtreeArgs of subtree items
+    std::vector<std::pair<size_t, size_t>> sub_of;   // (item, byte offset in subs)
     BatchItem* dev = nullptr;
     hipGraphExec_t graph = nullptr;
     int uses = 0;
@@ -1693,6 +1806,18 @@ void plans_clear(lap_ctx* c) {
     c->plans.clear();
 }
 
+// Batch plans and captured per-grid graphs bake in tilings and the subtree
+// split: drop them when either changes.
+void invalidate_cached(lap_ctx* c) {
+    plans_clear(c);
+    for (lap_grid* g : c->grids)
+        if (g->graph) {
+            hipGraphExecDestroy(g->graph);
+            g->graph = nullptr;
+            g->graph_key.clear();
+        }
+}
+
 int batch_kind(int op_kind) {
     switch (op_kind) {
         case OP_SWEEP: return BK_SWEEP;
@@ -1703,6 +1828,7 @@ int batch_kind(int op_kind) {
         case OP_DEFECT: return BK_DEFECT;
         case OP_ADI_ROWS: return BK_ADI_ROWS;
         case OP_ADI_COLS: return BK_ADI_COLS;
+        case OP_SUBTREE: return BK_SUBTREE;
     }
     return -1;
 }
@@ -1766,7 +1892,8 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o) {
             t.ntiles = (lines + per - 1) / per;
             break;
         }
-        case OP_COARSE: t.ntiles = 1; break;
+        case OP_COARSE:
+        case OP_SUBTREE: t.ntiles = 1; break;
     }
     it.V = t.V;
     it.ty = t.ty;
@@ -1791,6 +1918,7 @@ double item_bytes(const Op& op, const BatchItem& it) {
         case OP_DEFECT: return (8.0 + (op.ec ? 4.0 : 0.0) + (op.f ? 8.0 : 0.0) + 12.0) * n;
         case OP_ADI_ROWS:
         case OP_ADI_COLS: return (op.f ? 48.0 : 40.0) * 0.5 * n;
+        case OP_SUBTREE: return 2.0 * sz * (double)it.m * (double)it.n;
         default: return 0.0;
     }
 }
@@ -1805,6 +1933,7 @@ int kclass_of(const Op& op) {
         case OP_DEFECT: return KC_DEFECT;
         case OP_ADI_ROWS: return KC_ADI_ROWS;
         case OP_ADI_COLS: return KC_ADI_COLS;
+        case OP_SUBTREE: return KC_SUBTREE;
     }
     return KC_SWEEP;
 }
@@ -1860,13 +1989,35 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
             for (auto& go : skv.second) {
                 BatchItem it = make_item(go.first, go.second, o);
                 it.tile0 = tile0;
-                if (L.kind != BK_COARSE && L.kind != BK_FINALIZE) tile0 += it.ntiles;
+                if (L.kind == BK_SUBTREE) {
+                    const Op& op = go.second;
+                    const size_t off = p->subs.size();
+                    int lds = 0;
+                    if (op.dt == 0) {
+                        const auto a = subtree_args<double>(go.first, op.level, (double*)op.out,
+                                                            (const double*)op.f, op.omega, op.flags);
+                        p->subs.resize(off + round_up(sizeof(a), 64));
+                        std::memcpy(p->subs.data() + off, &a, sizeof(a));
+                        lds = a.lds_bytes;
+                    } else {
+                        const auto a = subtree_args<float>(go.first, op.level, (float*)op.out, (const float*)op.f,
+                                                           op.omega, op.flags);
+                        p->subs.resize(off + round_up(sizeof(a), 64));
+                        std::memcpy(p->subs.data() + off, &a, sizeof(a));
+                        lds = a.lds_bytes;
+                    }
+                    L.lds = std::max(L.lds, lds);
+                    p->sub_of.push_back({p->items.size(), off});
+                }
+                if (L.kind != BK_COARSE && L.kind != BK_FINALIZE && L.kind != BK_SUBTREE) tile0 += it.ntiles;
                 L.bytes += item_bytes(go.second, it);
                 p->items.push_back(it);
             }
             L.count = (int)skv.second.size();
             L.total = tile0;
-            if (L.kind == BK_COARSE || L.kind == BK_FINALIZE) {
+            if (L.kind == BK_SUBTREE) {
+                L.blocks = L.count;
+            } else if (L.kind == BK_COARSE || L.kind == BK_FINALIZE) {
                 L.blocks = std::min(L.count, 2048);
             } else if (L.kind == BK_ADI_ROWS || L.kind == BK_ADI_COLS) {
                 L.blocks = std::max(1, std::min(L.total, 4096));
@@ -1878,13 +2029,18 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
             p->launches.push_back(L);
         }
     }
-    p->dev = (BatchItem*)c->arena.alloc(p->items.size() * sizeof(BatchItem));
+    const size_t ibytes = round_up(p->items.size() * sizeof(BatchItem), kAlign);
+    p->dev = (BatchItem*)c->arena.alloc(ibytes + p->subs.size());
     if (!p->dev) {
         delete p;
         return fail(LAP_ENOMEM, "arena cannot hold the batch plan");
     }
+    unsigned char* sub_dev = (unsigned char*)p->dev + ibytes;
+    for (const auto& so : p->sub_of) p->items[so.first].sub = sub_dev + so.second;
     if (hipMemcpyAsync(p->dev, p->items.data(), p->items.size() * sizeof(BatchItem), hipMemcpyHostToDevice,
-                       c->stream) != hipSuccess) {
+                       c->stream) != hipSuccess ||
+        (!p->subs.empty() &&
+         hipMemcpyAsync(sub_dev, p->subs.data(), p->subs.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess)) {
         plan_free(c, p);
         return fail(LAP_EHIP, "plan upload failed");
     }
@@ -1901,6 +2057,7 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
 hipError_t run_plan_launches(lap_ctx* c, lap_ctx::Plan* p) {
     for (const MergedLaunch& L : p->launches)
         HIPERR(c->timed(L.cls, L.fine, L.bytes, [&]() {
+            if (L.kind == BK_SUBTREE) return launch_batch_subtree(L.dt, p->dev + L.off, L.count, L.lds, c->stream);
             return launch_batch(L.kind, L.dt, L.flags, p->dev + L.off, L.count, L.total, L.blocks, c->stream);
         }));
     return hipSuccess;
@@ -2124,6 +2281,22 @@ extern "C" lap_status lap_ctx_set_tiling(lap_ctx* c, int32_t cls, int32_t dtype,
     c->tileV[sc][cls][dtype] = V;
     c->tileTY[sc][cls][dtype] = ty;
     c->tileT[sc][cls][dtype] = ty == 0 ? target : 0;
+    invalidate_cached(c);
+    return LAP_OK;
+}
+
+extern "C" lap_status lap_ctx_set_subtree(lap_ctx* c, int64_t max_nodes) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    if (max_nodes < -1) return fail(LAP_EINVAL, "max_nodes must be -1, 0 or a node count");
+    c->sub_max_nodes = max_nodes;
+    invalidate_cached(c);
+    return LAP_OK;
+}
+
+extern "C" lap_status lap_ctx_get_subtree(lap_ctx* c, int64_t* max_nodes, int32_t* lds_bytes) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    if (max_nodes) *max_nodes = c->sub_max_nodes;
+    if (lds_bytes) *lds_bytes = c->lds_max;
     return LAP_OK;
 }
 
@@ -2298,13 +2471,7 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
     release();
     if (result != LAP_OK) return result;
     // cached graphs and batch plans hold the old tilings
-    plans_clear(c);
-    for (lap_grid* g : c->grids)
-        if (g->graph) {
-            hipGraphExecDestroy(g->graph);
-            g->graph = nullptr;
-            g->graph_key.clear();
-        }
+    invalidate_cached(c);
     if (report && report_bytes > 0) {
         std::strncpy(report, js.c_str(), report_bytes - 1);
         report[report_bytes - 1] = 0;

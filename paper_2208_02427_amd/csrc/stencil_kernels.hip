@@ -245,4 +245,58 @@ hipError_t launch_copy(const double* src, double* dst, int m, int n, int P, cons
     return hipGetLastError();
 }
 
+// ------------------------------------------------------- small-level subtree
+// Dynamic LDS: the levels' u and b (T), then the coarsest right-hand side
+// (double) at the next 8-byte boundary.
+template <typename T>
+__device__ __forceinline__ double* subtree_rhs(T* s, int lds_elems) {
+    return reinterpret_cast<double*>(s + ((lds_elems * (int)sizeof(T) + 7) / 8) * 8 / (int)sizeof(T));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSubBlock) void k_subtree(SubtreeArgs<T> S) {
+    if (S.ctrl != nullptr && S.ctrl->done) return;
+    extern __shared__ double lds_raw[];
+    T* s = reinterpret_cast<T*>(lds_raw);
+    subtree_block<T>(S, s, subtree_rhs(s, S.lds_elems));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSubBlock) void k_batch_subtree(const BatchItem* items, int count) {
+    const BatchItem& it = items[blockIdx.x];
+    if (it.ctrl != nullptr && it.ctrl->done) return;
+    const SubtreeArgs<T>& S = *reinterpret_cast<const SubtreeArgs<T>*>(it.sub);
+    extern __shared__ double lds_raw[];
+    T* s = reinterpret_cast<T*>(lds_raw);
+    subtree_block<T>(S, s, subtree_rhs(s, S.lds_elems));
+}
+
+template <typename T>
+hipError_t launch_subtree(const SubtreeArgs<T>& a, hipStream_t s) {
+    if (a.nlev < 2 || a.nlev > kMaxSub) return hipErrorInvalidValue;
+    k_subtree<T><<<1, kSubBlock, a.lds_bytes, s>>>(a);
+    return hipGetLastError();
+}
+template hipError_t launch_subtree<double>(const SubtreeArgs<double>&, hipStream_t);
+template hipError_t launch_subtree<float>(const SubtreeArgs<float>&, hipStream_t);
+
+hipError_t launch_batch_subtree(int dt, const BatchItem* items, int count, int lds_bytes, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (dt == 0)
+        k_batch_subtree<double><<<count, kSubBlock, lds_bytes, s>>>(items, count);
+    else
+        k_batch_subtree<float><<<count, kSubBlock, lds_bytes, s>>>(items, count);
+    return hipGetLastError();
+}
+
+hipError_t subtree_set_lds_limit(int bytes) {
+    const void* fns[4] = {(const void*)k_subtree<double>, (const void*)k_subtree<float>,
+                          (const void*)k_batch_subtree<double>, (const void*)k_batch_subtree<float>};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace lap

@@ -558,6 +558,132 @@ __device__ __forceinline__ void coarse_block(const CoarseArgs<T>& A, double* rhs
     }
 }
 
+// ------------------------------------------------------- small-level subtree
+// One workgroup, every level in LDS (pitch m), a barrier between passes.
+// Each node value is produced by the same expression, on the same operands,
+// as in the streaming kernels, so the top level's result is bitwise the one
+// of the multi-launch schedule.  Levels that are smoothed have odd m, so the
+// interior index t = (j-1)(m-2) + (i-1) has the parity of i + j: colour c is
+// exactly the nodes t = 2h + c.
+template <typename T>
+__device__ __forceinline__ void sub_colour(T* s, const SubLevel<T>& L, int colour, T om) {
+    const int mi = L.m - 2, N = mi * (L.n - 2), m = L.m;
+    T* u = s + L.ou;
+    const T* b = s + L.ob;
+    for (int h = threadIdx.x; 2 * h + colour < N; h += blockDim.x) {
+        const int t = 2 * h + colour;
+        const int c = (1 + t / mi) * m + 1 + t % mi;
+        const T x = (fma(L.cy, u[c - m] + u[c + m], L.cx * (u[c - 1] + u[c + 1])) - b[c]) * L.inv_d;
+        u[c] = fma(om, x - u[c], u[c]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void sub_sweep(T* s, const SubLevel<T>& L, T om) {
+    sub_colour<T>(s, L, 0, om);
+    __syncthreads();
+    sub_colour<T>(s, L, 1, om);
+    __syncthreads();
+}
+
+// residual b - L u at an interior node
+template <typename T>
+__device__ __forceinline__ T sub_res(const T* u, const T* b, const SubLevel<T>& L, int c) {
+    const int m = L.m;
+    const T Lu = fma(-L.d, u[c], fma(L.cy, u[c - m] + u[c + m], L.cx * (u[c - 1] + u[c + 1])));
+    return b[c] - Lu;
+}
+
+// full weighting of the residual of level F onto the right-hand side of C
+// (the nine fine nodes of an interior coarse node are interior)
+template <typename T>
+__device__ __forceinline__ void sub_restrict(T* s, const SubLevel<T>& F, const SubLevel<T>& C) {
+    const int mi = C.m - 2, N = mi * (C.n - 2), m = F.m;
+    const T* u = s + F.ou;
+    const T* b = s + F.ob;
+    T* bc = s + C.ob;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const int I = 1 + k % mi, J = 1 + k / mi;
+        const int c = 2 * J * m + 2 * I;
+        const T Cc = sub_res(u, b, F, c), W = sub_res(u, b, F, c - 1), E = sub_res(u, b, F, c + 1);
+        const T S = sub_res(u, b, F, c - m), Nn = sub_res(u, b, F, c + m);
+        const T SW = sub_res(u, b, F, c - m - 1), SE = sub_res(u, b, F, c - m + 1);
+        const T NW = sub_res(u, b, F, c + m - 1), NE = sub_res(u, b, F, c + m + 1);
+        bc[J * C.m + I] = (fma(T(4), Cc, T(2) * ((W + E) + (S + Nn))) + ((SW + SE) + (NW + NE))) * T(0.0625);
+    }
+}
+
+// u_F += P(u_C) on the interior of F (bilinear interpolation)
+template <typename T>
+__device__ __forceinline__ void sub_prolong_add(T* s, const SubLevel<T>& F, const SubLevel<T>& C) {
+    const int mi = F.m - 2, N = mi * (F.n - 2);
+    T* u = s + F.ou;
+    const T* ec = s + C.ou;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const int i = 1 + k % mi, j = 1 + k / mi;
+        const int I = i >> 1, J = j >> 1;
+        const bool sx = (i & 1) != 0, ty = (j & 1) != 0;
+        const T* r0 = ec + J * C.m + I;
+        const T e00 = r0[0];
+        const T e10 = sx ? r0[1] : T(0);
+        const T e01 = ty ? r0[C.m] : T(0);
+        const T e11 = (sx && ty) ? r0[C.m + 1] : T(0);
+        const T p_even = ty ? (e00 + e01) * T(0.5) : e00;
+        const T p_odd = ty ? ((e00 + e10) + (e01 + e11)) * T(0.25) : (e00 + e10) * T(0.5);
+        const T p = sx ? p_odd : p_even;
+        const int c = j * F.m + i;
+        u[c] = u[c] + p;
+    }
+}
+
+template <typename T>
+__device__ void subtree_block(const SubtreeArgs<T>& S, T* s, double* rhs) {
+    const int L = S.nlev;
+    const SubLevel<T>& top = S.lv[0];
+    // zero every level (zero start, homogeneous boundary), then the top
+    // level's right-hand side from HBM
+    const int tb0 = top.ob, tb1 = top.ob + top.m * top.n;
+    for (int k = threadIdx.x; k < S.lds_elems; k += blockDim.x)
+        if (k < tb0 || k >= tb1) s[k] = T(0);
+    for (int k = threadIdx.x; k < top.m * top.n; k += blockDim.x) {
+        const int i = k % top.m, j = k / top.m;
+        s[tb0 + k] = S.b != nullptr ? S.b[(size_t)j * S.P + i] : T(0);
+    }
+    __syncthreads();
+    for (int k = 0; k + 1 < L; ++k) {
+        for (int q = 0; q < S.nu1; ++q) sub_sweep<T>(s, S.lv[k], S.omega);
+        sub_restrict<T>(s, S.lv[k], S.lv[k + 1]);
+        __syncthreads();
+    }
+    {
+        const SubLevel<T>& C = S.lv[L - 1];
+        CoarseArgs<T> A{};
+        A.u = nullptr;
+        A.b = s + C.ob;
+        A.out = s + C.ou;
+        A.minv = S.minv;
+        A.work = S.work;
+        A.bw = S.bw;
+        A.ifast = S.ifast;
+        A.m = C.m;
+        A.n = C.n;
+        A.P = C.m;
+        A.cx = S.ccx;
+        A.cy = S.ccy;
+        coarse_block<T>(A, rhs);
+        __syncthreads();
+    }
+    for (int k = L - 2; k >= 0; --k) {
+        sub_prolong_add<T>(s, S.lv[k], S.lv[k + 1]);
+        __syncthreads();
+        for (int q = 0; q < S.nu2; ++q) sub_sweep<T>(s, S.lv[k], S.omega);
+    }
+    for (int k = threadIdx.x; k < top.m * top.n; k += blockDim.x) {
+        const int i = k % top.m, j = k / top.m;
+        S.out[(size_t)j * S.P + i] = s[top.ou + k];
+    }
+}
+
 // ------------------------------------------------------------ norm finalise
 __device__ __forceinline__ void finalize_block(const double* partials, int ntiles, Ctrl* ctrl, double* out2,
                                                int mode, double* ss, double* sm) {
