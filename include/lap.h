@@ -136,8 +136,10 @@ lap_status lap_ctx_usage(lap_ctx* ctx, size_t* used, size_t* largest_free);
  * with fused prolongation, 2 residual + full weighting, 3 defect correction
  * (FP64), 4 coarse solve, 5 norm finalise, 6 ADI row lines, 7 ADI column
  * lines, 8 residual, 9 small-level subtree (one launch per sub-V-cycle; its
- * bytes are the top level's right-hand side read and result written).
- * `fine_only` selects the finest-level bucket.
+ * bytes are the top level's right-hand side read and result written),
+ * 10 fused pre-smoothing pass (one or two sweeps + residual + full
+ * weighting), 11 fused two-sweep pass (post-smoothing, with or without the
+ * prolongation).  `fine_only` selects the finest-level bucket.
  * lap_ctx_kernel_stats synchronises the stream. */
 lap_status lap_ctx_set_timing(lap_ctx* ctx, int32_t on);
 lap_status lap_ctx_kernel_stats(lap_ctx* ctx, int32_t kernel_class, int32_t fine_only,
@@ -170,9 +172,22 @@ lap_status lap_ctx_get_tiling(lap_ctx* ctx, int32_t kernel_class, int32_t dtype,
 lap_status lap_ctx_set_subtree(lap_ctx* ctx, int64_t max_nodes);
 lap_status lap_ctx_get_subtree(lap_ctx* ctx, int64_t* max_nodes, int32_t* lds_bytes);
 
+/* Fused smoothing passes (multigrid, section 2.3): with fusion on (the
+ * default) a level's pre-smoothing runs as passes of up to two red-black
+ * sweeps, the last of which also forms the residual of its result and
+ * full-weights it onto the coarse right-hand side, and the post-smoothing as
+ * passes of up to two sweeps, the first of which adds the bilinear
+ * correction; each pass reads and writes the level once.  The fields are
+ * bitwise those of one launch per sweep (fusion off).  A level holding the
+ * iterate keeps an even number of passes (one two-sweep pass is split when
+ * needed).  Changing the setting drops captured graphs and batch plans. */
+lap_status lap_ctx_set_fusion(lap_ctx* ctx, int32_t on);
+lap_status lap_ctx_get_fusion(lap_ctx* ctx, int32_t* on);
+
 /* Autotuner: time every candidate tiling (V in {1,2,4}; ty in {16,32,64,128};
  * auto with 1 or 2 device wave rounds) of the sweep, sweep+prolongation,
- * residual+restriction, residual and defect kernels on scratch buffers of an
+ * residual+restriction, residual, defect, fused pre-smoothing and fused
+ * two-sweep kernels on scratch buffers of an
  * m x n level (odd m, n >= 5; carved from the arena and released), keep the
  * fastest per kernel class and dtype for that size class, and write a JSON
  * report of the choices into `report` (host buffer of report_bytes, may be

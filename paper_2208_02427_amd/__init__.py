@@ -163,6 +163,16 @@ class Context:
         else the largest top level (m*n nodes) that may run as one launch."""
         _check(lib().lap_ctx_set_subtree(self.handle, int(max_nodes)))
 
+    def set_fusion(self, on=True):
+        """Fused smoothing passes (two sweeps per pass, restriction and
+        prolongation folded in); off = one launch per sweep."""
+        _check(lib().lap_ctx_set_fusion(self.handle, 1 if on else 0))
+
+    def get_fusion(self):
+        v = ctypes.c_int32()
+        _check(lib().lap_ctx_get_fusion(self.handle, ctypes.byref(v)))
+        return bool(v.value)
+
     def get_subtree(self):
         v, b = ctypes.c_int64(), ctypes.c_int32()
         _check(lib().lap_ctx_get_subtree(self.handle, ctypes.byref(v), ctypes.byref(b)))

@@ -26,7 +26,7 @@ LAP_ALLOC_FP64, LAP_ALLOC_MIXED, LAP_ALLOC_ADI, LAP_ALLOC_ALL = 1, 2, 4, 7
 
 # kernel classes of lap_ctx_kernel_stats
 KC_SWEEP, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE, KC_ADI_ROWS, KC_ADI_COLS, \
-    KC_RESIDUAL, KC_SUBTREE = range(10)
+    KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO = range(12)
 
 
 class LapInfo(ctypes.Structure):
@@ -83,6 +83,8 @@ SIGNATURES = {
     "lap_ctx_set_tiling": (_S, [_P, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
     "lap_ctx_get_tiling": (_S, [_P, c_int32, c_int32, c_int32, _PS(c_int32), _PS(c_int32), _PS(c_int32)]),
     "lap_ctx_set_subtree": (_S, [_P, c_int64]),
+    "lap_ctx_set_fusion": (_S, [_P, c_int32]),
+    "lap_ctx_get_fusion": (_S, [_P, _PS(c_int32)]),
     "lap_ctx_get_subtree": (_S, [_P, _PS(c_int64), _PS(c_int32)]),
     "lap_autotune": (_S, [_P, c_int32, c_int32, c_int32, c_char_p, c_size_t]),
     "lap_op_stream_copy": (_S, [_P, _P, c_size_t, c_int32, _P]),

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblap.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["stencil_kernels.hip", "adi_kernels.hip", "batch_kernels.hip", "runtime.hip"]
+SOURCES = ["stencil_kernels.hip", "fused_kernels.hip", "batch_fused.hip", "adi_kernels.hip", "batch_kernels.hip",
+           "runtime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,94 @@
+// Merged fused passes of the ragged batch path: the tile lists of all grids
+// concatenated, a persistent grid of workgroups walking them (see
+// batch_kernels.hip), each tile running the same fused_tile as the
+// single-grid kernel with its grid's arguments, tiling and halo.
+#include "fused_tiles.hpp"
+
+namespace lap {
+
+__device__ __forceinline__ int find_fused_item(const BatchItem* it, int count, int t) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (it[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int FLS>
+__device__ __forceinline__ void batch_fused_tile(const BatchItem& it, int lt, int lane) {
+    SweepArgs<T> A{};
+    A.uin = (const T*)it.in;
+    A.uout = (T*)it.out;
+    A.f = (const T*)it.f;
+    A.ec = (const T*)it.ec;
+    A.bc = (T*)it.bc;
+    A.partials = it.partials;
+    A.ctrl = nullptr;
+    A.m = it.m;
+    A.n = it.n;
+    A.P = it.P;
+    A.mc = it.mc;
+    A.nc = it.nc;
+    A.Pc = it.Pc;
+    A.cx = (T)it.cx;
+    A.cy = (T)it.cy;
+    A.d = (T)it.d;
+    A.inv_d = (T)it.inv_d;
+    A.omega = (T)it.omega;
+    A.tl.V = it.V;
+    A.tl.ty = it.ty;
+    A.tl.nwin = it.nwin;
+    A.tl.nchunk = it.nchunk;
+    A.tl.ntiles = it.ntiles;
+    A.tl.H = it.H;
+    const bool hf = (it.flags & SW_F) != 0;
+    switch (it.V) {
+        case 1: hf ? fused_tile<T, 1, FLS | SW_F>(A, lt, lane) : fused_tile<T, 1, FLS>(A, lt, lane); break;
+        case 2: hf ? fused_tile<T, 2, FLS | SW_F>(A, lt, lane) : fused_tile<T, 2, FLS>(A, lt, lane); break;
+        default: hf ? fused_tile<T, 4, FLS | SW_F>(A, lt, lane) : fused_tile<T, 4, FLS>(A, lt, lane); break;
+    }
+}
+
+template <typename T, int FLS>
+__global__ __launch_bounds__(kBlock) void k_batch_fused(const BatchItem* items, int count, int total) {
+    const int nw = gridDim.x * kWavesPerBlock;
+    const int lane = threadIdx.x & 63;
+    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6); t < total; t += nw) {
+        const BatchItem& it = items[find_fused_item(items, count, t)];
+        if (it.ctrl->done) continue;
+        batch_fused_tile<T, FLS>(it, t - it.tile0, lane);
+    }
+}
+
+// step flags without SW_F (the right-hand side is a per-grid runtime choice)
+#define LAP_BATCH_FUSED_FLAGS(X)                                                           \
+    X(SW_TWO) X(SW_TWO | SW_ZERO) X(SW_TWO | SW_NORM) X(SW_TWO | SW_PROLONG) X(SW_RESTRICT) \
+    X(SW_RESTRICT | SW_ZERO) X(SW_RESTRICT | SW_NORM) X(SW_RESTRICT | SW_TWO)              \
+    X(SW_RESTRICT | SW_TWO | SW_ZERO) X(SW_RESTRICT | SW_TWO | SW_NORM)
+
+template <typename T>
+static hipError_t launch_batch_fused_t(int fl, const BatchItem* items, int count, int total, int blocks,
+                                       hipStream_t s) {
+    const dim3 g(blocks), b(kBlock);
+    switch (fl) {
+#define LAP_CASE(F)                                                    \
+    case (F):                                                          \
+        k_batch_fused<T, (F)><<<g, b, 0, s>>>(items, count, total);    \
+        break;
+        LAP_BATCH_FUSED_FLAGS(LAP_CASE)
+#undef LAP_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fused(int dt, int step_flags, const BatchItem* items, int count, int total, int blocks,
+                              hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (blocks < 1) blocks = 1;
+    return dt == 0 ? launch_batch_fused_t<double>(step_flags, items, count, total, blocks, s)
+                   : launch_batch_fused_t<float>(step_flags, items, count, total, blocks, s);
+}
+
+}  // namespace lap

@@ -26,6 +26,7 @@ __device__ __forceinline__ Tiling item_tiling(const BatchItem& it) {
     t.nwin = it.nwin;
     t.nchunk = it.nchunk;
     t.ntiles = it.ntiles;
+    t.H = it.H;
     return t;
 }
 

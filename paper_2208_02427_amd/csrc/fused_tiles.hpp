@@ -1,0 +1,226 @@
+// Fused streaming passes: several operations of a V-cycle level in one read
+// of the level.  A wavefront walks its window down the rows once; the loaded
+// rows go through a pipeline of red-black sweep stages held in registers
+// (each stage lags the previous one by two rows), and the rows leaving the
+// last stage are stored and, optionally, turned into residual rows that are
+// full-weighted onto the coarse right-hand side.  Per node every stage
+// evaluates exactly the expressions of the one-sweep kernel on the same
+// operands, so a fused pass is bitwise the sequence of separate launches.
+//
+// Valid columns shrink by two per sweep and by two more for residual + full
+// weighting, so windows overlap by the tiling's halo H on each side
+// (H = 2 * sweeps, + 2 with the restriction); valid rows shrink the same
+// way, so a chunk reads 2 * sweeps (+ 1 or 2) rows beyond its own above and
+// below.
+#pragma once
+
+#include "stencil_tiles.hpp"
+
+namespace lap {
+
+// One sweep stage: rows j-2 (final), j-1 (colour 0 done), j (input) and the
+// right-hand side of rows j-1, j.
+template <typename T, int V>
+struct RBStage {
+    T a[V], b[V], c[V];
+    T fb[V], fc[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void stage_zero(RBStage<T, V>& S) {
+    zero<T, V>(S.a);
+    zero<T, V>(S.b);
+    zero<T, V>(S.c);
+    zero<T, V>(S.fb);
+    zero<T, V>(S.fc);
+}
+
+// Push input row j+1 (d, fd) into a stage positioned at row j: colour 0 on
+// row j (its colour-1 neighbours still hold input values), then colour 1 on
+// row j-1 (its colour-0 neighbours are new).  Row j-1 is then final for this
+// sweep and is handed on in (out, fout); the stage moves to row j+1.
+template <typename T, int V, int JP>
+__device__ __forceinline__ void rb_push(RBStage<T, V>& S, const T (&d)[V], const T (&fd)[V], T (&out)[V],
+                                        T (&fout)[V], int j, int n, const Cols<V>& c, int ipar, T cx, T cy, T inv_d,
+                                        T om) {
+    const T cW = __shfl_up(S.c[V - 1], 1);
+    const T cE = __shfl_down(S.c[0], 1);
+    if (j >= 1 && j <= n - 2) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
+            if (!upd || !c.cint[e]) continue;
+            const T W = e > 0 ? S.c[e - 1] : cW;
+            const T E = e < V - 1 ? S.c[e + 1] : cE;
+            const T t = (fma(cy, S.b[e] + d[e], cx * (W + E)) - S.fc[e]) * inv_d;
+            S.c[e] = fma(om, t - S.c[e], S.c[e]);
+        }
+    }
+    const T bW = __shfl_up(S.b[V - 1], 1);
+    const T bE = __shfl_down(S.b[0], 1);
+    if (j - 1 >= 1 && j - 1 <= n - 2) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
+            if (!upd || !c.cint[e]) continue;
+            const T W = e > 0 ? S.b[e - 1] : bW;
+            const T E = e < V - 1 ? S.b[e + 1] : bE;
+            const T t = (fma(cy, S.a[e] + S.c[e], cx * (W + E)) - S.fb[e]) * inv_d;
+            S.b[e] = fma(om, t - S.b[e], S.b[e]);
+        }
+    }
+    copy<T, V>(out, S.b);
+    copy<T, V>(fout, S.fb);
+    copy<T, V>(S.a, S.b);
+    copy<T, V>(S.b, S.c);
+    copy<T, V>(S.c, d);
+    copy<T, V>(S.fb, S.fc);
+    copy<T, V>(S.fc, fd);
+}
+
+template <typename T, int V, int NS, bool RS>
+struct FusedRegs {
+    RBStage<T, V> st[NS];
+    T dn[V], fdn[V], dnn[V], fdnn[V];   // prefetched input rows j+2, j+3
+    T bo[V];                            // input row j-1 (norm of the input)
+    T ru0[V], ru1[V], rf1[V];           // final rows q-2, q-1 and f of row q-1
+    T r2[V], r1[V];                     // residual rows q-3, q-2
+    double s2, mx;
+    Prolong<T, V> pr;
+};
+
+// One step: input row j+1 enters, the last stage emits final row
+// q = j + 1 - 2 * NS.
+template <typename T, int V, int FL, int NS, bool RS, int JP>
+__device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS>& R, const Cols<V>& c,
+                                           int j, int j0, int j1, int Lend, int ipar) {
+    T d[V], fd[V];
+    copy<T, V>(d, R.dn);
+    copy<T, V>(fd, R.fdn);
+    copy<T, V>(R.dn, R.dnn);
+    copy<T, V>(R.fdn, R.fdnn);
+    if (j + 3 <= Lend) {
+        sweep_load<T, V, FL>(R.dnn, A, j + 3, c, R.pr);
+        sweep_loadf<T, V, FL>(R.fdnn, A, j + 3, c);
+    }
+    const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
+
+    if constexpr (FL & SW_NORM) {
+        // residual of the input at row j (rows j-1, j, j+1 are input values)
+        const T cW = __shfl_up(R.st[0].c[V - 1], 1);
+        const T cE = __shfl_down(R.st[0].c[0], 1);
+        if (j >= j0 && j <= j1) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                if (!c.cout[e]) continue;
+                const T W = e > 0 ? R.st[0].c[e - 1] : cW;
+                const T E = e < V - 1 ? R.st[0].c[e + 1] : cE;
+                const T L = fma(-A.d, R.st[0].c[e], fma(cy, R.bo[e] + d[e], cx * (W + E)));
+                const double r = (double)(R.st[0].fc[e] - L);
+                R.s2 = fma(r, r, R.s2);
+                R.mx = fmax(R.mx, fabs(r));
+            }
+        }
+        copy<T, V>(R.bo, R.st[0].c);
+    }
+
+    T o[V], fo[V];
+    rb_push<T, V, JP>(R.st[0], d, fd, o, fo, j, A.n, c, ipar, cx, cy, inv_d, om);
+    if constexpr (NS == 2) {
+        T o2[V], fo2[V];
+        rb_push<T, V, JP>(R.st[1], o, fo, o2, fo2, j - 2, A.n, c, ipar, cx, cy, inv_d, om);
+        copy<T, V>(o, o2);
+        copy<T, V>(fo, fo2);
+    }
+    const int q = j + 1 - 2 * NS;
+    if (q >= j0 && q <= j1) store_row<T, V>(A.uout, o, q, A.P, c);
+
+    if constexpr (RS) {
+        // residual of the result at row q-1, then full weighting at the even row q-2
+        T r0[V];
+        residual_row<T, V>(r0, R.ru0, R.ru1, o, R.rf1, (q - 1 >= 1) && (q - 1 <= A.n - 2), c, cx, cy, A.d);
+        // q - 2 is even exactly on steps with j odd
+        if (JP == 1 && q - 2 >= j0 && q - 2 <= j1) {
+            const int J = (q - 2) >> 1;
+            const T w2 = __shfl_up(R.r2[V - 1], 1), w1 = __shfl_up(R.r1[V - 1], 1), w0 = __shfl_up(r0[V - 1], 1);
+            const T e2 = __shfl_down(R.r2[0], 1), e1 = __shfl_down(R.r1[0], 1), e0 = __shfl_down(r0[0], 1);
+            if (J >= 1 && J <= A.nc - 2) {
+                T* brow = A.bc + (size_t)J * A.Pc;
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int i = c.i0 + e;
+                    if ((i & 1) || !c.cout[e]) continue;
+                    const int I = i >> 1;
+                    if (I < 1 || I > A.mc - 2) continue;
+                    const T C = R.r1[e];
+                    const T W = e > 0 ? R.r1[e - 1] : w1;
+                    const T E = e < V - 1 ? R.r1[e + 1] : e1;
+                    const T S = R.r2[e], N = r0[e];
+                    const T SW = e > 0 ? R.r2[e - 1] : w2;
+                    const T SE = e < V - 1 ? R.r2[e + 1] : e2;
+                    const T NW = e > 0 ? r0[e - 1] : w0;
+                    const T NE = e < V - 1 ? r0[e + 1] : e0;
+                    brow[I] = (fma(T(4), C, T(2) * ((W + E) + (S + N))) + ((SW + SE) + (NW + NE))) * T(0.0625);
+                }
+            }
+        }
+        copy<T, V>(R.r2, R.r1);
+        copy<T, V>(R.r1, r0);
+        copy<T, V>(R.ru0, R.ru1);
+        copy<T, V>(R.ru1, o);
+        copy<T, V>(R.rf1, fo);
+    }
+}
+
+template <typename T, int V, int FL>
+__device__ __forceinline__ void fused_tile(const SweepArgs<T>& A, int tile, int lane) {
+    constexpr int NS = (FL & SW_TWO) ? 2 : 1;
+    constexpr bool RS = (FL & SW_RESTRICT) != 0;
+    const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
+    const Cols<V> c(win, lane, A.m, A.P, A.tl.H);
+    const int j0 = 1 + chunk * A.tl.ty;   // odd
+    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
+    const int ipar = c.i0 & 1;
+    // input rows [L0, Lend]: the last stage is exact on [j0 - RS, j1 + 2 RS]
+    const int L0 = j0 - 2 * NS - (RS ? 1 : 0);
+    const int Lend = j1 + 2 * NS + (RS ? 2 : 0);
+
+    FusedRegs<T, V, NS, RS> R;
+    R.s2 = 0.0;
+    R.mx = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) stage_zero<T, V>(R.st[s]);
+    if constexpr (RS) {
+        zero<T, V>(R.ru0);
+        zero<T, V>(R.ru1);
+        zero<T, V>(R.rf1);
+        zero<T, V>(R.r2);
+        zero<T, V>(R.r1);
+    }
+    if constexpr (FL & SW_PROLONG) R.pr.init(A.ec, L0, A.nc, A.Pc, c.i0);
+    sweep_load<T, V, FL>(R.st[0].b, A, L0, c, R.pr);
+    sweep_load<T, V, FL>(R.st[0].c, A, L0 + 1, c, R.pr);
+    sweep_loadf<T, V, FL>(R.st[0].fc, A, L0 + 1, c);
+    sweep_load<T, V, FL>(R.dn, A, L0 + 2, c, R.pr);
+    sweep_loadf<T, V, FL>(R.fdn, A, L0 + 2, c);
+    sweep_load<T, V, FL>(R.dnn, A, L0 + 3, c, R.pr);
+    sweep_loadf<T, V, FL>(R.fdnn, A, L0 + 3, c);
+    if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.st[0].b);
+
+    // the first step's row L0 + 1 is even without restriction, odd with it
+    constexpr int JP0 = RS ? 1 : 0;
+    for (int j = L0 + 1; j <= Lend - 1; j += 2) {
+        fused_step<T, V, FL, NS, RS, JP0>(A, R, c, j, j0, j1, Lend, ipar);
+        if (j + 1 <= Lend - 1) fused_step<T, V, FL, NS, RS, 1 - JP0>(A, R, c, j + 1, j0, j1, Lend, ipar);
+    }
+    if constexpr (FL & SW_NORM) {
+        const double s = wave_sum(R.s2);
+        const double mx = wave_max(R.mx);
+        if (lane == 0) {
+            A.partials[2 * tile] = s;
+            A.partials[2 * tile + 1] = mx;
+        }
+    }
+}
+
+}  // namespace lap

@@ -25,10 +25,12 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kXcds = 8;          // MI355X: workgroups are dealt round-robin over 8 XCDs
 
-// Window geometry for V columns per lane: step between windows and the left
-// offset of window 0 (keeps every vector load V-aligned).
-__host__ __device__ constexpr int win_step(int V) { return 64 * V - 4; }
-__host__ __device__ constexpr int win_left(int V) { return V <= 2 ? 2 : V; }
+// Window geometry for V columns per lane and a halo of H columns on each
+// side (columns a window reads but does not own: 2 per red-black sweep fused
+// into one pass, 2 more for a fused residual + full weighting): step between
+// windows and the left offset of window 0 (keeps every vector load V-aligned).
+__host__ __device__ constexpr int win_step(int V, int H = 2) { return 64 * V - 2 * H; }
+__host__ __device__ constexpr int win_left(int V, int H = 2) { return (H + V - 1) / V * V; }
 
 struct Tiling {
     int V = 2;       // columns per lane
@@ -36,20 +38,26 @@ struct Tiling {
     int nwin = 0;    // windows across
     int nchunk = 0;  // chunks down
     int ntiles = 0;  // nwin * nchunk (one wavefront each)
+    int H = 2;       // halo columns per side
 };
+
+// Halo of the canonical norm tiling: wide enough for a fused pass of two
+// sweeps and a residual + full weighting.
+constexpr int kNormH = 6;
 
 // Tiling of an m x n level with V columns per lane.  ty > 0: chunks of ty
 // rows.  ty == 0: size the chunks so the launch has about `target` waves
 // (one full occupancy round of the device when target = its wave capacity),
 // which avoids a nearly empty last round.  Chunks are never shorter than 16
 // rows, which bounds the number of tiles (and norm partials) of a level.
-inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0) {
+inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0, int H = 2) {
     Tiling t;
     t.V = V;
-    const int S = win_step(V), H = win_left(V);
-    // outputs of window w: columns [w*S - H + 2, w*S - H + 64V - 2); need to reach m-2
+    t.H = H;
+    const int S = win_step(V, H), L = win_left(V, H);
+    // outputs of window w: columns [w*S - L + H, w*S - L + 64V - H); need to reach m-2
     int nw = 1;
-    while ((nw - 1) * S - H + 64 * V - 3 < m - 2) ++nw;
+    while ((nw - 1) * S - L + 64 * V - H - 1 < m - 2) ++nw;
     t.nwin = nw;
     const int rows = n - 2 > 0 ? n - 2 : 1;
     if (ty <= 0) {
@@ -70,7 +78,7 @@ inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0) {
 // pre-sweep with norms, residual norms, the FP64 defect correction): the
 // partial sums, and so the stopping decisions, then do not depend on the
 // tuning table or on whether the grid runs alone or inside a batch.
-inline Tiling norm_tiling(int m, int n) { return make_tiling(m, n, 1, 0, 16384); }
+inline Tiling norm_tiling(int m, int n) { return make_tiling(m, n, 1, 0, 16384, kNormH); }
 
 // Blocks of 4 waves; the grid is padded to a multiple of the XCD count so
 // the XCD-aware remap below is a bijection.
@@ -102,6 +110,8 @@ enum : int {
     SW_ZERO = 2,     // input is identically zero (u_in ignored)
     SW_PROLONG = 4,  // input is u_in + P(ec)
     SW_NORM = 8,     // accumulate residual norms of the input into partials
+    SW_RESTRICT = 16,// fused pass: residual + full weighting of the result into bc
+    SW_TWO = 32,     // fused pass: two sweeps
 };
 
 template <typename T>
@@ -110,6 +120,7 @@ struct SweepArgs {
     T* uout;
     const T* f;
     const T* ec;        // coarse correction (SW_PROLONG)
+    T* bc;              // coarse right-hand side (SW_RESTRICT)
     double* partials;   // 2 doubles per tile (SW_NORM)
     const Ctrl* ctrl;   // nullable: kernel returns at once if ctrl->done
     int m, n, P;
@@ -213,6 +224,9 @@ template <typename T> hipError_t launch_residual(const ResidualArgs<T>& a, hipSt
 template <typename T> hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s);
 hipError_t launch_defect(const DefectArgs& a, hipStream_t s);
 template <typename T> hipError_t launch_subtree(const SubtreeArgs<T>& a, hipStream_t s);
+// fused streaming pass (fused_kernels.hip): one or two sweeps (SW_TWO), input
+// zero / + prolongation / with norms, result optionally restricted (SW_RESTRICT)
+template <typename T> hipError_t launch_fused(const SweepArgs<T>& a, int flags, hipStream_t s);
 // merged subtree launch: one workgroup per item, items[k].sub -> SubtreeArgs<T> in device memory
 hipError_t launch_batch_subtree(int dt, const struct BatchItem* items, int count, int lds_bytes, hipStream_t s);
 // allow dynamic LDS up to `bytes` for the subtree kernels (once per device)
@@ -274,7 +288,7 @@ struct BatchItem {
     const double* piv;
     int m, n, P, mc, nc, Pc;
     double cx, cy, d, inv_d, omega, a_off;
-    int V, ty, nwin, nchunk;
+    int V, ty, nwin, nchunk, H;
     int ntiles, tile0;       // tiles (or line blocks) of this item; prefix offset in the launch
     int flags;               // SW_F for sweeps; ADI relaxation form
     int parity;              // ADI line parity
@@ -282,11 +296,14 @@ struct BatchItem {
 };
 
 enum BatchKind { BK_SWEEP = 0, BK_RESTRICT, BK_COARSE, BK_FINALIZE, BK_RESNORM, BK_DEFECT, BK_ADI_ROWS, BK_ADI_COLS,
-                 BK_SUBTREE };
+                 BK_SUBTREE, BK_FUSED };
 // Launch one merged operation over `count` items (device array) covering
 // `total` tiles with a persistent grid of `blocks` workgroups.
 hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items, int count, int total, int blocks,
                         hipStream_t s);
 hipError_t launch_batch_adi(int kind, const BatchItem* items, int count, int total, int blocks, hipStream_t s);
+// merged fused passes (fused_kernels.hip); step_flags without SW_F
+hipError_t launch_batch_fused(int dt, int step_flags, const BatchItem* items, int count, int total, int blocks,
+                              hipStream_t s);
 
 }  // namespace lap

@@ -252,7 +252,7 @@ size_t coarse_bytes(const LevelGeo& C) {
 enum Part { PART_ALL = 0, PART_HEAD = 1, PART_TAIL = 2 };
 
 enum KClass { KC_SWEEP = 0, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE,
-              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_COUNT };
+              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_COUNT };
 
 // Size classes for tilings, by interior node count.
 int size_class(size_t nint) {
@@ -289,6 +289,7 @@ struct lap_ctx {
     // largest top level (nodes m*n) a subtree may start at (0: never)
     int lds_max = 65536;
     int64_t sub_max_nodes = -1;     // -1: any level whose subtree fits in LDS
+    bool fuse = true;               // fused smoothing passes (two sweeps, + restriction, + prolongation)
     std::vector<lap_grid*> grids;
     std::map<std::string, std::vector<double>> inv_cache;
     Ctrl* pinned = nullptr;        // 4 host slots
@@ -343,9 +344,9 @@ struct lap_ctx {
         if (recs.size() > 8192) return flush_recs();
         return hipSuccess;
     }
-    Tiling tiling(int m, int n, int cls, int dt) const {
+    Tiling tiling(int m, int n, int cls, int dt, int H = 2) const {
         const int sc = size_class((size_t)(m - 2) * (size_t)(n - 2));
-        return make_tiling(m, n, tileV[sc][cls][dt], tileTY[sc][cls][dt], tileT[sc][cls][dt]);
+        return make_tiling(m, n, tileV[sc][cls][dt], tileTY[sc][cls][dt], tileT[sc][cls][dt], H);
     }
 };
 
@@ -405,8 +406,7 @@ struct Footprint {
 
 size_t max_tiles(int m, int n) {
     // the finest tiling any table entry may pick: V = 1, ty = 16
-    const Tiling t = make_tiling(m, n, 1, 16);
-    return (size_t)t.ntiles;
+    return (size_t)std::max(make_tiling(m, n, 1, 16).ntiles, make_tiling(m, n, 1, 16, 0, kNormH).ntiles);
 }
 
 // Mirrors the allocations of lap_grid_create_ex.
@@ -572,6 +572,31 @@ hipError_t enq_sweep(lap_grid* g, int l, const T* in, T* out, const T* f, const 
                          [&]() { return launch_sweep<T>(a, flags, g->ctx->stream); });
 }
 
+// Halo, kernel class and tiling of a fused pass with these flags.
+int fused_halo(int flags) { return ((flags & SW_TWO) ? 4 : 2) + ((flags & SW_RESTRICT) ? 2 : 0); }
+int fused_class(int flags) { return (flags & SW_RESTRICT) ? KC_PRE : KC_TWO; }
+bool is_fused(int flags) { return (flags & (SW_TWO | SW_RESTRICT)) != 0; }
+
+// Algorithmic bytes per interior node of a sweep or fused pass.
+double sweep_bytes_per_node(int flags, int sz) {
+    double per = (flags & SW_ZERO) ? 1.0 : 2.0;
+    if (flags & SW_F) per += 1.0;
+    if (flags & SW_PROLONG) per += 0.25;
+    if (flags & SW_RESTRICT) per += 0.25;
+    return per * sz;
+}
+
+template <typename T>
+hipError_t enq_fused(lap_grid* g, int l, const T* in, T* out, const T* f, const T* ec, T* bc, double omega,
+                     int flags) {
+    SweepArgs<T> a = sweep_args<T>(g, l, in, out, f, ec, omega, (flags & SW_NORM) != 0);
+    const LevelGeo& L = g->geo[l];
+    a.bc = bc;
+    if (!(flags & SW_NORM)) a.tl = g->ctx->tiling(L.m, L.n, fused_class(flags), dt_of<T>(), fused_halo(flags));
+    return g->ctx->timed(fused_class(flags), l == 0, sweep_bytes_per_node(flags, sizeof(T)) * nint(L),
+                         [&]() { return launch_fused<T>(a, flags, g->ctx->stream); });
+}
+
 hipError_t enq_finalize(lap_grid* g, int ntiles) {
     return g->ctx->timed(KC_FINALIZE, false, 16.0 * ntiles, [&]() {
         return launch_finalize(g->partials, ntiles, g->ctrl, nullptr, 0, g->ctx->stream);
@@ -699,7 +724,52 @@ void push_op(std::vector<Op>& ops, long key, int kind, int level, int flags, con
     ops.push_back(op);
 }
 
-int vcycle_result_index(const lap_opts& o);
+// Sweeps per pass of the pre- and post-smoothing of one level.  Without
+// fusion every sweep is a pass of its own; with fusion passes take up to two
+// sweeps (an odd pre-smoothing count puts the single sweep first, so the
+// restriction rides on a two-sweep pass; an odd post count puts it last).
+// A level that carries the iterate (not a zero start) must end in the buffer
+// it started in: if the number of passes is odd, the first two-sweep pass is
+// split (one exists, as nu1 + nu2 is even).
+struct PassPlan {
+    std::vector<int> pre, post;
+};
+
+PassPlan pass_plan(const lap_ctx* c, const lap_opts& o, bool keep_parity) {
+    PassPlan p;
+    if (!c->fuse) {
+        p.pre.assign(o.nu1, 1);
+        p.post.assign(o.nu2, 1);
+        return p;
+    }
+    int k = o.nu1;
+    if (k % 2) {
+        p.pre.push_back(1);
+        --k;
+    }
+    for (; k > 0; k -= 2) p.pre.push_back(2);
+    for (k = o.nu2; k >= 2; k -= 2) p.post.push_back(2);
+    if (k) p.post.push_back(1);
+    if (keep_parity && (p.pre.size() + p.post.size()) % 2) {
+        for (std::vector<int>* v : {&p.pre, &p.post}) {
+            auto it = std::find(v->begin(), v->end(), 2);
+            if (it != v->end()) {
+                *it = 1;
+                v->insert(it, 1);
+                break;
+            }
+        }
+    }
+    return p;
+}
+
+// Buffer (0/1) in which a zero-start V-cycle leaves its level result: the
+// first pre-smoothing pass writes buffer 0, every further pass flips.
+int vcycle_result_index(const lap_ctx* c, const lap_opts& o) {
+    const PassPlan p = pass_plan(c, o, false);
+    const int npre = (int)p.pre.size(), npost = (int)p.post.size();
+    return (npre >= 1 ? npre - 1 + npost : npost - 1) % 2;
+}
 
 // One V-cycle on level l of hierarchy H.  Level 0 either holds the iterate in
 // u0[0] (FP64 multigrid: the result returns to u0[0] since nu1+nu2 is even)
@@ -718,7 +788,7 @@ int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm
     if (zero_start && l == H.sub_root && l < L - 1) {
         // the whole sub-V-cycle in one launch; its result lands where the
         // multi-launch schedule would leave it
-        const int ri = vcycle_result_index(o);
+        const int ri = vcycle_result_index(g->ctx, o);
         push_op<T>(ops, KEY_COARSE, OP_SUBTREE, l, o.nu1 | (o.nu2 << 8), nullptr, U[ri], b, nullptr, nullptr,
                    o.omega);
         return ri;
@@ -742,16 +812,25 @@ int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm
         }
         if (!tail) return 0;
     }
-    for (int k = 0; k < o.nu1; ++k) {
+    const PassPlan pp = pass_plan(g->ctx, o, !zero_start);
+    const int npre = (int)pp.pre.size(), npost = (int)pp.post.size();
+    const bool fused_restrict = g->ctx->fuse && npre > 0;
+    for (int k = 0; k < npre; ++k) {
+        int fl = fb | (pp.pre[k] == 2 ? SW_TWO : 0);
+        void* bc = nullptr;
+        if (fused_restrict && k == npre - 1) {
+            fl |= SW_RESTRICT;
+            bc = H.b[l + 1];
+        }
         if (!have_u) {
-            push_op<T>(ops, key_pre(l, k), OP_SWEEP, l, SW_ZERO | fb, nullptr, U[0], b, nullptr, nullptr, o.omega);
+            push_op<T>(ops, key_pre(l, k), OP_SWEEP, l, SW_ZERO | fl, nullptr, U[0], b, nullptr, bc, o.omega);
             cur = 0;
             have_u = true;
         } else {
             const bool nk = split && k == 0;
             if (!nk || head) {
-                push_op<T>(ops, key_pre(l, k), OP_SWEEP, l, fb | (nk ? SW_NORM : 0), U[cur], U[1 - cur], b, nullptr,
-                           nullptr, o.omega);
+                push_op<T>(ops, key_pre(l, k), OP_SWEEP, l, fl | (nk ? SW_NORM : 0), U[cur], U[1 - cur], b, nullptr,
+                           bc, o.omega);
                 if (nk)
                     push_op<T>(ops, key_norm_fin(l), OP_FINALIZE, l, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
                                0.0);
@@ -760,18 +839,20 @@ int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm
             if (nk && !tail) return 0;
         }
     }
-    push_op<T>(ops, key_restrict(l), OP_RESTRICT, l, 0, have_u ? U[cur] : nullptr, nullptr, b, nullptr, H.b[l + 1],
-               0.0);
+    if (!fused_restrict)
+        push_op<T>(ops, key_restrict(l), OP_RESTRICT, l, 0, have_u ? U[cur] : nullptr, nullptr, b, nullptr, H.b[l + 1],
+                   0.0);
     const int cres = plan_vcycle<T>(g, H, l + 1, o, false, PART_ALL, ops);
     const T* ec = (cres == 0 ? H.u0[l + 1] : H.u1[l + 1]);
-    for (int k = 0; k < o.nu2; ++k) {
+    for (int k = 0; k < npost; ++k) {
+        const int fl = fb | (pp.post[k] == 2 ? SW_TWO : 0);
         if (k == 0) {
-            push_op<T>(ops, key_post(l, k), OP_SWEEP, l, SW_PROLONG | fb, have_u ? U[cur] : nullptr,
+            push_op<T>(ops, key_post(l, k), OP_SWEEP, l, SW_PROLONG | fl, have_u ? U[cur] : nullptr,
                        U[have_u ? 1 - cur : 0], b, ec, nullptr, o.omega);
             cur = have_u ? 1 - cur : 0;
             have_u = true;
         } else {
-            push_op<T>(ops, key_post(l, k), OP_SWEEP, l, fb, U[cur], U[1 - cur], b, nullptr, nullptr, o.omega);
+            push_op<T>(ops, key_post(l, k), OP_SWEEP, l, fl, U[cur], U[1 - cur], b, nullptr, nullptr, o.omega);
             cur = 1 - cur;
         }
     }
@@ -836,11 +917,6 @@ hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const 
 }
 
 // Buffer (0/1) in which a zero-start V-cycle leaves its level result.
-int vcycle_result_index(const lap_opts& o) {
-    const int pre = o.nu1 >= 1 ? o.nu1 : 0;   // first pre-sweep writes buffer 0, each further one flips
-    const int flips = (pre >= 1 ? pre - 1 + 1 : 0) + (o.nu2 - 1);
-    return flips % 2;
-}
 
 // One outer step of the mixed loop: defect correction (adds the previous
 // FP32 correction, forms the FP64 residual, tests it), then one FP32
@@ -912,6 +988,13 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
     const int l = op.level;
     switch (op.kind) {
         case OP_SWEEP:
+            if (is_fused(op.flags)) {
+                if (op.dt == 0)
+                    return enq_fused<double>(g, l, (const double*)op.in, (double*)op.out, (const double*)op.f,
+                                             (const double*)op.ec, (double*)op.bc, op.omega, op.flags);
+                return enq_fused<float>(g, l, (const float*)op.in, (float*)op.out, (const float*)op.f,
+                                        (const float*)op.ec, (float*)op.bc, op.omega, op.flags);
+            }
             if (op.dt == 0)
                 return enq_sweep<double>(g, l, (const double*)op.in, (double*)op.out, (const double*)op.f,
                                          (const double*)op.ec, op.omega, op.flags);
@@ -1068,7 +1151,7 @@ lap_status prepare(lap_grid* g, const lap_opts& o) {
     lap_status st = init_ctrl(g, o, step);
     if (st != LAP_OK) return st;
     g->step_idx = 0;
-    g->e_idx = vcycle_result_index(o);
+    g->e_idx = vcycle_result_index(g->ctx, o);
     if (o.method == LAP_ADI) {
         const Coef c = coef(g->dx, g->dy);
         const int mk = g->adi_maxk;
@@ -1818,9 +1901,9 @@ void invalidate_cached(lap_ctx* c) {
         }
 }
 
-int batch_kind(int op_kind) {
-    switch (op_kind) {
-        case OP_SWEEP: return BK_SWEEP;
+int batch_kind(const Op& op) {
+    switch (op.kind) {
+        case OP_SWEEP: return is_fused(op.flags) ? BK_FUSED : BK_SWEEP;
         case OP_RESTRICT: return BK_RESTRICT;
         case OP_COARSE: return BK_COARSE;
         case OP_FINALIZE: return BK_FINALIZE;
@@ -1867,8 +1950,12 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o) {
     Tiling t{};
     switch (op.kind) {
         case OP_SWEEP:
-            t = (op.flags & SW_NORM) ? norm_tiling(L.m, L.n)
-                                     : c->tiling(L.m, L.n, (op.flags & SW_PROLONG) ? KC_SWEEP_PROLONG : KC_SWEEP, op.dt);
+            if (op.flags & SW_NORM)
+                t = norm_tiling(L.m, L.n);
+            else if (is_fused(op.flags))
+                t = c->tiling(L.m, L.n, fused_class(op.flags), op.dt, fused_halo(op.flags));
+            else
+                t = c->tiling(L.m, L.n, (op.flags & SW_PROLONG) ? KC_SWEEP_PROLONG : KC_SWEEP, op.dt);
             break;
         case OP_RESTRICT: t = c->tiling(L.m, L.n, KC_RESTRICT, op.dt); break;
         case OP_RESNORM:
@@ -1900,6 +1987,7 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o) {
     it.nwin = t.nwin;
     it.nchunk = t.nchunk;
     it.ntiles = t.ntiles;
+    it.H = t.H;
     return it;
 }
 
@@ -1907,12 +1995,7 @@ double item_bytes(const Op& op, const BatchItem& it) {
     const double n = (double)(it.m - 2) * (double)(it.n - 2);
     const double sz = op.dt == 0 ? 8.0 : 4.0;
     switch (op.kind) {
-        case OP_SWEEP: {
-            double per = (op.flags & SW_ZERO) ? 1.0 : 2.0;
-            if (op.flags & SW_F) per += 1.0;
-            if (op.flags & SW_PROLONG) per += 0.25;
-            return per * sz * n;
-        }
+        case OP_SWEEP: return sweep_bytes_per_node(op.flags, (int)sz) * n;
         case OP_RESTRICT: return ((op.in ? 1.0 : 0.0) + (op.f ? 1.0 : 0.0) + 0.25) * sz * n;
         case OP_RESNORM: return (op.f ? 16.0 : 8.0) * n;
         case OP_DEFECT: return (8.0 + (op.ec ? 4.0 : 0.0) + (op.f ? 8.0 : 0.0) + 12.0) * n;
@@ -1925,7 +2008,9 @@ double item_bytes(const Op& op, const BatchItem& it) {
 
 int kclass_of(const Op& op) {
     switch (op.kind) {
-        case OP_SWEEP: return (op.flags & SW_PROLONG) ? KC_SWEEP_PROLONG : KC_SWEEP;
+        case OP_SWEEP:
+            if (is_fused(op.flags)) return fused_class(op.flags);
+            return (op.flags & SW_PROLONG) ? KC_SWEEP_PROLONG : KC_SWEEP;
         case OP_RESTRICT: return KC_RESTRICT;
         case OP_COARSE: return KC_COARSE;
         case OP_FINALIZE: return KC_FINALIZE;
@@ -1979,7 +2064,7 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
         for (auto& go : v) sub[std::make_tuple(go.second.kind, go.second.dt, go.second.flags & ~SW_F)].push_back(go);
         for (auto& skv : sub) {
             MergedLaunch L{};
-            L.kind = batch_kind(std::get<0>(skv.first));
+            L.kind = batch_kind(skv.second[0].second);
             L.dt = std::get<1>(skv.first);
             L.flags = std::get<2>(skv.first);
             L.off = p->items.size();
@@ -2058,6 +2143,8 @@ hipError_t run_plan_launches(lap_ctx* c, lap_ctx::Plan* p) {
     for (const MergedLaunch& L : p->launches)
         HIPERR(c->timed(L.cls, L.fine, L.bytes, [&]() {
             if (L.kind == BK_SUBTREE) return launch_batch_subtree(L.dt, p->dev + L.off, L.count, L.lds, c->stream);
+            if (L.kind == BK_FUSED)
+                return launch_batch_fused(L.dt, L.flags, p->dev + L.off, L.count, L.total, L.blocks, c->stream);
             return launch_batch(L.kind, L.dt, L.flags, p->dev + L.off, L.count, L.total, L.blocks, c->stream);
         }));
     return hipSuccess;
@@ -2293,6 +2380,19 @@ extern "C" lap_status lap_ctx_set_subtree(lap_ctx* c, int64_t max_nodes) {
     return LAP_OK;
 }
 
+extern "C" lap_status lap_ctx_set_fusion(lap_ctx* c, int32_t on) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    c->fuse = on != 0;
+    invalidate_cached(c);
+    return LAP_OK;
+}
+
+extern "C" lap_status lap_ctx_get_fusion(lap_ctx* c, int32_t* on) {
+    if (!c) return fail(LAP_EINVAL, "ctx is NULL");
+    if (on) *on = c->fuse ? 1 : 0;
+    return LAP_OK;
+}
+
 extern "C" lap_status lap_ctx_get_subtree(lap_ctx* c, int64_t* max_nodes, int32_t* lds_bytes) {
     if (!c) return fail(LAP_EINVAL, "ctx is NULL");
     if (max_nodes) *max_nodes = c->sub_max_nodes;
@@ -2337,6 +2437,18 @@ hipError_t tune_launch(lap_ctx* c, int cls, const Tiling& t, int m, int n, int P
         a.cx = (T)k.cx; a.cy = (T)k.cy; a.d = (T)k.d; a.inv_d = (T)k.inv_d; a.omega = (T)1.0;
         a.tl = t;
         return launch_sweep<T>(a, flags | (cls == KC_SWEEP_PROLONG ? SW_PROLONG : 0), c->stream);
+    }
+    if (cls == KC_PRE || cls == KC_TWO) {
+        SweepArgs<T> a{};
+        a.uin = (const T*)B.u[0];
+        a.uout = (T*)B.u[1];
+        a.f = (flags & SW_F) ? (const T*)B.f : nullptr;
+        a.ec = (const T*)B.ec;
+        a.bc = (T*)B.bc;
+        a.m = m; a.n = n; a.P = P; a.mc = mc; a.nc = nc; a.Pc = Pc;
+        a.cx = (T)k.cx; a.cy = (T)k.cy; a.d = (T)k.d; a.inv_d = (T)k.inv_d; a.omega = (T)1.0;
+        a.tl = t;
+        return launch_fused<T>(a, flags, c->stream);
     }
     if (cls == KC_RESTRICT) {
         RestrictArgs<T> a{};
@@ -2384,7 +2496,7 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
     B.bc = A(coarse);
     B.rhs32 = A(fine / 2);
     B.e32 = A(fine / 2);
-    B.partials = (double*)A((size_t)make_tiling(m, n, 1, 16).ntiles * 16);
+    B.partials = (double*)A(max_tiles(m, n) * 16);
     auto release = [&]() {
         hipStreamSynchronize(c->stream);
         for (void* p : held) c->arena.release(p);
@@ -2415,19 +2527,31 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
     std::string js = "{\"m\": " + std::to_string(m) + ", \"n\": " + std::to_string(n) + ", \"size_class\": " +
                      std::to_string(sc) + ", \"wave_cap\": " + std::to_string(c->wave_cap) + ", \"best\": [";
     const char* names[KC_COUNT] = {"sweep", "sweep_prolong", "restrict", "defect", "coarse", "finalize",
-                                   "adi_rows", "adi_cols", "residual"};
+                                   "adi_rows", "adi_cols", "residual", "subtree", "pre", "two"};
+    // the variant each class is timed on: pre-smoothing from zero with the
+    // restriction (coarse levels, FP32 level 0), post-smoothing with the
+    // prolongation (with and without a right-hand side, as the one-sweep kernel)
+    auto base_flags = [](int cls) {
+        if (cls == KC_PRE) return (int)(SW_RESTRICT | SW_TWO | SW_ZERO);
+        if (cls == KC_TWO) return (int)(SW_TWO | SW_PROLONG);
+        return 0;
+    };
     bool first = true;
     lap_status result = LAP_OK;
-    for (int cls : {(int)KC_SWEEP, (int)KC_SWEEP_PROLONG, (int)KC_RESTRICT, (int)KC_RESIDUAL, (int)KC_DEFECT}) {
+    for (int cls : {(int)KC_SWEEP, (int)KC_SWEEP_PROLONG, (int)KC_RESTRICT, (int)KC_RESIDUAL, (int)KC_DEFECT,
+                    (int)KC_PRE, (int)KC_TWO}) {
         for (int dt = 0; dt < 2; ++dt) {
             if (cls == KC_DEFECT && dt == 1) continue;
             double best = 1e30;
             Cand bc{2, 0, c->wave_cap};
             for (const Cand& cd : cands) {
-                const Tiling t = make_tiling(m, n, cd.V, cd.ty, cd.tgt);
+                const int H = (cls == KC_PRE || cls == KC_TWO) ? fused_halo(base_flags(cls)) : 2;
+                const Tiling t = make_tiling(m, n, cd.V, cd.ty, cd.tgt, H);
                 double total = 0.0;
-                for (int fl : {0, (int)SW_F}) {
-                    if (fl == 0 && cls != KC_SWEEP) continue;
+                for (int fl0 : {0, (int)SW_F}) {
+                    if (fl0 == 0 && cls != KC_SWEEP && cls != KC_TWO) continue;
+                    if (fl0 == 0 && cls == KC_PRE) continue;
+                    const int fl = fl0 | base_flags(cls);
                     auto go = [&]() {
                         return dt == 0 ? tune_launch<double>(c, cls, t, m, n, P, Pc, B, fl)
                                        : tune_launch<float>(c, cls, t, m, n, P, Pc, B, fl);

@@ -73,7 +73,7 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Per-lane column bookkeeping of one window.
+// Per-lane column bookkeeping of one window (halo H columns per side).
 template <int V>
 struct Cols {
     int ws, i0;
@@ -81,8 +81,8 @@ struct Cols {
     bool cint[V];             // interior column
     bool cout[V];             // interior and inside this window's output range
     bool all_out;
-    __device__ __forceinline__ Cols(int win, int lane, int m, int P) {
-        ws = win * win_step(V) - win_left(V);
+    __device__ __forceinline__ Cols(int win, int lane, int m, int P, int H) {
+        ws = win * win_step(V, H) - win_left(V, H);
         i0 = ws + lane * V;
         vin = (i0 >= 0) && (i0 + V <= P);
         all_out = true;
@@ -90,7 +90,7 @@ struct Cols {
         for (int e = 0; e < V; ++e) {
             const int i = i0 + e;
             cint[e] = (i >= 1) && (i <= m - 2);
-            cout[e] = cint[e] && (i >= ws + 2) && (i < ws + 64 * V - 2);
+            cout[e] = cint[e] && (i >= ws + H) && (i < ws + 64 * V - H);
             all_out = all_out && cout[e];
         }
     }
@@ -294,7 +294,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
 template <typename T, int V, int FL>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& A, int tile, int lane) {
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
-    const Cols<V> c(win, lane, A.m, A.P);
+    const Cols<V> c(win, lane, A.m, A.P, A.tl.H);
     const int j0 = 1 + chunk * A.tl.ty;          // odd
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
     const int ipar = c.i0 & 1;
@@ -346,7 +346,7 @@ __device__ __forceinline__ void residual_row(T (&r)[V], const T (&um)[V], const 
 template <typename T, int V>
 __device__ __forceinline__ void restrict_tile(const RestrictArgs<T>& A, int tile, int lane) {
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
-    const Cols<V> c(win, lane, A.m, A.P);
+    const Cols<V> c(win, lane, A.m, A.P, A.tl.H);
     const int j0 = 1 + chunk * A.tl.ty;
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
 
@@ -405,7 +405,7 @@ __device__ __forceinline__ void restrict_tile(const RestrictArgs<T>& A, int tile
 template <typename T, int V>
 __device__ __forceinline__ void residual_tile(const ResidualArgs<T>& A, int tile, int lane) {
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
-    const Cols<V> c(win, lane, A.m, A.P);
+    const Cols<V> c(win, lane, A.m, A.P, A.tl.H);
     const int j0 = 1 + chunk * A.tl.ty;
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
 
@@ -463,7 +463,7 @@ __device__ __forceinline__ void defect_load(double (&x)[V], const DefectArgs& A,
 template <int V>
 __device__ __forceinline__ void defect_tile(const DefectArgs& A, int tile, int lane) {
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
-    const Cols<V> c(win, lane, A.m, A.P);
+    const Cols<V> c(win, lane, A.m, A.P, A.tl.H);
     const int j0 = 1 + chunk * A.tl.ty;
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
 

@@ -1,0 +1,107 @@
+"""Fused smoothing passes (two sweeps per pass; residual + full weighting
+folded into the last pre-smoothing pass; bilinear correction into the first
+post-smoothing pass).  A fused pass evaluates every node with the one-sweep
+kernels' expressions on the same operands, so solutions are compared bit for
+bit with fusion switched off, across tilings and halos, alone and batched."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import need_gpu, say, to_dev, rand_problem
+from oracle import grid as ogrid
+
+pytestmark = pytest.mark.gpu
+
+KC_PRE, KC_TWO = 10, 11
+
+
+def _run(lap, torch, prob, fuse, sub=-1, tiling=None, **kw):
+    psi, f, dx, dy = prob
+    ctx = lap.Context(arena_bytes=256 << 20)
+    ctx.set_fusion(fuse)
+    ctx.set_subtree(sub)
+    if tiling is not None:
+        V, ty, tgt = tiling
+        for sc in range(4):
+            for cls in range(12):
+                for dt in (0, 1):
+                    ctx.set_tiling(cls, dt, sc, V, ty, tgt)
+    ctx.set_timing(True)
+    g = ctx.grid(to_dev(torch, psi), None if f is None else to_dev(torch, f), dx, dy)
+    info = g.solve("mg", **kw)
+    out = g.read().cpu().numpy()
+    fused = ctx.kernel_stats(KC_PRE)["launches"] + ctx.kernel_stats(KC_TWO)["launches"]
+    g.destroy()
+    ctx.close()
+    return info, out, fused
+
+
+CASES = [
+    # m, n, precision, nu1, nu2, source
+    (257, 257, "fp64", 2, 2, False),
+    (257, 257, "fp64", 2, 2, True),
+    (513, 129, "mixed", 2, 2, True),
+    (129, 257, "fp64", 1, 1, True),
+    (129, 129, "fp64", 3, 1, False),
+    (129, 129, "mixed", 1, 3, True),
+    (257, 129, "fp64", 0, 2, True),
+    (129, 129, "fp64", 4, 2, True),
+    (65, 33, "mixed", 2, 2, True),
+]
+
+
+@pytest.mark.parametrize("m,n,precision,nu1,nu2,source", CASES)
+def test_fused_bitwise_vs_unfused(m, n, precision, nu1, nu2, source):
+    torch, lap = need_gpu()
+    prob = rand_problem(m, n, seed=3 * m + n, dx=1.0 / (m - 1), dy=1.2 / (m - 1), source=source)
+    kw = dict(precision=precision, tol=1e-10, max_iter=40, nu1=nu1, nu2=nu2)
+    say("fused", m, n, precision, nu1, nu2, source)
+    sub = 0 if m * n < 65 * 65 else -1      # small grids: the whole FP32 cycle would be one subtree
+    off = _run(lap, torch, prob, False, sub=sub, **kw)
+    on = _run(lap, torch, prob, True, sub=sub, **kw)
+    assert off[2] == 0 and on[2] > 0
+    assert on[0]["status"] == 0 and on[0]["iterations"] == off[0]["iterations"]
+    assert np.array_equal(on[1], off[1])
+    psi, f, dx, dy = prob
+    r0 = ogrid.norm2(ogrid.residual(psi, f, dx, dy))
+    assert ogrid.norm2(ogrid.residual(on[1], f, dx, dy)) / r0 < 1e-10 * 1.0001
+
+
+@pytest.mark.parametrize("tiling", [(1, 16, 0), (2, 32, 0), (4, 16, 0), (2, 0, 256), (4, 0, 8192), (1, 0, 64)])
+def test_fused_bitwise_across_tilings(tiling):
+    """Many windows and chunks, ragged last window and chunk, no subtree
+    (every level through the streaming kernels)."""
+    torch, lap = need_gpu()
+    prob = rand_problem(449, 321, seed=17)
+    kw = dict(precision="fp64", tol=0.0, max_iter=3)
+    say("fused tiling", tiling)
+    ref = _run(lap, torch, prob, False, sub=0, **kw)
+    got = _run(lap, torch, prob, True, sub=0, tiling=tiling, **kw)
+    assert np.array_equal(got[1], ref[1])
+    kw["precision"] = "mixed"
+    ref = _run(lap, torch, prob, False, sub=0, **kw)
+    got = _run(lap, torch, prob, True, sub=0, tiling=tiling, **kw)
+    assert np.array_equal(got[1], ref[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_fused_bitwise(precision):
+    torch, lap = need_gpu()
+    probs = W.ragged_batch(count=10, lo=33, hi=513, seed=9, bumps=True)
+    kw = dict(method="mg", precision=precision, tol=1e-10, max_iter=60)
+    res = {}
+    for fuse in (False, True):
+        say("batch fused", precision, fuse)
+        ctx = lap.Context(arena_bytes=1 << 30)
+        ctx.set_fusion(fuse)
+        ctx.set_timing(True)
+        gs = [ctx.grid(to_dev(torch, p.psi0), None if p.f is None else to_dev(torch, p.f), p.dx, p.dy)
+              for p in probs]
+        infos = ctx.solve_batch(gs, **kw)
+        res[fuse] = ([g.read().cpu().numpy() for g in gs], [i["iterations"] for i in infos],
+                     ctx.kernel_stats(KC_PRE)["launches"])
+        ctx.close()
+    assert res[False][2] == 0 and res[True][2] > 0
+    assert res[False][1] == res[True][1]
+    for a, b in zip(res[False][0], res[True][0]):
+        assert np.array_equal(a, b)
