@@ -13,8 +13,9 @@ Also measured in the same run (reported beside the headline):
     inside FP64 defect correction vs FP64 multigrid, time to 1e-10 and speedup;
   * red-black SOR with w = 2/(1+sin(pi h)): sweeps/s and GLUP/s, and time to
     1e-10 on 4097 x 4097;
-  * the roofline of the dominant kernel (the FP64 red-black sweep on the
-    finest level) from HIP events around each of its launches;
+  * the roofline of the dominant kernel (the finest-level kernel class with
+    the most device time: the fused pre- or post-smoothing pass) from HIP
+    events around each of its launches;
   * the CPU oracle on the host cores (one V-cycle of the 4097 x 4097 solve).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N] [--no-cpu] [--quick]
@@ -37,11 +38,23 @@ import workloads as W  # noqa: E402
 
 METRIC = "GLUP/s + time to 1e-10 residual (FP32+FP64 refine vs FP64); p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the fine FP64 sweep (8193^2, f = 0) measured with
-# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by the counts of a 1 GiB
-# stream copy (profiles/sweep_fp64_8193_mg.md); valid for the tiling it was
-# taken with (V = 1, auto chunks for 16384 waves) and this kernel version.
-SWEEP_FINE_TRAFFIC = {(1, 0, 16384): 1.1096e9}
+# HBM bytes per launch of the finest-level kernels (8193^2, f = 0) measured
+# with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by the counts of a
+# 1 GiB stream copy (summaries under profiles/); keyed by kernel class and the
+# tiling (V, ty, target waves) they were taken with, for this kernel version.
+FINE_TRAFFIC = {}
+
+# kernel classes timed on the finest level (numbering of lap.h)
+FINE_CLASSES = {"sweep": 0, "sweep_prolong": 1, "restrict": 2, "pre": 10, "two": 11}
+FINE_LABELS = {
+    "sweep": "k_sweep<double,V,0>: one red-black sweep (finest level, f = 0)",
+    "sweep_prolong": "k_sweep<double,V,4>: bilinear correction + one red-black sweep",
+    "restrict": "k_restrict<double,V>: residual + full weighting",
+    "pre": "k_fused<double,2,56>: residual norms of the iterate + two red-black sweeps + residual + full "
+           "weighting (finest level, f = 0, canonical norm tiling)",
+    "two": "k_fused<double,V,36>: bilinear correction + two red-black sweeps (finest level, f = 0)",
+}
+ALL_CLASSES = range(12)
 
 
 def lup_per_cycle(levels, nu1=2, nu2=2):
@@ -110,9 +123,8 @@ def run_gpu(args):
     infos = [one_solve() for _ in range(args.steps)]
     sync()
     dt = time.perf_counter() - t0
-    sweep = ctx.kernel_stats(lap._native.KC_SWEEP, fine_only=True)
-    prol = ctx.kernel_stats(lap._native.KC_SWEEP_PROLONG, fine_only=True)
-    restr = ctx.kernel_stats(lap._native.KC_RESTRICT, fine_only=True)
+    fine = {k: ctx.kernel_stats(c, fine_only=True) for k, c in FINE_CLASSES.items()}
+    every = [ctx.kernel_stats(c) for c in ALL_CLASSES]
     ctx.set_timing(False)
     cycles = infos[-1]["iterations"]
     assert all(i["status"] == 0 for i in infos), infos
@@ -131,22 +143,31 @@ def run_gpu(args):
         out["time_to_tol_graph_s"] = time.perf_counter() - t0
     out["time_to_tol_s"] = out["ms_per_step"] / 1e3
 
-    # roofline of the dominant kernel: FP64 red-black sweep on the finest level
-    ach = sweep["alg_bytes"] / (sweep["device_ms"] / 1e3) / 1e9 if sweep["device_ms"] > 0 else 0.0
-    tiling = ctx.get_tiling(0, 0, lap.size_class(N, N))
+    # roofline of the dominant kernel: the finest-level kernel class with the
+    # most device time (HIP events around each launch on the library's stream)
+    dom = max(fine, key=lambda k: fine[k]["device_ms"])
+    st = fine[dom]
+    ach = st["alg_bytes"] / (st["device_ms"] / 1e3) / 1e9 if st["device_ms"] > 0 else 0.0
+    if dom == "pre":
+        tiling = (2, 0, 16384)          # the canonical norm tiling (the pass carries the stopping test)
+    else:
+        tiling = tuple(ctx.get_tiling(FINE_CLASSES[dom], 0, lap.size_class(N, N)))
     out["roofline"] = {
         "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(ach / HBM_PEAK_GBS, 4),
-        "traffic": SWEEP_FINE_TRAFFIC.get(tuple(tiling)) if N == 8193 else None,
+        "traffic": FINE_TRAFFIC.get((dom,) + tiling) if N == 8193 else None,
         "tiling": {"V": tiling[0], "ty": tiling[1], "target_waves": tiling[2]},
-        "kernel": "k_sweep<double,V,0> (fused two-colour red-black sweep, finest level, f = 0)",
-        "alg_bytes_per_launch": sweep["alg_bytes"] / max(1, sweep["launches"]),
-        "avg_launch_ms": sweep["device_ms"] / max(1, sweep["launches"]),
-        "launches": sweep["launches"],
+        "kernel": FINE_LABELS[dom],
+        "alg_bytes_per_launch": st["alg_bytes"] / max(1, st["launches"]),
+        "avg_launch_ms": st["device_ms"] / max(1, st["launches"]),
+        "launches": st["launches"],
     }
-    out["kernels_fine"] = {
-        "sweep": sweep, "sweep_prolong": prol, "restrict": restr,
-    }
+    out["kernels_fine"] = fine
+    # whole solve: algorithmic bytes of every launch over the step time
+    alg = sum(e["alg_bytes"] for e in every)
+    out["solve_hbm"] = {"alg_bytes_per_step": alg / args.steps,
+                        "GB/s_over_step_time": alg / dt / 1e9,
+                        "GB/s_over_device_time": alg / (sum(e["device_ms"] for e in every) / 1e3) / 1e9}
     # correctness of the timed result: oracle-side residual at sampled rows is
     # checked in the GPU tests; here record the library's own FP64 residual
     l2, linf = g.residual()
@@ -389,7 +410,8 @@ def main():
         "rel_res": out["rel_res"],
         "roofline": out["roofline"],
     }
-    for k in ("copy_probe", "mixed", "sor", "mg_4097", "ragged_batch", "serving", "kernels_fine", "autotune"):
+    for k in ("solve_hbm", "copy_probe", "mixed", "sor", "mg_4097", "ragged_batch", "serving", "kernels_fine",
+              "autotune"):
         if k in out:
             line[k] = out[k]
     if not args.no_cpu:

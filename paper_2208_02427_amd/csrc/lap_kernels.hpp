@@ -78,7 +78,14 @@ inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0, int H = 2
 // pre-sweep with norms, residual norms, the FP64 defect correction): the
 // partial sums, and so the stopping decisions, then do not depend on the
 // tuning table or on whether the grid runs alone or inside a batch.
-inline Tiling norm_tiling(int m, int n) { return make_tiling(m, n, 1, 0, 16384, kNormH); }
+// Two canonical tilings, by producer: the stencil passes (sweeps with
+// norms, fused pre-smoothing, residual norms) and the FP64 defect correction
+// of the mixed loop; a norm finalisation reduces the partials of the kind
+// that produced them.
+enum NormKind { NORM_PASS = 0, NORM_DEFECT = 1 };
+inline Tiling norm_tiling(int m, int n, int kind = NORM_PASS) {
+    return kind == NORM_DEFECT ? make_tiling(m, n, 1, 0, 16384, 2) : make_tiling(m, n, 2, 0, 16384, kNormH);
+}
 
 // Blocks of 4 waves; the grid is padded to a multiple of the XCD count so
 // the XCD-aware remap below is a bijection.

@@ -406,7 +406,9 @@ struct Footprint {
 
 size_t max_tiles(int m, int n) {
     // the finest tiling any table entry may pick: V = 1, ty = 16
-    return (size_t)std::max(make_tiling(m, n, 1, 16).ntiles, make_tiling(m, n, 1, 16, 0, kNormH).ntiles);
+    int t = make_tiling(m, n, 1, 16).ntiles;
+    for (int k : {(int)NORM_PASS, (int)NORM_DEFECT}) t = std::max(t, norm_tiling(m, n, k).ntiles);
+    return (size_t)t;
 }
 
 // Mirrors the allocations of lap_grid_create_ex.
@@ -911,7 +913,7 @@ hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const 
     a.cx = c.cx;
     a.cy = c.cy;
     a.d = c.d;
-    a.tl = norm_tiling(L.m, L.n);
+    a.tl = norm_tiling(L.m, L.n, NORM_DEFECT);
     const double per = 8.0 + (e ? 4.0 : 0.0) + (g->f64 ? 8.0 : 0.0) + 8.0 + 4.0;
     return g->ctx->timed(KC_DEFECT, true, per * nint(L), [&]() { return launch_defect(a, g->ctx->stream); });
 }
@@ -927,7 +929,8 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int
         const float* e = first ? nullptr : (e_idx == 0 ? g->l32[0].u[0] : g->l32[0].u[1]);
         push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, g->psi[in_idx], g->psi[1 - in_idx], g->f64, e,
                         g->l32[0].b, 0.0);
-        push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0);
+        push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr, nullptr,
+                        0.0);
     }
     if (part == PART_HEAD) return;
     HierView<float> H = view32(g);
@@ -1009,7 +1012,7 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
                 return enq_coarse<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.out);
             return enq_coarse<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.out);
         case OP_FINALIZE:
-            return enq_finalize(g, norm_tiling(g->geo[0].m, g->geo[0].n).ntiles);
+            return enq_finalize(g, norm_tiling(g->geo[0].m, g->geo[0].n, op.flags).ntiles);
         case OP_RESNORM:
             return enq_residual_norm<double>(g, l, (const double*)op.in, (const double*)op.f);
         case OP_DEFECT:
@@ -1958,9 +1961,9 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o) {
                 t = c->tiling(L.m, L.n, (op.flags & SW_PROLONG) ? KC_SWEEP_PROLONG : KC_SWEEP, op.dt);
             break;
         case OP_RESTRICT: t = c->tiling(L.m, L.n, KC_RESTRICT, op.dt); break;
-        case OP_RESNORM:
-        case OP_DEFECT:
-        case OP_FINALIZE: t = norm_tiling(g->geo[0].m, g->geo[0].n); break;
+        case OP_RESNORM: t = norm_tiling(g->geo[0].m, g->geo[0].n); break;
+        case OP_DEFECT: t = norm_tiling(g->geo[0].m, g->geo[0].n, NORM_DEFECT); break;
+        case OP_FINALIZE: t = norm_tiling(g->geo[0].m, g->geo[0].n, op.flags); break;
         case OP_ADI_ROWS:
         case OP_ADI_COLS: {
             const LineArgs la = adi_args(g, op.omega, op.flags, op.kind == OP_ADI_ROWS ? 0 : 1, op.parity);
