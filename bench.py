@@ -76,12 +76,22 @@ def run_gpu(args):
     arena = 12 << 30 if N > 4097 else 4 << 30
     ctx = lap.Context(arena_bytes=arena, device=dev)
     out = {}
-    # autotune the tilings of every size class the hierarchy visits (setup,
-    # untimed); without it the Context keeps the shipped MI355X table
+    # autotune the tilings of every level size the hierarchy visits down to
+    # the small-level subtree (setup, untimed); without it the Context keeps
+    # the shipped MI355X table
     tune = []
     if not args.no_tune:
-        for tn in (N, 2049, 257, 65):
+        sizes = [N]
+        while sizes[-1] > 65 and (sizes[-1] - 1) % 2 == 0:
+            sizes.append((sizes[-1] - 1) // 2 + 1)
+        for tn in sizes:
             tune.append(ctx.autotune(tn, tn, reps=3))
+        if args.tuning_out:
+            with open(args.tuning_out, "w") as fh:
+                json.dump({"device": "gfx950 (MI355X, 256 CUs)",
+                           "source": "lap_autotune on one MI355X, reps=3, sizes " + "/".join(map(str, sizes))
+                                     + " (python bench.py --tuning-out ...)",
+                           "reports": tune}, fh, indent=1)
     out["autotune"] = tune
 
     if args.copy_probe:
@@ -371,6 +381,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--no-tune", action="store_true", help="keep the shipped tiling table, no autotuning")
+    ap.add_argument("--tuning-out", default=None,
+                    help="write the autotune reports as a tiling table (the format of the shipped "
+                         "paper_2208_02427_amd/tuning_gfx950.json)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a plain 1 GiB device copy")
     ap.add_argument("--measure-only", action="store_true",
                     help="only measured-mode solves (for profiler runs: no graph replay leg)")

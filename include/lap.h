@@ -147,11 +147,14 @@ lap_status lap_ctx_kernel_stats(lap_ctx* ctx, int32_t kernel_class, int32_t fine
 lap_status lap_ctx_reset_stats(lap_ctx* ctx);
 
 /* Tilings of the stencil kernels.  Each kernel class (as numbered above) has,
- * per dtype (0 FP64, 1 FP32) and per size class of the level (0: fewer than
- * 2^14 interior nodes, 1: < 2^18, 2: < 2^22, 3: larger; lap_size_class), a
- * tiling: V columns per lane (1, 2 or 4) and chunks of ty rows (even, >= 16),
- * or ty = 0 for chunks sized so a launch has about target_waves wavefronts.
- * Every tiling produces bitwise identical fields; only speed differs. */
+ * per dtype (0 FP64, 1 FP32) and per size class of the level (k = 0..7: the
+ * level has fewer than 2^(12+2k) interior nodes, 7: 2^24 or more, so every
+ * level of a (2^j + 1)-sided hierarchy has a class of its own;
+ * lap_size_class), a tiling: V columns per lane (1, 2 or 4) and chunks of ty
+ * rows (even, >= 2), or ty = 0 for chunks (of at least 16 rows) sized so a
+ * launch has about target_waves wavefronts.  The tilings that produce norm
+ * partials are fixed and not in this table.  Every tiling produces bitwise
+ * identical fields; only speed differs. */
 int32_t lap_size_class(int32_t m, int32_t n);
 lap_status lap_ctx_set_tiling(lap_ctx* ctx, int32_t kernel_class, int32_t dtype, int32_t size_class,
                               int32_t V, int32_t ty, int32_t target_waves);

@@ -144,7 +144,8 @@ class Context:
 
     def apply_tuning(self, report: dict):
         """Re-apply the choices of an autotune report (e.g. loaded from JSON)."""
-        sc = int(report["size_class"])
+        # the class follows from the tuned size (tables written with other class bounds stay valid)
+        sc = size_class(int(report["m"]), int(report["n"])) if "m" in report else int(report["size_class"])
         for e in report["best"]:
             self.set_tiling(e["class"], 0 if e["dtype"] == "f64" else 1, sc, e["V"], e["ty"], e["target_waves"])
 

@@ -255,11 +255,14 @@ enum KClass { KC_SWEEP = 0, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE,
               KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_COUNT };
 
 // Size classes for tilings, by interior node count.
+// One class per factor 4 of interior nodes from 2^12 to 2^24, so each level
+// of a power-of-two hierarchy (65, 129, ..., 8193 nodes a side) has a class
+// of its own: 0 below 2^12, k below 2^(12 + 2k), 7 from 2^24 up.
+constexpr int kSizeClasses = 8;
 int size_class(size_t nint) {
-    if (nint < (1u << 14)) return 0;
-    if (nint < (1u << 18)) return 1;
-    if (nint < (1u << 22)) return 2;
-    return 3;
+    int k = 0;
+    while (k < kSizeClasses - 1 && nint >= ((size_t)1 << (12 + 2 * k))) ++k;
+    return k;
 }
 
 }  // namespace
@@ -281,9 +284,9 @@ struct lap_ctx {
     double ms[KC_COUNT][2] = {};
     double bytes[KC_COUNT][2] = {};
     // tiling table: [size class][kernel class][dtype 0=f64,1=f32] -> (V, ty)
-    int tileV[4][KC_COUNT][2];
-    int tileTY[4][KC_COUNT][2];     // 0: auto (chunks sized for tileT waves)
-    int tileT[4][KC_COUNT][2];
+    int tileV[kSizeClasses][KC_COUNT][2];
+    int tileTY[kSizeClasses][KC_COUNT][2];     // 0: auto (chunks sized for tileT waves)
+    int tileT[kSizeClasses][KC_COUNT][2];
     int wave_cap = 8192;            // CUs x 32 wavefronts (read from the device)
     // small-level subtree: LDS the device grants one workgroup, and the
     // largest top level (nodes m*n) a subtree may start at (0: never)
@@ -1300,7 +1303,7 @@ lap_status solve_one(lap_grid* g, const lap_opts& o, lap_info* info) {
 }
 
 void default_tilings(lap_ctx* c) {
-    for (int sc = 0; sc < 4; ++sc)
+    for (int sc = 0; sc < kSizeClasses; ++sc)
         for (int k = 0; k < KC_COUNT; ++k) {
             c->tileV[sc][k][0] = 2;
             c->tileTY[sc][k][0] = 0;
@@ -2357,7 +2360,7 @@ static lap_status tiling_args_ok(lap_ctx* c, int32_t cls, int32_t dtype, int32_t
     if (!c) return fail(LAP_EINVAL, "ctx is NULL");
     if (cls < 0 || cls >= KC_COUNT) return fail(LAP_EINVAL, "unknown kernel class");
     if (dtype != 0 && dtype != 1) return fail(LAP_EINVAL, "dtype must be 0 or 1");
-    if (sc < 0 || sc > 3) return fail(LAP_EINVAL, "size class must be 0..3");
+    if (sc < 0 || sc >= kSizeClasses) return fail(LAP_EINVAL, "size class must be 0..7");
     return LAP_OK;
 }
 
@@ -2366,7 +2369,7 @@ extern "C" lap_status lap_ctx_set_tiling(lap_ctx* c, int32_t cls, int32_t dtype,
     lap_status st = tiling_args_ok(c, cls, dtype, sc);
     if (st != LAP_OK) return st;
     if (V != 1 && V != 2 && V != 4) return fail(LAP_EINVAL, "V must be 1, 2 or 4");
-    if (ty != 0 && (ty < 16 || ty % 2)) return fail(LAP_EINVAL, "ty must be 0 (auto) or an even number >= 16");
+    if (ty != 0 && (ty < 2 || ty % 2)) return fail(LAP_EINVAL, "ty must be 0 (auto) or an even number >= 2");
     if (ty == 0 && target < 64) return fail(LAP_EINVAL, "auto tiling needs target_waves >= 64");
     c->tileV[sc][cls][dtype] = V;
     c->tileTY[sc][cls][dtype] = ty;
@@ -2523,7 +2526,7 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
     struct Cand { int V, ty, tgt; };
     std::vector<Cand> cands;
     for (int V : {1, 2, 4}) {
-        for (int ty : {16, 32, 64, 128}) cands.push_back({V, ty, 0});
+        for (int ty : {2, 4, 8, 16, 32, 64, 128}) cands.push_back({V, ty, 0});
         cands.push_back({V, 0, c->wave_cap});
         cands.push_back({V, 0, 2 * c->wave_cap});
     }

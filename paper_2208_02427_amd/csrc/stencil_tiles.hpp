@@ -120,33 +120,43 @@ __device__ __forceinline__ void store_row(T* base, const T (&x)[V], int j, int P
 // A lane owning fine columns i0..i0+V-1 needs coarse columns I0 = i0>>1 ..
 // I0 + V2 (V2 = max(1, V/2)); it loads I0..I0+V2-1 with one vector load per
 // coarse row and takes column I0+V2 from the next lane.  The two coarse rows
-// J, J+1 around the current fine row stay in registers: fine rows arrive in
-// increasing order, so each coarse row is loaded once per wave.
+// J, J+1 around the current fine row stay in registers, and row J+2 is
+// already in flight (its raw load is completed with the neighbour's column
+// only when it moves up), so the stream of fine rows never waits on a coarse
+// load: fine rows arrive in increasing order and each coarse row is loaded
+// once per wave, two fine rows before it is used.
 template <typename T, int V>
 struct Prolong {
     static constexpr int V2 = V >= 2 ? V / 2 : 1;
     T lo[V2 + 1], hi[V2 + 1];   // coarse rows Jcur, Jcur+1 (entry V2 from the next lane)
+    T nraw[V2], nlast;          // coarse row Jcur+2 as loaded (nlast: lane 63's column I0+V2)
     int Jcur;
-    __device__ __forceinline__ void load_coarse(T (&x)[V2 + 1], const T* ec, int J, int nc, int Pc, int I0) {
-        T v[V2];
+    __device__ __forceinline__ void issue(const T* ec, int J, int nc, int Pc, int I0) {
         if (J >= 0 && J < nc && I0 >= 0 && I0 + V2 <= Pc)
-            ldv<T, V2>(v, ec + (size_t)J * Pc + I0);
+            ldv<T, V2>(nraw, ec + (size_t)J * Pc + I0);
         else
-            zero<T, V2>(v);
-#pragma unroll
-        for (int q = 0; q < V2; ++q) x[q] = v[q];
-        x[V2] = __shfl_down(v[0], 1);
+            zero<T, V2>(nraw);
         // the last lane has no right neighbour, but its halo columns still need
         // coarse column I0 + V2 (the sweep reads the window's last column)
+        nlast = T(0);
         if ((threadIdx.x & 63) == 63) {
             const int I = I0 + V2;
-            x[V2] = (J >= 0 && J < nc && I >= 0 && I < Pc) ? ec[(size_t)J * Pc + I] : T(0);
+            if (J >= 0 && J < nc && I >= 0 && I < Pc) nlast = ec[(size_t)J * Pc + I];
         }
+    }
+    __device__ __forceinline__ void complete(T (&x)[V2 + 1]) {
+#pragma unroll
+        for (int q = 0; q < V2; ++q) x[q] = nraw[q];
+        const T r = __shfl_down(nraw[0], 1);
+        x[V2] = (threadIdx.x & 63) == 63 ? nlast : r;
     }
     __device__ __forceinline__ void init(const T* ec, int j, int nc, int Pc, int i0) {
         Jcur = j >> 1;
-        load_coarse(lo, ec, Jcur, nc, Pc, i0 >> 1);
-        load_coarse(hi, ec, Jcur + 1, nc, Pc, i0 >> 1);
+        issue(ec, Jcur, nc, Pc, i0 >> 1);
+        complete(lo);
+        issue(ec, Jcur + 1, nc, Pc, i0 >> 1);
+        complete(hi);
+        issue(ec, Jcur + 2, nc, Pc, i0 >> 1);
     }
     // add P(ec) to fine row j (j non-decreasing between calls)
     __device__ __forceinline__ void add(T (&x)[V], const T* ec, int j, int n, int nc, int Pc, int i0, int m) {
@@ -154,8 +164,9 @@ struct Prolong {
         while (Jcur < J) {   // at most one step per fine row
 #pragma unroll
             for (int q = 0; q <= V2; ++q) lo[q] = hi[q];
+            complete(hi);
             ++Jcur;
-            load_coarse(hi, ec, Jcur + 1, nc, Pc, i0 >> 1);
+            issue(ec, Jcur + 2, nc, Pc, i0 >> 1);
         }
         if (j < 0 || j >= n) return;
         const bool t = (j & 1) != 0;                  // wave-uniform

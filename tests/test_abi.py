@@ -53,6 +53,9 @@ def test_host_only_calls():
     assert lib.lap_grid_footprint(8193, 8193, N.LAP_ALLOC_ALL) > 3.5 * allf
     assert lib.lap_grid_footprint(2, 9, N.LAP_ALLOC_ALL) == 0
     assert lib.lap_op_work_bytes(65, 33) >= 33 * 64 * 8
+    # every level of a (2^j + 1)-sided hierarchy from 65 to 8193 has a tiling class of its own
+    assert [lib.lap_size_class(2 ** j + 1, 2 ** j + 1) for j in range(6, 14)] == list(range(8))
+    assert lib.lap_size_class(5, 5) == 0 and lib.lap_size_class(16385, 16385) == 7
     # argument errors are reported without touching a device
     h = ctypes.c_void_p()
     assert lib.lap_ctx_create(None, 1 << 30, None, ctypes.byref(h)) == N.LAP_EINVAL

@@ -20,7 +20,7 @@ def test_solution_bitwise_identical_across_tilings(precision):
     for (V, ty, tgt) in TILINGS:
         say("tiling", precision, V, ty, tgt)
         ctx = lap.Context(arena_bytes=256 << 20)
-        for sc in range(4):
+        for sc in range(8):
             for cls in range(12):
                 for dt in (0, 1):
                     ctx.set_tiling(cls, dt, sc, V, ty, tgt)
@@ -38,17 +38,19 @@ def test_autotune_report_and_effect():
     say("autotune 257")
     ctx = lap.Context(arena_bytes=256 << 20)
     rep = ctx.autotune(257, 257, reps=2)
-    assert rep["size_class"] == lap.size_class(257, 257) == 1
+    assert rep["size_class"] == lap.size_class(257, 257) == 2
     kinds = {(e["kernel"], e["dtype"]) for e in rep["best"]}
     assert ("sweep", "f64") in kinds and ("defect", "f64") in kinds and ("restrict", "f32") in kinds
     for e in rep["best"]:
-        assert (e["V"], e["ty"], e["target_waves"]) == ctx.get_tiling(e["class"], 0 if e["dtype"] == "f64" else 1, 1)
+        assert (e["V"], e["ty"], e["target_waves"]) == ctx.get_tiling(e["class"], 0 if e["dtype"] == "f64" else 1, 2)
         assert e["ms"] > 0
     ctx2 = lap.Context(arena_bytes=64 << 20)
     ctx2.apply_tuning(rep)
     e = rep["best"][0]
-    assert ctx2.get_tiling(e["class"], 0 if e["dtype"] == "f64" else 1, 1) == (e["V"], e["ty"], e["target_waves"])
+    assert ctx2.get_tiling(e["class"], 0 if e["dtype"] == "f64" else 1, 2) == (e["V"], e["ty"], e["target_waves"])
     with pytest.raises(lap.LapError):
         ctx.set_tiling(0, 0, 1, 3, 16, 0)
     with pytest.raises(lap.LapError):
         ctx.set_tiling(0, 0, 1, 2, 15, 0)
+    with pytest.raises(lap.LapError):
+        ctx.set_tiling(0, 0, 8, 2, 16, 0)
