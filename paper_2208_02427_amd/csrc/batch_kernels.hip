@@ -183,8 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_coarse(const BatchItem* items,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_finalize(const BatchItem* items, int count) {
-    __shared__ double ss[kBlock], sm[kBlock];
+__global__ __launch_bounds__(kFinBlock) void k_batch_finalize(const BatchItem* items, int count) {
+    __shared__ double ss[kFinBlock / 64], sm[kFinBlock / 64];
     for (int k = blockIdx.x; k < count; k += gridDim.x) {
         const BatchItem& it = items[k];
         if (it.ctrl->done) continue;
@@ -224,7 +224,7 @@ hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items
         case BK_COARSE:
             return dt == 0 ? launch_batch_t<double>(kind, step_flags, items, count, total, blocks, s)
                            : launch_batch_t<float>(kind, step_flags, items, count, total, blocks, s);
-        case BK_FINALIZE: k_batch_finalize<<<blocks, kBlock, 0, s>>>(items, count); break;
+        case BK_FINALIZE: k_batch_finalize<<<blocks, kFinBlock, 0, s>>>(items, count); break;
         case BK_RESNORM: k_batch_resnorm<<<blocks, kBlock, 0, s>>>(items, count, total); break;
         case BK_DEFECT: k_batch_defect<<<blocks, kBlock, 0, s>>>(items, count, total); break;
         case BK_ADI_ROWS:

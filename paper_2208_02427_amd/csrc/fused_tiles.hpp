@@ -78,10 +78,14 @@ __device__ __forceinline__ void rb_push(RBStage<T, V>& S, const T (&d)[V], const
     copy<T, V>(S.fc, fd);
 }
 
+// Input rows in flight per wavefront: a ring of kFusedPF rows, each issued
+// kFusedPF steps before it enters the pipeline.
+constexpr int kFusedPF = 4;
+
 template <typename T, int V, int NS, bool RS>
 struct FusedRegs {
     RBStage<T, V> st[NS];
-    T dn[V], fdn[V], dnn[V], fdnn[V];   // prefetched input rows j+2, j+3
+    T ring[kFusedPF][V], fring[kFusedPF][V];   // input rows j+1 .. j+kFusedPF (slot = step phase)
     T bo[V];                            // input row j-1 (norm of the input)
     T ru0[V], ru1[V], rf1[V];           // final rows q-2, q-1 and f of row q-1
     T r2[V], r1[V];                     // residual rows q-3, q-2
@@ -89,19 +93,18 @@ struct FusedRegs {
     Prolong<T, V> pr;
 };
 
-// One step: input row j+1 enters, the last stage emits final row
+// One step (ring phase PH): input row j+1 enters from its ring slot, the
+// slot is refilled with row j+1+kFusedPF, and the last stage emits final row
 // q = j + 1 - 2 * NS.
-template <typename T, int V, int FL, int NS, bool RS, int JP>
+template <typename T, int V, int FL, int NS, bool RS, int JP, int PH>
 __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS>& R, const Cols<V>& c,
                                            int j, int j0, int j1, int Lend, int ipar) {
     T d[V], fd[V];
-    copy<T, V>(d, R.dn);
-    copy<T, V>(fd, R.fdn);
-    copy<T, V>(R.dn, R.dnn);
-    copy<T, V>(R.fdn, R.fdnn);
-    if (j + 3 <= Lend) {
-        sweep_load<T, V, FL>(R.dnn, A, j + 3, c, R.pr);
-        sweep_loadf<T, V, FL>(R.fdnn, A, j + 3, c);
+    copy<T, V>(d, R.ring[PH]);
+    copy<T, V>(fd, R.fring[PH]);
+    if (j + 1 + kFusedPF <= Lend) {
+        sweep_load<T, V, FL>(R.ring[PH], A, j + 1 + kFusedPF, c, R.pr);
+        sweep_loadf<T, V, FL>(R.fring[PH], A, j + 1 + kFusedPF, c);
     }
     const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
 
@@ -201,17 +204,21 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A, int tile, int 
     sweep_load<T, V, FL>(R.st[0].b, A, L0, c, R.pr);
     sweep_load<T, V, FL>(R.st[0].c, A, L0 + 1, c, R.pr);
     sweep_loadf<T, V, FL>(R.st[0].fc, A, L0 + 1, c);
-    sweep_load<T, V, FL>(R.dn, A, L0 + 2, c, R.pr);
-    sweep_loadf<T, V, FL>(R.fdn, A, L0 + 2, c);
-    sweep_load<T, V, FL>(R.dnn, A, L0 + 3, c, R.pr);
-    sweep_loadf<T, V, FL>(R.fdnn, A, L0 + 3, c);
+#pragma unroll
+    for (int k = 0; k < kFusedPF; ++k) {
+        sweep_load<T, V, FL>(R.ring[k], A, L0 + 2 + k, c, R.pr);
+        sweep_loadf<T, V, FL>(R.fring[k], A, L0 + 2 + k, c);
+    }
     if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.st[0].b);
 
     // the first step's row L0 + 1 is even without restriction, odd with it
     constexpr int JP0 = RS ? 1 : 0;
-    for (int j = L0 + 1; j <= Lend - 1; j += 2) {
-        fused_step<T, V, FL, NS, RS, JP0>(A, R, c, j, j0, j1, Lend, ipar);
-        if (j + 1 <= Lend - 1) fused_step<T, V, FL, NS, RS, 1 - JP0>(A, R, c, j + 1, j0, j1, Lend, ipar);
+    static_assert(kFusedPF == 4, "the step loop below is unrolled for a ring of four rows");
+    for (int j = L0 + 1; j <= Lend - 1; j += 4) {
+        fused_step<T, V, FL, NS, RS, JP0, 0>(A, R, c, j, j0, j1, Lend, ipar);
+        if (j + 1 <= Lend - 1) fused_step<T, V, FL, NS, RS, 1 - JP0, 1>(A, R, c, j + 1, j0, j1, Lend, ipar);
+        if (j + 2 <= Lend - 1) fused_step<T, V, FL, NS, RS, JP0, 2>(A, R, c, j + 2, j0, j1, Lend, ipar);
+        if (j + 3 <= Lend - 1) fused_step<T, V, FL, NS, RS, 1 - JP0, 3>(A, R, c, j + 3, j0, j1, Lend, ipar);
     }
     if constexpr (FL & SW_NORM) {
         const double s = wave_sum(R.s2);

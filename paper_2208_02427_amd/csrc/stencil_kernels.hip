@@ -144,10 +144,10 @@ hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s) {
 template hipError_t launch_coarse<double>(const CoarseArgs<double>&, hipStream_t);
 template hipError_t launch_coarse<float>(const CoarseArgs<float>&, hipStream_t);
 
-__global__ __launch_bounds__(kBlock) void k_finalize(const double* partials, int ntiles, Ctrl* ctrl,
+__global__ __launch_bounds__(kFinBlock) void k_finalize(const double* partials, int ntiles, Ctrl* ctrl,
                                                      double* out2, int mode) {
     if (mode == 0 && ctrl->done) return;
-    __shared__ double ss[kBlock], sm[kBlock];
+    __shared__ double ss[kFinBlock / 64], sm[kFinBlock / 64];
     finalize_block(partials, ntiles, ctrl, out2, mode, ss, sm);
 }
 
@@ -174,7 +174,7 @@ hipError_t launch_ctrl_init(Ctrl* ctrl, double tol, int stop, int max_iter, int 
 
 hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, double* out2, int mode,
                            hipStream_t s) {
-    k_finalize<<<1, kBlock, 0, s>>>(partials, ntiles, ctrl, out2, mode);
+    k_finalize<<<1, kFinBlock, 0, s>>>(partials, ntiles, ctrl, out2, mode);
     return hipGetLastError();
 }
 

@@ -696,25 +696,45 @@ __device__ void subtree_block(const SubtreeArgs<T>& S, T* s, double* rhs) {
 }
 
 // ------------------------------------------------------------ norm finalise
+// One workgroup of kFinBlock threads: thread t sums partials t, t + kFinBlock,
+// ... in that order (loads issued four at a time), the waves reduce with a
+// fixed butterfly, and thread 0 adds the wave results in order, so the norm
+// does not depend on timing.
+constexpr int kFinBlock = 1024;
+
 __device__ __forceinline__ void finalize_block(const double* partials, int ntiles, Ctrl* ctrl, double* out2,
                                                int mode, double* ss, double* sm) {
     double s = 0.0, mx = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += kBlock) {
-        s += partials[2 * t];
-        mx = fmax(mx, partials[2 * t + 1]);
+    const double2* p2 = reinterpret_cast<const double2*>(partials);
+    int t = threadIdx.x;
+    for (; t + 3 * kFinBlock < ntiles; t += 4 * kFinBlock) {
+        const double2 a0 = p2[t], a1 = p2[t + kFinBlock], a2 = p2[t + 2 * kFinBlock], a3 = p2[t + 3 * kFinBlock];
+        s += a0.x;
+        s += a1.x;
+        s += a2.x;
+        s += a3.x;
+        mx = fmax(fmax(fmax(fmax(mx, a0.y), a1.y), a2.y), a3.y);
     }
-    ss[threadIdx.x] = s;
-    sm[threadIdx.x] = mx;
+    for (; t < ntiles; t += kFinBlock) {
+        const double2 a = p2[t];
+        s += a.x;
+        mx = fmax(mx, a.y);
+    }
+    s = wave_sum(s);
+    mx = wave_max(mx);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        ss[w] = s;
+        sm[w] = mx;
+    }
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            ss[threadIdx.x] += ss[threadIdx.x + w];
-            sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
-        }
-        __syncthreads();
-    }
     if (threadIdx.x != 0) return;
-    const double sum = ss[0], m = sm[0];
+    double sum = 0.0, m = 0.0;
+    for (int k = 0; k < kFinBlock / 64; ++k) {
+        sum += ss[k];
+        m = fmax(m, sm[k]);
+    }
+
     if (mode == 1) {
         out2[0] = sum;
         out2[1] = m;
