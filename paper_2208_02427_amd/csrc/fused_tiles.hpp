@@ -78,14 +78,18 @@ __device__ __forceinline__ void rb_push(RBStage<T, V>& S, const T (&d)[V], const
     copy<T, V>(S.fc, fd);
 }
 
-// Input rows in flight per wavefront: a ring of kFusedPF rows, each issued
-// kFusedPF steps before it enters the pipeline.
-constexpr int kFusedPF = 4;
+// Input rows in flight per wavefront: a ring of PF rows, each issued PF
+// steps before it enters the pipeline.  Measured on MI355X (8193^2 V-cycle
+// passes): FP64 gains up to six rows, FP32 (half the bytes per row, the
+// registers better spent on occupancy) is fastest with two.
+template <typename T>
+constexpr int fused_pf() { return sizeof(T) == 8 ? 6 : 2; }
 
 template <typename T, int V, int NS, bool RS>
 struct FusedRegs {
+    static constexpr int PF = fused_pf<T>();
     RBStage<T, V> st[NS];
-    T ring[kFusedPF][V], fring[kFusedPF][V];   // input rows j+1 .. j+kFusedPF (slot = step phase)
+    T ring[PF][V], fring[PF][V];        // input rows j+1 .. j+PF (slot = step phase)
     T bo[V];                            // input row j-1 (norm of the input)
     T ru0[V], ru1[V], rf1[V];           // final rows q-2, q-1 and f of row q-1
     T r2[V], r1[V];                     // residual rows q-3, q-2
@@ -94,17 +98,18 @@ struct FusedRegs {
 };
 
 // One step (ring phase PH): input row j+1 enters from its ring slot, the
-// slot is refilled with row j+1+kFusedPF, and the last stage emits final row
+// slot is refilled with row j+1+PF, and the last stage emits final row
 // q = j + 1 - 2 * NS.
 template <typename T, int V, int FL, int NS, bool RS, int JP, int PH>
 __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS>& R, const Cols<V>& c,
                                            int j, int j0, int j1, int Lend, int ipar) {
+    constexpr int PF = fused_pf<T>();
     T d[V], fd[V];
     copy<T, V>(d, R.ring[PH]);
     copy<T, V>(fd, R.fring[PH]);
-    if (j + 1 + kFusedPF <= Lend) {
-        sweep_load<T, V, FL>(R.ring[PH], A, j + 1 + kFusedPF, c, R.pr);
-        sweep_loadf<T, V, FL>(R.fring[PH], A, j + 1 + kFusedPF, c);
+    if (j + 1 + PF <= Lend) {
+        sweep_load<T, V, FL>(R.ring[PH], A, j + 1 + PF, c, R.pr);
+        sweep_loadf<T, V, FL>(R.fring[PH], A, j + 1 + PF, c);
     }
     const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
 
@@ -175,6 +180,18 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
     }
 }
 
+// Steps PH, PH+1, ... of one turn of the ring, starting at row j + PH.
+template <typename T, int V, int FL, int NS, bool RS, int JP0, int PH>
+__device__ __forceinline__ void fused_turn(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS>& R, const Cols<V>& c,
+                                           int j, int j0, int j1, int Lend, int ipar) {
+    if constexpr (PH < fused_pf<T>()) {
+        if (j + PH <= Lend - 1) {
+            fused_step<T, V, FL, NS, RS, (JP0 + PH) & 1, PH>(A, R, c, j + PH, j0, j1, Lend, ipar);
+            fused_turn<T, V, FL, NS, RS, JP0, PH + 1>(A, R, c, j, j0, j1, Lend, ipar);
+        }
+    }
+}
+
 template <typename T, int V, int FL>
 __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A, int tile, int lane) {
     constexpr int NS = (FL & SW_TWO) ? 2 : 1;
@@ -204,22 +221,21 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A, int tile, int 
     sweep_load<T, V, FL>(R.st[0].b, A, L0, c, R.pr);
     sweep_load<T, V, FL>(R.st[0].c, A, L0 + 1, c, R.pr);
     sweep_loadf<T, V, FL>(R.st[0].fc, A, L0 + 1, c);
+    constexpr int PF = fused_pf<T>();
 #pragma unroll
-    for (int k = 0; k < kFusedPF; ++k) {
+    for (int k = 0; k < PF; ++k) {
         sweep_load<T, V, FL>(R.ring[k], A, L0 + 2 + k, c, R.pr);
         sweep_loadf<T, V, FL>(R.fring[k], A, L0 + 2 + k, c);
     }
     if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.st[0].b);
 
-    // the first step's row L0 + 1 is even without restriction, odd with it
+    // the first step's row L0 + 1 is even without restriction, odd with it;
+    // the loop is unrolled over one turn of the ring (PF is even, so every
+    // turn starts on the same row parity)
     constexpr int JP0 = RS ? 1 : 0;
-    static_assert(kFusedPF == 4, "the step loop below is unrolled for a ring of four rows");
-    for (int j = L0 + 1; j <= Lend - 1; j += 4) {
-        fused_step<T, V, FL, NS, RS, JP0, 0>(A, R, c, j, j0, j1, Lend, ipar);
-        if (j + 1 <= Lend - 1) fused_step<T, V, FL, NS, RS, 1 - JP0, 1>(A, R, c, j + 1, j0, j1, Lend, ipar);
-        if (j + 2 <= Lend - 1) fused_step<T, V, FL, NS, RS, JP0, 2>(A, R, c, j + 2, j0, j1, Lend, ipar);
-        if (j + 3 <= Lend - 1) fused_step<T, V, FL, NS, RS, 1 - JP0, 3>(A, R, c, j + 3, j0, j1, Lend, ipar);
-    }
+    static_assert(PF % 2 == 0, "the ring turn must keep the row parity");
+    for (int j = L0 + 1; j <= Lend - 1; j += PF)
+        fused_turn<T, V, FL, NS, RS, JP0, 0>(A, R, c, j, j0, j1, Lend, ipar);
     if constexpr (FL & SW_NORM) {
         const double s = wave_sum(R.s2);
         const double mx = wave_max(R.mx);
