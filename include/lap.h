@@ -194,7 +194,10 @@ lap_status lap_ctx_get_fusion(lap_ctx* ctx, int32_t* on);
  * m x n level (odd m, n >= 5; carved from the arena and released), keep the
  * fastest per kernel class and dtype for that size class, and write a JSON
  * report of the choices into `report` (host buffer of report_bytes, may be
- * NULL).  `reps` timed launches per candidate.  Synchronises the stream. */
+ * NULL).  `reps` timed launches per candidate.  Levels with arrays of 16 MB
+ * or more are timed from a cold cache (a 512 MB copy through the arena before
+ * each timed launch, when the arena can hold it; "cold_cache" in the report).
+ * Synchronises the stream. */
 lap_status lap_autotune(lap_ctx* ctx, int32_t m, int32_t n, int32_t reps, char* report, size_t report_bytes);
 
 /* ------------------------------------------------------------------ grids */
