@@ -125,8 +125,9 @@ def run_gpu(args):
 
     for _ in range(args.warmup):
         one_solve()
-    # timed region: kernel timing on (HIP events around every launch on the library's stream)
-    ctx.set_timing(True)
+    # timed region: kernel timing on (HIP events around every finest-level
+    # launch on the library's stream; coarser launches are counted untimed)
+    ctx.set_timing(2)
     ctx.reset_stats()
     sync()
     t0 = time.perf_counter()
@@ -175,9 +176,7 @@ def run_gpu(args):
     out["kernels_fine"] = fine
     # whole solve: algorithmic bytes of every launch over the step time
     alg = sum(e["alg_bytes"] for e in every)
-    out["solve_hbm"] = {"alg_bytes_per_step": alg / args.steps,
-                        "GB/s_over_step_time": alg / dt / 1e9,
-                        "GB/s_over_device_time": alg / (sum(e["device_ms"] for e in every) / 1e3) / 1e9}
+    out["solve_hbm"] = {"alg_bytes_per_step": alg / args.steps, "GB/s_over_step_time": alg / dt / 1e9}
     # correctness of the timed result: oracle-side residual at sampled rows is
     # checked in the GPU tests; here record the library's own FP64 residual
     l2, linf = g.residual()

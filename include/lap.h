@@ -128,11 +128,15 @@ lap_status lap_ctx_destroy(lap_ctx* ctx);   /* destroys remaining grids; the are
 /* Bytes of arena in use and largest free block. */
 lap_status lap_ctx_usage(lap_ctx* ctx, size_t* used, size_t* largest_free);
 
-/* Timing of kernel launches (off by default).  When on, the library records a
- * pair of HIP events on its stream around every launch and accumulates, per
- * kernel class and for the finest level separately, the launch count, the
- * summed device time and the algorithmic bytes the launches move (interior
- * nodes x bytes per node of that kernel).  Classes: 0 RB sweep, 1 RB sweep
+/* Timing of kernel launches (off by default).  on = 1: the library records a
+ * pair of HIP events on its stream around every launch; on = 2: around the
+ * finest-level launches only (the others are counted without events).  It
+ * accumulates, per kernel class and for the finest level separately, the
+ * launch count, the summed device time and the algorithmic bytes the launches
+ * move (interior nodes x bytes per node of that kernel).  Solves run as with
+ * timing off (steps enqueued ahead of the stopping test, no graph replay);
+ * launches after the stopping test that ended a solve exit at once on the
+ * device and are left out of the statistics.  Classes: 0 RB sweep, 1 RB sweep
  * with fused prolongation, 2 residual + full weighting, 3 defect correction
  * (FP64), 4 coarse solve, 5 norm finalise, 6 ADI row lines, 7 ADI column
  * lines, 8 residual, 9 small-level subtree (one launch per sub-V-cycle; its

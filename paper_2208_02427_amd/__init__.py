@@ -119,8 +119,9 @@ class Context:
         _check(lib().lap_ctx_usage(self.handle, ctypes.byref(u), ctypes.byref(f)))
         return u.value, f.value
 
-    def set_timing(self, on: bool):
-        _check(lib().lap_ctx_set_timing(self.handle, 1 if on else 0))
+    def set_timing(self, on=True):
+        """False/0 off, True/1 events around every launch, 2 around finest-level launches only."""
+        _check(lib().lap_ctx_set_timing(self.handle, int(on)))
 
     def reset_stats(self):
         _check(lib().lap_ctx_reset_stats(self.handle))

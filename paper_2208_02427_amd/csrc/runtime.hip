@@ -271,13 +271,21 @@ int size_class(size_t nint) {
 struct lap_ctx {
     Arena arena;
     hipStream_t stream = nullptr;
-    bool timing = false;
+    // kernel timing: 0 off, 1 HIP events around every launch, 2 events around
+    // finest-level launches only (the others are counted, untimed)
+    int timing = 0;
     struct Rec {
         int cls;
         bool fine;
         double bytes;
-        hipEvent_t a, b;
+        hipEvent_t a, b;       // null: counted, not timed
+        int solve, step;       // solve serial number and its outer step
+        bool head;             // launched by the step's stopping test
     };
+    // tags of the launches being enqueued (single-grid solves); solve -1 = untagged
+    int rec_solve = -1, rec_step = 0, solve_serial = 0;
+    bool rec_head = false;
+    int safe_step = 0;         // steps below this of solve rec_solve are known to have done full work
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     int64_t launches[KC_COUNT][2] = {};
@@ -317,34 +325,61 @@ struct lap_ctx {
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         return e;
     }
-    hipError_t flush_recs() {
+    void recycle(Rec& r) {
+        if (r.a) pool.push_back(r.a);
+        if (r.b) pool.push_back(r.b);
+    }
+    // Accumulate the records into the statistics.  all = false keeps the
+    // records of the running solve that may still turn out speculative.
+    hipError_t flush_recs(bool all = true) {
         if (recs.empty()) return hipSuccess;
         HIPERR(hipStreamSynchronize(stream));
+        std::vector<Rec> keep;
         for (auto& r : recs) {
+            if (!all && r.solve == rec_solve && r.solve >= 0 && r.step >= safe_step) {
+                keep.push_back(r);
+                continue;
+            }
             float t = 0.f;
-            HIPERR(hipEventElapsedTime(&t, r.a, r.b));
+            if (r.a) HIPERR(hipEventElapsedTime(&t, r.a, r.b));
             for (int f = 0; f < 2; ++f) {
                 if (f == 1 && !r.fine) continue;
                 launches[r.cls][f] += 1;
                 ms[r.cls][f] += t;
                 bytes[r.cls][f] += r.bytes;
             }
-            pool.push_back(r.a);
-            pool.push_back(r.b);
+            recycle(r);
         }
-        recs.clear();
+        recs.swap(keep);
         return hipSuccess;
+    }
+    // Forget the launches of solve `solve` that came after its stopping test
+    // in step `last` (they exited at once on the device's done flag).
+    void drop_speculative(int solve, int last) {
+        std::vector<Rec> keep;
+        for (auto& r : recs) {
+            if (r.solve == solve && (r.step > last || (r.step == last && !r.head)))
+                recycle(r);
+            else
+                keep.push_back(r);
+        }
+        recs.swap(keep);
     }
     template <typename F>
     hipError_t timed(int cls, bool fine, double nbytes, F&& launch) {
         if (!timing) return launch();
-        hipEvent_t a = ev(), b = ev();
-        if (a == nullptr || b == nullptr) return hipErrorOutOfMemory;
-        HIPERR(hipEventRecord(a, stream));
-        HIPERR(launch());
-        HIPERR(hipEventRecord(b, stream));
-        recs.push_back({cls, fine, nbytes, a, b});
-        if (recs.size() > 8192) return flush_recs();
+        if (timing == 2 && !fine) {
+            HIPERR(launch());
+            recs.push_back({cls, fine, nbytes, nullptr, nullptr, rec_solve, rec_step, rec_head});
+        } else {
+            hipEvent_t a = ev(), b = ev();
+            if (a == nullptr || b == nullptr) return hipErrorOutOfMemory;
+            HIPERR(hipEventRecord(a, stream));
+            HIPERR(launch());
+            HIPERR(hipEventRecord(b, stream));
+            recs.push_back({cls, fine, nbytes, a, b, rec_solve, rec_step, rec_head});
+        }
+        if (recs.size() > 8192) return flush_recs(false);
         return hipSuccess;
     }
     Tiling tiling(int m, int n, int cls, int dt, int H = 2) const {
@@ -1032,8 +1067,22 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
     return hipErrorInvalidValue;
 }
 
+// Launch a step's operations in order; for the timing records, the
+// operations up to and including the step's first norm finalisation form
+// its stopping test (its head).
 hipError_t exec_ops(lap_grid* g, const std::vector<Op>& ops) {
-    for (const Op& op : ops) HIPERR(exec_op(g, op));
+    lap_ctx* c = g->ctx;
+    size_t fin = ops.size();
+    for (size_t k = 0; k < ops.size(); ++k)
+        if (ops[k].kind == OP_FINALIZE) {
+            fin = k;
+            break;
+        }
+    for (size_t k = 0; k < ops.size(); ++k) {
+        c->rec_head = k <= fin && fin < ops.size();
+        HIPERR(exec_op(g, ops[k]));
+    }
+    c->rec_head = false;
     return hipSuccess;
 }
 
@@ -1047,7 +1096,9 @@ lap_status init_ctrl(lap_grid* g, const lap_opts& o, int step) {
 lap_status drive(lap_grid* g, int max_steps, const std::function<hipError_t(int)>& step, Ctrl& out) {
     lap_ctx* c = g->ctx;
     int polled = -1;
+    c->safe_step = 0;
     for (int s = 0; s < max_steps; ++s) {
+        c->rec_step = s;
         hipError_t e = step(s);
         if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
         HIPCHK(hipMemcpyAsync(&c->pinned[s & 1], g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
@@ -1056,6 +1107,7 @@ lap_status drive(lap_grid* g, int max_steps, const std::function<hipError_t(int)
             HIPCHK(hipEventSynchronize(c->poll_ev[(s - 1) & 1]));
             polled = s - 1;
             if (c->pinned[(s - 1) & 1].done) break;
+            c->safe_step = s;   // step s-1 did not stop: steps up to s-1 did full work
         }
     }
     (void)polled;
@@ -1267,34 +1319,21 @@ lap_status fixup(lap_grid* g, const lap_opts& o, const Ctrl& h) {
     return LAP_OK;
 }
 
-// Measurement mode (kernel timing on): test the stopping rule synchronously
-// before the rest of each step, so no kernel is ever launched after the
-// device has decided to stop and every timed launch did its full work.
-lap_status drive_measured(lap_grid* g, const lap_opts& o, Ctrl& out) {
-    lap_ctx* c = g->ctx;
-    for (int s = 0; s <= max_steps(o); ++s) {
-        hipError_t e = step(g, o, PART_HEAD);
-        if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
-        HIPCHK(hipMemcpyAsync(&c->pinned[2], g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if (c->pinned[2].done) break;
-        e = step(g, o, PART_TAIL);
-        if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
-    }
-    HIPCHK(hipStreamSynchronize(c->stream));
-    out = c->pinned[2];
-    return LAP_OK;
-}
-
+// With kernel timing on, the solve runs as without (steps enqueued one
+// ahead of the poll, no graph replay) and every launch is tagged with its
+// step; once the device has stopped, the records of the launches that came
+// after the deciding stopping test (they exited at once) are dropped, so
+// the statistics hold only launches that did their full work.
 lap_status solve_one(lap_grid* g, const lap_opts& o, lap_info* info) {
     const double t0 = now_s();
     lap_status st = prepare(g, o);
     if (st != LAP_OK) return st;
+    lap_ctx* c = g->ctx;
+    c->rec_solve = c->timing ? c->solve_serial++ : -1;
     Ctrl h{};
-    if (g->ctx->timing)
-        st = drive_measured(g, o, h);
-    else
-        st = drive(g, max_steps(o) + 1, [&](int) -> hipError_t { return step(g, o); }, h);
+    st = drive(g, max_steps(o) + 1, [&](int) -> hipError_t { return step(g, o); }, h);
+    if (c->timing && st == LAP_OK) c->drop_speculative(c->rec_solve, h.checks - 1);
+    c->rec_solve = -1;
     if (st != LAP_OK) return st;
     st = fixup(g, o, h);
     if (st != LAP_OK) return st;
@@ -1411,7 +1450,9 @@ lap_status lap_ctx_usage(lap_ctx* c, size_t* used, size_t* largest_free) {
 
 lap_status lap_ctx_set_timing(lap_ctx* c, int32_t on) {
     if (!c) return fail(LAP_EINVAL, "ctx is NULL");
-    c->timing = on != 0;
+    if (on < 0 || on > 2) return fail(LAP_EINVAL, "timing must be 0 (off), 1 (every launch) or 2 (finest level)");
+    HIPCHK(c->flush_recs());
+    c->timing = on;
     return LAP_OK;
 }
 

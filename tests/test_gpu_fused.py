@@ -105,3 +105,32 @@ def test_batch_fused_bitwise(precision):
     assert res[False][1] == res[True][1]
     for a, b in zip(res[False][0], res[True][0]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_timing_counts_only_full_work_launches(mode):
+    """Kernel statistics of a solve hold exactly the launches before and
+    including the deciding stopping test: one fused pre pass per cycle plus
+    the final test, one post pass per cycle (speculative launches after the
+    device stopped are left out).  Mode 2 times the finest level only."""
+    torch, lap = need_gpu()
+    p = W.square_problem(513, seed=2)
+    ctx = lap.Context(arena_bytes=256 << 20)
+    ctx.set_timing(mode)
+    g = ctx.grid(to_dev(torch, p.psi0), None, p.dx, p.dy)
+    say("timing", mode)
+    for _ in range(2):
+        ctx.reset_stats()
+        g.write(to_dev(torch, p.psi0))
+        info = g.solve("mg", tol=1e-10, max_iter=40)
+        k = info["iterations"]
+        pre = ctx.kernel_stats(KC_PRE, fine_only=True)
+        two = ctx.kernel_stats(KC_TWO, fine_only=True)
+        assert pre["launches"] == k + 1 and two["launches"] == k
+        assert pre["device_ms"] > 0 and two["device_ms"] > 0
+        allp = ctx.kernel_stats(KC_PRE)
+        assert allp["launches"] > pre["launches"]          # coarse levels counted too
+        if mode == 2:
+            assert allp["device_ms"] == pytest.approx(pre["device_ms"])   # ... but not timed
+    g.destroy()
+    ctx.close()
