@@ -141,7 +141,7 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
         copy<T, V>(fo, fo2);
     }
     const int q = j + 1 - 2 * NS;
-    if (q >= j0 && q <= j1) store_row<T, V>(A.uout, o, q, A.P, c);
+    if (q >= j0 && q <= j1) store_row<T, V>(A.uout, o, q, A.Ps, c);
 
     if constexpr (RS) {
         // residual of the result at row q-1, then full weighting at the even row q-2
@@ -153,7 +153,7 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
             const T w2 = __shfl_up(R.r2[V - 1], 1), w1 = __shfl_up(R.r1[V - 1], 1), w0 = __shfl_up(r0[V - 1], 1);
             const T e2 = __shfl_down(R.r2[0], 1), e1 = __shfl_down(R.r1[0], 1), e0 = __shfl_down(r0[0], 1);
             if (J >= 1 && J <= A.nc - 2) {
-                T* brow = A.bc + (size_t)J * A.Pc;
+                T* brow = A.bc + (ptrdiff_t)J * A.Pcs;
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     const int i = c.i0 + e;
@@ -192,18 +192,47 @@ __device__ __forceinline__ void fused_turn(const SweepArgs<T>& A, FusedRegs<T, V
     }
 }
 
+// Odd row chunks walk upwards, through a vertically flipped view of the
+// level (base at the last row, negative row strides; the coarse arrays
+// likewise).  Neighbouring chunks then reach their common boundary at the
+// same time, both at the start or both at the end of their walks, so the
+// halo rows one of them re-reads are still in L2.  With an odd number of
+// rows the flip keeps every node's colour (n - 1 is even), fine row 2J
+// stays over coarse row J, and each expression only sees its north and
+// south operands swapped in a commutative sum: the values are unchanged.
 template <typename T, int V, int FL>
-__device__ __forceinline__ void fused_tile(const SweepArgs<T>& A, int tile, int lane) {
+__device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int lane) {
     constexpr int NS = (FL & SW_TWO) ? 2 : 1;
     constexpr bool RS = (FL & SW_RESTRICT) != 0;
+    SweepArgs<T> A = A0;
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
     const Cols<V> c(win, lane, A.m, A.P, A.tl.H);
-    const int j0 = 1 + chunk * A.tl.ty;   // odd
-    const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
+    int j0 = 1 + chunk * A.tl.ty;
+    int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
+    A.Ps = A.P;
+    A.Pcs = A.Pc;
+    if ((chunk & 1) && (A.n & 1)) {
+        const ptrdiff_t last = (ptrdiff_t)(A.n - 1) * A.P, clast = (ptrdiff_t)(A.nc - 1) * A.Pc;
+        if (A.uin) A.uin += last;
+        A.uout += last;
+        if (A.f) A.f += last;
+        if (A.ec) A.ec += clast;
+        if (A.bc) A.bc += clast;
+        A.Ps = -A.P;
+        A.Pcs = -A.Pc;
+        const int t0 = A.n - 1 - j1;
+        j1 = A.n - 1 - j0;
+        j0 = t0;
+    }
     const int ipar = c.i0 & 1;
-    // input rows [L0, Lend]: the last stage is exact on [j0 - RS, j1 + 2 RS]
-    const int L0 = j0 - 2 * NS - (RS ? 1 : 0);
-    const int Lend = j1 + 2 * NS + (RS ? 2 : 0);
+    // input rows [L0, Lend]: the last stage must be exact on the chunk's rows
+    // and, with the restriction, two rows around its first and last even row;
+    // L0 is moved up one row if needed so the first step has parity JP0
+    constexpr int JP0 = RS ? 1 : 0;
+    const int e0 = j0 + (j0 & 1), e1 = j1 - (j1 & 1);
+    int L0 = (RS ? e0 - 2 : j0) - 2 * NS;
+    if (((L0 + 1) & 1) != JP0) --L0;
+    const int Lend = (RS ? e1 + 2 : j1) + 2 * NS;
 
     FusedRegs<T, V, NS, RS> R;
     R.s2 = 0.0;
@@ -217,7 +246,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A, int tile, int 
         zero<T, V>(R.r2);
         zero<T, V>(R.r1);
     }
-    if constexpr (FL & SW_PROLONG) R.pr.init(A.ec, L0, A.nc, A.Pc, c.i0);
+    if constexpr (FL & SW_PROLONG) R.pr.init(A.ec, L0, A.nc, A.Pc, A.Pcs, c.i0);
     sweep_load<T, V, FL>(R.st[0].b, A, L0, c, R.pr);
     sweep_load<T, V, FL>(R.st[0].c, A, L0 + 1, c, R.pr);
     sweep_loadf<T, V, FL>(R.st[0].fc, A, L0 + 1, c);
@@ -229,10 +258,8 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A, int tile, int 
     }
     if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.st[0].b);
 
-    // the first step's row L0 + 1 is even without restriction, odd with it;
     // the loop is unrolled over one turn of the ring (PF is even, so every
-    // turn starts on the same row parity)
-    constexpr int JP0 = RS ? 1 : 0;
+    // turn starts on the row parity JP0)
     static_assert(PF % 2 == 0, "the ring turn must keep the row parity");
     for (int j = L0 + 1; j <= Lend - 1; j += PF)
         fused_turn<T, V, FL, NS, RS, JP0, 0>(A, R, c, j, j0, j1, Lend, ipar);

@@ -132,6 +132,10 @@ struct SweepArgs {
     const Ctrl* ctrl;   // nullable: kernel returns at once if ctrl->done
     int m, n, P;
     int mc, nc, Pc;
+    // row strides of (uin, uout, f) and of (ec, bc) as the tile sees them:
+    // 0 = P / Pc; the fused kernels walk some chunks through a vertically
+    // flipped view (base at the last row, stride -P)
+    int Ps, Pcs;
     T cx, cy, d, inv_d, omega;
     Tiling tl;
 };

@@ -96,17 +96,19 @@ struct Cols {
     }
 };
 
+// P is the row stride (negative for a flipped view); vin says the lane's
+// columns lie inside the row.
 template <typename T, int V>
 __device__ __forceinline__ void load_row(T (&x)[V], const T* base, int j, int n, int P, int i0, bool vin) {
     if (base != nullptr && vin && j >= 0 && j < n)
-        ldv<T, V>(x, base + (size_t)j * P + i0);
+        ldv<T, V>(x, base + (ptrdiff_t)j * P + i0);
     else
         zero<T, V>(x);
 }
 
 template <typename T, int V>
 __device__ __forceinline__ void store_row(T* base, const T (&x)[V], int j, int P, const Cols<V>& c) {
-    T* p = base + (size_t)j * P + c.i0;
+    T* p = base + (ptrdiff_t)j * P + c.i0;
     if (c.vin && c.all_out) {
         stv<T, V>(p, x);
     } else {
@@ -131,9 +133,10 @@ struct Prolong {
     T lo[V2 + 1], hi[V2 + 1];   // coarse rows Jcur, Jcur+1 (entry V2 from the next lane)
     T nraw[V2], nlast;          // coarse row Jcur+2 as loaded (nlast: lane 63's column I0+V2)
     int Jcur;
-    __device__ __forceinline__ void issue(const T* ec, int J, int nc, int Pc, int I0) {
+    // Pc: the coarse row length bound (pitch), Ps: the coarse row stride
+    __device__ __forceinline__ void issue(const T* ec, int J, int nc, int Pc, int Ps, int I0) {
         if (J >= 0 && J < nc && I0 >= 0 && I0 + V2 <= Pc)
-            ldv<T, V2>(nraw, ec + (size_t)J * Pc + I0);
+            ldv<T, V2>(nraw, ec + (ptrdiff_t)J * Ps + I0);
         else
             zero<T, V2>(nraw);
         // the last lane has no right neighbour, but its halo columns still need
@@ -141,7 +144,7 @@ struct Prolong {
         nlast = T(0);
         if ((threadIdx.x & 63) == 63) {
             const int I = I0 + V2;
-            if (J >= 0 && J < nc && I >= 0 && I < Pc) nlast = ec[(size_t)J * Pc + I];
+            if (J >= 0 && J < nc && I >= 0 && I < Pc) nlast = ec[(ptrdiff_t)J * Ps + I];
         }
     }
     __device__ __forceinline__ void complete(T (&x)[V2 + 1]) {
@@ -150,23 +153,24 @@ struct Prolong {
         const T r = __shfl_down(nraw[0], 1);
         x[V2] = (threadIdx.x & 63) == 63 ? nlast : r;
     }
-    __device__ __forceinline__ void init(const T* ec, int j, int nc, int Pc, int i0) {
+    __device__ __forceinline__ void init(const T* ec, int j, int nc, int Pc, int Ps, int i0) {
         Jcur = j >> 1;
-        issue(ec, Jcur, nc, Pc, i0 >> 1);
+        issue(ec, Jcur, nc, Pc, Ps, i0 >> 1);
         complete(lo);
-        issue(ec, Jcur + 1, nc, Pc, i0 >> 1);
+        issue(ec, Jcur + 1, nc, Pc, Ps, i0 >> 1);
         complete(hi);
-        issue(ec, Jcur + 2, nc, Pc, i0 >> 1);
+        issue(ec, Jcur + 2, nc, Pc, Ps, i0 >> 1);
     }
     // add P(ec) to fine row j (j non-decreasing between calls)
-    __device__ __forceinline__ void add(T (&x)[V], const T* ec, int j, int n, int nc, int Pc, int i0, int m) {
+    __device__ __forceinline__ void add(T (&x)[V], const T* ec, int j, int n, int nc, int Pc, int Ps, int i0,
+                                        int m) {
         const int J = j >> 1;
         while (Jcur < J) {   // at most one step per fine row
 #pragma unroll
             for (int q = 0; q <= V2; ++q) lo[q] = hi[q];
             complete(hi);
             ++Jcur;
-            issue(ec, Jcur + 2, nc, Pc, i0 >> 1);
+            issue(ec, Jcur + 2, nc, Pc, Ps, i0 >> 1);
         }
         if (j < 0 || j >= n) return;
         const bool t = (j & 1) != 0;                  // wave-uniform
@@ -205,15 +209,15 @@ __device__ __forceinline__ void sweep_load(T (&x)[V], const SweepArgs<T>& A, int
     if constexpr (FL & SW_ZERO) {
         zero<T, V>(x);
     } else {
-        load_row<T, V>(x, A.uin, j, A.n, A.P, c.i0, c.vin);
-        if constexpr (FL & SW_PROLONG) pr.add(x, A.ec, j, A.n, A.nc, A.Pc, c.i0, A.m);
+        load_row<T, V>(x, A.uin, j, A.n, A.Ps, c.i0, c.vin);
+        if constexpr (FL & SW_PROLONG) pr.add(x, A.ec, j, A.n, A.nc, A.Pc, A.Pcs, c.i0, A.m);
     }
 }
 
 template <typename T, int V, int FL>
 __device__ __forceinline__ void sweep_loadf(T (&x)[V], const SweepArgs<T>& A, int j, const Cols<V>& c) {
     if constexpr (FL & SW_F)
-        load_row<T, V>(x, A.f, j, A.n, A.P, c.i0, c.vin);
+        load_row<T, V>(x, A.f, j, A.n, A.Ps, c.i0, c.vin);
     else
         zero<T, V>(x);
 }
@@ -293,7 +297,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
             R.b[e] = fma(om, t - R.b[e], R.b[e]);
         }
     }
-    if (j - 1 >= j0 && j - 1 <= j1) store_row<T, V>(A.uout, R.b, j - 1, A.P, c);
+    if (j - 1 >= j0 && j - 1 <= j1) store_row<T, V>(A.uout, R.b, j - 1, A.Ps, c);
 
     copy<T, V>(R.a, R.b);
     copy<T, V>(R.b, R.c);
@@ -303,7 +307,10 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
 }
 
 template <typename T, int V, int FL>
-__device__ __forceinline__ void sweep_tile(const SweepArgs<T>& A, int tile, int lane) {
+__device__ __forceinline__ void sweep_tile(const SweepArgs<T>& A0, int tile, int lane) {
+    SweepArgs<T> A = A0;
+    A.Ps = A.P;
+    A.Pcs = A.Pc;
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
     const Cols<V> c(win, lane, A.m, A.P, A.tl.H);
     const int j0 = 1 + chunk * A.tl.ty;          // odd
@@ -315,7 +322,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& A, int tile, int 
     R.mx = 0.0;
     zero<T, V>(R.a);
     zero<T, V>(R.fb);
-    if constexpr (FL & SW_PROLONG) R.pr.init(A.ec, j0 - 2, A.nc, A.Pc, c.i0);
+    if constexpr (FL & SW_PROLONG) R.pr.init(A.ec, j0 - 2, A.nc, A.Pc, A.Pcs, c.i0);
     sweep_load<T, V, FL>(R.b, A, j0 - 2, c, R.pr);
     sweep_load<T, V, FL>(R.c, A, j0 - 1, c, R.pr);
     sweep_loadf<T, V, FL>(R.fc, A, j0 - 1, c);
