@@ -54,7 +54,7 @@ template <typename T, int FLS>
 __global__ __launch_bounds__(kBlock) void k_batch_fused(const BatchItem* items, int count, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
-    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6); t < total; t += nw) {
+    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (int)(threadIdx.x >> 6); t < total; t += nw) {
         const BatchItem& it = items[find_fused_item(items, count, t)];
         if (it.ctrl->done) continue;
         batch_fused_tile<T, FLS>(it, t - it.tile0, lane);

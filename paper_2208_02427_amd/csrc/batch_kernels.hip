@@ -63,7 +63,7 @@ template <typename T, int FLS>
 __global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchItem* items, int count, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
-    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6); t < total; t += nw) {
+    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block(); t < total; t += nw) {
         const BatchItem& it = items[find_item(items, count, t)];
         if (it.ctrl->done) continue;
         batch_sweep_tile<T, FLS>(it, t - it.tile0, lane);
@@ -74,7 +74,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_batch_restrict(const BatchItem* items, int count, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
-    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6); t < total; t += nw) {
+    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block(); t < total; t += nw) {
         const BatchItem& it = items[find_item(items, count, t)];
         if (it.ctrl->done) continue;
         RestrictArgs<T> A{};
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_restrict(const BatchItem* item
 __global__ __launch_bounds__(kBlock) void k_batch_resnorm(const BatchItem* items, int count, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
-    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6); t < total; t += nw) {
+    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block(); t < total; t += nw) {
         const BatchItem& it = items[find_item(items, count, t)];
         if (it.ctrl->done) continue;
         ResidualArgs<double> A{};
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_resnorm(const BatchItem* items
 __global__ __launch_bounds__(kBlock) void k_batch_defect(const BatchItem* items, int count, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
-    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6); t < total; t += nw) {
+    for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block(); t < total; t += nw) {
         const BatchItem& it = items[find_item(items, count, t)];
         if (it.ctrl->done) continue;
         DefectArgs A{};

@@ -28,7 +28,7 @@ template <typename T, int V, int FL>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
+    const int tile = b * kWavesPerBlock + wave_in_block();
     if (tile >= A.tl.ntiles) return;
     sweep_tile<T, V, FL>(A, tile, threadIdx.x & 63);
 }
@@ -66,7 +66,7 @@ template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void k_restrict(RestrictArgs<T> A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
+    const int tile = b * kWavesPerBlock + wave_in_block();
     if (tile >= A.tl.ntiles) return;
     restrict_tile<T, V>(A, tile, threadIdx.x & 63);
 }
@@ -89,7 +89,7 @@ template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs<T> A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
+    const int tile = b * kWavesPerBlock + wave_in_block();
     if (tile >= A.tl.ntiles) return;
     residual_tile<T, V>(A, tile, threadIdx.x & 63);
 }
@@ -112,7 +112,7 @@ template <int V>
 __global__ __launch_bounds__(kBlock) void k_defect(DefectArgs A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int tile = b * kWavesPerBlock + (threadIdx.x >> 6);
+    const int tile = b * kWavesPerBlock + wave_in_block();
     if (tile >= A.tl.ntiles) return;
     defect_tile<V>(A, tile, threadIdx.x & 63);
 }

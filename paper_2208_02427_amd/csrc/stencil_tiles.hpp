@@ -55,6 +55,12 @@ __device__ __forceinline__ void copy(T (&dst)[V], const T (&src)[V]) {
     for (int e = 0; e < V; ++e) dst[e] = src[e];
 }
 
+// Index of the calling wavefront in its workgroup, as a wave-uniform value
+// (threadIdx.x >> 6 is the same on every lane, but the compiler cannot know
+// it; read from lane 0, every row and chunk test derived from it becomes a
+// scalar branch instead of an exec-masked vector one).
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // Workgroups are dealt to the XCDs round-robin; give XCD x the contiguous
 // tile range [x*per, (x+1)*per) so neighbouring tiles share that XCD's L2.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
