@@ -803,6 +803,19 @@ PassPlan pass_plan(const lap_ctx* c, const lap_opts& o, bool keep_parity) {
     return p;
 }
 
+// Sweeps per pass of one red-black SOR check block of `ce` sweeps: pairs
+// with fusion (an odd count ends with a single sweep), else single sweeps.
+std::vector<int> sor_passes(const lap_ctx* c, int ce) {
+    std::vector<int> p;
+    if (!c->fuse) {
+        p.assign(ce, 1);
+        return p;
+    }
+    p.assign(ce / 2, 2);
+    if (ce % 2) p.push_back(1);
+    return p;
+}
+
 // Buffer (0/1) in which a zero-start V-cycle leaves its level result: the
 // first pre-smoothing pass writes buffer 0, every further pass flips.
 int vcycle_result_index(const lap_ctx* c, const lap_opts& o) {
@@ -1262,14 +1275,24 @@ void plan_step(lap_grid* g, const lap_opts& o, int s, int part, std::vector<Op>&
             }
             return;
         case LAP_SOR_RB: {
+            // one check block: the first pass also forms the residual norms
+            // of the incoming iterate (the stopping test)
             const int fb = g->f64 ? SW_F : 0;
-            for (int k = (part == PART_TAIL ? 1 : 0); k < (part == PART_HEAD ? 1 : o.check_every); ++k) {
-                const int cur = (s * o.check_every + k) % 2;
-                push_op<double>(ops, key_pre(0, 0) + 2L * k, OP_SWEEP, 0, fb | (k == 0 ? SW_NORM : 0), g->psi[cur],
-                                g->psi[1 - cur], g->f64, nullptr, nullptr, o.omega);
+            const std::vector<int> pp = sor_passes(g->ctx, o.check_every);
+            const int np = (int)pp.size();
+            int cur = (s % 2) * (np % 2);   // parity of the passes of steps 0..s-1
+            for (int k = 0; k < np; ++k) {
+                if ((part == PART_TAIL && k == 0) || (part == PART_HEAD && k > 0)) {
+                    cur = 1 - cur;
+                    continue;
+                }
+                const int fl = fb | (k == 0 ? SW_NORM : 0) | (pp[k] == 2 ? SW_TWO : 0);
+                push_op<double>(ops, key_pre(0, 0) + 2L * k, OP_SWEEP, 0, fl, g->psi[cur], g->psi[1 - cur], g->f64,
+                                nullptr, nullptr, o.omega);
                 if (k == 0)
                     push_op<double>(ops, key_pre(0, 0) + 1, OP_FINALIZE, 0, 0, nullptr, nullptr, nullptr, nullptr,
                                     nullptr, 0.0);
+                cur = 1 - cur;
             }
             return;
         }
@@ -1312,7 +1335,7 @@ lap_status fixup(lap_grid* g, const lap_opts& o, const Ctrl& h) {
     lap_ctx* c = g->ctx;
     const size_t bytes = (size_t)g->n * g->P * 8;
     int where = 0;
-    if (o.method == LAP_SOR_RB) where = h.iters % 2;
+    if (o.method == LAP_SOR_RB) where = ((h.checks - 1) % 2) * ((int)sor_passes(c, o.check_every).size() % 2);
     if (o.method == LAP_MG && o.precision == LAP_MIXED) where = h.checks % 2;
     if (where == 1) HIPCHK(hipMemcpyAsync(g->psi[0], g->psi[1], bytes, hipMemcpyDeviceToDevice, c->stream));
     if (o.method == LAP_ADI) HIPCHK(hipMemcpyAsync(g->psi[1], g->psi[0], bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -2083,7 +2106,8 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
         for (size_t k = 0; k < gs.size(); ++k) {
             const int par = (o.method == LAP_MG && o.precision == LAP_MIXED)
                                 ? (steps[k] == 0 ? 2 : steps[k] % 2)
-                                : (o.method == LAP_SOR_RB ? (steps[k] * o.check_every) % 2 : 0);
+                                : (o.method == LAP_SOR_RB ? (steps[k] % 2) * ((int)sor_passes(c, o.check_every).size() % 2)
+                                                          : 0);
             snprintf(buf, sizeof buf, "%p:%d,", (void*)gs[k], par);
             key += buf;
         }

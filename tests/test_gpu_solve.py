@@ -45,6 +45,31 @@ def test_sor_iterates(m, n, k):
     g.destroy()
 
 
+@pytest.mark.parametrize("m,n", [(33, 17), (129, 65), (130, 67), (257, 129)])
+@pytest.mark.parametrize("ce", [2, 3, 5])
+def test_sor_check_blocks(m, n, ce):
+    """Check blocks of ce sweeps run as fused two-sweep passes (an odd block
+    ends with a single sweep); two blocks against the oracle, and bitwise
+    against one launch per sweep."""
+    say("sor blocks", m, n, ce)
+    psi, f, dx, dy = rand_problem(m, n, m + 3 * n + ce)
+    torch, lap, c = ctx()
+    outs = []
+    for fuse in (True, False):
+        c.set_fusion(fuse)
+        g = make_grid(psi, f, dx, dy)
+        info = g.solve("sor", omega=1.7, tol=0.0, max_iter=2 * ce, check_every=ce)
+        assert info["iterations"] == 2 * ce
+        outs.append(g.read().cpu().numpy())
+        g.destroy()
+    c.set_fusion(True)
+    ref = psi.copy()
+    for _ in range(2 * ce):
+        relax.rb_sweep(ref, f, dx, dy, 1.7)
+    assert maxabs(outs[0], ref) <= 1e-10
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("m,n", [(33, 17), (129, 65), (257, 257), (65, 129), (9, 9), (5, 5), (6, 6), (3, 3)])
 @pytest.mark.parametrize("k", [1, 3])
 def test_mg_fp64_cycles(m, n, k):
