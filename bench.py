@@ -336,9 +336,10 @@ def run_serving_leg(args, ctx, torch, lap, dev):
         jobs = [Job(r.rid, r.arrival, r.m, r.n, r.tol, payload=device_request(torch, r, dev)) for r in reqs]
         nodes = {j.rid: (j.m - 2) * (j.n - 2) for j in jobs}
         sync()
-        stats = Server(DeviceBackend(ctx, precision="mixed"), max_active=256).run(jobs)
+        stats = Server(DeviceBackend(ctx, precision="mixed"), max_active=256, burst=args.burst).run(jobs)
         sm = stats.summary()
         sm["GLUP/s"] = None
+        sm["burst"] = args.burst
         res[str(int(rate))] = {"batched_mixed": sm}
         if rate in args.baseline_rates:
             def solve_one(job):
@@ -391,6 +392,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--adi-iters", type=int, default=20)
     ap.add_argument("--serve-count", type=int, default=300)
+    ap.add_argument("--burst", type=int, default=4, help="outer steps per serving tick when no request waits")
     ap.add_argument("--rates", type=float, nargs="*", default=[100, 300, 1000, 3000, 10000])
     ap.add_argument("--baseline-rates", type=float, nargs="*", default=[100, 1000])
     args = ap.parse_args()

@@ -271,12 +271,16 @@ lap_status lap_solve_batch(lap_ctx* ctx, lap_grid* const* grids, int32_t count,
                            const lap_opts* opts, lap_info* infos);
 
 /* One scheduling tick for continuous batching: advance every listed grid by
- * one outer step (MG cycle / mixed outer step) with merged per-level
- * launches.  A grid whose stopping rule already holds is left unchanged and
- * reports done.  tol per grid is taken from lap_grid_set_tol (default 1e-10).
- * done_host[k] (host array) is set to 1 when grid k has converged or failed. */
+ * `steps` (>= 1) outer steps (MG cycle / mixed outer step) with merged
+ * per-level launches, enqueued back to back, then read every grid's control
+ * block once.  A grid whose stopping rule holds during the tick stops there
+ * (its later launches exit on the device), so each grid's iterate sequence
+ * is the same for any `steps`; more steps per tick mean fewer host round
+ * trips.  A grid already done is left unchanged and reports done.  tol per
+ * grid is taken from lap_grid_set_tol (default 1e-10).  done_host[k] (host
+ * array) is set to 1 when grid k has converged or failed. */
 lap_status lap_batch_step(lap_ctx* ctx, lap_grid* const* grids, int32_t count,
-                          int32_t precision, int32_t* done_host, lap_info* infos);
+                          int32_t precision, int32_t steps, int32_t* done_host, lap_info* infos);
 lap_status lap_grid_set_tol(lap_grid* g, double tol);
 /* Restart the stopping test of a grid (r_0 is re-taken at its next step). */
 lap_status lap_grid_reset(lap_grid* g);

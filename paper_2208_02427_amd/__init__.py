@@ -193,15 +193,15 @@ class Context:
         _check(st, allow=(N.LAP_ENOTCONV, N.LAP_EDIVERGED))
         return [i.as_dict() for i in infos]
 
-    def batch_step(self, grids, precision="mixed"):
-        """One continuous-batching tick; returns (done flags, infos)."""
+    def batch_step(self, grids, precision="mixed", steps=1):
+        """One continuous-batching tick of `steps` outer steps; returns (done flags, infos)."""
         n = len(grids)
         arr = (ctypes.c_void_p * n)(*[g.handle.value for g in grids])
         done = (ctypes.c_int32 * n)()
         infos = (LapInfo * n)()
         self._enter()
         st = lib().lap_batch_step(self.handle, arr, n, PRECISIONS[precision] if isinstance(precision, str)
-                                  else int(precision), done, infos)
+                                  else int(precision), int(steps), done, infos)
         self._leave()
         _check(st, allow=(N.LAP_ENOTCONV, N.LAP_EDIVERGED))
         return [bool(d) for d in done], [i.as_dict() for i in infos]

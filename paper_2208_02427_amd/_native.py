@@ -69,7 +69,7 @@ SIGNATURES = {
     "lap_residual": (_S, [_P, _PS(c_double), _PS(c_double)]),
     "lap_residual_ex": (_S, [_P, _PS(c_double), _PS(c_double)]),
     "lap_solve_batch": (_S, [_P, _PS(_P), c_int32, _PS(LapOpts), _PS(LapInfo)]),
-    "lap_batch_step": (_S, [_P, _PS(_P), c_int32, c_int32, _PS(c_int32), _PS(LapInfo)]),
+    "lap_batch_step": (_S, [_P, _PS(_P), c_int32, c_int32, c_int32, _PS(c_int32), _PS(LapInfo)]),
     "lap_grid_set_tol": (_S, [_P, c_double]),
     "lap_grid_reset": (_S, [_P]),
     "lap_op_rb_sweep": (_S, [c_int32, c_int32, c_int32, c_int32, c_double, c_double, c_double,

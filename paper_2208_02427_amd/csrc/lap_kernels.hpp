@@ -185,14 +185,14 @@ struct CoarseArgs {
     const T* b;         // right-hand side (nullable = 0)
     T* out;             // solution (interior written)
     const double* minv; // dense: (N x N) inverse of L_h on the interior unknowns, FP64, symmetric
-                        // banded: Cholesky factor of -L_h, N rows of (bw + 1) entries, row k
-                        // holding L(k, k), L(k, k-1), ..., L(k, k-bw)
-    double* work;       // banded: N doubles of FP64 scratch
+                        // lines: the short-side sine transform (p x p), then per mode the
+                        // Thomas factors c' and 1/pivot (q each) along the long side
+    double* work;       // lines: N doubles of FP64 scratch (the mode coefficients)
     const Ctrl* ctrl;
     int m, n, P;
     double cx, cy;
-    int bw;             // 0: dense inverse; > 0: banded Cholesky with this bandwidth
-    int ifast;          // banded ordering: 1 = i fastest, 0 = j fastest
+    int bw;             // 0: dense inverse; > 0: separable solve, p = the short interior side
+    int ifast;          // separable solve: 1 = the short side runs along x (i), 0 = along y
 };
 
 // The small-level tail of a V-cycle run by one workgroup with every level
@@ -220,7 +220,7 @@ struct SubtreeArgs {
     T omega;
     int lds_elems;       // elements of T for all levels' u and b
     int lds_bytes;       // dynamic LDS of the launch (levels + coarse rhs)
-    const double* minv;  // coarsest factor (dense inverse or band), see CoarseArgs
+    const double* minv;  // coarsest factor (dense inverse or separable), see CoarseArgs
     double* work;
     int bw, ifast;
     double ccx, ccy;     // coarsest-level coefficients in FP64
@@ -277,7 +277,8 @@ hipError_t launch_adi_rows(const LineArgs& a, hipStream_t s);
 hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s);
 
 // Coarsest levels with at most this many unknowns use a dense inverse (all
-// lanes in parallel); larger ones a banded Cholesky factor.
+// lanes in parallel); larger ones (long thin grids) a separable solve: sine
+// transform along the short side, a tridiagonal solve per mode along the long.
 constexpr int kDenseCoarseMax = 256;
 
 // ---- merged ragged-batch launches (batch_kernels.hip) ----
@@ -289,8 +290,8 @@ struct BatchItem {
     const void* f;           // right-hand side
     const void* ec;          // sweep: coarse correction; defect: FP32 correction
     void* bc;                // restrict: coarse right-hand side; defect: FP32 rhs
-    const double* minv;      // coarse solve (dense inverse or banded factor)
-    double* cwork;           // banded coarse solve scratch
+    const double* minv;      // coarse solve (dense inverse or separable factor)
+    double* cwork;           // separable coarse solve scratch
     int cbw, cifast;
     double* partials;        // norm partials
     Ctrl* ctrl;

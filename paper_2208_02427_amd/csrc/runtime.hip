@@ -195,42 +195,42 @@ bool coarse_inverse(int m, int n, double dx, double dy, std::vector<double>& out
     return true;
 }
 
-// Coarsest-level factor of levels too large for the dense inverse: banded
-// Cholesky of -L_h with the unknowns ordered along the longer side, so the
-// bandwidth is the number of interior nodes across the shorter side.  Band
-// row k holds L(k, k), L(k, k-1), ..., L(k, k-bw).
-constexpr int kBandMax = 128;
-constexpr size_t kBandStorageMax = (size_t)8 << 20;   // doubles
+// Coarsest levels above kDenseCoarseMax unknowns (long thin grids) are
+// solved by separation of variables: the 5-point operator on a rectangle
+// with constant coefficients is diagonalised along the short side by the
+// orthonormal sine transform Q (p x p, p = short interior side), leaving one
+// tridiagonal system along the long side per mode (q = long interior side).
+// Factor layout: Q (p*p), then per mode k the Thomas factors of
+// -L restricted to that mode, c'_l (q) and 1/pivot_l (q).
+constexpr int kLineMax = 128;
+constexpr size_t kLineStorageMax = (size_t)8 << 20;   // doubles
 
-bool coarse_band(int m, int n, double dx, double dy, std::vector<double>& out, int& bw, int& ifast) {
+bool coarse_lines(int m, int n, double dx, double dy, std::vector<double>& out, int& p, int& ifast) {
     const Coef c = coef(dx, dy);
-    const int mi = m - 2, ni = n - 2, N = mi * ni;
-    ifast = mi <= ni ? 1 : 0;
-    const int fast = ifast ? mi : ni;
-    const double cf = ifast ? c.cx : c.cy, cs = ifast ? c.cy : c.cx;
-    bw = fast;
-    const int W = bw + 1;
-    if (bw > kBandMax || (size_t)N * W > kBandStorageMax) return false;
-    auto Aval = [&](int k, int p) -> double {   // entries of -L_h, p <= k
-        if (p == k) return c.d;
-        if (k - p == 1 && (k % fast) != 0) return -cf;
-        if (k - p == fast) return -cs;
-        return 0.0;
-    };
-    out.assign((size_t)N * W, 0.0);
-    auto L = [&](int k, int p) -> double& { return out[(size_t)k * W + (k - p)]; };
-    for (int k = 0; k < N; ++k) {
-        const int p0 = k - bw > 0 ? k - bw : 0;
-        for (int j = p0; j < k; ++j) {
-            double v = Aval(k, j);
-            const int q0 = (j - bw > p0) ? j - bw : p0;
-            for (int p = q0; p < j; ++p) v -= L(k, p) * L(j, p);
-            L(k, j) = v / L(j, j);
+    const int mi = m - 2, ni = n - 2;
+    ifast = mi <= ni ? 1 : 0;                // 1: the short side runs along x
+    p = ifast ? mi : ni;
+    const int q = ifast ? ni : mi;
+    if (p < 1 || p > kLineMax || (size_t)p * p + 2 * (size_t)p * q > kLineStorageMax) return false;
+    const double cs = ifast ? c.cx : c.cy, cl = ifast ? c.cy : c.cx;
+    out.assign((size_t)p * p + 2 * (size_t)p * q, 0.0);
+    const double pi = std::acos(-1.0), nrm = std::sqrt(2.0 / (p + 1));
+    for (int k = 0; k < p; ++k)
+        for (int s = 0; s < p; ++s) out[(size_t)k * p + s] = nrm * std::sin(pi * (k + 1) * (s + 1) / (p + 1));
+    for (int k = 0; k < p; ++k) {
+        // mode k of -L_h along the long side: diagonal cs*mu_k + 2 cl, off-diagonal -cl
+        const double mu = 2.0 - 2.0 * std::cos(pi * (k + 1) / (p + 1));
+        const double diag = cs * mu + 2.0 * cl, off = -cl;
+        double* cpr = out.data() + (size_t)p * p + 2 * (size_t)k * q;
+        double* ipv = cpr + q;
+        double prev = 0.0;
+        for (int l = 0; l < q; ++l) {
+            const double piv = diag - off * prev;
+            if (!(piv > 0.0)) return false;
+            ipv[l] = 1.0 / piv;
+            cpr[l] = off / piv;
+            prev = cpr[l];
         }
-        double v = Aval(k, k);
-        for (int p = p0; p < k; ++p) v -= L(k, p) * L(k, p);
-        if (!(v > 0.0)) return false;
-        L(k, k) = std::sqrt(v);
     }
     return true;
 }
@@ -238,15 +238,15 @@ bool coarse_band(int m, int n, double dx, double dy, std::vector<double>& out, i
 bool coarse_ok(const LevelGeo& C) {
     const size_t N = C.interior();
     if (N <= (size_t)kDenseCoarseMax) return true;
-    const size_t fast = std::min(C.m, C.n) - 2;
-    return fast <= (size_t)kBandMax && N * (fast + 1) <= kBandStorageMax;
+    const size_t p = std::min(C.m, C.n) - 2, q = std::max(C.m, C.n) - 2;
+    return p <= (size_t)kLineMax && p * p + 2 * p * q <= kLineStorageMax;
 }
 
 size_t coarse_bytes(const LevelGeo& C) {
     const size_t N = C.interior();
     if (N <= (size_t)kDenseCoarseMax) return N * N * 8;
-    const size_t fast = std::min(C.m, C.n) - 2;
-    return N * (fast + 1) * 8;
+    const size_t p = std::min(C.m, C.n) - 2, q = std::max(C.m, C.n) - 2;
+    return (p * p + 2 * p * q) * 8;
 }
 
 enum Part { PART_ALL = 0, PART_HEAD = 1, PART_TAIL = 2 };
@@ -404,8 +404,8 @@ struct lap_grid {
     double* f64 = nullptr;
     std::vector<LevelBufs<double>> l64;
     std::vector<LevelBufs<float>> l32;
-    double* minv = nullptr;          // dense inverse or banded factor of the coarsest level
-    double* coarse_work = nullptr;   // banded solve scratch
+    double* minv = nullptr;          // dense inverse or separable factor of the coarsest level
+    double* coarse_work = nullptr;   // separable solve scratch
     int coarse_bw = 0, coarse_ifast = 1;
     double* adi_scratch = nullptr;
     double* adi_tab = nullptr;       // rows cprime, rows piv, cols cprime, cols piv (each maxK)
@@ -1572,7 +1572,7 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
         int bw = 0, ifast = 1;
         if (it == c->inv_cache.end()) {
             const bool okf = C.interior() <= (size_t)kDenseCoarseMax ? coarse_inverse(C.m, C.n, C.dx, C.dy, inv)
-                                                                     : coarse_band(C.m, C.n, C.dx, C.dy, inv, bw, ifast);
+                                                                     : coarse_lines(C.m, C.n, C.dx, C.dy, inv, bw, ifast);
             if (!okf) {
                 lap_grid_destroy(g);
                 return fail(LAP_EINVAL, "coarse operator factorisation failed");
@@ -1986,8 +1986,11 @@ int batch_kind(const Op& op) {
     return -1;
 }
 
+constexpr int kBatchMinRows = 32;
+constexpr size_t kBatchManyGrids = 4;
+
 // Fill the item of grid g for operation op (tiling, geometry, coefficients).
-BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o) {
+BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, bool many) {
     lap_ctx* c = g->ctx;
     const LevelGeo& L = g->geo[op.level];
     const Coef k = coef(L.dx, L.dy);
@@ -2052,6 +2055,13 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o) {
         case OP_COARSE:
         case OP_SUBTREE: t.ntiles = 1; break;
     }
+    // The table's short row chunks (down to 2 rows) minimise the latency of
+    // one grid's small level; inside a merged launch over many grids the
+    // launch is throughput-bound and a chunk's halo rows (up to 11 for a
+    // fused pass) would dominate, so plans of several grids use chunks of
+    // >= 32 rows.
+    if (many && (op.kind == OP_SWEEP || op.kind == OP_RESTRICT) && !(op.flags & SW_NORM) && t.ty < kBatchMinRows)
+        t = make_tiling(L.m, L.n, t.V, kBatchMinRows, 0, t.H);
     it.V = t.V;
     it.ty = t.ty;
     it.nwin = t.nwin;
@@ -2143,7 +2153,7 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
             L.fine = skv.second[0].second.level == 0;
             int tile0 = 0;
             for (auto& go : skv.second) {
-                BatchItem it = make_item(go.first, go.second, o);
+                BatchItem it = make_item(go.first, go.second, o, gs.size() >= kBatchManyGrids);
                 it.tile0 = tile0;
                 if (L.kind == BK_SUBTREE) {
                     const Op& op = go.second;
@@ -2339,9 +2349,10 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
 }
 
 extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t count, int32_t precision,
-                                     int32_t* done_host, lap_info* infos) {
+                                     int32_t nsteps, int32_t* done_host, lap_info* infos) {
     if (!c || (count > 0 && (!grids || !done_host))) return fail(LAP_EINVAL, "NULL argument");
     if (precision != LAP_FP64 && precision != LAP_MIXED) return fail(LAP_EINVAL, "unknown precision");
+    if (nsteps < 1) return fail(LAP_EINVAL, "steps must be >= 1");
     const double t0 = now_s();
     std::vector<lap_grid*> active;
     std::vector<int> steps;
@@ -2377,7 +2388,7 @@ extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t
         active.push_back(g);
         steps.push_back(g->step_idx);
     }
-    if (!active.empty()) {
+    for (int t = 0; t < nsteps && !active.empty(); ++t) {
         // the stopping tolerance lives in each grid's control block, so grids
         // with different tolerances share one plan
         lap_ctx::Plan* p = nullptr;
@@ -2385,7 +2396,7 @@ extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t
         if (st != LAP_OK) return st;
         hipError_t e = run_plan(c, p, true);
         if (e != hipSuccess) return fail(LAP_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
-        for (lap_grid* g : active) g->step_idx++;
+        for (size_t k = 0; k < active.size(); ++k) steps[k] = ++active[k]->step_idx;
     }
     std::vector<Ctrl> hs;
     lap_status st = batch_read(c, active, hs);

@@ -556,29 +556,52 @@ __device__ __forceinline__ void coarse_block(const CoarseArgs<T>& A, double* rhs
         }
         return;
     }
-    // banded Cholesky of -L_h (unknowns ordered along the longer side, so the
-    // bandwidth is the shorter interior side): (-L_h) x = -rhs by forward and
-    // back substitution, sequential along the ordering (one lane)
-    if (threadIdx.x != 0) return;
-    const int bw = A.bw, W = bw + 1;
-    const int fast = A.ifast ? mi : ni;
-    double* y = A.work;
-    for (int k = 0; k < N; ++k) {
-        const int a = k % fast, c = k / fast;
-        const int i = 1 + (A.ifast ? a : c), j = 1 + (A.ifast ? c : a);
-        double v = -rhs_at(i, j);
-        const int dmax = k < bw ? k : bw;
-        for (int d = 1; d <= dmax; ++d) v = fma(-A.minv[(size_t)k * W + d], y[k - d], v);
-        y[k] = v / A.minv[(size_t)k * W];
+    // separable solve (all threads of the block): sine transform along the
+    // short side, one Thomas solve per mode along the long side, inverse
+    // transform.  R (A.work) holds the p x q mode coefficients.
+    const int p = A.bw, q = N / p;
+    const double* Q = A.minv;
+    const double* fac = A.minv + (size_t)p * p;
+    const double off = -(A.ifast ? A.cy : A.cx);   // long-side coupling of -L_h
+    double* R = A.work;
+    auto node = [&](int sidx, int l, int& i, int& j) {
+        i = 1 + (A.ifast ? sidx : l);
+        j = 1 + (A.ifast ? l : sidx);
+    };
+    for (int t = threadIdx.x; t < p * q; t += blockDim.x) {
+        const int k = t / q, l = t - k * q;
+        double acc = 0.0;
+        for (int sidx = 0; sidx < p; ++sidx) {
+            int i, j;
+            node(sidx, l, i, j);
+            acc = fma(Q[(size_t)k * p + sidx], -rhs_at(i, j), acc);
+        }
+        R[t] = acc;
     }
-    for (int k = N - 1; k >= 0; --k) {
-        double v = y[k];
-        const int dmax = (N - 1 - k) < bw ? (N - 1 - k) : bw;
-        for (int d = 1; d <= dmax; ++d) v = fma(-A.minv[(size_t)(k + d) * W + d], y[k + d], v);
-        y[k] = v / A.minv[(size_t)k * W];
-        const int a = k % fast, c = k / fast;
-        const int i = 1 + (A.ifast ? a : c), j = 1 + (A.ifast ? c : a);
-        A.out[(size_t)j * A.P + i] = (T)y[k];
+    __syncthreads();
+    for (int k = threadIdx.x; k < p; k += blockDim.x) {
+        const double* cpr = fac + 2 * (size_t)k * q;
+        const double* ipv = cpr + q;
+        double* r = R + (size_t)k * q;
+        double prev = 0.0;
+        for (int l = 0; l < q; ++l) {
+            prev = fma(-off, prev, r[l]) * ipv[l];
+            r[l] = prev;
+        }
+        double x = 0.0;
+        for (int l = q - 1; l >= 0; --l) {
+            x = fma(-cpr[l], x, r[l]);
+            r[l] = x;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < p * q; t += blockDim.x) {
+        const int sidx = t / q, l = t - sidx * q;
+        double acc = 0.0;
+        for (int k = 0; k < p; ++k) acc = fma(Q[(size_t)k * p + sidx], R[(size_t)k * q + l], acc);
+        int i, j;
+        node(sidx, l, i, j);
+        A.out[(size_t)j * A.P + i] = (T)acc;
     }
 }
 

@@ -13,10 +13,13 @@ Policy (host side) over the library's tick primitive (lap_batch_step):
   into single launches; grids whose stopping rule holds leave the active set,
   their solution is read back and their hierarchy returned to the arena, so
   the next queued requests can join at the following tick;
+* when no request is waiting, a tick runs `burst` outer steps back to back
+  before reading the grids' state (a grid that converges inside the burst
+  stops on the device), trading admission delay for fewer host round trips;
 * latency of a request = time its result is readable - its arrival time.
 
 The backend is any object with footprint(m, n) -> bytes, free_bytes(),
-admit(request) -> handle, tick(handles) -> (done flags, infos), and
+admit(request) -> handle, tick(handles, steps) -> (done flags, infos), and
 retire(handle) -> result.  `DeviceBackend` drives liblap; tests drive the
 policy with a simulated backend on a virtual clock.
 """
@@ -79,10 +82,11 @@ class ServeStats:
 class Server:
     """Continuous batching with admission by footprint."""
 
-    def __init__(self, backend, max_active: int = 512, clock=time.perf_counter):
+    def __init__(self, backend, max_active: int = 512, clock=time.perf_counter, burst: int = 1):
         self.backend = backend
         self.max_active = max_active
         self.clock = clock
+        self.burst = max(1, int(burst))
         self.queue: list[Job] = []
         self.active: list[Job] = []
 
@@ -107,7 +111,8 @@ class Server:
         self._admit(self.clock())
         if not self.active:
             return []
-        done, infos = self.backend.tick([j.handle for j in self.active])
+        steps = 1 if self.queue else self.burst
+        done, infos = self.backend.tick([j.handle for j in self.active], steps)
         now = self.clock()
         finished, still = [], []
         for job, d, info in zip(self.active, done, infos):
@@ -206,8 +211,8 @@ class DeviceBackend:
         g.set_tol(job.tol)
         return g
 
-    def tick(self, grids):
-        return self.ctx.batch_step(grids, precision=self.precision)
+    def tick(self, grids, steps=1):
+        return self.ctx.batch_step(grids, precision=self.precision, steps=steps)
 
     def retire(self, g):
         out = g.read() if self.keep_results else None

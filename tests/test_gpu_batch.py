@@ -50,9 +50,11 @@ def test_batch_alone_vs_mix_bitwise(method, precision):
         g.destroy()
 
 
-def test_batch_step_ticks_match_alone():
-    """Continuous batching: grids join at different ticks and leave when done;
-    each result equals the grid solved alone."""
+@pytest.mark.parametrize("steps", [1, 3])
+def test_batch_step_ticks_match_alone(steps):
+    """Continuous batching: grids join at different ticks and leave when done
+    (ticks of `steps` outer steps: a grid converging inside a tick stops
+    there); each result equals the grid solved alone."""
     torch, lap = need_gpu()
     probs = W.ragged_batch(count=6, lo=33, hi=129, seed=7, bumps=True)
     say("ticks", [(p.m, p.n) for p in probs])
@@ -68,7 +70,7 @@ def test_batch_step_ticks_match_alone():
     while pending or active:
         if pending and tick % 2 == 0:        # a new request joins every other tick
             active.append(pending.pop(0))
-        done, infos = ctx.batch_step([gs[k] for k in active], precision="mixed")
+        done, infos = ctx.batch_step([gs[k] for k in active], precision="mixed", steps=steps)
         still = []
         for k, d, info in zip(active, done, infos):
             if d:

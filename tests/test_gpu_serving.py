@@ -11,7 +11,8 @@ from oracle import grid as ogrid
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_meet_tolerance_and_match_alone():
+@pytest.mark.parametrize("burst", [1, 3])
+def test_served_results_meet_tolerance_and_match_alone(burst):
     torch, lap = need_gpu()
     from paper_2208_02427_amd.serving import Job, Server, DeviceBackend
     reqs = W.poisson_requests(rate=400.0, count=24, seed=11, lo=17, hi=129)
@@ -20,7 +21,7 @@ def test_served_results_meet_tolerance_and_match_alone():
     ctx = lap.Context(arena_bytes=512 << 20)
     jobs = [Job(r.rid, r.arrival, r.m, r.n, r.tol,
                 payload=(to_dev(torch, p.psi0), to_dev(torch, p.f), p.dx, p.dy)) for r, p in zip(reqs, probs)]
-    stats = Server(DeviceBackend(ctx, keep_results=True), max_active=8).run(jobs)
+    stats = Server(DeviceBackend(ctx, keep_results=True), max_active=8, burst=burst).run(jobs)
     s = stats.summary()
     assert s["completed"] == len(jobs) and s["failed"] == 0
     assert stats.max_active > 1

@@ -240,11 +240,12 @@ def test_warm_start_continues():
     g2.destroy()
 
 
-@pytest.mark.parametrize("m,n", [(6, 400), (401, 8)])
-def test_banded_coarse_solve_single_level(m, n):
-    """A grid that cannot coarsen and has more than 1024 unknowns: multigrid
-    is one banded-Cholesky direct solve, equal to the exact DST solution."""
-    say("banded single level", m, n)
+@pytest.mark.parametrize("m,n", [(6, 400), (401, 8), (3, 300), (130, 67), (4, 200)])
+def test_separable_coarse_solve_single_level(m, n):
+    """A grid that cannot coarsen and has more than 256 unknowns: multigrid
+    is one separable direct solve (sine transform across the short side,
+    tridiagonal solves along the long side), equal to the exact DST solution."""
+    say("separable single level", m, n)
     psi, f, dx, dy = rand_problem(m, n, m * n, dx=0.01, dy=0.013, interior=False)
     g = make_grid(psi, f, dx, dy)
     assert g.levels() == [(m, n)]
@@ -255,9 +256,9 @@ def test_banded_coarse_solve_single_level(m, n):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_banded_coarse_in_vcycle(precision):
-    """9 x 1025 coarsens once to 5 x 513 (1533 unknowns, banded factor)."""
-    say("banded coarse vcycle", precision)
+def test_separable_coarse_in_vcycle(precision):
+    """9 x 1025 coarsens once to 5 x 513 (1533 unknowns, separable solve)."""
+    say("separable coarse vcycle", precision)
     m, n = 9, 1025
     psi, f, dx, dy = rand_problem(m, n, 77, dx=1 / 1024, dy=1 / 1024, interior=False)
     g = make_grid(psi, f, dx, dy)

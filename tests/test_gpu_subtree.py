@@ -86,14 +86,14 @@ def test_subtree_node_limit_moves_the_root():
     ctx.close()
 
 
-def test_subtree_with_banded_coarsest():
-    """Long thin grid: the FP32 V-cycle's subtree ends in the banded
-    Cholesky coarsest solve (more than 256 coarsest unknowns)."""
+def test_subtree_with_separable_coarsest():
+    """Long thin grid: the FP32 V-cycle's subtree ends in the separable
+    coarsest solve (more than 256 coarsest unknowns)."""
     torch, lap = need_gpu()
     m, n = 9, 1025
     prob = rand_problem(m, n, seed=5, dx=1.0 / 1024, dy=1.0 / 1024)
     kw = dict(precision="mixed", tol=1e-10, max_iter=40)
-    say("subtree banded", m, n)
+    say("subtree separable", m, n)
     ctx = lap.Context(arena_bytes=256 << 20)
     off = _solve(lap, torch, ctx, prob, 0, **kw)
     on = _solve(lap, torch, ctx, prob, -1, **kw)

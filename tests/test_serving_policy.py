@@ -19,12 +19,14 @@ class SimBackend:
     """Each grid needs `cycles` ticks; a tick costs base + per-grid time on
     the virtual clock; memory is a fixed pool."""
 
-    def __init__(self, clock, pool=10_000, tick_base=1e-3, per_grid=1e-4):
+    def __init__(self, clock, pool=10_000, tick_base=1e-3, per_grid=1e-4, sync=0.0):
         self.clock = clock
         self.pool = pool
         self.used = 0
         self.tick_base = tick_base
         self.per_grid = per_grid
+        self.sync = sync           # host round trip per tick
+        self.steps = []
         self.admitted = []
         self.max_used = 0
         self.batches = []
@@ -41,12 +43,13 @@ class SimBackend:
         self.admitted.append(job.rid)
         return {"job": job, "left": job.payload}
 
-    def tick(self, handles):
+    def tick(self, handles, steps=1):
         self.batches.append(len(handles))
-        self.clock.t += self.tick_base + self.per_grid * len(handles)
+        self.steps.append(steps)
+        self.clock.t += self.sync + steps * (self.tick_base + self.per_grid * len(handles))
         done = []
         for h in handles:
-            h["left"] -= 1
+            h["left"] -= steps        # a grid that converges inside the burst stops there
             done.append(h["left"] <= 0)
         return done, [{"iterations": h["job"].payload, "status": 0} for h in handles]
 
@@ -122,3 +125,28 @@ def test_summary_percentiles():
     s = st.summary()
     assert s["p50_ms"] == np.percentile(np.arange(1, 101), 50) * 1e3
     assert s["solves_per_s"] == 1.0
+
+
+def test_burst_ticks_cut_round_trips_at_low_load():
+    """With nothing waiting, a tick runs `burst` steps before the host reads
+    back: at low load latency drops by the saved round trips; every job still
+    needs exactly its own number of steps."""
+    res = {}
+    for burst in (1, 4):
+        clk = Clock()
+        be = SimBackend(clk, pool=10**9, tick_base=2e-4, per_grid=1e-5, sync=3e-4)
+        jobs = jobs_from_stream(rate=50.0, count=100)
+        stats = Server(be, clock=clk, burst=burst).run(jobs)
+        res[burst] = (stats.summary(), be.steps)
+        assert all(j.iterations == j.payload for j in jobs)
+    assert max(res[1][1]) == 1 and max(res[4][1]) == 4
+    assert res[4][0]["p50_ms"] < res[1][0]["p50_ms"]
+
+
+def test_burst_falls_back_to_single_steps_when_requests_wait():
+    clk = Clock()
+    be = SimBackend(clk, pool=70_000, tick_base=1e-3, per_grid=0.0)
+    jobs = [Job(k, 0.0, 257, 257, 1e-10, payload=5) for k in range(3)]   # one fits at a time
+    Server(be, clock=clk, burst=4).run(jobs)
+    # while others queue, ticks are single steps; the last job runs alone with bursts
+    assert be.steps[0] == 1 and be.steps[-1] == 4
