@@ -15,12 +15,23 @@
 // Expression order and divisions follow the plain definition exactly (no
 // fused multiply-add: the file is built with -ffp-contract=off).
 //
-// Columns: one thread per column line, marching j; consecutive threads own
-// consecutive lines, so every row access of a wavefront is one contiguous
-// span.  Rows: one 64-lane wavefront owns 64 row lines and moves through
-// 64-column chunks; each chunk is loaded / stored row by row (coalesced)
-// through an LDS tile in which each lane walks its own line.
+// Two solvers.  The segmented one (lines of up to 4095 unknowns along rows,
+// 1023 along columns) splits every line into short blocks solved in
+// parallel and couples them through a small reduced system (see
+// lap_kernels.hpp); it reads and writes every value once.  The sequential
+// one serves longer lines: columns, one thread per column line, marching j
+// (consecutive threads own consecutive lines, so every row access of a
+// wavefront is one contiguous span); rows, one 64-lane wavefront owns 64 row
+// lines and moves through 64-column chunks, each chunk loaded / stored row by
+// row through an LDS tile in which each lane walks its own line.  The
+// sequential solver follows the plain recurrence (divisions, no fused
+// multiply-add); the segmented one multiplies by tabulated reciprocals and
+// fuses, so the two agree to rounding.
+#include <cmath>
+#include <cstring>
+
 #include "lap_kernels.hpp"
+#include "stencil_tiles.hpp"
 
 namespace lap {
 
@@ -67,10 +78,13 @@ __global__ __launch_bounds__(kBlock) void k_adi_cols(LineArgs A) {
     adi_col_line(A, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+hipError_t launch_adi_cols_seg(const LineArgs& a, int lines, hipStream_t s);
+
 hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s) {
     const int first = a.parity ? 1 : 2;
     const int lines = a.m - 2 >= first ? (a.m - 2 - first) / 2 + 1 : 0;
     if (lines <= 0) return hipSuccess;
+    if (a.seg != nullptr && seg_fits(1, a.n - 2)) return launch_adi_cols_seg(a, lines, s);
     const int nb = (lines + kBlock - 1) / kBlock;
     k_adi_cols<<<nb, kBlock, 0, s>>>(a);
     return hipGetLastError();
@@ -163,24 +177,358 @@ __global__ __launch_bounds__(64) void k_adi_rows(LineArgs A) {
     adi_rows_block(A, blockIdx.x, tile, told);
 }
 
+hipError_t launch_adi_rows_seg(const LineArgs& a, int lines, hipStream_t s);
+
 hipError_t launch_adi_rows(const LineArgs& a, hipStream_t s) {
     const int first = a.parity ? 1 : 2;
     const int lines = a.n - 2 >= first ? (a.n - 2 - first) / 2 + 1 : 0;
     if (lines <= 0) return hipSuccess;
+    if (a.seg != nullptr && seg_fits(0, a.m - 2)) return launch_adi_rows_seg(a, lines, s);
     const int nb = (lines + kRowTile - 1) / kRowTile;
     k_adi_rows<<<nb, kRowTile, 0, s>>>(a);
     return hipGetLastError();
 }
 
-// ------------------------------------------------------- merged batch launches
-__device__ __forceinline__ int find_item(const BatchItem* it, int count, int t) {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (it[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+// --------------------------------------------------------- segmented solver
+static_assert(kSegL + 1 == 16, "block index arithmetic assumes 16 unknowns per block and separator");
+constexpr int kSegBS = kSegL + 2;   // LDS slots of a row block: kSegL unknowns, separator, separator value
+
+void adi_seg_table(double Dd, double Ed, int K, double* tab) {
+    std::memset(tab, 0, sizeof(double) * kSegTab);
+    if (K <= 0) return;
+    typedef long double R;
+    const int L = kSegL;
+    const int S = seg_count(K);
+    const int Ll = K - (S - 1) * (L + 1);
+    const R D = Dd, E = Ed;
+    R piv[kSegL], cq[kSegL];
+    piv[0] = D;
+    for (int k = 1; k < L; ++k) piv[k] = D - E * E / piv[k - 1];
+    for (int k = 0; k < L; ++k) cq[k] = E / piv[k];
+    // response of a block of length len to a unit value left of it:
+    // solve tridiag(-E, D, -E) g = E e_1
+    auto resp = [&](int len, R* g) {
+        R z = 0;
+        for (int k = 0; k < len; ++k) {
+            z = ((k == 0 ? E : (R)0) + E * z) / piv[k];
+            g[k] = z;
+        }
+        for (int k = len - 2; k >= 0; --k) g[k] = g[k] + cq[k] * g[k + 1];
+    };
+    R g[kSegL] = {}, gl[kSegL] = {};
+    resp(L, g);
+    resp(Ll, gl);
+    for (int k = 0; k < L; ++k) {
+        tab[SEG_IPIV + k] = (double)(1 / piv[k]);
+        tab[SEG_CQ + k] = (double)cq[k];
+        tab[SEG_G + k] = (double)g[k];
+        tab[SEG_GL + k] = (double)gl[k];
     }
-    return lo;
+    tab[SEG_E] = Ed;
+    // one block only, or more separators than the table holds (such lines
+    // take the sequential solver)
+    if (S < 2 || S > kSegMaxS) return;
+    // reduced system over the separators: tridiag(-E_R, D_R, -E_R), the last
+    // separator couples to the last block (or, if that is empty, to nothing)
+    const R ER = E * g[L - 1];
+    const R DR = D - 2 * E * g[0];
+    const R DRend = D - E * g[0] - (Ll > 0 ? E * gl[0] : (R)0);
+    const int NR = S - 1;
+    R pv = 0;
+    for (int p = 0; p < NR; ++p) {
+        const R dg = (p == NR - 1) ? DRend : DR;
+        pv = (p == 0) ? dg : dg - ER * ER / pv;
+        tab[SEG_IPIVR + p] = (double)(1 / pv);
+        tab[SEG_CQR + p] = (double)(ER / pv);
+    }
+    tab[SEG_E + 1] = (double)ER;
 }
+
+// Right-hand side of one unknown from its own old value, the sum of its two
+// neighbours across the line and f (end values are added by the caller).
+__device__ __forceinline__ double seg_rhs(const LineArgs& A, double cc, double own, double nb, double fv) {
+    const double base = cc * nb - fv;
+    return A.form == 0 ? base : (1.0 - A.omega) * A.d * own + A.omega * base;
+}
+
+// Forward elimination of one block given its right-hand sides r[0..len)
+// (len <= kSegL); leaves the block's zero-end solution in r, returns its
+// last value in *last.
+__device__ __forceinline__ void seg_block(const double* T, double E, int len, double (&r)[kSegL], double* last) {
+    double z = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSegL; ++k)
+        if (k < len) {
+            z = fma(E, z, r[k]) * T[SEG_IPIV + k];
+            r[k] = z;
+        }
+    double x = 0.0, e = 0.0;
+#pragma unroll
+    for (int k = kSegL - 1; k >= 0; --k)
+        if (k < len) {
+            x = fma(T[SEG_CQ + k], x, r[k]);
+            r[k] = x;
+            if (k == len - 1) e = x;
+        }
+    *last = e;
+}
+
+// Reduced system of one line: rho[p * stride], p < NR, holds the separator
+// right-hand sides on entry and the separator values on exit.
+__device__ __forceinline__ void seg_reduced(const double* T, double* rho, int stride, int NR) {
+    const double ER = T[SEG_E + 1];
+    double z = 0.0;
+    int p = 0;
+    for (; p + 4 <= NR; p += 4) {
+        const double r0 = rho[p * stride], r1 = rho[(p + 1) * stride], r2 = rho[(p + 2) * stride],
+                     r3 = rho[(p + 3) * stride];
+        z = fma(ER, z, r0) * T[SEG_IPIVR + p];
+        rho[p * stride] = z;
+        z = fma(ER, z, r1) * T[SEG_IPIVR + p + 1];
+        rho[(p + 1) * stride] = z;
+        z = fma(ER, z, r2) * T[SEG_IPIVR + p + 2];
+        rho[(p + 2) * stride] = z;
+        z = fma(ER, z, r3) * T[SEG_IPIVR + p + 3];
+        rho[(p + 3) * stride] = z;
+    }
+    for (; p < NR; ++p) {
+        z = fma(ER, z, rho[p * stride]) * T[SEG_IPIVR + p];
+        rho[p * stride] = z;
+    }
+    double x = 0.0;
+    p = NR - 1;
+    for (; p >= 3; p -= 4) {
+        const double z0 = rho[p * stride], z1 = rho[(p - 1) * stride], z2 = rho[(p - 2) * stride],
+                     z3 = rho[(p - 3) * stride];
+        x = fma(T[SEG_CQR + p], x, z0);
+        rho[p * stride] = x;
+        x = fma(T[SEG_CQR + p - 1], x, z1);
+        rho[(p - 1) * stride] = x;
+        x = fma(T[SEG_CQR + p - 2], x, z2);
+        rho[(p - 2) * stride] = x;
+        x = fma(T[SEG_CQR + p - 3], x, z3);
+        rho[(p - 3) * stride] = x;
+    }
+    for (; p >= 0; --p) {
+        x = fma(T[SEG_CQR + p], x, rho[p * stride]);
+        rho[p * stride] = x;
+    }
+}
+
+// Row lines of the parity in A, tile `tile` (W = NT / S lines), one
+// workgroup of NT threads.  The lines' right-hand sides are staged in
+// LDS row by row (coalesced); thread (line c, block s), s fastest, solves its
+// block from LDS; the solution goes back through LDS and is written row by
+// row with the relaxation.  lds: W * S * kSegBS doubles.
+template <int NT>
+static __device__ void adi_rows_seg(const LineArgs& A, int tile, double* lds) {
+    const int K = A.m - 2;
+    const int S = seg_count(K);
+    const int W = NT / S;
+    const int first = A.parity ? 1 : 2;
+    const int nlines = A.n - 2 >= first ? (A.n - 2 - first) / 2 + 1 : 0;
+    const int line0 = tile * W;
+    const int nl = min(W, nlines - line0);
+    if (nl <= 0) return;
+    const size_t P = (size_t)A.P;
+    const double* T = A.seg;
+    const double E = T[SEG_E];
+    const double cc = A.cy;
+    const int LW = S * kSegBS;
+    const int tid = threadIdx.x;
+    const int total = nl * K;
+    // element q of the tile is (line q / K, unknown q % K)
+    const float invK = 1.0f / (float)K;
+    constexpr int kU = 8;   // elements in flight per thread
+    for (int q0 = tid; q0 < total; q0 += kU * NT) {
+        double r[kU];
+        int slot[kU];
+#pragma unroll
+        for (int v = 0; v < kU; ++v) {
+            const int q = q0 + v * NT;
+            slot[v] = -1;
+            r[v] = 0.0;
+            if (q < total) {
+                const int c = seg_div(q, invK);
+                const int k = q - c * K;
+                const size_t row = (size_t)(first + 2 * (line0 + c)) * P;
+                const size_t o = row + k + 1;
+                // the line's own old value enters only with relaxation inside
+                const double own = A.form == 0 ? 0.0 : A.u[o];
+                r[v] = seg_rhs(A, cc, own, A.u[o - P] + A.u[o + P], A.f != nullptr ? A.f[o] : 0.0);
+                if (k == 0) r[v] = r[v] + E * A.u[row];
+                if (k == K - 1) r[v] = r[v] + E * A.u[row + A.m - 1];
+                slot[v] = c * LW + (k >> 4) * kSegBS + (k & 15);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < kU; ++v)
+            if (slot[v] >= 0) lds[slot[v]] = r[v];
+    }
+    __syncthreads();
+    const int c = seg_div(tid, 1.0f / (float)S);
+    const int s = tid - c * S;
+    const bool act = c < nl;
+    const int len = s < S - 1 ? kSegL : K - (S - 1) * (kSegL + 1);
+    double* blk = lds + c * LW + s * kSegBS;
+    double y[kSegL];
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < kSegL; ++k) y[k] = k < len ? blk[k] : 0.0;
+        double e;
+        seg_block(T, E, len, y, &e);
+        blk[0] = len > 0 ? y[0] : 0.0;
+        blk[1] = e;
+    }
+    __syncthreads();
+    if (act && s < S - 1) blk[kSegL + 1] = fma(E, blk[1] + blk[kSegBS], blk[kSegL]);
+    __syncthreads();
+    if (S > 1 && s == 0 && c < nl) seg_reduced(T, lds + c * LW + kSegL + 1, kSegBS, S - 1);
+    __syncthreads();
+    if (act) {
+        const double xl = s > 0 ? blk[kSegL + 1 - kSegBS] : 0.0;
+        if (s < S - 1) {
+            const double xr = blk[kSegL + 1];
+#pragma unroll
+            for (int k = 0; k < kSegL; ++k)
+                blk[k] = fma(xr, T[SEG_G + kSegL - 1 - k], fma(xl, T[SEG_G + k], y[k]));
+            blk[kSegL] = xr;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSegL; ++k)
+                if (k < len) blk[k] = fma(xl, T[SEG_GL + k], y[k]);
+        }
+    }
+    __syncthreads();
+    const double w = A.omega;
+    for (int q0 = tid; q0 < total; q0 += kU * NT) {
+        double old[kU], t[kU];
+        size_t at[kU];
+#pragma unroll
+        for (int v = 0; v < kU; ++v) {
+            const int q = q0 + v * NT;
+            at[v] = 0;
+            old[v] = t[v] = 0.0;
+            if (q < total) {
+                const int c2 = seg_div(q, invK);
+                const int k = q - c2 * K;
+                at[v] = (size_t)(first + 2 * (line0 + c2)) * P + k + 1;
+                t[v] = lds[c2 * LW + (k >> 4) * kSegBS + (k & 15)];
+                if (A.form == 0) old[v] = A.u[at[v]];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < kU; ++v)
+            if (q0 + v * NT < total) A.u[at[v]] = (A.form == 0) ? old[v] + w * (t[v] - old[v]) : t[v];
+    }
+}
+
+// Column lines of the parity in A, tile `tile` (W = NT / S lines), one
+// workgroup of NT threads; thread (line c, block s), c fastest,
+// so a wavefront's accesses to one row are contiguous.  Each thread keeps
+// its block's old values and solution in registers.  sh: 3 *
+// NT doubles (first and last block values, separator values).
+template <int NT>
+static __device__ void adi_cols_seg(const LineArgs& A, int tile, double* sh) {
+    const int K = A.n - 2;
+    const int S = seg_count(K);
+    const int W = NT / S;
+    const int first = A.parity ? 1 : 2;
+    const int nlines = A.m - 2 >= first ? (A.m - 2 - first) / 2 + 1 : 0;
+    const int line0 = tile * W;
+    const int nl = min(W, nlines - line0);
+    if (nl <= 0) return;
+    const size_t P = (size_t)A.P;
+    const double* T = A.seg;
+    const double E = T[SEG_E];
+    const double cc = A.cx;
+    const int tid = threadIdx.x;
+    const int s = seg_div(tid, 1.0f / (float)W);
+    const int c = tid - s * W;
+    const bool act = c < nl && s < S;
+    const int len = s < S - 1 ? kSegL : K - (S - 1) * (kSegL + 1);
+    const int i = first + 2 * (line0 + c);
+    const int k0 = s * (kSegL + 1);
+    double* yF = sh;
+    double* yE = sh + NT;
+    double* xs = sh + 2 * NT;
+    const int me = s * W + c;
+    double y[kSegL], old[kSegL];
+    double osep = 0.0, rsep = 0.0, e = 0.0;
+    if (act) {
+        const double* up = A.u + (size_t)(k0 + 1) * P + i;
+        const double* fp = A.f != nullptr ? A.f + (size_t)(k0 + 1) * P + i : nullptr;
+#pragma unroll
+        for (int k = 0; k < kSegL; ++k) {
+            old[k] = 0.0;
+            y[k] = 0.0;
+            if (k < len) {
+                const double* q = up + (size_t)k * P;
+                old[k] = q[0];
+                y[k] = seg_rhs(A, cc, q[0], q[-1] + q[1], fp != nullptr ? fp[(size_t)k * P] : 0.0);
+            }
+        }
+        if (s == 0) y[0] = y[0] + E * A.u[i];
+        if (len > 0 && k0 + len == K) {
+#pragma unroll
+            for (int k = 0; k < kSegL; ++k)
+                if (k == len - 1) y[k] = y[k] + E * A.u[(size_t)(A.n - 1) * P + i];
+        }
+        if (s < S - 1) {
+            const double* q = up + (size_t)kSegL * P;
+            osep = q[0];
+            rsep = seg_rhs(A, cc, q[0], q[-1] + q[1], fp != nullptr ? fp[(size_t)kSegL * P] : 0.0);
+            if (k0 + kSegL == K - 1) rsep = rsep + E * A.u[(size_t)(A.n - 1) * P + i];
+        }
+        seg_block(T, E, len, y, &e);
+        yF[me] = len > 0 ? y[0] : 0.0;
+        yE[me] = e;
+    }
+    __syncthreads();
+    if (act && s < S - 1) xs[me] = fma(E, e + yF[me + W], rsep);
+    __syncthreads();
+    if (S > 1 && s == 0 && c < nl) seg_reduced(T, xs + c, W, S - 1);
+    __syncthreads();
+    if (act) {
+        const double w = A.omega;
+        const double xl = s > 0 ? xs[me - W] : 0.0;
+        double* up = A.u + (size_t)(k0 + 1) * P + i;
+        if (s < S - 1) {
+            const double xr = xs[me];
+#pragma unroll
+            for (int k = 0; k < kSegL; ++k) {
+                const double t = fma(xr, T[SEG_G + kSegL - 1 - k], fma(xl, T[SEG_G + k], y[k]));
+                up[(size_t)k * P] = (A.form == 0) ? old[k] + w * (t - old[k]) : t;
+            }
+            up[(size_t)kSegL * P] = (A.form == 0) ? osep + w * (xr - osep) : xr;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSegL; ++k)
+                if (k < len) {
+                    const double t = fma(xl, T[SEG_GL + k], y[k]);
+                    up[(size_t)k * P] = (A.form == 0) ? old[k] + w * (t - old[k]) : t;
+                }
+        }
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_adi_rows_seg(LineArgs A, int ntiles) {
+    if (A.ctrl != nullptr && A.ctrl->done) return;
+    __shared__ double lds[NT * kSegBS];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t < ntiles) adi_rows_seg<NT>(A, t, lds);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_adi_cols_seg(LineArgs A, int ntiles) {
+    if (A.ctrl != nullptr && A.ctrl->done) return;
+    __shared__ double sh[3 * NT];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t < ntiles) adi_cols_seg<NT>(A, t, sh);
+}
+
+// ------------------------------------------------------- merged batch launches
 
 __device__ __forceinline__ LineArgs line_args(const BatchItem& it) {
     LineArgs a{};
@@ -200,36 +548,98 @@ __device__ __forceinline__ LineArgs line_args(const BatchItem& it) {
     a.a_off = it.a_off;
     a.form = it.flags;
     a.parity = it.parity;
+    a.seg = it.seg;
     return a;
 }
 
 // Row lines of all grids: one 64-lane block per 64-line block of a grid,
 // the grid loops over all (grid, line block) tiles.
-__global__ __launch_bounds__(64) void k_batch_adi_rows(const BatchItem* items, int count, int total) {
+__global__ __launch_bounds__(64) void k_batch_adi_rows(const BatchItem* items, const int* tmap, int total) {
     __shared__ double tile[kRowTile][kRowTile + 1];
     __shared__ double told[kRowTile][kRowTile + 1];
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const BatchItem& it = items[find_item(items, count, t)];
+        const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
         adi_rows_block(line_args(it), t - it.tile0, tile, told);
     }
 }
 
 // Column lines of all grids: one thread per line, 256 lines per tile.
-__global__ __launch_bounds__(kBlock) void k_batch_adi_cols(const BatchItem* items, int count, int total) {
+__global__ __launch_bounds__(kBlock) void k_batch_adi_cols(const BatchItem* items, const int* tmap, int total) {
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const BatchItem& it = items[find_item(items, count, t)];
+        const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
         adi_col_line(line_args(it), (t - it.tile0) * kBlock + threadIdx.x);
     }
 }
 
-hipError_t launch_batch_adi(int kind, const BatchItem* items, int count, int total, int blocks, hipStream_t s) {
-    if (total <= 0 || count <= 0) return hipSuccess;
-    if (kind == BK_ADI_ROWS)
-        k_batch_adi_rows<<<blocks, kRowTile, 0, s>>>(items, count, total);
+// Segmented solver over all grids: tiles of seg_lines lines of one grid,
+// dealt XCD-contiguously (neighbouring tiles share boundary lines).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_adi_rows_seg(const BatchItem* items, const int* tmap, int total) {
+    __shared__ double lds[NT * kSegBS];
+    for (int t = xcd_remap(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
+        const BatchItem& it = items[tmap[t]];
+        if (it.ctrl->done) continue;
+        adi_rows_seg<NT>(line_args(it), t - it.tile0, lds);
+        __syncthreads();
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_adi_cols_seg(const BatchItem* items, const int* tmap, int total) {
+    __shared__ double sh[3 * NT];
+    for (int t = xcd_remap(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
+        const BatchItem& it = items[tmap[t]];
+        if (it.ctrl->done) continue;
+        adi_cols_seg<NT>(line_args(it), t - it.tile0, sh);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_adi_rows_seg(const LineArgs& a, int lines, hipStream_t s) {
+    const int W = seg_lines(0, a.m - 2);
+    const int nt = (lines + W - 1) / W;
+    if (seg_code(0, a.m - 2) == 1)
+        k_adi_rows_seg<256><<<xcd_pad(nt), 256, 0, s>>>(a, nt);
     else
-        k_batch_adi_cols<<<blocks, kBlock, 0, s>>>(items, count, total);
+        k_adi_rows_seg<128><<<xcd_pad(nt), 128, 0, s>>>(a, nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_adi_cols_seg(const LineArgs& a, int lines, hipStream_t s) {
+    const int W = seg_lines(1, a.n - 2);
+    const int nt = (lines + W - 1) / W;
+    if (seg_code(1, a.n - 2) == 0)
+        k_adi_cols_seg<256><<<xcd_pad(nt), 256, 0, s>>>(a, nt);
+    else
+        k_adi_cols_seg<1024><<<xcd_pad(nt), 1024, 0, s>>>(a, nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_adi(int kind, int flags, const BatchItem* items, const int* tmap, int total, int blocks,
+                            hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    if (flags & ADI_SEG) {
+        blocks = xcd_pad(blocks);
+        const int code = (flags >> ADI_CODE_SHIFT) & 3;
+        if (kind == BK_ADI_ROWS) {
+            if (code == 1)
+                k_batch_adi_rows_seg<256><<<blocks, 256, 0, s>>>(items, tmap, total);
+            else
+                k_batch_adi_rows_seg<128><<<blocks, 128, 0, s>>>(items, tmap, total);
+        } else {
+            if (code == 0)
+                k_batch_adi_cols_seg<256><<<blocks, 256, 0, s>>>(items, tmap, total);
+            else
+                k_batch_adi_cols_seg<1024><<<blocks, 1024, 0, s>>>(items, tmap, total);
+        }
+        return hipGetLastError();
+    }
+    if (kind == BK_ADI_ROWS)
+        k_batch_adi_rows<<<blocks, kRowTile, 0, s>>>(items, tmap, total);
+    else
+        k_batch_adi_cols<<<blocks, kBlock, 0, s>>>(items, tmap, total);
     return hipGetLastError();
 }
 

@@ -6,14 +6,6 @@
 
 namespace lap {
 
-__device__ __forceinline__ int find_fused_item(const BatchItem* it, int count, int t) {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (it[mid].tile0 <= t) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 template <typename T, int FLS>
 __device__ __forceinline__ void batch_fused_tile(const BatchItem& it, int lt, int lane) {
@@ -51,11 +43,11 @@ __device__ __forceinline__ void batch_fused_tile(const BatchItem& it, int lt, in
 }
 
 template <typename T, int FLS>
-__global__ __launch_bounds__(kBlock) void k_batch_fused(const BatchItem* items, int count, int total) {
+__global__ __launch_bounds__(kBlock) void k_batch_fused(const BatchItem* items, const int* tmap, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
     for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (int)(threadIdx.x >> 6); t < total; t += nw) {
-        const BatchItem& it = items[find_fused_item(items, count, t)];
+        const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
         batch_fused_tile<T, FLS>(it, t - it.tile0, lane);
     }
@@ -68,13 +60,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(const BatchItem* items, 
     X(SW_RESTRICT | SW_TWO | SW_ZERO) X(SW_RESTRICT | SW_TWO | SW_NORM)
 
 template <typename T>
-static hipError_t launch_batch_fused_t(int fl, const BatchItem* items, int count, int total, int blocks,
+static hipError_t launch_batch_fused_t(int fl, const BatchItem* items, const int* tmap, int total, int blocks,
                                        hipStream_t s) {
     const dim3 g(blocks), b(kBlock);
     switch (fl) {
 #define LAP_CASE(F)                                                    \
     case (F):                                                          \
-        k_batch_fused<T, (F)><<<g, b, 0, s>>>(items, count, total);    \
+        k_batch_fused<T, (F)><<<g, b, 0, s>>>(items, tmap, total);     \
         break;
         LAP_BATCH_FUSED_FLAGS(LAP_CASE)
 #undef LAP_CASE
@@ -83,12 +75,12 @@ static hipError_t launch_batch_fused_t(int fl, const BatchItem* items, int count
     return hipGetLastError();
 }
 
-hipError_t launch_batch_fused(int dt, int step_flags, const BatchItem* items, int count, int total, int blocks,
+hipError_t launch_batch_fused(int dt, int step_flags, const BatchItem* items, const int* tmap, int total, int blocks,
                               hipStream_t s) {
-    if (count <= 0) return hipSuccess;
+    if (total <= 0) return hipSuccess;
     if (blocks < 1) blocks = 1;
-    return dt == 0 ? launch_batch_fused_t<double>(step_flags, items, count, total, blocks, s)
-                   : launch_batch_fused_t<float>(step_flags, items, count, total, blocks, s);
+    return dt == 0 ? launch_batch_fused_t<double>(step_flags, items, tmap, total, blocks, s)
+                   : launch_batch_fused_t<float>(step_flags, items, tmap, total, blocks, s);
 }
 
 }  // namespace lap

@@ -10,14 +10,6 @@
 
 namespace lap {
 
-__device__ __forceinline__ int find_item(const BatchItem* it, int count, int t) {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (it[mid].tile0 <= t) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 __device__ __forceinline__ Tiling item_tiling(const BatchItem& it) {
     Tiling t;
@@ -60,22 +52,22 @@ __device__ __forceinline__ void batch_sweep_tile(const BatchItem& it, int lt, in
 }
 
 template <typename T, int FLS>
-__global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchItem* items, int count, int total) {
+__global__ __launch_bounds__(kBlock) void k_batch_sweep(const BatchItem* items, const int* tmap, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
     for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block(); t < total; t += nw) {
-        const BatchItem& it = items[find_item(items, count, t)];
+        const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
         batch_sweep_tile<T, FLS>(it, t - it.tile0, lane);
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_batch_restrict(const BatchItem* items, int count, int total) {
+__global__ __launch_bounds__(kBlock) void k_batch_restrict(const BatchItem* items, const int* tmap, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
     for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block(); t < total; t += nw) {
-        const BatchItem& it = items[find_item(items, count, t)];
+        const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
         RestrictArgs<T> A{};
         A.u = (const T*)it.in;
@@ -101,11 +93,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_restrict(const BatchItem* item
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_resnorm(const BatchItem* items, int count, int total) {
+__global__ __launch_bounds__(kBlock) void k_batch_resnorm(const BatchItem* items, const int* tmap, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
     for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block(); t < total; t += nw) {
-        const BatchItem& it = items[find_item(items, count, t)];
+        const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
         ResidualArgs<double> A{};
         A.u = (const double*)it.in;
@@ -128,11 +120,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_resnorm(const BatchItem* items
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_defect(const BatchItem* items, int count, int total) {
+__global__ __launch_bounds__(kBlock) void k_batch_defect(const BatchItem* items, const int* tmap, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
     for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block(); t < total; t += nw) {
-        const BatchItem& it = items[find_item(items, count, t)];
+        const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
         DefectArgs A{};
         A.psi_in = (const double*)it.in;
@@ -194,27 +186,29 @@ __global__ __launch_bounds__(kFinBlock) void k_batch_finalize(const BatchItem* i
 }
 
 template <typename T>
-static hipError_t launch_batch_t(int kind, int fl, const BatchItem* items, int count, int total, int blocks,
+static hipError_t launch_batch_t(int kind, int fl, const BatchItem* items, const int* tmap, int count, int total,
+                                 int blocks,
                                  hipStream_t s) {
     const dim3 g(blocks), b(kBlock);
     switch (kind) {
         case BK_SWEEP:
             switch (fl) {
-                case 0: k_batch_sweep<T, 0><<<g, b, 0, s>>>(items, count, total); break;
-                case SW_ZERO: k_batch_sweep<T, SW_ZERO><<<g, b, 0, s>>>(items, count, total); break;
-                case SW_PROLONG: k_batch_sweep<T, SW_PROLONG><<<g, b, 0, s>>>(items, count, total); break;
-                case SW_NORM: k_batch_sweep<T, SW_NORM><<<g, b, 0, s>>>(items, count, total); break;
+                case 0: k_batch_sweep<T, 0><<<g, b, 0, s>>>(items, tmap, total); break;
+                case SW_ZERO: k_batch_sweep<T, SW_ZERO><<<g, b, 0, s>>>(items, tmap, total); break;
+                case SW_PROLONG: k_batch_sweep<T, SW_PROLONG><<<g, b, 0, s>>>(items, tmap, total); break;
+                case SW_NORM: k_batch_sweep<T, SW_NORM><<<g, b, 0, s>>>(items, tmap, total); break;
                 default: return hipErrorInvalidValue;
             }
             break;
-        case BK_RESTRICT: k_batch_restrict<T><<<g, b, 0, s>>>(items, count, total); break;
+        case BK_RESTRICT: k_batch_restrict<T><<<g, b, 0, s>>>(items, tmap, total); break;
         case BK_COARSE: k_batch_coarse<T><<<g, b, 0, s>>>(items, count); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items, int count, int total, int blocks,
+hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items, const int* tmap, int count, int total,
+                        int blocks,
                         hipStream_t s) {
     if (count <= 0) return hipSuccess;
     if (blocks < 1) blocks = 1;
@@ -222,13 +216,13 @@ hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items
         case BK_SWEEP:
         case BK_RESTRICT:
         case BK_COARSE:
-            return dt == 0 ? launch_batch_t<double>(kind, step_flags, items, count, total, blocks, s)
-                           : launch_batch_t<float>(kind, step_flags, items, count, total, blocks, s);
+            return dt == 0 ? launch_batch_t<double>(kind, step_flags, items, tmap, count, total, blocks, s)
+                           : launch_batch_t<float>(kind, step_flags, items, tmap, count, total, blocks, s);
         case BK_FINALIZE: k_batch_finalize<<<blocks, kFinBlock, 0, s>>>(items, count); break;
-        case BK_RESNORM: k_batch_resnorm<<<blocks, kBlock, 0, s>>>(items, count, total); break;
-        case BK_DEFECT: k_batch_defect<<<blocks, kBlock, 0, s>>>(items, count, total); break;
+        case BK_RESNORM: k_batch_resnorm<<<blocks, kBlock, 0, s>>>(items, tmap, total); break;
+        case BK_DEFECT: k_batch_defect<<<blocks, kBlock, 0, s>>>(items, tmap, total); break;
         case BK_ADI_ROWS:
-        case BK_ADI_COLS: return launch_batch_adi(kind, items, count, total, blocks, s);
+        case BK_ADI_COLS: return launch_batch_adi(kind, step_flags, items, tmap, total, blocks, s);
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

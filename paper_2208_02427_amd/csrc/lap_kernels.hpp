@@ -89,10 +89,8 @@ inline Tiling norm_tiling(int m, int n, int kind = NORM_PASS) {
 
 // Blocks of 4 waves; the grid is padded to a multiple of the XCD count so
 // the XCD-aware remap below is a bijection.
-inline int blocks_for(const Tiling& t) {
-    int nb = (t.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    return ((nb + kXcds - 1) / kXcds) * kXcds;
-}
+inline int xcd_pad(int nb) { return ((nb + kXcds - 1) / kXcds) * kXcds; }
+inline int blocks_for(const Tiling& t) { return xcd_pad((t.ntiles + kWavesPerBlock - 1) / kWavesPerBlock); }
 
 // Kernel-side control block of one solve (device memory).
 struct Ctrl {
@@ -248,6 +246,9 @@ hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, doubl
                            hipStream_t s);
 // Reset a control block for a new solve (stream-ordered, graph-safe).
 hipError_t launch_ctrl_init(Ctrl* ctrl, double tol, int stop, int max_iter, int step, hipStream_t s);
+// The same for `count` control blocks (device array of pointers).
+hipError_t launch_ctrl_init_many(Ctrl* const* ctrls, int count, double tol, int stop, int max_iter, int step,
+                                 hipStream_t s);
 // Gather the control blocks of a batch of grids into one array.
 hipError_t launch_gather_ctrl(Ctrl* const* src, Ctrl* dst, int count, hipStream_t s);
 // Streaming copy of `bytes` (a multiple of 16) with `blocks` workgroups.
@@ -271,10 +272,58 @@ struct LineArgs {
     double a_off;            // off-diagonal of the line matrix (-cx or -w cx, rows; -cy.. cols)
     int form;                // 0 relax after, 1 relax inside
     int parity;              // 1: odd lines, 0: even lines
+    const double* seg;       // segment table of this direction (adi_seg_table), or NULL
 };
-constexpr int kRowTile = 64;   // row lines per ADI row block
+constexpr int kRowTile = 64;   // row lines per ADI row block (sequential solver)
 hipError_t launch_adi_rows(const LineArgs& a, hipStream_t s);
 hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s);
+
+// Segmented line solver.  A line of K unknowns is cut into S blocks of
+// kSegL unknowns, each followed by one separator unknown (the last block
+// holds the remaining 0..kSegL).  Every block is solved on its own with zero
+// end values (one thread per block, values kept in registers); the block
+// solutions enter a reduced tridiagonal system over the S-1 separators,
+// solved per line; each block then adds the responses to its two separator
+// values.  The line matrix is constant along the line, so the block factors,
+// the response vectors and the reduced system's factors depend only on
+// (K, d, E) and are tabulated once per solve on the host.
+constexpr int kSegL = 15;
+constexpr int kSegMaxS = 256;
+constexpr int kSegColMaxS = 64;        // columns: S <= 64 (rows: S <= kSegMaxS)
+// table layout (doubles)
+constexpr int SEG_IPIV = 0;                       // 1/pivot_k of a block, k < kSegL
+constexpr int SEG_CQ = kSegL;                     // E/pivot_k
+constexpr int SEG_G = 2 * kSegL;                  // response of a full block to a unit left value
+constexpr int SEG_GL = 3 * kSegL;                 // the same for the last block
+constexpr int SEG_IPIVR = 4 * kSegL;              // reduced system: 1/pivot_p
+constexpr int SEG_CQR = 4 * kSegL + kSegMaxS;     // reduced system: E_R/pivot_p
+constexpr int SEG_E = 4 * kSegL + 2 * kSegMaxS;   // E, E_R
+constexpr int kSegTab = SEG_E + 2;
+__host__ __device__ constexpr int seg_count(int K) { return K <= 0 ? 0 : (K + kSegL + 1) / (kSegL + 1); }
+// Workgroup sizes: rows stage their lines in LDS (8.5 bytes per unknown), so
+// small workgroups keep several resident per CU; columns keep 8 or more
+// lines per workgroup so a wavefront's row accesses stay contiguous.
+// Size code c of a line length: rows use 128 << c threads (c = 0, 1),
+// columns 256 << c (c = 0 for lines of at most 4 blocks, else 2: 1024
+// threads, 16 or more lines per workgroup).
+__host__ __device__ constexpr int seg_code(int dir, int K) {
+    return dir == 0 ? (seg_count(K) <= 128 ? 0 : 1) : (seg_count(K) <= 4 ? 0 : 2);
+}
+__host__ __device__ constexpr int seg_threads(int dir, int code) { return (dir == 0 ? 128 : 256) << code; }
+// lines per workgroup of the segmented kernels (one thread per block of a line)
+__host__ __device__ constexpr int seg_lines(int dir, int K) {
+    return seg_threads(dir, seg_code(dir, K)) / seg_count(K);
+}
+// q / d for 0 <= q < 2^20, 1 <= d <= 2^12, through single precision: the
+// quotient's fractional part is at least 0.5 / d away from an integer, far
+// above the rounding error
+__device__ __forceinline__ int seg_div(int q, float inv_d) { return (int)(((float)q + 0.5f) * inv_d); }
+__host__ __device__ constexpr bool seg_fits(int dir, int K) {
+    return K >= 1 && seg_count(K) <= (dir == 0 ? kSegMaxS : kSegColMaxS);
+}
+// Tabulate the segmented solve of the line matrix tridiag(-E, D, -E) of
+// order K (host, extended precision).
+void adi_seg_table(double D, double E, int K, double* tab);
 
 // Coarsest levels with at most this many unknowns use a dense inverse (all
 // lanes in parallel); larger ones (long thin grids) a separable solve: sine
@@ -298,6 +347,7 @@ struct BatchItem {
     double* scratch;         // ADI
     const double* cprime;
     const double* piv;
+    const double* seg;       // ADI segment table (NULL: sequential solver)
     int m, n, P, mc, nc, Pc;
     double cx, cy, d, inv_d, omega, a_off;
     int V, ty, nwin, nchunk, H;
@@ -310,12 +360,18 @@ struct BatchItem {
 enum BatchKind { BK_SWEEP = 0, BK_RESTRICT, BK_COARSE, BK_FINALIZE, BK_RESNORM, BK_DEFECT, BK_ADI_ROWS, BK_ADI_COLS,
                  BK_SUBTREE, BK_FUSED };
 // Launch one merged operation over `count` items (device array) covering
-// `total` tiles with a persistent grid of `blocks` workgroups.
-hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items, int count, int total, int blocks,
-                        hipStream_t s);
-hipError_t launch_batch_adi(int kind, const BatchItem* items, int count, int total, int blocks, hipStream_t s);
+// `total` tiles with a persistent grid of `blocks` workgroups; tmap[t] is the
+// item of tile t (kinds with tiles; one workgroup per item otherwise).
+hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items, const int* tmap, int count,
+                        int total, int blocks, hipStream_t s);
+// ADI lines of all items; flags ADI_SEG: the segmented solver (every item
+// has a segment table and fits it), else the sequential one.
+constexpr int ADI_SEG = 2;
+constexpr int ADI_CODE_SHIFT = 2;   // segmented: size code (seg_code) in bits 2..3
+hipError_t launch_batch_adi(int kind, int flags, const BatchItem* items, const int* tmap, int total, int blocks,
+                            hipStream_t s);
 // merged fused passes (fused_kernels.hip); step_flags without SW_F
-hipError_t launch_batch_fused(int dt, int step_flags, const BatchItem* items, int count, int total, int blocks,
-                              hipStream_t s);
+hipError_t launch_batch_fused(int dt, int step_flags, const BatchItem* items, const int* tmap, int total,
+                              int blocks, hipStream_t s);
 
 }  // namespace lap

@@ -408,9 +408,13 @@ struct lap_grid {
     double* coarse_work = nullptr;   // separable solve scratch
     int coarse_bw = 0, coarse_ifast = 1;
     double* adi_scratch = nullptr;
-    double* adi_tab = nullptr;       // rows cprime, rows piv, cols cprime, cols piv (each maxK)
+    double* adi_tab = nullptr;       // rows cprime, rows piv, cols cprime, cols piv (each maxK), then
+                                     // the rows and the columns segment tables (kSegTab each)
     int adi_maxk = 0;
     std::vector<double> adi_host;
+    double adi_omega = -1.0;         // (omega, form) the uploaded tables were made for
+    int adi_form = -1;
+    bool psi1_stale = false;         // psi[1]'s interior lags psi[0] (after ADI, which works in place)
     Ctrl* ctrl = nullptr;
     double* partials = nullptr;
     int max_partials = 0;
@@ -989,6 +993,19 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int
 }
 
 // ------------------------------------------------------------------ ADI
+// Algorithmic bytes of one zebra half (all lines of one parity) per interior
+// node of the grid: half the nodes are updated, each reading its own old
+// value and f and writing the new one, and the other half are read once as
+// the neighbours across the lines (FP64).
+double adi_bytes_per_node(bool with_f) { return 0.5 * (8.0 + 8.0 + 8.0 + (with_f ? 8.0 : 0.0)); }
+
+// Which line solver (and workgroup size) a half of lines of length K takes;
+// merged launches group operations by these flags.
+int adi_kernel_flags(int dir, int K) {
+    if (!seg_fits(dir, K)) return 0;
+    return ADI_SEG | (seg_code(dir, K) << ADI_CODE_SHIFT);
+}
+
 void adi_factor(double b, double a, double c, int K, double* cp, double* piv) {
     if (K <= 0) return;
     cp[0] = c / b;
@@ -1015,23 +1032,24 @@ LineArgs adi_args(lap_grid* g, double omega, int form, int dir, int parity) {
     a.cy = c.cy;
     a.d = c.d;
     a.omega = omega;
-    a.form = form;
+    a.form = form & 1;
     a.parity = parity;
+    a.seg = g->adi_tab + 4 * mk + dir * kSegTab;
     if (dir == 0) {
         a.cprime = g->adi_tab;
         a.piv = g->adi_tab + mk;
-        a.a_off = form == 0 ? -c.cx : -omega * c.cx;
+        a.a_off = (form & 1) == 0 ? -c.cx : -omega * c.cx;
     } else {
         a.cprime = g->adi_tab + 2 * mk;
         a.piv = g->adi_tab + 3 * mk;
-        a.a_off = form == 0 ? -c.cy : -omega * c.cy;
+        a.a_off = (form & 1) == 0 ? -c.cy : -omega * c.cy;
     }
     return a;
 }
 
 hipError_t enq_adi_half(lap_grid* g, double omega, int form, int dir, int parity) {
     const LineArgs a = adi_args(g, omega, form, dir, parity);
-    const double per = (g->f64 ? 48.0 : 40.0) * 0.5 * nint(g->geo[0]);
+    const double per = adi_bytes_per_node(g->f64 != nullptr) * nint(g->geo[0]);
     if (dir == 0)
         return g->ctx->timed(KC_ADI_ROWS, true, per, [&]() { return launch_adi_rows(a, g->ctx->stream); });
     return g->ctx->timed(KC_ADI_COLS, true, per, [&]() { return launch_adi_cols(a, g->ctx->stream); });
@@ -1217,13 +1235,26 @@ bool use_graph(lap_grid* g, const lap_opts& o) {
     return o.use_graph && g->ctx->stream != nullptr && !g->ctx->timing && o.method == LAP_MG;
 }
 
-lap_status prepare(lap_grid* g, const lap_opts& o) {
-    const int step = (o.method == LAP_MG) ? 1 : o.check_every;
-    lap_status st = init_ctrl(g, o, step);
-    if (st != LAP_OK) return st;
+int ctrl_step(const lap_opts& o) { return (o.method == LAP_MG) ? 1 : o.check_every; }
+
+// Per-solve set-up of one grid; init = false leaves the control block to the
+// caller (a batch resets all of them in one launch).
+lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
+    if (init) {
+        lap_status st = init_ctrl(g, o, ctrl_step(o));
+        if (st != LAP_OK) return st;
+    }
     g->step_idx = 0;
     g->e_idx = vcycle_result_index(g->ctx, o);
-    if (o.method == LAP_ADI) {
+    // the two-buffer methods need both buffers equal when they start
+    if (g->psi1_stale && o.method != LAP_ADI) {
+        HIPCHK(hipMemcpyAsync(g->psi[1], g->psi[0], (size_t)g->n * g->P * 8, hipMemcpyDeviceToDevice,
+                              g->ctx->stream));
+        g->psi1_stale = false;
+    }
+    if (o.method == LAP_ADI && (g->adi_omega != o.omega || g->adi_form != o.adi_form)) {
+        g->adi_omega = o.omega;
+        g->adi_form = o.adi_form;
         const Coef c = coef(g->dx, g->dy);
         const int mk = g->adi_maxk;
         g->adi_host.assign((size_t)4 * mk, 0.0);
@@ -1231,7 +1262,10 @@ lap_status prepare(lap_grid* g, const lap_opts& o) {
         const double wy = o.adi_form == 0 ? c.cy : o.omega * c.cy;
         adi_factor(c.d, -wx, -wx, g->m - 2, g->adi_host.data(), g->adi_host.data() + mk);
         adi_factor(c.d, -wy, -wy, g->n - 2, g->adi_host.data() + 2 * mk, g->adi_host.data() + 3 * mk);
-        HIPCHK(hipMemcpyAsync(g->adi_tab, g->adi_host.data(), (size_t)4 * mk * 8, hipMemcpyHostToDevice,
+        g->adi_host.resize((size_t)4 * mk + 2 * kSegTab);
+        adi_seg_table(c.d, wx, g->m - 2, g->adi_host.data() + 4 * mk);
+        adi_seg_table(c.d, wy, g->n - 2, g->adi_host.data() + 4 * mk + kSegTab);
+        HIPCHK(hipMemcpyAsync(g->adi_tab, g->adi_host.data(), g->adi_host.size() * 8, hipMemcpyHostToDevice,
                               g->ctx->stream));
     }
     if (use_graph(g, o)) {
@@ -1305,7 +1339,8 @@ void plan_step(lap_grid* g, const lap_opts& o, int s, int part, std::vector<Op>&
             if (part != PART_HEAD)
                 for (int k = 0; k < o.check_every; ++k)
                     for (int q = 0; q < 4; ++q)
-                        push_op<double>(ops, 1000 + 4L * k + q, q < 2 ? OP_ADI_ROWS : OP_ADI_COLS, 0, o.adi_form,
+                        push_op<double>(ops, 1000 + 4L * k + q, q < 2 ? OP_ADI_ROWS : OP_ADI_COLS, 0,
+                                        o.adi_form | adi_kernel_flags(q < 2 ? 0 : 1, q < 2 ? g->m - 2 : g->n - 2),
                                         nullptr, nullptr, nullptr, nullptr, nullptr, o.omega, (q % 2) ? 0 : 1);
             return;
     }
@@ -1338,7 +1373,7 @@ lap_status fixup(lap_grid* g, const lap_opts& o, const Ctrl& h) {
     if (o.method == LAP_SOR_RB) where = ((h.checks - 1) % 2) * ((int)sor_passes(c, o.check_every).size() % 2);
     if (o.method == LAP_MG && o.precision == LAP_MIXED) where = h.checks % 2;
     if (where == 1) HIPCHK(hipMemcpyAsync(g->psi[0], g->psi[1], bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (o.method == LAP_ADI) HIPCHK(hipMemcpyAsync(g->psi[1], g->psi[0], bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (o.method == LAP_ADI) g->psi1_stale = true;   // copied when a two-buffer method next starts
     return LAP_OK;
 }
 
@@ -1593,7 +1628,7 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
     if (flags & LAP_ALLOC_ADI) {
         g->adi_scratch = (double*)A(f0 * 8);
         g->adi_maxk = std::max(m, n);
-        g->adi_tab = (double*)A((size_t)4 * g->adi_maxk * 8);
+        g->adi_tab = (double*)A(((size_t)4 * g->adi_maxk + 2 * kSegTab) * 8);
     }
     g->ctrl = (Ctrl*)A(sizeof(Ctrl));
     g->max_partials = (int)max_tiles(m, n);
@@ -1657,6 +1692,7 @@ lap_status lap_grid_write(lap_grid* g, const double* src) {
     if (!g) return fail(LAP_EINVAL, "grid is NULL");
     if (!src) return fail(LAP_EINVAL, "src is NULL");
     HIPCHK(launch_write_field(src, g->psi[0], g->psi[1], g->m, g->n, g->P, g->ctx->stream));
+    g->psi1_stale = false;
     g->batch_started = false;
     return LAP_OK;
 }
@@ -1803,7 +1839,8 @@ extern "C" lap_status lap_op_rb_sweep(int32_t dtype, int32_t m, int32_t n, int32
 extern "C" size_t lap_op_work_bytes(int32_t m, int32_t n) {
     if (m < 3 || n < 3) return 0;
     const size_t part = round_up((size_t)make_tiling(m, n, 1, 16).ntiles * 16, kAlign);
-    const size_t line = round_up((size_t)n * pitch_of(m) * 8, kAlign) + round_up((size_t)2 * std::max(m, n) * 8, kAlign);
+    const size_t line = round_up((size_t)n * pitch_of(m) * 8, kAlign) +
+                        round_up(((size_t)2 * std::max(m, n) + kSegTab) * 8, kAlign);
     return std::max(part, line);
 }
 
@@ -1891,9 +1928,10 @@ extern "C" lap_status lap_op_adi_half(int32_t dtype, int32_t m, int32_t n, int32
     if (form == 1 && omega >= 1.0 + (dir == 0 ? c.cy / c.cx : c.cx / c.cy))
         return fail(LAP_EINVAL, "relaxation inside the line system needs omega < 1 + beta^2");
     const int K = dir == 0 ? m - 2 : n - 2;
-    std::vector<double> tab(2 * (size_t)K);
+    std::vector<double> tab(2 * (size_t)K + kSegTab);
     const double wl = form == 0 ? cl : omega * cl;
     adi_factor(c.d, -wl, -wl, K, tab.data(), tab.data() + K);
+    adi_seg_table(c.d, wl, K, tab.data() + 2 * (size_t)K);
     // tables live at the end of the work buffer
     char* wbase = (char*)work;
     double* scratch = (double*)wbase;
@@ -1907,6 +1945,7 @@ extern "C" lap_status lap_op_adi_half(int32_t dtype, int32_t m, int32_t n, int32
     a.scratch = scratch;
     a.cprime = dtab;
     a.piv = dtab + K;
+    a.seg = dtab + 2 * (size_t)K;
     a.m = m;
     a.n = n;
     a.P = ld;
@@ -1931,6 +1970,7 @@ struct MergedLaunch {
     int count, total, blocks;
     int lds;                 // subtree: dynamic LDS bytes (largest item)
     size_t off;              // first item in the plan's item array
+    size_t toff;             // first entry in the plan's tile map
     double bytes;            // algorithmic bytes of the launch
 };
 
@@ -1939,7 +1979,9 @@ struct lap_ctx::Plan {
     std::vector<BatchItem> items;
     std::vector<unsigned char> subs;                 // SubtreeArgs of subtree items
     std::vector<std::pair<size_t, size_t>> sub_of;   // (item, byte offset in subs)
+    std::vector<int32_t> tmap;                       // item (within its launch) of every tile
     BatchItem* dev = nullptr;
+    const int32_t* tmap_dev = nullptr;
     hipGraphExec_t graph = nullptr;
     int uses = 0;
 };
@@ -2042,13 +2084,15 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, bool many) {
             it.scratch = la.scratch;
             it.cprime = la.cprime;
             it.piv = la.piv;
+            it.seg = la.seg;
             it.a_off = la.a_off;
-            it.flags = op.flags;
+            it.flags = op.flags & 1;
             it.parity = op.parity;
             const int first = op.parity ? 1 : 2;
             const int span = op.kind == OP_ADI_ROWS ? L.n - 2 : L.m - 2;
             const int lines = span >= first ? (span - first) / 2 + 1 : 0;
-            const int per = op.kind == OP_ADI_ROWS ? kRowTile : kBlock;
+            int per = op.kind == OP_ADI_ROWS ? kRowTile : kBlock;
+            if (op.flags & ADI_SEG) per = op.kind == OP_ADI_ROWS ? seg_lines(0, L.m - 2) : seg_lines(1, L.n - 2);
             t.ntiles = (lines + per - 1) / per;
             break;
         }
@@ -2080,7 +2124,7 @@ double item_bytes(const Op& op, const BatchItem& it) {
         case OP_RESNORM: return (op.f ? 16.0 : 8.0) * n;
         case OP_DEFECT: return (8.0 + (op.ec ? 4.0 : 0.0) + (op.f ? 8.0 : 0.0) + 12.0) * n;
         case OP_ADI_ROWS:
-        case OP_ADI_COLS: return (op.f ? 48.0 : 40.0) * 0.5 * n;
+        case OP_ADI_COLS: return adi_bytes_per_node(op.f != nullptr) * n;
         case OP_SUBTREE: return 2.0 * sz * (double)it.m * (double)it.n;
         default: return 0.0;
     }
@@ -2149,6 +2193,7 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
             L.dt = std::get<1>(skv.first);
             L.flags = std::get<2>(skv.first);
             L.off = p->items.size();
+            L.toff = p->tmap.size();
             L.cls = kclass_of(skv.second[0].second);
             L.fine = skv.second[0].second.level == 0;
             int tile0 = 0;
@@ -2175,7 +2220,10 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
                     L.lds = std::max(L.lds, lds);
                     p->sub_of.push_back({p->items.size(), off});
                 }
-                if (L.kind != BK_COARSE && L.kind != BK_FINALIZE && L.kind != BK_SUBTREE) tile0 += it.ntiles;
+                if (L.kind != BK_COARSE && L.kind != BK_FINALIZE && L.kind != BK_SUBTREE) {
+                    p->tmap.insert(p->tmap.end(), (size_t)it.ntiles, (int32_t)(p->items.size() - L.off));
+                    tile0 += it.ntiles;
+                }
                 L.bytes += item_bytes(go.second, it);
                 p->items.push_back(it);
             }
@@ -2186,7 +2234,7 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
             } else if (L.kind == BK_COARSE || L.kind == BK_FINALIZE) {
                 L.blocks = std::min(L.count, 2048);
             } else if (L.kind == BK_ADI_ROWS || L.kind == BK_ADI_COLS) {
-                L.blocks = std::max(1, std::min(L.total, 4096));
+                L.blocks = std::max(1, L.total);   // one workgroup per line tile
             } else {
                 int nb = (L.total + kWavesPerBlock - 1) / kWavesPerBlock;
                 nb = std::min(nb, 2 * c->wave_cap / kWavesPerBlock);
@@ -2196,17 +2244,21 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
         }
     }
     const size_t ibytes = round_up(p->items.size() * sizeof(BatchItem), kAlign);
-    p->dev = (BatchItem*)c->arena.alloc(ibytes + p->subs.size());
+    const size_t sbytes = round_up(p->subs.size(), kAlign);
+    p->dev = (BatchItem*)c->arena.alloc(ibytes + sbytes + p->tmap.size() * sizeof(int32_t));
     if (!p->dev) {
         delete p;
         return fail(LAP_ENOMEM, "arena cannot hold the batch plan");
     }
     unsigned char* sub_dev = (unsigned char*)p->dev + ibytes;
+    p->tmap_dev = (const int32_t*)(sub_dev + sbytes);
     for (const auto& so : p->sub_of) p->items[so.first].sub = sub_dev + so.second;
     if (hipMemcpyAsync(p->dev, p->items.data(), p->items.size() * sizeof(BatchItem), hipMemcpyHostToDevice,
                        c->stream) != hipSuccess ||
         (!p->subs.empty() &&
-         hipMemcpyAsync(sub_dev, p->subs.data(), p->subs.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess)) {
+         hipMemcpyAsync(sub_dev, p->subs.data(), p->subs.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+        (!p->tmap.empty() && hipMemcpyAsync((void*)p->tmap_dev, p->tmap.data(), p->tmap.size() * sizeof(int32_t),
+                                            hipMemcpyHostToDevice, c->stream) != hipSuccess)) {
         plan_free(c, p);
         return fail(LAP_EHIP, "plan upload failed");
     }
@@ -2221,13 +2273,26 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
 }
 
 hipError_t run_plan_launches(lap_ctx* c, lap_ctx::Plan* p) {
-    for (const MergedLaunch& L : p->launches)
+    // launches up to and including the first norm finalisation are the
+    // step's stopping test (its head)
+    size_t fin = p->launches.size();
+    for (size_t k = 0; k < p->launches.size(); ++k)
+        if (p->launches[k].kind == BK_FINALIZE) {
+            fin = k;
+            break;
+        }
+    for (size_t k = 0; k < p->launches.size(); ++k) {
+        const MergedLaunch& L = p->launches[k];
+        c->rec_head = k <= fin && fin < p->launches.size();
         HIPERR(c->timed(L.cls, L.fine, L.bytes, [&]() {
             if (L.kind == BK_SUBTREE) return launch_batch_subtree(L.dt, p->dev + L.off, L.count, L.lds, c->stream);
+            const int32_t* tm = p->tmap_dev + L.toff;
             if (L.kind == BK_FUSED)
-                return launch_batch_fused(L.dt, L.flags, p->dev + L.off, L.count, L.total, L.blocks, c->stream);
-            return launch_batch(L.kind, L.dt, L.flags, p->dev + L.off, L.count, L.total, L.blocks, c->stream);
+                return launch_batch_fused(L.dt, L.flags, p->dev + L.off, tm, L.total, L.blocks, c->stream);
+            return launch_batch(L.kind, L.dt, L.flags, p->dev + L.off, tm, L.count, L.total, L.blocks, c->stream);
         }));
+    }
+    c->rec_head = false;
     return hipSuccess;
 }
 
@@ -2303,8 +2368,17 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
     lap_opts po = *o;
     po.use_graph = 0;   // per-grid graphs are not used; the merged plans have their own
     for (int k = 0; k < count; ++k) {
-        lap_status st = prepare(grids[k], po);
+        lap_status st = prepare(grids[k], po, false);
         if (st != LAP_OK) return st;
+    }
+    if (count > 0) {   // all control blocks reset in one launch
+        lap_status st = batch_reserve(c, count);
+        if (st != LAP_OK) return st;
+        c->batch_ptrs_host.resize(count);
+        for (int k = 0; k < count; ++k) c->batch_ptrs_host[k] = grids[k]->ctrl;
+        HIPCHK(hipMemcpyAsync(c->batch_ptrs, c->batch_ptrs_host.data(), (size_t)count * sizeof(Ctrl*),
+                              hipMemcpyHostToDevice, c->stream));
+        HIPCHK(launch_ctrl_init_many(c->batch_ptrs, count, o->tol, o->stop, o->max_iter, ctrl_step(*o), c->stream));
     }
     // every grid stays in the plan until all are done (a finished grid's
     // tiles exit at its control block), so the plans and graphs are reused
@@ -2314,8 +2388,16 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
     std::vector<Ctrl> hs;
     std::map<lap_grid*, Ctrl> final_ctrl;
     const int rounds = max_steps(*o) + 1;
+    // kernel timing: each round is a step of one timed solve; the launches of
+    // the round whose stopping tests ended the last grids (after its head)
+    // exited at once and are dropped from the statistics
+    c->rec_solve = c->timing ? c->solve_serial++ : -1;
+    c->safe_step = 0;
+    int last_round = -1;
     for (int r = 0; r < rounds && !active.empty(); ++r) {
         lap_ctx::Plan* p = nullptr;
+        c->rec_step = r;
+        last_round = r;
         for (int k = 0; k < count; ++k) steps[k] = r;
         lap_status st = get_plan(c, all, steps, *o, &p);
         if (st != LAP_OK) return st;
@@ -2332,7 +2414,10 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
                 next.push_back(active[k]);
         }
         active.swap(next);
+        if (!active.empty()) c->safe_step = r + 1;
     }
+    if (c->timing && active.empty() && last_round >= 0) c->drop_speculative(c->rec_solve, last_round);
+    c->rec_solve = -1;
     lap_status worst = LAP_OK;
     for (int k = 0; k < count; ++k) {
         lap_grid* g = grids[k];

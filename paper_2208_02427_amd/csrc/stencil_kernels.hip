@@ -172,6 +172,24 @@ hipError_t launch_ctrl_init(Ctrl* ctrl, double tol, int stop, int max_iter, int 
     return hipGetLastError();
 }
 
+__global__ void k_ctrl_init_many(Ctrl* const* ctrls, int count, double tol, int stop, int max_iter, int step) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    Ctrl c{};
+    c.tol = tol;
+    c.stop = stop;
+    c.max_iter = max_iter;
+    c.step = step;
+    *ctrls[k] = c;
+}
+
+hipError_t launch_ctrl_init_many(Ctrl* const* ctrls, int count, double tol, int stop, int max_iter, int step,
+                                 hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_ctrl_init_many<<<(count + 255) / 256, 256, 0, s>>>(ctrls, count, tol, stop, max_iter, step);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, double* out2, int mode,
                            hipStream_t s) {
     k_finalize<<<1, kFinBlock, 0, s>>>(partials, ntiles, ctrl, out2, mode);

@@ -90,3 +90,25 @@ def test_batch_step_ticks_match_alone(steps):
         assert alone["iterations"] == info["iterations"]
         assert np.array_equal(g.read().cpu().numpy(), u), k
         g.destroy()
+
+
+def test_batch_timing_counts_only_full_work_launches():
+    """Kernel statistics of a batched solve leave out the launches of the
+    round whose stopping tests ended the last grids (they exit at once),
+    apart from that round's test itself: check blocks of 3 ADI iterations,
+    6 iterations -> 3 tests, 2 row and 2 column launches per iteration
+    (grids of 81..129 points a side take one merged launch per line half)."""
+    torch, lap = need_gpu()
+    from paper_2208_02427_amd._native import KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL
+    probs = W.ragged_batch(count=6, lo=81, hi=129, seed=5)
+    say("batch timing", [(p.m, p.n) for p in probs])
+    ctx = lap.Context(arena_bytes=1 << 30)
+    gs = _grids(ctx, probs, torch)
+    ctx.set_timing(1)
+    nit = 6
+    infos = ctx.solve_batch(gs, method="adi", omega=1.0, tol=0.0, max_iter=nit, check_every=3)
+    assert all(i["iterations"] == nit for i in infos)
+    assert ctx.kernel_stats(KC_ADI_ROWS)["launches"] == 2 * nit
+    assert ctx.kernel_stats(KC_ADI_COLS)["launches"] == 2 * nit
+    assert ctx.kernel_stats(KC_RESIDUAL)["launches"] == nit // 3 + 1
+    ctx.close()

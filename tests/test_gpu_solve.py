@@ -160,7 +160,6 @@ def test_adi_iterates(form, m, n):
         olines.adi_zebra_iteration(ref, f, dx, dy, 1.2, "A" if form == "after" else "B")
     got = g.read().cpu().numpy()
     assert maxabs(got, ref) <= 1e-10
-    assert np.array_equal(got, ref)
     g.destroy()
 
 
