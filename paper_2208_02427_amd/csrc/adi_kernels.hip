@@ -273,46 +273,62 @@ __device__ __forceinline__ void seg_block(const double* T, double E, int len, do
     *last = e;
 }
 
-// Reduced system of one line: rho[p * stride], p < NR, holds the separator
-// right-hand sides on entry and the separator values on exit.
-__device__ __forceinline__ void seg_reduced(const double* T, double* rho, int stride, int NR) {
-    const double ER = T[SEG_E + 1];
-    double z = 0.0;
-    int p = 0;
-    for (; p + 4 <= NR; p += 4) {
-        const double r0 = rho[p * stride], r1 = rho[(p + 1) * stride], r2 = rho[(p + 2) * stride],
-                     r3 = rho[(p + 3) * stride];
-        z = fma(ER, z, r0) * T[SEG_IPIVR + p];
-        rho[p * stride] = z;
-        z = fma(ER, z, r1) * T[SEG_IPIVR + p + 1];
-        rho[(p + 1) * stride] = z;
-        z = fma(ER, z, r2) * T[SEG_IPIVR + p + 2];
-        rho[(p + 2) * stride] = z;
-        z = fma(ER, z, r3) * T[SEG_IPIVR + p + 3];
-        rho[(p + 3) * stride] = z;
+// Reduced system of one line, its unknown p held by one thread (act; NR
+// and the loop trip counts are uniform over the workgroup, every thread
+// reaches every barrier).  The forward elimination z_p = (rho_p + E_R
+// z_{p-1}) / pivot_p and the back substitution x_p = z_p + (E_R / pivot_p)
+// x_{p+1} are first-order linear recurrences: each is evaluated as a
+// Hillis-Steele scan of affine maps in ceil(log2 NR) steps through two LDS
+// buffer pairs (a0, b0), (a1, b1) addressed by slot(p).  Returns x_p.
+template <typename Slot>
+__device__ __forceinline__ double seg_scan(const double* T, int NR, int p, bool act, double rho, Slot slot,
+                                           double* a0, double* b0, double* a1, double* b1) {
+    double a = 0.0, b = 0.0;
+    if (act) {
+        const double ip = T[SEG_IPIVR + p];
+        a = p > 0 ? T[SEG_E + 1] * ip : 0.0;
+        b = rho * ip;
+        a0[slot(p)] = a;
+        b0[slot(p)] = b;
     }
-    for (; p < NR; ++p) {
-        z = fma(ER, z, rho[p * stride]) * T[SEG_IPIVR + p];
-        rho[p * stride] = z;
+    __syncthreads();
+    double *ra = a0, *rb = b0, *wa = a1, *wb = b1;
+    for (int h = 1; h < NR; h <<= 1) {
+        if (act) {
+            if (p >= h) {
+                const int q = slot(p - h);
+                b = fma(a, rb[q], b);
+                a = a * ra[q];
+            }
+            wa[slot(p)] = a;
+            wb[slot(p)] = b;
+        }
+        __syncthreads();
+        double* t = ra; ra = wa; wa = t;
+        t = rb; rb = wb; wb = t;
     }
-    double x = 0.0;
-    p = NR - 1;
-    for (; p >= 3; p -= 4) {
-        const double z0 = rho[p * stride], z1 = rho[(p - 1) * stride], z2 = rho[(p - 2) * stride],
-                     z3 = rho[(p - 3) * stride];
-        x = fma(T[SEG_CQR + p], x, z0);
-        rho[p * stride] = x;
-        x = fma(T[SEG_CQR + p - 1], x, z1);
-        rho[(p - 1) * stride] = x;
-        x = fma(T[SEG_CQR + p - 2], x, z2);
-        rho[(p - 2) * stride] = x;
-        x = fma(T[SEG_CQR + p - 3], x, z3);
-        rho[(p - 3) * stride] = x;
+    // b = z_p; now x_p = c_p x_{p+1} + z_p, scanned from the end
+    double c = (act && p < NR - 1) ? T[SEG_CQR + p] : 0.0;
+    if (act) {
+        ra[slot(p)] = c;
+        rb[slot(p)] = b;
     }
-    for (; p >= 0; --p) {
-        x = fma(T[SEG_CQR + p], x, rho[p * stride]);
-        rho[p * stride] = x;
+    __syncthreads();
+    for (int h = 1; h < NR; h <<= 1) {
+        if (act) {
+            if (p + h < NR) {
+                const int q = slot(p + h);
+                b = fma(c, rb[q], b);
+                c = c * ra[q];
+            }
+            wa[slot(p)] = c;
+            wb[slot(p)] = b;
+        }
+        __syncthreads();
+        double* t = ra; ra = wa; wa = t;
+        t = rb; rb = wb; wb = t;
     }
+    return b;
 }
 
 // Row lines of the parity in A, tile `tile` (W = NT / S lines), one
@@ -381,10 +397,16 @@ static __device__ void adi_rows_seg(const LineArgs& A, int tile, double* lds) {
         blk[1] = e;
     }
     __syncthreads();
-    if (act && s < S - 1) blk[kSegL + 1] = fma(E, blk[1] + blk[kSegBS], blk[kSegL]);
-    __syncthreads();
-    if (S > 1 && s == 0 && c < nl) seg_reduced(T, lds + c * LW + kSegL + 1, kSegBS, S - 1);
-    __syncthreads();
+    if (S > 1) {
+        // slots 2..5 of each block are free now (its unknowns live in y)
+        const bool sep = act && s < S - 1;
+        const double rho = sep ? fma(E, blk[1] + blk[kSegBS], blk[kSegL]) : 0.0;
+        double* lb = lds + c * LW;
+        const auto slot = [](int p) { return p * kSegBS; };
+        const double x = seg_scan(T, S - 1, s, sep, rho, slot, lb + 2, lb + 3, lb + 4, lb + 5);
+        if (sep) blk[kSegL + 1] = x;
+        __syncthreads();
+    }
     if (act) {
         const double xl = s > 0 ? blk[kSegL + 1 - kSegBS] : 0.0;
         if (s < S - 1) {
@@ -426,8 +448,8 @@ static __device__ void adi_rows_seg(const LineArgs& A, int tile, double* lds) {
 // Column lines of the parity in A, tile `tile` (W = NT / S lines), one
 // workgroup of NT threads; thread (line c, block s), c fastest,
 // so a wavefront's accesses to one row are contiguous.  Each thread keeps
-// its block's old values and solution in registers.  sh: 3 *
-// NT doubles (first and last block values, separator values).
+// its block's old values and solution in registers.  sh: 5 * NT doubles
+// (first and last block values, separator values, scan buffers).
 template <int NT>
 static __device__ void adi_cols_seg(const LineArgs& A, int tile, double* sh) {
     const int K = A.n - 2;
@@ -485,10 +507,15 @@ static __device__ void adi_cols_seg(const LineArgs& A, int tile, double* sh) {
         yE[me] = e;
     }
     __syncthreads();
-    if (act && s < S - 1) xs[me] = fma(E, e + yF[me + W], rsep);
-    __syncthreads();
-    if (S > 1 && s == 0 && c < nl) seg_reduced(T, xs + c, W, S - 1);
-    __syncthreads();
+    if (S > 1) {
+        const bool sep = act && s < S - 1;
+        const double rho = sep ? fma(E, e + yF[me + W], rsep) : 0.0;
+        const auto slot = [W, c](int p) { return p * W + c; };
+        const double x = seg_scan(T, S - 1, s, sep, rho, slot, yE, xs, sh + 3 * NT, sh + 4 * NT);
+        // yF is read above until every thread has passed the scan's first barrier
+        if (sep) xs[me] = x;
+        __syncthreads();
+    }
     if (act) {
         const double w = A.omega;
         const double xl = s > 0 ? xs[me - W] : 0.0;
@@ -523,7 +550,7 @@ __global__ __launch_bounds__(NT) void k_adi_rows_seg(LineArgs A, int ntiles) {
 template <int NT>
 __global__ __launch_bounds__(NT) void k_adi_cols_seg(LineArgs A, int ntiles) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
-    __shared__ double sh[3 * NT];
+    __shared__ double sh[5 * NT];
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     if (t < ntiles) adi_cols_seg<NT>(A, t, sh);
 }
@@ -588,7 +615,7 @@ __global__ __launch_bounds__(NT) void k_batch_adi_rows_seg(const BatchItem* item
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_batch_adi_cols_seg(const BatchItem* items, const int* tmap, int total) {
-    __shared__ double sh[3 * NT];
+    __shared__ double sh[5 * NT];
     for (int t = xcd_remap(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
         const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
