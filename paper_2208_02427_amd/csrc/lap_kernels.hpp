@@ -289,7 +289,7 @@ hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s);
 // (K, d, E) and are tabulated once per solve on the host.
 constexpr int kSegL = 15;
 constexpr int kSegMaxS = 256;
-constexpr int kSegColMaxS = 64;        // columns: S <= 64 (rows: S <= kSegMaxS)
+constexpr int kSegColMaxS = 256;       // columns: S <= 256 as rows (4 or more lines per workgroup)
 // table layout (doubles)
 constexpr int SEG_IPIV = 0;                       // 1/pivot_k of a block, k < kSegL
 constexpr int SEG_CQ = kSegL;                     // E/pivot_k
@@ -305,7 +305,7 @@ __host__ __device__ constexpr int seg_count(int K) { return K <= 0 ? 0 : (K + kS
 // lines per workgroup so a wavefront's row accesses stay contiguous.
 // Size code c of a line length: rows use 128 << c threads (c = 0, 1),
 // columns 256 << c (c = 0 for lines of at most 4 blocks, else 2: 1024
-// threads, 16 or more lines per workgroup).
+// threads, 4 or more lines per workgroup).
 __host__ __device__ constexpr int seg_code(int dir, int K) {
     return dir == 0 ? (seg_count(K) <= 128 ? 0 : 1) : (seg_count(K) <= 4 ? 0 : 2);
 }

@@ -114,17 +114,17 @@ def test_restrict(m, n, dtype):
 
 def _seg_fits(direction, K):
     """Whether the library solves these lines with the segmented solver
-    (blocks of 15 unknowns + separators; at most 256 blocks along rows, 64
-    along columns); longer lines use the sequential recurrence."""
+    (blocks of 15 unknowns + separators, at most 256 blocks); longer lines
+    use the sequential recurrence."""
     S = 0 if K <= 0 else (K + 16) // 16
-    return K >= 1 and S <= (256 if direction == 0 else 64)
+    return K >= 1 and S <= 256
 
 
 # sizes: tiny; one block (K = 15); a separator as the last unknown (K = 16,
-# 32); several blocks with ragged tails; the longest lines of the segmented
-# solver (K = 1023 along columns); lines past it (sequential solver)
+# 32); several blocks with ragged tails; long lines (K = 1023, 1024, 4095);
+# lines past the segmented solver (sequential solver)
 @pytest.mark.parametrize("m,n", [(3, 3), (4, 7), (17, 18), (18, 34), (35, 19), (25, 17), (66, 35), (200, 131),
-                                 (131, 260), (1025, 24), (24, 1025), (9, 1026), (4200, 5)])
+                                 (131, 260), (1025, 24), (24, 1025), (9, 1026), (6, 4097), (4200, 5), (5, 4200)])
 @pytest.mark.parametrize("direction", [0, 1])
 @pytest.mark.parametrize("form", [0, 1])
 def test_adi_half(m, n, direction, form):
