@@ -255,6 +255,13 @@ hipError_t launch_gather_ctrl(Ctrl* const* src, Ctrl* dst, int count, hipStream_
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int blocks, hipStream_t s);
 // Dense m x n FP64 field (row pitch m) into pitched fields d0 and (if not NULL) d1.
 hipError_t launch_write_field(const double* src, double* d0, double* d1, int m, int n, int P, hipStream_t s);
+// Copies of whole buffers (16-byte vectors), one launch for all of them.
+struct CopyItem {
+    const double2* src;
+    double2* dst;
+    size_t nvec;
+};
+hipError_t launch_copy_many(const CopyItem* items, int count, hipStream_t s);
 // Copy interior of src into dst (FP64 fields of the same layout).
 hipError_t launch_copy(const double* src, double* dst, int m, int n, int P, const Ctrl* ctrl,
                        hipStream_t s);

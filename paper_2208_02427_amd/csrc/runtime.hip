@@ -308,8 +308,10 @@ struct lap_ctx {
     int batch_cap = 0;
     Ctrl** batch_ptrs = nullptr;
     Ctrl* batch_ctrl = nullptr;
-    Ctrl* batch_host = nullptr;
+    Ctrl* batch_host = nullptr;      // pinned, 2 * batch_cap (two rounds in flight)
+    CopyItem* copy_dev = nullptr;    // batch_cap end-of-solve buffer copies
     std::vector<Ctrl*> batch_ptrs_host;
+    std::vector<CopyItem> copy_host;
     // merged-launch plans of batches, by composition key (grid set, step parity, options)
     struct Plan;
     std::vector<std::pair<std::string, Plan*>> plans;
@@ -1365,14 +1367,19 @@ hipError_t step(lap_grid* g, const lap_opts& o, int part = PART_ALL) {
     return exec_ops(g, ops);
 }
 
+// The buffer holding the tested iterate (the solution) at the end of a solve.
+int result_buffer(lap_grid* g, const lap_opts& o, const Ctrl& h) {
+    if (o.method == LAP_SOR_RB) return ((h.checks - 1) % 2) * ((int)sor_passes(g->ctx, o.check_every).size() % 2);
+    if (o.method == LAP_MG && o.precision == LAP_MIXED) return h.checks % 2;
+    return 0;
+}
+
 // The tested iterate is the solution; bring it to psi[0] and make psi[1] equal.
 lap_status fixup(lap_grid* g, const lap_opts& o, const Ctrl& h) {
     lap_ctx* c = g->ctx;
     const size_t bytes = (size_t)g->n * g->P * 8;
-    int where = 0;
-    if (o.method == LAP_SOR_RB) where = ((h.checks - 1) % 2) * ((int)sor_passes(c, o.check_every).size() % 2);
-    if (o.method == LAP_MG && o.precision == LAP_MIXED) where = h.checks % 2;
-    if (where == 1) HIPCHK(hipMemcpyAsync(g->psi[0], g->psi[1], bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (result_buffer(g, o, h) == 1)
+        HIPCHK(hipMemcpyAsync(g->psi[0], g->psi[1], bytes, hipMemcpyDeviceToDevice, c->stream));
     if (o.method == LAP_ADI) g->psi1_stale = true;   // copied when a two-buffer method next starts
     return LAP_OK;
 }
@@ -2028,7 +2035,7 @@ int batch_kind(const Op& op) {
     return -1;
 }
 
-constexpr int kBatchMinRows = 32;
+constexpr int kBatchMinRows = 64;
 constexpr size_t kBatchManyGrids = 4;
 
 // Fill the item of grid g for operation op (tiling, geometry, coefficients).
@@ -2103,7 +2110,7 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, bool many) {
     // one grid's small level; inside a merged launch over many grids the
     // launch is throughput-bound and a chunk's halo rows (up to 11 for a
     // fused pass) would dominate, so plans of several grids use chunks of
-    // >= 32 rows.
+    // >= 64 rows (the measured best for ragged batches of 33..1025 points a side).
     if (many && (op.kind == OP_SWEEP || op.kind == OP_RESTRICT) && !(op.flags & SW_NORM) && t.ty < kBatchMinRows)
         t = make_tiling(L.m, L.n, t.V, kBatchMinRows, 0, t.H);
     it.V = t.V;
@@ -2320,15 +2327,18 @@ hipError_t run_plan(lap_ctx* c, lap_ctx::Plan* p, bool graph) {
 lap_status batch_reserve(lap_ctx* c, int count) {
     if (count <= c->batch_cap) return LAP_OK;
     int cap = std::max(count, 2 * c->batch_cap);
+    hipStreamSynchronize(c->stream);   // the old tables may still be in use by queued work
     if (c->batch_ptrs) c->arena.release(c->batch_ptrs);
     if (c->batch_ctrl) c->arena.release(c->batch_ctrl);
+    if (c->copy_dev) c->arena.release(c->copy_dev);
     if (c->batch_host) hipHostFree(c->batch_host);
     c->batch_ptrs = (Ctrl**)c->arena.alloc((size_t)cap * sizeof(Ctrl*));
     c->batch_ctrl = (Ctrl*)c->arena.alloc((size_t)cap * sizeof(Ctrl));
+    c->copy_dev = (CopyItem*)c->arena.alloc((size_t)cap * sizeof(CopyItem));
     c->batch_host = nullptr;
     c->batch_cap = 0;
-    if (!c->batch_ptrs || !c->batch_ctrl) return fail(LAP_ENOMEM, "arena cannot hold the batch tables");
-    HIPCHK(hipHostMalloc((void**)&c->batch_host, (size_t)cap * sizeof(Ctrl), hipHostMallocDefault));
+    if (!c->batch_ptrs || !c->batch_ctrl || !c->copy_dev) return fail(LAP_ENOMEM, "arena cannot hold the batch tables");
+    HIPCHK(hipHostMalloc((void**)&c->batch_host, (size_t)2 * cap * sizeof(Ctrl), hipHostMallocDefault));
     c->batch_cap = cap;
     return LAP_OK;
 }
@@ -2381,52 +2391,79 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
         HIPCHK(launch_ctrl_init_many(c->batch_ptrs, count, o->tol, o->stop, o->max_iter, ctrl_step(*o), c->stream));
     }
     // every grid stays in the plan until all are done (a finished grid's
-    // tiles exit at its control block), so the plans and graphs are reused
+    // tiles exit at its control block), so the plans and graphs are reused.
+    // Rounds are enqueued one ahead: after enqueueing round r the host reads
+    // the control blocks as they stood after round r-1 (gathered into pinned
+    // memory behind it), so the device never waits for the host.
     std::vector<lap_grid*> all(grids, grids + count);
-    std::vector<lap_grid*> active = all;
     std::vector<int> steps(count, 0);
-    std::vector<Ctrl> hs;
-    std::map<lap_grid*, Ctrl> final_ctrl;
+    std::vector<char> known(count, 0);
+    std::vector<Ctrl> final_ctrl(count);
+    int remaining = count;
     const int rounds = max_steps(*o) + 1;
-    // kernel timing: each round is a step of one timed solve; the launches of
-    // the round whose stopping tests ended the last grids (after its head)
-    // exited at once and are dropped from the statistics
+    // kernel timing: each round is a step of one timed solve; the launches
+    // after the stopping tests that ended the last grids exited at once and
+    // are dropped from the statistics
     c->rec_solve = c->timing ? c->solve_serial++ : -1;
     c->safe_step = 0;
-    int last_round = -1;
-    for (int r = 0; r < rounds && !active.empty(); ++r) {
+    int decided = -1;   // the round after which every grid was done
+    auto absorb = [&](int r) -> lap_status {
+        HIPCHK(hipEventSynchronize(c->poll_ev[r & 1]));
+        const Ctrl* hs = c->batch_host + (size_t)(r & 1) * c->batch_cap;
+        for (int k = 0; k < count; ++k)
+            if (!known[k]) {
+                final_ctrl[k] = hs[k];   // the last state seen, final once done
+                if (hs[k].done) {
+                    known[k] = 1;
+                    --remaining;
+                }
+            }
+        if (remaining == 0 && decided < 0) decided = r;
+        if (remaining > 0) c->safe_step = r + 1;
+        return LAP_OK;
+    };
+    int r = 0;
+    for (; r < rounds && remaining > 0 && decided < 0; ++r) {
         lap_ctx::Plan* p = nullptr;
         c->rec_step = r;
-        last_round = r;
         for (int k = 0; k < count; ++k) steps[k] = r;
         lap_status st = get_plan(c, all, steps, *o, &p);
         if (st != LAP_OK) return st;
         hipError_t e = run_plan(c, p, o->use_graph != 0);
         if (e != hipSuccess) return fail(LAP_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
         for (lap_grid* g : all) g->step_idx = r + 1;
-        st = batch_read(c, active, hs);
-        if (st != LAP_OK) return st;
-        std::vector<lap_grid*> next;
-        for (size_t k = 0; k < active.size(); ++k) {
-            if (hs[k].done)
-                final_ctrl[active[k]] = hs[k];
-            else
-                next.push_back(active[k]);
+        HIPCHK(launch_gather_ctrl(c->batch_ptrs, c->batch_ctrl, count, c->stream));
+        HIPCHK(hipMemcpyAsync(c->batch_host + (size_t)(r & 1) * c->batch_cap, c->batch_ctrl,
+                              (size_t)count * sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipEventRecord(c->poll_ev[r & 1], c->stream));
+        if (r >= 1) {
+            st = absorb(r - 1);
+            if (st != LAP_OK) return st;
         }
-        active.swap(next);
-        if (!active.empty()) c->safe_step = r + 1;
     }
-    if (c->timing && active.empty() && last_round >= 0) c->drop_speculative(c->rec_solve, last_round);
+    if (r >= 1 && decided < 0) {
+        lap_status st = absorb(r - 1);
+        if (st != LAP_OK) return st;
+    }
+    if (c->timing && decided >= 0) c->drop_speculative(c->rec_solve, decided);
     c->rec_solve = -1;
-    lap_status worst = LAP_OK;
+    // results that ended in the second buffer come back in one launch
+    c->copy_host.clear();
     for (int k = 0; k < count; ++k) {
         lap_grid* g = grids[k];
-        Ctrl h{};
-        auto it = final_ctrl.find(g);
-        if (it != final_ctrl.end()) h = it->second;
-        lap_status st = fixup(g, *o, h);
-        if (st != LAP_OK) return st;
-        st = finish(g, *o, h, t0, infos ? &infos[k] : nullptr);
+        const Ctrl& h = final_ctrl[k];
+        if (result_buffer(g, *o, h) == 1)
+            c->copy_host.push_back({(const double2*)g->psi[1], (double2*)g->psi[0], (size_t)g->n * g->P / 2});
+        if (o->method == LAP_ADI) g->psi1_stale = true;
+    }
+    if (!c->copy_host.empty()) {
+        HIPCHK(hipMemcpyAsync(c->copy_dev, c->copy_host.data(), c->copy_host.size() * sizeof(CopyItem),
+                              hipMemcpyHostToDevice, c->stream));
+        HIPCHK(launch_copy_many(c->copy_dev, (int)c->copy_host.size(), c->stream));
+    }
+    lap_status worst = LAP_OK;
+    for (int k = 0; k < count; ++k) {
+        lap_status st = finish(grids[k], *o, final_ctrl[k], t0, infos ? &infos[k] : nullptr);
         if (st != LAP_OK && worst == LAP_OK) worst = st;
     }
     HIPCHK(hipStreamSynchronize(c->stream));

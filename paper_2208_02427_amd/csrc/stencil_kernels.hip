@@ -263,6 +263,19 @@ hipError_t launch_copy(const double* src, double* dst, int m, int n, int P, cons
     return hipGetLastError();
 }
 
+// Item blockIdx.y, its vectors strided over blockIdx.x.
+__global__ __launch_bounds__(kBlock) void k_copy_many(const CopyItem* items) {
+    const CopyItem it = items[blockIdx.y];
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < it.nvec; k += (size_t)gridDim.x * blockDim.x)
+        it.dst[k] = it.src[k];
+}
+
+hipError_t launch_copy_many(const CopyItem* items, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_copy_many<<<dim3(64, count), kBlock, 0, s>>>(items);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------- small-level subtree
 // Dynamic LDS: the levels' u and b (T), then the coarsest right-hand side
 // (double) at the next 8-byte boundary.
