@@ -95,22 +95,7 @@ def run_gpu(args):
     out["autotune"] = tune
 
     if args.copy_probe:
-        # achievable HBM bandwidth: plain copy of 1 GiB, several grid sizes
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        best = {}
-        for blocks in (1024, 2048, 4096, 8192):
-            lap.op_stream_copy(src, dst, blocks=blocks)
-            sync()
-            t0 = time.perf_counter()
-            for _ in range(10):
-                lap.op_stream_copy(src, dst, blocks=blocks)
-            sync()
-            t = (time.perf_counter() - t0) / 10
-            best[blocks] = 2 * (1 << 30) / t / 1e9
-        out["copy_probe"] = {"bytes_per_launch": 2 * (1 << 30), "GB/s_by_blocks": best,
-                             "best_GB/s": max(best.values())}
-        del src, dst
+        out["copy_probe"] = run_copy_probe(torch, lap, dev)
 
     # ---------------------------------------------------------------- headline
     p = W.square_problem(N, seed=2)
@@ -274,6 +259,25 @@ def device_request(torch, req, dev):
     return torch.as_tensor(psi0, device=dev), f, h, h
 
 
+def run_copy_probe(torch, lap, dev):
+    """Achievable HBM bandwidth: plain copy of 1 GiB with several grid sizes
+    (also the calibration kernel of the byte counters)."""
+    src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    best = {}
+    for blocks in (1024, 2048, 4096, 8192):
+        lap.op_stream_copy(src, dst, blocks=blocks)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            lap.op_stream_copy(src, dst, blocks=blocks)
+        sync()
+        t = (time.perf_counter() - t0) / 10
+        best[blocks] = 2 * (1 << 30) / t / 1e9
+    del src, dst
+    return {"bytes_per_launch": 2 * (1 << 30), "GB/s_by_blocks": best, "best_GB/s": max(best.values())}
+
+
 def run_batch_leg(args, ctx, torch, lap, dev):
     """Ragged batch: 512 grids, m, n log-uniform in [33, 1025] (snapped to
     c*2^k+1), aspect <= 3, beta in [0.5, 2], U[0,1) boundary, f = 0."""
@@ -322,7 +326,12 @@ def run_batch_leg(args, ctx, torch, lap, dev):
     ctx.solve_batch(grids, method="adi", omega=1.0, tol=0.0, max_iter=nit, check_every=nit)
     sync()
     ta = time.perf_counter() - t0
-    out["adi"] = {"iterations": nit, "seconds": ta, "line_updates_G/s": 2 * nit * nodes / ta / 1e9}
+    # algorithmic bytes: each of the four line launches of an iteration (rows,
+    # columns; two parities each) reads its lines' old values and the other
+    # parity's lines once and writes its lines (f = 0): 12 B per grid node and
+    # launch, 48 B per node and iteration
+    out["adi"] = {"iterations": nit, "seconds": ta, "line_updates_G/s": 2 * nit * nodes / ta / 1e9,
+                  "alg_GB/s": 48.0 * nit * nodes / ta / 1e9}
     for g in grids:
         g.destroy()
     return out
@@ -391,6 +400,8 @@ def main():
     ap.add_argument("--measure-only", action="store_true",
                     help="only measured-mode solves (for profiler runs: no graph replay leg)")
     ap.add_argument("--no-batch", dest="batch", action="store_false", help="skip the ragged-batch leg")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the ragged-batch leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--no-serve", dest="serve", action="store_false", help="skip the serving leg")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--adi-iters", type=int, default=20)
@@ -403,6 +414,15 @@ def main():
         print("bench.py measures one GPU only: this build runs each grid on a single MI355X "
               "(see the sharding paragraph of the design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.batch_only:
+        import torch
+        import paper_2208_02427_amd as lap
+        ctx = lap.Context(arena_bytes=16 << 30, device="cuda:0")
+        res = {"ragged_batch": run_batch_leg(args, ctx, torch, lap, "cuda:0")}
+        if args.copy_probe:
+            res["copy_probe"] = run_copy_probe(torch, lap, "cuda:0")
+        print(json.dumps(res), flush=True)
+        return
     out, levels = run_gpu(args)
     line = {
         "metric": METRIC,

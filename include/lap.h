@@ -320,9 +320,16 @@ lap_status lap_op_restrict(int32_t dtype, int32_t m, int32_t n, int32_t ld, doub
                            const void* u, const void* f, void* bc, int32_t ldc, void* stream);
 
 /* One ADI half-iteration in zebra order: rows (dir 0: odd rows j, then even)
- * or columns (dir 1: odd columns i, then even), each line solved by the
- * Thomas algorithm, relaxation placement `form`.  In place on u (FP64 only:
- * dtype must be 0).  `work` must hold lap_op_work_bytes(m, n) bytes. */
+ * or columns (dir 1: odd columns i, then even), each line's tridiagonal
+ * system (SLOR / ADI sections, Eqs. (8)-(10)) solved by Gaussian elimination
+ * without pivoting, relaxation placement `form`.  Lines of up to 4095
+ * unknowns are solved in parallel blocks of 15 unknowns coupled through a
+ * reduced system over the block separators (equal to the sequential Thomas
+ * recurrence up to rounding); longer lines by the sequential recurrence.
+ * In place on u (FP64 only: dtype must be 0).  `work` must hold
+ * lap_op_work_bytes(m, n) bytes.  The line tables are copied from the host
+ * into `work` first; the call waits for that copy (a stream synchronisation),
+ * then enqueues the two launches. */
 lap_status lap_op_adi_half(int32_t dtype, int32_t m, int32_t n, int32_t ld, double dx, double dy,
                            double omega, int32_t dir, int32_t form, void* u, const void* f,
                            void* work, void* stream);

@@ -50,7 +50,7 @@ constexpr int kNormH = 6;
 // (one full occupancy round of the device when target = its wave capacity),
 // which avoids a nearly empty last round.  Chunks are never shorter than 16
 // rows, which bounds the number of tiles (and norm partials) of a level.
-inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0, int H = 2) {
+inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0, int H = 2, int min_rows = 16) {
     Tiling t;
     t.V = V;
     t.H = H;
@@ -65,7 +65,7 @@ inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0, int H = 2
         if (chunks < 1) chunks = 1;
         ty = (rows + chunks - 1) / chunks;
         ty += ty & 1;
-        if (ty < 16) ty = 16;
+        if (ty < min_rows) ty = min_rows;
     }
     t.ty = ty;
     t.nchunk = (rows + ty - 1) / ty;
@@ -83,8 +83,12 @@ inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0, int H = 2
 // of the mixed loop; a norm finalisation reduces the partials of the kind
 // that produced them.
 enum NormKind { NORM_PASS = 0, NORM_DEFECT = 1 };
+// The defect pass keeps chunks of >= 64 rows: on small grids (and so in
+// batches of them) shorter chunks leave each wavefront too little to stream.
+constexpr int kDefectMinRows = 64;
 inline Tiling norm_tiling(int m, int n, int kind = NORM_PASS) {
-    return kind == NORM_DEFECT ? make_tiling(m, n, 1, 0, 16384, 2) : make_tiling(m, n, 2, 0, 16384, kNormH);
+    return kind == NORM_DEFECT ? make_tiling(m, n, 1, 0, 16384, 2, kDefectMinRows)
+                               : make_tiling(m, n, 2, 0, 16384, kNormH);
 }
 
 // Blocks of 4 waves; the grid is padded to a multiple of the XCD count so
