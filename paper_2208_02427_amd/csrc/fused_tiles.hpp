@@ -43,8 +43,8 @@ template <typename T, int V, int JP>
 __device__ __forceinline__ void rb_push(RBStage<T, V>& S, const T (&d)[V], const T (&fd)[V], T (&out)[V],
                                         T (&fout)[V], int j, int n, const Cols<V>& c, int ipar, T cx, T cy, T inv_d,
                                         T om) {
-    const T cW = __shfl_up(S.c[V - 1], 1);
-    const T cE = __shfl_down(S.c[0], 1);
+    const T cW = lane_prev(S.c[V - 1]);
+    const T cE = lane_next(S.c[0]);
     if (j >= 1 && j <= n - 2) {
 #pragma unroll
         for (int e = 0; e < V; ++e) {
@@ -56,8 +56,8 @@ __device__ __forceinline__ void rb_push(RBStage<T, V>& S, const T (&d)[V], const
             S.c[e] = fma(om, t - S.c[e], S.c[e]);
         }
     }
-    const T bW = __shfl_up(S.b[V - 1], 1);
-    const T bE = __shfl_down(S.b[0], 1);
+    const T bW = lane_prev(S.b[V - 1]);
+    const T bE = lane_next(S.b[0]);
     if (j - 1 >= 1 && j - 1 <= n - 2) {
 #pragma unroll
         for (int e = 0; e < V; ++e) {
@@ -115,8 +115,8 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
 
     if constexpr (FL & SW_NORM) {
         // residual of the input at row j (rows j-1, j, j+1 are input values)
-        const T cW = __shfl_up(R.st[0].c[V - 1], 1);
-        const T cE = __shfl_down(R.st[0].c[0], 1);
+        const T cW = lane_prev(R.st[0].c[V - 1]);
+        const T cE = lane_next(R.st[0].c[0]);
         if (j >= j0 && j <= j1) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
@@ -150,8 +150,8 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
         // q - 2 is even exactly on steps with j odd
         if (JP == 1 && q - 2 >= j0 && q - 2 <= j1) {
             const int J = (q - 2) >> 1;
-            const T w2 = __shfl_up(R.r2[V - 1], 1), w1 = __shfl_up(R.r1[V - 1], 1), w0 = __shfl_up(r0[V - 1], 1);
-            const T e2 = __shfl_down(R.r2[0], 1), e1 = __shfl_down(R.r1[0], 1), e0 = __shfl_down(r0[0], 1);
+            const T w2 = lane_prev(R.r2[V - 1]), w1 = lane_prev(R.r1[V - 1]), w0 = lane_prev(r0[V - 1]);
+            const T e2 = lane_next(R.r2[0]), e1 = lane_next(R.r1[0]), e0 = lane_next(r0[0]);
             if (J >= 1 && J <= A.nc - 2) {
                 T* brow = A.bc + (ptrdiff_t)J * A.Pcs;
 #pragma unroll

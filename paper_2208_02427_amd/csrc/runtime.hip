@@ -476,7 +476,7 @@ Footprint footprint(int m, int n, bool has_f, int flags) {
     }
     if (flags & LAP_ALLOC_ADI) {
         fp.add(f0 * 8);
-        fp.add((size_t)4 * std::max(m, n) * 8);
+        fp.add(((size_t)4 * std::max(m, n) + 2 * kSegTab) * 8);
     }
     fp.add(sizeof(Ctrl));
     fp.add(max_tiles(m, n) * 16);

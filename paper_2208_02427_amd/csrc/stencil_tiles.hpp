@@ -68,6 +68,30 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (b % kXcds) * per + (b / kXcds);
 }
 
+// The value held by the previous / next lane of the wavefront, moved by a
+// DPP wavefront shift: one VALU move per 32 bits instead of a permute
+// through LDS.  The first / last lane, which has no such neighbour, gets 0:
+// in every tile those lanes' outer columns are halo columns, whose values
+// never reach an output.  Every lane must be active (the stencil tiles call
+// these in wave-uniform control flow).
+constexpr int kDppWaveShr1 = 0x138;   // lane i reads lane i - 1
+constexpr int kDppWaveShl1 = 0x130;   // lane i reads lane i + 1
+template <int CTRL, typename T>
+__device__ __forceinline__ T lane_shift(T x) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, true);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, true);
+        return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+    }
+}
+template <typename T>
+__device__ __forceinline__ T lane_prev(T x) { return lane_shift<kDppWaveShr1>(x); }
+template <typename T>
+__device__ __forceinline__ T lane_next(T x) { return lane_shift<kDppWaveShl1>(x); }
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -156,7 +180,7 @@ struct Prolong {
     __device__ __forceinline__ void complete(T (&x)[V2 + 1]) {
 #pragma unroll
         for (int q = 0; q < V2; ++q) x[q] = nraw[q];
-        const T r = __shfl_down(nraw[0], 1);
+        const T r = lane_next(nraw[0]);
         x[V2] = (threadIdx.x & 63) == 63 ? nlast : r;
     }
     __device__ __forceinline__ void init(const T* ec, int j, int nc, int Pc, int Ps, int i0) {
@@ -255,8 +279,8 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
     const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
 
     // old row j: neighbours across lanes
-    const T cW = __shfl_up(R.c[V - 1], 1);
-    const T cE = __shfl_down(R.c[0], 1);
+    const T cW = lane_prev(R.c[V - 1]);
+    const T cE = lane_next(R.c[0]);
 
     if constexpr (FL & SW_NORM) {
         if (j >= j0 && j <= j1) {
@@ -290,8 +314,8 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
         }
     }
     // colour 1 on row j-1 ((i+j-1) odd) from the new colour-0 values
-    const T bW = __shfl_up(R.b[V - 1], 1);
-    const T bE = __shfl_down(R.b[0], 1);
+    const T bW = lane_prev(R.b[V - 1]);
+    const T bE = lane_next(R.b[0]);
     if (rjm) {
 #pragma unroll
         for (int e = 0; e < V; ++e) {
@@ -356,8 +380,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& A0, int tile, int
 template <typename T, int V>
 __device__ __forceinline__ void residual_row(T (&r)[V], const T (&um)[V], const T (&uc)[V], const T (&up)[V],
                                              const T (&f)[V], bool rowint, const Cols<V>& c, T cx, T cy, T d) {
-    const T W0 = __shfl_up(uc[V - 1], 1);
-    const T E0 = __shfl_down(uc[0], 1);
+    const T W0 = lane_prev(uc[V - 1]);
+    const T E0 = lane_next(uc[0]);
 #pragma unroll
     for (int e = 0; e < V; ++e) {
         const T W = e > 0 ? uc[e - 1] : W0;
@@ -395,8 +419,8 @@ __device__ __forceinline__ void restrict_tile(const RestrictArgs<T>& A, int tile
         residual_row<T, V>(r0, um, uc, up, fr, (j >= 1) && (j <= A.n - 2), c, A.cx, A.cy, A.d);
         if ((j & 1) && j >= j0 + 2) {
             const int J = (j - 1) >> 1;               // coarse row at fine row j-1
-            const T w2 = __shfl_up(r2[V - 1], 1), w1 = __shfl_up(r1[V - 1], 1), w0 = __shfl_up(r0[V - 1], 1);
-            const T e2 = __shfl_down(r2[0], 1), e1 = __shfl_down(r1[0], 1), e0 = __shfl_down(r0[0], 1);
+            const T w2 = lane_prev(r2[V - 1]), w1 = lane_prev(r1[V - 1]), w0 = lane_prev(r0[V - 1]);
+            const T e2 = lane_next(r2[0]), e1 = lane_next(r1[0]), e0 = lane_next(r0[0]);
             if (J >= 1 && J <= A.nc - 2) {
                 T* brow = A.bc + (size_t)J * A.Pc;
 #pragma unroll

@@ -107,6 +107,32 @@ def test_batch_fused_bitwise(precision):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("max_iter,tol", [(1, 0.0), (2, 0.0), (3, 0.0), (40, 1e30), (40, 1e-10)])
+def test_fused_stops_and_restarts(max_iter, tol):
+    """FP64 V(2,2), fused passes against one launch per sweep: stopping after
+    1, 2, 3 cycles, at the initial iterate, at convergence; then a warm
+    restart of the same grid from its result.  Bitwise, with the same
+    iteration counts."""
+    torch, lap = need_gpu()
+    psi, f, dx, dy = rand_problem(129, 97, seed=21, dx=1.0 / 128, dy=1.0 / 96, source=True)
+    res = {}
+    for fuse in (False, True):
+        ctx = lap.Context(arena_bytes=256 << 20)
+        ctx.set_fusion(fuse)
+        g = ctx.grid(to_dev(torch, psi), to_dev(torch, f), dx, dy)
+        i1 = g.solve("mg", precision="fp64", tol=tol, max_iter=max_iter)
+        a = g.read().cpu().numpy()
+        i2 = g.solve("mg", precision="fp64", tol=1e-10, max_iter=40)
+        b = g.read().cpu().numpy()
+        res[fuse] = (i1["iterations"], a, i2["iterations"], b)
+        g.destroy()
+        ctx.close()
+    say("stops", max_iter, tol, res[False][0], res[False][2])
+    assert res[False][0] == res[True][0] and res[False][2] == res[True][2]
+    assert np.array_equal(res[False][1], res[True][1])
+    assert np.array_equal(res[False][3], res[True][3])
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_timing_counts_only_full_work_launches(mode):
     """Kernel statistics of a solve hold exactly the launches before and
