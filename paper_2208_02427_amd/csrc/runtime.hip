@@ -2106,13 +2106,15 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, bool many) {
         case OP_COARSE:
         case OP_SUBTREE: t.ntiles = 1; break;
     }
-    // The table's short row chunks (down to 2 rows) minimise the latency of
-    // one grid's small level; inside a merged launch over many grids the
-    // launch is throughput-bound and a chunk's halo rows (up to 11 for a
-    // fused pass) would dominate, so plans of several grids use chunks of
-    // >= 64 rows (the measured best for ragged batches of 33..1025 points a side).
-    if (many && (op.kind == OP_SWEEP || op.kind == OP_RESTRICT) && !(op.flags & SW_NORM) && t.ty < kBatchMinRows)
-        t = make_tiling(L.m, L.n, t.V, kBatchMinRows, 0, t.H);
+    // The table's short row chunks (down to 2 rows) and narrow windows
+    // minimise the latency of one grid's small level; inside a merged launch
+    // over many grids the launch is throughput-bound and a chunk's halo rows
+    // (up to 11 for a fused pass) would dominate, so plans of several grids
+    // use chunks of >= 64 rows and 4 columns per lane (the measured best for
+    // ragged batches of 33..1025 points a side: 32 or 128 rows, V = 1 or 2
+    // were slower).
+    if (many && (op.kind == OP_SWEEP || op.kind == OP_RESTRICT) && !(op.flags & SW_NORM))
+        t = make_tiling(L.m, L.n, 4, std::max(t.ty, kBatchMinRows), 0, t.H);
     it.V = t.V;
     it.ty = t.ty;
     it.nwin = t.nwin;
