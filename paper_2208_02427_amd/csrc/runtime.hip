@@ -149,49 +149,66 @@ std::vector<LevelGeo> plan_levels(int m, int n, double dx, double dy) {
 }
 
 // Inverse of L_h restricted to the interior unknowns (k = (j-1)(m-2)+(i-1))
-// of a small level, in FP64: Cholesky factorisation of the SPD matrix -L_h,
-// then column-by-column solves; returns L_h^{-1} = -(-L_h)^{-1}.
+// of a small level, in FP64, by separation of variables: with Q the
+// orthonormal sine transform across the short side (p unknowns, symmetric,
+// Q^2 = I) and T_k the tridiagonal mode-k operator of -L_h along the long
+// side (q unknowns), -L_h = (Q x I) diag_k(T_k) (Q x I), so
+//   L_h^{-1}[(s,l),(s0,l0)] = - sum_k Q[s][k] Q[k][s0] T_k^{-1}[l][l0].
+// T_k^{-1} comes from q Thomas solves; the whole inverse costs O(p N^2)
+// (a dense factorisation took O(N^3), milliseconds per new level shape).
 bool coarse_inverse(int m, int n, double dx, double dy, std::vector<double>& out) {
     const Coef c = coef(dx, dy);
     const int mi = m - 2, ni = n - 2, N = mi * ni;
-    std::vector<double> A((size_t)N * N, 0.0);
-    for (int j = 0; j < ni; ++j)
-        for (int i = 0; i < mi; ++i) {
-            const int k = j * mi + i;
-            A[(size_t)k * N + k] = c.d;
-            if (i > 0) A[(size_t)k * N + k - 1] = -c.cx;
-            if (i < mi - 1) A[(size_t)k * N + k + 1] = -c.cx;
-            if (j > 0) A[(size_t)k * N + k - mi] = -c.cy;
-            if (j < ni - 1) A[(size_t)k * N + k + mi] = -c.cy;
+    if (mi < 1 || ni < 1) return false;
+    const bool xs = mi <= ni;                  // the short side runs along x
+    const int p = xs ? mi : ni, q = xs ? ni : mi;
+    const double cs = xs ? c.cx : c.cy, cl = xs ? c.cy : c.cx;
+    const double pi = std::acos(-1.0), nrm = std::sqrt(2.0 / (p + 1));
+    std::vector<double> Q((size_t)p * p), G((size_t)p * q * q);
+    for (int k = 0; k < p; ++k)
+        for (int s = 0; s < p; ++s) Q[(size_t)k * p + s] = nrm * std::sin(pi * (k + 1) * (s + 1) / (p + 1));
+    std::vector<double> cp(q), z(q);
+    for (int k = 0; k < p; ++k) {
+        const double mu = 2.0 - 2.0 * std::cos(pi * (k + 1) / (p + 1));
+        const double diag = cs * mu + 2.0 * cl, off = -cl;
+        // factor once: pivots and c'
+        std::vector<double> ipv(q);
+        double prev = 0.0;
+        for (int l = 0; l < q; ++l) {
+            const double piv = diag - off * prev;
+            if (!(piv > 0.0)) return false;
+            ipv[l] = 1.0 / piv;
+            cp[l] = off * ipv[l];
+            prev = cp[l];
         }
-    // in-place Cholesky, lower triangle
-    for (int k = 0; k < N; ++k) {
-        double s = A[(size_t)k * N + k];
-        for (int p = 0; p < k; ++p) s -= A[(size_t)k * N + p] * A[(size_t)k * N + p];
-        if (!(s > 0.0)) return false;
-        const double lkk = std::sqrt(s);
-        A[(size_t)k * N + k] = lkk;
-        for (int r = k + 1; r < N; ++r) {
-            double t = A[(size_t)r * N + k];
-            for (int p = 0; p < k; ++p) t -= A[(size_t)r * N + p] * A[(size_t)k * N + p];
-            A[(size_t)r * N + k] = t / lkk;
+        double* Gk = G.data() + (size_t)k * q * q;
+        for (int l0 = 0; l0 < q; ++l0) {           // column l0 of T_k^{-1}
+            double zp = 0.0;
+            for (int l = 0; l < q; ++l) {
+                zp = ((l == l0 ? 1.0 : 0.0) - off * zp) * ipv[l];
+                z[l] = zp;
+            }
+            double x = 0.0;
+            for (int l = q - 1; l >= 0; --l) {
+                x = z[l] - cp[l] * x;
+                Gk[(size_t)l * q + l0] = x;
+            }
         }
     }
     out.assign((size_t)N * N, 0.0);
-    std::vector<double> y(N);
-    for (int col = 0; col < N; ++col) {
-        for (int r = 0; r < N; ++r) {
-            double t = (r == col) ? 1.0 : 0.0;
-            for (int p = 0; p < r; ++p) t -= A[(size_t)r * N + p] * y[p];
-            y[r] = t / A[(size_t)r * N + r];
+    std::vector<double> w(p);
+    for (int s = 0; s < p; ++s)
+        for (int s0 = 0; s0 < p; ++s0) {
+            for (int k = 0; k < p; ++k) w[k] = Q[(size_t)s * p + k] * Q[(size_t)k * p + s0];
+            for (int l = 0; l < q; ++l)
+                for (int l0 = 0; l0 < q; ++l0) {
+                    double v = 0.0;
+                    for (int k = 0; k < p; ++k) v += w[k] * G[((size_t)k * q + l) * q + l0];
+                    const size_t r = xs ? (size_t)l * mi + s : (size_t)s * mi + l;
+                    const size_t col = xs ? (size_t)l0 * mi + s0 : (size_t)s0 * mi + l0;
+                    out[r * N + col] = -v;
+                }
         }
-        for (int r = N - 1; r >= 0; --r) {
-            double t = y[r];
-            for (int p = r + 1; p < N; ++p) t -= A[(size_t)p * N + r] * y[p];
-            y[r] = t / A[(size_t)r * N + r];
-        }
-        for (int r = 0; r < N; ++r) out[(size_t)r * N + col] = -y[r];
-    }
     return true;
 }
 
