@@ -2052,11 +2052,13 @@ int batch_kind(const Op& op) {
     return -1;
 }
 
-constexpr int kBatchMinRows = 64;
+constexpr int kBatchMinRows = 32;
 constexpr size_t kBatchManyGrids = 4;
+constexpr size_t kBatchWideGrids = 64;
+constexpr int kBatchWideRows = 64;
 
 // Fill the item of grid g for operation op (tiling, geometry, coefficients).
-BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, bool many) {
+BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) {
     lap_ctx* c = g->ctx;
     const LevelGeo& L = g->geo[op.level];
     const Coef k = coef(L.dx, L.dy);
@@ -2124,14 +2126,18 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, bool many) {
         case OP_SUBTREE: t.ntiles = 1; break;
     }
     // The table's short row chunks (down to 2 rows) and narrow windows
-    // minimise the latency of one grid's small level; inside a merged launch
-    // over many grids the launch is throughput-bound and a chunk's halo rows
-    // (up to 11 for a fused pass) would dominate, so plans of several grids
-    // use chunks of >= 64 rows and 4 columns per lane (the measured best for
-    // ragged batches of 33..1025 points a side: 32 or 128 rows, V = 1 or 2
-    // were slower).
-    if (many && (op.kind == OP_SWEEP || op.kind == OP_RESTRICT) && !(op.flags & SW_NORM))
-        t = make_tiling(L.m, L.n, 4, std::max(t.ty, kBatchMinRows), 0, t.H);
+    // minimise the latency of one grid's small level.  Inside a merged launch
+    // over several grids a chunk's halo rows (up to 11 for a fused pass)
+    // weigh more, so plans of 4 or more grids use chunks of >= 32 rows; plans
+    // of 64 or more grids are throughput-bound and take >= 64 rows and 4
+    // columns per lane (the measured best for a 512-grid ragged batch of
+    // 33..1025 points a side; with 10-20 grids of a serving tick the wide
+    // tiles doubled the latency).
+    const bool tile_op = (op.kind == OP_SWEEP || op.kind == OP_RESTRICT) && !(op.flags & SW_NORM);
+    if (tile_op && nplan >= kBatchWideGrids)
+        t = make_tiling(L.m, L.n, 4, std::max(t.ty, kBatchWideRows), 0, t.H);
+    else if (tile_op && nplan >= kBatchManyGrids && t.ty < kBatchMinRows)
+        t = make_tiling(L.m, L.n, t.V, kBatchMinRows, 0, t.H);
     it.V = t.V;
     it.ty = t.ty;
     it.nwin = t.nwin;
@@ -2224,7 +2230,7 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
             L.fine = skv.second[0].second.level == 0;
             int tile0 = 0;
             for (auto& go : skv.second) {
-                BatchItem it = make_item(go.first, go.second, o, gs.size() >= kBatchManyGrids);
+                BatchItem it = make_item(go.first, go.second, o, gs.size());
                 it.tile0 = tile0;
                 if (L.kind == BK_SUBTREE) {
                     const Op& op = go.second;
