@@ -82,12 +82,14 @@ __device__ __forceinline__ void rb_push(RBStage<T, V>& S, const T (&d)[V], const
 // steps before it enters the pipeline.  Measured on MI355X (8193^2 V-cycle
 // passes): FP64 gains up to six rows, FP32 (half the bytes per row, the
 // registers better spent on occupancy) is fastest with two.
-template <typename T>
-constexpr int fused_pf() { return sizeof(T) == 8 ? 6 : 2; }
+// FP64 passes that also stream a right-hand side carry a second ring (6 rows
+// measured best there too; 4 and 2 were slower).
+constexpr int kPfF64WithF = 6;
+template <typename T, int FL>
+constexpr int fused_pf() { return sizeof(T) == 8 ? ((FL & SW_F) ? kPfF64WithF : 6) : 2; }
 
-template <typename T, int V, int NS, bool RS>
+template <typename T, int V, int NS, bool RS, int PF>
 struct FusedRegs {
-    static constexpr int PF = fused_pf<T>();
     RBStage<T, V> st[NS];
     T ring[PF][V], fring[PF][V];        // input rows j+1 .. j+PF (slot = step phase)
     T bo[V];                            // input row j-1 (norm of the input)
@@ -101,9 +103,9 @@ struct FusedRegs {
 // slot is refilled with row j+1+PF, and the last stage emits final row
 // q = j + 1 - 2 * NS.
 template <typename T, int V, int FL, int NS, bool RS, int JP, int PH>
-__device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS>& R, const Cols<V>& c,
-                                           int j, int j0, int j1, int Lend, int ipar) {
-    constexpr int PF = fused_pf<T>();
+__device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS, fused_pf<T, FL>()>& R,
+                                           const Cols<V>& c, int j, int j0, int j1, int Lend, int ipar) {
+    constexpr int PF = fused_pf<T, FL>();
     T d[V], fd[V];
     copy<T, V>(d, R.ring[PH]);
     copy<T, V>(fd, R.fring[PH]);
@@ -182,9 +184,9 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
 
 // Steps PH, PH+1, ... of one turn of the ring, starting at row j + PH.
 template <typename T, int V, int FL, int NS, bool RS, int JP0, int PH>
-__device__ __forceinline__ void fused_turn(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS>& R, const Cols<V>& c,
-                                           int j, int j0, int j1, int Lend, int ipar) {
-    if constexpr (PH < fused_pf<T>()) {
+__device__ __forceinline__ void fused_turn(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS, fused_pf<T, FL>()>& R,
+                                           const Cols<V>& c, int j, int j0, int j1, int Lend, int ipar) {
+    if constexpr (PH < fused_pf<T, FL>()) {
         if (j + PH <= Lend - 1) {
             fused_step<T, V, FL, NS, RS, (JP0 + PH) & 1, PH>(A, R, c, j + PH, j0, j1, Lend, ipar);
             fused_turn<T, V, FL, NS, RS, JP0, PH + 1>(A, R, c, j, j0, j1, Lend, ipar);
@@ -234,7 +236,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
     if (((L0 + 1) & 1) != JP0) --L0;
     const int Lend = (RS ? e1 + 2 : j1) + 2 * NS;
 
-    FusedRegs<T, V, NS, RS> R;
+    FusedRegs<T, V, NS, RS, fused_pf<T, FL>()> R;
     R.s2 = 0.0;
     R.mx = 0.0;
 #pragma unroll
@@ -250,7 +252,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
     sweep_load<T, V, FL>(R.st[0].b, A, L0, c, R.pr);
     sweep_load<T, V, FL>(R.st[0].c, A, L0 + 1, c, R.pr);
     sweep_loadf<T, V, FL>(R.st[0].fc, A, L0 + 1, c);
-    constexpr int PF = fused_pf<T>();
+    constexpr int PF = fused_pf<T, FL>();
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
         sweep_load<T, V, FL>(R.ring[k], A, L0 + 2 + k, c, R.pr);
