@@ -34,6 +34,18 @@ __device__ __forceinline__ void batch_fused_tile(const BatchItem& it, int lt, in
     A.tl.nchunk = it.nchunk;
     A.tl.ntiles = it.ntiles;
     A.tl.H = it.H;
+    if constexpr ((FLS & SW_DEF) != 0) {
+        A.uin = (const T*)it.e;
+        A.uout = nullptr;
+        A.psi_in = (const double*)it.in;
+        A.psi_out = (double*)it.out;
+        A.f64 = it.f64;
+        A.rhs_out = (T*)it.bc;
+        A.bc = nullptr;
+        A.dcx = it.cx;
+        A.dcy = it.cy;
+        A.dd = it.d;
+    }
     const bool hf = (it.flags & SW_F) != 0;
     switch (it.V) {
         case 1: hf ? fused_tile<T, 1, FLS | SW_F>(A, lt, lane) : fused_tile<T, 1, FLS>(A, lt, lane); break;
@@ -57,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(const BatchItem* items, 
 #define LAP_BATCH_FUSED_FLAGS(X)                                                           \
     X(SW_TWO) X(SW_TWO | SW_ZERO) X(SW_TWO | SW_NORM) X(SW_TWO | SW_PROLONG) X(SW_RESTRICT) \
     X(SW_RESTRICT | SW_ZERO) X(SW_RESTRICT | SW_NORM) X(SW_RESTRICT | SW_TWO)              \
-    X(SW_RESTRICT | SW_TWO | SW_ZERO) X(SW_RESTRICT | SW_TWO | SW_NORM)
+    X(SW_RESTRICT | SW_TWO | SW_ZERO) X(SW_RESTRICT | SW_TWO | SW_NORM) X(SW_DEF | SW_PROLONG | SW_TWO)
 
 template <typename T>
 static hipError_t launch_batch_fused_t(int fl, const BatchItem* items, const int* tmap, int total, int blocks,

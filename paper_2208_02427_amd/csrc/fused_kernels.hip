@@ -1,7 +1,8 @@
 // Fused streaming passes of one grid (see fused_tiles.hpp): pre-smoothing
 // (one or two sweeps, from zero / with the input's residual norms) with the
-// residual + full weighting of its result, and post-smoothing (bilinear
-// correction + two sweeps).  One wavefront per (window, chunk) tile, blocks
+// residual + full weighting of its result, post-smoothing (bilinear
+// correction + two sweeps), and the mixed loop's FP32 post-smoothing of the
+// finest level merged with the next FP64 defect correction.  One wavefront per (window, chunk) tile, blocks
 // of four wavefronts dealt XCD-contiguously as in the one-sweep kernel.
 #include "fused_tiles.hpp"
 
@@ -25,7 +26,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(SweepArgs<T> A) {
     X(SW_RESTRICT) X(SW_RESTRICT | SW_F) X(SW_RESTRICT | SW_ZERO | SW_F) X(SW_RESTRICT | SW_NORM) \
     X(SW_RESTRICT | SW_NORM | SW_F) X(SW_RESTRICT | SW_TWO) X(SW_RESTRICT | SW_TWO | SW_F)       \
     X(SW_RESTRICT | SW_TWO | SW_ZERO | SW_F) X(SW_RESTRICT | SW_TWO | SW_NORM)                    \
-    X(SW_RESTRICT | SW_TWO | SW_NORM | SW_F)
+    X(SW_RESTRICT | SW_TWO | SW_NORM | SW_F) X(SW_DEF | SW_PROLONG | SW_TWO | SW_F)
 
 template <typename T, int V>
 static hipError_t launch_fused_v(const SweepArgs<T>& a, int flags, hipStream_t s) {
@@ -45,7 +46,7 @@ static hipError_t launch_fused_v(const SweepArgs<T>& a, int flags, hipStream_t s
 template <typename T>
 hipError_t launch_fused(const SweepArgs<T>& a, int flags, hipStream_t s) {
     // the halo must cover every fused stage
-    const int need = ((flags & SW_TWO) ? 4 : 2) + ((flags & SW_RESTRICT) ? 2 : 0);
+    const int need = ((flags & SW_TWO) ? 4 : 2) + ((flags & (SW_RESTRICT | SW_DEF)) ? 2 : 0);
     if (a.tl.H < need) return hipErrorInvalidValue;
     switch (a.tl.V) {
         case 1: return launch_fused_v<T, 1>(a, flags, s);

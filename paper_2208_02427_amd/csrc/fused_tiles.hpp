@@ -83,10 +83,15 @@ __device__ __forceinline__ void rb_push(RBStage<T, V>& S, const T (&d)[V], const
 // passes): FP64 gains up to six rows, FP32 (half the bytes per row, the
 // registers better spent on occupancy) is fastest with two.
 // FP64 passes that also stream a right-hand side carry a second ring (6 rows
-// measured best there too; 4 and 2 were slower).
+// measured best there too; 4 and 2 were slower).  The FP32 post-smoothing +
+// FP64 defect pass (five input streams, two rings of FP64 rows besides the
+// FP32 ones) is fastest with two rows (4 and 6 were 2-4% slower per solve).
 constexpr int kPfF64WithF = 6;
 template <typename T, int FL>
-constexpr int fused_pf() { return sizeof(T) == 8 ? ((FL & SW_F) ? kPfF64WithF : 6) : 2; }
+constexpr int fused_pf() {
+    if constexpr ((FL & SW_DEF) != 0) return 2;
+    return sizeof(T) == 8 ? ((FL & SW_F) ? kPfF64WithF : 6) : 2;
+}
 
 template <typename T, int V, int NS, bool RS, int PF>
 struct FusedRegs {
@@ -95,6 +100,8 @@ struct FusedRegs {
     T bo[V];                            // input row j-1 (norm of the input)
     T ru0[V], ru1[V], rf1[V];           // final rows q-2, q-1 and f of row q-1
     T r2[V], r1[V];                     // residual rows q-3, q-2
+    double pring[PF][V], qring[PF][V];  // SW_DEF: FP64 iterate and source rows q .. q+PF-1
+    double pm[V], pc[V], fm[V];         // SW_DEF: updated rows q-2, q-1 and the source of row q-1
     double s2, mx;
     Prolong<T, V> pr;
 };
@@ -143,7 +150,36 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
         copy<T, V>(fo, fo2);
     }
     const int q = j + 1 - 2 * NS;
-    if (q >= j0 && q <= j1) store_row<T, V>(A.uout, o, q, A.Ps, c);
+    if constexpr (FL & SW_DEF) {
+        // o is row q of the final correction: psi_out = psi_in + e there, and
+        // the FP64 residual of the updated iterate at row q - 1
+        double ps[V], fq[V], pn[V];
+        copy<double, V>(ps, R.pring[PH]);
+        copy<double, V>(fq, R.qring[PH]);
+        load_row<double, V>(R.pring[PH], A.psi_in, q + PF, A.n, A.Ps, c.i0, c.vin);
+        load_row<double, V>(R.qring[PH], A.f64, q + PF, A.n, A.Ps, c.i0, c.vin);
+#pragma unroll
+        for (int e = 0; e < V; ++e) pn[e] = ps[e] + (double)o[e];
+        if (q >= j0 && q <= j1) store_row<double, V>(A.psi_out, pn, q, A.Ps, c);
+        if (q - 1 >= j0 && q - 1 <= j1) {
+            double r[V];
+            T r32[V];
+            residual_row<double, V>(r, R.pm, R.pc, pn, R.fm, true, c, A.dcx, A.dcy, A.dd);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                r32[e] = (T)r[e];
+                if (!c.cout[e]) continue;
+                R.s2 = fma(r[e], r[e], R.s2);
+                R.mx = fmax(R.mx, fabs(r[e]));
+            }
+            store_row<T, V>(A.rhs_out, r32, q - 1, A.Ps, c);
+        }
+        copy<double, V>(R.pm, R.pc);
+        copy<double, V>(R.pc, pn);
+        copy<double, V>(R.fm, fq);
+    } else if (q >= j0 && q <= j1) {
+        store_row<T, V>(A.uout, o, q, A.Ps, c);
+    }
 
     if constexpr (RS) {
         // residual of the result at row q-1, then full weighting at the even row q-2
@@ -216,8 +252,14 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
     if ((chunk & 1) && (A.n & 1)) {
         const ptrdiff_t last = (ptrdiff_t)(A.n - 1) * A.P, clast = (ptrdiff_t)(A.nc - 1) * A.Pc;
         if (A.uin) A.uin += last;
-        A.uout += last;
+        if (A.uout) A.uout += last;
         if (A.f) A.f += last;
+        if constexpr (FL & SW_DEF) {
+            A.psi_in += last;
+            A.psi_out += last;
+            if (A.f64) A.f64 += last;
+            A.rhs_out += last;
+        }
         if (A.ec) A.ec += clast;
         if (A.bc) A.bc += clast;
         A.Ps = -A.P;
@@ -230,11 +272,13 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
     // input rows [L0, Lend]: the last stage must be exact on the chunk's rows
     // and, with the restriction, two rows around its first and last even row;
     // L0 is moved up one row if needed so the first step has parity JP0
+    // (SW_DEF: the residual needs the final rows j0 - 1 .. j1 + 1)
     constexpr int JP0 = RS ? 1 : 0;
+    constexpr int DX = (FL & SW_DEF) ? 1 : 0;
     const int e0 = j0 + (j0 & 1), e1 = j1 - (j1 & 1);
-    int L0 = (RS ? e0 - 2 : j0) - 2 * NS;
+    int L0 = (RS ? e0 - 2 : j0 - DX) - 2 * NS;
     if (((L0 + 1) & 1) != JP0) --L0;
-    const int Lend = (RS ? e1 + 2 : j1) + 2 * NS;
+    const int Lend = (RS ? e1 + 2 : j1 + DX) + 2 * NS;
 
     FusedRegs<T, V, NS, RS, fused_pf<T, FL>()> R;
     R.s2 = 0.0;
@@ -259,13 +303,24 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
         sweep_loadf<T, V, FL>(R.fring[k], A, L0 + 2 + k, c);
     }
     if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.st[0].b);
+    if constexpr (FL & SW_DEF) {
+        // the first step emits final row L0 + 2 - 2 * NS
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            load_row<double, V>(R.pring[k], A.psi_in, L0 + 2 - 2 * NS + k, A.n, A.Ps, c.i0, c.vin);
+            load_row<double, V>(R.qring[k], A.f64, L0 + 2 - 2 * NS + k, A.n, A.Ps, c.i0, c.vin);
+        }
+        zero<double, V>(R.pm);
+        zero<double, V>(R.pc);
+        zero<double, V>(R.fm);
+    }
 
     // the loop is unrolled over one turn of the ring (PF is even, so every
     // turn starts on the row parity JP0)
     static_assert(PF % 2 == 0, "the ring turn must keep the row parity");
     for (int j = L0 + 1; j <= Lend - 1; j += PF)
         fused_turn<T, V, FL, NS, RS, JP0, 0>(A, R, c, j, j0, j1, Lend, ipar);
-    if constexpr (FL & SW_NORM) {
+    if constexpr ((FL & (SW_NORM | SW_DEF)) != 0) {
         const double s = wave_sum(R.s2);
         const double mx = wave_max(R.mx);
         if (lane == 0) {

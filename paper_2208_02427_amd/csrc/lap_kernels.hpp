@@ -78,17 +78,24 @@ inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0, int H = 2
 // pre-sweep with norms, residual norms, the FP64 defect correction): the
 // partial sums, and so the stopping decisions, then do not depend on the
 // tuning table or on whether the grid runs alone or inside a batch.
-// Two canonical tilings, by producer: the stencil passes (sweeps with
-// norms, fused pre-smoothing, residual norms) and the FP64 defect correction
-// of the mixed loop; a norm finalisation reduces the partials of the kind
-// that produced them.
-enum NormKind { NORM_PASS = 0, NORM_DEFECT = 1 };
+// Canonical tilings by producer: the stencil passes (sweeps with norms,
+// fused pre-smoothing, residual norms), the FP64 defect correction of the
+// mixed loop, and the fused FP32 post-smoothing + FP64 defect pass (halo of
+// two sweeps and the residual); a norm finalisation reduces the partials of
+// the kind that produced them.
+enum NormKind { NORM_PASS = 0, NORM_DEFECT = 1, NORM_POSTDEF = 2 };
 // The defect pass keeps chunks of >= 64 rows: on small grids (and so in
 // batches of them) shorter chunks leave each wavefront too little to stream.
 constexpr int kDefectMinRows = 64;
+// The post-smoothing + defect pass reads 2 * 2 + 1 halo rows above and below
+// each chunk: chunks of >= 64 rows up to 4097 rows (faster by 4% at 4097^2,
+// and by far in batches of small grids), of >= 16 rows beyond (the 16384
+// waves' chunks of 8193^2 are 36 rows; 64-row chunks were 1.5% slower).
+constexpr int kPostDefShortRowsN = 4097;
 inline Tiling norm_tiling(int m, int n, int kind = NORM_PASS) {
-    return kind == NORM_DEFECT ? make_tiling(m, n, 1, 0, 16384, 2, kDefectMinRows)
-                               : make_tiling(m, n, 2, 0, 16384, kNormH);
+    if (kind == NORM_DEFECT) return make_tiling(m, n, 1, 0, 16384, 2, kDefectMinRows);
+    if (kind == NORM_POSTDEF) return make_tiling(m, n, 2, 0, 16384, kNormH, n > kPostDefShortRowsN ? 16 : 64);
+    return make_tiling(m, n, 2, 0, 16384, kNormH);
 }
 
 // Blocks of 4 waves; the grid is padded to a multiple of the XCD count so
@@ -121,6 +128,9 @@ enum : int {
     SW_NORM = 8,     // accumulate residual norms of the input into partials
     SW_RESTRICT = 16,// fused pass: residual + full weighting of the result into bc
     SW_TWO = 32,     // fused pass: two sweeps
+    SW_DEF = 64,     // fused FP32 post-smoothing pass (with SW_PROLONG | SW_TWO | SW_F) whose result, the
+                     // correction, goes straight into the next FP64 defect correction (psi_in -> psi_out,
+                     // the residual's norms, its FP32 copy into rhs_out); the correction is not stored
 };
 
 template <typename T>
@@ -140,6 +150,12 @@ struct SweepArgs {
     int Ps, Pcs;
     T cx, cy, d, inv_d, omega;
     Tiling tl;
+    // SW_DEF: the FP64 iterate, its update, the FP64 source and the next FP32 right-hand side
+    const double* psi_in;
+    double* psi_out;
+    const double* f64;
+    T* rhs_out;
+    double dcx, dcy, dd;
 };
 
 template <typename T>
@@ -366,6 +382,10 @@ struct BatchItem {
     int flags;               // SW_F for sweeps; ADI relaxation form
     int parity;              // ADI line parity
     const void* sub;         // BK_SUBTREE: device SubtreeArgs<T> of this grid
+    // fused post-smoothing + defect pass (SW_DEF; in / out: the FP64 iterate,
+    // f / bc: this and the next FP32 right-hand side, ec: coarse correction)
+    const void* e;           // the FP32 level-0 buffer the post-smoothing starts from
+    const double* f64;       // FP64 source (nullable)
 };
 
 enum BatchKind { BK_SWEEP = 0, BK_RESTRICT, BK_COARSE, BK_FINALIZE, BK_RESNORM, BK_DEFECT, BK_ADI_ROWS, BK_ADI_COLS,

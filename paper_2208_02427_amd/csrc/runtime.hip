@@ -423,6 +423,7 @@ struct lap_grid {
     double* f64 = nullptr;
     std::vector<LevelBufs<double>> l64;
     std::vector<LevelBufs<float>> l32;
+    float* rhs2 = nullptr;           // second level-0 FP32 right-hand side (mixed: steps alternate)
     double* minv = nullptr;          // dense inverse or separable factor of the coarsest level
     double* coarse_work = nullptr;   // separable solve scratch
     int coarse_bw = 0, coarse_ifast = 1;
@@ -445,6 +446,7 @@ struct lap_grid {
     double batch_t0 = 0.0;
     int step_idx = 0;                // next outer step of the running solve
     int e_idx = 0;                   // buffer of the last FP32 correction (mixed)
+    bool pdef = false;               // the running mixed solve uses the post-smoothing + defect pass
     lap_opts batch_opts{};
     // graph cache
     hipGraphExec_t graph = nullptr;
@@ -468,7 +470,7 @@ struct Footprint {
 size_t max_tiles(int m, int n) {
     // the finest tiling any table entry may pick: V = 1, ty = 16
     int t = make_tiling(m, n, 1, 16).ntiles;
-    for (int k : {(int)NORM_PASS, (int)NORM_DEFECT}) t = std::max(t, norm_tiling(m, n, k).ntiles);
+    for (int k : {(int)NORM_PASS, (int)NORM_DEFECT, (int)NORM_POSTDEF}) t = std::max(t, norm_tiling(m, n, k).ntiles);
     return (size_t)t;
 }
 
@@ -484,9 +486,11 @@ Footprint footprint(int m, int n, bool has_f, int flags) {
     if (flags & LAP_ALLOC_FP64)
         for (size_t l = 1; l < lv.size(); ++l)
             for (int k = 0; k < 3; ++k) fp.add((size_t)lv[l].n * lv[l].P * 8);
-    if (flags & LAP_ALLOC_MIXED)
+    if (flags & LAP_ALLOC_MIXED) {
         for (size_t l = 0; l < lv.size(); ++l)
             for (int k = 0; k < 3; ++k) fp.add((size_t)lv[l].n * lv[l].P * 4);
+        fp.add(f0 * 4);
+    }
     if (flags & (LAP_ALLOC_FP64 | LAP_ALLOC_MIXED)) {
         fp.add(coarse_bytes(lv.back()));
         if (lv.back().interior() > (size_t)kDenseCoarseMax) fp.add(lv.back().interior() * 8);
@@ -742,7 +746,7 @@ hipError_t enq_residual_norm(lap_grid* g, int l, const T* u, const T* f) {
 // pre-smoothing and restriction of level l, then every grid's coarsest
 // solve, then the post-smoothing of level l from coarse to fine.
 enum OpKind { OP_SWEEP, OP_RESTRICT, OP_COARSE, OP_FINALIZE, OP_RESNORM, OP_DEFECT, OP_ADI_ROWS, OP_ADI_COLS,
-              OP_SUBTREE };
+              OP_SUBTREE, OP_POSTDEF };
 
 struct Op {
     long key;
@@ -754,9 +758,9 @@ struct Op {
     void* out;       // sweep / coarse output, defect psi_out
     const void* f;   // right-hand side
     const void* ec;  // sweep: coarse correction; defect: FP32 correction
-    void* bc;        // restrict: coarse right-hand side
+    void* bc;        // restrict: coarse right-hand side; post + defect: the new FP32 right-hand side
     double omega;
-    int parity;      // ADI line parity
+    int parity;      // ADI line parity; post + defect: buffer of the level-0 pre-smoothing result
 };
 
 constexpr long KEY_HEAD = 10;
@@ -847,13 +851,23 @@ int vcycle_result_index(const lap_ctx* c, const lap_opts& o) {
     return (npre >= 1 ? npre - 1 + npost : npost - 1) % 2;
 }
 
+// The first post-smoothing pass of level 0, left out of a cycle's plan (the
+// next outer step runs it fused with its defect correction): the buffer it
+// starts from and the coarse correction it adds.
+struct DeferredPost {
+    int in = -1;
+    const void* ec = nullptr;
+};
+
 // One V-cycle on level l of hierarchy H.  Level 0 either holds the iterate in
 // u0[0] (FP64 multigrid: the result returns to u0[0] since nu1+nu2 is even)
 // or starts from zero (error equation).  Returns the buffer index (0/1)
 // that holds the level's result.  `part` (level 0 with a norm only):
 // PART_HEAD records the stopping test of the incoming iterate, PART_TAIL the rest.
+// With dp, level 0 stops before its post-smoothing and describes it in *dp.
 template <typename T>
-int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm, int part, std::vector<Op>& ops) {
+int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm, int part, std::vector<Op>& ops,
+                DeferredPost* dp = nullptr) {
     const int L = (int)g->geo.size();
     const bool zero_start = (l > 0) || H.zero_start0;
     const bool split = norm && !zero_start;
@@ -920,6 +934,11 @@ int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm
                    0.0);
     const int cres = plan_vcycle<T>(g, H, l + 1, o, false, PART_ALL, ops);
     const T* ec = (cres == 0 ? H.u0[l + 1] : H.u1[l + 1]);
+    if (dp != nullptr && l == 0) {
+        dp->in = have_u ? cur : -1;
+        dp->ec = ec;
+        return cur;
+    }
     for (int k = 0; k < npost; ++k) {
         const int fl = fb | (pp.post[k] == 2 ? SW_TWO : 0);
         if (k == 0) {
@@ -970,7 +989,7 @@ HierView<float> view32(lap_grid* g) {
     return H;
 }
 
-hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const float* e) {
+hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const float* e, float* rhs) {
     const LevelGeo& L = g->geo[0];
     const Coef c = coef(L.dx, L.dy);
     DefectArgs a{};
@@ -978,7 +997,7 @@ hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const 
     a.psi_out = psi_out;
     a.e = e;
     a.f = g->f64;
-    a.rhs = g->l32[0].b;
+    a.rhs = rhs;
     a.partials = g->partials;
     a.ctrl = g->ctrl;
     a.m = L.m;
@@ -992,13 +1011,95 @@ hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const 
     return g->ctx->timed(KC_DEFECT, true, per * nint(L), [&]() { return launch_defect(a, g->ctx->stream); });
 }
 
-// Buffer (0/1) in which a zero-start V-cycle leaves its level result.
+// The previous step's level-0 post-smoothing (two sweeps after the bilinear
+// correction, FP32) fused with this step's defect correction: psi_out =
+// psi_in + e, the FP64 residual of psi_out, its norms, and its FP32 copy as
+// the next right-hand side, in one pass.  e itself is never stored.
+constexpr int kPostDefFlags = SW_DEF | SW_PROLONG | SW_TWO | SW_F;
+// Algorithmic bytes per interior node: e, a quarter node of coarse correction
+// and f (FP32), psi in and out, the next right-hand side (FP32), f (FP64).
+double postdef_bytes_per_node(bool with_f) { return 4.0 + 1.0 + 4.0 + 8.0 + 8.0 + 4.0 + (with_f ? 8.0 : 0.0); }
+
+hipError_t enq_postdef(lap_grid* g, const Op& op, double omega) {
+    const LevelGeo& L = g->geo[0];
+    const LevelGeo& C = g->geo[1];
+    const Coef c = coef(L.dx, L.dy);
+    SweepArgs<float> a{};
+    a.uin = g->l32[0].u[op.parity];
+    a.uout = nullptr;
+    a.f = (const float*)op.f;
+    a.ec = (const float*)op.ec;
+    a.partials = g->partials;
+    a.ctrl = g->ctrl;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    a.mc = C.m;
+    a.nc = C.n;
+    a.Pc = C.P;
+    a.cx = (float)c.cx;
+    a.cy = (float)c.cy;
+    a.d = (float)c.d;
+    a.inv_d = (float)c.inv_d;
+    a.omega = (float)omega;
+    a.tl = norm_tiling(L.m, L.n, NORM_POSTDEF);
+    a.psi_in = (const double*)op.in;
+    a.psi_out = (double*)op.out;
+    a.f64 = g->f64;
+    a.rhs_out = (float*)op.bc;
+    a.dcx = c.cx;
+    a.dcy = c.cy;
+    a.dd = c.d;
+    return g->ctx->timed(KC_DEFECT, true, postdef_bytes_per_node(g->f64 != nullptr) * nint(L), [&]() {
+        return launch_fused<float>(a, kPostDefFlags, g->ctx->stream);
+    });
+}
+
+// Whether a mixed solve of g with o runs its steps through the post-smoothing
+// + defect pass: fusion on, level 0 of the FP32 cycle smoothed by the
+// streaming kernels with one two-sweep post-smoothing pass (nu2 = 2) from a
+// smoothed start (nu1 >= 2).
+bool postdef_ok(lap_grid* g, const lap_opts& o) {
+    if (o.method != LAP_MG || o.precision != LAP_MIXED || !g->ctx->fuse || !g->rhs2) return false;
+    if (o.nu2 != 2 || o.nu1 < 2 || g->geo.size() < 2) return false;
+    return subtree_root<float>(g, 0) != 0;
+}
 
 // One outer step of the mixed loop: defect correction (adds the previous
 // FP32 correction, forms the FP64 residual, tests it), then one FP32
-// V-cycle on the error equation.
+// V-cycle on the error equation.  With g->pdef, step s >= 1 starts with the
+// fused pass that finishes step s - 1's cycle (its level-0 post-smoothing)
+// and does the defect correction; the FP32 right-hand sides of consecutive
+// steps alternate between l32[0].b and rhs2.
 void plan_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int e_idx, int part,
                      std::vector<Op>& ops) {
+    if (g->pdef) {
+        float* R[2] = {g->l32[0].b, g->rhs2};
+        const int par = in_idx;
+        HierView<float> H = view32(g);
+        DeferredPost dp;
+        if (part != PART_TAIL) {
+            if (first) {
+                push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, g->psi[in_idx], g->psi[1 - in_idx], g->f64, nullptr,
+                                R[0], 0.0);
+                push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, 0.0);
+            } else {
+                // the previous step's cycle, planned again only to find its deferred pass
+                std::vector<Op> prev;
+                H.b[0] = R[1 - par];
+                plan_vcycle<float>(g, H, 0, o, false, PART_ALL, prev, &dp);
+                push_op<float>(ops, KEY_HEAD, OP_POSTDEF, 0, kPostDefFlags, g->psi[in_idx], g->psi[1 - in_idx],
+                               R[1 - par], dp.ec, R[par], o.omega, dp.in);
+                push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_POSTDEF, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, 0.0);
+            }
+        }
+        if (part == PART_HEAD) return;
+        H.b[0] = R[par];
+        plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops, &dp);
+        return;
+    }
     if (part != PART_TAIL) {
         const float* e = first ? nullptr : (e_idx == 0 ? g->l32[0].u[0] : g->l32[0].u[1]);
         push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, g->psi[in_idx], g->psi[1 - in_idx], g->f64, e,
@@ -1104,7 +1205,9 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
         case OP_RESNORM:
             return enq_residual_norm<double>(g, l, (const double*)op.in, (const double*)op.f);
         case OP_DEFECT:
-            return enq_defect(g, (const double*)op.in, (double*)op.out, (const float*)op.ec);
+            return enq_defect(g, (const double*)op.in, (double*)op.out, (const float*)op.ec, (float*)op.bc);
+        case OP_POSTDEF:
+            return enq_postdef(g, op, op.omega);
         case OP_ADI_ROWS:
             return enq_adi_half(g, op.omega, op.flags, 0, op.parity);
         case OP_ADI_COLS:
@@ -1265,6 +1368,7 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
     }
     g->step_idx = 0;
     g->e_idx = vcycle_result_index(g->ctx, o);
+    g->pdef = postdef_ok(g, o);   // fixed for the whole solve
     // the two-buffer methods need both buffers equal when they start
     if (g->psi1_stale && o.method != LAP_ADI) {
         HIPCHK(hipMemcpyAsync(g->psi[1], g->psi[0], (size_t)g->n * g->P * 8, hipMemcpyDeviceToDevice,
@@ -1300,7 +1404,7 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
             });
         } else {
             // two outer steps (psi[1] -> psi[0] -> psi[1]); step 0 runs without the graph
-            snprintf(key, sizeof key, "mixed:%d:%d:%.17g", o.nu1, o.nu2, o.omega);
+            snprintf(key, sizeof key, "mixed%s:%d:%d:%.17g", g->pdef ? "+pd" : "", o.nu1, o.nu2, o.omega);
             e = capture(g, key, [&]() {
                 std::vector<Op> ops;
                 plan_mixed_step(g, o, 1, false, g->e_idx, PART_ALL, ops);
@@ -1621,6 +1725,7 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
             g->l32[l].u[1] = (float*)A(sz);
             g->l32[l].b = (float*)A(sz);
         }
+    if (flags & LAP_ALLOC_MIXED) g->rhs2 = (float*)A(f0 * 4);
     std::vector<double> inv;
     const std::vector<double>* factor = nullptr;   // lives in the context's cache
     if (mg) {
@@ -2048,6 +2153,7 @@ int batch_kind(const Op& op) {
         case OP_ADI_ROWS: return BK_ADI_ROWS;
         case OP_ADI_COLS: return BK_ADI_COLS;
         case OP_SUBTREE: return BK_SUBTREE;
+        case OP_POSTDEF: return BK_FUSED;
     }
     return -1;
 }
@@ -2101,6 +2207,12 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
         case OP_RESTRICT: t = c->tiling(L.m, L.n, KC_RESTRICT, op.dt); break;
         case OP_RESNORM: t = norm_tiling(g->geo[0].m, g->geo[0].n); break;
         case OP_DEFECT: t = norm_tiling(g->geo[0].m, g->geo[0].n, NORM_DEFECT); break;
+        case OP_POSTDEF:
+            t = norm_tiling(L.m, L.n, NORM_POSTDEF);
+            it.e = g->l32[0].u[op.parity];
+            it.f64 = g->f64;
+            it.flags = SW_F;
+            break;
         case OP_FINALIZE: t = norm_tiling(g->geo[0].m, g->geo[0].n, op.flags); break;
         case OP_ADI_ROWS:
         case OP_ADI_COLS: {
@@ -2155,6 +2267,7 @@ double item_bytes(const Op& op, const BatchItem& it) {
         case OP_RESTRICT: return ((op.in ? 1.0 : 0.0) + (op.f ? 1.0 : 0.0) + 0.25) * sz * n;
         case OP_RESNORM: return (op.f ? 16.0 : 8.0) * n;
         case OP_DEFECT: return (8.0 + (op.ec ? 4.0 : 0.0) + (op.f ? 8.0 : 0.0) + 12.0) * n;
+        case OP_POSTDEF: return postdef_bytes_per_node(it.f64 != nullptr) * n;
         case OP_ADI_ROWS:
         case OP_ADI_COLS: return adi_bytes_per_node(op.f != nullptr) * n;
         case OP_SUBTREE: return 2.0 * sz * (double)it.m * (double)it.n;
@@ -2175,6 +2288,7 @@ int kclass_of(const Op& op) {
         case OP_ADI_ROWS: return KC_ADI_ROWS;
         case OP_ADI_COLS: return KC_ADI_COLS;
         case OP_SUBTREE: return KC_SUBTREE;
+        case OP_POSTDEF: return KC_DEFECT;
     }
     return KC_SWEEP;
 }
@@ -2194,7 +2308,7 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
                                 ? (steps[k] == 0 ? 2 : steps[k] % 2)
                                 : (o.method == LAP_SOR_RB ? (steps[k] % 2) * ((int)sor_passes(c, o.check_every).size() % 2)
                                                           : 0);
-            snprintf(buf, sizeof buf, "%p:%d,", (void*)gs[k], par);
+            snprintf(buf, sizeof buf, "%p:%d%s,", (void*)gs[k], par, gs[k]->pdef ? "d" : "");
             key += buf;
         }
     }

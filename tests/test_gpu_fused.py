@@ -160,3 +160,57 @@ def test_timing_counts_only_full_work_launches(mode):
             assert allp["device_ms"] == pytest.approx(pre["device_ms"])   # ... but not timed
     g.destroy()
     ctx.close()
+
+
+KC_DEFECT = 3
+
+
+@pytest.mark.parametrize("max_iter,tol", [(1, 0.0), (2, 0.0), (3, 0.0), (4, 0.0), (40, 1e-10)])
+def test_mixed_post_defect_pass(max_iter, tol):
+    """Mixed V(2,2) with fusion: every outer step after the first opens with
+    one pass that finishes the previous FP32 cycle (its level-0 bilinear
+    correction + two sweeps) and does this step's FP64 defect correction, so
+    the level-0 FP32 post-smoothing never has a launch of its own.  Bitwise
+    against fusion off, eager and with graph replay (two steps per graph),
+    stopping after 1-4 steps and at convergence, then a warm restart."""
+    torch, lap = need_gpu()
+    psi, f, dx, dy = rand_problem(257, 193, seed=23, dx=1.0 / 256, dy=1.0 / 192, source=True)
+    res = {}
+    for mode in ("off", "eager", "graph"):
+        ctx = lap.Context(arena_bytes=256 << 20)
+        ctx.set_fusion(mode != "off")
+        g = ctx.grid(to_dev(torch, psi), to_dev(torch, f), dx, dy)
+        kw = dict(precision="mixed", use_graph=(mode == "graph"))
+        i1 = g.solve("mg", tol=tol, max_iter=max_iter, **kw)
+        a = g.read().cpu().numpy()
+        i2 = g.solve("mg", tol=1e-10, max_iter=40, **kw)
+        b = g.read().cpu().numpy()
+        res[mode] = (i1["iterations"], a, i2["iterations"], b)
+        g.destroy()
+        ctx.close()
+    say("post+defect", max_iter, tol, res["off"][0], res["off"][2])
+    for mode in ("eager", "graph"):
+        assert res[mode][0] == res["off"][0] and res[mode][2] == res["off"][2]
+        assert np.array_equal(res[mode][1], res["off"][1])
+        assert np.array_equal(res[mode][3], res["off"][3])
+
+
+def test_mixed_post_defect_launch_counts():
+    """With the post + defect pass, a mixed solve of k steps records k + 1
+    defect-class launches (the first step's plain defect correction, then one
+    fused pass per step up to the deciding test) and no level-0 FP32
+    post-smoothing launch."""
+    torch, lap = need_gpu()
+    psi, f, dx, dy = rand_problem(513, 257, seed=29, dx=1.0 / 512, dy=1.0 / 256, source=True)
+    ctx = lap.Context(arena_bytes=256 << 20)
+    ctx.set_timing(True)
+    g = ctx.grid(to_dev(torch, psi), to_dev(torch, f), dx, dy)
+    info = g.solve("mg", precision="mixed", tol=1e-10, max_iter=40)
+    k = info["iterations"]
+    say("post+defect counts", k)
+    assert info["status"] == 0 and k >= 3
+    assert ctx.kernel_stats(KC_DEFECT)["launches"] == k + 1
+    assert ctx.kernel_stats(KC_TWO, fine_only=True)["launches"] == 0
+    assert ctx.kernel_stats(KC_PRE, fine_only=True)["launches"] == k
+    g.destroy()
+    ctx.close()
