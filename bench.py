@@ -171,31 +171,7 @@ def run_gpu(args):
     if args.quick:
         args.batch = args.serve = False
     if not args.quick:
-        # ---------------------------------------------- mixed vs FP64 (bumps)
-        pb = W.square_problem(N, seed=2, bumps=True, bump_seed=3)
-        psib = torch.as_tensor(pb.psi0, device=dev)
-        fb = torch.as_tensor(pb.f, device=dev)
-        gb = ctx.grid(psib, fb, pb.dx, pb.dy, alloc=lap.LAP_ALLOC_FP64 | lap.LAP_ALLOC_MIXED)
-        res = {}
-        for prec in ("fp64", "mixed", "fp64", "mixed"):
-            gb.write(psib)
-            sync()
-            t0 = time.perf_counter()
-            info = gb.solve("mg", precision=prec, tol=1e-10, max_iter=60)
-            sync()
-            t = time.perf_counter() - t0
-            res[prec] = {"time_to_tol_s": t, "iterations": info["iterations"], "rel_res": info["rel_res_l2"],
-                         "status": info["status"]}
-        gb.write(psib)
-        gb.solve("mg", precision="fp64", tol=1e-10, max_iter=60)
-        u64 = gb.read()
-        gb.write(psib)
-        gb.solve("mg", precision="mixed", tol=1e-10, max_iter=60)
-        um = gb.read()
-        res["max_abs_mixed_vs_fp64"] = float((um - u64).abs().max().item())
-        res["speedup_mixed_over_fp64"] = res["fp64"]["time_to_tol_s"] / res["mixed"]["time_to_tol_s"]
-        out["mixed"] = res
-        gb.destroy()
+        out["mixed"] = run_mixed_leg(N, ctx, torch, lap, dev)
 
         # ---------------------------------------------- red-black SOR
         sor = {}
@@ -234,6 +210,37 @@ def run_gpu(args):
         out["serving"] = run_serving_leg(args, ctx, torch, lap, dev)
     ctx.close()
     return out, levels
+
+
+def run_mixed_leg(N, ctx, torch, lap, dev):
+    """Mixed precision vs FP64 multigrid on the N x N grid with the 32-bump
+    source: time to a 1e-10 relative residual (the second of two solves of
+    each), cycles / outer steps, and the largest difference of the results."""
+    sync = torch.cuda.synchronize
+    pb = W.square_problem(N, seed=2, bumps=True, bump_seed=3)
+    psib = torch.as_tensor(pb.psi0, device=dev)
+    fb = torch.as_tensor(pb.f, device=dev)
+    gb = ctx.grid(psib, fb, pb.dx, pb.dy, alloc=lap.LAP_ALLOC_FP64 | lap.LAP_ALLOC_MIXED)
+    res = {}
+    for prec in ("fp64", "mixed", "fp64", "mixed"):
+        gb.write(psib)
+        sync()
+        t0 = time.perf_counter()
+        info = gb.solve("mg", precision=prec, tol=1e-10, max_iter=60)
+        sync()
+        t = time.perf_counter() - t0
+        res[prec] = {"time_to_tol_s": t, "iterations": info["iterations"], "rel_res": info["rel_res_l2"],
+                     "status": info["status"]}
+    gb.write(psib)
+    gb.solve("mg", precision="fp64", tol=1e-10, max_iter=60)
+    u64 = gb.read()
+    gb.write(psib)
+    gb.solve("mg", precision="mixed", tol=1e-10, max_iter=60)
+    um = gb.read()
+    res["max_abs_mixed_vs_fp64"] = float((um - u64).abs().max().item())
+    res["speedup_mixed_over_fp64"] = res["fp64"]["time_to_tol_s"] / res["mixed"]["time_to_tol_s"]
+    gb.destroy()
+    return res
 
 
 def device_request(torch, req, dev):
@@ -400,6 +407,8 @@ def main():
     ap.add_argument("--measure-only", action="store_true",
                     help="only measured-mode solves (for profiler runs: no graph replay leg)")
     ap.add_argument("--no-batch", dest="batch", action="store_false", help="skip the ragged-batch leg")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="run only the mixed-vs-FP64 leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the ragged-batch leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--no-serve", dest="serve", action="store_false", help="skip the serving leg")
@@ -414,6 +423,15 @@ def main():
         print("bench.py measures one GPU only: this build runs each grid on a single MI355X "
               "(see the sharding paragraph of the design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.mixed_only:
+        import torch
+        import paper_2208_02427_amd as lap
+        ctx = lap.Context(arena_bytes=16 << 30, device="cuda:0")
+        res = {"mixed": run_mixed_leg(args.size, ctx, torch, lap, "cuda:0")}
+        if args.copy_probe:
+            res["copy_probe"] = run_copy_probe(torch, lap, "cuda:0")
+        print(json.dumps(res), flush=True)
+        return
     if args.batch_only:
         import torch
         import paper_2208_02427_amd as lap
