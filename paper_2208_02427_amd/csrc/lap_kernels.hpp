@@ -44,6 +44,13 @@ struct Tiling {
 // Halo of the canonical norm tiling: wide enough for a fused pass of two
 // sweeps and a residual + full weighting.
 constexpr int kNormH = 6;
+// Waves the canonical tiling of the stencil passes aims at.  On 8193^2 the
+// finest pre-smoothing pass took 259 us with 16384 waves (36-row chunks),
+// 252 us with 32768 (18 rows), 267 us with 49152 or 65536: halo rows shared
+// by neighbouring chunks come from L2, so shorter chunks pay little and
+// buy parallelism, up to a point.  Below ~6000 rows the 16-row minimum
+// decides instead.
+constexpr int kNormWaves = 32768;
 
 // Tiling of an m x n level with V columns per lane.  ty > 0: chunks of ty
 // rows.  ty == 0: size the chunks so the launch has about `target` waves
@@ -95,7 +102,7 @@ constexpr int kPostDefShortRowsN = 4097;
 inline Tiling norm_tiling(int m, int n, int kind = NORM_PASS) {
     if (kind == NORM_DEFECT) return make_tiling(m, n, 1, 0, 16384, 2, kDefectMinRows);
     if (kind == NORM_POSTDEF) return make_tiling(m, n, 2, 0, 16384, kNormH, n > kPostDefShortRowsN ? 16 : 64);
-    return make_tiling(m, n, 2, 0, 16384, kNormH);
+    return make_tiling(m, n, 2, 0, kNormWaves, kNormH);
 }
 
 // Blocks of 4 waves; the grid is padded to a multiple of the XCD count so
