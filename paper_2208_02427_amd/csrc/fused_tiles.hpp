@@ -160,7 +160,7 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
         load_row<double, V>(R.qring[PH], A.f64, q + PF, A.n, A.Ps, c.i0, c.vin);
 #pragma unroll
         for (int e = 0; e < V; ++e) pn[e] = ps[e] + (double)o[e];
-        if (q >= j0 && q <= j1) store_row<double, V>(A.psi_out, pn, q, A.Ps, c);
+        if (q >= j0 && q <= j1) store_row_nt<double, V>(A.nt != 0, A.psi_out, pn, q, A.Ps, c);
         if (q - 1 >= j0 && q - 1 <= j1) {
             double r[V];
             T r32[V];
@@ -172,13 +172,13 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
                 R.s2 = fma(r[e], r[e], R.s2);
                 R.mx = fmax(R.mx, fabs(r[e]));
             }
-            store_row<T, V>(A.rhs_out, r32, q - 1, A.Ps, c);
+            store_row_nt<T, V>(A.nt != 0, A.rhs_out, r32, q - 1, A.Ps, c);
         }
         copy<double, V>(R.pm, R.pc);
         copy<double, V>(R.pc, pn);
         copy<double, V>(R.fm, fq);
     } else if (q >= j0 && q <= j1) {
-        store_row<T, V>(A.uout, o, q, A.Ps, c);
+        store_row_nt<T, V>(A.nt != 0, A.uout, o, q, A.Ps, c);
     }
 
     if constexpr (RS) {

@@ -163,6 +163,7 @@ struct SweepArgs {
     const double* f64;
     T* rhs_out;
     double dcx, dcy, dd;
+    int nt;             // nonzero: the pass's row stores are nontemporal (streamed past the caches)
 };
 
 template <typename T>

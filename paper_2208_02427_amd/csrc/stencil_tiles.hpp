@@ -30,7 +30,7 @@ __device__ __forceinline__ void ldv(T (&x)[V], const T* p) {
     }
 }
 
-template <typename T, int V>
+template <typename T, int V, bool NT = false>
 __device__ __forceinline__ void stv(T* p, const T (&x)[V]) {
     using VT = typename VecT<T, V>::type;
     VT v;
@@ -40,7 +40,10 @@ __device__ __forceinline__ void stv(T* p, const T (&x)[V]) {
 #pragma unroll
         for (int e = 0; e < V; ++e) v[e] = x[e];
     }
-    *reinterpret_cast<VT*>(p) = v;
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, reinterpret_cast<VT*>(p));
+    else
+        *reinterpret_cast<VT*>(p) = v;
 }
 
 template <typename T, int V>
@@ -136,16 +139,30 @@ __device__ __forceinline__ void load_row(T (&x)[V], const T* base, int j, int n,
         zero<T, V>(x);
 }
 
-template <typename T, int V>
+template <typename T, int V, bool NT = false>
 __device__ __forceinline__ void store_row(T* base, const T (&x)[V], int j, int P, const Cols<V>& c) {
     T* p = base + (ptrdiff_t)j * P + c.i0;
     if (c.vin && c.all_out) {
-        stv<T, V>(p, x);
+        stv<T, V, NT>(p, x);
     } else {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-            if (c.cout[e]) p[e] = x[e];
+        for (int e = 0; e < V; ++e) {
+            if (!c.cout[e]) continue;
+            if constexpr (NT)
+                __builtin_nontemporal_store(x[e], p + e);
+            else
+                p[e] = x[e];
+        }
     }
+}
+
+// store_row with a wave-uniform runtime choice of nontemporal stores
+template <typename T, int V>
+__device__ __forceinline__ void store_row_nt(bool nt, T* base, const T (&x)[V], int j, int P, const Cols<V>& c) {
+    if (nt)
+        store_row<T, V, true>(base, x, j, P, c);
+    else
+        store_row<T, V, false>(base, x, j, P, c);
 }
 
 // Bilinear interpolation of a coarse correction, streamed with the fine rows.
