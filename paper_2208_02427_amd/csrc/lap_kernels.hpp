@@ -91,16 +91,21 @@ inline Tiling make_tiling(int m, int n, int V, int ty, int target = 0, int H = 2
 // two sweeps and the residual); a norm finalisation reduces the partials of
 // the kind that produced them.
 enum NormKind { NORM_PASS = 0, NORM_DEFECT = 1, NORM_POSTDEF = 2 };
-// The defect pass keeps chunks of >= 64 rows: on small grids (and so in
-// batches of them) shorter chunks leave each wavefront too little to stream.
+// The defect pass keeps chunks of >= 64 rows on levels of more than 257
+// rows, >= 16 below.  Grids whose whole FP32 cycle fits one workgroup's LDS
+// (up to ~15k nodes) take this pass at every outer step; in a batch they
+// share a launch that the row walk of their chunks makes latency-bound
+// (64-row chunks: ~67 us per launch; 16-row chunks: 512-grid batch
+// 15.9 -> 15.4 ms).
 constexpr int kDefectMinRows = 64;
+constexpr int kDefectShortRowsN = 257;
 // The post-smoothing + defect pass reads 2 * 2 + 1 halo rows above and below
 // each chunk: chunks of >= 64 rows up to 4097 rows (faster by 4% at 4097^2,
 // and by far in batches of small grids), of >= 16 rows beyond (the 16384
 // waves' chunks of 8193^2 are 36 rows; 64-row chunks were 1.5% slower).
 constexpr int kPostDefShortRowsN = 4097;
 inline Tiling norm_tiling(int m, int n, int kind = NORM_PASS) {
-    if (kind == NORM_DEFECT) return make_tiling(m, n, 1, 0, 16384, 2, kDefectMinRows);
+    if (kind == NORM_DEFECT) return make_tiling(m, n, 1, 0, 16384, 2, n <= kDefectShortRowsN ? 16 : kDefectMinRows);
     if (kind == NORM_POSTDEF) return make_tiling(m, n, 2, 0, 16384, kNormH, n > kPostDefShortRowsN ? 16 : 64);
     return make_tiling(m, n, 2, 0, kNormWaves, kNormH);
 }
