@@ -355,10 +355,12 @@ def run_serving_leg(args, ctx, torch, lap, dev):
         jobs = [Job(r.rid, r.arrival, r.m, r.n, r.tol, payload=device_request(torch, r, dev)) for r in reqs]
         nodes = {j.rid: (j.m - 2) * (j.n - 2) for j in jobs}
         sync()
-        stats = Server(DeviceBackend(ctx, precision="mixed"), max_active=256, burst=args.burst).run(jobs)
+        stats = Server(DeviceBackend(ctx, precision="mixed"), max_active=256, burst=args.burst,
+                       solo_max_nodes=args.solo_max_nodes).run(jobs)
         sm = stats.summary()
         sm["GLUP/s"] = None
         sm["burst"] = args.burst
+        sm["solo_max_nodes"] = args.solo_max_nodes
         res[str(int(rate))] = {"batched_mixed": sm}
         if rate in args.baseline_rates:
             def solve_one(job):
@@ -416,6 +418,8 @@ def main():
     ap.add_argument("--adi-iters", type=int, default=20)
     ap.add_argument("--serve-count", type=int, default=300)
     ap.add_argument("--burst", type=int, default=4, help="outer steps per serving tick when no request waits")
+    ap.add_argument("--solo-max-nodes", type=int, default=2049 * 2049,
+                    help="largest request (m*n) solved alone when it finds the device idle (0: never)")
     ap.add_argument("--rates", type=float, nargs="*", default=[100, 300, 1000, 3000, 10000])
     ap.add_argument("--baseline-rates", type=float, nargs="*", default=[100, 1000])
     args = ap.parse_args()

@@ -45,6 +45,7 @@ __device__ __forceinline__ void batch_fused_tile(const BatchItem& it, int lt, in
         A.dcx = it.cx;
         A.dcy = it.cy;
         A.dd = it.d;
+        A.rowpart = it.rowpart;
     }
     const bool hf = (it.flags & SW_F) != 0;
     switch (it.V) {

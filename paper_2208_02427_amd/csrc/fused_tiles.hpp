@@ -172,6 +172,18 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
                 R.s2 = fma(r[e], r[e], R.s2);
                 R.mx = fmax(R.mx, fabs(r[e]));
             }
+            if (A.rowpart && ((q - 1) % kRowBlock == 0 || q - 1 == j1)) {
+                // end of a block of kRowBlock rows (wave-uniform): its
+                // partials, summed in row order whatever chunk holds it
+                const double s = wave_sum(R.s2), m = wave_max(R.mx);
+                if ((threadIdx.x & 63) == 0) {
+                    const int b = A.rp_off + (q - 2) / kRowBlock;
+                    A.partials[2 * b] = s;
+                    A.partials[2 * b + 1] = m;
+                }
+                R.s2 = 0.0;
+                R.mx = 0.0;
+            }
             store_row_nt<T, V>(A.nt != 0, A.rhs_out, r32, q - 1, A.Ps, c);
         }
         copy<double, V>(R.pm, R.pc);
@@ -249,7 +261,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
     int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
     A.Ps = A.P;
     A.Pcs = A.Pc;
-    if ((chunk & 1) && (A.n & 1)) {
+    if ((chunk & 1) && (A.n & 1) && !((FL & SW_DEF) && A.rowpart)) {
         const ptrdiff_t last = (ptrdiff_t)(A.n - 1) * A.P, clast = (ptrdiff_t)(A.nc - 1) * A.Pc;
         if (A.uin) A.uin += last;
         if (A.uout) A.uout += last;
@@ -269,6 +281,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
         j0 = t0;
     }
     const int ipar = c.i0 & 1;
+    if constexpr ((FL & SW_DEF) != 0) A.rp_off = win * row_blocks(A.n);
     // input rows [L0, Lend]: the last stage must be exact on the chunk's rows
     // and, with the restriction, two rows around its first and last even row;
     // L0 is moved up one row if needed so the first step has parity JP0
@@ -321,6 +334,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
     for (int j = L0 + 1; j <= Lend - 1; j += PF)
         fused_turn<T, V, FL, NS, RS, JP0, 0>(A, R, c, j, j0, j1, Lend, ipar);
     if constexpr ((FL & (SW_NORM | SW_DEF)) != 0) {
+        if ((FL & SW_DEF) && A.rowpart) return;
         const double s = wave_sum(R.s2);
         const double mx = wave_max(R.mx);
         if (lane == 0) {

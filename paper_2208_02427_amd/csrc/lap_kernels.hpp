@@ -104,10 +104,32 @@ constexpr int kDefectShortRowsN = 257;
 // and by far in batches of small grids), of >= 16 rows beyond (the 16384
 // waves' chunks of 8193^2 are 36 rows; 64-row chunks were 1.5% slower).
 constexpr int kPostDefShortRowsN = 4097;
+// Levels of at most this many rows take the post-smoothing + defect pass's
+// norms per (window, block of 16 rows): one grid alone then walks 16-row
+// chunks (4x the waves of 64-row chunks: mixed solves of 129^2 / 257^2 /
+// 513^2 / 1025^2 grids 0.91 / 1.06 / 1.21 / 1.38 -> 0.62 / 0.73 / 0.85 /
+// 1.03 ms) while merged batch launches keep 64-row chunks (a 512-grid batch
+// with 16-row chunks: 15.4 -> 16.0 ms; with the block partials 15.6 ms),
+// and both reduce the same partials in the same order.
+constexpr int kRowPartN = 1025;
+constexpr int kRowBlock = 16;
+inline bool postdef_rowpart(int n) { return n <= kRowPartN; }
+__host__ __device__ inline int row_blocks(int n) { return (n - 2 + kRowBlock - 1) / kRowBlock; }
 inline Tiling norm_tiling(int m, int n, int kind = NORM_PASS) {
     if (kind == NORM_DEFECT) return make_tiling(m, n, 1, 0, 16384, 2, n <= kDefectShortRowsN ? 16 : kDefectMinRows);
     if (kind == NORM_POSTDEF) return make_tiling(m, n, 2, 0, 16384, kNormH, n > kPostDefShortRowsN ? 16 : 64);
     return make_tiling(m, n, 2, 0, kNormWaves, kNormH);
+}
+// Tiling of the post-smoothing + defect pass alone or in a merged launch.
+inline Tiling postdef_tiling(int m, int n, bool merged) {
+    if (postdef_rowpart(n)) return make_tiling(m, n, 2, merged ? 4 * kRowBlock : kRowBlock, 0, kNormH);
+    return norm_tiling(m, n, NORM_POSTDEF);
+}
+// Norm partials a finalisation of this kind reduces.
+inline int norm_partials(int m, int n, int kind) {
+    const Tiling t = norm_tiling(m, n, kind);
+    if (kind == NORM_POSTDEF && postdef_rowpart(n)) return t.nwin * row_blocks(n);
+    return t.ntiles;
 }
 
 // Blocks of 4 waves; the grid is padded to a multiple of the XCD count so
@@ -169,6 +191,10 @@ struct SweepArgs {
     T* rhs_out;
     double dcx, dcy, dd;
     int nt;             // nonzero: the pass's row stores are nontemporal (streamed past the caches)
+    // SW_DEF with rowpart: chunks of a multiple of kRowBlock rows walk downwards and the norm
+    // partials are per (window, block of kRowBlock rows), at win * row_blocks(n) + (row - 1) /
+    // kRowBlock, instead of per tile: the same sums whatever the chunk length (rp_off: set by the kernel)
+    int rowpart, rp_off;
 };
 
 template <typename T>
@@ -399,6 +425,7 @@ struct BatchItem {
     // f / bc: this and the next FP32 right-hand side, ec: coarse correction)
     const void* e;           // the FP32 level-0 buffer the post-smoothing starts from
     const double* f64;       // FP64 source (nullable)
+    int rowpart;             // norm partials per (window, row block) (see SweepArgs)
 };
 
 enum BatchKind { BK_SWEEP = 0, BK_RESTRICT, BK_COARSE, BK_FINALIZE, BK_RESNORM, BK_DEFECT, BK_ADI_ROWS, BK_ADI_COLS,

@@ -451,6 +451,9 @@ struct lap_grid {
     // graph cache
     hipGraphExec_t graph = nullptr;
     std::string graph_key;
+    std::vector<std::string> graph_seen;   // options of recent solves (a repeat captures the graph)
+    std::string graph_run_key;             // options of the running solve
+    bool graph_on = false;           // the running solve replays the graph
     std::vector<void*> allocs;
 };
 
@@ -470,7 +473,7 @@ struct Footprint {
 size_t max_tiles(int m, int n) {
     // the finest tiling any table entry may pick: V = 1, ty = 16
     int t = make_tiling(m, n, 1, 16).ntiles;
-    for (int k : {(int)NORM_PASS, (int)NORM_DEFECT, (int)NORM_POSTDEF}) t = std::max(t, norm_tiling(m, n, k).ntiles);
+    for (int k : {(int)NORM_PASS, (int)NORM_DEFECT, (int)NORM_POSTDEF}) t = std::max(t, norm_partials(m, n, k));
     return (size_t)t;
 }
 
@@ -1054,7 +1057,8 @@ hipError_t enq_postdef(lap_grid* g, const Op& op, double omega) {
     a.d = (float)c.d;
     a.inv_d = (float)c.inv_d;
     a.omega = (float)omega;
-    a.tl = norm_tiling(L.m, L.n, NORM_POSTDEF);
+    a.tl = postdef_tiling(L.m, L.n, false);
+    a.rowpart = postdef_rowpart(L.n) ? 1 : 0;
     a.psi_in = (const double*)op.in;
     a.psi_out = (double*)op.out;
     a.f64 = g->f64;
@@ -1214,7 +1218,7 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
                 return enq_coarse<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.out);
             return enq_coarse<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.out);
         case OP_FINALIZE:
-            return enq_finalize(g, norm_tiling(g->geo[0].m, g->geo[0].n, op.flags).ntiles);
+            return enq_finalize(g, norm_partials(g->geo[0].m, g->geo[0].n, op.flags));
         case OP_RESNORM:
             return enq_residual_norm<double>(g, l, (const double*)op.in, (const double*)op.f);
         case OP_DEFECT:
@@ -1404,12 +1408,32 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
         HIPCHK(hipMemcpyAsync(g->adi_tab, g->adi_host.data(), g->adi_host.size() * 8, hipMemcpyHostToDevice,
                               g->ctx->stream));
     }
+    // A grid's cycle graph is captured on its second solve with the same
+    // options: capturing and instantiating costs more than one solve of a
+    // small or medium grid saves by replaying (a request solved once, as in
+    // serving, never pays for it).
+    g->graph_on = false;
     if (use_graph(g, o)) {
         char key[128];
+        if (o.precision == LAP_FP64)
+            snprintf(key, sizeof key, "mg64:%d:%d:%.17g", o.nu1, o.nu2, o.omega);
+        else
+            snprintf(key, sizeof key, "mixed%s:%d:%d:%.17g", g->pdef ? "+pd" : "", o.nu1, o.nu2, o.omega);
+        const bool have = g->graph != nullptr && g->graph_key == key;
+        auto& seen = g->graph_seen;
+        const bool again = std::find(seen.begin(), seen.end(), std::string(key)) != seen.end();
+        g->graph_on = have || again;
+        if (!again) {
+            if (seen.size() >= 8) seen.erase(seen.begin());
+            seen.push_back(key);
+        }
+        g->graph_run_key = key;
+    }
+    if (g->graph_on) {
+        const std::string key = g->graph_run_key;
         hipError_t e;
         if (o.precision == LAP_FP64) {
-            snprintf(key, sizeof key, "mg64:%d:%d:%.17g", o.nu1, o.nu2, o.omega);
-            e = capture(g, key, [&]() {
+            e = capture(g, key.c_str(), [&]() {
                 HierView<double> H = view64(g);
                 std::vector<Op> ops;
                 plan_vcycle<double>(g, H, 0, o, true, PART_ALL, ops);
@@ -1417,8 +1441,7 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
             });
         } else {
             // two outer steps (psi[1] -> psi[0] -> psi[1]); step 0 runs without the graph
-            snprintf(key, sizeof key, "mixed%s:%d:%d:%.17g", g->pdef ? "+pd" : "", o.nu1, o.nu2, o.omega);
-            e = capture(g, key, [&]() {
+            e = capture(g, key.c_str(), [&]() {
                 std::vector<Op> ops;
                 plan_mixed_step(g, o, 1, false, g->e_idx, PART_ALL, ops);
                 plan_mixed_step(g, o, 0, false, g->e_idx, PART_ALL, ops);
@@ -1488,7 +1511,7 @@ hipError_t step(lap_grid* g, const lap_opts& o, int part = PART_ALL) {
     const int s = g->step_idx;
     if (part != PART_HEAD) g->step_idx++;
     lap_ctx* c = g->ctx;
-    const bool graph = use_graph(g, o) && part == PART_ALL;
+    const bool graph = g->graph_on && part == PART_ALL;
     if (graph && o.method == LAP_MG) {
         if (o.precision == LAP_FP64) return hipGraphLaunch(g->graph, c->stream);
         if (s % 2 == 1) {               // the mixed graph covers steps s (odd) and s + 1
@@ -2221,12 +2244,13 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
         case OP_RESNORM: t = norm_tiling(g->geo[0].m, g->geo[0].n); break;
         case OP_DEFECT: t = norm_tiling(g->geo[0].m, g->geo[0].n, NORM_DEFECT); break;
         case OP_POSTDEF:
-            t = norm_tiling(L.m, L.n, NORM_POSTDEF);
+            t = postdef_tiling(L.m, L.n, true);
+            it.rowpart = postdef_rowpart(L.n) ? 1 : 0;
             it.e = g->l32[0].u[op.parity];
             it.f64 = g->f64;
             it.flags = SW_F;
             break;
-        case OP_FINALIZE: t = norm_tiling(g->geo[0].m, g->geo[0].n, op.flags); break;
+        case OP_FINALIZE: t.ntiles = norm_partials(g->geo[0].m, g->geo[0].n, op.flags); break;
         case OP_ADI_ROWS:
         case OP_ADI_COLS: {
             const LineArgs la = adi_args(g, op.omega, op.flags, op.kind == OP_ADI_ROWS ? 0 : 1, op.parity);

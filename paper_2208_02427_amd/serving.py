@@ -16,11 +16,16 @@ Policy (host side) over the library's tick primitive (lap_batch_step):
 * when no request is waiting, a tick runs `burst` outer steps back to back
   before reading the grids' state (a grid that converges inside the burst
   stops on the device), trading admission delay for fewer host round trips;
+* a request that finds the device idle and nobody waiting, and is small
+  enough (`solo_max_nodes`), is solved alone to its tolerance in one library
+  call (single-grid graph replay, no merged plan, one status read per step
+  instead of one per tick); requests arriving meanwhile queue for at most
+  that solve;
 * latency of a request = time its result is readable - its arrival time.
 
 The backend is any object with footprint(m, n) -> bytes, free_bytes(),
 admit(request) -> handle, tick(handles, steps) -> (done flags, infos), and
-retire(handle) -> result.  `DeviceBackend` drives liblap; tests drive the
+retire(handle) -> result, and optionally solve_alone(handle, request) -> info.  `DeviceBackend` drives liblap; tests drive the
 policy with a simulated backend on a virtual clock.
 """
 from __future__ import annotations
@@ -45,6 +50,7 @@ class Job:
     status: int | None = None
     result: object = None
     handle: object = None
+    stepped: bool = False         # has taken part in a batched tick
 
     @property
     def latency(self):
@@ -58,6 +64,7 @@ class ServeStats:
     wall: float = 0.0
     max_active: int = 0
     busy_ticks: int = 0
+    solo: int = 0                 # requests solved alone (idle device, nobody waiting)
 
     def summary(self, lup_of=None):
         lat = np.array([j.latency for j in self.jobs if j.latency is not None])
@@ -73,6 +80,7 @@ class ServeStats:
             "max_active": self.max_active,
             "wall_s": self.wall,
             "failed": sum(1 for j in self.jobs if j.status not in (None, 0)),
+            "solo": self.solo,
         }
         if lup_of is not None and self.wall > 0:
             out["GLUP/s"] = sum(lup_of(j) for j in self.jobs if j.finished is not None) / self.wall / 1e9
@@ -82,11 +90,13 @@ class ServeStats:
 class Server:
     """Continuous batching with admission by footprint."""
 
-    def __init__(self, backend, max_active: int = 512, clock=time.perf_counter, burst: int = 1):
+    def __init__(self, backend, max_active: int = 512, clock=time.perf_counter, burst: int = 1,
+                 solo_max_nodes: int = 2049 * 2049):
         self.backend = backend
         self.max_active = max_active
         self.clock = clock
         self.burst = max(1, int(burst))
+        self.solo_max_nodes = solo_max_nodes if hasattr(backend, "solve_alone") else 0
         self.queue: list[Job] = []
         self.active: list[Job] = []
 
@@ -106,22 +116,30 @@ class Server:
             self.active.append(job)
 
     def tick(self, stats: ServeStats | None = None):
-        """Admit what fits, advance every active grid by one outer step,
-        retire the finished ones.  Returns the finished jobs."""
+        """Admit what fits, advance every active grid by one outer step (or
+        `burst` steps), retire the finished ones; a lone small request on an
+        idle device is solved alone instead.  Returns the finished jobs."""
         self._admit(self.clock())
         if not self.active:
             return []
+        if len(self.active) == 1 and not self.queue:
+            job = self.active[0]
+            if not job.stepped and job.m * job.n <= self.solo_max_nodes:
+                info = self.backend.solve_alone(job.handle, job)
+                self._retire(job, info)
+                self.active = []
+                if stats is not None:
+                    stats.ticks += 1
+                    stats.solo += 1
+                    stats.max_active = max(stats.max_active, 1)
+                return [job]
         steps = 1 if self.queue else self.burst
         done, infos = self.backend.tick([j.handle for j in self.active], steps)
-        now = self.clock()
         finished, still = [], []
         for job, d, info in zip(self.active, done, infos):
+            job.stepped = True
             if d:
-                job.result = self.backend.retire(job.handle)
-                job.finished = self.clock()
-                job.iterations = info.get("iterations")
-                job.status = info.get("status")
-                job.handle = None
+                self._retire(job, info)
                 finished.append(job)
             else:
                 still.append(job)
@@ -130,8 +148,14 @@ class Server:
             stats.ticks += 1
             stats.busy_ticks += 1
             stats.max_active = max(stats.max_active, len(self.active) + len(finished))
-        del now
         return finished
+
+    def _retire(self, job, info):
+        job.result = self.backend.retire(job.handle)
+        job.finished = self.clock()
+        job.iterations = info.get("iterations")
+        job.status = info.get("status")
+        job.handle = None
 
     def run(self, jobs: list[Job], t0: float | None = None, idle_sleep: float = 0.0) -> ServeStats:
         """Serve a whole stream: job.arrival is relative to the start."""
@@ -213,6 +237,9 @@ class DeviceBackend:
 
     def tick(self, grids, steps=1):
         return self.ctx.batch_step(grids, precision=self.precision, steps=steps)
+
+    def solve_alone(self, g, job):
+        return g.solve("mg", precision=self.precision, tol=job.tol, max_iter=1000)
 
     def retire(self, g):
         out = g.read() if self.keep_results else None

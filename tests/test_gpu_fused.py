@@ -214,3 +214,30 @@ def test_mixed_post_defect_launch_counts():
     assert ctx.kernel_stats(KC_PRE, fine_only=True)["launches"] == k
     g.destroy()
     ctx.close()
+
+
+def test_mixed_norms_alone_equal_batched():
+    """Alone, the post + defect pass of a level of <= 1025 rows walks 16-row
+    chunks; in a merged batch launch, 64-row chunks.  Its norm partials are
+    kept per (window, row) there, so both reduce the same values in the same
+    order: the reported residuals are bitwise equal, as are the iterates and
+    the iteration counts (taller levels share one tiling)."""
+    torch, lap = need_gpu()
+    probs = W.ragged_batch(count=8, lo=97, hi=513, seed=13, bumps=True)
+    probs.append(W.square_problem(1281, seed=2, bumps=True, bump_seed=3))
+    say("norms alone/batched", [(p.m, p.n) for p in probs])
+    assert any(p.n <= 1025 for p in probs) and any(p.n > 1025 for p in probs)
+    ctx = lap.Context(arena_bytes=1 << 30)
+    gs = [ctx.grid(to_dev(torch, p.psi0), to_dev(torch, p.f), p.dx, p.dy) for p in probs]
+    infos = ctx.solve_batch(gs, method="mg", precision="mixed", tol=1e-10, max_iter=60)
+    outs = [g.read().cpu().numpy() for g in gs]
+    ctx.close()
+    ctx2 = lap.Context(arena_bytes=1 << 30)
+    for p, ib, ub in zip(probs, infos, outs):
+        g = ctx2.grid(to_dev(torch, p.psi0), to_dev(torch, p.f), p.dx, p.dy)
+        ia = g.solve("mg", precision="mixed", tol=1e-10, max_iter=60)
+        assert ia["status"] == 0 and ia["iterations"] == ib["iterations"]
+        assert ia["rel_res_l2"] == ib["rel_res_l2"] and ia["res_linf"] == ib["res_linf"], (p.m, p.n)
+        assert np.array_equal(g.read().cpu().numpy(), ub)
+        g.destroy()
+    ctx2.close()

@@ -89,10 +89,18 @@ def test_mg_fp64_cycles(m, n, k):
 
 @pytest.mark.parametrize("use_graph", [True, False])
 def test_mg_fp64_full_solve_matches_oracle(use_graph):
+    """With graphs on, the first solve of a grid runs eagerly and a repeat
+    with the same options replays the captured cycle: both are checked."""
     say("mg64 full", use_graph)
+    torch, lap, c = ctx()
     p = W.square_problem(257, seed=2, bumps=True, bump_seed=3)
     g = make_grid(p.psi0, p.f, p.dx, p.dy)
     info = g.solve("mg", tol=1e-10, max_iter=50, use_graph=use_graph)
+    first = g.read().cpu().numpy()
+    g.write(to_dev(torch, p.psi0))
+    info2 = g.solve("mg", tol=1e-10, max_iter=50, use_graph=use_graph)
+    assert info2["iterations"] == info["iterations"]
+    assert np.array_equal(g.read().cpu().numpy(), first)
     u_ref, k_ref, h_ref = osolve.mg_solve(p.psi0, p.f, p.dx, p.dy, tol=1e-10)
     assert info["status"] == 0
     assert info["iterations"] == k_ref

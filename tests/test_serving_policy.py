@@ -61,6 +61,21 @@ class SimBackend:
         self.clock.t += dt
 
 
+class SoloBackend(SimBackend):
+    """SimBackend that can also solve one grid alone: its steps back to back
+    with no per-tick round trip."""
+
+    def __init__(self, *a, **kw):
+        super().__init__(*a, **kw)
+        self.solo = []
+
+    def solve_alone(self, h, job):
+        self.solo.append(job.rid)
+        self.clock.t += job.payload * (self.tick_base + self.per_grid)
+        h["left"] = 0
+        return {"iterations": job.payload, "status": 0}
+
+
 def jobs_from_stream(rate, count, seed=5, lo=17, hi=257):
     reqs = W.poisson_requests(rate, count, seed=seed, lo=lo, hi=hi)
     return [Job(r.rid, r.arrival, r.m, r.n, r.tol, payload=7 if r.tol < 1e-9 else 5) for r in reqs]
@@ -150,3 +165,37 @@ def test_burst_falls_back_to_single_steps_when_requests_wait():
     Server(be, clock=clk, burst=4).run(jobs)
     # while others queue, ticks are single steps; the last job runs alone with bursts
     assert be.steps[0] == 1 and be.steps[-1] == 4
+
+
+def test_lone_small_request_is_solved_alone():
+    """A request that finds the device idle and nobody waiting is solved alone
+    (no per-tick round trips); under load the same requests are batched, and
+    requests above the size limit never go alone."""
+    res = {}
+    for rate in (20.0, 20000.0):
+        clk = Clock()
+        be = SoloBackend(clk, pool=10**9, tick_base=2e-4, per_grid=1e-5, sync=3e-4)
+        jobs = jobs_from_stream(rate=rate, count=100)
+        stats = Server(be, clock=clk).run(jobs)
+        s = stats.summary()
+        assert s["completed"] == 100 and s["solo"] == len(be.solo)
+        assert all(j.iterations == j.payload for j in jobs)
+        res[rate] = (s, max(be.batches) if be.batches else 0)
+    assert res[20.0][0]["solo"] > 80               # nearly every request arrives to an idle device
+    assert res[20000.0][0]["solo"] < 10 and res[20000.0][1] > 1
+    clk = Clock()
+    be = SoloBackend(clk, pool=10**9)
+    jobs = [Job(0, 0.0, 129, 129, 1e-10, payload=3), Job(1, 1.0, 33, 33, 1e-10, payload=3)]
+    Server(be, clock=clk, solo_max_nodes=65 * 65).run(jobs)
+    assert be.solo == [1] and be.batches == [1, 1, 1]    # 129^2 above the limit: three batched ticks
+
+
+def test_solo_latency_beats_ticks_at_low_load():
+    res = {}
+    for solo in (0, 2049 * 2049):
+        clk = Clock()
+        be = SoloBackend(clk, pool=10**9, tick_base=2e-4, per_grid=1e-5, sync=3e-4)
+        jobs = jobs_from_stream(rate=20.0, count=100)
+        res[solo] = Server(be, clock=clk, solo_max_nodes=solo).run(jobs).summary()
+    assert res[0]["solo"] == 0
+    assert res[2049 * 2049]["p50_ms"] < res[0]["p50_ms"]
