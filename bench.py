@@ -418,7 +418,7 @@ def main():
     ap.add_argument("--adi-iters", type=int, default=20)
     ap.add_argument("--serve-count", type=int, default=300)
     ap.add_argument("--burst", type=int, default=4, help="outer steps per serving tick when no request waits")
-    ap.add_argument("--solo-max-nodes", type=int, default=2049 * 2049,
+    ap.add_argument("--solo-max-nodes", type=int, default=4097 * 4097,
                     help="largest request (m*n) solved alone when it finds the device idle (0: never)")
     ap.add_argument("--rates", type=float, nargs="*", default=[100, 300, 1000, 3000, 10000])
     ap.add_argument("--baseline-rates", type=float, nargs="*", default=[100, 1000])

@@ -91,7 +91,7 @@ class Server:
     """Continuous batching with admission by footprint."""
 
     def __init__(self, backend, max_active: int = 512, clock=time.perf_counter, burst: int = 1,
-                 solo_max_nodes: int = 2049 * 2049):
+                 solo_max_nodes: int = 4097 * 4097):
         self.backend = backend
         self.max_active = max_active
         self.clock = clock
