@@ -166,6 +166,7 @@ def run_gpu(args):
     # checked in the GPU tests; here record the library's own FP64 residual
     l2, linf = g.residual()
     out["final_res_l2"] = l2
+    out["residual_kernel"] = run_residual_leg(ctx, g, lap)
     g.destroy()
 
     if args.quick:
@@ -212,6 +213,24 @@ def run_gpu(args):
     return out, levels
 
 
+def run_residual_leg(ctx, g, lap, reps=20):
+    """The FP64 residual-norm kernel alone (lap_residual: r = f - L_h u and its
+    norms, u and f read once): HIP events around each launch on the
+    library's stream."""
+    KC_RESIDUAL = 8
+    g.residual()
+    ctx.set_timing(True)
+    ctx.reset_stats()
+    for _ in range(reps):
+        g.residual()
+    st = ctx.kernel_stats(KC_RESIDUAL)
+    ctx.set_timing(False)
+    ms = st["device_ms"] / max(1, st["launches"])
+    gbs = st["alg_bytes"] / max(1, st["launches"]) / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    return {"launches": st["launches"], "avg_launch_ms": ms, "alg_bytes_per_launch": st["alg_bytes"] / max(1, st["launches"]),
+            "achieved_GB/s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+
+
 def run_mixed_leg(N, ctx, torch, lap, dev):
     """Mixed precision vs FP64 multigrid on the N x N grid with the 32-bump
     source: time to a 1e-10 relative residual (the second of two solves of
@@ -239,6 +258,7 @@ def run_mixed_leg(N, ctx, torch, lap, dev):
     um = gb.read()
     res["max_abs_mixed_vs_fp64"] = float((um - u64).abs().max().item())
     res["speedup_mixed_over_fp64"] = res["fp64"]["time_to_tol_s"] / res["mixed"]["time_to_tol_s"]
+    res["residual_kernel_with_f"] = run_residual_leg(ctx, gb, lap)
     gb.destroy()
     return res
 
@@ -469,8 +489,8 @@ def main():
         "rel_res": out["rel_res"],
         "roofline": out["roofline"],
     }
-    for k in ("solve_hbm", "copy_probe", "mixed", "sor", "mg_4097", "ragged_batch", "serving", "kernels_fine",
-              "autotune"):
+    for k in ("solve_hbm", "residual_kernel", "copy_probe", "mixed", "sor", "mg_4097", "ragged_batch", "serving",
+              "kernels_fine", "autotune"):
         if k in out:
             line[k] = out[k]
     if not args.no_cpu:

@@ -107,7 +107,9 @@ typedef struct lap_opts {
     int32_t nu1, nu2;     /* MG pre- and post-smoothing sweeps (default 2, 2)             */
     int32_t check_every;  /* SOR/ADI: test the stopping rule every k iterations (>= 1)    */
     int32_t adi_form;     /* LAP_ADI_RELAX_AFTER or LAP_ADI_RELAX_INSIDE                  */
-    int32_t use_graph;    /* MG: replay a captured hipGraph per cycle (1) or launch (0)   */
+    int32_t use_graph;    /* MG: replay a captured hipGraph per cycle (1) or launch (0);
+                           * a grid's graph is captured on its second solve with the same
+                           * method options (its first solve launches directly)           */
 } lap_opts;
 
 /* Fill *o with the defaults: MG, FP64, omega 1, tol 1e-10, max_iter 100,

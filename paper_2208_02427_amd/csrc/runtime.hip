@@ -1910,7 +1910,8 @@ lap_status lap_residual_ex(lap_grid* g, double* l2, double* linf) {
     a.cy = c.cy;
     a.d = c.d;
     a.tl = norm_tiling(L.m, L.n);
-    HIPCHK(launch_residual<double>(a, g->ctx->stream));
+    const double bytes = (g->f64 ? 16.0 : 8.0) * nint(L);   // u (and f) read once
+    HIPCHK(g->ctx->timed(KC_RESIDUAL, true, bytes, [&]() { return launch_residual<double>(a, g->ctx->stream); }));
     HIPCHK(launch_finalize(g->partials, a.tl.ntiles, nullptr, g->norm_out, 1, g->ctx->stream));
     double h[2];
     HIPCHK(hipMemcpyAsync(h, g->norm_out, 16, hipMemcpyDeviceToHost, g->ctx->stream));
