@@ -47,6 +47,9 @@ CASES = [
     (257, 129, "fp64", 0, 2, True),
     (129, 129, "fp64", 4, 2, True),
     (65, 33, "mixed", 2, 2, True),
+    (129, 257, "mixed", 4, 2, True),     # post + defect pass after two pre passes
+    (257, 129, "mixed", 2, 2, False),
+    (4097, 129, "mixed", 2, 2, True),    # many windows, 16-row chunks with row-block norm partials
 ]
 
 
