@@ -7,7 +7,7 @@
 namespace lap {
 
 
-template <typename T, int FLS>
+template <typename T, int FLS, int V>
 __device__ __forceinline__ void batch_fused_tile(const BatchItem& it, int lt, int lane) {
     SweepArgs<T> A{};
     A.uin = (const T*)it.in;
@@ -47,22 +47,22 @@ __device__ __forceinline__ void batch_fused_tile(const BatchItem& it, int lt, in
         A.dd = it.d;
         A.rowpart = it.rowpart;
     }
-    const bool hf = (it.flags & SW_F) != 0;
-    switch (it.V) {
-        case 1: hf ? fused_tile<T, 1, FLS | SW_F>(A, lt, lane) : fused_tile<T, 1, FLS>(A, lt, lane); break;
-        case 2: hf ? fused_tile<T, 2, FLS | SW_F>(A, lt, lane) : fused_tile<T, 2, FLS>(A, lt, lane); break;
-        default: hf ? fused_tile<T, 4, FLS | SW_F>(A, lt, lane) : fused_tile<T, 4, FLS>(A, lt, lane); break;
-    }
+    if (it.flags & SW_F)
+        fused_tile<T, V, FLS | SW_F>(A, lt, lane);
+    else
+        fused_tile<T, V, FLS>(A, lt, lane);
 }
 
-template <typename T, int FLS>
+// One kernel per columns-per-lane V (the host groups items by V), so a
+// launch is compiled, and occupies registers, for its own V only.
+template <typename T, int FLS, int V>
 __global__ __launch_bounds__(kBlock) void k_batch_fused(const BatchItem* items, const int* tmap, int total) {
     const int nw = gridDim.x * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
     for (int t = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + (int)(threadIdx.x >> 6); t < total; t += nw) {
         const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
-        batch_fused_tile<T, FLS>(it, t - it.tile0, lane);
+        batch_fused_tile<T, FLS, V>(it, t - it.tile0, lane);
     }
 }
 
@@ -72,14 +72,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(const BatchItem* items, 
     X(SW_RESTRICT | SW_ZERO) X(SW_RESTRICT | SW_NORM) X(SW_RESTRICT | SW_TWO)              \
     X(SW_RESTRICT | SW_TWO | SW_ZERO) X(SW_RESTRICT | SW_TWO | SW_NORM) X(SW_DEF | SW_PROLONG | SW_TWO)
 
-template <typename T>
-static hipError_t launch_batch_fused_t(int fl, const BatchItem* items, const int* tmap, int total, int blocks,
+template <typename T, int V>
+static hipError_t launch_batch_fused_v(int fl, const BatchItem* items, const int* tmap, int total, int blocks,
                                        hipStream_t s) {
     const dim3 g(blocks), b(kBlock);
     switch (fl) {
-#define LAP_CASE(F)                                                    \
-    case (F):                                                          \
-        k_batch_fused<T, (F)><<<g, b, 0, s>>>(items, tmap, total);     \
+#define LAP_CASE(F)                                                       \
+    case (F):                                                             \
+        k_batch_fused<T, (F), V><<<g, b, 0, s>>>(items, tmap, total);     \
         break;
         LAP_BATCH_FUSED_FLAGS(LAP_CASE)
 #undef LAP_CASE
@@ -88,12 +88,23 @@ static hipError_t launch_batch_fused_t(int fl, const BatchItem* items, const int
     return hipGetLastError();
 }
 
-hipError_t launch_batch_fused(int dt, int step_flags, const BatchItem* items, const int* tmap, int total, int blocks,
-                              hipStream_t s) {
+template <typename T>
+static hipError_t launch_batch_fused_t(int fl, int V, const BatchItem* items, const int* tmap, int total, int blocks,
+                                       hipStream_t s) {
+    switch (V) {
+        case 1: return launch_batch_fused_v<T, 1>(fl, items, tmap, total, blocks, s);
+        case 2: return launch_batch_fused_v<T, 2>(fl, items, tmap, total, blocks, s);
+        case 4: return launch_batch_fused_v<T, 4>(fl, items, tmap, total, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_fused(int dt, int step_flags, int V, const BatchItem* items, const int* tmap, int total,
+                              int blocks, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     if (blocks < 1) blocks = 1;
-    return dt == 0 ? launch_batch_fused_t<double>(step_flags, items, tmap, total, blocks, s)
-                   : launch_batch_fused_t<float>(step_flags, items, tmap, total, blocks, s);
+    return dt == 0 ? launch_batch_fused_t<double>(step_flags, V, items, tmap, total, blocks, s)
+                   : launch_batch_fused_t<float>(step_flags, V, items, tmap, total, blocks, s);
 }
 
 }  // namespace lap

@@ -441,8 +441,8 @@ constexpr int ADI_SEG = 2;
 constexpr int ADI_CODE_SHIFT = 2;   // segmented: size code (seg_code) in bits 2..3
 hipError_t launch_batch_adi(int kind, int flags, const BatchItem* items, const int* tmap, int total, int blocks,
                             hipStream_t s);
-// merged fused passes (fused_kernels.hip); step_flags without SW_F
-hipError_t launch_batch_fused(int dt, int step_flags, const BatchItem* items, const int* tmap, int total,
+// merged fused passes (batch_fused.hip); step_flags without SW_F; every item has V columns per lane
+hipError_t launch_batch_fused(int dt, int step_flags, int V, const BatchItem* items, const int* tmap, int total,
                               int blocks, hipStream_t s);
 
 }  // namespace lap

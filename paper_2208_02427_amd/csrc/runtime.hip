@@ -2131,6 +2131,7 @@ extern "C" lap_status lap_op_adi_half(int32_t dtype, int32_t m, int32_t n, int32
 // ------------------------------------------------------------------ batches
 struct MergedLaunch {
     int kind, dt, flags;     // BatchKind, dtype, step flags of a sweep
+    int V;                   // fused passes: columns per lane of every item
     int cls;                 // kernel class for timing
     bool fine;
     int count, total, blocks;
@@ -2368,21 +2369,32 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
     lap_ctx::Plan* p = new lap_ctx::Plan();
     for (auto& kv : groups) {
         auto& v = kv.second;
-        // one merged launch per (kind, dtype, step flags) inside a key (normally exactly one)
-        std::map<std::tuple<int, int, int>, std::vector<std::pair<lap_grid*, Op>>> sub;
-        for (auto& go : v) sub[std::make_tuple(go.second.kind, go.second.dt, go.second.flags & ~SW_F)].push_back(go);
+        // one merged launch per (kind, dtype, step flags) inside a key (normally
+        // exactly one), fused passes also per columns-per-lane V: each V is a
+        // kernel of its own, so a launch occupies the registers of its own V
+        // only (one kernel for all three ran at the V = 4 variant's occupancy)
+        using GoIt = std::pair<std::pair<lap_grid*, Op>, BatchItem>;
+        std::map<std::tuple<int, int, int, int>, std::vector<GoIt>> sub;
+        for (auto& go : v) {
+            const BatchItem it = make_item(go.first, go.second, o, gs.size());
+            const int vkey = batch_kind(go.second) == BK_FUSED ? it.V : 0;
+            sub[std::make_tuple(go.second.kind, go.second.dt, go.second.flags & ~SW_F, vkey)].push_back({go, it});
+        }
         for (auto& skv : sub) {
             MergedLaunch L{};
-            L.kind = batch_kind(skv.second[0].second);
+            const Op& op0 = skv.second[0].first.second;
+            L.kind = batch_kind(op0);
             L.dt = std::get<1>(skv.first);
             L.flags = std::get<2>(skv.first);
+            L.V = std::get<3>(skv.first);
             L.off = p->items.size();
             L.toff = p->tmap.size();
-            L.cls = kclass_of(skv.second[0].second);
-            L.fine = skv.second[0].second.level == 0;
+            L.cls = kclass_of(op0);
+            L.fine = op0.level == 0;
             int tile0 = 0;
-            for (auto& go : skv.second) {
-                BatchItem it = make_item(go.first, go.second, o, gs.size());
+            for (auto& gi : skv.second) {
+                const auto& go = gi.first;
+                BatchItem it = gi.second;
                 it.tile0 = tile0;
                 if (L.kind == BK_SUBTREE) {
                     const Op& op = go.second;
@@ -2472,7 +2484,7 @@ hipError_t run_plan_launches(lap_ctx* c, lap_ctx::Plan* p) {
             if (L.kind == BK_SUBTREE) return launch_batch_subtree(L.dt, p->dev + L.off, L.count, L.lds, c->stream);
             const int32_t* tm = p->tmap_dev + L.toff;
             if (L.kind == BK_FUSED)
-                return launch_batch_fused(L.dt, L.flags, p->dev + L.off, tm, L.total, L.blocks, c->stream);
+                return launch_batch_fused(L.dt, L.flags, L.V, p->dev + L.off, tm, L.total, L.blocks, c->stream);
             return launch_batch(L.kind, L.dt, L.flags, p->dev + L.off, tm, L.count, L.total, L.blocks, c->stream);
         }));
     }
