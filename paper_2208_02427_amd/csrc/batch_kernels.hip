@@ -112,11 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_resnorm(const BatchItem* items
         A.cy = it.cy;
         A.d = it.d;
         A.tl = item_tiling(it);
-        switch (it.V) {                                     // the canonical norm tiling's V
-            case 1: residual_tile<double, 1>(A, t - it.tile0, lane); break;
-            case 2: residual_tile<double, 2>(A, t - it.tile0, lane); break;
-            default: residual_tile<double, 4>(A, t - it.tile0, lane); break;
-        }
+        residual_tile<double, kNormPassV>(A, t - it.tile0, lane);   // the canonical norm tiling
     }
 }
 
@@ -141,11 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_defect(const BatchItem* items,
         A.cy = it.cy;
         A.d = it.d;
         A.tl = item_tiling(it);
-        switch (it.V) {                                     // the canonical norm tiling's V
-            case 1: defect_tile<1>(A, t - it.tile0, lane); break;
-            case 2: defect_tile<2>(A, t - it.tile0, lane); break;
-            default: defect_tile<4>(A, t - it.tile0, lane); break;
-        }
+        defect_tile<kNormDefectV>(A, t - it.tile0, lane);   // the canonical defect tiling
     }
 }
 

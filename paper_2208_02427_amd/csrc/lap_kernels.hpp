@@ -115,10 +115,16 @@ constexpr int kRowPartN = 1025;
 constexpr int kRowBlock = 16;
 inline bool postdef_rowpart(int n) { return n <= kRowPartN; }
 __host__ __device__ inline int row_blocks(int n) { return (n - 2 + kRowBlock - 1) / kRowBlock; }
+// Columns per lane of the stencil passes' and the defect correction's
+// canonical tilings (the merged batch kernels of the residual norms and the
+// defect correction are compiled for these only).
+constexpr int kNormPassV = 2;
+constexpr int kNormDefectV = 1;
 inline Tiling norm_tiling(int m, int n, int kind = NORM_PASS) {
-    if (kind == NORM_DEFECT) return make_tiling(m, n, 1, 0, 16384, 2, n <= kDefectShortRowsN ? 16 : kDefectMinRows);
+    if (kind == NORM_DEFECT)
+        return make_tiling(m, n, kNormDefectV, 0, 16384, 2, n <= kDefectShortRowsN ? 16 : kDefectMinRows);
     if (kind == NORM_POSTDEF) return make_tiling(m, n, 2, 0, 16384, kNormH, n > kPostDefShortRowsN ? 16 : 64);
-    return make_tiling(m, n, 2, 0, kNormWaves, kNormH);
+    return make_tiling(m, n, kNormPassV, 0, kNormWaves, kNormH);
 }
 // Tiling of the post-smoothing + defect pass alone or in a merged launch.
 inline Tiling postdef_tiling(int m, int n, bool merged) {

@@ -2377,7 +2377,13 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
         std::map<std::tuple<int, int, int, int>, std::vector<GoIt>> sub;
         for (auto& go : v) {
             const BatchItem it = make_item(go.first, go.second, o, gs.size());
-            const int vkey = batch_kind(go.second) == BK_FUSED ? it.V : 0;
+            const int bk = batch_kind(go.second);
+            const int vkey = bk == BK_FUSED ? it.V : 0;
+            // the merged residual-norm and defect kernels are built for the canonical V only
+            if ((bk == BK_RESNORM && it.V != kNormPassV) || (bk == BK_DEFECT && it.V != kNormDefectV)) {
+                delete p;
+                return fail(LAP_EINVAL, "internal error: a norm item without its canonical tiling");
+            }
             sub[std::make_tuple(go.second.kind, go.second.dt, go.second.flags & ~SW_F, vkey)].push_back({go, it});
         }
         for (auto& skv : sub) {
