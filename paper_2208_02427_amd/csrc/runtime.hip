@@ -1036,6 +1036,7 @@ constexpr int kPostDefFlags = SW_DEF | SW_PROLONG | SW_TWO | SW_F;
 double postdef_bytes_per_node(bool with_f) { return 4.0 + 1.0 + 4.0 + 8.0 + 8.0 + 4.0 + (with_f ? 8.0 : 0.0); }
 
 hipError_t enq_postdef(lap_grid* g, const Op& op, double omega) {
+    if ((op.parity != 0 && op.parity != 1) || g->geo.size() < 2) return hipErrorInvalidValue;
     const LevelGeo& L = g->geo[0];
     const LevelGeo& C = g->geo[1];
     const Coef c = coef(L.dx, L.dy);
@@ -2248,7 +2249,7 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
         case OP_POSTDEF:
             t = postdef_tiling(L.m, L.n, true);
             it.rowpart = postdef_rowpart(L.n) ? 1 : 0;
-            it.e = g->l32[0].u[op.parity];
+            it.e = (op.parity == 0 || op.parity == 1) ? g->l32[0].u[op.parity] : nullptr;
             it.f64 = g->f64;
             it.flags = SW_F;
             break;
@@ -2380,9 +2381,10 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
             const int bk = batch_kind(go.second);
             const int vkey = bk == BK_FUSED ? it.V : 0;
             // the merged residual-norm and defect kernels are built for the canonical V only
-            if ((bk == BK_RESNORM && it.V != kNormPassV) || (bk == BK_DEFECT && it.V != kNormDefectV)) {
+            if ((bk == BK_RESNORM && it.V != kNormPassV) || (bk == BK_DEFECT && it.V != kNormDefectV) ||
+                (go.second.kind == OP_POSTDEF && it.e == nullptr)) {
                 delete p;
-                return fail(LAP_EINVAL, "internal error: a norm item without its canonical tiling");
+                return fail(LAP_EINVAL, "internal error: a norm item without its canonical tiling or input");
             }
             sub[std::make_tuple(go.second.kind, go.second.dt, go.second.flags & ~SW_F, vkey)].push_back({go, it});
         }
