@@ -54,7 +54,7 @@ FINE_LABELS = {
            "weighting (finest level, f = 0, canonical norm tiling)",
     "two": "k_fused<double,V,36>: bilinear correction + two red-black sweeps (finest level, f = 0)",
 }
-ALL_CLASSES = range(12)
+ALL_CLASSES = range(13)
 
 
 def lup_per_cycle(levels, nu1=2, nu2=2):

@@ -144,8 +144,11 @@ lap_status lap_ctx_usage(lap_ctx* ctx, size_t* used, size_t* largest_free);
  * lines, 8 residual, 9 small-level subtree (one launch per sub-V-cycle; its
  * bytes are the top level's right-hand side read and result written),
  * 10 fused pre-smoothing pass (one or two sweeps + residual + full
- * weighting), 11 fused two-sweep pass (post-smoothing, with or without the
- * prolongation).  `fine_only` selects the finest-level bucket.
+ * weighting), 11 fused two-sweep pass with the prolongation (post-smoothing),
+ * 12 fused two-sweep pass without a transfer (red-black SOR, further
+ * smoothing passes).  Class 3 also holds the mixed loop's fused FP32
+ * post-smoothing + FP64 defect pass.  `fine_only` selects the finest-level
+ * bucket.
  * lap_ctx_kernel_stats synchronises the stream. */
 lap_status lap_ctx_set_timing(lap_ctx* ctx, int32_t on);
 lap_status lap_ctx_kernel_stats(lap_ctx* ctx, int32_t kernel_class, int32_t fine_only,

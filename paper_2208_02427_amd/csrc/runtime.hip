@@ -269,7 +269,7 @@ size_t coarse_bytes(const LevelGeo& C) {
 enum Part { PART_ALL = 0, PART_HEAD = 1, PART_TAIL = 2 };
 
 enum KClass { KC_SWEEP = 0, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE,
-              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_COUNT };
+              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_TWO_PLAIN, KC_COUNT };
 
 // Size classes for tilings, by interior node count.
 // One class per factor 4 of interior nodes from 2^12 to 2^24, so each level
@@ -644,7 +644,12 @@ hipError_t enq_sweep(lap_grid* g, int l, const T* in, T* out, const T* f, const 
 
 // Halo, kernel class and tiling of a fused pass with these flags.
 int fused_halo(int flags) { return ((flags & SW_TWO) ? 4 : 2) + ((flags & SW_RESTRICT) ? 2 : 0); }
-int fused_class(int flags) { return (flags & SW_RESTRICT) ? KC_PRE : KC_TWO; }
+// (two-sweep passes with the prolongation and without any transfer, as red-black
+// SOR runs them, are tuned apart: their best tilings differ)
+int fused_class(int flags) {
+    if (flags & SW_RESTRICT) return KC_PRE;
+    return (flags & SW_PROLONG) ? KC_TWO : KC_TWO_PLAIN;
+}
 bool is_fused(int flags) { return (flags & (SW_TWO | SW_RESTRICT)) != 0; }
 
 // Algorithmic bytes per interior node of a sweep or fused pass.
@@ -2858,7 +2863,7 @@ hipError_t tune_launch(lap_ctx* c, int cls, const Tiling& t, int m, int n, int P
         a.tl = t;
         return launch_sweep<T>(a, flags | (cls == KC_SWEEP_PROLONG ? SW_PROLONG : 0), c->stream);
     }
-    if (cls == KC_PRE || cls == KC_TWO) {
+    if (cls == KC_PRE || cls == KC_TWO || cls == KC_TWO_PLAIN) {
         SweepArgs<T> a{};
         a.uin = (const T*)B.u[0];
         a.uout = (T*)B.u[1];
@@ -2966,30 +2971,31 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
     }
     std::string js = "{\"m\": " + std::to_string(m) + ", \"n\": " + std::to_string(n) + ", \"size_class\": " +
                      std::to_string(sc) + ", \"wave_cap\": " + std::to_string(c->wave_cap) + ", \"best\": [";
-    const char* names[KC_COUNT] = {"sweep", "sweep_prolong", "restrict", "defect", "coarse", "finalize",
-                                   "adi_rows", "adi_cols", "residual", "subtree", "pre", "two"};
+    const char* names[KC_COUNT] = {"sweep",    "sweep_prolong", "restrict", "defect", "coarse", "finalize", "adi_rows",
+                                   "adi_cols", "residual",      "subtree",  "pre",    "two",    "two_plain"};
     // the variant each class is timed on: pre-smoothing from zero with the
     // restriction (coarse levels, FP32 level 0), post-smoothing with the
     // prolongation (with and without a right-hand side, as the one-sweep kernel)
     auto base_flags = [](int cls) {
         if (cls == KC_PRE) return (int)(SW_RESTRICT | SW_TWO | SW_ZERO);
         if (cls == KC_TWO) return (int)(SW_TWO | SW_PROLONG);
+        if (cls == KC_TWO_PLAIN) return (int)SW_TWO;
         return 0;
     };
     bool first = true;
     lap_status result = LAP_OK;
     for (int cls : {(int)KC_SWEEP, (int)KC_SWEEP_PROLONG, (int)KC_RESTRICT, (int)KC_RESIDUAL, (int)KC_DEFECT,
-                    (int)KC_PRE, (int)KC_TWO}) {
+                    (int)KC_PRE, (int)KC_TWO, (int)KC_TWO_PLAIN}) {
         for (int dt = 0; dt < 2; ++dt) {
-            if (cls == KC_DEFECT && dt == 1) continue;
+            if ((cls == KC_DEFECT || cls == KC_TWO_PLAIN) && dt == 1) continue;   // FP64 only
             double best = 1e30;
             Cand bc{2, 0, c->wave_cap};
             for (const Cand& cd : cands) {
-                const int H = (cls == KC_PRE || cls == KC_TWO) ? fused_halo(base_flags(cls)) : 2;
+                const int H = (cls == KC_PRE || cls == KC_TWO || cls == KC_TWO_PLAIN) ? fused_halo(base_flags(cls)) : 2;
                 const Tiling t = make_tiling(m, n, cd.V, cd.ty, cd.tgt, H);
                 double total = 0.0;
                 for (int fl0 : {0, (int)SW_F}) {
-                    if (fl0 == 0 && cls != KC_SWEEP && cls != KC_TWO) continue;
+                    if (fl0 == 0 && cls != KC_SWEEP && cls != KC_TWO && cls != KC_TWO_PLAIN) continue;
                     if (fl0 == 0 && cls == KC_PRE) continue;
                     const int fl = fl0 | base_flags(cls);
                     auto go = [&]() {
