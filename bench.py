@@ -444,8 +444,8 @@ def main():
     ap.add_argument("--baseline-rates", type=float, nargs="*", default=[100, 1000])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs each grid on a single MI355X "
-              "(see the sharding paragraph of the design notes); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs each grid on a single MI355X "
+              "(sharding across GPUs is not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.mixed_only:
         import torch

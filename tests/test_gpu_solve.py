@@ -2,7 +2,7 @@
 against the oracle, in the same ordering: red-black SOR sweeps, zebra ADI
 iterations, FP64 V(2,2) cycles and mixed-precision outer steps.
 
-Gate (the benchmark spec): FP64 results within 1e-10 max-abs of the oracle; the
+Gate: FP64 results within 1e-10 max-abs of the oracle; the
 error against the exact discrete solution is reported for converged runs.
 Mixed precision is compared with the oracle's float32-emulated loop.
 """
