@@ -1093,18 +1093,22 @@ bool postdef_ok(lap_grid* g, const lap_opts& o) {
 // V-cycle on the error equation.  With g->pdef, step s >= 1 starts with the
 // fused pass that finishes step s - 1's cycle (its level-0 post-smoothing)
 // and does the defect correction; the FP32 right-hand sides of consecutive
-// steps alternate between l32[0].b and rhs2.
-void plan_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int e_idx, int part,
-                     std::vector<Op>& ops) {
+// steps alternate between l32[0].b and rhs2.  Step 0 corrects nothing yet
+// and works in place on psi[0] (no copy of the iterate); step s >= 1 reads
+// psi[(s + 1) % 2] and writes psi[s % 2].
+void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part, std::vector<Op>& ops) {
+    const bool first = s == 0;
+    const int in_idx = first ? 0 : (s + 1) % 2;
+    double* pin = g->psi[in_idx];
+    double* pout = first ? g->psi[0] : g->psi[1 - in_idx];
     if (g->pdef) {
         float* R[2] = {g->l32[0].b, g->rhs2};
-        const int par = in_idx;
+        const int par = s % 2;
         HierView<float> H = view32(g);
         DeferredPost dp;
         if (part != PART_TAIL) {
             if (first) {
-                push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, g->psi[in_idx], g->psi[1 - in_idx], g->f64, nullptr,
-                                R[0], 0.0);
+                push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, pin, pout, g->f64, nullptr, R[0], 0.0);
                 push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr,
                                 nullptr, 0.0);
             } else {
@@ -1112,8 +1116,8 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int
                 std::vector<Op> prev;
                 H.b[0] = R[1 - par];
                 plan_vcycle<float>(g, H, 0, o, false, PART_ALL, prev, &dp);
-                push_op<float>(ops, KEY_HEAD, OP_POSTDEF, 0, kPostDefFlags, g->psi[in_idx], g->psi[1 - in_idx],
-                               R[1 - par], dp.ec, R[par], o.omega, dp.in);
+                push_op<float>(ops, KEY_HEAD, OP_POSTDEF, 0, kPostDefFlags, pin, pout, R[1 - par], dp.ec, R[par],
+                               o.omega, dp.in);
                 push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_POSTDEF, nullptr, nullptr, nullptr, nullptr,
                                 nullptr, 0.0);
             }
@@ -1125,8 +1129,7 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int in_idx, bool first, int
     }
     if (part != PART_TAIL) {
         const float* e = first ? nullptr : (e_idx == 0 ? g->l32[0].u[0] : g->l32[0].u[1]);
-        push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, g->psi[in_idx], g->psi[1 - in_idx], g->f64, e,
-                        g->l32[0].b, 0.0);
+        push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, pin, pout, g->f64, e, g->l32[0].b, 0.0);
         push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr, nullptr,
                         0.0);
     }
@@ -1465,11 +1468,12 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
                 return exec_ops(g, ops);
             });
         } else {
-            // two outer steps (psi[1] -> psi[0] -> psi[1]); step 0 runs without the graph
+            // two outer steps, an odd one (psi[0] -> psi[1]) and the next (psi[1] -> psi[0]);
+            // step 0 runs without the graph
             e = capture(g, key.c_str(), [&]() {
                 std::vector<Op> ops;
-                plan_mixed_step(g, o, 1, false, g->e_idx, PART_ALL, ops);
-                plan_mixed_step(g, o, 0, false, g->e_idx, PART_ALL, ops);
+                plan_mixed_step(g, o, 1, g->e_idx, PART_ALL, ops);
+                plan_mixed_step(g, o, 2, g->e_idx, PART_ALL, ops);
                 return exec_ops(g, ops);
             });
         }
@@ -1489,7 +1493,7 @@ void plan_step(lap_grid* g, const lap_opts& o, int s, int part, std::vector<Op>&
                 HierView<double> H = view64(g);
                 plan_vcycle<double>(g, H, 0, o, true, part, ops);
             } else {
-                plan_mixed_step(g, o, s % 2, s == 0, g->e_idx, part, ops);
+                plan_mixed_step(g, o, s, g->e_idx, part, ops);
             }
             return;
         case LAP_SOR_RB: {
@@ -1552,7 +1556,7 @@ hipError_t step(lap_grid* g, const lap_opts& o, int part = PART_ALL) {
 // The buffer holding the tested iterate (the solution) at the end of a solve.
 int result_buffer(lap_grid* g, const lap_opts& o, const Ctrl& h) {
     if (o.method == LAP_SOR_RB) return ((h.checks - 1) % 2) * ((int)sor_passes(g->ctx, o.check_every).size() % 2);
-    if (o.method == LAP_MG && o.precision == LAP_MIXED) return h.checks % 2;
+    if (o.method == LAP_MG && o.precision == LAP_MIXED) return h.checks > 0 ? (h.checks - 1) % 2 : 0;
     return 0;
 }
 
