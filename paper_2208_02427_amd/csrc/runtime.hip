@@ -1027,7 +1027,8 @@ hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const 
     a.cy = c.cy;
     a.d = c.d;
     a.tl = norm_tiling(L.m, L.n, NORM_DEFECT);
-    const double per = 8.0 + (e ? 4.0 : 0.0) + (g->f64 ? 8.0 : 0.0) + 8.0 + 4.0;
+    // psi and e (and f) read, psi written unless in place, the FP32 right-hand side written
+    const double per = 8.0 + (e ? 4.0 : 0.0) + (g->f64 ? 8.0 : 0.0) + (psi_out != psi_in || e ? 8.0 : 0.0) + 4.0;
     return g->ctx->timed(KC_DEFECT, true, per * nint(L), [&]() { return launch_defect(a, g->ctx->stream); });
 }
 
@@ -2340,7 +2341,8 @@ double item_bytes(const Op& op, const BatchItem& it) {
         case OP_SWEEP: return sweep_bytes_per_node(op.flags, (int)sz) * n;
         case OP_RESTRICT: return ((op.in ? 1.0 : 0.0) + (op.f ? 1.0 : 0.0) + 0.25) * sz * n;
         case OP_RESNORM: return (op.f ? 16.0 : 8.0) * n;
-        case OP_DEFECT: return (8.0 + (op.ec ? 4.0 : 0.0) + (op.f ? 8.0 : 0.0) + 12.0) * n;
+        case OP_DEFECT:
+            return (8.0 + (op.ec ? 4.0 : 0.0) + (op.f ? 8.0 : 0.0) + (op.out != op.in || op.ec ? 8.0 : 0.0) + 4.0) * n;
         case OP_POSTDEF: return postdef_bytes_per_node(it.f64 != nullptr) * n;
         case OP_ADI_ROWS:
         case OP_ADI_COLS: return adi_bytes_per_node(op.f != nullptr) * n;
