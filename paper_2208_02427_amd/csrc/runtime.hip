@@ -2425,6 +2425,16 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
             sub[std::make_tuple(go.second.kind, go.second.dt, go.second.flags & ~SW_F, vkey)].push_back({go, it});
         }
         for (auto& skv : sub) {
+            if (batch_kind(skv.second[0].first.second) == BK_SUBTREE) {
+                // one workgroup per grid, all with the largest grid's LDS: the
+                // largest sub-V-cycles go first so the last round holds the short ones
+                auto nodes = [](const GoIt& gi) {
+                    const LevelGeo& L = gi.first.first->geo[gi.first.second.level];
+                    return (size_t)L.m * (size_t)L.n;
+                };
+                std::stable_sort(skv.second.begin(), skv.second.end(),
+                                 [&](const GoIt& a, const GoIt& b) { return nodes(a) > nodes(b); });
+            }
             MergedLaunch L{};
             const Op& op0 = skv.second[0].first.second;
             L.kind = batch_kind(op0);
