@@ -2228,12 +2228,7 @@ int batch_kind(const Op& op) {
 
 constexpr int kBatchMinRows = 32;
 constexpr size_t kBatchManyGrids = 4;
-constexpr size_t kBatchWideGrids = 64;
-constexpr int kBatchWideRows = 64;
-// Smaller plans (serving ticks) give every grid's fused passes the same
-// columns per lane: each V is a launch of its own, and a tick's latency
-// grows with its launches.
-constexpr int kBatchTickV = 2;
+constexpr int kBatchV = 2;
 
 // Fill the item of grid g for operation op (tiling, geometry, coefficients).
 BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) {
@@ -2313,18 +2308,16 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
     // The table's short row chunks (down to 2 rows) and narrow windows
     // minimise the latency of one grid's small level.  Inside a merged launch
     // over several grids a chunk's halo rows (up to 11 for a fused pass)
-    // weigh more, so plans of 4 or more grids use chunks of >= 32 rows; plans
-    // of 64 or more grids are throughput-bound and take >= 64 rows and 4
-    // columns per lane (the measured best for a 512-grid ragged batch of
-    // 33..1025 points a side; with 10-20 grids of a serving tick the wide
-    // tiles doubled the latency), plans of 2-63 grids 2 columns per lane.
+    // weigh more, so plans of 4 or more grids use chunks of >= 32 rows, and
+    // every plan of 2 or more grids 2 columns per lane (one launch per key;
+    // a 512-grid ragged batch of 33..1025 points a side: 13.8 ms with 4
+    // columns per lane and >= 64 rows, 11.7 ms with 2 and >= 32; 15.4 ms with
+    // the table's chunks).
     const bool tile_op = (op.kind == OP_SWEEP || op.kind == OP_RESTRICT) && !(op.flags & SW_NORM);
-    if (tile_op && nplan >= kBatchWideGrids)
-        t = make_tiling(L.m, L.n, 4, std::max(t.ty, kBatchWideRows), 0, t.H);
-    else if (tile_op && nplan >= kBatchManyGrids)
-        t = make_tiling(L.m, L.n, kBatchTickV, std::max(t.ty, kBatchMinRows), 0, t.H);
+    if (tile_op && nplan >= kBatchManyGrids)
+        t = make_tiling(L.m, L.n, kBatchV, std::max(t.ty, kBatchMinRows), 0, t.H);
     else if (tile_op && nplan >= 2)
-        t = make_tiling(L.m, L.n, kBatchTickV, t.ty, 0, t.H);
+        t = make_tiling(L.m, L.n, kBatchV, t.ty, 0, t.H);
     it.V = t.V;
     it.ty = t.ty;
     it.nwin = t.nwin;
