@@ -170,9 +170,10 @@ lap_status lap_ctx_set_tiling(lap_ctx* ctx, int32_t kernel_class, int32_t dtype,
 lap_status lap_ctx_get_tiling(lap_ctx* ctx, int32_t kernel_class, int32_t dtype, int32_t size_class,
                               int32_t* V, int32_t* ty, int32_t* target_waves);
 
-/* Small-level subtree (multigrid, section 2.3's V-cycle below a size): from
- * the first zero-start level whose remaining hierarchy (u and b of every level
- * below it, plus the coarsest right-hand side) fits one workgroup's LDS, the
+/* Small-level subtree (the V-cycle of "Multigrid Method (V-Cycle)",
+ * Eqs. (11)-(15), below a size): from the first zero-start level whose
+ * remaining hierarchy (u and b of every level below it, plus the coarsest
+ * right-hand side) fits one workgroup's LDS, the
  * rest of the V-cycle (pre-smoothing, full weighting, coarsest solve,
  * bilinear correction, post-smoothing on every level below) runs as ONE
  * launch of one workgroup (per grid, in a batch) instead of five launches per
@@ -184,10 +185,11 @@ lap_status lap_ctx_get_tiling(lap_ctx* ctx, int32_t kernel_class, int32_t dtype,
 lap_status lap_ctx_set_subtree(lap_ctx* ctx, int64_t max_nodes);
 lap_status lap_ctx_get_subtree(lap_ctx* ctx, int64_t* max_nodes, int32_t* lds_bytes);
 
-/* Fused smoothing passes (multigrid, section 2.3): with fusion on (the
- * default) a level's pre-smoothing runs as passes of up to two red-black
- * sweeps, the last of which also forms the residual of its result and
- * full-weights it onto the coarse right-hand side, and the post-smoothing as
+/* Fused smoothing passes (the V-cycle of "Multigrid Method (V-Cycle)",
+ * Eqs. (11)-(15)): with fusion on (the default) a level's pre-smoothing
+ * runs as passes of up to two red-black sweeps, the last of which also
+ * forms the residual of its result and full-weights it onto the coarse
+ * right-hand side, and the post-smoothing as
  * passes of up to two sweeps, the first of which adds the bilinear
  * correction; each pass reads and writes the level once.  The fields are
  * bitwise those of one launch per sweep (fusion off).  A level holding the

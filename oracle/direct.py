@@ -14,7 +14,7 @@ solution without iterating, two independent ways:
   transform itself is scipy.fft.dstn (a library routine sharing nothing with
   the iterative code).
 
-Pins (tests/test_oracle_direct.py): dense GE against numpy.linalg.solve;
+Pins (tests/test_oracle_grid.py): dense GE against numpy.linalg.solve;
 dense GE against DST on rectangles with dx != dy; both reproduce the
 discretely harmonic fields exactly.
 """

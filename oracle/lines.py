@@ -24,7 +24,9 @@ Readings:
 
 Pins (tests/test_oracle_lines.py): Thomas against scipy.linalg.solve_banded
 and against its own residual; every line method leaves a discretely harmonic
-field unchanged; closed-form asymptotic rate of line Gauss-Seidel; converged
+field unchanged; closed-form asymptotic rate of line Gauss-Seidel; the rate
+of relaxation after the line solve (form 'A', ascending and zebra rows) at
+w = 1.3, 1.5, 1.8 and the block optimum against Young's formula; converged
 solutions against the dense direct solve; the paper's printed iteration count
 for SLOR at w = 1 on the chamber.  The paper's ADI and SLORB counts at their
 optimal w (33, 55) are reported, not gated: parity unpinned (the ADI

@@ -134,3 +134,53 @@ def test_paper_optimal_omega_slorb_and_adi(paper):
                 counts[float(w)] = k
         best = min(counts, key=lambda w: (counts[w], w))
         assert best == paper["omega_opt"][key]
+
+
+def _young_line_sor_rate(mu: float, w: float) -> float:
+    """Spectral radius of SOR for a consistently ordered block matrix whose
+    block Jacobi radius is mu (Young's theorem): below the optimum
+    w_opt = 2 / (1 + sqrt(1 - mu^2)) it is ((w mu + sqrt(w^2 mu^2 - 4(w-1))) / 2)^2,
+    from the optimum on it is w - 1."""
+    w_opt = 2.0 / (1.0 + np.sqrt(1.0 - mu * mu))
+    if w >= w_opt:
+        return w - 1.0
+    return ((w * mu + np.sqrt(w * w * mu * mu - 4.0 * (w - 1.0))) / 2.0) ** 2
+
+
+def _rows_zebra_history(p, w, tol=1e-13, max_iter=3000):
+    """delta history of repeated zebra row halves (odd rows, then even rows,
+    relaxation after the line solve): x-line SOR in red-black line order."""
+    u = p.psi0.copy()
+    hist = []
+    for _ in range(max_iter):
+        old = u.copy()
+        lines.adi_zebra_rows_half(u, None, p.dx, p.dy, w, "A")
+        hist.append(float(np.max(np.abs(u - old))))
+        if hist[-1] < tol:
+            break
+    return hist
+
+
+@pytest.mark.parametrize("order", ["rows_ascending", "rows_zebra"])
+@pytest.mark.parametrize("w,rel", [(1.3, 0.002), (1.5, 0.002), (1.8, 0.01), ("opt", 0.05)])
+def test_relax_after_line_sor_rate_young(order, w, rel):
+    """Relaxation after the line solve (SLORA, Eqs. (8)-(9); the zebra ADI
+    default) at w != 1.  x-line SOR is block SOR on a block tridiagonal
+    matrix, consistently ordered for ascending rows and for odd-then-even
+    rows alike, so its asymptotic rate follows Young's formula with the
+    x-line Jacobi radius; at the block optimum w_opt = 1.6220 (chamber) it is
+    w - 1 up to the Jordan-block transient.  A misplaced relaxation (e.g.
+    dividing by w, or relaxing toward the old row with the wrong sign) keeps
+    the fixed point but changes this rate."""
+    p = W.chamber(psi_ab=1.0)
+    mu = lines.rate_line_jacobi_x(p.m, p.n, p.dx, p.dy)
+    w_opt = 2.0 / (1.0 + np.sqrt(1.0 - mu * mu))
+    assert w_opt == pytest.approx(1.6220, abs=1e-4)
+    w = w_opt if w == "opt" else w
+    if order == "rows_ascending":
+        _, _, h = solve.iterate("slora", p.psi0, None, p.dx, p.dy, w, "delta", 1e-13, max_iter=5000)
+    else:
+        h = _rows_zebra_history(p, w)
+    h = np.asarray(h[-40:])
+    ratio = float(np.exp(np.mean(np.log(h[1:] / h[:-1]))))
+    assert ratio == pytest.approx(_young_line_sor_rate(mu, w), rel=rel)
