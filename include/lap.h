@@ -321,6 +321,24 @@ lap_status lap_op_residual(int32_t dtype, int32_t m, int32_t n, int32_t ld, doub
                            const void* u, const void* f, void* r, double* norms, void* work, void* stream);
 size_t lap_op_work_bytes(int32_t m, int32_t n);
 
+/* lap_op_residual without a work buffer, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the per-tile norm partials go to a fixed
+ * 1 MiB device array of the library (one per GPU, held until the process
+ * ends; its address is looked up once per device on the first call, the only
+ * call that is not purely stream-ordered).  The call allocates nothing.
+ * Arguments, layout and results are those of lap_op_residual; the kernels
+ * are the same, so r and norms are bitwise equal to it.  Limit: at most
+ * 65536 norm tiles (windows of 124 FP64 / 252 FP32 columns x chunks of 32
+ * rows; square grids up to 16121^2 in FP64, 22931^2 in FP32; 8193^2 FP64
+ * uses 17152); larger grids are rejected with LAP_EINVAL when norms != NULL,
+ * before anything is enqueued.
+ * All calls on one GPU share the array: calls that overlap on that GPU (on
+ * different streams, or from different host threads) race and may return
+ * each other's norms; serialise them. */
+lap_status lap_op_residual_static(int32_t dtype, int32_t m, int32_t n, int32_t ld, double dx, double dy,
+                                  const void* u, const void* f, void* r, double* norms, void* stream);
+
 /* Residual followed by full weighting onto the coarse grid: writes the
  * interior of bc ((m-1)/2+1 x (n-1)/2+1, pitch ldc); m and n must be odd. */
 lap_status lap_op_restrict(int32_t dtype, int32_t m, int32_t n, int32_t ld, double dx, double dy,

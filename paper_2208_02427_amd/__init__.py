@@ -349,6 +349,17 @@ def op_residual(m, n, dx, dy, u, f=None, r=None, want_norms=True):
     return norms
 
 
+def op_residual_static(m, n, dx, dy, u, f=None, r=None, want_norms=True):
+    """op_residual without a work buffer: the norm partials go to the
+    library's fixed per-GPU array (lap_op_residual_static)."""
+    torch = _torch()
+    ld = u.shape[1]
+    norms = torch.zeros(2, dtype=torch.float64, device=u.device) if want_norms else None
+    _check(lib().lap_op_residual_static(_dt(u), m, n, ld, float(dx), float(dy), _ptr(u), _ptr(f), _ptr(r),
+                                        _ptr(norms), _stream()))
+    return norms
+
+
 def op_restrict(m, n, dx, dy, u, f, bc):
     ld = u.shape[1] if u is not None else f.shape[1]
     _check(lib().lap_op_restrict(_dt(bc), m, n, ld, float(dx), float(dy), _ptr(u), _ptr(f), _ptr(bc), bc.shape[1],

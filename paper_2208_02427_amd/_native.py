@@ -75,6 +75,7 @@ SIGNATURES = {
     "lap_op_rb_sweep": (_S, [c_int32, c_int32, c_int32, c_int32, c_double, c_double, c_double,
                              _P, _P, _P, c_int32, _P, _P]),
     "lap_op_residual": (_S, [c_int32, c_int32, c_int32, c_int32, c_double, c_double, _P, _P, _P, _P, _P, _P]),
+    "lap_op_residual_static": (_S, [c_int32, c_int32, c_int32, c_int32, c_double, c_double, _P, _P, _P, _P, _P]),
     "lap_op_work_bytes": (c_size_t, [c_int32, c_int32]),
     "lap_op_restrict": (_S, [c_int32, c_int32, c_int32, c_int32, c_double, c_double, _P, _P, _P, c_int32, _P]),
     "lap_op_adi_half": (_S, [c_int32, c_int32, c_int32, c_int32, c_double, c_double, c_double, c_int32,

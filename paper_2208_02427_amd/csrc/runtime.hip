@@ -13,6 +13,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2069,6 +2070,66 @@ extern "C" lap_status lap_op_residual(int32_t dtype, int32_t m, int32_t n, int32
     if (norms && !work) return fail(LAP_EINVAL, "norms need a work buffer");
     if (!aligned(u) || (f && !aligned(f)) || (r && !aligned(r))) return fail(LAP_EINVAL, "pointers must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
+    return dtype == 0 ? op_residual<double>(m, n, ld, dx, dy, u, f, r, norms, work, s)
+                      : op_residual<float>(m, n, ld, dx, dy, u, f, r, norms, work, s);
+}
+
+// ------------------------------------------- residual without a workspace
+// The per-tile norm partials of lap_op_residual_static live in this fixed
+// device array instead of a caller's work buffer.  Every GPU the library runs
+// on holds its own copy, at its own address, until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in symbol): it looks up the device address once per device and
+// passes that.
+constexpr int kStaticNormTiles = 65536;                 // 1 MiB of partials
+static __device__ __align__(256) double scratch[2 * kStaticNormTiles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// The address of `scratch` on the device of `s` (the current device for the
+// default stream); looked up on the first call per device.
+lap_status static_scratch(hipStream_t s, double** out) {
+    int cur = 0, dev = 0;
+    HIPCHK(hipGetDevice(&cur));
+    dev = cur;
+    if (s != nullptr) HIPCHK(hipStreamGetDevice(s, &dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LAP_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[dev] == nullptr) {
+        if (dev != cur) HIPCHK(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) HIPCHK(hipSetDevice(cur));
+        if (e != hipSuccess || p == nullptr)
+            return fail(LAP_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return LAP_OK;
+}
+}  // namespace
+
+extern "C" lap_status lap_op_residual_static(int32_t dtype, int32_t m, int32_t n, int32_t ld, double dx, double dy,
+                                             const void* u, const void* f, void* r, double* norms, void* stream) {
+    lap_status st = op_check(dtype, m, n, ld, dx, dy);
+    if (st != LAP_OK) return st;
+    if (!u) return fail(LAP_EINVAL, "u is NULL");
+    if (!aligned(u) || (f && !aligned(f)) || (r && !aligned(r))) return fail(LAP_EINVAL, "pointers must be 256-byte aligned");
+    const int ntiles = make_tiling(m, n, kOpV[dtype == 0 ? 0 : 1], kOpTY).ntiles;
+    if (norms && ntiles > kStaticNormTiles)
+        return fail(LAP_EINVAL, "grid too large for lap_op_residual_static: " + std::to_string(ntiles) +
+                                    " norm tiles, at most " + std::to_string(kStaticNormTiles) +
+                                    " (use lap_op_residual with a work buffer)");
+    hipStream_t s = (hipStream_t)stream;
+    double* work = nullptr;
+    if (norms) {
+        st = static_scratch(s, &work);
+        if (st != LAP_OK) return st;
+    }
+    // every tile overwrites its two partials, so nothing is cleared first
     return dtype == 0 ? op_residual<double>(m, n, ld, dx, dy, u, f, r, norms, work, s)
                       : op_residual<float>(m, n, ld, dx, dy, u, f, r, norms, work, s);
 }
