@@ -75,11 +75,15 @@ def thomas(a, b, c, r):
 def thomas_many(a: float, b: float, c: float, R: np.ndarray) -> np.ndarray:
     """The same recurrences for many independent systems with constant
     coefficients: R has shape (K, L), one system per column; the loop runs
-    along k with numpy operations across the L systems."""
+    along k with numpy operations across the L systems.  The arithmetic is
+    done in R's precision (float32 R: coefficients rounded to float32 and
+    every operation rounded to float32, as in the mixed inner cycle)."""
     K = R.shape[0]
     if K > 1 and abs(b) <= abs(a) + abs(c):
         raise ValueError("tridiagonal system not diagonally dominant")
-    cp = np.zeros(K)
+    dt = R.dtype.type
+    a, b, c = dt(a), dt(b), dt(c)
+    cp = np.zeros(K, dtype=R.dtype)
     rp = np.zeros_like(R)
     cp[0] = c / b
     rp[0] = R[0] / b

@@ -17,7 +17,12 @@ Readings (the V-cycle figure is not available):
   dense elimination of oracle.direct.
 * Smoother: red-black SOR (oracle.relax.rb_sweep) with nu1 pre- and nu2
   post-sweeps; the paper's own variant is 3 lexicographic GS sweeps per visit
-  and is available with smoother='gs_lex'.
+  and is available with smoother='gs_lex'.  smoother='zebra' smooths with the
+  paper's line relaxation instead: one smoothing step is one ADI iteration in
+  zebra order (oracle.lines.adi_zebra_iteration: odd rows, even rows, odd
+  columns, even columns, each line solved exactly, relaxation after the
+  solve with omega_s), which stays a good smoother when dx != dy makes the
+  5-point operator anisotropic.
 * Sign: r = f - L_h u and L_h e = r (equivalent to Eqs. (12)-(15)).
 
 Mixed precision (not in the paper): psi and the residual stay FP64; each
@@ -37,6 +42,7 @@ import numpy as np
 
 from .grid import coefficients, residual, norm2
 from .relax import rb_sweep, gs_lex_sweep
+from .lines import adi_zebra_iteration
 from .direct import dense_solve
 
 
@@ -114,6 +120,8 @@ def vcycle(levels, l: int, u: np.ndarray, b: np.ndarray | None, nu1: int = 2, nu
             rb_sweep(u, b, dx, dy, omega_s, dtype)
         elif smoother == "gs_lex":
             gs_lex_sweep(u, b, dx, dy, omega_s)
+        elif smoother == "zebra":
+            adi_zebra_iteration(u, b, dx, dy, omega_s, "A")
         else:
             raise ValueError(smoother)
 
@@ -129,7 +137,7 @@ def vcycle(levels, l: int, u: np.ndarray, b: np.ndarray | None, nu1: int = 2, nu
         smooth()
 
 
-def mixed_step(psi: np.ndarray, f: np.ndarray | None, levels, nu1=2, nu2=2, omega_s=1.0):
+def mixed_step(psi: np.ndarray, f: np.ndarray | None, levels, nu1=2, nu2=2, omega_s=1.0, smoother="rb"):
     """One outer step of the mixed-precision defect correction:
         r64 = f - L_h psi64;  b32 = fl32(r64);  e32 = FP32 V-cycle from 0;
         psi64 += fl64(e32).
@@ -138,7 +146,7 @@ def mixed_step(psi: np.ndarray, f: np.ndarray | None, levels, nu1=2, nu2=2, omeg
     r = residual(psi, f, dx, dy)
     b32 = r.astype(np.float32)
     e32 = np.zeros_like(b32)
-    vcycle(levels, 0, e32, b32, nu1, nu2, omega_s, np.float32)
+    vcycle(levels, 0, e32, b32, nu1, nu2, omega_s, np.float32, smoother)
     psi += e32.astype(np.float64)
     return r
 
