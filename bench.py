@@ -8,15 +8,26 @@ to 5 x 5 solved directly).  `value` is the smoother throughput of the step in
 GLUP/s: interior nodes updated by all smoothing sweeps on all levels, per
 second of whole-step wall time (inputs resident in HBM).
 
-Also measured in the same run (reported beside the headline):
-  * mixed precision on the same grid with a 32-bump source: FP32 V-cycles
-    inside FP64 defect correction vs FP64 multigrid, time to 1e-10 and speedup;
-  * red-black SOR with w = 2/(1+sin(pi h)): sweeps/s and GLUP/s, and time to
-    1e-10 on 4097 x 4097;
+Also measured in the same run, each leg on its own grids (setup untimed):
+  * mixed precision (FP32 V-cycles inside FP64 defect correction) vs FP64
+    multigrid on the 8193^2 and 4097^2 grids with a 32-bump source: time to
+    1e-10 (graph replay, the third solve of each precision), speedup,
+    difference between the two results;
+  * red-black SOR with w = 2/(1+sin(pi h)) to 1e-10 on 4097^2 and 8193^2;
+    FP64 multigrid on 4097^2;
+  * the paper's 25 x 17 chamber on the GPU: red-black SOR for w = 1.00 ..
+    1.95, zebra ADI, the 3-level V(2,2) cycle, to max|r| < 1e-6;
+  * a ragged batch of 512 grids (mixed multigrid, zebra ADI) and the serving
+    loop (Poisson arrivals, 2000 requests per rate after 200 warm-up);
   * the roofline of the dominant kernel (the finest-level kernel class with
-    the most device time: the fused pre- or post-smoothing pass) from HIP
-    events around each of its launches;
-  * the CPU oracle on the host cores (one V-cycle of the 4097 x 4097 solve).
+    the most device time) from HIP events around each of its launches;
+  * the CPU oracle on the host (one FP64 V-cycle of the 8193^2 solve,
+    extrapolated to the solve's cycle count), and in the same leg the error
+    of the large GPU results against the oracle's exact spectral solution.
+
+stdout: ONE compact JSON line (the headline, `roofline`, `cpu_baseline` and
+short per-leg figures in `legs`).  The full record of every leg goes to
+stderr as one JSON line, and to --detail-out if given.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N] [--no-cpu] [--quick]
 """
@@ -50,11 +61,11 @@ FINE_LABELS = {
     "sweep": "k_sweep<double,V,0>: one red-black sweep (finest level, f = 0)",
     "sweep_prolong": "k_sweep<double,V,4>: bilinear correction + one red-black sweep",
     "restrict": "k_restrict<double,V>: residual + full weighting",
-    "pre": "k_fused<double,2,56>: residual norms of the iterate + two red-black sweeps + residual + full "
-           "weighting (finest level, f = 0, canonical norm tiling)",
-    "two": "k_fused<double,V,36>: bilinear correction + two red-black sweeps (finest level, f = 0)",
+    "pre": "k_fused<double,2,56> pre pass: input norms, 2 RB sweeps, residual, full weighting",
+    "two": "k_fused<double,V,36> post pass: bilinear correction, 2 RB sweeps",
 }
 ALL_CLASSES = range(13)
+KC_RESIDUAL = 8
 
 
 def lup_per_cycle(levels, nu1=2, nu2=2):
@@ -67,37 +78,40 @@ def sync():
     torch.cuda.synchronize()
 
 
-def run_gpu(args):
-    import torch
-    import paper_2208_02427_amd as lap
+def say(*a):
+    """Progress line on stderr (one per leg)."""
+    print("[bench]", time.strftime("%H:%M:%S"), *a, file=sys.stderr, flush=True)
 
+
+def sig(x, d=4):
+    """Round to d significant digits (compact output)."""
+    if x is None or not isinstance(x, (int, float)) or x == 0 or not math.isfinite(x):
+        return x
+    return float(f"{x:.{d}g}")
+
+
+def timed_solves(g, reset, reps, **kw):
+    """`reps` timed solves after the grid's graph exists (two untimed solves
+    first: the graph is captured on the second solve with the same options);
+    returns (median seconds, info of the last solve)."""
+    for _ in range(2):
+        reset()
+        g.solve(**kw)
+    ts, info = [], None
+    for _ in range(reps):
+        reset()
+        sync()
+        t0 = time.perf_counter()
+        info = g.solve(**kw)
+        sync()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), info
+
+
+# ------------------------------------------------------------------ headline
+def run_headline(args, ctx, torch, lap, dev, keep):
     N = args.size
-    dev = "cuda:0"
-    arena = 12 << 30 if N > 4097 else 4 << 30
-    ctx = lap.Context(arena_bytes=arena, device=dev)
     out = {}
-    # autotune the tilings of every level size the hierarchy visits down to
-    # the small-level subtree (setup, untimed); without it the Context keeps
-    # the shipped MI355X table
-    tune = []
-    if not args.no_tune:
-        sizes = [N]
-        while sizes[-1] > 65 and (sizes[-1] - 1) % 2 == 0:
-            sizes.append((sizes[-1] - 1) // 2 + 1)
-        for tn in sizes:
-            tune.append(ctx.autotune(tn, tn, reps=3))
-        if args.tuning_out:
-            with open(args.tuning_out, "w") as fh:
-                json.dump({"device": "gfx950 (MI355X, 256 CUs)",
-                           "source": "lap_autotune on one MI355X, reps=3, sizes " + "/".join(map(str, sizes))
-                                     + " (python bench.py --tuning-out ...)",
-                           "reports": tune}, fh, indent=1)
-    out["autotune"] = tune
-
-    if args.copy_probe:
-        out["copy_probe"] = run_copy_probe(torch, lap, dev)
-
-    # ---------------------------------------------------------------- headline
     p = W.square_problem(N, seed=2)
     psi0 = torch.as_tensor(p.psi0, device=dev)
     g = ctx.grid(psi0, None, p.dx, p.dy, alloc=lap.LAP_ALLOC_FP64)
@@ -122,22 +136,18 @@ def run_gpu(args):
     fine = {k: ctx.kernel_stats(c, fine_only=True) for k, c in FINE_CLASSES.items()}
     every = [ctx.kernel_stats(c) for c in ALL_CLASSES]
     ctx.set_timing(False)
-    cycles = infos[-1]["iterations"]
     assert all(i["status"] == 0 for i in infos), infos
     total_lup = sum(i["iterations"] for i in infos) * lpc
     out["value"] = total_lup / dt / 1e9
     out["ms_per_step"] = dt / args.steps * 1e3
-    out["cycles"] = cycles
+    out["cycles"] = infos[-1]["iterations"]
+    out["levels"] = len(levels)
     out["rel_res"] = infos[-1]["rel_res_l2"]
     # graph replay (no per-launch events) for the same solve
     out["time_to_tol_graph_s"] = None
     if not args.measure_only:
-        sync()
-        t0 = time.perf_counter()
-        one_solve()
-        sync()
-        out["time_to_tol_graph_s"] = time.perf_counter() - t0
-    out["time_to_tol_s"] = out["ms_per_step"] / 1e3
+        tg, _ = timed_solves(g, lambda: g.write(psi0), 3, method="mg", precision="fp64", tol=1e-10, max_iter=60)
+        out["time_to_tol_graph_s"] = tg
 
     # roofline of the dominant kernel: the finest-level kernel class with the
     # most device time (HIP events around each launch on the library's stream)
@@ -152,8 +162,8 @@ def run_gpu(args):
         "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(ach / HBM_PEAK_GBS, 4),
         "traffic": FINE_TRAFFIC.get((dom,) + tiling) if N == 8193 else None,
-        "tiling": {"V": tiling[0], "ty": tiling[1], "target_waves": tiling[2]},
         "kernel": FINE_LABELS[dom],
+        "tiling": {"V": tiling[0], "ty": tiling[1], "target_waves": tiling[2]},
         "alg_bytes_per_launch": st["alg_bytes"] / max(1, st["launches"]),
         "avg_launch_ms": st["device_ms"] / max(1, st["launches"]),
         "launches": st["launches"],
@@ -162,62 +172,19 @@ def run_gpu(args):
     # whole solve: algorithmic bytes of every launch over the step time
     alg = sum(e["alg_bytes"] for e in every)
     out["solve_hbm"] = {"alg_bytes_per_step": alg / args.steps, "GB/s_over_step_time": alg / dt / 1e9}
-    # correctness of the timed result: oracle-side residual at sampled rows is
-    # checked in the GPU tests; here record the library's own FP64 residual
     l2, linf = g.residual()
     out["final_res_l2"] = l2
-    out["residual_kernel"] = run_residual_leg(ctx, g, lap)
+    out["residual_kernel"] = run_residual_leg(ctx, g)
+    if keep is not None:
+        keep["mg"] = (p, g.read().cpu().numpy())
     g.destroy()
-
-    if args.quick:
-        args.batch = args.serve = False
-    if not args.quick:
-        out["mixed"] = run_mixed_leg(N, ctx, torch, lap, dev)
-
-        # ---------------------------------------------- red-black SOR
-        sor = {}
-        for Ns, full in ((4097, True), (N, False)):
-            ps = W.square_problem(Ns, seed=2)
-            h = 1.0 / (Ns - 1)
-            w = 2.0 / (1.0 + math.sin(math.pi * h))
-            gs = ctx.grid(torch.as_tensor(ps.psi0, device=dev), None, ps.dx, ps.dy, alloc=lap.LAP_ALLOC_ADI)
-            nsw = 40000 if full else 2000
-            sync()
-            t0 = time.perf_counter()
-            info = gs.solve("sor", omega=w, tol=1e-10 if full else 0.0, max_iter=nsw, check_every=50)
-            sync()
-            t = time.perf_counter() - t0
-            lups = info["iterations"] * (Ns - 2) ** 2
-            sor[str(Ns)] = {"omega": w, "sweeps": info["iterations"], "seconds": t, "GLUP/s": lups / t / 1e9,
-                            "to_tol": full, "rel_res": info["rel_res_l2"], "status": info["status"]}
-            gs.destroy()
-        out["sor"] = sor
-        # ---------------------------------------------- MG at 4097
-        p4 = W.square_problem(4097, seed=2)
-        g4 = ctx.grid(torch.as_tensor(p4.psi0, device=dev), None, p4.dx, p4.dy, alloc=lap.LAP_ALLOC_FP64)
-        g4.solve("mg", tol=1e-10, max_iter=60)
-        g4.write(torch.as_tensor(p4.psi0, device=dev))
-        sync()
-        t0 = time.perf_counter()
-        i4 = g4.solve("mg", tol=1e-10, max_iter=60)
-        sync()
-        t4 = time.perf_counter() - t0
-        out["mg_4097"] = {"time_to_tol_s": t4, "cycles": i4["iterations"],
-                          "GLUP/s": i4["iterations"] * lup_per_cycle(g4.levels()) / t4 / 1e9}
-        g4.destroy()
-    if args.batch:
-        out["ragged_batch"] = run_batch_leg(args, ctx, torch, lap, dev)
-    if args.serve:
-        out["serving"] = run_serving_leg(args, ctx, torch, lap, dev)
-    ctx.close()
-    return out, levels
+    return out
 
 
-def run_residual_leg(ctx, g, lap, reps=20):
+def run_residual_leg(ctx, g, reps=20):
     """The FP64 residual-norm kernel alone (lap_residual: r = f - L_h u and its
     norms, u and f read once): HIP events around each launch on the
     library's stream."""
-    KC_RESIDUAL = 8
     g.residual()
     ctx.set_timing(True)
     ctx.reset_stats()
@@ -227,46 +194,110 @@ def run_residual_leg(ctx, g, lap, reps=20):
     ctx.set_timing(False)
     ms = st["device_ms"] / max(1, st["launches"])
     gbs = st["alg_bytes"] / max(1, st["launches"]) / (ms / 1e3) / 1e9 if ms > 0 else 0.0
-    return {"launches": st["launches"], "avg_launch_ms": ms, "alg_bytes_per_launch": st["alg_bytes"] / max(1, st["launches"]),
+    return {"launches": st["launches"], "avg_launch_ms": ms,
+            "alg_bytes_per_launch": st["alg_bytes"] / max(1, st["launches"]),
             "achieved_GB/s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 
-def run_mixed_leg(N, ctx, torch, lap, dev):
+def run_mixed_leg(N, ctx, torch, lap, dev, keep=None, reps=3):
     """Mixed precision vs FP64 multigrid on the N x N grid with the 32-bump
-    source: time to a 1e-10 relative residual (the second of two solves of
-    each), cycles / outer steps, and the largest difference of the results."""
-    sync = torch.cuda.synchronize
+    source: time to a 1e-10 relative residual (median of `reps` graph-replay
+    solves per precision, each grid holding one precision's graph), outer
+    steps / cycles, and the largest difference of the two results."""
     pb = W.square_problem(N, seed=2, bumps=True, bump_seed=3)
     psib = torch.as_tensor(pb.psi0, device=dev)
     fb = torch.as_tensor(pb.f, device=dev)
-    gb = ctx.grid(psib, fb, pb.dx, pb.dy, alloc=lap.LAP_ALLOC_FP64 | lap.LAP_ALLOC_MIXED)
     res = {}
-    for prec in ("fp64", "mixed", "fp64", "mixed"):
-        gb.write(psib)
-        sync()
-        t0 = time.perf_counter()
-        info = gb.solve("mg", precision=prec, tol=1e-10, max_iter=60)
-        sync()
-        t = time.perf_counter() - t0
+    results = {}
+    for prec, alloc in (("fp64", lap.LAP_ALLOC_FP64), ("mixed", lap.LAP_ALLOC_MIXED)):
+        g = ctx.grid(psib, fb, pb.dx, pb.dy, alloc=alloc)
+        t, info = timed_solves(g, lambda: g.write(psib), reps, method="mg", precision=prec, tol=1e-10,
+                               max_iter=60)
         res[prec] = {"time_to_tol_s": t, "iterations": info["iterations"], "rel_res": info["rel_res_l2"],
-                     "status": info["status"]}
-    gb.write(psib)
-    gb.solve("mg", precision="fp64", tol=1e-10, max_iter=60)
-    u64 = gb.read()
-    gb.write(psib)
-    gb.solve("mg", precision="mixed", tol=1e-10, max_iter=60)
-    um = gb.read()
-    res["max_abs_mixed_vs_fp64"] = float((um - u64).abs().max().item())
+                     "status": info["status"], "graph_replay": True}
+        results[prec] = g.read()
+        if prec == "fp64":
+            res["residual_kernel_with_f"] = run_residual_leg(ctx, g)
+        g.destroy()
+    res["max_abs_mixed_vs_fp64"] = float((results["mixed"] - results["fp64"]).abs().max().item())
     res["speedup_mixed_over_fp64"] = res["fp64"]["time_to_tol_s"] / res["mixed"]["time_to_tol_s"]
-    res["residual_kernel_with_f"] = run_residual_leg(ctx, gb, lap)
-    gb.destroy()
+    if keep is not None:
+        keep["bumps"] = (pb, results["fp64"].cpu().numpy(), results["mixed"].cpu().numpy())
+    del results
     return res
 
 
+def run_sor_leg(ctx, torch, lap, dev, sizes):
+    """Red-black SOR at w = 2/(1+sin(pi h)) to a 1e-10 relative residual
+    (stopping test every 50 sweeps)."""
+    sor = {}
+    for Ns in sizes:
+        ps = W.square_problem(Ns, seed=2)
+        h = 1.0 / (Ns - 1)
+        w = 2.0 / (1.0 + math.sin(math.pi * h))
+        gs = ctx.grid(torch.as_tensor(ps.psi0, device=dev), None, ps.dx, ps.dy, alloc=lap.LAP_ALLOC_ADI)
+        sync()
+        t0 = time.perf_counter()
+        info = gs.solve("sor", omega=w, tol=1e-10, max_iter=80000, check_every=50)
+        sync()
+        t = time.perf_counter() - t0
+        lups = info["iterations"] * (Ns - 2) ** 2
+        sor[str(Ns)] = {"omega": w, "sweeps": info["iterations"], "seconds": t, "GLUP/s": lups / t / 1e9,
+                        "rel_res": info["rel_res_l2"], "status": info["status"]}
+        gs.destroy()
+    return sor
+
+
+def run_mg4097_leg(ctx, torch, lap, dev):
+    p4 = W.square_problem(4097, seed=2)
+    psi = torch.as_tensor(p4.psi0, device=dev)
+    g4 = ctx.grid(psi, None, p4.dx, p4.dy, alloc=lap.LAP_ALLOC_FP64)
+    t4, i4 = timed_solves(g4, lambda: g4.write(psi), 3, method="mg", tol=1e-10, max_iter=60)
+    out = {"time_to_tol_s": t4, "cycles": i4["iterations"],
+           "GLUP/s": i4["iterations"] * lup_per_cycle(g4.levels()) / t4 / 1e9}
+    g4.destroy()
+    return out
+
+
+def run_chamber_leg(ctx, torch, lap, dev, reps=5):
+    """The paper's 25 x 17 chamber (psi_AB = 100) on the GPU, to max|r| < 1e-6
+    (physical units): red-black SOR for w = 1.00 .. 1.95, zebra ADI
+    (relaxation after the line solve, w = 1; inside, w = 1.3) and the 3-level
+    V(2,2) multigrid cycle (25x17 -> 13x9 -> 7x5, the last solved exactly);
+    iterations and microseconds per solve (median of `reps`)."""
+    p = W.chamber(psi_ab=100.0)
+    psi = torch.as_tensor(p.psi0, device=dev)
+    g = ctx.grid(psi, None, p.dx, p.dy)
+
+    def run(method, **kw):
+        ts, info = [], None
+        for _ in range(reps):
+            g.write(psi)
+            sync()
+            t0 = time.perf_counter()
+            info = g.solve(method, tol=1e-6, stop="res_inf", max_iter=20000, **kw)
+            sync()
+            ts.append(time.perf_counter() - t0)
+        assert info["status"] == 0, (method, kw, info)
+        return info["iterations"], float(np.median(ts)) * 1e6
+
+    sor = {}
+    for k in range(20):
+        w = round(1.0 + 0.05 * k, 2)
+        sor[f"{w:.2f}"] = run("sor", omega=w)
+    best = min(sor, key=lambda w: (sor[w][0], float(w)))
+    out = {"levels": g.levels(), "sor_iters_us": sor, "sor_best_omega": float(best),
+           "adi_after_w1": run("adi", omega=1.0, adi_form="after"),
+           "adi_inside_w1.3": run("adi", omega=1.3, adi_form="inside"),
+           "mg_v22": run("mg")}
+    g.destroy()
+    return out
+
+
 def device_request(torch, req, dev):
-    """A serving request's inputs generated on the device (same recipe as
-    workloads.request_problem: U[0,1) boundary and 32 Gaussian bumps drawn
-    from the request's seed; the bumps are evaluated with torch)."""
+    """A serving request's inputs generated on the device (U[0,1) boundary
+    and 32 Gaussian bumps drawn from the request's seed, the bumps evaluated
+    with torch; the same draws as workloads.request_problem)."""
     rng = np.random.default_rng(req.seed)
     m, n = req.m, req.n
     h = 1.0 / (max(m, n) - 1)
@@ -275,13 +306,13 @@ def device_request(torch, req, dev):
     amp = rng.standard_normal(32)
     cx = rng.random(32) * lx
     cy = rng.random(32) * ly
-    sig = rng.uniform(0.01, 0.1, 32) * max(lx, ly)
+    sig_ = rng.uniform(0.01, 0.1, 32) * max(lx, ly)
     x = torch.arange(m, device=dev, dtype=torch.float64) * h
     y = torch.arange(n, device=dev, dtype=torch.float64) * h
     f = torch.zeros((n, m), device=dev, dtype=torch.float64)
     for k in range(32):
-        gx = torch.exp(-((x - cx[k]) ** 2) / (2.0 * sig[k] ** 2))
-        gy = torch.exp(-((y - cy[k]) ** 2) / (2.0 * sig[k] ** 2))
+        gx = torch.exp(-((x - cx[k]) ** 2) / (2.0 * sig_[k] ** 2))
+        gy = torch.exp(-((y - cy[k]) ** 2) / (2.0 * sig_[k] ** 2))
         f += amp[k] * torch.outer(gy, gx)
     return torch.as_tensor(psi0, device=dev), f, h, h
 
@@ -311,14 +342,18 @@ def run_batch_leg(args, ctx, torch, lap, dev):
     count = args.batch_count
     probs = W.ragged_batch(count=count, lo=33, hi=1025, seed=4)
     grids = [ctx.grid(torch.as_tensor(p.psi0, device=dev), None, p.dx, p.dy,
-                      alloc=lap.LAP_ALLOC_MIXED | lap.LAP_ALLOC_ADI) for p in probs]
+                      alloc=lap.LAP_ALLOC_MIXED | lap.LAP_ALLOC_ADI | lap.LAP_ALLOC_FP64) for p in probs]
     nodes = sum((p.m - 2) * (p.n - 2) for p in probs)
     lpc = [lup_per_cycle(g.levels()) for g in grids]
     out = {"grids": count, "interior_nodes": nodes}
+
+    def reset():
+        for g, p in zip(grids, probs):
+            g.write(torch.as_tensor(p.psi0, device=dev))
+
     # warm-up (plans, graphs), then timed batched mixed-precision multigrid
     ctx.solve_batch(grids, method="mg", precision="mixed", tol=1e-10, max_iter=200)
-    for g, p in zip(grids, probs):
-        g.write(torch.as_tensor(p.psi0, device=dev))
+    reset()
     sync()
     t0 = time.perf_counter()
     infos = ctx.solve_batch(grids, method="mg", precision="mixed", tol=1e-10, max_iter=200)
@@ -329,9 +364,19 @@ def run_batch_leg(args, ctx, torch, lap, dev):
                        "cycles_min": min(its), "cycles_max": max(its),
                        "all_converged": all(i["status"] == 0 for i in infos),
                        "solves_per_s": count / t}
+    # error against FP64: sampled grids solved alone with FP64 multigrid
+    sample = list(range(0, count, max(1, count // 8)))
+    mixed_u = {k: grids[k].read() for k in sample}
+    errs = []
+    for k in sample:
+        g = grids[k]
+        g.write(torch.as_tensor(probs[k].psi0, device=dev))
+        g.solve("mg", precision="fp64", tol=1e-10, max_iter=200)
+        errs.append(float((g.read() - mixed_u[k]).abs().max().item()))
+    out["mg_mixed"]["max_abs_vs_fp64_sampled"] = max(errs)
+    out["mg_mixed"]["sampled_grids"] = len(sample)
     # the same grids one at a time
-    for g, p in zip(grids, probs):
-        g.write(torch.as_tensor(p.psi0, device=dev))
+    reset()
     sync()
     t0 = time.perf_counter()
     seq = [g.solve("mg", precision="mixed", tol=1e-10, max_iter=200) for g in grids]
@@ -341,13 +386,11 @@ def run_batch_leg(args, ctx, torch, lap, dev):
                                      "same_iterations": [i["iterations"] for i in seq] == its}
     # batched zebra ADI: fixed number of iterations (every interior node is
     # updated twice per iteration: once by its row, once by its column)
-    for g, p in zip(grids, probs):
-        g.write(torch.as_tensor(p.psi0, device=dev))
     nit = args.adi_iters
+    reset()
     # warm-up builds the merged-launch plan of the timed step (same check block)
     ctx.solve_batch(grids, method="adi", omega=1.0, tol=0.0, max_iter=nit, check_every=nit)
-    for g, p in zip(grids, probs):
-        g.write(torch.as_tensor(p.psi0, device=dev))
+    reset()
     sync()
     t0 = time.perf_counter()
     ctx.solve_batch(grids, method="adi", omega=1.0, tol=0.0, max_iter=nit, check_every=nit)
@@ -367,40 +410,100 @@ def run_batch_leg(args, ctx, torch, lap, dev):
 def run_serving_leg(args, ctx, torch, lap, dev):
     """Poisson arrivals; m, n log-uniform in [17, 4097] snapped, beta = 1,
     32-bump source, tol 1e-8 or 1e-10; continuous batching (mixed) vs
-    one-at-a-time FP64 solves."""
+    one-at-a-time FP64 solves.  Every rate serves warm-up + count requests
+    (the request sizes, seeds and tolerances are the same at every rate, only
+    the arrival times scale); latency percentiles, solves/s and GLUP/s cover
+    the `count` requests after the warm-up, over the span from the first of
+    them arriving to the last finishing."""
     from paper_2208_02427_amd.serving import Job, Server, DeviceBackend, serve_sequential
-    res = {}
+    warm, count = args.serve_warmup, args.serve_count
+    total = warm + count
+    base = W.poisson_requests(1.0, total, seed=5, lo=17, hi=4097)
+    payload = {r.rid: device_request(torch, r, dev) for r in base}
+    sync()
+    lpc = {}
+
+    def lpc_of(m, n):          # smoother updates per cycle, from the hierarchy of an admitted grid
+        return lpc[(m, n)]
+
+    # requests whose result is compared with an FP64 solve of the same input
+    sample = {r.rid for r in base[warm:] if r.m * r.n <= 1025 * 1025}
+    sample = set(sorted(sample)[:: max(1, len(sample) // 6)])
+
+    class Backend(DeviceBackend):
+        def admit(self, job):
+            g = super().admit(job)
+            lpc[(job.m, job.n)] = lup_per_cycle(g.levels())
+            g._rid = job.rid
+            return g
+
+        def retire(self, g):
+            job_rid = getattr(g, "_rid", None)
+            out = g.read() if job_rid in sample else None
+            g.destroy()
+            return out
+
+    def stats_of(jobs):
+        meas = [j for j in jobs if j.rid >= warm and j.finished is not None]
+        lat = np.array([j.finished - j.arrival for j in meas])
+        span = max(j.finished for j in meas) - min(j.arrival for j in meas)
+        lups = sum(j.iterations * lpc_of(j.m, j.n) for j in meas)
+        return {"requests": len(meas), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "solves_per_s": len(meas) / span,
+                "GLUP/s": lups / span / 1e9,
+                "failed": sum(1 for j in jobs if j.status not in (None, 0))}
+
+    res = {"warmup_requests": warm, "measured_requests": count}
+    errs = []
     for rate in args.rates:
-        reqs = W.poisson_requests(rate, args.serve_count, seed=5, lo=17, hi=4097)
-        jobs = [Job(r.rid, r.arrival, r.m, r.n, r.tol, payload=device_request(torch, r, dev)) for r in reqs]
-        nodes = {j.rid: (j.m - 2) * (j.n - 2) for j in jobs}
+        say("serving", rate, "requests/s")
+        jobs = [Job(r.rid, r.arrival / rate, r.m, r.n, r.tol, payload=payload[r.rid]) for r in base]
         sync()
-        stats = Server(DeviceBackend(ctx, precision="mixed"), max_active=256, burst=args.burst,
-                       solo_max_nodes=args.solo_max_nodes).run(jobs)
-        sm = stats.summary()
-        sm["GLUP/s"] = None
-        sm["burst"] = args.burst
-        sm["solo_max_nodes"] = args.solo_max_nodes
+        server = Server(Backend(ctx, precision="mixed"), max_active=256, burst=args.burst,
+                        solo_max_nodes=args.solo_max_nodes)
+        stats = server.run(jobs)
+        sm = stats_of(jobs)
+        sm["max_active"] = stats.max_active
+        sm["solo"] = stats.solo
         res[str(int(rate))] = {"batched_mixed": sm}
+        if not errs:
+            # error against FP64 of sampled served results (first rate only)
+            for j in jobs:
+                if j.rid in sample and j.result is not None:
+                    psi0, f, dx, dy = j.payload
+                    g = ctx.grid(psi0, f, dx, dy, alloc=lap.LAP_ALLOC_FP64)
+                    g.solve("mg", precision="fp64", tol=j.tol, max_iter=100)
+                    errs.append(float((g.read() - j.result).abs().max().item()))
+                    g.destroy()
+            res["max_abs_served_vs_fp64_sampled"] = max(errs) if errs else None
+            res["sampled_requests"] = len(errs)
+        for j in jobs:
+            j.result = None
         if rate in args.baseline_rates:
             def solve_one(job):
                 psi0, f, dx, dy = job.payload
                 g = ctx.grid(psi0, f, dx, dy, alloc=lap.LAP_ALLOC_FP64)
                 info = g.solve("mg", precision="fp64", tol=job.tol, max_iter=100)
+                lpc[(job.m, job.n)] = lup_per_cycle(g.levels())
                 g.destroy()
                 return info
-            jobs2 = [Job(j.rid, r.arrival, j.m, j.n, j.tol, payload=j.payload) for j, r in zip(jobs, reqs)]
+            jobs2 = [Job(r.rid, r.arrival / rate, r.m, r.n, r.tol, payload=payload[r.rid]) for r in base]
+            say("serving one at a time (FP64)", rate, "requests/s")
             sync()
-            res[str(int(rate))]["one_at_a_time_fp64"] = serve_sequential(solve_one, jobs2).summary()
-        del jobs
+            serve_sequential(solve_one, jobs2)
+            res[str(int(rate))]["one_at_a_time_fp64"] = stats_of(jobs2)
         torch.cuda.empty_cache()
+    del payload
     return res
 
 
-def cpu_baseline():
-    """The oracle as it stands: one FP64 V(2,2) cycle of the 4097 x 4097 solve."""
-    from oracle import multigrid as omg
-    N = 4097
+def cpu_baseline_leg(headline, keep, N):
+    """The oracle as it stands, on this host: one FP64 V(2,2) cycle of the
+    N x N headline solve (numpy; its elementwise operations run on one core),
+    extrapolated to the solve's cycle count.  The oracle is loaded here, so
+    this leg also checks the large GPU results against the oracle's exact
+    spectral solution of the same discrete problem (DST-I in x and y)."""
+    from oracle import multigrid as omg, direct
     p = W.square_problem(N, seed=2)
     lv = omg.hierarchy(N, N, p.dx, p.dy)
     u = p.psi0.copy()
@@ -408,9 +511,84 @@ def cpu_baseline():
     omg.vcycle(lv, 0, u, None)
     t = time.perf_counter() - t0
     lups = lup_per_cycle([(a, b) for a, b, _, _ in lv])
-    return {"value": lups / t / 1e9, "unit": "GLUP/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 V(2,2) cycle of the 4097x4097 solve (11 levels), numpy oracle, {t:.1f} s; "
-                      f"host has {len(os.sched_getaffinity(0))} cores, numpy elementwise runs on 1"}
+    cycles = headline["cycles"]
+    base = {"value": lups / t / 1e9, "unit": "GLUP/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 of {cycles} FP64 V(2,2) cycles of the {N}^2 solve (numpy, {t:.1f} s, 1 core of "
+                      f"{len(os.sched_getaffinity(0))}); solve x{cycles} = {cycles * t:.0f} s extrapolated"}
+    errors = {}
+    t0 = time.perf_counter()
+    if "mg" in keep:
+        pp, ug = keep["mg"]
+        ex = direct.dst_solve(pp.m, pp.n, pp.dx, pp.dy, pp.psi0, pp.f)
+        errors["fp64_mg_vs_exact"] = float(np.max(np.abs(ug - ex)))
+        del ex
+    if "bumps" in keep:
+        pb, u64, umx = keep["bumps"]
+        ex = direct.dst_solve(pb.m, pb.n, pb.dx, pb.dy, pb.psi0, pb.f)
+        errors["bumps_fp64_vs_exact"] = float(np.max(np.abs(u64 - ex)))
+        errors["bumps_mixed_vs_exact"] = float(np.max(np.abs(umx - ex)))
+        errors["bumps_exact_max_abs"] = float(np.max(np.abs(ex)))
+        del ex
+    errors["dst_seconds"] = time.perf_counter() - t0
+    return base, errors
+
+
+def compact(line_full, d):
+    """The per-leg figures that go on the stdout line."""
+    legs = {}
+    if d.get("time_to_tol_graph_s"):
+        legs["mg_graph_ms"] = sig(d["time_to_tol_graph_s"] * 1e3)
+    legs["residual_kernel_frac"] = sig(d["residual_kernel"]["frac_of_peak"], 3)
+    legs["solve_alg_GB/s"] = sig(d["solve_hbm"]["GB/s_over_step_time"])
+    for key in ("mixed", "mixed_4097"):
+        if key in d:
+            x = d[key]
+            legs[key] = {"fp64_ms": sig(x["fp64"]["time_to_tol_s"] * 1e3),
+                         "mixed_ms": sig(x["mixed"]["time_to_tol_s"] * 1e3),
+                         "speedup": sig(x["speedup_mixed_over_fp64"], 3),
+                         "steps": [x["fp64"]["iterations"], x["mixed"]["iterations"]],
+                         "err": sig(x["max_abs_mixed_vs_fp64"], 2)}
+    if "sor" in d:
+        legs["sor"] = {k: [v["sweeps"], sig(v["seconds"], 3), sig(v["GLUP/s"])] for k, v in d["sor"].items()}
+        legs["sor"]["cols"] = "sweeps,s,GLUP/s"
+    if "mg_4097" in d:
+        legs["mg_4097_ms"] = sig(d["mg_4097"]["time_to_tol_s"] * 1e3)
+    if "chamber" in d:
+        c = d["chamber"]
+        wb = f"{c['sor_best_omega']:.2f}"
+        legs["chamber"] = {"cols": "iterations,us", "sor1": [c["sor_iters_us"]["1.00"][0], sig(c["sor_iters_us"]["1.00"][1], 3)],
+                           "sor" + wb: [c["sor_iters_us"][wb][0], sig(c["sor_iters_us"][wb][1], 3)],
+                           "adi1": [c["adi_after_w1"][0], sig(c["adi_after_w1"][1], 3)],
+                           "mg": [c["mg_v22"][0], sig(c["mg_v22"][1], 3)]}
+    if "ragged_batch" in d:
+        b = d["ragged_batch"]
+        legs["batch512"] = {"mg_ms": sig(b["mg_mixed"]["seconds"] * 1e3),
+                            "cycles": [b["mg_mixed"]["cycles_min"], b["mg_mixed"]["cycles_max"]],
+                            "GLUP/s": sig(b["mg_mixed"]["GLUP/s"]),
+                            "vs_one_at_a_time": sig(b["mg_mixed_one_at_a_time"]["speedup_of_batch"], 3),
+                            "err": sig(b["mg_mixed"]["max_abs_vs_fp64_sampled"], 2),
+                            "adi20_ms": sig(b["adi"]["seconds"] * 1e3), "adi_GB/s": sig(b["adi"]["alg_GB/s"])}
+    if "serving" in d:
+        s = d["serving"]
+        sv = {}
+        for rate, v in s.items():
+            if not isinstance(v, dict) or "batched_mixed" not in v:
+                continue
+            bm = v["batched_mixed"]
+            row = [sig(bm["p50_ms"], 3), sig(bm["p99_ms"], 3), sig(bm["solves_per_s"], 4), sig(bm["GLUP/s"], 3)]
+            if "one_at_a_time_fp64" in v:
+                o = v["one_at_a_time_fp64"]
+                row += [sig(o["p50_ms"], 3), sig(o["p99_ms"], 3), sig(o["solves_per_s"], 4)]
+            sv[rate] = row
+        sv["cols"] = "p50,p99 ms,solves/s,GLUP/s[,FP64 1-by-1 p50,p99,solves/s]"
+        sv["err"] = sig(s.get("max_abs_served_vs_fp64_sampled"), 2)
+        legs["serve"] = sv
+    if "errors_vs_exact" in d:
+        short = {"fp64_mg_vs_exact": "mg", "bumps_fp64_vs_exact": "bumps_fp64", "bumps_mixed_vs_exact": "bumps_mixed",
+                 "bumps_exact_max_abs": "bumps_max|u|"}
+        legs["err_vs_exact"] = {short[k]: sig(v, 2) for k, v in d["errors_vs_exact"].items() if k in short}
+    line_full["legs"] = legs
+    return line_full
 
 
 def main():
@@ -425,6 +603,7 @@ def main():
     ap.add_argument("--tuning-out", default=None,
                     help="write the autotune reports as a tiling table (the format of the shipped "
                          "paper_2208_02427_amd/tuning_gfx950.json)")
+    ap.add_argument("--detail-out", default=None, help="also write the full record of every leg here (JSON)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a plain 1 GiB device copy")
     ap.add_argument("--measure-only", action="store_true",
                     help="only measured-mode solves (for profiler runs: no graph replay leg)")
@@ -436,7 +615,8 @@ def main():
     ap.add_argument("--no-serve", dest="serve", action="store_false", help="skip the serving leg")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--adi-iters", type=int, default=20)
-    ap.add_argument("--serve-count", type=int, default=300)
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--burst", type=int, default=4, help="outer steps per serving tick when no request waits")
     ap.add_argument("--solo-max-nodes", type=int, default=4097 * 4097,
                     help="largest request (m*n) solved alone when it finds the device idle (0: never)")
@@ -447,55 +627,91 @@ def main():
         print("bench.py measures one GPU only: the library runs each grid on a single MI355X "
               "(sharding across GPUs is not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    if args.mixed_only:
-        import torch
-        import paper_2208_02427_amd as lap
-        ctx = lap.Context(arena_bytes=16 << 30, device="cuda:0")
-        res = {"mixed": run_mixed_leg(args.size, ctx, torch, lap, "cuda:0")}
+    import torch
+    import paper_2208_02427_amd as lap
+    dev = "cuda:0"
+    if args.mixed_only or args.batch_only:
+        ctx = lap.Context(arena_bytes=16 << 30, device=dev)
+        res = {"mixed": run_mixed_leg(args.size, ctx, torch, lap, dev)} if args.mixed_only else \
+              {"ragged_batch": run_batch_leg(args, ctx, torch, lap, dev)}
         if args.copy_probe:
-            res["copy_probe"] = run_copy_probe(torch, lap, "cuda:0")
+            res["copy_probe"] = run_copy_probe(torch, lap, dev)
         print(json.dumps(res), flush=True)
         return
-    if args.batch_only:
-        import torch
-        import paper_2208_02427_amd as lap
-        ctx = lap.Context(arena_bytes=16 << 30, device="cuda:0")
-        res = {"ragged_batch": run_batch_leg(args, ctx, torch, lap, "cuda:0")}
-        if args.copy_probe:
-            res["copy_probe"] = run_copy_probe(torch, lap, "cuda:0")
-        print(json.dumps(res), flush=True)
-        return
-    out, levels = run_gpu(args)
+
+    N = args.size
+    ctx = lap.Context(arena_bytes=(16 << 30) if N > 4097 else (4 << 30), device=dev)
+    d = {}
+    # autotune the tilings of every level size the hierarchy visits down to
+    # the small-level subtree (setup, untimed); without it the Context keeps
+    # the shipped MI355X table
+    if not args.no_tune:
+        say("autotune")
+        sizes = [N]
+        while sizes[-1] > 65 and (sizes[-1] - 1) % 2 == 0:
+            sizes.append((sizes[-1] - 1) // 2 + 1)
+        t0 = time.perf_counter()
+        tune = [ctx.autotune(tn, tn, reps=3) for tn in sizes]
+        d["autotune"] = {"sizes": sizes, "seconds": time.perf_counter() - t0}
+        if args.tuning_out:
+            with open(args.tuning_out, "w") as fh:
+                json.dump({"device": "gfx950 (MI355X, 256 CUs)",
+                           "source": "lap_autotune on one MI355X, reps=3, sizes " + "/".join(map(str, sizes))
+                                     + " (python bench.py --tuning-out ...)",
+                           "reports": tune}, fh, indent=1)
+    if args.copy_probe:
+        d["copy_probe"] = run_copy_probe(torch, lap, dev)
+    keep = {} if not args.no_cpu else None
+    say("headline", N)
+    d.update(run_headline(args, ctx, torch, lap, dev, keep))
+    if not args.quick:
+        say("mixed", N)
+        d["mixed"] = run_mixed_leg(N, ctx, torch, lap, dev, keep)
+        if N > 4097:
+            say("mixed", 4097)
+            d["mixed_4097"] = run_mixed_leg(4097, ctx, torch, lap, dev)
+        say("sor")
+        d["sor"] = run_sor_leg(ctx, torch, lap, dev, sorted({4097, N}))
+        d["mg_4097"] = run_mg4097_leg(ctx, torch, lap, dev)
+        say("chamber")
+        d["chamber"] = run_chamber_leg(ctx, torch, lap, dev)
+        if args.batch:
+            say("ragged batch")
+            d["ragged_batch"] = run_batch_leg(args, ctx, torch, lap, dev)
+        if args.serve:
+            d["serving"] = run_serving_leg(args, ctx, torch, lap, dev)
+    ctx.close()
     line = {
         "metric": METRIC,
-        "value": round(out["value"], 3),
+        "value": round(d["value"], 3),
         "unit": "GLUP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(out["ms_per_step"], 3),
+        "ms_per_step": round(d["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.size}x{args.size} Laplace, unit square, U[0,1) Dirichlet (seed 2), f=0, "
-                        f"FP64 V(2,2) multigrid to rel. residual 1e-10",
-            "levels": len(levels), "cycles": out["cycles"], "parallelism": "single GPU",
+            "workload": f"{N}^2 unit square, U[0,1) boundary (seed 2), f=0, FP64 V(2,2) MG to rel.res 1e-10",
+            "levels": d["levels"], "cycles": d["cycles"], "parallelism": "single GPU",
         },
-        "time_to_tol_s": round(out["time_to_tol_s"], 5),
-        "time_to_tol_graph_s": None if out["time_to_tol_graph_s"] is None else round(out["time_to_tol_graph_s"], 5),
-        "rel_res": out["rel_res"],
-        "roofline": out["roofline"],
+        "roofline": {k: d["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel")},
     }
-    for k in ("solve_hbm", "residual_kernel", "copy_probe", "mixed", "sor", "mg_4097", "ragged_batch", "serving",
-              "kernels_fine", "autotune"):
-        if k in out:
-            line[k] = out[k]
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(line), flush=True)
+        say("cpu baseline (oracle) and errors against the exact solution")
+        base, errors = cpu_baseline_leg(d, keep, N)
+        line["cpu_baseline"] = base
+        d["cpu_baseline"] = base
+        d["errors_vs_exact"] = errors
+    d["roofline_full"] = d["roofline"]
+    print(json.dumps(d, default=float), file=sys.stderr, flush=True)
+    if args.detail_out:
+        with open(args.detail_out, "w") as fh:
+            json.dump(d, fh, indent=1, default=float)
+    print(json.dumps(compact(line, d)), flush=True)
 
 
 if __name__ == "__main__":

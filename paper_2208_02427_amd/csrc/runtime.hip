@@ -2549,7 +2549,14 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
     }
     const size_t ibytes = round_up(p->items.size() * sizeof(BatchItem), kAlign);
     const size_t sbytes = round_up(p->subs.size(), kAlign);
-    p->dev = (BatchItem*)c->arena.alloc(ibytes + sbytes + p->tmap.size() * sizeof(int32_t));
+    const size_t pbytes = ibytes + sbytes + p->tmap.size() * sizeof(int32_t);
+    p->dev = (BatchItem*)c->arena.alloc(pbytes);
+    if (!p->dev && !c->plans.empty()) {
+        // the grids filled the arena: drop the cached plans (after the work
+        // that may still read them) and try once more
+        plans_clear(c);
+        p->dev = (BatchItem*)c->arena.alloc(pbytes);
+    }
     if (!p->dev) {
         delete p;
         return fail(LAP_ENOMEM, "arena cannot hold the batch plan");

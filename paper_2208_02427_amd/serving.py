@@ -4,10 +4,18 @@ Policy (host side) over the library's tick primitive (lap_batch_step):
 
 * requests queue in arrival order;
 * at every tick, queued requests are admitted while their multigrid
-  hierarchy's HBM footprint (lap_grid_footprint) fits the context's largest
-  free arena block and the active set is below `max_active`; admission
-  copies the request's boundary data and source into a device-resident
-  hierarchy;
+  hierarchy's HBM footprint (lap_grid_footprint), plus the headroom the
+  backend asks for its per-tick tables (tick_reserve), fits the context's
+  largest free arena block and the active set is below `max_active`;
+  admission copies the request's boundary data and source into a
+  device-resident hierarchy;
+* a request whose footprint exceeds the whole arena (capacity) can never be
+  admitted: it fails at once with status LAP_ENOMEM instead of blocking the
+  queue;
+* if a tick still runs out of arena (TickOutOfMemory), the most recently
+  admitted grid that has not stepped yet (else the most recent one) is
+  released and goes back to the head of the queue, and the tick is retried
+  with the others; a grid that cannot tick alone fails with LAP_ENOMEM;
 * one tick advances every active grid by one outer step (one FP32 V-cycle
   inside FP64 defect correction), all grids' operations of a level merged
   into single launches; grids whose stopping rule holds leave the active set,
@@ -25,8 +33,11 @@ Policy (host side) over the library's tick primitive (lap_batch_step):
 
 The backend is any object with footprint(m, n) -> bytes, free_bytes(),
 admit(request) -> handle, tick(handles, steps) -> (done flags, infos), and
-retire(handle) -> result, and optionally solve_alone(handle, request) -> info.  `DeviceBackend` drives liblap; tests drive the
-policy with a simulated backend on a virtual clock.
+retire(handle) -> result, and optionally solve_alone(handle, request) ->
+info, capacity() -> bytes, tick_reserve(active grids) -> bytes and
+release(handle) (give the memory back without a result).  `DeviceBackend`
+drives liblap; tests drive the policy with a simulated backend on a virtual
+clock.
 """
 from __future__ import annotations
 
@@ -34,6 +45,12 @@ import time
 from dataclasses import dataclass, field
 
 import numpy as np
+
+ENOMEM = -2                         # lap_status LAP_ENOMEM
+
+
+class TickOutOfMemory(MemoryError):
+    """A tick could not allocate its per-tick tables in the arena."""
 
 
 @dataclass
@@ -103,17 +120,54 @@ class Server:
     def submit(self, job: Job):
         self.queue.append(job)
 
+    def _fail(self, job, status=ENOMEM):
+        job.status = status
+        job.finished = self.clock()
+        job.handle = None
+
     def _admit(self, now):
+        cap = getattr(self.backend, "capacity", None)
+        reserve = getattr(self.backend, "tick_reserve", None)
         while self.queue and len(self.active) < self.max_active:
             job = self.queue[0]
             if job.arrival > now:
                 break
-            if self.backend.footprint(job.m, job.n) > self.backend.free_bytes():
+            need = self.backend.footprint(job.m, job.n)
+            if cap is not None and need + (reserve(1) if reserve else 0) > cap():
+                self.queue.pop(0)           # can never fit: fail now rather than block the queue
+                self._fail(job)
+                continue
+            if reserve is not None:
+                need += reserve(len(self.active) + 1)
+            if need > self.backend.free_bytes():
                 break                       # wait for memory to free up (FIFO: no overtaking)
             self.queue.pop(0)
             job.handle = self.backend.admit(job)
             job.admitted = self.clock()
             self.active.append(job)
+
+    def _tick_active(self, steps):
+        """backend.tick over the active set; on TickOutOfMemory release the
+        most recently admitted grid (preferring one that has not stepped),
+        requeue it at the head of the queue and retry with the others."""
+        while True:
+            try:
+                return self.backend.tick([j.handle for j in self.active], steps)
+            except TickOutOfMemory:
+                if len(self.active) == 1:
+                    job = self.active.pop()
+                    if hasattr(self.backend, "release"):
+                        self.backend.release(job.handle)
+                    self._fail(job)
+                    return [], []
+                fresh = [k for k, j in enumerate(self.active) if not j.stepped]
+                k = fresh[-1] if fresh else len(self.active) - 1
+                job = self.active.pop(k)
+                self.backend.release(job.handle)
+                job.handle = None
+                job.admitted = None
+                job.stepped = False
+                self.queue.insert(0, job)
 
     def tick(self, stats: ServeStats | None = None):
         """Admit what fits, advance every active grid by one outer step (or
@@ -134,7 +188,7 @@ class Server:
                     stats.max_active = max(stats.max_active, 1)
                 return [job]
         steps = 1 if self.queue else self.burst
-        done, infos = self.backend.tick([j.handle for j in self.active], steps)
+        done, infos = self._tick_active(steps)
         finished, still = [], []
         for job, d, info in zip(self.active, done, infos):
             job.stepped = True
@@ -170,6 +224,13 @@ class Server:
             while k < len(pending) and pending[k].arrival <= now:
                 self.submit(pending[k])
                 k += 1
+            if not self.active and self.queue and self.queue[0].arrival <= now:
+                # nothing runs, so the arena holds no grid: a queued request
+                # that still does not fit cannot be served
+                self._admit(now)
+                if not self.active and self.queue and self.queue[0].arrival <= self.clock():
+                    self._fail(self.queue.pop(0))
+                continue
             if not self.active and not self.queue and k < len(pending):
                 # idle: wait for the next arrival
                 wait = pending[k].arrival - self.clock()
@@ -229,6 +290,18 @@ class DeviceBackend:
     def free_bytes(self):
         return self.ctx.usage()[1]
 
+    def capacity(self):
+        return int(self.ctx.arena.numel())
+
+    def tick_reserve(self, active):
+        """Arena headroom for one tick's merged plan and control tables
+        (tile tables and launch items: well under 256 KiB per grid up to
+        4097^2) besides the grids' hierarchies."""
+        return (8 << 20) + active * (256 << 10)
+
+    def release(self, g):
+        g.destroy()
+
     def admit(self, job):
         psi0, f, dx, dy = job.payload
         g = self.ctx.grid(psi0, f, dx, dy, alloc=self.alloc)
@@ -236,7 +309,14 @@ class DeviceBackend:
         return g
 
     def tick(self, grids, steps=1):
-        return self.ctx.batch_step(grids, precision=self.precision, steps=steps)
+        from . import LapError
+        from ._native import LAP_ENOMEM
+        try:
+            return self.ctx.batch_step(grids, precision=self.precision, steps=steps)
+        except LapError as e:
+            if e.status == LAP_ENOMEM:
+                raise TickOutOfMemory(str(e)) from e
+            raise
 
     def solve_alone(self, g, job):
         return g.solve("mg", precision=self.precision, tol=job.tol, max_iter=1000)

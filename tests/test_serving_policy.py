@@ -199,3 +199,80 @@ def test_solo_latency_beats_ticks_at_low_load():
         res[solo] = Server(be, clock=clk, solo_max_nodes=solo).run(jobs).summary()
     assert res[0]["solo"] == 0
     assert res[2049 * 2049]["p50_ms"] < res[0]["p50_ms"]
+
+
+class TightBackend(SimBackend):
+    """SimBackend with an arena capacity, a per-tick table reserve and a
+    tick that fails (TickOutOfMemory) while the active set exceeds
+    `tick_limit` grids; release() gives a grid's memory back."""
+
+    def __init__(self, *a, tick_limit=None, **kw):
+        super().__init__(*a, **kw)
+        self.tick_limit = tick_limit
+        self.released = []
+        self.oom_ticks = 0
+
+    def capacity(self):
+        return self.pool
+
+    def tick_reserve(self, active):
+        return 10 * active
+
+    def tick(self, handles, steps=1):
+        from paper_2208_02427_amd.serving import TickOutOfMemory
+        if self.tick_limit is not None and len(handles) > self.tick_limit:
+            self.oom_ticks += 1
+            raise TickOutOfMemory("plan does not fit")
+        return super().tick(handles, steps)
+
+    def release(self, h):
+        self.released.append(h["job"].rid)
+        self.used -= self.footprint(h["job"].m, h["job"].n)
+
+
+def test_request_that_never_fits_fails_without_blocking_the_queue():
+    clock = Clock()
+    be = TightBackend(clock, pool=5000)
+    jobs = [Job(0, 0.0, 10, 10, 1e-8, payload=3),
+            Job(1, 0.001, 100, 100, 1e-8, payload=3),       # 10000 > the whole pool
+            Job(2, 0.002, 20, 20, 1e-8, payload=2)]
+    stats = Server(be, clock=clock).run(jobs)
+    s = stats.summary()
+    assert s["completed"] == 3 and s["failed"] == 1
+    assert jobs[1].status == -2 and jobs[1].result is None
+    assert jobs[0].status == 0 and jobs[2].status == 0 and jobs[2].result == "result"
+    assert 1 not in be.admitted and be.used == 0
+
+
+def test_admission_keeps_headroom_for_tick_tables():
+    """Two grids of 2500 fit a 5000 pool by footprint alone, but not with the
+    reserve of 10 per active grid: the second waits for the first."""
+    clock = Clock()
+    be = TightBackend(clock, pool=5000)
+    jobs = [Job(0, 0.0, 50, 50, 1e-8, payload=4), Job(1, 0.0, 50, 50, 1e-8, payload=4)]
+    Server(be, clock=clock).run(jobs)
+    assert max(be.batches) == 1 and be.max_used <= 5000 - 10
+    assert all(j.status == 0 for j in jobs)
+
+
+def test_tick_out_of_memory_requeues_the_newest_grid():
+    """Ticks of more than two grids fail: the server releases the newest
+    grid that has not stepped, requeues it, and every request completes."""
+    clock = Clock()
+    be = TightBackend(clock, pool=100_000, tick_limit=2)
+    jobs = [Job(k, 0.0, 10, 10, 1e-8, payload=3 + k) for k in range(5)]
+    stats = Server(be, clock=clock).run(jobs)
+    s = stats.summary()
+    assert s["completed"] == 5 and s["failed"] == 0
+    assert be.oom_ticks > 0 and be.released
+    assert max(be.batches) <= 2
+    assert [j.iterations for j in jobs] == [3, 4, 5, 6, 7]
+
+
+def test_grid_that_cannot_tick_alone_fails():
+    clock = Clock()
+    be = TightBackend(clock, pool=100_000, tick_limit=0)
+    jobs = [Job(0, 0.0, 10, 10, 1e-8, payload=3)]
+    stats = Server(be, clock=clock).run(jobs)
+    assert stats.summary()["failed"] == 1 and jobs[0].status == -2
+    assert be.used == 0
