@@ -79,6 +79,18 @@ enum {
     LAP_ADI_RELAX_INSIDE = 1  /* w folded into the line system (SLORB, Eq. (10)); needs w < 1 + beta^2 */
 };
 
+/* Multigrid smoother (lap_opts.smoother; "Multigrid Method (V-Cycle)" with
+ * the line relaxation of the SLOR / ADI sections, Eqs. (8)-(9)). */
+enum {
+    LAP_SMOOTH_RB = 0,     /* red-black SOR sweeps; nu1 / nu2 count sweeps                     */
+    LAP_SMOOTH_ZEBRA = 1   /* alternating zebra line relaxation: one smoothing step = odd rows,
+                            * even rows, odd columns, even columns, each line solved exactly
+                            * (relaxation after the solve with omega); nu1 / nu2 count steps
+                            * (1, 1 is the usual choice).  Robust when dx != dy makes the
+                            * operator anisotropic.  Every level's lines must fit the segmented
+                            * line solver: sides of at most 4097 (LAP_EINVAL otherwise). */
+};
+
 /* Allocation flags (lap_grid_create_ex). */
 enum {
     LAP_ALLOC_FP64 = 1,       /* FP64 multigrid hierarchy (LAP_MG with LAP_FP64) */
@@ -110,10 +122,12 @@ typedef struct lap_opts {
     int32_t use_graph;    /* MG: replay a captured hipGraph per cycle (1) or launch (0);
                            * a grid's graph is captured on its second solve with the same
                            * method options (its first solve launches directly)           */
+    int32_t smoother;     /* MG: LAP_SMOOTH_RB or LAP_SMOOTH_ZEBRA                        */
 } lap_opts;
 
 /* Fill *o with the defaults: MG, FP64, omega 1, tol 1e-10, max_iter 100,
- * REL_L2, nu1 = nu2 = 2, check_every 1, ADI relax-after, use_graph 1. */
+ * REL_L2, nu1 = nu2 = 2, check_every 1, ADI relax-after, use_graph 1,
+ * smoother LAP_SMOOTH_RB. */
 void lap_opts_default(lap_opts* o);
 
 /* ---------------------------------------------------------------- context */

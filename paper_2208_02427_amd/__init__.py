@@ -16,7 +16,8 @@ import os
 
 from . import _native as N
 from ._native import (LAP_SOR_RB, LAP_ADI, LAP_MG, LAP_FP64, LAP_MIXED, LAP_STOP_REL_L2,  # noqa: F401
-                      LAP_STOP_RES_INF, LAP_ADI_RELAX_AFTER, LAP_ADI_RELAX_INSIDE, LAP_ALLOC_FP64,
+                      LAP_STOP_RES_INF, LAP_ADI_RELAX_AFTER, LAP_ADI_RELAX_INSIDE, LAP_SMOOTH_RB,
+                      LAP_SMOOTH_ZEBRA, LAP_ALLOC_FP64,
                       LAP_ALLOC_MIXED, LAP_ALLOC_ADI, LAP_ALLOC_ALL, LapInfo, LapOpts)
 
 # tilings measured by the autotuner on MI355X (applied to every new Context)
@@ -53,8 +54,11 @@ def _torch():
     return torch
 
 
+SMOOTHERS = {"rb": LAP_SMOOTH_RB, "zebra": LAP_SMOOTH_ZEBRA}
+
+
 def opts(method="mg", precision="fp64", omega=1.0, tol=1e-10, max_iter=100, stop="rel_l2", nu1=2, nu2=2,
-         check_every=1, adi_form="after", use_graph=True) -> LapOpts:
+         check_every=1, adi_form="after", use_graph=True, smoother="rb") -> LapOpts:
     o = LapOpts()
     lib().lap_opts_default(ctypes.byref(o))
     o.method = METHODS[method] if isinstance(method, str) else int(method)
@@ -69,6 +73,7 @@ def opts(method="mg", precision="fp64", omega=1.0, tol=1e-10, max_iter=100, stop
     o.adi_form = {"after": LAP_ADI_RELAX_AFTER, "inside": LAP_ADI_RELAX_INSIDE}[adi_form] \
         if isinstance(adi_form, str) else int(adi_form)
     o.use_graph = 1 if use_graph else 0
+    o.smoother = SMOOTHERS[smoother] if isinstance(smoother, str) else int(smoother)
     return o
 
 

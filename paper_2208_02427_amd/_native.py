@@ -22,6 +22,7 @@ LAP_SOR_RB, LAP_ADI, LAP_MG = 1, 2, 3
 LAP_FP64, LAP_MIXED = 0, 1
 LAP_STOP_REL_L2, LAP_STOP_RES_INF = 0, 1
 LAP_ADI_RELAX_AFTER, LAP_ADI_RELAX_INSIDE = 0, 1
+LAP_SMOOTH_RB, LAP_SMOOTH_ZEBRA = 0, 1
 LAP_ALLOC_FP64, LAP_ALLOC_MIXED, LAP_ALLOC_ADI, LAP_ALLOC_ALL = 1, 2, 4, 7
 
 # kernel classes of lap_ctx_kernel_stats
@@ -41,7 +42,7 @@ class LapInfo(ctypes.Structure):
 class LapOpts(ctypes.Structure):
     _fields_ = [("method", c_int32), ("precision", c_int32), ("omega", c_double), ("tol", c_double),
                 ("max_iter", c_int32), ("stop", c_int32), ("nu1", c_int32), ("nu2", c_int32),
-                ("check_every", c_int32), ("adi_form", c_int32), ("use_graph", c_int32)]
+                ("check_every", c_int32), ("adi_form", c_int32), ("use_graph", c_int32), ("smoother", c_int32)]
 
 
 _P = c_void_p

@@ -190,11 +190,16 @@ hipError_t launch_adi_rows(const LineArgs& a, hipStream_t s) {
 }
 
 // --------------------------------------------------------- segmented solver
+// Templated on the element type T of the field: FP64 for the ADI method,
+// FP32 as well for zebra line smoothing inside the mixed-precision V-cycle.
+// Every operation of a T solve is done in T with T coefficients and a T
+// table (the FP32 table is the extended-precision one rounded once).
 static_assert(kSegL + 1 == 16, "block index arithmetic assumes 16 unknowns per block and separator");
 constexpr int kSegBS = kSegL + 2;   // LDS slots of a row block: kSegL unknowns, separator, separator value
 
-void adi_seg_table(double Dd, double Ed, int K, double* tab) {
-    std::memset(tab, 0, sizeof(double) * kSegTab);
+template <typename T>
+void adi_seg_table_t(double Dd, double Ed, int K, T* tab) {
+    std::memset(tab, 0, sizeof(T) * kSegTab);
     if (K <= 0) return;
     typedef long double R;
     const int L = kSegL;
@@ -219,12 +224,12 @@ void adi_seg_table(double Dd, double Ed, int K, double* tab) {
     resp(L, g);
     resp(Ll, gl);
     for (int k = 0; k < L; ++k) {
-        tab[SEG_IPIV + k] = (double)(1 / piv[k]);
-        tab[SEG_CQ + k] = (double)cq[k];
-        tab[SEG_G + k] = (double)g[k];
-        tab[SEG_GL + k] = (double)gl[k];
+        tab[SEG_IPIV + k] = (T)(1 / piv[k]);
+        tab[SEG_CQ + k] = (T)cq[k];
+        tab[SEG_G + k] = (T)g[k];
+        tab[SEG_GL + k] = (T)gl[k];
     }
-    tab[SEG_E] = Ed;
+    tab[SEG_E] = (T)Ed;
     // one block only, or more separators than the table holds (such lines
     // take the sequential solver)
     if (S < 2 || S > kSegMaxS) return;
@@ -238,35 +243,40 @@ void adi_seg_table(double Dd, double Ed, int K, double* tab) {
     for (int p = 0; p < NR; ++p) {
         const R dg = (p == NR - 1) ? DRend : DR;
         pv = (p == 0) ? dg : dg - ER * ER / pv;
-        tab[SEG_IPIVR + p] = (double)(1 / pv);
-        tab[SEG_CQR + p] = (double)(ER / pv);
+        tab[SEG_IPIVR + p] = (T)(1 / pv);
+        tab[SEG_CQR + p] = (T)(ER / pv);
     }
-    tab[SEG_E + 1] = (double)ER;
+    tab[SEG_E + 1] = (T)ER;
 }
+
+void adi_seg_table(double D, double E, int K, double* tab) { adi_seg_table_t<double>(D, E, K, tab); }
+void adi_seg_table(double D, double E, int K, float* tab) { adi_seg_table_t<float>(D, E, K, tab); }
 
 // Right-hand side of one unknown from its own old value, the sum of its two
 // neighbours across the line and f (end values are added by the caller).
-__device__ __forceinline__ double seg_rhs(const LineArgs& A, double cc, double own, double nb, double fv) {
-    const double base = cc * nb - fv;
-    return A.form == 0 ? base : (1.0 - A.omega) * A.d * own + A.omega * base;
+template <typename T>
+__device__ __forceinline__ T seg_rhs(const LineArgsT<T>& A, T cc, T own, T nb, T fv) {
+    const T base = cc * nb - fv;
+    return A.form == 0 ? base : (T(1) - (T)A.omega) * (T)A.d * own + (T)A.omega * base;
 }
 
 // Forward elimination of one block given its right-hand sides r[0..len)
 // (len <= kSegL); leaves the block's zero-end solution in r, returns its
 // last value in *last.
-__device__ __forceinline__ void seg_block(const double* T, double E, int len, double (&r)[kSegL], double* last) {
-    double z = 0.0;
+template <typename T>
+__device__ __forceinline__ void seg_block(const T* Tb, T E, int len, T (&r)[kSegL], T* last) {
+    T z = 0;
 #pragma unroll
     for (int k = 0; k < kSegL; ++k)
         if (k < len) {
-            z = fma(E, z, r[k]) * T[SEG_IPIV + k];
+            z = fma(E, z, r[k]) * Tb[SEG_IPIV + k];
             r[k] = z;
         }
-    double x = 0.0, e = 0.0;
+    T x = 0, e = 0;
 #pragma unroll
     for (int k = kSegL - 1; k >= 0; --k)
         if (k < len) {
-            x = fma(T[SEG_CQ + k], x, r[k]);
+            x = fma(Tb[SEG_CQ + k], x, r[k]);
             r[k] = x;
             if (k == len - 1) e = x;
         }
@@ -280,19 +290,19 @@ __device__ __forceinline__ void seg_block(const double* T, double E, int len, do
 // x_{p+1} are first-order linear recurrences: each is evaluated as a
 // Hillis-Steele scan of affine maps in ceil(log2 NR) steps through two LDS
 // buffer pairs (a0, b0), (a1, b1) addressed by slot(p).  Returns x_p.
-template <typename Slot>
-__device__ __forceinline__ double seg_scan(const double* T, int NR, int p, bool act, double rho, Slot slot,
-                                           double* a0, double* b0, double* a1, double* b1) {
-    double a = 0.0, b = 0.0;
+template <typename T, typename Slot>
+__device__ __forceinline__ T seg_scan(const T* Tb, int NR, int p, bool act, T rho, Slot slot, T* a0, T* b0,
+                                      T* a1, T* b1) {
+    T a = 0, b = 0;
     if (act) {
-        const double ip = T[SEG_IPIVR + p];
-        a = p > 0 ? T[SEG_E + 1] * ip : 0.0;
+        const T ip = Tb[SEG_IPIVR + p];
+        a = p > 0 ? Tb[SEG_E + 1] * ip : T(0);
         b = rho * ip;
         a0[slot(p)] = a;
         b0[slot(p)] = b;
     }
     __syncthreads();
-    double *ra = a0, *rb = b0, *wa = a1, *wb = b1;
+    T *ra = a0, *rb = b0, *wa = a1, *wb = b1;
     for (int h = 1; h < NR; h <<= 1) {
         if (act) {
             if (p >= h) {
@@ -304,11 +314,11 @@ __device__ __forceinline__ double seg_scan(const double* T, int NR, int p, bool 
             wb[slot(p)] = b;
         }
         __syncthreads();
-        double* t = ra; ra = wa; wa = t;
+        T* t = ra; ra = wa; wa = t;
         t = rb; rb = wb; wb = t;
     }
     // b = z_p; now x_p = c_p x_{p+1} + z_p, scanned from the end
-    double c = (act && p < NR - 1) ? T[SEG_CQR + p] : 0.0;
+    T c = (act && p < NR - 1) ? Tb[SEG_CQR + p] : T(0);
     if (act) {
         ra[slot(p)] = c;
         rb[slot(p)] = b;
@@ -325,7 +335,7 @@ __device__ __forceinline__ double seg_scan(const double* T, int NR, int p, bool 
             wb[slot(p)] = b;
         }
         __syncthreads();
-        double* t = ra; ra = wa; wa = t;
+        T* t = ra; ra = wa; wa = t;
         t = rb; rb = wb; wb = t;
     }
     return b;
@@ -335,9 +345,9 @@ __device__ __forceinline__ double seg_scan(const double* T, int NR, int p, bool 
 // workgroup of NT threads.  The lines' right-hand sides are staged in
 // LDS row by row (coalesced); thread (line c, block s), s fastest, solves its
 // block from LDS; the solution goes back through LDS and is written row by
-// row with the relaxation.  lds: W * S * kSegBS doubles.
-template <int NT>
-static __device__ void adi_rows_seg(const LineArgs& A, int tile, double* lds) {
+// row with the relaxation.  lds: W * S * kSegBS values.
+template <typename T, int NT>
+static __device__ void adi_rows_seg(const LineArgsT<T>& A, int tile, T* lds) {
     const int K = A.m - 2;
     const int S = seg_count(K);
     const int W = NT / S;
@@ -347,9 +357,9 @@ static __device__ void adi_rows_seg(const LineArgs& A, int tile, double* lds) {
     const int nl = min(W, nlines - line0);
     if (nl <= 0) return;
     const size_t P = (size_t)A.P;
-    const double* T = A.seg;
-    const double E = T[SEG_E];
-    const double cc = A.cy;
+    const T* Tb = A.seg;
+    const T E = Tb[SEG_E];
+    const T cc = (T)A.cy;
     const int LW = S * kSegBS;
     const int tid = threadIdx.x;
     const int total = nl * K;
@@ -357,21 +367,21 @@ static __device__ void adi_rows_seg(const LineArgs& A, int tile, double* lds) {
     const float invK = 1.0f / (float)K;
     constexpr int kU = 8;   // elements in flight per thread
     for (int q0 = tid; q0 < total; q0 += kU * NT) {
-        double r[kU];
+        T r[kU];
         int slot[kU];
 #pragma unroll
         for (int v = 0; v < kU; ++v) {
             const int q = q0 + v * NT;
             slot[v] = -1;
-            r[v] = 0.0;
+            r[v] = 0;
             if (q < total) {
                 const int c = seg_div(q, invK);
                 const int k = q - c * K;
                 const size_t row = (size_t)(first + 2 * (line0 + c)) * P;
                 const size_t o = row + k + 1;
                 // the line's own old value enters only with relaxation inside
-                const double own = A.form == 0 ? 0.0 : A.u[o];
-                r[v] = seg_rhs(A, cc, own, A.u[o - P] + A.u[o + P], A.f != nullptr ? A.f[o] : 0.0);
+                const T own = A.form == 0 ? T(0) : A.u[o];
+                r[v] = seg_rhs<T>(A, cc, own, A.u[o - P] + A.u[o + P], A.f != nullptr ? A.f[o] : T(0));
                 if (k == 0) r[v] = r[v] + E * A.u[row];
                 if (k == K - 1) r[v] = r[v] + E * A.u[row + A.m - 1];
                 slot[v] = c * LW + (k >> 4) * kSegBS + (k & 15);
@@ -386,51 +396,51 @@ static __device__ void adi_rows_seg(const LineArgs& A, int tile, double* lds) {
     const int s = tid - c * S;
     const bool act = c < nl;
     const int len = s < S - 1 ? kSegL : K - (S - 1) * (kSegL + 1);
-    double* blk = lds + c * LW + s * kSegBS;
-    double y[kSegL];
+    T* blk = lds + c * LW + s * kSegBS;
+    T y[kSegL];
     if (act) {
 #pragma unroll
-        for (int k = 0; k < kSegL; ++k) y[k] = k < len ? blk[k] : 0.0;
-        double e;
-        seg_block(T, E, len, y, &e);
-        blk[0] = len > 0 ? y[0] : 0.0;
+        for (int k = 0; k < kSegL; ++k) y[k] = k < len ? blk[k] : T(0);
+        T e;
+        seg_block<T>(Tb, E, len, y, &e);
+        blk[0] = len > 0 ? y[0] : T(0);
         blk[1] = e;
     }
     __syncthreads();
     if (S > 1) {
         // slots 2..5 of each block are free now (its unknowns live in y)
         const bool sep = act && s < S - 1;
-        const double rho = sep ? fma(E, blk[1] + blk[kSegBS], blk[kSegL]) : 0.0;
-        double* lb = lds + c * LW;
+        const T rho = sep ? fma(E, blk[1] + blk[kSegBS], blk[kSegL]) : T(0);
+        T* lb = lds + c * LW;
         const auto slot = [](int p) { return p * kSegBS; };
-        const double x = seg_scan(T, S - 1, s, sep, rho, slot, lb + 2, lb + 3, lb + 4, lb + 5);
+        const T x = seg_scan<T>(Tb, S - 1, s, sep, rho, slot, lb + 2, lb + 3, lb + 4, lb + 5);
         if (sep) blk[kSegL + 1] = x;
         __syncthreads();
     }
     if (act) {
-        const double xl = s > 0 ? blk[kSegL + 1 - kSegBS] : 0.0;
+        const T xl = s > 0 ? blk[kSegL + 1 - kSegBS] : T(0);
         if (s < S - 1) {
-            const double xr = blk[kSegL + 1];
+            const T xr = blk[kSegL + 1];
 #pragma unroll
             for (int k = 0; k < kSegL; ++k)
-                blk[k] = fma(xr, T[SEG_G + kSegL - 1 - k], fma(xl, T[SEG_G + k], y[k]));
+                blk[k] = fma(xr, Tb[SEG_G + kSegL - 1 - k], fma(xl, Tb[SEG_G + k], y[k]));
             blk[kSegL] = xr;
         } else {
 #pragma unroll
             for (int k = 0; k < kSegL; ++k)
-                if (k < len) blk[k] = fma(xl, T[SEG_GL + k], y[k]);
+                if (k < len) blk[k] = fma(xl, Tb[SEG_GL + k], y[k]);
         }
     }
     __syncthreads();
-    const double w = A.omega;
+    const T w = (T)A.omega;
     for (int q0 = tid; q0 < total; q0 += kU * NT) {
-        double old[kU], t[kU];
+        T old[kU], t[kU];
         size_t at[kU];
 #pragma unroll
         for (int v = 0; v < kU; ++v) {
             const int q = q0 + v * NT;
             at[v] = 0;
-            old[v] = t[v] = 0.0;
+            old[v] = t[v] = 0;
             if (q < total) {
                 const int c2 = seg_div(q, invK);
                 const int k = q - c2 * K;
@@ -448,10 +458,10 @@ static __device__ void adi_rows_seg(const LineArgs& A, int tile, double* lds) {
 // Column lines of the parity in A, tile `tile` (W = NT / S lines), one
 // workgroup of NT threads; thread (line c, block s), c fastest,
 // so a wavefront's accesses to one row are contiguous.  Each thread keeps
-// its block's old values and solution in registers.  sh: 5 * NT doubles
+// its block's old values and solution in registers.  sh: 5 * NT values
 // (first and last block values, separator values, scan buffers).
-template <int NT>
-static __device__ void adi_cols_seg(const LineArgs& A, int tile, double* sh) {
+template <typename T, int NT>
+static __device__ void adi_cols_seg(const LineArgsT<T>& A, int tile, T* sh) {
     const int K = A.n - 2;
     const int S = seg_count(K);
     const int W = NT / S;
@@ -461,9 +471,9 @@ static __device__ void adi_cols_seg(const LineArgs& A, int tile, double* sh) {
     const int nl = min(W, nlines - line0);
     if (nl <= 0) return;
     const size_t P = (size_t)A.P;
-    const double* T = A.seg;
-    const double E = T[SEG_E];
-    const double cc = A.cx;
+    const T* Tb = A.seg;
+    const T E = Tb[SEG_E];
+    const T cc = (T)A.cx;
     const int tid = threadIdx.x;
     const int s = seg_div(tid, 1.0f / (float)W);
     const int c = tid - s * W;
@@ -471,23 +481,23 @@ static __device__ void adi_cols_seg(const LineArgs& A, int tile, double* sh) {
     const int len = s < S - 1 ? kSegL : K - (S - 1) * (kSegL + 1);
     const int i = first + 2 * (line0 + c);
     const int k0 = s * (kSegL + 1);
-    double* yF = sh;
-    double* yE = sh + NT;
-    double* xs = sh + 2 * NT;
+    T* yF = sh;
+    T* yE = sh + NT;
+    T* xs = sh + 2 * NT;
     const int me = s * W + c;
-    double y[kSegL], old[kSegL];
-    double osep = 0.0, rsep = 0.0, e = 0.0;
+    T y[kSegL], old[kSegL];
+    T osep = 0, rsep = 0, e = 0;
     if (act) {
-        const double* up = A.u + (size_t)(k0 + 1) * P + i;
-        const double* fp = A.f != nullptr ? A.f + (size_t)(k0 + 1) * P + i : nullptr;
+        const T* up = A.u + (size_t)(k0 + 1) * P + i;
+        const T* fp = A.f != nullptr ? A.f + (size_t)(k0 + 1) * P + i : nullptr;
 #pragma unroll
         for (int k = 0; k < kSegL; ++k) {
-            old[k] = 0.0;
-            y[k] = 0.0;
+            old[k] = 0;
+            y[k] = 0;
             if (k < len) {
-                const double* q = up + (size_t)k * P;
+                const T* q = up + (size_t)k * P;
                 old[k] = q[0];
-                y[k] = seg_rhs(A, cc, q[0], q[-1] + q[1], fp != nullptr ? fp[(size_t)k * P] : 0.0);
+                y[k] = seg_rhs<T>(A, cc, q[0], q[-1] + q[1], fp != nullptr ? fp[(size_t)k * P] : T(0));
             }
         }
         if (s == 0) y[0] = y[0] + E * A.u[i];
@@ -497,34 +507,34 @@ static __device__ void adi_cols_seg(const LineArgs& A, int tile, double* sh) {
                 if (k == len - 1) y[k] = y[k] + E * A.u[(size_t)(A.n - 1) * P + i];
         }
         if (s < S - 1) {
-            const double* q = up + (size_t)kSegL * P;
+            const T* q = up + (size_t)kSegL * P;
             osep = q[0];
-            rsep = seg_rhs(A, cc, q[0], q[-1] + q[1], fp != nullptr ? fp[(size_t)kSegL * P] : 0.0);
+            rsep = seg_rhs<T>(A, cc, q[0], q[-1] + q[1], fp != nullptr ? fp[(size_t)kSegL * P] : T(0));
             if (k0 + kSegL == K - 1) rsep = rsep + E * A.u[(size_t)(A.n - 1) * P + i];
         }
-        seg_block(T, E, len, y, &e);
-        yF[me] = len > 0 ? y[0] : 0.0;
+        seg_block<T>(Tb, E, len, y, &e);
+        yF[me] = len > 0 ? y[0] : T(0);
         yE[me] = e;
     }
     __syncthreads();
     if (S > 1) {
         const bool sep = act && s < S - 1;
-        const double rho = sep ? fma(E, e + yF[me + W], rsep) : 0.0;
+        const T rho = sep ? fma(E, e + yF[me + W], rsep) : T(0);
         const auto slot = [W, c](int p) { return p * W + c; };
-        const double x = seg_scan(T, S - 1, s, sep, rho, slot, yE, xs, sh + 3 * NT, sh + 4 * NT);
+        const T x = seg_scan<T>(Tb, S - 1, s, sep, rho, slot, yE, xs, sh + 3 * NT, sh + 4 * NT);
         // yF is read above until every thread has passed the scan's first barrier
         if (sep) xs[me] = x;
         __syncthreads();
     }
     if (act) {
-        const double w = A.omega;
-        const double xl = s > 0 ? xs[me - W] : 0.0;
-        double* up = A.u + (size_t)(k0 + 1) * P + i;
+        const T w = (T)A.omega;
+        const T xl = s > 0 ? xs[me - W] : T(0);
+        T* up = A.u + (size_t)(k0 + 1) * P + i;
         if (s < S - 1) {
-            const double xr = xs[me];
+            const T xr = xs[me];
 #pragma unroll
             for (int k = 0; k < kSegL; ++k) {
-                const double t = fma(xr, T[SEG_G + kSegL - 1 - k], fma(xl, T[SEG_G + k], y[k]));
+                const T t = fma(xr, Tb[SEG_G + kSegL - 1 - k], fma(xl, Tb[SEG_G + k], y[k]));
                 up[(size_t)k * P] = (A.form == 0) ? old[k] + w * (t - old[k]) : t;
             }
             up[(size_t)kSegL * P] = (A.form == 0) ? osep + w * (xr - osep) : xr;
@@ -532,35 +542,36 @@ static __device__ void adi_cols_seg(const LineArgs& A, int tile, double* sh) {
 #pragma unroll
             for (int k = 0; k < kSegL; ++k)
                 if (k < len) {
-                    const double t = fma(xl, T[SEG_GL + k], y[k]);
+                    const T t = fma(xl, Tb[SEG_GL + k], y[k]);
                     up[(size_t)k * P] = (A.form == 0) ? old[k] + w * (t - old[k]) : t;
                 }
         }
     }
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_adi_rows_seg(LineArgs A, int ntiles) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_adi_rows_seg(LineArgsT<T> A, int ntiles) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
-    __shared__ double lds[NT * kSegBS];
+    __shared__ T lds[NT * kSegBS];
     const int t = xcd_remap(blockIdx.x, gridDim.x);
-    if (t < ntiles) adi_rows_seg<NT>(A, t, lds);
+    if (t < ntiles) adi_rows_seg<T, NT>(A, t, lds);
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_adi_cols_seg(LineArgs A, int ntiles) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_adi_cols_seg(LineArgsT<T> A, int ntiles) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
-    __shared__ double sh[5 * NT];
+    __shared__ T sh[5 * NT];
     const int t = xcd_remap(blockIdx.x, gridDim.x);
-    if (t < ntiles) adi_cols_seg<NT>(A, t, sh);
+    if (t < ntiles) adi_cols_seg<T, NT>(A, t, sh);
 }
 
 // ------------------------------------------------------- merged batch launches
 
-__device__ __forceinline__ LineArgs line_args(const BatchItem& it) {
-    LineArgs a{};
-    a.u = (double*)it.out;
-    a.f = (const double*)it.f;
+template <typename T>
+__device__ __forceinline__ LineArgsT<T> line_args(const BatchItem& it) {
+    LineArgsT<T> a{};
+    a.u = (T*)it.out;
+    a.f = (const T*)it.f;
     a.scratch = it.scratch;
     a.cprime = it.cprime;
     a.piv = it.piv;
@@ -575,7 +586,7 @@ __device__ __forceinline__ LineArgs line_args(const BatchItem& it) {
     a.a_off = it.a_off;
     a.form = it.flags;
     a.parity = it.parity;
-    a.seg = it.seg;
+    a.seg = (const T*)it.seg;
     return a;
 }
 
@@ -587,7 +598,7 @@ __global__ __launch_bounds__(64) void k_batch_adi_rows(const BatchItem* items, c
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
-        adi_rows_block(line_args(it), t - it.tile0, tile, told);
+        adi_rows_block(line_args<double>(it), t - it.tile0, tile, told);
     }
 }
 
@@ -596,73 +607,112 @@ __global__ __launch_bounds__(kBlock) void k_batch_adi_cols(const BatchItem* item
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
-        adi_col_line(line_args(it), (t - it.tile0) * kBlock + threadIdx.x);
+        adi_col_line(line_args<double>(it), (t - it.tile0) * kBlock + threadIdx.x);
     }
 }
 
 // Segmented solver over all grids: tiles of seg_lines lines of one grid,
 // dealt XCD-contiguously (neighbouring tiles share boundary lines).
-template <int NT>
+template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_batch_adi_rows_seg(const BatchItem* items, const int* tmap, int total) {
-    __shared__ double lds[NT * kSegBS];
+    __shared__ T lds[NT * kSegBS];
     for (int t = xcd_remap(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
         const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
-        adi_rows_seg<NT>(line_args(it), t - it.tile0, lds);
+        adi_rows_seg<T, NT>(line_args<T>(it), t - it.tile0, lds);
         __syncthreads();
     }
 }
 
-template <int NT>
+template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_batch_adi_cols_seg(const BatchItem* items, const int* tmap, int total) {
-    __shared__ double sh[5 * NT];
+    __shared__ T sh[5 * NT];
     for (int t = xcd_remap(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
         const BatchItem& it = items[tmap[t]];
         if (it.ctrl->done) continue;
-        adi_cols_seg<NT>(line_args(it), t - it.tile0, sh);
+        adi_cols_seg<T, NT>(line_args<T>(it), t - it.tile0, sh);
         __syncthreads();
     }
 }
 
-hipError_t launch_adi_rows_seg(const LineArgs& a, int lines, hipStream_t s) {
+template <typename T>
+hipError_t launch_adi_rows_seg(const LineArgsT<T>& a, int lines, hipStream_t s) {
     const int W = seg_lines(0, a.m - 2);
     const int nt = (lines + W - 1) / W;
     if (seg_code(0, a.m - 2) == 1)
-        k_adi_rows_seg<256><<<xcd_pad(nt), 256, 0, s>>>(a, nt);
+        k_adi_rows_seg<T, 256><<<xcd_pad(nt), 256, 0, s>>>(a, nt);
     else
-        k_adi_rows_seg<128><<<xcd_pad(nt), 128, 0, s>>>(a, nt);
+        k_adi_rows_seg<T, 128><<<xcd_pad(nt), 128, 0, s>>>(a, nt);
     return hipGetLastError();
 }
 
-hipError_t launch_adi_cols_seg(const LineArgs& a, int lines, hipStream_t s) {
+template <typename T>
+hipError_t launch_adi_cols_seg(const LineArgsT<T>& a, int lines, hipStream_t s) {
     const int W = seg_lines(1, a.n - 2);
     const int nt = (lines + W - 1) / W;
     if (seg_code(1, a.n - 2) == 0)
-        k_adi_cols_seg<256><<<xcd_pad(nt), 256, 0, s>>>(a, nt);
+        k_adi_cols_seg<T, 256><<<xcd_pad(nt), 256, 0, s>>>(a, nt);
     else
-        k_adi_cols_seg<1024><<<xcd_pad(nt), 1024, 0, s>>>(a, nt);
+        k_adi_cols_seg<T, 1024><<<xcd_pad(nt), 1024, 0, s>>>(a, nt);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_adi(int kind, int flags, const BatchItem* items, const int* tmap, int total, int blocks,
-                            hipStream_t s) {
+hipError_t launch_adi_rows_seg(const LineArgs& a, int lines, hipStream_t s) {
+    return launch_adi_rows_seg<double>(a, lines, s);
+}
+hipError_t launch_adi_cols_seg(const LineArgs& a, int lines, hipStream_t s) {
+    return launch_adi_cols_seg<double>(a, lines, s);
+}
+
+// Zebra line smoothing half (segmented solver only): lines of one parity of
+// one direction, in place on a.u, FP64 or FP32.
+template <typename T>
+hipError_t launch_zebra_lines(const LineArgsT<T>& a, int dir, hipStream_t s) {
+    const int first = a.parity ? 1 : 2;
+    const int across = dir == 0 ? a.n - 2 : a.m - 2;
+    const int K = dir == 0 ? a.m - 2 : a.n - 2;
+    const int lines = across >= first ? (across - first) / 2 + 1 : 0;
+    if (lines <= 0) return hipSuccess;
+    if (a.seg == nullptr || !seg_fits(dir, K)) return hipErrorInvalidValue;
+    return dir == 0 ? launch_adi_rows_seg<T>(a, lines, s) : launch_adi_cols_seg<T>(a, lines, s);
+}
+template hipError_t launch_zebra_lines<double>(const LineArgsT<double>&, int, hipStream_t);
+template hipError_t launch_zebra_lines<float>(const LineArgsT<float>&, int, hipStream_t);
+
+hipError_t launch_batch_adi(int kind, int flags, int dt, const BatchItem* items, const int* tmap, int total,
+                            int blocks, hipStream_t s) {
     if (total <= 0) return hipSuccess;
     if (flags & ADI_SEG) {
         blocks = xcd_pad(blocks);
         const int code = (flags >> ADI_CODE_SHIFT) & 3;
         if (kind == BK_ADI_ROWS) {
-            if (code == 1)
-                k_batch_adi_rows_seg<256><<<blocks, 256, 0, s>>>(items, tmap, total);
-            else
-                k_batch_adi_rows_seg<128><<<blocks, 128, 0, s>>>(items, tmap, total);
+            if (dt == 0) {
+                if (code == 1)
+                    k_batch_adi_rows_seg<double, 256><<<blocks, 256, 0, s>>>(items, tmap, total);
+                else
+                    k_batch_adi_rows_seg<double, 128><<<blocks, 128, 0, s>>>(items, tmap, total);
+            } else {
+                if (code == 1)
+                    k_batch_adi_rows_seg<float, 256><<<blocks, 256, 0, s>>>(items, tmap, total);
+                else
+                    k_batch_adi_rows_seg<float, 128><<<blocks, 128, 0, s>>>(items, tmap, total);
+            }
         } else {
-            if (code == 0)
-                k_batch_adi_cols_seg<256><<<blocks, 256, 0, s>>>(items, tmap, total);
-            else
-                k_batch_adi_cols_seg<1024><<<blocks, 1024, 0, s>>>(items, tmap, total);
+            if (dt == 0) {
+                if (code == 0)
+                    k_batch_adi_cols_seg<double, 256><<<blocks, 256, 0, s>>>(items, tmap, total);
+                else
+                    k_batch_adi_cols_seg<double, 1024><<<blocks, 1024, 0, s>>>(items, tmap, total);
+            } else {
+                if (code == 0)
+                    k_batch_adi_cols_seg<float, 256><<<blocks, 256, 0, s>>>(items, tmap, total);
+                else
+                    k_batch_adi_cols_seg<float, 1024><<<blocks, 1024, 0, s>>>(items, tmap, total);
+            }
         }
         return hipGetLastError();
     }
+    if (dt != 0) return hipErrorInvalidValue;   // the sequential solver is FP64 only
     if (kind == BK_ADI_ROWS)
         k_batch_adi_rows<<<blocks, kRowTile, 0, s>>>(items, tmap, total);
     else

@@ -73,6 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_restrict(const BatchItem* item
         A.u = (const T*)it.in;
         A.f = (const T*)it.f;
         A.bc = (T*)it.bc;
+        A.uc0 = (T*)it.out;
         A.ctrl = nullptr;
         A.m = it.m;
         A.n = it.n;
@@ -128,6 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_defect(const BatchItem* items,
         A.e = (const float*)it.ec;
         A.f = (const double*)it.f;
         A.rhs = (float*)it.bc;
+        A.ezero = (float*)it.e;
         A.partials = it.partials;
         A.ctrl = nullptr;
         A.m = it.m;
@@ -188,6 +190,9 @@ static hipError_t launch_batch_t(int kind, int fl, const BatchItem* items, const
                 case 0: k_batch_sweep<T, 0><<<g, b, 0, s>>>(items, tmap, total); break;
                 case SW_ZERO: k_batch_sweep<T, SW_ZERO><<<g, b, 0, s>>>(items, tmap, total); break;
                 case SW_PROLONG: k_batch_sweep<T, SW_PROLONG><<<g, b, 0, s>>>(items, tmap, total); break;
+                case SW_PROLONG | SW_PONLY:
+                    k_batch_sweep<T, SW_PROLONG | SW_PONLY><<<g, b, 0, s>>>(items, tmap, total);
+                    break;
                 case SW_NORM: k_batch_sweep<T, SW_NORM><<<g, b, 0, s>>>(items, tmap, total); break;
                 default: return hipErrorInvalidValue;
             }
@@ -214,7 +219,7 @@ hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items
         case BK_RESNORM: k_batch_resnorm<<<blocks, kBlock, 0, s>>>(items, tmap, total); break;
         case BK_DEFECT: k_batch_defect<<<blocks, kBlock, 0, s>>>(items, tmap, total); break;
         case BK_ADI_ROWS:
-        case BK_ADI_COLS: return launch_batch_adi(kind, step_flags, items, tmap, total, blocks, s);
+        case BK_ADI_COLS: return launch_batch_adi(kind, step_flags, dt, items, tmap, total, blocks, s);
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -171,6 +171,9 @@ enum : int {
     SW_DEF = 64,     // fused FP32 post-smoothing pass (with SW_PROLONG | SW_TWO | SW_F) whose result, the
                      // correction, goes straight into the next FP64 defect correction (psi_in -> psi_out,
                      // the residual's norms, its FP32 copy into rhs_out); the correction is not stored
+    SW_PONLY = 128,  // with SW_PROLONG: only u_in + P(ec), no colour updates (u_out may equal u_in:
+                     // every stored value depends on its own node only); the multigrid correction
+                     // step when the smoother is zebra line relaxation
 };
 
 template <typename T>
@@ -208,6 +211,7 @@ struct RestrictArgs {
     const T* u;
     const T* f;
     T* bc;
+    T* uc0;             // nullable: coarse iterate set to zero at every coarse interior node (zero start)
     const Ctrl* ctrl;
     int m, n, P;
     int mc, nc, Pc;
@@ -235,6 +239,7 @@ struct DefectArgs {
     const float* e;
     const double* f;
     float* rhs;
+    float* ezero;       // nullable: FP32 level-0 buffer set to zero at every interior node (next cycle's start)
     double* partials;
     const Ctrl* ctrl;
     int m, n, P;
@@ -332,10 +337,13 @@ hipError_t launch_copy(const double* src, double* dst, int m, int n, int P, cons
                        hipStream_t s);
 
 // ---- ADI (adi_kernels.hip) ----
-struct LineArgs {
-    double* u;               // in place
-    const double* f;         // nullable
-    double* scratch;         // forward-sweep values, same layout as u
+// T: element type of the field (the sequential solver is FP64 only; the
+// segmented one is also built for FP32, for line smoothing in the FP32 cycle)
+template <typename T>
+struct LineArgsT {
+    T* u;                    // in place
+    const T* f;              // nullable
+    double* scratch;         // forward-sweep values, same layout as u (sequential solver)
     const double* cprime;    // c'_k of the constant-coefficient factorisation, k = 0..K-1
     const double* piv;       // pivot_k (piv_0 = d)
     const Ctrl* ctrl;
@@ -344,11 +352,17 @@ struct LineArgs {
     double a_off;            // off-diagonal of the line matrix (-cx or -w cx, rows; -cy.. cols)
     int form;                // 0 relax after, 1 relax inside
     int parity;              // 1: odd lines, 0: even lines
-    const double* seg;       // segment table of this direction (adi_seg_table), or NULL
+    const T* seg;            // segment table of this direction (adi_seg_table), or NULL
 };
+using LineArgs = LineArgsT<double>;
 constexpr int kRowTile = 64;   // row lines per ADI row block (sequential solver)
 hipError_t launch_adi_rows(const LineArgs& a, hipStream_t s);
 hipError_t launch_adi_cols(const LineArgs& a, hipStream_t s);
+// One zebra line-smoothing half inside a V-cycle: all lines of a.parity along
+// rows (dir 0) or columns (dir 1), segmented solver only (every line must
+// fit it: hipErrorInvalidValue otherwise), in place on a.u.
+template <typename T>
+hipError_t launch_zebra_lines(const LineArgsT<T>& a, int dir, hipStream_t s);
 
 // Segmented line solver.  A line of K unknowns is cut into S blocks of
 // kSegL unknowns, each followed by one separator unknown (the last block
@@ -396,6 +410,7 @@ __host__ __device__ constexpr bool seg_fits(int dir, int K) {
 // Tabulate the segmented solve of the line matrix tridiag(-E, D, -E) of
 // order K (host, extended precision).
 void adi_seg_table(double D, double E, int K, double* tab);
+void adi_seg_table(double D, double E, int K, float* tab);   // the same, rounded once to FP32
 
 // Coarsest levels with at most this many unknowns use a dense inverse (all
 // lanes in parallel); larger ones (long thin grids) a separable solve: sine
@@ -419,7 +434,7 @@ struct BatchItem {
     double* scratch;         // ADI
     const double* cprime;
     const double* piv;
-    const double* seg;       // ADI segment table (NULL: sequential solver)
+    const void* seg;         // ADI segment table of the item's element type (NULL: sequential solver)
     int m, n, P, mc, nc, Pc;
     double cx, cy, d, inv_d, omega, a_off;
     int V, ty, nwin, nchunk, H;
@@ -429,7 +444,8 @@ struct BatchItem {
     const void* sub;         // BK_SUBTREE: device SubtreeArgs<T> of this grid
     // fused post-smoothing + defect pass (SW_DEF; in / out: the FP64 iterate,
     // f / bc: this and the next FP32 right-hand side, ec: coarse correction)
-    const void* e;           // the FP32 level-0 buffer the post-smoothing starts from
+    const void* e;           // post + defect: the FP32 level-0 buffer the post-smoothing starts from;
+                             // defect: the FP32 buffer it sets to zero (nullable)
     const double* f64;       // FP64 source (nullable)
     int rowpart;             // norm partials per (window, row block) (see SweepArgs)
 };
@@ -445,8 +461,9 @@ hipError_t launch_batch(int kind, int dt, int step_flags, const BatchItem* items
 // has a segment table and fits it), else the sequential one.
 constexpr int ADI_SEG = 2;
 constexpr int ADI_CODE_SHIFT = 2;   // segmented: size code (seg_code) in bits 2..3
-hipError_t launch_batch_adi(int kind, int flags, const BatchItem* items, const int* tmap, int total, int blocks,
-                            hipStream_t s);
+constexpr int ADI_MG = 16;          // zebra line smoothing of a multigrid level (operation flag)
+hipError_t launch_batch_adi(int kind, int flags, int dt, const BatchItem* items, const int* tmap, int total,
+                            int blocks, hipStream_t s);
 // merged fused passes (batch_fused.hip); step_flags without SW_F; every item has V columns per lane
 hipError_t launch_batch_fused(int dt, int step_flags, int V, const BatchItem* items, const int* tmap, int total,
                               int blocks, hipStream_t s);

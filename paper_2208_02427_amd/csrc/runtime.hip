@@ -447,6 +447,13 @@ struct lap_grid {
     double batch_t0 = 0.0;
     int step_idx = 0;                // next outer step of the running solve
     int e_idx = 0;                   // buffer of the last FP32 correction (mixed)
+    // zebra line smoothing: segment tables of every smoothed level, rows then
+    // columns (2 * kSegTab values per level), FP64 and FP32
+    double* ztab64 = nullptr;
+    float* ztab32 = nullptr;
+    std::vector<double> zhost64;     // host copies (the uploads read them asynchronously)
+    std::vector<float> zhost32;
+    bool zebra_ok = false;
     bool pdef = false;               // the running mixed solve uses the post-smoothing + defect pass
     lap_opts batch_opts{};
     // graph cache
@@ -478,6 +485,14 @@ size_t max_tiles(int m, int n) {
     return (size_t)t;
 }
 
+// Whether every smoothed level's row and column lines fit the segmented line
+// solver (zebra line smoothing needs it).
+bool zebra_fits(const std::vector<LevelGeo>& lv) {
+    for (size_t l = 0; l + 1 < lv.size(); ++l)
+        if (!seg_fits(0, lv[l].m - 2) || !seg_fits(1, lv[l].n - 2)) return false;
+    return true;
+}
+
 // Mirrors the allocations of lap_grid_create_ex.
 Footprint footprint(int m, int n, bool has_f, int flags) {
     Footprint fp;
@@ -498,6 +513,10 @@ Footprint footprint(int m, int n, bool has_f, int flags) {
     if (flags & (LAP_ALLOC_FP64 | LAP_ALLOC_MIXED)) {
         fp.add(coarse_bytes(lv.back()));
         if (lv.back().interior() > (size_t)kDenseCoarseMax) fp.add(lv.back().interior() * 8);
+        if (zebra_fits(lv)) {
+            if (flags & LAP_ALLOC_FP64) fp.add(lv.size() * 2 * kSegTab * 8);
+            if (flags & LAP_ALLOC_MIXED) fp.add(lv.size() * 2 * kSegTab * 4);
+        }
     }
     if (flags & LAP_ALLOC_ADI) {
         fp.add(f0 * 8);
@@ -692,7 +711,7 @@ hipError_t enq_finalize(lap_grid* g, int ntiles) {
 }
 
 template <typename T>
-hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc) {
+hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc, T* uc0 = nullptr) {
     const LevelGeo& L = g->geo[l];
     const LevelGeo& C = g->geo[l + 1];
     const Coef c = coef(L.dx, L.dy);
@@ -700,6 +719,7 @@ hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc) {
     a.u = u;
     a.f = f;
     a.bc = bc;
+    a.uc0 = uc0;
     a.ctrl = g->ctrl;
     a.m = L.m;
     a.n = L.n;
@@ -711,7 +731,7 @@ hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc) {
     a.cy = (T)c.cy;
     a.d = (T)c.d;
     a.tl = g->ctx->tiling(L.m, L.n, KC_RESTRICT, dt_of<T>());
-    const double per = (u ? 1.0 : 0.0) + (f ? 1.0 : 0.0) + 0.25;
+    const double per = (u ? 1.0 : 0.0) + (f ? 1.0 : 0.0) + (uc0 ? 0.5 : 0.25);
     return g->ctx->timed(KC_RESTRICT, l == 0, per * sizeof(T) * nint(L),
                          [&]() { return launch_restrict<T>(a, g->ctx->stream); });
 }
@@ -782,6 +802,7 @@ struct Op {
     void* bc;        // restrict: coarse right-hand side; post + defect: the new FP32 right-hand side
     double omega;
     int parity;      // ADI line parity; post + defect: buffer of the level-0 pre-smoothing result
+    void* zbuf = nullptr;   // defect: FP32 buffer to set to zero (the next zebra cycle's start)
 };
 
 constexpr long KEY_HEAD = 10;
@@ -886,9 +907,61 @@ struct DeferredPost {
 // that holds the level's result.  `part` (level 0 with a norm only):
 // PART_HEAD records the stopping test of the incoming iterate, PART_TAIL the rest.
 // With dp, level 0 stops before its post-smoothing and describes it in *dp.
+int adi_kernel_flags(int dir, int K);
+
+// Zebra line smoothing of level l: `steps` alternating steps (odd rows, even
+// rows, odd columns, even columns), in place on u, keys k0, k0+1, ...
+template <typename T>
+void push_zebra(lap_grid* g, int l, T* u, const T* b, double omega, int steps, long k0, std::vector<Op>& ops) {
+    const LevelGeo& G = g->geo[l];
+    for (int k = 0; k < steps; ++k)
+        for (int q = 0; q < 4; ++q) {
+            const int dir = q < 2 ? 0 : 1;
+            push_op<T>(ops, k0 + 4L * k + q, dir == 0 ? OP_ADI_ROWS : OP_ADI_COLS, l,
+                       ADI_MG | adi_kernel_flags(dir, dir == 0 ? G.m - 2 : G.n - 2), nullptr, u, b, nullptr,
+                       nullptr, omega, (q % 2) ? 0 : 1);
+        }
+}
+
+// V-cycle with zebra line smoothing (LAP_SMOOTH_ZEBRA).  Every level works
+// in place on its first buffer: the smoothing steps, then r = b - L u and
+// its full weighting onto the coarse right-hand side (the same launch sets
+// the coarse iterate to zero), the coarse cycle, u += P(e_c), the smoothing
+// steps.  A zero-start level 0 (error equation) was zeroed by the defect
+// correction that formed its right-hand side.  The stopping test's norms of
+// the incoming iterate come from the residual-norm kernel.  Returns 0 (the
+// buffer holding the result).
+template <typename T>
+int plan_vcycle_zebra(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm, int part,
+                      std::vector<Op>& ops) {
+    const int L = (int)g->geo.size();
+    const bool zero_start = (l > 0) || H.zero_start0;
+    const bool split = norm && !zero_start;
+    const bool head = !split || part != PART_TAIL;
+    const bool tail = !split || part != PART_HEAD;
+    T* U = H.u0[l];
+    const T* b = H.b[l];
+    if (split && head) {
+        push_op<T>(ops, KEY_HEAD, OP_RESNORM, l, 0, U, nullptr, b, nullptr, nullptr, 0.0);
+        push_op<T>(ops, KEY_HEAD + 1, OP_FINALIZE, l, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0);
+    }
+    if (!tail) return 0;
+    if (l == L - 1) {
+        push_op<T>(ops, KEY_COARSE, OP_COARSE, l, 0, zero_start ? nullptr : U, U, b, nullptr, nullptr, 0.0);
+        return 0;
+    }
+    push_zebra<T>(g, l, U, b, o.omega, o.nu1, key_pre(l, 0), ops);
+    push_op<T>(ops, key_restrict(l), OP_RESTRICT, l, 0, U, H.u0[l + 1], b, nullptr, H.b[l + 1], 0.0);
+    plan_vcycle_zebra<T>(g, H, l + 1, o, false, PART_ALL, ops);
+    push_op<T>(ops, key_post(l, 0), OP_SWEEP, l, SW_PROLONG | SW_PONLY, U, U, nullptr, H.u0[l + 1], nullptr, 0.0);
+    push_zebra<T>(g, l, U, b, o.omega, o.nu2, key_post(l, 1), ops);
+    return 0;
+}
+
 template <typename T>
 int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm, int part, std::vector<Op>& ops,
                 DeferredPost* dp = nullptr) {
+    if (o.smoother == LAP_SMOOTH_ZEBRA) return plan_vcycle_zebra<T>(g, H, l, o, norm, part, ops);
     const int L = (int)g->geo.size();
     const bool zero_start = (l > 0) || H.zero_start0;
     const bool split = norm && !zero_start;
@@ -1010,7 +1083,8 @@ HierView<float> view32(lap_grid* g) {
     return H;
 }
 
-hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const float* e, float* rhs) {
+hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const float* e, float* rhs,
+                      float* ezero = nullptr) {
     const LevelGeo& L = g->geo[0];
     const Coef c = coef(L.dx, L.dy);
     DefectArgs a{};
@@ -1019,6 +1093,7 @@ hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const 
     a.e = e;
     a.f = g->f64;
     a.rhs = rhs;
+    a.ezero = ezero;
     a.partials = g->partials;
     a.ctrl = g->ctrl;
     a.m = L.m;
@@ -1029,7 +1104,8 @@ hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const 
     a.d = c.d;
     a.tl = norm_tiling(L.m, L.n, NORM_DEFECT);
     // psi and e (and f) read, psi written unless in place, the FP32 right-hand side written
-    const double per = 8.0 + (e ? 4.0 : 0.0) + (g->f64 ? 8.0 : 0.0) + (psi_out != psi_in || e ? 8.0 : 0.0) + 4.0;
+    const double per = 8.0 + (e ? 4.0 : 0.0) + (g->f64 ? 8.0 : 0.0) + (psi_out != psi_in || e ? 8.0 : 0.0) + 4.0 +
+                       (ezero ? 4.0 : 0.0);
     return g->ctx->timed(KC_DEFECT, true, per * nint(L), [&]() { return launch_defect(a, g->ctx->stream); });
 }
 
@@ -1086,6 +1162,7 @@ hipError_t enq_postdef(lap_grid* g, const Op& op, double omega) {
 // smoothed start (nu1 >= 2).
 bool postdef_ok(lap_grid* g, const lap_opts& o) {
     if (o.method != LAP_MG || o.precision != LAP_MIXED || !g->ctx->fuse || !g->rhs2) return false;
+    if (o.smoother != LAP_SMOOTH_RB) return false;
     if (o.nu2 != 2 || o.nu1 < 2 || g->geo.size() < 2) return false;
     return subtree_root<float>(g, 0) != 0;
 }
@@ -1127,6 +1204,24 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
         if (part == PART_HEAD) return;
         H.b[0] = R[par];
         plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops, &dp);
+        return;
+    }
+    if (o.smoother == LAP_SMOOTH_ZEBRA) {
+        // step s's FP32 cycle works in place on level-0 buffer s % 2, which
+        // the step's defect correction sets to zero while it adds the previous
+        // correction (buffer (s - 1) % 2)
+        float* z = g->l32[0].u[s % 2];
+        if (part != PART_TAIL) {
+            const float* e = first ? nullptr : g->l32[0].u[(s + 1) % 2];
+            push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, pin, pout, g->f64, e, g->l32[0].b, 0.0);
+            ops.back().zbuf = z;
+            push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, 0.0);
+        }
+        if (part == PART_HEAD) return;
+        HierView<float> H = view32(g);
+        H.u0[0] = z;
+        plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops);
         return;
     }
     if (part != PART_TAIL) {
@@ -1203,6 +1298,41 @@ hipError_t enq_adi_half(lap_grid* g, double omega, int form, int dir, int parity
     return g->ctx->timed(KC_ADI_COLS, true, per, [&]() { return launch_adi_cols(a, g->ctx->stream); });
 }
 
+// Arguments of a zebra line-smoothing half on level l (relaxation after the
+// line solve with omega; the level's own segment table).
+template <typename T>
+LineArgsT<T> zebra_args(lap_grid* g, int l, T* u, const T* b, double omega, int dir, int parity) {
+    const LevelGeo& L = g->geo[l];
+    const Coef c = coef(L.dx, L.dy);
+    LineArgsT<T> a{};
+    a.u = u;
+    a.f = b;
+    a.ctrl = g->ctrl;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    a.cx = c.cx;
+    a.cy = c.cy;
+    a.d = c.d;
+    a.omega = omega;
+    a.form = LAP_ADI_RELAX_AFTER;
+    a.parity = parity;
+    const size_t off = ((size_t)2 * l + dir) * kSegTab;
+    if constexpr (sizeof(T) == 8)
+        a.seg = g->ztab64 + off;
+    else
+        a.seg = g->ztab32 + off;
+    return a;
+}
+
+template <typename T>
+hipError_t enq_zebra(lap_grid* g, const Op& op, int dir) {
+    const LineArgsT<T> a = zebra_args<T>(g, op.level, (T*)op.out, (const T*)op.f, op.omega, dir, op.parity);
+    const double per = adi_bytes_per_node(op.f != nullptr) * sizeof(T) / 8.0 * nint(g->geo[op.level]);
+    return g->ctx->timed(dir == 0 ? KC_ADI_ROWS : KC_ADI_COLS, op.level == 0, per,
+                         [&]() { return launch_zebra_lines<T>(a, dir, g->ctx->stream); });
+}
+
 // Launch one recorded operation of grid g.
 hipError_t exec_op(lap_grid* g, const Op& op) {
     const int l = op.level;
@@ -1222,8 +1352,9 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
                                     (const float*)op.ec, op.omega, op.flags);
         case OP_RESTRICT:
             if (op.dt == 0)
-                return enq_restrict<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.bc);
-            return enq_restrict<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.bc);
+                return enq_restrict<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.bc,
+                                            (double*)op.out);
+            return enq_restrict<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.bc, (float*)op.out);
         case OP_COARSE:
             if (op.dt == 0)
                 return enq_coarse<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.out);
@@ -1233,13 +1364,16 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
         case OP_RESNORM:
             return enq_residual_norm<double>(g, l, (const double*)op.in, (const double*)op.f);
         case OP_DEFECT:
-            return enq_defect(g, (const double*)op.in, (double*)op.out, (const float*)op.ec, (float*)op.bc);
+            return enq_defect(g, (const double*)op.in, (double*)op.out, (const float*)op.ec, (float*)op.bc,
+                              (float*)op.zbuf);
         case OP_POSTDEF:
             return enq_postdef(g, op, op.omega);
         case OP_ADI_ROWS:
-            return enq_adi_half(g, op.omega, op.flags, 0, op.parity);
-        case OP_ADI_COLS:
-            return enq_adi_half(g, op.omega, op.flags, 1, op.parity);
+        case OP_ADI_COLS: {
+            const int dir = op.kind == OP_ADI_ROWS ? 0 : 1;
+            if (op.flags & ADI_MG) return op.dt == 0 ? enq_zebra<double>(g, op, dir) : enq_zebra<float>(g, op, dir);
+            return enq_adi_half(g, op.omega, op.flags, dir, op.parity);
+        }
         case OP_SUBTREE:
             if (op.dt == 0)
                 return enq_subtree<double>(g, l, (double*)op.out, (const double*)op.f, op.omega, op.flags);
@@ -1349,7 +1483,16 @@ lap_status validate_opts(lap_grid* g, const lap_opts& o) {
         return fail(LAP_EINVAL, "unknown method");
     if (o.precision != LAP_FP64 && o.precision != LAP_MIXED) return fail(LAP_EINVAL, "unknown precision");
     if (o.precision == LAP_MIXED && o.method != LAP_MG) return fail(LAP_EINVAL, "LAP_MIXED needs LAP_MG");
-    if (o.method == LAP_MG) {
+    if (o.smoother != LAP_SMOOTH_RB && o.smoother != LAP_SMOOTH_ZEBRA) return fail(LAP_EINVAL, "unknown smoother");
+    if (o.method == LAP_MG && o.smoother == LAP_SMOOTH_ZEBRA) {
+        if (!g->zebra_ok)
+            return fail(LAP_EINVAL, "zebra smoothing needs every level's lines in the segmented line solver "
+                                    "(sides of at most 4097)");
+        if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.nu1 > 8 || o.nu2 > 8)
+            return fail(LAP_EINVAL, "zebra smoothing needs 0 <= nu1, nu2 <= 8 and nu1 + nu2 >= 1");
+        if (o.precision == LAP_FP64 && !(g->flags & LAP_ALLOC_FP64)) return fail(LAP_EINVAL, "grid has no FP64 hierarchy");
+        if (o.precision == LAP_MIXED && !(g->flags & LAP_ALLOC_MIXED)) return fail(LAP_EINVAL, "grid has no mixed hierarchy");
+    } else if (o.method == LAP_MG) {
         if (o.nu1 < 0 || o.nu2 < 1) return fail(LAP_EINVAL, "multigrid needs nu1 >= 0 and nu2 >= 1");
         if ((o.nu1 + o.nu2) % 2) return fail(LAP_EINVAL, "multigrid needs nu1 + nu2 even");
         if (o.precision == LAP_FP64 && !(g->flags & LAP_ALLOC_FP64)) return fail(LAP_EINVAL, "grid has no FP64 hierarchy");
@@ -1446,9 +1589,10 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
     if (use_graph(g, o)) {
         char key[128];
         if (o.precision == LAP_FP64)
-            snprintf(key, sizeof key, "mg64:%d:%d:%.17g", o.nu1, o.nu2, o.omega);
+            snprintf(key, sizeof key, "mg64:%d:%d:%d:%.17g", o.smoother, o.nu1, o.nu2, o.omega);
         else
-            snprintf(key, sizeof key, "mixed%s:%d:%d:%.17g", g->pdef ? "+pd" : "", o.nu1, o.nu2, o.omega);
+            snprintf(key, sizeof key, "mixed%s:%d:%d:%d:%.17g", g->pdef ? "+pd" : "", o.smoother, o.nu1, o.nu2,
+                     o.omega);
         const bool have = g->graph != nullptr && g->graph_key == key;
         auto& seen = g->graph_seen;
         const bool again = std::find(seen.begin(), seen.end(), std::string(key)) != seen.end();
@@ -1628,6 +1772,7 @@ void lap_opts_default(lap_opts* o) {
     o->check_every = 1;
     o->adi_form = LAP_ADI_RELAX_AFTER;
     o->use_graph = 1;
+    o->smoother = LAP_SMOOTH_RB;
 }
 
 lap_status lap_ctx_create(void* dev_arena, size_t arena_bytes, void* hip_stream, lap_ctx** out) {
@@ -1821,6 +1966,22 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
         factor = &c->inv_cache[key];
         g->minv = (double*)A(factor->size() * 8);
     }
+    std::vector<double>& z64 = g->zhost64;
+    std::vector<float>& z32 = g->zhost32;
+    if (mg && zebra_fits(lv)) {
+        g->zebra_ok = true;
+        z64.assign((size_t)L * 2 * kSegTab, 0.0);
+        z32.assign((size_t)L * 2 * kSegTab, 0.0f);
+        for (int l = 0; l + 1 < L; ++l) {
+            const Coef k = coef(lv[l].dx, lv[l].dy);
+            adi_seg_table(k.d, k.cx, lv[l].m - 2, z64.data() + (size_t)2 * l * kSegTab);
+            adi_seg_table(k.d, k.cy, lv[l].n - 2, z64.data() + ((size_t)2 * l + 1) * kSegTab);
+            adi_seg_table(k.d, k.cx, lv[l].m - 2, z32.data() + (size_t)2 * l * kSegTab);
+            adi_seg_table(k.d, k.cy, lv[l].n - 2, z32.data() + ((size_t)2 * l + 1) * kSegTab);
+        }
+        if (flags & LAP_ALLOC_FP64) g->ztab64 = (double*)A(z64.size() * 8);
+        if (flags & LAP_ALLOC_MIXED) g->ztab32 = (float*)A(z32.size() * 4);
+    }
     if (flags & LAP_ALLOC_ADI) {
         g->adi_scratch = (double*)A(f0 * 8);
         g->adi_maxk = std::max(m, n);
@@ -1849,6 +2010,8 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
     if (e == hipSuccess && source) e = launch_write_field(source, g->f64, nullptr, m, n, g->P, s);
     if (e == hipSuccess && mg)
         e = hipMemcpyAsync(g->minv, factor->data(), factor->size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && g->ztab64) e = hipMemcpyAsync(g->ztab64, z64.data(), z64.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && g->ztab32) e = hipMemcpyAsync(g->ztab32, z32.data(), z32.size() * 4, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         lap_grid_destroy(g);
         return fail(LAP_EHIP, std::string("grid upload: ") + hipGetErrorString(e));
@@ -2334,7 +2497,10 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
             break;
         case OP_RESTRICT: t = c->tiling(L.m, L.n, KC_RESTRICT, op.dt); break;
         case OP_RESNORM: t = norm_tiling(g->geo[0].m, g->geo[0].n); break;
-        case OP_DEFECT: t = norm_tiling(g->geo[0].m, g->geo[0].n, NORM_DEFECT); break;
+        case OP_DEFECT:
+            t = norm_tiling(g->geo[0].m, g->geo[0].n, NORM_DEFECT);
+            it.e = op.zbuf;   // the FP32 buffer the defect correction sets to zero (zebra cycles)
+            break;
         case OP_POSTDEF:
             t = postdef_tiling(L.m, L.n, true);
             it.rowpart = postdef_rowpart(L.n) ? 1 : 0;
@@ -2345,15 +2511,27 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
         case OP_FINALIZE: t.ntiles = norm_partials(g->geo[0].m, g->geo[0].n, op.flags); break;
         case OP_ADI_ROWS:
         case OP_ADI_COLS: {
-            const LineArgs la = adi_args(g, op.omega, op.flags, op.kind == OP_ADI_ROWS ? 0 : 1, op.parity);
-            it.out = la.u;
-            it.f = la.f;
-            it.scratch = la.scratch;
-            it.cprime = la.cprime;
-            it.piv = la.piv;
-            it.seg = la.seg;
-            it.a_off = la.a_off;
-            it.flags = op.flags & 1;
+            const int dir = op.kind == OP_ADI_ROWS ? 0 : 1;
+            if (op.flags & ADI_MG) {
+                // zebra smoothing of a multigrid level: the level's buffers and table
+                it.out = op.out;
+                it.f = op.f;
+                it.seg = op.dt == 0 ? (const void*)zebra_args<double>(g, op.level, (double*)op.out,
+                                                                      (const double*)op.f, op.omega, dir, op.parity).seg
+                                    : (const void*)zebra_args<float>(g, op.level, (float*)op.out, (const float*)op.f,
+                                                                     op.omega, dir, op.parity).seg;
+                it.flags = LAP_ADI_RELAX_AFTER;
+            } else {
+                const LineArgs la = adi_args(g, op.omega, op.flags, dir, op.parity);
+                it.out = la.u;
+                it.f = la.f;
+                it.scratch = la.scratch;
+                it.cprime = la.cprime;
+                it.piv = la.piv;
+                it.seg = la.seg;
+                it.a_off = la.a_off;
+                it.flags = op.flags & 1;
+            }
             it.parity = op.parity;
             const int first = op.parity ? 1 : 2;
             const int span = op.kind == OP_ADI_ROWS ? L.n - 2 : L.m - 2;
@@ -2393,13 +2571,14 @@ double item_bytes(const Op& op, const BatchItem& it) {
     const double sz = op.dt == 0 ? 8.0 : 4.0;
     switch (op.kind) {
         case OP_SWEEP: return sweep_bytes_per_node(op.flags, (int)sz) * n;
-        case OP_RESTRICT: return ((op.in ? 1.0 : 0.0) + (op.f ? 1.0 : 0.0) + 0.25) * sz * n;
+        case OP_RESTRICT: return ((op.in ? 1.0 : 0.0) + (op.f ? 1.0 : 0.0) + (op.out ? 0.5 : 0.25)) * sz * n;
         case OP_RESNORM: return (op.f ? 16.0 : 8.0) * n;
         case OP_DEFECT:
-            return (8.0 + (op.ec ? 4.0 : 0.0) + (op.f ? 8.0 : 0.0) + (op.out != op.in || op.ec ? 8.0 : 0.0) + 4.0) * n;
+            return (8.0 + (op.ec ? 4.0 : 0.0) + (op.f ? 8.0 : 0.0) + (op.out != op.in || op.ec ? 8.0 : 0.0) + 4.0 +
+                    (op.zbuf ? 4.0 : 0.0)) * n;
         case OP_POSTDEF: return postdef_bytes_per_node(it.f64 != nullptr) * n;
         case OP_ADI_ROWS:
-        case OP_ADI_COLS: return adi_bytes_per_node(op.f != nullptr) * n;
+        case OP_ADI_COLS: return adi_bytes_per_node(op.f != nullptr) * sz / 8.0 * n;
         case OP_SUBTREE: return 2.0 * sz * (double)it.m * (double)it.n;
         default: return 0.0;
     }
@@ -2430,8 +2609,8 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
     std::string key;
     {
         char buf[96];
-        snprintf(buf, sizeof buf, "%d:%d:%d:%d:%d:%d:%.17g|", o.method, o.precision, o.nu1, o.nu2, o.check_every,
-                 o.adi_form, o.omega);
+        snprintf(buf, sizeof buf, "%d:%d:%d:%d:%d:%d:%d:%.17g|", o.method, o.precision, o.smoother, o.nu1, o.nu2,
+                 o.check_every, o.adi_form, o.omega);
         key = buf;
         for (size_t k = 0; k < gs.size(); ++k) {
             const int par = (o.method == LAP_MG && o.precision == LAP_MIXED)

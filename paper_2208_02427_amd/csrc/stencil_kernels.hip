@@ -43,6 +43,7 @@ static hipError_t launch_sweep_v(const SweepArgs<T>& a, int flags, hipStream_t s
         case SW_ZERO: k_sweep<T, V, SW_ZERO><<<grid, block, 0, s>>>(a); break;
         case SW_PROLONG: k_sweep<T, V, SW_PROLONG><<<grid, block, 0, s>>>(a); break;
         case SW_PROLONG | SW_F: k_sweep<T, V, SW_PROLONG | SW_F><<<grid, block, 0, s>>>(a); break;
+        case SW_PROLONG | SW_PONLY: k_sweep<T, V, SW_PROLONG | SW_PONLY><<<grid, block, 0, s>>>(a); break;
         case SW_NORM: k_sweep<T, V, SW_NORM><<<grid, block, 0, s>>>(a); break;
         case SW_NORM | SW_F: k_sweep<T, V, SW_NORM | SW_F><<<grid, block, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;

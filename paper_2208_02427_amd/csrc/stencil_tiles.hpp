@@ -315,8 +315,8 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
         copy<T, V>(R.bo, R.c);
     }
 
-    const bool rj = (j >= 1) && (j <= A.n - 2);
-    const bool rjm = (j - 1 >= 1) && (j - 1 <= A.n - 2);
+    const bool rj = !(FL & SW_PONLY) && (j >= 1) && (j <= A.n - 2);
+    const bool rjm = !(FL & SW_PONLY) && (j - 1 >= 1) && (j - 1 <= A.n - 2);
 
     // colour 0 ((i+j) even) on row j from old colour-1 neighbours
     if (rj) {
@@ -456,6 +456,7 @@ __device__ __forceinline__ void restrict_tile(const RestrictArgs<T>& A, int tile
                     const T NE = e < V - 1 ? r0[e + 1] : e0;
                     const T v = (fma(T(4), C, T(2) * ((W + E) + (S + N))) + ((SW + SE) + (NW + NE))) * T(0.0625);
                     brow[I] = v;
+                    if (A.uc0 != nullptr) A.uc0[(size_t)J * A.Pc + I] = T(0);
                 }
             }
         }
@@ -553,6 +554,11 @@ __device__ __forceinline__ void defect_tile(const DefectArgs& A, int tile, int l
 #pragma unroll
         for (int e = 0; e < V; ++e) r32[e] = (float)r[e];
         store_row<float, V>(A.rhs, r32, j, A.P, c);
+        if (A.ezero != nullptr) {
+            float z[V];
+            zero<float, V>(z);
+            store_row<float, V>(A.ezero, z, j, A.P, c);
+        }
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             if (!c.cout[e]) continue;
