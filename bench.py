@@ -364,8 +364,24 @@ def run_batch_leg(args, ctx, torch, lap, dev):
                        "cycles_min": min(its), "cycles_max": max(its),
                        "all_converged": all(i["status"] == 0 for i in infos),
                        "solves_per_s": count / t}
+    # the same batch with zebra line smoothing (V(1,1): robust for beta != 1)
+    zkw = dict(method="mg", precision="mixed", smoother="zebra", nu1=1, nu2=1, tol=1e-10, max_iter=200)
+    reset()
+    ctx.solve_batch(grids, **zkw)
+    reset()
+    sync()
+    t0 = time.perf_counter()
+    zinf = ctx.solve_batch(grids, **zkw)
+    sync()
+    tz = time.perf_counter() - t0
+    zits = [i["iterations"] for i in zinf]
+    out["mg_mixed_zebra"] = {"seconds": tz, "GLUP/s": sum(k * l for k, l in zip(zits, lpc)) / tz / 1e9,
+                             "cycles_min": min(zits), "cycles_max": max(zits),
+                             "all_converged": all(i["status"] == 0 for i in zinf), "solves_per_s": count / tz}
     # error against FP64: sampled grids solved alone with FP64 multigrid
     sample = list(range(0, count, max(1, count // 8)))
+    reset()
+    ctx.solve_batch(grids, method="mg", precision="mixed", tol=1e-10, max_iter=200)
     mixed_u = {k: grids[k].read() for k in sample}
     errs = []
     for k in sample:
@@ -567,6 +583,8 @@ def compact(line_full, d):
                             "GLUP/s": sig(b["mg_mixed"]["GLUP/s"]),
                             "vs_one_at_a_time": sig(b["mg_mixed_one_at_a_time"]["speedup_of_batch"], 3),
                             "err": sig(b["mg_mixed"]["max_abs_vs_fp64_sampled"], 2),
+                            "zebra_ms": sig(b["mg_mixed_zebra"]["seconds"] * 1e3),
+                            "zebra_cycles": [b["mg_mixed_zebra"]["cycles_min"], b["mg_mixed_zebra"]["cycles_max"]],
                             "adi20_ms": sig(b["adi"]["seconds"] * 1e3), "adi_GB/s": sig(b["adi"]["alg_GB/s"])}
     if "serving" in d:
         s = d["serving"]
