@@ -286,10 +286,20 @@ def run_chamber_leg(ctx, torch, lap, dev, reps=5):
         w = round(1.0 + 0.05 * k, 2)
         sor[f"{w:.2f}"] = run("sor", omega=w)
     best = min(sor, key=lambda w: (sor[w][0], float(w)))
+    # the paper's own orderings (one workgroup, the grid in LDS, whole solve in one launch)
+    lex = {}
+    for k in range(20):
+        w = round(1.0 + 0.05 * k, 2)
+        lex[f"{w:.2f}"] = run("sor_lex", omega=w)
+    lbest = min(lex, key=lambda w: (lex[w][0], float(w)))
     out = {"levels": g.levels(), "sor_iters_us": sor, "sor_best_omega": float(best),
            "adi_after_w1": run("adi", omega=1.0, adi_form="after"),
            "adi_inside_w1.3": run("adi", omega=1.3, adi_form="inside"),
-           "mg_v22": run("mg")}
+           "mg_v22": run("mg"),
+           "paper_order": {"jacobi": run("jacobi"), "sor_lex": lex, "sor_lex_best_omega": float(lbest),
+                           "slora_w1": run("slor_lex", omega=1.0, adi_form="after"),
+                           "slorb_w1.25": run("slor_lex", omega=1.25, adi_form="inside"),
+                           "adi_lex_w1.3": run("adi_lex", omega=1.3, adi_form="inside")}}
     g.destroy()
     return out
 
@@ -576,6 +586,13 @@ def compact(line_full, d):
                            "sor" + wb: [c["sor_iters_us"][wb][0], sig(c["sor_iters_us"][wb][1], 3)],
                            "adi1": [c["adi_after_w1"][0], sig(c["adi_after_w1"][1], 3)],
                            "mg": [c["mg_v22"][0], sig(c["mg_v22"][1], 3)]}
+        po = c["paper_order"]
+        lb = f"{po['sor_lex_best_omega']:.2f}"
+        legs["chamber_lex"] = {"jacobi": [po["jacobi"][0], sig(po["jacobi"][1], 3)],
+                               "gs": [po["sor_lex"]["1.00"][0], sig(po["sor_lex"]["1.00"][1], 3)],
+                               "sor" + lb: [po["sor_lex"][lb][0], sig(po["sor_lex"][lb][1], 3)],
+                               "slorb1.25": [po["slorb_w1.25"][0], sig(po["slorb_w1.25"][1], 3)],
+                               "adi1.3": [po["adi_lex_w1.3"][0], sig(po["adi_lex_w1.3"][1], 3)]}
     if "ragged_batch" in d:
         b = d["ragged_batch"]
         legs["batch512"] = {"mg_ms": sig(b["mg_mixed"]["seconds"] * 1e3),

@@ -58,7 +58,17 @@ typedef enum lap_status {
 enum {
     LAP_SOR_RB = 1,  /* red-black SOR sweeps: colour (i+j) even, then odd (Eq. (7) reordered) */
     LAP_ADI = 2,     /* line ADI: all row systems, then all column systems, zebra order       */
-    LAP_MG = 3       /* multigrid V(nu1,nu2) cycles, red-black smoother, exact coarsest solve */
+    LAP_MG = 3,      /* multigrid V(nu1,nu2) cycles, red-black smoother, exact coarsest solve */
+    /* The paper's sequential orderings, exactly (same update order and
+     * expressions as the methods' definitions), for grids that fit one
+     * workgroup's LDS (2 m n + 3 max(m, n) doubles: up to about 100 x 100 on
+     * gfx950); the whole solve runs in one launch of one workgroup. */
+    LAP_JACOBI = 4,  /* Jacobi, Eq. (5)                                                       */
+    LAP_SOR_LEX = 5, /* lexicographic SOR, Eq. (7) (Gauss-Seidel, Eq. (6), at omega = 1)      */
+    LAP_SLOR_LEX = 6,/* line SOR by rows, ascending: adi_form AFTER = SLORA (Eqs. (8)-(9)),
+                      * INSIDE = SLORB (Eq. (10))                                             */
+    LAP_ADI_LEX = 7  /* ADI: every row line ascending, then every column line ascending,
+                      * relaxation placement by adi_form (ADI section)                        */
 };
 
 /* Precision (lap_solve, lap_grid_footprint). */
@@ -70,7 +80,9 @@ enum {
 /* Stopping rules (lap_opts.stop). */
 enum {
     LAP_STOP_REL_L2 = 0,   /* ||r_k||_2 / ||r_0||_2 < tol, r_0 at the start of the call */
-    LAP_STOP_RES_INF = 1   /* max |r_k| < tol (physical units of L_h)                   */
+    LAP_STOP_RES_INF = 1,  /* max |r_k| < tol (physical units of L_h)                   */
+    LAP_STOP_DELTA = 2     /* max |psi^{k+1} - psi^k| < tol, Eq. (16) (LAP_JACOBI ..
+                            * LAP_ADI_LEX only)                                         */
 };
 
 /* ADI relaxation placement (lap_opts.adi_form). */
@@ -107,6 +119,8 @@ typedef struct lap_info {
     double res_linf;      /* max |r| of the returned psi                                      */
     double res0_l2;       /* ||r_0||_2 at the start of the call                               */
     double seconds;       /* wall time of the call, host clock                                */
+    double monitor;       /* LAP_JACOBI .. LAP_ADI_LEX: the stopping rule's quantity after the
+                           * last iteration (max update, max |r| or relative l2); else 0      */
 } lap_info;
 
 typedef struct lap_opts {
@@ -160,7 +174,8 @@ lap_status lap_ctx_usage(lap_ctx* ctx, size_t* used, size_t* largest_free);
  * 10 fused pre-smoothing pass (one or two sweeps + residual + full
  * weighting), 11 fused two-sweep pass with the prolongation (post-smoothing),
  * 12 fused two-sweep pass without a transfer (red-black SOR, further
- * smoothing passes).  Class 3 also holds the mixed loop's fused FP32
+ * smoothing passes), 13 one whole solve of a paper-order method
+ * (LAP_JACOBI .. LAP_ADI_LEX; no algorithmic bytes).  Class 3 also holds the mixed loop's fused FP32
  * post-smoothing + FP64 defect pass.  `fine_only` selects the finest-level
  * bucket.
  * lap_ctx_kernel_stats synchronises the stream. */

@@ -15,7 +15,8 @@ import json
 import os
 
 from . import _native as N
-from ._native import (LAP_SOR_RB, LAP_ADI, LAP_MG, LAP_FP64, LAP_MIXED, LAP_STOP_REL_L2,  # noqa: F401
+from ._native import (LAP_SOR_RB, LAP_ADI, LAP_MG, LAP_JACOBI, LAP_SOR_LEX, LAP_SLOR_LEX,  # noqa: F401
+                      LAP_ADI_LEX, LAP_STOP_DELTA, LAP_FP64, LAP_MIXED, LAP_STOP_REL_L2,
                       LAP_STOP_RES_INF, LAP_ADI_RELAX_AFTER, LAP_ADI_RELAX_INSIDE, LAP_SMOOTH_RB,
                       LAP_SMOOTH_ZEBRA, LAP_ALLOC_FP64,
                       LAP_ALLOC_MIXED, LAP_ALLOC_ADI, LAP_ALLOC_ALL, LapInfo, LapOpts)
@@ -23,7 +24,10 @@ from ._native import (LAP_SOR_RB, LAP_ADI, LAP_MG, LAP_FP64, LAP_MIXED, LAP_STOP
 # tilings measured by the autotuner on MI355X (applied to every new Context)
 DEFAULT_TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 
-METHODS = {"sor": LAP_SOR_RB, "rb": LAP_SOR_RB, "adi": LAP_ADI, "mg": LAP_MG}
+METHODS = {"sor": LAP_SOR_RB, "rb": LAP_SOR_RB, "adi": LAP_ADI, "mg": LAP_MG,
+           # the paper's sequential orderings (one workgroup, grid in LDS)
+           "jacobi": LAP_JACOBI, "sor_lex": LAP_SOR_LEX, "gs_lex": LAP_SOR_LEX, "slor_lex": LAP_SLOR_LEX,
+           "adi_lex": LAP_ADI_LEX}
 PRECISIONS = {"fp64": LAP_FP64, "mixed": LAP_MIXED}
 
 
@@ -66,7 +70,8 @@ def opts(method="mg", precision="fp64", omega=1.0, tol=1e-10, max_iter=100, stop
     o.omega = float(omega)
     o.tol = float(tol)
     o.max_iter = int(max_iter)
-    o.stop = {"rel_l2": LAP_STOP_REL_L2, "res_inf": LAP_STOP_RES_INF}[stop] if isinstance(stop, str) else int(stop)
+    o.stop = {"rel_l2": LAP_STOP_REL_L2, "res_inf": LAP_STOP_RES_INF, "delta": LAP_STOP_DELTA}[stop] \
+        if isinstance(stop, str) else int(stop)
     o.nu1 = int(nu1)
     o.nu2 = int(nu2)
     o.check_every = int(check_every)

@@ -19,21 +19,22 @@ LAP_OK, LAP_EINVAL, LAP_ENOMEM, LAP_ENOTCONV, LAP_EDIVERGED, LAP_EHIP = 0, -1, -
 STATUS_NAMES = {0: "LAP_OK", -1: "LAP_EINVAL", -2: "LAP_ENOMEM", -3: "LAP_ENOTCONV",
                 -4: "LAP_EDIVERGED", -5: "LAP_EHIP"}
 LAP_SOR_RB, LAP_ADI, LAP_MG = 1, 2, 3
+LAP_JACOBI, LAP_SOR_LEX, LAP_SLOR_LEX, LAP_ADI_LEX = 4, 5, 6, 7
 LAP_FP64, LAP_MIXED = 0, 1
-LAP_STOP_REL_L2, LAP_STOP_RES_INF = 0, 1
+LAP_STOP_REL_L2, LAP_STOP_RES_INF, LAP_STOP_DELTA = 0, 1, 2
 LAP_ADI_RELAX_AFTER, LAP_ADI_RELAX_INSIDE = 0, 1
 LAP_SMOOTH_RB, LAP_SMOOTH_ZEBRA = 0, 1
 LAP_ALLOC_FP64, LAP_ALLOC_MIXED, LAP_ALLOC_ADI, LAP_ALLOC_ALL = 1, 2, 4, 7
 
 # kernel classes of lap_ctx_kernel_stats
 KC_SWEEP, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE, KC_ADI_ROWS, KC_ADI_COLS, \
-    KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_TWO_PLAIN = range(13)
+    KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_TWO_PLAIN, KC_PAPER = range(14)
 
 
 class LapInfo(ctypes.Structure):
     _fields_ = [("iterations", c_int32), ("status", c_int32), ("rel_res_l2", c_double),
                 ("res_l2", c_double), ("res_linf", c_double), ("res0_l2", c_double),
-                ("seconds", c_double)]
+                ("seconds", c_double), ("monitor", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblap.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["stencil_kernels.hip", "fused_kernels.hip", "batch_fused.hip", "adi_kernels.hip", "batch_kernels.hip",
-           "runtime.hip"]
+           "paper_kernels.hip", "runtime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -336,6 +336,23 @@ hipError_t launch_copy_many(const CopyItem* items, int count, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, int m, int n, int P, const Ctrl* ctrl,
                        hipStream_t s);
 
+// ---- the paper's sequential orderings in one workgroup (paper_kernels.hip) ----
+struct PaperArgs {
+    double* u;               // the grid (pitched, perimeter = Dirichlet data), in and out
+    const double* f;         // nullable
+    Ctrl* ctrl;              // iterations, done, status, last monitored quantity (rel), r0
+    int m, n, P;
+    double cx, cy, d, inv_d, omega;
+    int method;              // LAP_JACOBI, LAP_SOR_LEX, LAP_SLOR_LEX, LAP_ADI_LEX
+    int form;                // line methods: 0 relaxation after the solve, 1 inside
+    int stop;                // LAP_STOP_DELTA, LAP_STOP_RES_INF or LAP_STOP_REL_L2
+    double tol;
+    int max_iter;
+};
+size_t paper_lds_bytes(int m, int n);
+hipError_t paper_set_lds_limit(int bytes);
+hipError_t launch_paper(const PaperArgs& a, hipStream_t s);
+
 // ---- ADI (adi_kernels.hip) ----
 // T: element type of the field (the sequential solver is FP64 only; the
 // segmented one is also built for FP32, for line smoothing in the FP32 cycle)

@@ -270,7 +270,7 @@ size_t coarse_bytes(const LevelGeo& C) {
 enum Part { PART_ALL = 0, PART_HEAD = 1, PART_TAIL = 2 };
 
 enum KClass { KC_SWEEP = 0, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE,
-              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_TWO_PLAIN, KC_COUNT };
+              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_TWO_PLAIN, KC_PAPER, KC_COUNT };
 
 // Size classes for tilings, by interior node count.
 // One class per factor 4 of interior nodes from 2^12 to 2^24, so each level
@@ -1468,16 +1468,40 @@ lap_status finish(lap_grid* g, const lap_opts& o, const Ctrl& h, double t0, lap_
         info->res_linf = h.res_inf;
         info->res0_l2 = h.r0;
         info->seconds = now_s() - t0;
+        info->monitor = 0.0;
     }
     if (st == LAP_ENOTCONV) g_err = "max_iter reached before the stopping rule held";
     if (st == LAP_EDIVERGED) g_err = "residual diverged (NaN/Inf or growth by 1e6)";
     return st;
 }
 
+bool is_paper_method(int method) {
+    return method == LAP_JACOBI || method == LAP_SOR_LEX || method == LAP_SLOR_LEX || method == LAP_ADI_LEX;
+}
+
 lap_status validate_opts(lap_grid* g, const lap_opts& o) {
     if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(LAP_EINVAL, "omega must lie in (0, 2)");
     if (o.max_iter < 0) return fail(LAP_EINVAL, "max_iter must be >= 0");
     if (!(o.tol >= 0.0)) return fail(LAP_EINVAL, "tol must be >= 0");
+    if (is_paper_method(o.method)) {
+        if (o.stop != LAP_STOP_REL_L2 && o.stop != LAP_STOP_RES_INF && o.stop != LAP_STOP_DELTA)
+            return fail(LAP_EINVAL, "unknown stopping rule");
+        if (o.precision != LAP_FP64) return fail(LAP_EINVAL, "the paper-order methods run in FP64");
+        if (paper_lds_bytes(g->m, g->n) > (size_t)g->ctx->lds_max)
+            return fail(LAP_EINVAL, "the paper-order methods need the grid in one workgroup's LDS "
+                                    "(2 m n + 3 max(m, n) doubles)");
+        if ((o.method == LAP_SLOR_LEX || o.method == LAP_ADI_LEX) && o.adi_form != 0 && o.adi_form != 1)
+            return fail(LAP_EINVAL, "unknown line relaxation form");
+        if ((o.method == LAP_SLOR_LEX || o.method == LAP_ADI_LEX) && o.adi_form == 1) {
+            const Coef c = coef(g->dx, g->dy);
+            const double lim = o.method == LAP_SLOR_LEX ? 1.0 + c.cy / c.cx : 1.0 + std::min(c.cy / c.cx, c.cx / c.cy);
+            if (o.omega >= lim)
+                return fail(LAP_EINVAL, "relaxation inside the line system needs omega < 1 + beta^2");
+        }
+        if (o.max_iter < 0 || !(o.tol >= 0.0) || !(o.omega > 0.0 && o.omega < 2.0))
+            return fail(LAP_EINVAL, "bad omega, tol or max_iter");
+        return LAP_OK;
+    }
     if (o.stop != LAP_STOP_REL_L2 && o.stop != LAP_STOP_RES_INF) return fail(LAP_EINVAL, "unknown stopping rule");
     if (o.method != LAP_SOR_RB && o.method != LAP_ADI && o.method != LAP_MG)
         return fail(LAP_EINVAL, "unknown method");
@@ -1721,7 +1745,62 @@ lap_status fixup(lap_grid* g, const lap_opts& o, const Ctrl& h) {
 // step; once the device has stopped, the records of the launches that came
 // after the deciding stopping test (they exited at once) are dropped, so
 // the statistics hold only launches that did their full work.
+lap_status residual_norms(lap_grid* g, double* l2, double* linf);
+
+// The paper's sequential orderings: the whole solve in one launch of one
+// workgroup (the grid in LDS); FP64 residual norms before and after.
+lap_status solve_paper(lap_grid* g, const lap_opts& o, lap_info* info) {
+    const double t0 = now_s();
+    double r0 = 0.0, r0inf = 0.0;
+    lap_status st = residual_norms(g, &r0, &r0inf);
+    if (st != LAP_OK) return st;
+    const LevelGeo& L = g->geo[0];
+    const Coef c = coef(L.dx, L.dy);
+    PaperArgs a{};
+    a.u = g->psi[0];
+    a.f = g->f64;
+    a.ctrl = g->ctrl;
+    a.m = L.m;
+    a.n = L.n;
+    a.P = L.P;
+    a.cx = c.cx;
+    a.cy = c.cy;
+    a.d = c.d;
+    a.inv_d = c.inv_d;
+    a.omega = o.omega;
+    a.method = o.method;
+    a.form = o.adi_form;
+    a.stop = o.stop;
+    a.tol = o.tol;
+    a.max_iter = o.max_iter;
+    lap_ctx* cx = g->ctx;
+    HIPCHK(cx->timed(KC_PAPER, true, 0.0, [&]() { return launch_paper(a, cx->stream); }));
+    Ctrl h{};
+    HIPCHK(hipMemcpyAsync(&h, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, cx->stream));
+    HIPCHK(hipStreamSynchronize(cx->stream));
+    g->psi1_stale = true;   // psi[0] changed alone
+    double l2 = 0.0, linf = 0.0;
+    st = residual_norms(g, &l2, &linf);
+    if (st != LAP_OK) return st;
+    lap_status res = (lap_status)h.status;
+    if (res == LAP_OK && !h.done) res = o.tol > 0.0 ? LAP_ENOTCONV : LAP_OK;
+    if (info) {
+        info->iterations = h.iters;
+        info->status = res;
+        info->rel_res_l2 = r0 > 0.0 ? l2 / r0 : 0.0;
+        info->res_l2 = l2;
+        info->res_linf = linf;
+        info->res0_l2 = r0;
+        info->monitor = h.rel;
+        info->seconds = now_s() - t0;
+    }
+    if (res == LAP_ENOTCONV) g_err = "max_iter reached before the stopping rule held";
+    if (res == LAP_EDIVERGED) g_err = "iterate diverged (NaN/Inf or beyond 1e30)";
+    return res;
+}
+
 lap_status solve_one(lap_grid* g, const lap_opts& o, lap_info* info) {
+    if (is_paper_method(o.method)) return solve_paper(g, o, info);
     const double t0 = now_s();
     lap_status st = prepare(g, o);
     if (st != LAP_OK) return st;
@@ -1797,7 +1876,7 @@ lap_status lap_ctx_create(void* dev_arena, size_t arena_bytes, void* hip_stream,
         if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
         lds = std::max(lds, optin);
         if (lds > 0) {
-            if (subtree_set_lds_limit(lds) == hipSuccess) {
+            if (subtree_set_lds_limit(lds) == hipSuccess && paper_set_lds_limit(lds) == hipSuccess) {
                 c->lds_max = lds;
             } else {
                 (void)hipGetLastError();
@@ -2091,6 +2170,12 @@ lap_status lap_solve(lap_grid* g, int32_t method, double omega, double tol, int3
 
 lap_status lap_residual_ex(lap_grid* g, double* l2, double* linf) {
     if (!g) return fail(LAP_EINVAL, "grid is NULL");
+    return residual_norms(g, l2, linf);
+}
+}  // extern "C"
+
+namespace {
+lap_status residual_norms(lap_grid* g, double* l2, double* linf) {
     const LevelGeo& L = g->geo[0];
     const Coef c = coef(L.dx, L.dy);
     ResidualArgs<double> a{};
@@ -2114,6 +2199,9 @@ lap_status lap_residual_ex(lap_grid* g, double* l2, double* linf) {
     if (linf) *linf = h[1];
     return LAP_OK;
 }
+}  // namespace
+
+extern "C" {
 
 lap_status lap_residual(lap_grid* g, double* l2_rel, double* linf) {
     double l2 = 0.0;
@@ -2850,6 +2938,8 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
                                       lap_info* infos) {
     if (!c || !o || (count > 0 && !grids)) return fail(LAP_EINVAL, "NULL argument");
     if (count < 0) return fail(LAP_EINVAL, "count must be >= 0");
+    if (is_paper_method(o->method))
+        return fail(LAP_EINVAL, "the paper-order methods solve one grid at a time (lap_solve)");
     const double t0 = now_s();
     for (int k = 0; k < count; ++k) {
         if (!grids[k] || grids[k]->ctx != c) return fail(LAP_EINVAL, "grid does not belong to this context");
