@@ -154,3 +154,39 @@ def mixed_step(psi: np.ndarray, f: np.ndarray | None, levels, nu1=2, nu2=2, omeg
 def mixed_residual_after(psi, f, levels):
     m, n, dx, dy = levels[0]
     return norm2(residual(psi, f, dx, dy))
+
+
+def boundary_on_level(psi_b: np.ndarray, l: int) -> np.ndarray:
+    """The Dirichlet data of level l: the fine perimeter values at the nodes
+    the level keeps (every 2^l-th node), on an otherwise zero array."""
+    s = 1 << l
+    g = psi_b[::s, ::s].copy()
+    g[1:-1, 1:-1] = 0.0
+    return g
+
+
+def fmg(levels, psi_b: np.ndarray, f: np.ndarray | None, nu1: int = 2, nu2: int = 2,
+        omega_s: float = 1.0, smoother: str = "rb") -> np.ndarray:
+    """Full multigrid start (not in the paper; it follows the paper's argument
+    for multigrid, that the low-frequency error a fine grid removes slowly is
+    removed cheaply on coarse grids): the problem itself, not its error
+    equation, is posed on every level, with the boundary data of the level's
+    nodes and the source full-weighted down the hierarchy; the coarsest level
+    is solved exactly, and each finer level starts from the bilinear
+    interpolation of the coarser level's solution (boundary included) and
+    takes one V(nu1, nu2) cycle.  Returns the level-0 field."""
+    L = len(levels)
+    fs = [None] * L
+    fs[0] = np.zeros_like(psi_b) if f is None else np.array(f, dtype=np.float64)
+    for l in range(1, L):
+        fs[l] = restrict_fw(fs[l - 1])
+    m, n, dx, dy = levels[L - 1]
+    u = boundary_on_level(psi_b, L - 1)
+    coarse_solve(u, fs[L - 1], dx, dy)
+    for l in range(L - 2, -1, -1):
+        m, n, dx, dy = levels[l]
+        v = boundary_on_level(psi_b, l)
+        v[1:-1, 1:-1] = prolong(u, m, n)[1:-1, 1:-1]
+        vcycle(levels[l:], 0, v, fs[l], nu1, nu2, omega_s, np.float64, smoother)
+        u = v
+    return u

@@ -258,3 +258,80 @@ def test_zebra_mixed_reaches_fp64_solution():
     assert e.dtype == np.float32
     rel = np.max(np.abs(e - e64)) / np.max(np.abs(e64))
     assert 1e-9 < rel < 1e-5
+
+
+# ---------------------------------------------------------------- full multigrid
+def _smooth_case(N, with_source):
+    """u* = exp(pi x) sin(pi y) / e^pi (harmonic) or u* = sin(pi x) sin(2 pi y)
+    + x y^2 with f = laplacian(u*), on the unit square, N x N nodes."""
+    h = 1.0 / (N - 1)
+    x = np.arange(N) * h
+    X, Y = np.meshgrid(x, x)
+    if with_source:
+        ue = np.sin(np.pi * X) * np.sin(2 * np.pi * Y) + X * Y * Y
+        f = -5.0 * np.pi ** 2 * np.sin(np.pi * X) * np.sin(2 * np.pi * Y) + 2.0 * X
+    else:
+        ue = np.exp(np.pi * X) * np.sin(np.pi * Y) / np.exp(np.pi)
+        f = None
+    psi = ue.copy()
+    psi[1:-1, 1:-1] = 0.0
+    return psi, f, h, ue
+
+
+@pytest.mark.parametrize("with_source", [False, True])
+def test_fmg_reaches_discretisation_error(with_source):
+    """One FMG pass (exact coarsest solve, bilinear interpolation, one V(2,2)
+    per level) ends within 1.5x the discretisation error of the exact
+    discrete solution (DST) against the smooth continuous solution, the
+    algebraic error stays below half of it, and both fall about 4x per
+    halving of h (second order)."""
+    disc, full = {}, {}
+    for N in (33, 65, 129, 257):
+        psi, f, h, ue = _smooth_case(N, with_source)
+        lv = multigrid.hierarchy(N, N, h, h)
+        ud = direct.dst_solve(N, N, h, h, psi, f)
+        uf = multigrid.fmg(lv, psi, f)
+        disc[N] = np.max(np.abs(ud - ue))
+        full[N] = np.max(np.abs(uf - ue))
+        assert full[N] <= 1.5 * disc[N], (N, full[N], disc[N])
+        assert np.max(np.abs(uf - ud)) <= 0.5 * disc[N]
+    for a, b in ((33, 65), (65, 129), (129, 257)):
+        assert 3.7 < disc[a] / disc[b] < 4.3
+        assert 3.5 < full[a] / full[b] < 4.5
+
+
+def test_fmg_without_level_cycles_is_worse():
+    """The V-cycle on each level is what brings the interpolated start to
+    discretisation accuracy: interpolation alone (a dropped cycle) ends far
+    above the discretisation error, so the test above would catch it."""
+    N = 129
+    psi, f, h, ue = _smooth_case(N, True)
+    lv = multigrid.hierarchy(N, N, h, h)
+    ud = direct.dst_solve(N, N, h, h, psi, f)
+    orig = multigrid.vcycle
+    try:
+        multigrid.vcycle = lambda *a, **k: None
+        uf = multigrid.fmg(lv, psi, f)
+    finally:
+        multigrid.vcycle = orig
+    assert np.max(np.abs(uf - ue)) > 3.0 * np.max(np.abs(ud - ue))
+
+
+def test_fmg_exact_on_bilinear_harmonic_field():
+    """xy is discretely harmonic on every level and bilinear interpolation
+    reproduces it: every level starts exact and stays exact, so FMG returns
+    it (a quadratic such as x^2 - y^2 is not interpolated exactly, so FMG
+    then ends at discretisation accuracy, not at the field)."""
+    p, exact = W.manufactured("xy", 65, 33, 0.05, 0.09, x0=-0.4)
+    lv = multigrid.hierarchy(p.m, p.n, p.dx, p.dy)
+    uf = multigrid.fmg(lv, p.psi0, p.f)
+    assert np.max(np.abs(uf - exact)) <= 1e-11 * max(1, np.max(np.abs(exact)))
+
+
+def test_fmg_boundary_on_level():
+    psi = W.random_boundary(17, 9, 3)
+    g = multigrid.boundary_on_level(psi, 2)
+    assert g.shape == (3, 5)
+    assert np.array_equal(g[0, :], psi[0, ::4]) and np.array_equal(g[-1, :], psi[-1, ::4])
+    assert np.array_equal(g[:, 0], psi[::4, 0]) and np.array_equal(g[:, -1], psi[::4, -1])
+    assert np.all(g[1:-1, 1:-1] == 0)
