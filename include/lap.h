@@ -137,11 +137,17 @@ typedef struct lap_opts {
                            * a grid's graph is captured on its second solve with the same
                            * method options (its first solve launches directly)           */
     int32_t smoother;     /* MG: LAP_SMOOTH_RB or LAP_SMOOTH_ZEBRA                        */
+    int32_t fmg;          /* MG, FP64, red-black smoother, one grid (lap_solve): 1 = start
+                           * with one full-multigrid pass (the problem posed on every level
+                           * with its boundary nodes and the full-weighted source, exact
+                           * coarsest solve, bilinear interpolation of each coarse solution,
+                           * one V-cycle per level); it counts as the first iteration, the
+                           * stopping test's r_0 is the residual of the incoming field      */
 } lap_opts;
 
 /* Fill *o with the defaults: MG, FP64, omega 1, tol 1e-10, max_iter 100,
  * REL_L2, nu1 = nu2 = 2, check_every 1, ADI relax-after, use_graph 1,
- * smoother LAP_SMOOTH_RB. */
+ * smoother LAP_SMOOTH_RB, fmg 0. */
 void lap_opts_default(lap_opts* o);
 
 /* ---------------------------------------------------------------- context */

@@ -336,6 +336,11 @@ hipError_t launch_copy_many(const CopyItem* items, int count, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, int m, int n, int P, const Ctrl* ctrl,
                        hipStream_t s);
 
+// Perimeter of a level's buffers d0 (and d1, nullable): the finest level's
+// Dirichlet data src (pitch Ps) at every stride-th node, or zero if src is NULL.
+hipError_t launch_level_boundary(double* d0, double* d1, const double* src, int m, int n, int P, int Ps, int stride,
+                                 const Ctrl* ctrl, hipStream_t s);
+
 // ---- the paper's sequential orderings in one workgroup (paper_kernels.hip) ----
 struct PaperArgs {
     double* u;               // the grid (pitched, perimeter = Dirichlet data), in and out

@@ -540,6 +540,7 @@ template <typename T>
 struct HierView {
     std::vector<T*> u0, u1, b;
     bool zero_start0 = false;  // level 0 starts from zero (error equation) or holds the iterate
+    int root = 0;              // level of the cycle's root (full multigrid roots cycles on coarse levels)
     int sub_root = -1;         // level whose whole sub-V-cycle runs as one LDS-resident launch
 };
 
@@ -787,7 +788,7 @@ hipError_t enq_residual_norm(lap_grid* g, int l, const T* u, const T* f) {
 // pre-smoothing and restriction of level l, then every grid's coarsest
 // solve, then the post-smoothing of level l from coarse to fine.
 enum OpKind { OP_SWEEP, OP_RESTRICT, OP_COARSE, OP_FINALIZE, OP_RESNORM, OP_DEFECT, OP_ADI_ROWS, OP_ADI_COLS,
-              OP_SUBTREE, OP_POSTDEF };
+              OP_SUBTREE, OP_POSTDEF, OP_BOUNDARY };
 
 struct Op {
     long key;
@@ -963,7 +964,7 @@ int plan_vcycle(lap_grid* g, HierView<T>& H, int l, const lap_opts& o, bool norm
                 DeferredPost* dp = nullptr) {
     if (o.smoother == LAP_SMOOTH_ZEBRA) return plan_vcycle_zebra<T>(g, H, l, o, norm, part, ops);
     const int L = (int)g->geo.size();
-    const bool zero_start = (l > 0) || H.zero_start0;
+    const bool zero_start = (l > H.root) || (l == H.root && H.zero_start0);
     const bool split = norm && !zero_start;
     const bool head = !split || part != PART_TAIL;
     const bool tail = !split || part != PART_HEAD;
@@ -1235,6 +1236,44 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
     plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops);
 }
 
+// Full multigrid start (FP64): the source full-weighted down the hierarchy
+// into the levels' right-hand sides, every level's boundary nodes set from
+// the finest level's Dirichlet data, the coarsest problem solved exactly;
+// then, level by level upwards, the interior starts from the bilinear
+// interpolation of the coarser solution (boundary included), the coarser
+// level's boundary goes back to zero (it serves the next cycle as an error
+// level) and one V-cycle rooted at this level runs.  Ends with the FMG field
+// in psi[0].
+void plan_fmg(lap_grid* g, const lap_opts& o, std::vector<Op>& ops) {
+    const int L = (int)g->geo.size();
+    HierView<double> H = view64(g);
+    long key = 50000;   // single-grid schedule: keys only need to increase
+    auto boundary = [&](int l, bool set) {
+        Op op{};
+        op.key = key++;
+        op.kind = OP_BOUNDARY;
+        op.dt = 0;
+        op.level = l;
+        op.flags = set ? 1 : 0;
+        op.out = H.u0[l];
+        op.bc = H.u1[l];
+        ops.push_back(op);
+    };
+    for (int l = 1; l < L; ++l)
+        push_op<double>(ops, key++, OP_RESTRICT, l - 1, 0, nullptr, nullptr, H.b[l - 1], nullptr, H.b[l], 0.0);
+    for (int l = 1; l < L; ++l) boundary(l, true);
+    push_op<double>(ops, key++, OP_COARSE, L - 1, 0, H.u0[L - 1], H.u0[L - 1], H.b[L - 1], nullptr, nullptr, 0.0);
+    for (int l = L - 2; l >= 0; --l) {
+        push_op<double>(ops, key++, OP_SWEEP, l, SW_ZERO | SW_PROLONG | SW_PONLY, nullptr, H.u0[l], nullptr,
+                        H.u0[l + 1], nullptr, 0.0);
+        boundary(l + 1, false);
+        HierView<double> R = H;
+        R.root = l;
+        R.sub_root = subtree_root<double>(g, l + 1);
+        plan_vcycle<double>(g, R, l, o, false, PART_ALL, ops);
+    }
+}
+
 // ------------------------------------------------------------------ ADI
 // Algorithmic bytes of one zebra half (all lines of one parity) per interior
 // node of the grid: half the nodes are updated, each reading its own old
@@ -1378,6 +1417,11 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
             if (op.dt == 0)
                 return enq_subtree<double>(g, l, (double*)op.out, (const double*)op.f, op.omega, op.flags);
             return enq_subtree<float>(g, l, (float*)op.out, (const float*)op.f, op.omega, op.flags);
+        case OP_BOUNDARY: {
+            const LevelGeo& G = g->geo[l];
+            return launch_level_boundary((double*)op.out, (double*)op.bc, op.flags ? g->psi[0] : nullptr, G.m, G.n,
+                                         G.P, g->P, 1 << l, g->ctrl, g->ctx->stream);
+        }
     }
     return hipErrorInvalidValue;
 }
@@ -1508,6 +1552,9 @@ lap_status validate_opts(lap_grid* g, const lap_opts& o) {
     if (o.precision != LAP_FP64 && o.precision != LAP_MIXED) return fail(LAP_EINVAL, "unknown precision");
     if (o.precision == LAP_MIXED && o.method != LAP_MG) return fail(LAP_EINVAL, "LAP_MIXED needs LAP_MG");
     if (o.smoother != LAP_SMOOTH_RB && o.smoother != LAP_SMOOTH_ZEBRA) return fail(LAP_EINVAL, "unknown smoother");
+    if (o.fmg != 0 && o.fmg != 1) return fail(LAP_EINVAL, "fmg must be 0 or 1");
+    if (o.fmg && (o.method != LAP_MG || o.precision != LAP_FP64 || o.smoother != LAP_SMOOTH_RB))
+        return fail(LAP_EINVAL, "the full multigrid start needs LAP_MG, LAP_FP64 and the red-black smoother");
     if (o.method == LAP_MG && o.smoother == LAP_SMOOTH_ZEBRA) {
         if (!g->zebra_ok)
             return fail(LAP_EINVAL, "zebra smoothing needs every level's lines in the segmented line solver "
@@ -1659,7 +1706,15 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
 void plan_step(lap_grid* g, const lap_opts& o, int s, int part, std::vector<Op>& ops) {
     switch (o.method) {
         case LAP_MG:
-            if (o.precision == LAP_FP64) {
+            if (o.precision == LAP_FP64 && o.fmg && s == 0) {
+                // the stopping test of the incoming field, then the full multigrid pass
+                if (part != PART_TAIL) {
+                    push_op<double>(ops, KEY_HEAD, OP_RESNORM, 0, 0, g->psi[0], nullptr, g->f64, nullptr, nullptr, 0.0);
+                    push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, 0, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr, 0.0);
+                }
+                if (part != PART_HEAD) plan_fmg(g, o, ops);
+            } else if (o.precision == LAP_FP64) {
                 HierView<double> H = view64(g);
                 plan_vcycle<double>(g, H, 0, o, true, part, ops);
             } else {
@@ -1710,7 +1765,7 @@ hipError_t step(lap_grid* g, const lap_opts& o, int part = PART_ALL) {
     const int s = g->step_idx;
     if (part != PART_HEAD) g->step_idx++;
     lap_ctx* c = g->ctx;
-    const bool graph = g->graph_on && part == PART_ALL;
+    const bool graph = g->graph_on && part == PART_ALL && !(o.fmg && s == 0);
     if (graph && o.method == LAP_MG) {
         if (o.precision == LAP_FP64) return hipGraphLaunch(g->graph, c->stream);
         if (s % 2 == 1) {               // the mixed graph covers steps s (odd) and s + 1
@@ -2940,6 +2995,7 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
     if (count < 0) return fail(LAP_EINVAL, "count must be >= 0");
     if (is_paper_method(o->method))
         return fail(LAP_EINVAL, "the paper-order methods solve one grid at a time (lap_solve)");
+    if (o->fmg) return fail(LAP_EINVAL, "the full multigrid start runs on one grid at a time (lap_solve)");
     const double t0 = now_s();
     for (int k = 0; k < count; ++k) {
         if (!grids[k] || grids[k]->ctx != c) return fail(LAP_EINVAL, "grid does not belong to this context");

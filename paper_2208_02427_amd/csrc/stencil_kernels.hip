@@ -44,6 +44,9 @@ static hipError_t launch_sweep_v(const SweepArgs<T>& a, int flags, hipStream_t s
         case SW_PROLONG: k_sweep<T, V, SW_PROLONG><<<grid, block, 0, s>>>(a); break;
         case SW_PROLONG | SW_F: k_sweep<T, V, SW_PROLONG | SW_F><<<grid, block, 0, s>>>(a); break;
         case SW_PROLONG | SW_PONLY: k_sweep<T, V, SW_PROLONG | SW_PONLY><<<grid, block, 0, s>>>(a); break;
+        case SW_ZERO | SW_PROLONG | SW_PONLY:
+            k_sweep<T, V, SW_ZERO | SW_PROLONG | SW_PONLY><<<grid, block, 0, s>>>(a);
+            break;
         case SW_NORM: k_sweep<T, V, SW_NORM><<<grid, block, 0, s>>>(a); break;
         case SW_NORM | SW_F: k_sweep<T, V, SW_NORM | SW_F><<<grid, block, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
@@ -243,6 +246,41 @@ hipError_t launch_write_field(const double* src, double* d0, double* d1, int m, 
     int nb = (int)std::min<size_t>((total + kBlock - 1) / kBlock, 8192);
     if (nb < 1) nb = 1;
     k_write_field<<<nb, kBlock, 0, s>>>(src, d0, d1, m, n, P);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------- level boundary data
+// Perimeter of a level's two buffers: the finest level's Dirichlet data at
+// every stride-th node (src), or zero (src == NULL).
+__global__ __launch_bounds__(kBlock) void k_level_boundary(double* d0, double* d1, const double* src, int m, int n,
+                                                          int P, int Ps, int stride, const Ctrl* ctrl) {
+    if (ctrl != nullptr && ctrl->done) return;
+    const int per = 2 * m + 2 * (n - 2);
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < per; k += gridDim.x * blockDim.x) {
+        int i, j;
+        if (k < m) {
+            i = k;
+            j = 0;
+        } else if (k < 2 * m) {
+            i = k - m;
+            j = n - 1;
+        } else if (k < 2 * m + (n - 2)) {
+            i = 0;
+            j = 1 + (k - 2 * m);
+        } else {
+            i = m - 1;
+            j = 1 + (k - 2 * m - (n - 2));
+        }
+        const double v = src != nullptr ? src[(size_t)j * stride * Ps + (size_t)i * stride] : 0.0;
+        d0[(size_t)j * P + i] = v;
+        if (d1 != nullptr) d1[(size_t)j * P + i] = v;
+    }
+}
+
+hipError_t launch_level_boundary(double* d0, double* d1, const double* src, int m, int n, int P, int Ps, int stride,
+                                 const Ctrl* ctrl, hipStream_t s) {
+    const int per = 2 * m + 2 * (n - 2);
+    k_level_boundary<<<(per + kBlock - 1) / kBlock, kBlock, 0, s>>>(d0, d1, src, m, n, P, Ps, stride, ctrl);
     return hipGetLastError();
 }
 

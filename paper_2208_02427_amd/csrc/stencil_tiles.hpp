@@ -255,6 +255,8 @@ __device__ __forceinline__ void sweep_load(T (&x)[V], const SweepArgs<T>& A, int
                                            Prolong<T, V>& pr) {
     if constexpr (FL & SW_ZERO) {
         zero<T, V>(x);
+        // zero start plus the correction only: the interpolated coarse solution
+        if constexpr ((FL & SW_PONLY) && (FL & SW_PROLONG)) pr.add(x, A.ec, j, A.n, A.nc, A.Pc, A.Pcs, c.i0, A.m);
     } else {
         load_row<T, V>(x, A.uin, j, A.n, A.Ps, c.i0, c.vin);
         if constexpr (FL & SW_PROLONG) pr.add(x, A.ec, j, A.n, A.nc, A.Pc, A.Pcs, c.i0, A.m);

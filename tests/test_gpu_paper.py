@@ -121,9 +121,9 @@ def test_paper_method_errors():
     with pytest.raises(LapError):
         big.solve("sor_lex", raise_on_fail=True)
     big.destroy()
-    g = ctx.grid(to_dev(torch, np.zeros((17, 9))), None, 0.1, 0.1)
+    g = ctx.grid(to_dev(torch, np.zeros((17, 9))), None, 0.1, 0.2)          # beta^2 = cy / cx = 0.25
     with pytest.raises(LapError):
         ctx.solve_batch([g], method="jacobi")
     with pytest.raises(LapError):                                           # SLORB needs w < 1 + beta^2
-        g.solve("slor_lex", omega=1.9, adi_form="inside", raise_on_fail=True)
+        g.solve("slor_lex", omega=1.3, adi_form="inside", raise_on_fail=True)
     g.destroy()
