@@ -8,8 +8,17 @@
 
 namespace lap {
 
+// FP64 restricting passes of two columns per lane without a source sit just
+// above 128 registers with whole ring turns; held to 128, they keep four
+// waves per SIMD.
 template <typename T, int V, int FL>
-__global__ __launch_bounds__(kBlock) void k_fused(SweepArgs<T> A) {
+constexpr int fused_min_waves() {
+    return (sizeof(T) == 8 && V == 2 && (FL & (SW_RESTRICT | SW_F | SW_PROLONG)) == SW_RESTRICT) ? 4 : 1;
+}
+
+template <typename T, int V, int FL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fused_min_waves<T, V, FL>())))
+void k_fused(SweepArgs<T> A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     // the wave index stays a vector value here: with a uniform one

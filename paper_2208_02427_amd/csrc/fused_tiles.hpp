@@ -41,19 +41,18 @@ __device__ __forceinline__ void stage_zero(RBStage<T, V>& S) {
 // sweep and is handed on in (out, fout); the stage moves to row j+1.
 template <typename T, int V, int JP>
 __device__ __forceinline__ void rb_push(RBStage<T, V>& S, const T (&d)[V], const T (&fd)[V], T (&out)[V],
-                                        T (&fout)[V], int j, int n, const Cols<V>& c, int ipar, T cx, T cy, T inv_d,
-                                        T om) {
+                                        T (&fout)[V], int j, int n, const OmegaMask<T, V>& wm, T cx, T cy,
+                                        T inv_d) {
     const T cW = lane_prev(S.c[V - 1]);
     const T cE = lane_next(S.c[0]);
     if (j >= 1 && j <= n - 2) {
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
-            if (!upd || !c.cint[e]) continue;
+            if (colour_skip<V, JP>(e)) continue;
             const T W = e > 0 ? S.c[e - 1] : cW;
             const T E = e < V - 1 ? S.c[e + 1] : cE;
             const T t = (fma(cy, S.b[e] + d[e], cx * (W + E)) - S.fc[e]) * inv_d;
-            S.c[e] = fma(om, t - S.c[e], S.c[e]);
+            S.c[e] = fma(wm.w[JP][e], t - S.c[e], S.c[e]);
         }
     }
     const T bW = lane_prev(S.b[V - 1]);
@@ -61,12 +60,11 @@ __device__ __forceinline__ void rb_push(RBStage<T, V>& S, const T (&d)[V], const
     if (j - 1 >= 1 && j - 1 <= n - 2) {
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
-            if (!upd || !c.cint[e]) continue;
+            if (colour_skip<V, JP>(e)) continue;
             const T W = e > 0 ? S.b[e - 1] : bW;
             const T E = e < V - 1 ? S.b[e + 1] : bE;
             const T t = (fma(cy, S.a[e] + S.c[e], cx * (W + E)) - S.fb[e]) * inv_d;
-            S.b[e] = fma(om, t - S.b[e], S.b[e]);
+            S.b[e] = fma(wm.w[JP][e], t - S.b[e], S.b[e]);
         }
     }
     copy<T, V>(out, S.b);
@@ -93,6 +91,16 @@ constexpr int fused_pf() {
     return sizeof(T) == 8 ? ((FL & SW_F) ? kPfF64WithF : 6) : 2;
 }
 
+// Whole ring turns as straight-line code (the tail turn keeps its per-step
+// row test) save the register copies of the rotating pipeline: 14% fewer
+// VALU instructions in the FP64 restricting pass.  Passes that prolong hold
+// the coarse rows as well and would need more registers, costing a wave of
+// occupancy, so they keep the tested turn.
+template <typename T, int FL>
+constexpr bool fused_full_turns() {
+    return (FL & SW_PROLONG) == 0;
+}
+
 template <typename T, int V, int NS, bool RS, int PF>
 struct FusedRegs {
     RBStage<T, V> st[NS];
@@ -111,7 +119,8 @@ struct FusedRegs {
 // q = j + 1 - 2 * NS.
 template <typename T, int V, int FL, int NS, bool RS, int JP, int PH>
 __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS, fused_pf<T, FL>()>& R,
-                                           const Cols<V>& c, int j, int j0, int j1, int Lend, int ipar) {
+                                           const Cols<V>& c, int j, int j0, int j1, int Lend,
+                                           const OmegaMask<T, V>& wm) {
     constexpr int PF = fused_pf<T, FL>();
     T d[V], fd[V];
     copy<T, V>(d, R.ring[PH]);
@@ -120,7 +129,7 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
         sweep_load<T, V, FL>(R.ring[PH], A, j + 1 + PF, c, R.pr);
         sweep_loadf<T, V, FL>(R.fring[PH], A, j + 1 + PF, c);
     }
-    const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
+    const T cx = A.cx, cy = A.cy, inv_d = A.inv_d;
 
     if constexpr (FL & SW_NORM) {
         // residual of the input at row j (rows j-1, j, j+1 are input values)
@@ -129,11 +138,10 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
         if (j >= j0 && j <= j1) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                if (!c.cout[e]) continue;
                 const T W = e > 0 ? R.st[0].c[e - 1] : cW;
                 const T E = e < V - 1 ? R.st[0].c[e + 1] : cE;
                 const T L = fma(-A.d, R.st[0].c[e], fma(cy, R.bo[e] + d[e], cx * (W + E)));
-                const double r = (double)(R.st[0].fc[e] - L);
+                const double r = c.cout[e] ? (double)(R.st[0].fc[e] - L) : 0.0;
                 R.s2 = fma(r, r, R.s2);
                 R.mx = fmax(R.mx, fabs(r));
             }
@@ -142,10 +150,10 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
     }
 
     T o[V], fo[V];
-    rb_push<T, V, JP>(R.st[0], d, fd, o, fo, j, A.n, c, ipar, cx, cy, inv_d, om);
+    rb_push<T, V, JP>(R.st[0], d, fd, o, fo, j, A.n, wm, cx, cy, inv_d);
     if constexpr (NS == 2) {
         T o2[V], fo2[V];
-        rb_push<T, V, JP>(R.st[1], o, fo, o2, fo2, j - 2, A.n, c, ipar, cx, cy, inv_d, om);
+        rb_push<T, V, JP>(R.st[1], o, fo, o2, fo2, j - 2, A.n, wm, cx, cy, inv_d);
         copy<T, V>(o, o2);
         copy<T, V>(fo, fo2);
     }
@@ -168,9 +176,9 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 r32[e] = (T)r[e];
-                if (!c.cout[e]) continue;
-                R.s2 = fma(r[e], r[e], R.s2);
-                R.mx = fmax(R.mx, fabs(r[e]));
+                const double rr = c.cout[e] ? r[e] : 0.0;
+                R.s2 = fma(rr, rr, R.s2);
+                R.mx = fmax(R.mx, fabs(rr));
             }
             if (A.rowpart && ((q - 1) % kRowBlock == 0 || q - 1 == j1)) {
                 // end of a block of kRowBlock rows (wave-uniform): its
@@ -233,12 +241,26 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
 // Steps PH, PH+1, ... of one turn of the ring, starting at row j + PH.
 template <typename T, int V, int FL, int NS, bool RS, int JP0, int PH>
 __device__ __forceinline__ void fused_turn(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS, fused_pf<T, FL>()>& R,
-                                           const Cols<V>& c, int j, int j0, int j1, int Lend, int ipar) {
+                                           const Cols<V>& c, int j, int j0, int j1, int Lend,
+                                           const OmegaMask<T, V>& wm) {
     if constexpr (PH < fused_pf<T, FL>()) {
         if (j + PH <= Lend - 1) {
-            fused_step<T, V, FL, NS, RS, (JP0 + PH) & 1, PH>(A, R, c, j + PH, j0, j1, Lend, ipar);
-            fused_turn<T, V, FL, NS, RS, JP0, PH + 1>(A, R, c, j, j0, j1, Lend, ipar);
+            fused_step<T, V, FL, NS, RS, (JP0 + PH) & 1, PH>(A, R, c, j + PH, j0, j1, Lend, wm);
+            fused_turn<T, V, FL, NS, RS, JP0, PH + 1>(A, R, c, j, j0, j1, Lend, wm);
         }
+    }
+}
+
+// A whole turn of the ring, every step taken (the caller knows all PF rows
+// exist): straight-line code, so the pipeline's register roles rotate by
+// renaming instead of copies.
+template <typename T, int V, int FL, int NS, bool RS, int JP0, int PH>
+__device__ __forceinline__ void fused_turn_full(const SweepArgs<T>& A,
+                                                FusedRegs<T, V, NS, RS, fused_pf<T, FL>()>& R, const Cols<V>& c,
+                                                int j, int j0, int j1, int Lend, const OmegaMask<T, V>& wm) {
+    if constexpr (PH < fused_pf<T, FL>()) {
+        fused_step<T, V, FL, NS, RS, (JP0 + PH) & 1, PH>(A, R, c, j + PH, j0, j1, Lend, wm);
+        fused_turn_full<T, V, FL, NS, RS, JP0, PH + 1>(A, R, c, j, j0, j1, Lend, wm);
     }
 }
 
@@ -281,6 +303,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
         j0 = t0;
     }
     const int ipar = c.i0 & 1;
+    const OmegaMask<T, V> wm(c, ipar, A.omega);
     if constexpr ((FL & SW_DEF) != 0) A.rp_off = win * row_blocks(A.n);
     // input rows [L0, Lend]: the last stage must be exact on the chunk's rows
     // and, with the restriction, two rows around its first and last even row;
@@ -331,8 +354,10 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
     // the loop is unrolled over one turn of the ring (PF is even, so every
     // turn starts on the row parity JP0)
     static_assert(PF % 2 == 0, "the ring turn must keep the row parity");
-    for (int j = L0 + 1; j <= Lend - 1; j += PF)
-        fused_turn<T, V, FL, NS, RS, JP0, 0>(A, R, c, j, j0, j1, Lend, ipar);
+    int j = L0 + 1;
+    if constexpr (fused_full_turns<T, FL>())
+        for (; j + PF - 1 <= Lend - 1; j += PF) fused_turn_full<T, V, FL, NS, RS, JP0, 0>(A, R, c, j, j0, j1, Lend, wm);
+    for (; j <= Lend - 1; j += PF) fused_turn<T, V, FL, NS, RS, JP0, 0>(A, R, c, j, j0, j1, Lend, wm);
     if constexpr ((FL & (SW_NORM | SW_DEF)) != 0) {
         if ((FL & SW_DEF) && A.rowpart) return;
         const double s = wave_sum(R.s2);

@@ -129,6 +129,28 @@ struct Cols {
     }
 };
 
+// The relaxation factor of each of a lane's columns for each row parity JP:
+// omega where the node is interior and has the colour the sweep updates on
+// that row, else 0.  An update psi <- fma(w, t - psi, psi) with w = 0 leaves
+// psi unchanged (up to the sign of a zero), so the sweeps need no per-lane
+// branch; for even V the colour of element e is fixed by e and JP and the
+// elements of the other colour are skipped at compile time.
+template <typename T, int V>
+struct OmegaMask {
+    T w[2][V];
+    __device__ __forceinline__ OmegaMask(const Cols<V>& c, int ipar, T om) {
+#pragma unroll
+        for (int jp = 0; jp < 2; ++jp)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const bool upd = ((((V % 2 == 0) ? 0 : ipar) + e + jp) & 1) == 0;
+                w[jp][e] = (upd && c.cint[e]) ? om : T(0);
+            }
+    }
+};
+template <int V, int JP>
+__host__ __device__ constexpr bool colour_skip(int e) { return V % 2 == 0 && ((e + JP) & 1) != 0; }
+
 // P is the row stride (negative for a flipped view); vin says the lane's
 // columns lie inside the row.
 template <typename T, int V>
@@ -285,7 +307,7 @@ struct SweepRegs {
 
 template <typename T, int V, int FL, int JP>
 __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V>& R, const Cols<V>& c,
-                                           int j, int j0, int j1, int ipar) {
+                                           int j, int j0, int j1, const OmegaMask<T, V>& wm) {
     // rotate in the prefetched row j+1, prefetch row j+3 (two rows in flight)
     copy<T, V>(R.d, R.dn);
     copy<T, V>(R.fd, R.fdn);
@@ -295,7 +317,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
         sweep_load<T, V, FL>(R.dnn, A, j + 3, c, R.pr);
         sweep_loadf<T, V, FL>(R.fdnn, A, j + 3, c);
     }
-    const T cx = A.cx, cy = A.cy, inv_d = A.inv_d, om = A.omega;
+    const T cx = A.cx, cy = A.cy, inv_d = A.inv_d;
 
     // old row j: neighbours across lanes
     const T cW = lane_prev(R.c[V - 1]);
@@ -305,11 +327,10 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
         if (j >= j0 && j <= j1) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                if (!c.cout[e]) continue;
                 const T W = e > 0 ? R.c[e - 1] : cW;
                 const T E = e < V - 1 ? R.c[e + 1] : cE;
                 const T L = fma(-A.d, R.c[e], fma(cy, R.bo[e] + R.d[e], cx * (W + E)));
-                const double r = (double)(R.fc[e] - L);
+                const double r = c.cout[e] ? (double)(R.fc[e] - L) : 0.0;
                 R.s2 = fma(r, r, R.s2);
                 R.mx = fmax(R.mx, fabs(r));
             }
@@ -324,12 +345,11 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
     if (rj) {
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
-            if (!upd || !c.cint[e]) continue;
+            if (colour_skip<V, JP>(e)) continue;
             const T W = e > 0 ? R.c[e - 1] : cW;
             const T E = e < V - 1 ? R.c[e + 1] : cE;
             const T t = (fma(cy, R.b[e] + R.d[e], cx * (W + E)) - R.fc[e]) * inv_d;
-            R.c[e] = fma(om, t - R.c[e], R.c[e]);
+            R.c[e] = fma(wm.w[JP][e], t - R.c[e], R.c[e]);
         }
     }
     // colour 1 on row j-1 ((i+j-1) odd) from the new colour-0 values
@@ -338,12 +358,11 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V
     if (rjm) {
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-            const bool upd = (((V % 2 == 0 ? 0 : ipar) + e + JP) & 1) == 0;
-            if (!upd || !c.cint[e]) continue;
+            if (colour_skip<V, JP>(e)) continue;
             const T W = e > 0 ? R.b[e - 1] : bW;
             const T E = e < V - 1 ? R.b[e + 1] : bE;
             const T t = (fma(cy, R.a[e] + R.c[e], cx * (W + E)) - R.fb[e]) * inv_d;
-            R.b[e] = fma(om, t - R.b[e], R.b[e]);
+            R.b[e] = fma(wm.w[JP][e], t - R.b[e], R.b[e]);
         }
     }
     if (j - 1 >= j0 && j - 1 <= j1) store_row<T, V>(A.uout, R.b, j - 1, A.Ps, c);
@@ -365,6 +384,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& A0, int tile, int
     const int j0 = 1 + chunk * A.tl.ty;          // odd
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
     const int ipar = c.i0 & 1;
+    const OmegaMask<T, V> wm(c, ipar, A.omega);
 
     SweepRegs<T, V> R;
     R.s2 = 0.0;
@@ -382,8 +402,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& A0, int tile, int
     if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.b);
 
     for (int j = j0 - 1; j <= j1 + 1; j += 2) {   // j0 - 1 is even
-        sweep_step<T, V, FL, 0>(A, R, c, j, j0, j1, ipar);
-        if (j + 1 <= j1 + 1) sweep_step<T, V, FL, 1>(A, R, c, j + 1, j0, j1, ipar);
+        sweep_step<T, V, FL, 0>(A, R, c, j, j0, j1, wm);
+        if (j + 1 <= j1 + 1) sweep_step<T, V, FL, 1>(A, R, c, j + 1, j0, j1, wm);
     }
     if constexpr (FL & SW_NORM) {
         const double s = wave_sum(R.s2);
