@@ -124,9 +124,12 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
     constexpr int PF = fused_pf<T, FL>();
     T d[V], fd[V];
     copy<T, V>(d, R.ring[PH]);
+    // the ring holds rows as stored; the correction is added as a row enters,
+    // so the loads in flight are not waited for until then
+    if constexpr (adds_correction<FL>()) R.pr.add(d, A.ec, j + 1, A.n, A.nc, A.Pc, A.Pcs, c.i0, A.m);
     copy<T, V>(fd, R.fring[PH]);
     if (j + 1 + PF <= Lend) {
-        sweep_load<T, V, FL>(R.ring[PH], A, j + 1 + PF, c, R.pr);
+        sweep_load_raw<T, V, FL>(R.ring[PH], A, j + 1 + PF, c);
         sweep_loadf<T, V, FL>(R.fring[PH], A, j + 1 + PF, c);
     }
     const T cx = A.cx, cy = A.cy, inv_d = A.inv_d;
@@ -335,7 +338,7 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
     constexpr int PF = fused_pf<T, FL>();
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
-        sweep_load<T, V, FL>(R.ring[k], A, L0 + 2 + k, c, R.pr);
+        sweep_load_raw<T, V, FL>(R.ring[k], A, L0 + 2 + k, c);
         sweep_loadf<T, V, FL>(R.fring[k], A, L0 + 2 + k, c);
     }
     if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.st[0].b);

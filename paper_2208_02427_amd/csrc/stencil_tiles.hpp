@@ -191,29 +191,31 @@ __device__ __forceinline__ void store_row_nt(bool nt, T* base, const T (&x)[V], 
 // A lane owning fine columns i0..i0+V-1 needs coarse columns I0 = i0>>1 ..
 // I0 + V2 (V2 = max(1, V/2)); it loads I0..I0+V2-1 with one vector load per
 // coarse row and takes column I0+V2 from the next lane.  The two coarse rows
-// J, J+1 around the current fine row stay in registers, and row J+2 is
-// already in flight (its raw load is completed with the neighbour's column
-// only when it moves up), so the stream of fine rows never waits on a coarse
-// load: fine rows arrive in increasing order and each coarse row is loaded
-// once per wave, two fine rows before it is used.
+// J, J+1 around the current fine row stay in registers, and rows J+2 and J+3
+// are already in flight (a raw load is completed with the neighbour's column
+// only when it moves up), so the stream of fine rows does not wait on a
+// coarse load: fine rows arrive in increasing order and each coarse row is
+// loaded once per wave, four to six fine rows before it is used.
 template <typename T, int V>
 struct Prolong {
     static constexpr int V2 = V >= 2 ? V / 2 : 1;
     T lo[V2 + 1], hi[V2 + 1];   // coarse rows Jcur, Jcur+1 (entry V2 from the next lane)
     T nraw[V2], nlast;          // coarse row Jcur+2 as loaded (nlast: lane 63's column I0+V2)
+    T mraw[V2], mlast;          // coarse row Jcur+3 as loaded (two coarse rows in flight)
     int Jcur;
     // Pc: the coarse row length bound (pitch), Ps: the coarse row stride
-    __device__ __forceinline__ void issue(const T* ec, int J, int nc, int Pc, int Ps, int I0) {
+    __device__ __forceinline__ void issue(T (&raw)[V2], T& last, const T* ec, int J, int nc, int Pc, int Ps,
+                                          int I0) {
         if (J >= 0 && J < nc && I0 >= 0 && I0 + V2 <= Pc)
-            ldv<T, V2>(nraw, ec + (ptrdiff_t)J * Ps + I0);
+            ldv<T, V2>(raw, ec + (ptrdiff_t)J * Ps + I0);
         else
-            zero<T, V2>(nraw);
+            zero<T, V2>(raw);
         // the last lane has no right neighbour, but its halo columns still need
         // coarse column I0 + V2 (the sweep reads the window's last column)
-        nlast = T(0);
+        last = T(0);
         if ((threadIdx.x & 63) == 63) {
             const int I = I0 + V2;
-            if (J >= 0 && J < nc && I >= 0 && I < Pc) nlast = ec[(ptrdiff_t)J * Ps + I];
+            if (J >= 0 && J < nc && I >= 0 && I < Pc) last = ec[(ptrdiff_t)J * Ps + I];
         }
     }
     __device__ __forceinline__ void complete(T (&x)[V2 + 1]) {
@@ -224,11 +226,12 @@ struct Prolong {
     }
     __device__ __forceinline__ void init(const T* ec, int j, int nc, int Pc, int Ps, int i0) {
         Jcur = j >> 1;
-        issue(ec, Jcur, nc, Pc, Ps, i0 >> 1);
+        issue(nraw, nlast, ec, Jcur, nc, Pc, Ps, i0 >> 1);
         complete(lo);
-        issue(ec, Jcur + 1, nc, Pc, Ps, i0 >> 1);
+        issue(nraw, nlast, ec, Jcur + 1, nc, Pc, Ps, i0 >> 1);
         complete(hi);
-        issue(ec, Jcur + 2, nc, Pc, Ps, i0 >> 1);
+        issue(nraw, nlast, ec, Jcur + 2, nc, Pc, Ps, i0 >> 1);
+        issue(mraw, mlast, ec, Jcur + 3, nc, Pc, Ps, i0 >> 1);
     }
     // add P(ec) to fine row j (j non-decreasing between calls)
     __device__ __forceinline__ void add(T (&x)[V], const T* ec, int j, int n, int nc, int Pc, int Ps, int i0,
@@ -239,7 +242,9 @@ struct Prolong {
             for (int q = 0; q <= V2; ++q) lo[q] = hi[q];
             complete(hi);
             ++Jcur;
-            issue(ec, Jcur + 2, nc, Pc, Ps, i0 >> 1);
+            copy<T, V2>(nraw, mraw);
+            nlast = mlast;
+            issue(mraw, mlast, ec, Jcur + 3, nc, Pc, Ps, i0 >> 1);
         }
         if (j < 0 || j >= n) return;
         const bool t = (j & 1) != 0;                  // wave-uniform
@@ -272,17 +277,29 @@ struct Prolong {
 };
 
 // ------------------------------------------------------------ red-black sweep
+// Input row j as stored (zero for a zero start), before any correction.
+template <typename T, int V, int FL>
+__device__ __forceinline__ void sweep_load_raw(T (&x)[V], const SweepArgs<T>& A, int j, const Cols<V>& c) {
+    if constexpr (FL & SW_ZERO)
+        zero<T, V>(x);
+    else
+        load_row<T, V>(x, A.uin, j, A.n, A.Ps, c.i0, c.vin);
+}
+
+// Whether input rows take the bilinear correction P(ec): passes with the
+// prolongation, except a zero start without SW_PONLY.  (A zero start with
+// SW_PONLY is the interpolated coarse solution alone.)
+template <int FL>
+__host__ __device__ constexpr bool adds_correction() {
+    return (FL & SW_PROLONG) != 0 && ((FL & SW_ZERO) == 0 || (FL & SW_PONLY) != 0);
+}
+
+// Input row j of a sweep: as stored, plus the correction where the pass adds it.
 template <typename T, int V, int FL>
 __device__ __forceinline__ void sweep_load(T (&x)[V], const SweepArgs<T>& A, int j, const Cols<V>& c,
                                            Prolong<T, V>& pr) {
-    if constexpr (FL & SW_ZERO) {
-        zero<T, V>(x);
-        // zero start plus the correction only: the interpolated coarse solution
-        if constexpr ((FL & SW_PONLY) && (FL & SW_PROLONG)) pr.add(x, A.ec, j, A.n, A.nc, A.Pc, A.Pcs, c.i0, A.m);
-    } else {
-        load_row<T, V>(x, A.uin, j, A.n, A.Ps, c.i0, c.vin);
-        if constexpr (FL & SW_PROLONG) pr.add(x, A.ec, j, A.n, A.nc, A.Pc, A.Pcs, c.i0, A.m);
-    }
+    sweep_load_raw<T, V, FL>(x, A, j, c);
+    if constexpr (adds_correction<FL>()) pr.add(x, A.ec, j, A.n, A.nc, A.Pc, A.Pcs, c.i0, A.m);
 }
 
 template <typename T, int V, int FL>
