@@ -3370,10 +3370,11 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
     std::vector<Cand> cands;
     for (int V : {1, 2, 4}) {
         for (int ty : {2, 4, 8, 16, 32, 64, 128}) cands.push_back({V, ty, 0});
-        // one round of waves at 4, 5, 6 and 8 waves per SIMD, and two at 8
+        // one round of waves at 2 to 6 and 8 waves per SIMD, and two at 8
         // (a pass whose waves fill the device exactly once avoids a partly
-        // occupied last round: 8193^2 post pass 276 -> 270 us at 5 per SIMD)
-        for (int q : {4, 5, 6}) cands.push_back({V, 0, c->wave_cap * q / 8});
+        // occupied last round: 8193^2 post pass 276 -> 270 us at 5 per SIMD;
+        // passes of 129 to 156 registers hold at most 3 waves per SIMD)
+        for (int q : {2, 3, 4, 5, 6}) cands.push_back({V, 0, c->wave_cap * q / 8});
         cands.push_back({V, 0, c->wave_cap});
         cands.push_back({V, 0, 2 * c->wave_cap});
     }
