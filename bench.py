@@ -53,7 +53,7 @@ HBM_PEAK_GBS = 8000.0
 # with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by the counts of a
 # 1 GiB stream copy (summaries under profiles/); keyed by kernel class and the
 # tiling (V, ty, target waves) they were taken with, for this kernel version.
-FINE_TRAFFIC = {("pre", 2, 0, 32768): 1.2917e9, ("two", 2, 64, 0): 1.2517e9, ("two", 4, 0, 6144): 1.3161e9}
+FINE_TRAFFIC = {("pre", 2, 0, 32768): 1.2861e9, ("two", 4, 0, 6144): 1.3160e9}
 
 # kernel classes timed on the finest level (numbering of lap.h)
 FINE_CLASSES = {"sweep": 0, "sweep_prolong": 1, "restrict": 2, "pre": 10, "two": 11}
@@ -333,12 +333,16 @@ def device_request(torch, req, dev):
 
 
 def run_copy_probe(torch, lap, dev):
-    """Achievable HBM bandwidth: plain copy of 1 GiB with several grid sizes
-    (also the calibration kernel of the byte counters)."""
+    """Achievable HBM bandwidth: plain copy of 1 GiB (also the calibration
+    kernel of the byte counters), timed two ways: ten launches back to back
+    (wall clock; each launch starts with the last one's written lines dirty in
+    the caches) and single launches after a 1 GiB read of another buffer has
+    flushed the caches (HIP events); plus a 1 GiB read-only reduction."""
     src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     dst = torch.empty_like(src)
-    best = {}
-    for blocks in (1024, 2048, 4096, 8192):
+    other = torch.ones((1 << 30) // 8, dtype=torch.float64, device=dev)
+    b2b, single = {}, {}
+    for blocks in (1024, 2048, 4096, 8192, 32768):
         lap.op_stream_copy(src, dst, blocks=blocks)
         sync()
         t0 = time.perf_counter()
@@ -346,9 +350,30 @@ def run_copy_probe(torch, lap, dev):
             lap.op_stream_copy(src, dst, blocks=blocks)
         sync()
         t = (time.perf_counter() - t0) / 10
-        best[blocks] = 2 * (1 << 30) / t / 1e9
-    del src, dst
-    return {"bytes_per_launch": 2 * (1 << 30), "GB/s_by_blocks": best, "best_GB/s": max(best.values())}
+        b2b[blocks] = 2 * (1 << 30) / t / 1e9
+        ts = []
+        for _ in range(5):
+            other.sum()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lap.op_stream_copy(src, dst, blocks=blocks)
+            e1.record()
+            sync()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        ts.sort()
+        single[blocks] = [2 * (1 << 30) / ts[len(ts) // 2] / 1e9, 2 * (1 << 30) / ts[0] / 1e9]
+    rd = []
+    for _ in range(5):
+        src.view(torch.float64).sum()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        other.sum()
+        e1.record()
+        sync()
+        rd.append((1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst, other
+    return {"bytes_per_launch": 2 * (1 << 30), "GB/s_by_blocks": b2b, "best_GB/s": max(b2b.values()),
+            "single_after_flush_GB/s_median_best": single, "read_only_GB/s_best": max(rd)}
 
 
 def run_batch_leg(args, ctx, torch, lap, dev):
