@@ -88,6 +88,7 @@ constexpr int kPfF64WithF = 6;
 template <typename T, int FL>
 constexpr int fused_pf() {
     if constexpr ((FL & SW_DEF) != 0) return 2;
+    if constexpr (sizeof(T) == 4 && (FL & SW_PROLONG) != 0) return 4;
     return sizeof(T) == 8 ? ((FL & SW_F) ? kPfF64WithF : 6) : 2;
 }
 

@@ -325,13 +325,15 @@ struct SweepRegs {
 template <typename T, int V, int FL, int JP>
 __device__ __forceinline__ void sweep_step(const SweepArgs<T>& A, SweepRegs<T, V>& R, const Cols<V>& c,
                                            int j, int j0, int j1, const OmegaMask<T, V>& wm) {
-    // rotate in the prefetched row j+1, prefetch row j+3 (two rows in flight)
+    // rotate in the prefetched row j+1 (the correction is added as it enters),
+    // prefetch row j+3 (two rows in flight)
     copy<T, V>(R.d, R.dn);
+    if constexpr (adds_correction<FL>()) R.pr.add(R.d, A.ec, j + 1, A.n, A.nc, A.Pc, A.Pcs, c.i0, A.m);
     copy<T, V>(R.fd, R.fdn);
     copy<T, V>(R.dn, R.dnn);
     copy<T, V>(R.fdn, R.fdnn);
     if (j + 3 <= j1 + 2) {
-        sweep_load<T, V, FL>(R.dnn, A, j + 3, c, R.pr);
+        sweep_load_raw<T, V, FL>(R.dnn, A, j + 3, c);
         sweep_loadf<T, V, FL>(R.fdnn, A, j + 3, c);
     }
     const T cx = A.cx, cy = A.cy, inv_d = A.inv_d;
@@ -412,9 +414,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& A0, int tile, int
     sweep_load<T, V, FL>(R.b, A, j0 - 2, c, R.pr);
     sweep_load<T, V, FL>(R.c, A, j0 - 1, c, R.pr);
     sweep_loadf<T, V, FL>(R.fc, A, j0 - 1, c);
-    sweep_load<T, V, FL>(R.dn, A, j0, c, R.pr);
+    sweep_load_raw<T, V, FL>(R.dn, A, j0, c);
     sweep_loadf<T, V, FL>(R.fdn, A, j0, c);
-    sweep_load<T, V, FL>(R.dnn, A, j0 + 1, c, R.pr);
+    sweep_load_raw<T, V, FL>(R.dnn, A, j0 + 1, c);
     sweep_loadf<T, V, FL>(R.fdnn, A, j0 + 1, c);
     if constexpr (FL & SW_NORM) copy<T, V>(R.bo, R.b);
 
