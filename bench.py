@@ -53,7 +53,7 @@ HBM_PEAK_GBS = 8000.0
 # with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by the counts of a
 # 1 GiB stream copy (summaries under profiles/); keyed by kernel class and the
 # tiling (V, ty, target waves) they were taken with, for this kernel version.
-FINE_TRAFFIC = {("pre", 2, 0, 32768): 1.2861e9, ("two", 4, 0, 6144): 1.3160e9}
+FINE_TRAFFIC = {("pre", 2, 0, 32768): 1.2863e9, ("two", 2, 0, 3072): 1.2285e9}
 
 # kernel classes timed on the finest level (numbering of lap.h)
 FINE_CLASSES = {"sweep": 0, "sweep_prolong": 1, "restrict": 2, "pre": 10, "two": 11}
