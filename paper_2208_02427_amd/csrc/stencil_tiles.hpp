@@ -831,18 +831,18 @@ __device__ __forceinline__ void finalize_block(const double* partials, int ntile
     double s = 0.0, mx = 0.0;
     const double2* p2 = reinterpret_cast<const double2*>(partials);
     int t = threadIdx.x;
-    for (; t + 3 * kFinBlock < ntiles; t += 4 * kFinBlock) {
-        const double2 a0 = p2[t], a1 = p2[t + kFinBlock], a2 = p2[t + 2 * kFinBlock], a3 = p2[t + 3 * kFinBlock];
-        s += a0.x;
-        s += a1.x;
-        s += a2.x;
-        s += a3.x;
-        mx = fmax(fmax(fmax(fmax(mx, a0.y), a1.y), a2.y), a3.y);
-    }
-    for (; t < ntiles; t += kFinBlock) {
-        const double2 a = p2[t];
-        s += a.x;
-        mx = fmax(mx, a.y);
+    // each thread adds partials t, t + kFinBlock, t + 2 kFinBlock, ... in that
+    // order; sixteen loads in flight per round trip
+    for (; t < ntiles; t += 16 * kFinBlock) {
+        double2 a[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) a[k] = t + k * kFinBlock < ntiles ? p2[t + k * kFinBlock] : double2{0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (t + k * kFinBlock < ntiles) {
+                s += a[k].x;
+                mx = fmax(mx, a[k].y);
+            }
     }
     s = wave_sum(s);
     mx = wave_max(mx);
