@@ -28,9 +28,10 @@ field unchanged; closed-form asymptotic rate of line Gauss-Seidel; the rate
 of relaxation after the line solve (form 'A', ascending and zebra rows) at
 w = 1.3, 1.5, 1.8 and the block optimum against Young's formula; converged
 solutions against the dense direct solve; the paper's printed iteration count
-for SLOR at w = 1 on the chamber.  The paper's ADI and SLORB counts at their
-optimal w (33, 55) are reported, not gated: parity unpinned (the ADI
-relaxation placement is not printed).
+for SLOR at w = 1 on the chamber; the paper's ADI and SLORB counts at their
+optimal w (33 at 1.3, 55 at 1.25), reproduced exactly with the relaxation
+inside the line system (the ADI placement the paper does not print; the
+placement after the solve does not reproduce 33).
 """
 from __future__ import annotations
 
