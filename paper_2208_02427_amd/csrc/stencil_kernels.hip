@@ -230,21 +230,24 @@ hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int bloc
 
 // ------------------------------------------------------- field upload/copy
 // Dense (m-pitched) FP64 field -> one or two pitched fields (perimeter included).
+// Workgroups walk rows, threads the row's columns (no index division).
 __global__ __launch_bounds__(kBlock) void k_write_field(const double* __restrict__ src, double* __restrict__ d0,
                                                         double* __restrict__ d1, int m, int n, int P) {
-    const size_t total = (size_t)m * n;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
-        const size_t j = k / (size_t)m, i = k - j * (size_t)m;
-        const double v = src[k];
-        d0[j * P + i] = v;
-        if (d1 != nullptr) d1[j * P + i] = v;
+    for (int j = blockIdx.x; j < n; j += gridDim.x) {
+        const double* s = src + (size_t)j * m;
+        double* a = d0 + (size_t)j * P;
+        double* b = d1 != nullptr ? d1 + (size_t)j * P : nullptr;
+        for (int i = threadIdx.x; i < m; i += blockDim.x) {
+            const double v = s[i];
+            a[i] = v;
+            if (b != nullptr) b[i] = v;
+        }
     }
 }
 
 hipError_t launch_write_field(const double* src, double* d0, double* d1, int m, int n, int P, hipStream_t s) {
-    const size_t total = (size_t)m * n;
-    int nb = (int)std::min<size_t>((total + kBlock - 1) / kBlock, 8192);
-    if (nb < 1) nb = 1;
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const int nb = std::min(n, 16384);
     k_write_field<<<nb, kBlock, 0, s>>>(src, d0, d1, m, n, P);
     return hipGetLastError();
 }
