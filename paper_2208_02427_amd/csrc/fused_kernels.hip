@@ -35,7 +35,10 @@ void k_fused(SweepArgs<T> A) {
     X(SW_RESTRICT) X(SW_RESTRICT | SW_F) X(SW_RESTRICT | SW_ZERO | SW_F) X(SW_RESTRICT | SW_NORM) \
     X(SW_RESTRICT | SW_NORM | SW_F) X(SW_RESTRICT | SW_TWO) X(SW_RESTRICT | SW_TWO | SW_F)       \
     X(SW_RESTRICT | SW_TWO | SW_ZERO | SW_F) X(SW_RESTRICT | SW_TWO | SW_NORM)                    \
-    X(SW_RESTRICT | SW_TWO | SW_NORM | SW_F) X(SW_DEF | SW_PROLONG | SW_TWO | SW_F)
+    X(SW_RESTRICT | SW_TWO | SW_NORM | SW_F) X(SW_DEF | SW_PROLONG | SW_TWO | SW_F)                  \
+    X(SW_PROBE | SW_RESTRICT | SW_TWO | SW_NORM) X(SW_PROBE | SW_RESTRICT | SW_TWO | SW_NORM | SW_F)  \
+    X(SW_PROBE | SW_RESTRICT | SW_NORM) X(SW_PROBE | SW_RESTRICT | SW_NORM | SW_F)                \
+    X(SW_PROBE | SW_TWO | SW_NORM) X(SW_PROBE | SW_TWO | SW_NORM | SW_F)
 
 template <typename T, int V>
 static hipError_t launch_fused_v(const SweepArgs<T>& a, int flags, hipStream_t s) {

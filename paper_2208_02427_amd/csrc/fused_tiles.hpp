@@ -152,6 +152,12 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
         }
         copy<T, V>(R.bo, R.st[0].c);
     }
+    if constexpr ((FL & SW_PROBE) != 0) {
+        // norms only: move the input rows the norm reads, no stage work
+        copy<T, V>(R.st[0].c, d);
+        copy<T, V>(R.st[0].fc, fd);
+        return;
+    }
 
     T o[V], fo[V];
     rb_push<T, V, JP>(R.st[0], d, fd, o, fo, j, A.n, wm, cx, cy, inv_d);

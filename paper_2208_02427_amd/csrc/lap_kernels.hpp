@@ -174,6 +174,8 @@ enum : int {
     SW_PONLY = 128,  // with SW_PROLONG: only u_in + P(ec), no colour updates (u_out may equal u_in:
                      // every stored value depends on its own node only); the multigrid correction
                      // step when the smoother is zebra line relaxation
+    SW_PROBE = 256,  // with SW_NORM: the input's residual norms only, exactly as the pass with the
+                     // other flags computes them (same tiles, walk and order); nothing is stored
 };
 
 template <typename T>
@@ -311,7 +313,10 @@ hipError_t launch_batch_subtree(int dt, const struct BatchItem* items, int count
 // allow dynamic LDS up to `bytes` for the subtree kernels (once per device)
 hipError_t subtree_set_lds_limit(int bytes);
 // Sum the per-tile partials in a fixed order and run the stopping test.
-// mode 0: stopping test of a solve; mode 1: write norms only (out2 = {sum, max}).
+// mode 0: stopping test of a solve; mode 1: write norms only (out2 = {sum, max});
+// mode 2: a probe of the test the next step opens with: recorded (and the
+// solve stopped) only if it ends the solve, else the control block is left
+// as it was.
 hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, double* out2, int mode,
                            hipStream_t s);
 // Reset a control block for a new solve (stream-ordered, graph-safe).

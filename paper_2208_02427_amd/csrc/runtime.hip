@@ -668,6 +668,7 @@ int fused_halo(int flags) { return ((flags & SW_TWO) ? 4 : 2) + ((flags & SW_RES
 // (two-sweep passes with the prolongation and without any transfer, as red-black
 // SOR runs them, are tuned apart: their best tilings differ)
 int fused_class(int flags) {
+    if (flags & SW_PROBE) return KC_RESIDUAL;   // norms only: timed with the residual-norm kernels
     if (flags & SW_RESTRICT) return KC_PRE;
     return (flags & SW_PROLONG) ? KC_TWO : KC_TWO_PLAIN;
 }
@@ -675,6 +676,7 @@ bool is_fused(int flags) { return (flags & (SW_TWO | SW_RESTRICT)) != 0; }
 
 // Algorithmic bytes per interior node of a sweep or fused pass.
 double sweep_bytes_per_node(int flags, int sz) {
+    if (flags & SW_PROBE) return ((flags & SW_F) ? 2.0 : 1.0) * sz;   // reads u (and f) only
     double per = (flags & SW_ZERO) ? 1.0 : 2.0;
     if (flags & SW_F) per += 1.0;
     if (flags & SW_PROLONG) per += 0.25;
@@ -705,9 +707,9 @@ hipError_t enq_fused(lap_grid* g, int l, const T* in, T* out, const T* f, const 
                          [&]() { return launch_fused<T>(a, flags, g->ctx->stream); });
 }
 
-hipError_t enq_finalize(lap_grid* g, int ntiles) {
+hipError_t enq_finalize(lap_grid* g, int ntiles, int mode = 0) {
     return g->ctx->timed(KC_FINALIZE, false, 16.0 * ntiles, [&]() {
-        return launch_finalize(g->partials, ntiles, g->ctrl, nullptr, 0, g->ctx->stream);
+        return launch_finalize(g->partials, ntiles, g->ctrl, nullptr, mode, g->ctx->stream);
     });
 }
 
@@ -807,6 +809,8 @@ struct Op {
 };
 
 constexpr long KEY_HEAD = 10;
+// Op.parity of a finalisation that probes the test the next step opens with
+constexpr int kProbeFinalize = 2;
 // (the stopping test's finalise must sit between the first and the second
 // pre-smoothing sweep: keys of a grid increase along its own operation order)
 inline long key_pre(int l, int k) { return 1000 + 100L * l + 2L * k; }
@@ -1399,7 +1403,7 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
                 return enq_coarse<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.out);
             return enq_coarse<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.out);
         case OP_FINALIZE:
-            return enq_finalize(g, norm_partials(g->geo[0].m, g->geo[0].n, op.flags));
+            return enq_finalize(g, norm_partials(g->geo[0].m, g->geo[0].n, op.flags), op.parity == kProbeFinalize ? 2 : 0);
         case OP_RESNORM:
             return enq_residual_norm<double>(g, l, (const double*)op.in, (const double*)op.f);
         case OP_DEFECT:
@@ -1458,7 +1462,17 @@ lap_status init_ctrl(lap_grid* g, const lap_opts& o, int step) {
 // whole speculative step of launches that exit at once (about 0.1 ms for a
 // multigrid cycle of an 8193^2 grid); a wrong prediction costs one host
 // round trip.
-lap_status drive(lap_grid* g, int max_steps, const std::function<hipError_t(int)>& step, Ctrl& out) {
+//
+// A solve that can probe (FP64 multigrid) does more once the tests predict,
+// two steps ahead of the last one read, that the test step s opens with
+// will end the solve: it first enqueues that test alone (the norms-only
+// version of the step's first pass and a finalisation that records the test
+// only if it ends the solve) and reads it.  If it ends the solve, the step's
+// sweeps, its restriction and the rest of its cycle are never enqueued;
+// otherwise the full step follows and repeats the same test (same norms,
+// same control block), so results and counts do not depend on probing.
+lap_status drive(lap_grid* g, int max_steps, const std::function<hipError_t(int)>& step, Ctrl& out,
+                 const std::function<hipError_t(int, bool*)>* probe = nullptr) {
     lap_ctx* c = g->ctx;
     int polled = -1;                 // last step whose control block was read
     double q_prev = -1.0, q_last = -1.0, tol = 0.0;
@@ -1481,6 +1495,24 @@ lap_status drive(lap_grid* g, int max_steps, const std::function<hipError_t(int)
             q_last * (q_last / q_prev) < 0.5 * tol) {
             HIPCHK(poll(s - 1));
             if (stop) break;
+        }
+        if (probe != nullptr && s >= 2 && polled >= s - 2 && q_prev > 0.0 && q_last > 0.0 && q_last < q_prev) {
+            double qs = q_last;
+            for (int k = polled; k < s; ++k) qs *= q_last / q_prev;
+            bool did = false;
+            if (qs < 0.5 * tol) {
+                c->rec_step = s;
+                hipError_t e = (*probe)(s, &did);
+                if (e != hipSuccess) return fail(LAP_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+            }
+            if (did) {
+                HIPCHK(hipMemcpyAsync(&c->pinned[s & 1], g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+                HIPCHK(hipEventRecord(c->poll_ev[s & 1], c->stream));
+                if (polled < s - 1) HIPCHK(poll(s - 1));
+                if (stop) break;
+                HIPCHK(hipEventSynchronize(c->poll_ev[s & 1]));
+                if (c->pinned[s & 1].done) break;   // the probe ended the solve
+            }
         }
         c->rec_step = s;
         hipError_t e = step(s);
@@ -1778,6 +1810,28 @@ hipError_t step(lap_grid* g, const lap_opts& o, int part = PART_ALL) {
     return exec_ops(g, ops);
 }
 
+// The test FP64 multigrid step s opens with, as a probe: the step's first
+// (fused) pre-smoothing pass with SW_PROBE, which computes the norms of the
+// incoming iterate exactly as that pass does and stores nothing, and a
+// finalisation that records the test only if it ends the solve.  Empty when
+// the step does not open with such a pass (nothing to save then).
+std::vector<Op> probe_ops(lap_grid* g, const lap_opts& o, int s) {
+    std::vector<Op> ops;
+    if (o.method != LAP_MG || o.precision != LAP_FP64 || o.smoother != LAP_SMOOTH_RB || (o.fmg && s == 0))
+        return ops;
+    plan_step(g, o, s, PART_HEAD, ops);
+    if (ops.size() != 2 || ops[0].kind != OP_SWEEP || !(ops[0].flags & SW_NORM) || !is_fused(ops[0].flags) ||
+        ops[1].kind != OP_FINALIZE) {
+        ops.clear();
+        return ops;
+    }
+    ops[0].flags |= SW_PROBE;
+    ops[0].out = nullptr;
+    ops[0].bc = nullptr;
+    ops[1].parity = kProbeFinalize;
+    return ops;
+}
+
 // The buffer holding the tested iterate (the solution) at the end of a solve.
 int result_buffer(lap_grid* g, const lap_opts& o, const Ctrl& h) {
     if (o.method == LAP_SOR_RB) return ((h.checks - 1) % 2) * ((int)sor_passes(g->ctx, o.check_every).size() % 2);
@@ -1862,7 +1916,12 @@ lap_status solve_one(lap_grid* g, const lap_opts& o, lap_info* info) {
     lap_ctx* c = g->ctx;
     c->rec_solve = c->timing ? c->solve_serial++ : -1;
     Ctrl h{};
-    st = drive(g, max_steps(o) + 1, [&](int) -> hipError_t { return step(g, o); }, h);
+    const std::function<hipError_t(int, bool*)> probe = [&](int s, bool* did) -> hipError_t {
+        const std::vector<Op> ops = probe_ops(g, o, s);
+        *did = !ops.empty();
+        return ops.empty() ? hipSuccess : exec_ops(g, ops);
+    };
+    st = drive(g, max_steps(o) + 1, [&](int) -> hipError_t { return step(g, o); }, h, &probe);
     if (c->timing && st == LAP_OK) c->drop_speculative(c->rec_solve, h.checks - 1);
     c->rec_solve = -1;
     if (st != LAP_OK) return st;

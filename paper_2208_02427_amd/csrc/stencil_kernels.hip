@@ -150,7 +150,7 @@ template hipError_t launch_coarse<float>(const CoarseArgs<float>&, hipStream_t);
 
 __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* partials, int ntiles, Ctrl* ctrl,
                                                      double* out2, int mode) {
-    if (mode == 0 && ctrl->done) return;
+    if (mode != 1 && ctrl->done) return;
     __shared__ double ss[kFinBlock / 64], sm[kFinBlock / 64];
     finalize_block(partials, ntiles, ctrl, out2, mode, ss, sm);
 }

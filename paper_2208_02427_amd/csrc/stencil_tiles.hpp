@@ -865,24 +865,29 @@ __device__ __forceinline__ void finalize_block(const double* partials, int ntile
         return;
     }
     const double res = sqrt(sum);
-    if (ctrl->checks == 0) ctrl->r0 = res;
-    const double r0 = ctrl->r0;
+    const double r0 = ctrl->checks == 0 ? res : ctrl->r0;
+    const double rel = r0 > 0.0 ? res / r0 : 0.0;
+    const double q = ctrl->stop == 0 ? rel : m;
+    int status = 1;   // 1: the solve goes on
+    if (!isfinite(res) || !isfinite(m) || (r0 > 0.0 && res > 1e6 * r0))
+        status = -4;   // LAP_EDIVERGED
+    else if (q < ctrl->tol || res == 0.0)
+        status = 0;
+    else if (ctrl->iters >= ctrl->max_iter)
+        status = -3;   // LAP_ENOTCONV
+    // mode 2 (a probe of the test the next step opens with): only a test
+    // that ends the solve is recorded; otherwise that step repeats it
+    if (mode == 2 && status == 1) return;
+    ctrl->r0 = r0;
     ctrl->res_l2 = res;
     ctrl->res_inf = m;
-    ctrl->rel = r0 > 0.0 ? res / r0 : 0.0;
+    ctrl->rel = rel;
     ctrl->checks += 1;
-    const double q = ctrl->stop == 0 ? ctrl->rel : m;
-    if (!isfinite(res) || !isfinite(m) || (r0 > 0.0 && res > 1e6 * r0)) {
-        ctrl->done = 1;
-        ctrl->status = -4;   // LAP_EDIVERGED
-    } else if (q < ctrl->tol || res == 0.0) {
-        ctrl->done = 1;
-        ctrl->status = 0;
-    } else if (ctrl->iters >= ctrl->max_iter) {
-        ctrl->done = 1;
-        ctrl->status = -3;   // LAP_ENOTCONV
-    } else {
+    if (status == 1) {
         ctrl->iters += ctrl->step > 0 ? ctrl->step : 1;
+    } else {
+        ctrl->done = 1;
+        ctrl->status = status;
     }
 }
 

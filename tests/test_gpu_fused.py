@@ -12,7 +12,7 @@ from oracle import grid as ogrid
 
 pytestmark = pytest.mark.gpu
 
-KC_PRE, KC_TWO = 10, 11
+KC_PRE, KC_TWO, KC_RESIDUAL = 10, 11, 8
 
 
 def _run(lap, torch, prob, fuse, sub=-1, tiling=None, **kw):
@@ -139,9 +139,12 @@ def test_fused_stops_and_restarts(max_iter, tol):
 @pytest.mark.parametrize("mode", [1, 2])
 def test_timing_counts_only_full_work_launches(mode):
     """Kernel statistics of a solve hold exactly the launches before and
-    including the deciding stopping test: one fused pre pass per cycle plus
-    the final test, one post pass per cycle (speculative launches after the
-    device stopped are left out).  Mode 2 times the finest level only."""
+    including the deciding stopping test: one fused pre pass per cycle, one
+    post pass per cycle, and the final test (speculative launches after the
+    device stopped are left out).  The final test is the norms-only probe of
+    the pre pass (timed with the residual-norm kernels) once the tests predict
+    it ends the solve, as on this geometric convergence.  Mode 2 times the
+    finest level only."""
     torch, lap = need_gpu()
     p = W.square_problem(513, seed=2)
     ctx = lap.Context(arena_bytes=256 << 20)
@@ -155,7 +158,9 @@ def test_timing_counts_only_full_work_launches(mode):
         k = info["iterations"]
         pre = ctx.kernel_stats(KC_PRE, fine_only=True)
         two = ctx.kernel_stats(KC_TWO, fine_only=True)
-        assert pre["launches"] == k + 1 and two["launches"] == k
+        probe = ctx.kernel_stats(KC_RESIDUAL, fine_only=True)
+        assert probe["launches"] == 1
+        assert pre["launches"] == k and two["launches"] == k
         assert pre["device_ms"] > 0 and two["device_ms"] > 0
         allp = ctx.kernel_stats(KC_PRE)
         assert allp["launches"] > pre["launches"]          # coarse levels counted too
