@@ -34,7 +34,9 @@ interpolation reproduce linear fields exactly and satisfy the adjoint
 identity 4 <FW r, e>_c = <r, P e>_f; the V-cycle leaves discretely harmonic
 fields unchanged and converges to the DST solution; its asymptotic factor is
 below 0.15 and its cycle count to 1e-10 does not grow with the grid
-(h-independence); the mixed loop reaches the FP64 solution.
+(h-independence); the mixed loop reaches the FP64 solution; with several
+FP32 cycles per defect correction its residual after each step follows the
+FP64 cycle history at every inner-th cycle.
 """
 from __future__ import annotations
 
@@ -137,16 +139,21 @@ def vcycle(levels, l: int, u: np.ndarray, b: np.ndarray | None, nu1: int = 2, nu
         smooth()
 
 
-def mixed_step(psi: np.ndarray, f: np.ndarray | None, levels, nu1=2, nu2=2, omega_s=1.0, smoother="rb"):
+def mixed_step(psi: np.ndarray, f: np.ndarray | None, levels, nu1=2, nu2=2, omega_s=1.0, smoother="rb",
+               inner: int = 1):
     """One outer step of the mixed-precision defect correction:
-        r64 = f - L_h psi64;  b32 = fl32(r64);  e32 = FP32 V-cycle from 0;
+        r64 = f - L_h psi64;  b32 = fl32(r64);
+        e32 = `inner` FP32 V-cycles on L_h e = b32, the first from 0;
         psi64 += fl64(e32).
-    Returns the FP64 residual taken at the start of the step."""
+    (Eqs. (13)-(15) solve the error equation with the cycle; more cycles per
+    correction solve it more accurately before the FP64 update.)  Returns the
+    FP64 residual taken at the start of the step."""
     m, n, dx, dy = levels[0]
     r = residual(psi, f, dx, dy)
     b32 = r.astype(np.float32)
     e32 = np.zeros_like(b32)
-    vcycle(levels, 0, e32, b32, nu1, nu2, omega_s, np.float32, smoother)
+    for _ in range(inner):
+        vcycle(levels, 0, e32, b32, nu1, nu2, omega_s, np.float32, smoother)
     psi += e32.astype(np.float64)
     return r
 

@@ -104,7 +104,8 @@ def mg_solve(psi0: np.ndarray, f, dx: float, dy: float, tol: float = 1e-10, max_
 
 
 def mixed_solve(psi0: np.ndarray, f, dx: float, dy: float, tol: float = 1e-10, max_steps: int = 100,
-                nu1: int = 2, nu2: int = 2, omega_s: float = 1.0, max_levels: int = 64, smoother: str = "rb"):
+                nu1: int = 2, nu2: int = 2, omega_s: float = 1.0, max_levels: int = 64, smoother: str = "rb",
+                inner: int = 1):
     """Mixed-precision defect correction until ||r||_2/||r_0||_2 < tol (the
     test is taken on the FP64 residual before each step)."""
     n, m = psi0.shape
@@ -118,5 +119,5 @@ def mixed_solve(psi0: np.ndarray, f, dx: float, dy: float, tol: float = 1e-10, m
             hist.append(q)
         if not np.isfinite(q) or q < tol or k == max_steps:
             return u, k, hist
-        multigrid.mixed_step(u, f, levels, nu1, nu2, omega_s, smoother)
+        multigrid.mixed_step(u, f, levels, nu1, nu2, omega_s, smoother, inner)
     return u, max_steps, hist

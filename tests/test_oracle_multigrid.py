@@ -156,6 +156,26 @@ def test_mixed_reaches_fp64_solution(N):
     assert np.allclose(hm, h64, rtol=1e-4)
 
 
+@pytest.mark.parametrize("inner", [2, 3])
+def test_mixed_inner_cycles(inner):
+    """`inner` FP32 V-cycles per defect correction, each from the previous
+    one's correction (the first from 0): on the linear error equation that is
+    `inner` V-cycles applied to the iterate, so the outer residual after step
+    k follows the FP64 cycle history at cycle inner * (k + 1) (to the FP32
+    rounding), and the loop reaches the FP64 solution in about 1 / inner of
+    the steps.  Restarting a later cycle from 0, or skipping one, would leave
+    one cycle's factor per step."""
+    p = W.square_problem(129, seed=3, bumps=True)
+    u64, k64, h64 = solve.mg_solve(p.psi0, p.f, p.dx, p.dy, tol=1e-10)
+    um, km, hm = solve.mixed_solve(p.psi0, p.f, p.dx, p.dy, tol=1e-10, inner=inner)
+    assert hm[-1] < 1e-10
+    for k in range(len(hm) - 1):
+        assert hm[k] == pytest.approx(h64[inner * (k + 1) - 1], rel=1e-2)
+    assert km <= (k64 + inner - 1) // inner + 1
+    ex = direct.dst_solve(p.m, p.n, p.dx, p.dy, p.psi0, p.f)
+    assert np.max(np.abs(um - ex)) <= 1e-8 * np.max(np.abs(ex))
+
+
 def test_mixed_inner_cycle_is_float32():
     p = W.square_problem(33, seed=3, bumps=True)
     lv = multigrid.hierarchy(p.m, p.n, p.dx, p.dy)
