@@ -143,11 +143,16 @@ typedef struct lap_opts {
                            * coarsest solve, bilinear interpolation of each coarse solution,
                            * one V-cycle per level); it counts as the first iteration, the
                            * stopping test's r_0 is the residual of the incoming field      */
+    int32_t inner;        /* MIXED, red-black smoother, one grid (lap_solve): FP32 V-cycles
+                           * per FP64 defect correction, 1..8 (default 1); the first starts
+                           * from zero, each next from the previous correction.  LAP_EINVAL
+                           * outside 1..8, for inner > 1 with FP64 or zebra smoothing, and
+                           * for inner != 1 in lap_solve_batch                              */
 } lap_opts;
 
 /* Fill *o with the defaults: MG, FP64, omega 1, tol 1e-10, max_iter 100,
  * REL_L2, nu1 = nu2 = 2, check_every 1, ADI relax-after, use_graph 1,
- * smoother LAP_SMOOTH_RB, fmg 0. */
+ * smoother LAP_SMOOTH_RB, fmg 0, inner 1. */
 void lap_opts_default(lap_opts* o);
 
 /* ---------------------------------------------------------------- context */

@@ -62,7 +62,7 @@ SMOOTHERS = {"rb": LAP_SMOOTH_RB, "zebra": LAP_SMOOTH_ZEBRA}
 
 
 def opts(method="mg", precision="fp64", omega=1.0, tol=1e-10, max_iter=100, stop="rel_l2", nu1=2, nu2=2,
-         check_every=1, adi_form="after", use_graph=True, smoother="rb", fmg=False) -> LapOpts:
+         check_every=1, adi_form="after", use_graph=True, smoother="rb", fmg=False, inner=1) -> LapOpts:
     o = LapOpts()
     lib().lap_opts_default(ctypes.byref(o))
     o.method = METHODS[method] if isinstance(method, str) else int(method)
@@ -80,6 +80,7 @@ def opts(method="mg", precision="fp64", omega=1.0, tol=1e-10, max_iter=100, stop
     o.use_graph = 1 if use_graph else 0
     o.smoother = SMOOTHERS[smoother] if isinstance(smoother, str) else int(smoother)
     o.fmg = 1 if fmg else 0
+    o.inner = int(inner)
     return o
 
 

@@ -44,7 +44,7 @@ class LapOpts(ctypes.Structure):
     _fields_ = [("method", c_int32), ("precision", c_int32), ("omega", c_double), ("tol", c_double),
                 ("max_iter", c_int32), ("stop", c_int32), ("nu1", c_int32), ("nu2", c_int32),
                 ("check_every", c_int32), ("adi_form", c_int32), ("use_graph", c_int32), ("smoother", c_int32),
-                ("fmg", c_int32)]
+                ("fmg", c_int32), ("inner", c_int32)]
 
 
 _P = c_void_p

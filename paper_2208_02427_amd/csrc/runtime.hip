@@ -1180,6 +1180,33 @@ bool postdef_ok(lap_grid* g, const lap_opts& o) {
 // steps alternate between l32[0].b and rhs2.  Step 0 corrects nothing yet
 // and works in place on psi[0] (no copy of the iterate); step s >= 1 reads
 // psi[(s + 1) % 2] and writes psi[s % 2].
+// The FP32 cycles of a mixed step on the error equation of H (level 0's
+// right-hand side set): o.inner V-cycles, the first from zero, each next from
+// the previous correction (level 0 then carries an iterate, in whichever of
+// its two buffers the previous cycle left it).  With dp the last cycle stops
+// before its level-0 post-smoothing, described in *dp.  Returns the level-0
+// buffer (0/1 of g->l32[0].u) holding the correction; dp->in is given the
+// same way.
+int plan_inner_cycles(lap_grid* g, const lap_opts& o, HierView<float> H, std::vector<Op>& ops,
+                      DeferredPost* dp = nullptr) {
+    float* B[2] = {g->l32[0].u[0], g->l32[0].u[1]};
+    int base = 0;   // buffer of g->l32[0].u that H.u0[0] is
+    int res = 0;
+    for (int c = 0; c < o.inner; ++c) {
+        const bool last = c == o.inner - 1;
+        if (c > 0) {
+            H.zero_start0 = false;
+            H.u0[0] = B[res];
+            H.u1[0] = B[1 - res];
+            base = res;
+        }
+        const int r = plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops, last ? dp : nullptr);
+        res = r == 0 ? base : 1 - base;
+        if (last && dp != nullptr && dp->in >= 0) dp->in = dp->in == 0 ? base : 1 - base;
+    }
+    return res;
+}
+
 void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part, std::vector<Op>& ops) {
     const bool first = s == 0;
     const int in_idx = first ? 0 : (s + 1) % 2;
@@ -1196,10 +1223,10 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
                 push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr,
                                 nullptr, 0.0);
             } else {
-                // the previous step's cycle, planned again only to find its deferred pass
+                // the previous step's cycles, planned again only to find its deferred pass
                 std::vector<Op> prev;
                 H.b[0] = R[1 - par];
-                plan_vcycle<float>(g, H, 0, o, false, PART_ALL, prev, &dp);
+                plan_inner_cycles(g, o, H, prev, &dp);
                 push_op<float>(ops, KEY_HEAD, OP_POSTDEF, 0, kPostDefFlags, pin, pout, R[1 - par], dp.ec, R[par],
                                o.omega, dp.in);
                 push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_POSTDEF, nullptr, nullptr, nullptr, nullptr,
@@ -1208,7 +1235,7 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
         }
         if (part == PART_HEAD) return;
         H.b[0] = R[par];
-        plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops, &dp);
+        plan_inner_cycles(g, o, H, ops, &dp);
         return;
     }
     if (o.smoother == LAP_SMOOTH_ZEBRA) {
@@ -1237,7 +1264,7 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
     }
     if (part == PART_HEAD) return;
     HierView<float> H = view32(g);
-    plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops);
+    plan_inner_cycles(g, o, H, ops);
 }
 
 // Full multigrid start (FP64): the source full-weighted down the hierarchy
@@ -1559,6 +1586,9 @@ lap_status validate_opts(lap_grid* g, const lap_opts& o) {
     if (!(o.omega > 0.0 && o.omega < 2.0)) return fail(LAP_EINVAL, "omega must lie in (0, 2)");
     if (o.max_iter < 0) return fail(LAP_EINVAL, "max_iter must be >= 0");
     if (!(o.tol >= 0.0)) return fail(LAP_EINVAL, "tol must be >= 0");
+    if (o.inner < 1 || o.inner > 8) return fail(LAP_EINVAL, "inner must lie in 1..8");
+    if (o.inner > 1 && (o.precision != LAP_MIXED || o.smoother != LAP_SMOOTH_RB))
+        return fail(LAP_EINVAL, "inner > 1 needs LAP_MIXED and the red-black smoother");
     if (is_paper_method(o.method)) {
         if (o.stop != LAP_STOP_REL_L2 && o.stop != LAP_STOP_RES_INF && o.stop != LAP_STOP_DELTA)
             return fail(LAP_EINVAL, "unknown stopping rule");
@@ -1660,8 +1690,12 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
         if (st != LAP_OK) return st;
     }
     g->step_idx = 0;
-    g->e_idx = vcycle_result_index(g->ctx, o);
     g->pdef = postdef_ok(g, o);   // fixed for the whole solve
+    g->e_idx = vcycle_result_index(g->ctx, o);
+    if (o.method == LAP_MG && o.precision == LAP_MIXED && o.inner > 1 && !g->l32.empty()) {
+        std::vector<Op> dry;   // where the step's last FP32 cycle leaves the correction
+        g->e_idx = plan_inner_cycles(g, o, view32(g), dry);
+    }
     // the two-buffer methods need both buffers equal when they start
     if (g->psi1_stale && o.method != LAP_ADI) {
         HIPCHK(hipMemcpyAsync(g->psi[1], g->psi[0], (size_t)g->n * g->P * 8, hipMemcpyDeviceToDevice,
@@ -1694,8 +1728,8 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
         if (o.precision == LAP_FP64)
             snprintf(key, sizeof key, "mg64:%d:%d:%d:%.17g", o.smoother, o.nu1, o.nu2, o.omega);
         else
-            snprintf(key, sizeof key, "mixed%s:%d:%d:%d:%.17g", g->pdef ? "+pd" : "", o.smoother, o.nu1, o.nu2,
-                     o.omega);
+            snprintf(key, sizeof key, "mixed%s:%d:%d:%d:%d:%.17g", g->pdef ? "+pd" : "", o.smoother, o.nu1, o.nu2,
+                     o.inner, o.omega);
         const bool have = g->graph != nullptr && g->graph_key == key;
         auto& seen = g->graph_seen;
         const bool again = std::find(seen.begin(), seen.end(), std::string(key)) != seen.end();
@@ -1966,6 +2000,7 @@ void lap_opts_default(lap_opts* o) {
     o->adi_form = LAP_ADI_RELAX_AFTER;
     o->use_graph = 1;
     o->smoother = LAP_SMOOTH_RB;
+    o->inner = 1;
 }
 
 lap_status lap_ctx_create(void* dev_arena, size_t arena_bytes, void* hip_stream, lap_ctx** out) {
@@ -3055,6 +3090,7 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
     if (is_paper_method(o->method))
         return fail(LAP_EINVAL, "the paper-order methods solve one grid at a time (lap_solve)");
     if (o->fmg) return fail(LAP_EINVAL, "the full multigrid start runs on one grid at a time (lap_solve)");
+    if (o->inner != 1) return fail(LAP_EINVAL, "batches take one FP32 cycle per defect correction (inner = 1)");
     const double t0 = now_s();
     for (int k = 0; k < count; ++k) {
         if (!grids[k] || grids[k]->ctx != c) return fail(LAP_EINVAL, "grid does not belong to this context");

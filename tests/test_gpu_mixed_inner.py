@@ -1,0 +1,100 @@
+"""Mixed precision with several FP32 V-cycles per FP64 defect correction
+(lap_opts.inner) against the oracle.
+
+Each outer step forms r = f - L_h psi in FP64, runs `inner` FP32 V(2,2)
+cycles on L_h e = fl32(r) (the first from zero, each next from the previous
+correction) and adds fl64(e) (the defect correction around Eqs. (13)-(15)).
+The oracle is oracle.multigrid.mixed_step(inner=...).  Steps agree within 3x
+the oracle's own FP32 rounding effect at that step (its distance from the same
+steps with FP64 cycles: up to 1.2e-5 of the field after the first step, 1e-11
+after the third), with the fused post-smoothing + defect pass (default) and
+without it (fusion off); a solve
+to 1e-10 takes the oracle's step count (within one) and reaches its
+residual; a graph replay gives the same bits."""
+import numpy as np
+import pytest
+
+from gpu_helpers import need_gpu, say, to_dev, rand_problem, maxabs
+from oracle import multigrid as omg, grid as ogrid, solve as osolve
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(lap, fuse):
+    ctx = lap.Context(arena_bytes=512 << 20)
+    ctx.set_fusion(fuse)
+    return ctx
+
+
+@pytest.mark.parametrize("m,n", [(257, 193), (129, 65)])
+@pytest.mark.parametrize("inner", [2, 3])
+@pytest.mark.parametrize("fuse", [True, False])
+def test_inner_cycle_steps_vs_oracle(m, n, inner, fuse):
+    torch, lap = need_gpu()
+    psi, f, dx, dy = rand_problem(m, n, 13 * m + n + inner, dx=1.0 / (m - 1), dy=1.3 / (n - 1), source=True)
+    ctx = _ctx(lap, fuse)
+    g = ctx.grid(to_dev(torch, psi), to_dev(torch, f), dx, dy)
+    lv = omg.hierarchy(m, n, dx, dy)
+    ref = psi.copy()
+    ref64 = psi.copy()   # the same steps with FP64 inner cycles: the size of the FP32 rounding effect
+    for k in (1, 2, 3):
+        say("mixed inner steps", m, n, inner, fuse, k)
+        g.write(to_dev(torch, psi))
+        info = g.solve("mg", precision="mixed", inner=inner, tol=0.0, max_iter=k)
+        assert info["iterations"] == k
+        omg.mixed_step(ref, f, lv, 2, 2, inner=inner)
+        r = ogrid.residual(ref64, f, dx, dy)
+        e = np.zeros_like(r)
+        for _ in range(inner):
+            omg.vcycle(lv, 0, e, r, 2, 2, 1.0, np.float64, "rb")
+        ref64 += e
+        scale = float(np.max(np.abs(ref)))
+        noise = maxabs(ref, ref64)
+        got = maxabs(g.read().cpu().numpy(), ref)
+        # two FP32 evaluations of the same cycles differ by rounding order only: about as much as
+        # either differs from FP64 cycles; a cycle dropped or restarted from zero is ~1e-2 off
+        assert got <= 3.0 * noise + 1e-12 * scale, (k, got, noise)
+    g.destroy()
+    ctx.close()
+
+
+@pytest.mark.parametrize("inner", [2, 3])
+def test_inner_cycle_solve_to_tol(inner):
+    torch, lap = need_gpu()
+    m, n = 513, 257
+    psi, f, dx, dy = rand_problem(m, n, 41 + inner, dx=1.0 / 512, dy=1.0 / 256, source=True)
+    ctx = _ctx(lap, True)
+    g = ctx.grid(to_dev(torch, psi), to_dev(torch, f), dx, dy)
+    say("mixed inner solve", inner)
+    kw = dict(precision="mixed", inner=inner, tol=1e-10, max_iter=40)
+    infos, outs = [], []
+    for _ in range(3):   # the third solve replays the captured graph
+        g.write(to_dev(torch, psi))
+        infos.append(g.solve("mg", **kw))
+        outs.append(g.read().cpu().numpy())
+    assert all(i["status"] == 0 for i in infos)
+    assert infos[0]["iterations"] == infos[1]["iterations"] == infos[2]["iterations"]
+    assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[1], outs[2])
+    ref, kref, _ = osolve.mixed_solve(psi, f, dx, dy, tol=1e-10, inner=inner)
+    assert abs(infos[0]["iterations"] - kref) <= 1, (infos[0]["iterations"], kref)
+    r0 = ogrid.norm2(ogrid.residual(psi, f, dx, dy))
+    assert ogrid.norm2(ogrid.residual(outs[0], f, dx, dy)) / r0 < 1e-10 * 1.0001
+    assert maxabs(outs[0], ref) <= 1e-9 * max(1.0, float(np.max(np.abs(ref))))
+    g.destroy()
+    ctx.close()
+
+
+def test_inner_cycle_argument_errors():
+    torch, lap = need_gpu()
+    from paper_2208_02427_amd import LapError
+    ctx = _ctx(lap, True)
+    g = ctx.grid(to_dev(torch, np.zeros((17, 17))), None, 0.1, 0.1)
+    for kw in (dict(precision="mixed", inner=0), dict(precision="mixed", inner=9), dict(precision="fp64", inner=2),
+               dict(precision="mixed", inner=2, smoother="zebra", nu1=1, nu2=1)):
+        say("inner errors", kw)
+        with pytest.raises(LapError):
+            g.solve("mg", raise_on_fail=True, **kw)
+    with pytest.raises(LapError):
+        ctx.solve_batch([g], method="mg", precision="mixed", inner=2)
+    g.destroy()
+    ctx.close()
