@@ -27,7 +27,9 @@ Readings (the V-cycle figure is not available):
 
 Mixed precision (not in the paper): psi and the residual stay FP64; each
 outer step solves the error equation approximately by one FP32 V-cycle from
-a zero start and adds the FP32 correction to the FP64 iterate.
+a zero start (or `inner` cycles, each next from the previous correction) and
+adds the FP32 correction to the FP64 iterate.  How many cycles a step runs
+is the driver's choice (oracle.solve.mixed_solve).
 
 Pins (tests/test_oracle_multigrid.py): full weighting and bilinear
 interpolation reproduce linear fields exactly and satisfy the adjoint
@@ -36,7 +38,9 @@ fields unchanged and converges to the DST solution; its asymptotic factor is
 below 0.15 and its cycle count to 1e-10 does not grow with the grid
 (h-independence); the mixed loop reaches the FP64 solution; with several
 FP32 cycles per defect correction its residual after each step follows the
-FP64 cycle history at every inner-th cycle.
+FP64 cycle history at the cycles run so far; a last step shortened to one
+cycle (oracle.solve.one_cycle_suffices, pinned against its closed form)
+lands on the history one cycle further, with no more steps than without it.
 """
 from __future__ import annotations
 

@@ -103,21 +103,50 @@ def mg_solve(psi0: np.ndarray, f, dx: float, dy: float, tol: float = 1e-10, max_
     return u, max_cycles, hist
 
 
+# Safety factor of the one-cycle prediction below (a cycle's factor grows
+# slowly as the FP32 rounding floor nears, about 10-15% between steps).
+ONE_CYCLE_MARGIN = 1.5
+
+
+def one_cycle_suffices(q: float, q_prev: float, ran: int, tol: float) -> bool:
+    """Whether the step that opens with test value q (the one before it q_prev,
+    after a step of `ran` FP32 cycles) takes one cycle instead of `inner`:
+    with the per-cycle factor rho = (q / q_prev)^(1 / ran) measured on that
+    step, one cycle is predicted to pass the test, 1.5 q rho < tol.  Written
+    as q / q_prev < (tol / (1.5 q))^ran, with the power taken by repeated
+    multiplication (no root)."""
+    x = tol / (ONE_CYCLE_MARGIN * q)
+    p = 1.0
+    for _ in range(ran):
+        p *= x
+    return q / q_prev < p
+
+
 def mixed_solve(psi0: np.ndarray, f, dx: float, dy: float, tol: float = 1e-10, max_steps: int = 100,
                 nu1: int = 2, nu2: int = 2, omega_s: float = 1.0, max_levels: int = 64, smoother: str = "rb",
-                inner: int = 1):
+                inner: int = 1, schedule: list | None = None):
     """Mixed-precision defect correction until ||r||_2/||r_0||_2 < tol (the
-    test is taken on the FP64 residual before each step)."""
+    test is taken on the FP64 residual before each step).  With inner > 1 a
+    step runs `inner` FP32 V-cycles, or one where one_cycle_suffices() holds
+    for its test and the two before it (not for the first step); the cycles
+    each step ran are appended to `schedule` if given."""
     n, m = psi0.shape
     levels = multigrid.hierarchy(m, n, dx, dy, max_levels)
     u = np.array(psi0, dtype=np.float64, copy=True)
     r0 = norm2(residual(u, f, dx, dy))
     hist = []
+    q_prev, ran = None, 0
     for k in range(0, max_steps + 1):
         q = norm2(residual(u, f, dx, dy)) / r0 if r0 > 0 else 0.0
         if k > 0:
             hist.append(q)
         if not np.isfinite(q) or q < tol or k == max_steps:
             return u, k, hist
-        multigrid.mixed_step(u, f, levels, nu1, nu2, omega_s, smoother, inner)
+        c = inner
+        if inner > 1 and q_prev is not None and one_cycle_suffices(q, q_prev, ran, tol):
+            c = 1
+        multigrid.mixed_step(u, f, levels, nu1, nu2, omega_s, smoother, c)
+        if schedule is not None:
+            schedule.append(c)
+        q_prev, ran = q, c
     return u, max_steps, hist

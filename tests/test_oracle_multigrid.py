@@ -167,13 +167,53 @@ def test_mixed_inner_cycles(inner):
     one cycle's factor per step."""
     p = W.square_problem(129, seed=3, bumps=True)
     u64, k64, h64 = solve.mg_solve(p.psi0, p.f, p.dx, p.dy, tol=1e-10)
-    um, km, hm = solve.mixed_solve(p.psi0, p.f, p.dx, p.dy, tol=1e-10, inner=inner)
+    sch = []
+    um, km, hm = solve.mixed_solve(p.psi0, p.f, p.dx, p.dy, tol=1e-10, inner=inner, schedule=sch)
     assert hm[-1] < 1e-10
-    for k in range(len(hm) - 1):
-        assert hm[k] == pytest.approx(h64[inner * (k + 1) - 1], rel=1e-2)
+    assert len(sch) == km and all(c in (1, inner) for c in sch) and sch[0] == inner
+    cum = np.cumsum(sch)
+    for k in range(len(hm)):
+        if cum[k] <= len(h64):
+            assert hm[k] == pytest.approx(h64[cum[k] - 1], rel=1e-2)
     assert km <= (k64 + inner - 1) // inner + 1
     ex = direct.dst_solve(p.m, p.n, p.dx, p.dy, p.psi0, p.f)
     assert np.max(np.abs(um - ex)) <= 1e-8 * np.max(np.abs(ex))
+
+
+def test_one_cycle_rule_closed_form():
+    """one_cycle_suffices(q, q_prev, ran, tol) is 1.5 q rho < tol with rho the
+    ran-th root of q / q_prev, written without the root."""
+    for q, qp, ran in ((1e-9, 4e-7, 2), (1.5e-9, 4e-7, 2), (7.5e-10, 3.8e-7, 2), (1e-9, 1e-5, 3),
+                       (2e-9, 1e-7, 1), (5e-12, 1e-9, 2)):
+        rho = (q / qp) ** (1.0 / ran)
+        assert solve.one_cycle_suffices(q, qp, ran, 1e-10) == (1.5 * q * rho < 1e-10), (q, qp, ran)
+    assert solve.one_cycle_suffices(1e-9, 4e-7, 2, 1e-10)        # rho 0.05: 7.5e-11
+    assert not solve.one_cycle_suffices(1.5e-9, 4e-7, 2, 1e-10)  # rho 0.061: 1.4e-10
+
+
+@pytest.mark.parametrize("inner", [2, 3])
+def test_mixed_one_cycle_last_step(inner, monkeypatch):
+    """On 257^2 the last step's test predicts that one FP32 cycle passes the
+    test: the step runs one cycle (its residual is the FP64 cycle history at
+    the cycles run so far, not one step further), and the loop takes as many
+    steps as with `inner` cycles in every step.  With tol = 0 (a fixed step
+    count) no step is shortened."""
+    p = W.square_problem(257, seed=3, bumps=True)
+    u64, k64, h64 = solve.mg_solve(p.psi0, p.f, p.dx, p.dy, tol=1e-10)
+    sch = []
+    um, km, hm = solve.mixed_solve(p.psi0, p.f, p.dx, p.dy, tol=1e-10, inner=inner, schedule=sch)
+    assert sch[-1] == 1 and all(c == inner for c in sch[:-1])
+    assert hm[-1] == pytest.approx(h64[sum(sch) - 1], rel=1e-2)
+    assert 1e-11 < hm[-1] < 1e-10
+    monkeypatch.setattr(solve, "ONE_CYCLE_MARGIN", float("inf"))   # never one cycle
+    sch_full = []
+    _, kf, hf = solve.mixed_solve(p.psi0, p.f, p.dx, p.dy, tol=1e-10, inner=inner, schedule=sch_full)
+    assert kf == km and all(c == inner for c in sch_full)
+    assert hf[-1] < hm[-1] / 10
+    monkeypatch.undo()
+    sch0 = []
+    solve.mixed_solve(p.psi0, p.f, p.dx, p.dy, tol=0.0, max_steps=5, inner=inner, schedule=sch0)
+    assert sch0 == [inner] * 5
 
 
 def test_mixed_inner_cycle_is_float32():
