@@ -180,6 +180,30 @@ def test_mixed_inner_cycles(inner):
     assert np.max(np.abs(um - ex)) <= 1e-8 * np.max(np.abs(ex))
 
 
+def test_continuing_cycle_has_fp64_residual():
+    """A mixed step of two FP32 cycles on 513^2 lands within FP32 storage
+    noise (2e-7) of two FP64 V-cycles from the same iterate.  The second
+    cycle starts from the first one's smooth correction: with its level-0
+    residual in FP32 arithmetic the step is 20x farther (4e-6; on 8193^2 the
+    smooth error of the step is then that of one cycle)."""
+    p = W.square_problem(513, seed=2, bumps=True, bump_seed=3)
+    lv = multigrid.hierarchy(p.m, p.n, p.dx, p.dy)
+    u64 = p.psi0.copy()
+    for _ in range(2):
+        r = grid.residual(u64, p.f, p.dx, p.dy)
+        e = np.zeros_like(r)
+        multigrid.vcycle(lv, 0, e, r)
+        u64 += e
+    um = p.psi0.copy()
+    multigrid.mixed_step(um, p.f, lv, 2, 2, inner=2)
+    assert np.max(np.abs(um - u64)) < 1e-6
+    b32 = grid.residual(p.psi0, p.f, p.dx, p.dy).astype(np.float32)
+    e32 = np.zeros_like(b32)
+    for _ in range(2):   # both cycles with the FP32 residual
+        multigrid.vcycle(lv, 0, e32, b32, 2, 2, 1.0, np.float32)
+    assert np.max(np.abs(p.psi0 + e32.astype(np.float64) - u64)) > 2e-6
+
+
 def test_one_cycle_rule_closed_form():
     """one_cycle_suffices(q, q_prev, ran, tol) is 1.5 q rho < tol with rho the
     ran-th root of q / q_prev, written without the root."""
