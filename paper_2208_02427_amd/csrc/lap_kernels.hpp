@@ -157,7 +157,7 @@ struct Ctrl {
     int32_t done;       // nonzero: stop; every kernel of the solve becomes a no-op
     int32_t status;     // lap_status when done
     int32_t step;       // iterations between two tests (SOR / ADI check interval)
-    int32_t pad;
+    int32_t cycles;     // mixed steps with several FP32 cycles: cycles the last step runs
 };
 
 // Flags of the red-black sweep.
@@ -176,6 +176,9 @@ enum : int {
                      // step when the smoother is zebra line relaxation
     SW_PROBE = 256,  // with SW_NORM: the input's residual norms only, exactly as the pass with the
                      // other flags computes them (same tiles, walk and order); nothing is stored
+    SW_R64 = 512,    // with SW_RESTRICT, FP32: the residual and its full weighting in FP64 arithmetic
+                     // on the FP32 values (coefficients dcx, dcy, dd), the coarse right-hand side
+                     // rounded to FP32 (a cycle that continues from a smooth correction)
 };
 
 template <typename T>
@@ -219,6 +222,8 @@ struct RestrictArgs {
     int mc, nc, Pc;
     T cx, cy, d;
     Tiling tl;
+    int r64;            // FP32: residual and full weighting in FP64 arithmetic (as SW_R64)
+    double dcx, dcy, dd;
 };
 
 template <typename T>
@@ -317,8 +322,20 @@ hipError_t subtree_set_lds_limit(int bytes);
 // mode 2: a probe of the test the next step opens with: recorded (and the
 // solve stopped) only if it ends the solve, else the control block is left
 // as it was.
+// gate: when not null, the launch does nothing while gate->done is set (a
+// finalisation of one of two alternative step openings).
+// cyc (mode 0, mixed steps of up to `cycles & 255` FP32 V-cycles): after the
+// test, choose how many cycles the step runs, one or all, and write the
+// choice into the gate pair cyc[2 p], cyc[2 p + 1] (p = cycles >> 8):
+// cyc[2 p].done is set when the step runs one cycle (it gates the cycles
+// after the first and the next step's opening that finishes the last of
+// them), cyc[2 p + 1].done when it runs all (it gates the next step's
+// opening after a one-cycle step).  A test that ends the solve sets the done
+// flags of all four.  One cycle is chosen when, with the per-cycle factor
+// rho = (q / q_prev)^(1 / c) of the previous step's c cycles, 1.5 q rho < tol
+// (q: the test's quantity; never on the first test).
 hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, double* out2, int mode,
-                           hipStream_t s);
+                           hipStream_t s, const Ctrl* gate = nullptr, Ctrl* cyc = nullptr, int cycles = 0);
 // Reset a control block for a new solve (stream-ordered, graph-safe).
 hipError_t launch_ctrl_init(Ctrl* ctrl, double tol, int stop, int max_iter, int step, hipStream_t s);
 // The same for `count` control blocks (device array of pointers).

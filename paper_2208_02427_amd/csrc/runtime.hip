@@ -437,6 +437,8 @@ struct lap_grid {
     int adi_form = -1;
     bool psi1_stale = false;         // psi[1]'s interior lags psi[0] (after ADI, which works in place)
     Ctrl* ctrl = nullptr;
+    Ctrl* cyc = nullptr;             // four gates of mixed steps with several FP32 cycles (two per step parity)
+    Ctrl* op_ctrl = nullptr;         // while an operation is launched: the control block its kernels test
     double* partials = nullptr;
     int max_partials = 0;
     double* norm_out = nullptr;
@@ -447,6 +449,7 @@ struct lap_grid {
     double batch_t0 = 0.0;
     int step_idx = 0;                // next outer step of the running solve
     int e_idx = 0;                   // buffer of the last FP32 correction (mixed)
+    int e1_idx = 0;                  // buffer of the first cycle's correction (mixed, several cycles)
     // zebra line smoothing: segment tables of every smoothed level, rows then
     // columns (2 * kSegTab values per level), FP64 and FP32
     double* ztab64 = nullptr;
@@ -466,6 +469,10 @@ struct lap_grid {
 };
 
 namespace {
+
+// The control block whose done flag the kernels of the operation being
+// launched test: a gate of a mixed step while one is set, else the solve's.
+inline Ctrl* kctrl(const lap_grid* g) { return g->op_ctrl != nullptr ? g->op_ctrl : g->ctrl; }
 
 void* galloc(lap_grid* g, size_t bytes) {
     void* p = g->ctx->arena.alloc(bytes);
@@ -522,7 +529,7 @@ Footprint footprint(int m, int n, bool has_f, int flags) {
         fp.add(f0 * 8);
         fp.add(((size_t)4 * std::max(m, n) + 2 * kSegTab) * 8);
     }
-    fp.add(sizeof(Ctrl));
+    fp.add(5 * sizeof(Ctrl));
     fp.add(max_tiles(m, n) * 16);
     fp.add(16);
     return fp;
@@ -609,7 +616,7 @@ SubtreeArgs<T> subtree_args(const lap_grid* g, int l, T* out, const T* b, double
     const Coef cc = coef(g->geo.back().dx, g->geo.back().dy);
     a.ccx = cc.cx;
     a.ccy = cc.cy;
-    a.ctrl = g->ctrl;
+    a.ctrl = kctrl(g);
     return a;
 }
 
@@ -633,7 +640,7 @@ SweepArgs<T> sweep_args(lap_grid* g, int l, const T* in, T* out, const T* f, con
     a.f = f;
     a.ec = ec;
     a.partials = norm ? g->partials : nullptr;
-    a.ctrl = g->ctrl;
+    a.ctrl = kctrl(g);
     a.m = L.m;
     a.n = L.n;
     a.P = L.P;
@@ -647,6 +654,9 @@ SweepArgs<T> sweep_args(lap_grid* g, int l, const T* in, T* out, const T* f, con
     a.d = (T)c.d;
     a.inv_d = (T)c.inv_d;
     a.omega = (T)omega;
+    a.dcx = c.cx;
+    a.dcy = c.cy;
+    a.dd = c.d;
     a.tl = norm ? norm_tiling(L.m, L.n) : g->ctx->tiling(L.m, L.n, ec ? KC_SWEEP_PROLONG : KC_SWEEP, dt_of<T>());
     return a;
 }
@@ -707,14 +717,15 @@ hipError_t enq_fused(lap_grid* g, int l, const T* in, T* out, const T* f, const 
                          [&]() { return launch_fused<T>(a, flags, g->ctx->stream); });
 }
 
-hipError_t enq_finalize(lap_grid* g, int ntiles, int mode = 0) {
+hipError_t enq_finalize(lap_grid* g, int ntiles, int mode = 0, const Ctrl* gate = nullptr, int cycles = -1) {
     return g->ctx->timed(KC_FINALIZE, false, 16.0 * ntiles, [&]() {
-        return launch_finalize(g->partials, ntiles, g->ctrl, nullptr, mode, g->ctx->stream);
+        return launch_finalize(g->partials, ntiles, g->ctrl, nullptr, mode, g->ctx->stream, gate,
+                               cycles >= 0 ? g->cyc : nullptr, cycles >= 0 ? cycles : 0);
     });
 }
 
 template <typename T>
-hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc, T* uc0 = nullptr) {
+hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc, T* uc0 = nullptr, bool r64 = false) {
     const LevelGeo& L = g->geo[l];
     const LevelGeo& C = g->geo[l + 1];
     const Coef c = coef(L.dx, L.dy);
@@ -723,7 +734,7 @@ hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc, T* uc
     a.f = f;
     a.bc = bc;
     a.uc0 = uc0;
-    a.ctrl = g->ctrl;
+    a.ctrl = kctrl(g);
     a.m = L.m;
     a.n = L.n;
     a.P = L.P;
@@ -733,6 +744,10 @@ hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc, T* uc
     a.cx = (T)c.cx;
     a.cy = (T)c.cy;
     a.d = (T)c.d;
+    a.r64 = r64 ? 1 : 0;
+    a.dcx = c.cx;
+    a.dcy = c.cy;
+    a.dd = c.d;
     a.tl = g->ctx->tiling(L.m, L.n, KC_RESTRICT, dt_of<T>());
     const double per = (u ? 1.0 : 0.0) + (f ? 1.0 : 0.0) + (uc0 ? 0.5 : 0.25);
     return g->ctx->timed(KC_RESTRICT, l == 0, per * sizeof(T) * nint(L),
@@ -751,7 +766,7 @@ hipError_t enq_coarse(lap_grid* g, int l, const T* ubnd, const T* b, T* out) {
     a.work = g->coarse_work;
     a.bw = g->coarse_bw;
     a.ifast = g->coarse_ifast;
-    a.ctrl = g->ctrl;
+    a.ctrl = kctrl(g);
     a.m = L.m;
     a.n = L.n;
     a.P = L.P;
@@ -770,7 +785,7 @@ hipError_t enq_residual_norm(lap_grid* g, int l, const T* u, const T* f) {
     a.f = f;
     a.r = nullptr;
     a.partials = g->partials;
-    a.ctrl = g->ctrl;
+    a.ctrl = kctrl(g);
     a.m = L.m;
     a.n = L.n;
     a.P = L.P;
@@ -806,6 +821,8 @@ struct Op {
     double omega;
     int parity;      // ADI line parity; post + defect: buffer of the level-0 pre-smoothing result
     void* zbuf = nullptr;   // defect: FP32 buffer to set to zero (the next zebra cycle's start)
+    Ctrl* gate = nullptr;   // its kernels do nothing while gate->done is set (mixed steps of several cycles)
+    int cycles = -1;        // finalisation of a mixed step of several cycles: inner | parity << 8
 };
 
 constexpr long KEY_HEAD = 10;
@@ -1100,7 +1117,7 @@ hipError_t enq_defect(lap_grid* g, const double* psi_in, double* psi_out, const 
     a.rhs = rhs;
     a.ezero = ezero;
     a.partials = g->partials;
-    a.ctrl = g->ctrl;
+    a.ctrl = kctrl(g);
     a.m = L.m;
     a.n = L.n;
     a.P = L.P;
@@ -1134,7 +1151,7 @@ hipError_t enq_postdef(lap_grid* g, const Op& op, double omega) {
     a.f = (const float*)op.f;
     a.ec = (const float*)op.ec;
     a.partials = g->partials;
-    a.ctrl = g->ctrl;
+    a.ctrl = kctrl(g);
     a.m = L.m;
     a.n = L.n;
     a.P = L.P;
@@ -1184,11 +1201,13 @@ bool postdef_ok(lap_grid* g, const lap_opts& o) {
 // right-hand side set): o.inner V-cycles, the first from zero, each next from
 // the previous correction (level 0 then carries an iterate, in whichever of
 // its two buffers the previous cycle left it).  With dp the last cycle stops
-// before its level-0 post-smoothing, described in *dp.  Returns the level-0
-// buffer (0/1 of g->l32[0].u) holding the correction; dp->in is given the
-// same way.
+// before its level-0 post-smoothing, described in *dp.  The operations of
+// the cycles after the first are gated by `later` (a step that runs one
+// cycle skips them).  Returns the level-0 buffer (0/1 of g->l32[0].u)
+// holding the correction; dp->in is given the same way, and *first the
+// buffer holding the first cycle's correction.
 int plan_inner_cycles(lap_grid* g, const lap_opts& o, HierView<float> H, std::vector<Op>& ops,
-                      DeferredPost* dp = nullptr) {
+                      DeferredPost* dp = nullptr, Ctrl* later = nullptr, int* first = nullptr) {
     float* B[2] = {g->l32[0].u[0], g->l32[0].u[1]};
     int base = 0;   // buffer of g->l32[0].u that H.u0[0] is
     int res = 0;
@@ -1200,11 +1219,44 @@ int plan_inner_cycles(lap_grid* g, const lap_opts& o, HierView<float> H, std::ve
             H.u1[0] = B[1 - res];
             base = res;
         }
+        const size_t mark = ops.size();
         const int r = plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops, last ? dp : nullptr);
+        if (c > 0)
+            for (size_t k = mark; k < ops.size(); ++k) {
+                Op& op = ops[k];
+                op.gate = later;
+                // the residual of level 0's correction in FP64 arithmetic: in FP32 it is a
+                // small difference of terms of size 8|e|/h^2 whose rounding swamps its
+                // smooth part (the part the coarse levels must see)
+                if (op.level == 0 && ((op.kind == OP_SWEEP && (op.flags & SW_RESTRICT)) || op.kind == OP_RESTRICT))
+                    op.flags |= SW_R64;
+            }
         res = r == 0 ? base : 1 - base;
+        if (c == 0 && first != nullptr) *first = res;
         if (last && dp != nullptr && dp->in >= 0) dp->in = dp->in == 0 ? base : 1 - base;
     }
     return res;
+}
+
+// Gates of a mixed step s with several FP32 cycles: its opening after a step
+// of all cycles / after a one-cycle step (chosen by step s - 1's test), the
+// gate of its own later cycles (chosen by its test), and the cycle word of
+// its test's finalisation.
+struct StepGates {
+    Ctrl* after_all = nullptr;
+    Ctrl* after_one = nullptr;
+    Ctrl* later = nullptr;
+    int cycles = -1;
+};
+StepGates step_gates(lap_grid* g, const lap_opts& o, int s) {
+    StepGates G;
+    if (o.inner <= 1) return G;
+    const int p = s % 2, q = (s + 1) % 2;
+    G.after_all = g->cyc + 2 * p;
+    G.after_one = g->cyc + 2 * p + 1;
+    G.later = g->cyc + 2 * q;
+    G.cycles = o.inner | (q << 8);
+    return G;
 }
 
 void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part, std::vector<Op>& ops) {
@@ -1212,6 +1264,7 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
     const int in_idx = first ? 0 : (s + 1) % 2;
     double* pin = g->psi[in_idx];
     double* pout = first ? g->psi[0] : g->psi[1 - in_idx];
+    const StepGates G = step_gates(g, o, s);
     if (g->pdef) {
         float* R[2] = {g->l32[0].b, g->rhs2};
         const int par = s % 2;
@@ -1222,20 +1275,36 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
                 push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, pin, pout, g->f64, nullptr, R[0], 0.0);
                 push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr,
                                 nullptr, 0.0);
+                ops.back().cycles = G.cycles;
             } else {
                 // the previous step's cycles, planned again only to find its deferred pass
                 std::vector<Op> prev;
                 H.b[0] = R[1 - par];
-                plan_inner_cycles(g, o, H, prev, &dp);
+                int e1 = 0;
+                plan_inner_cycles(g, o, H, prev, &dp, nullptr, &e1);
                 push_op<float>(ops, KEY_HEAD, OP_POSTDEF, 0, kPostDefFlags, pin, pout, R[1 - par], dp.ec, R[par],
                                o.omega, dp.in);
+                ops.back().gate = G.after_all;
                 push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_POSTDEF, nullptr, nullptr, nullptr, nullptr,
                                 nullptr, 0.0);
+                ops.back().gate = G.after_all;
+                ops.back().cycles = G.cycles;
+                if (o.inner > 1) {
+                    // after a one-cycle step: its correction is complete (its level-0
+                    // post-smoothing ran), a plain defect correction adds it
+                    push_op<double>(ops, KEY_HEAD + 2, OP_DEFECT, 0, 0, pin, pout, g->f64, g->l32[0].u[e1], R[par],
+                                    0.0);
+                    ops.back().gate = G.after_one;
+                    push_op<double>(ops, KEY_HEAD + 3, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr,
+                                    nullptr, nullptr, 0.0);
+                    ops.back().gate = G.after_one;
+                    ops.back().cycles = G.cycles;
+                }
             }
         }
         if (part == PART_HEAD) return;
         H.b[0] = R[par];
-        plan_inner_cycles(g, o, H, ops, &dp);
+        plan_inner_cycles(g, o, H, ops, &dp, G.later);
         return;
     }
     if (o.smoother == LAP_SMOOTH_ZEBRA) {
@@ -1259,12 +1328,20 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
     if (part != PART_TAIL) {
         const float* e = first ? nullptr : (e_idx == 0 ? g->l32[0].u[0] : g->l32[0].u[1]);
         push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, pin, pout, g->f64, e, g->l32[0].b, 0.0);
+        if (!first && o.inner > 1) {
+            // after a step of all cycles its last correction, after a one-cycle step its first
+            ops.back().gate = G.after_all;
+            push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, pin, pout, g->f64, g->l32[0].u[g->e1_idx],
+                            g->l32[0].b, 0.0);
+            ops.back().gate = G.after_one;
+        }
         push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr, nullptr,
                         0.0);
+        ops.back().cycles = G.cycles;
     }
     if (part == PART_HEAD) return;
     HierView<float> H = view32(g);
-    plan_inner_cycles(g, o, H, ops);
+    plan_inner_cycles(g, o, H, ops, nullptr, G.later);
 }
 
 // Full multigrid start (FP64): the source full-weighted down the hierarchy
@@ -1337,7 +1414,7 @@ LineArgs adi_args(lap_grid* g, double omega, int form, int dir, int parity) {
     a.u = g->psi[0];
     a.f = g->f64;
     a.scratch = g->adi_scratch;
-    a.ctrl = g->ctrl;
+    a.ctrl = kctrl(g);
     a.m = L.m;
     a.n = L.n;
     a.P = L.P;
@@ -1377,7 +1454,7 @@ LineArgsT<T> zebra_args(lap_grid* g, int l, T* u, const T* b, double omega, int 
     LineArgsT<T> a{};
     a.u = u;
     a.f = b;
-    a.ctrl = g->ctrl;
+    a.ctrl = kctrl(g);
     a.m = L.m;
     a.n = L.n;
     a.P = L.P;
@@ -1404,7 +1481,7 @@ hipError_t enq_zebra(lap_grid* g, const Op& op, int dir) {
 }
 
 // Launch one recorded operation of grid g.
-hipError_t exec_op(lap_grid* g, const Op& op) {
+hipError_t exec_op_body(lap_grid* g, const Op& op) {
     const int l = op.level;
     switch (op.kind) {
         case OP_SWEEP:
@@ -1424,13 +1501,15 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
             if (op.dt == 0)
                 return enq_restrict<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.bc,
                                             (double*)op.out);
-            return enq_restrict<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.bc, (float*)op.out);
+            return enq_restrict<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.bc, (float*)op.out,
+                                       (op.flags & SW_R64) != 0);
         case OP_COARSE:
             if (op.dt == 0)
                 return enq_coarse<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.out);
             return enq_coarse<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.out);
         case OP_FINALIZE:
-            return enq_finalize(g, norm_partials(g->geo[0].m, g->geo[0].n, op.flags), op.parity == kProbeFinalize ? 2 : 0);
+            return enq_finalize(g, norm_partials(g->geo[0].m, g->geo[0].n, op.flags),
+                                op.parity == kProbeFinalize ? 2 : 0, op.gate, op.cycles);
         case OP_RESNORM:
             return enq_residual_norm<double>(g, l, (const double*)op.in, (const double*)op.f);
         case OP_DEFECT:
@@ -1451,10 +1530,17 @@ hipError_t exec_op(lap_grid* g, const Op& op) {
         case OP_BOUNDARY: {
             const LevelGeo& G = g->geo[l];
             return launch_level_boundary((double*)op.out, (double*)op.bc, op.flags ? g->psi[0] : nullptr, G.m, G.n,
-                                         G.P, g->P, 1 << l, g->ctrl, g->ctx->stream);
+                                         G.P, g->P, 1 << l, kctrl(g), g->ctx->stream);
         }
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t exec_op(lap_grid* g, const Op& op) {
+    g->op_ctrl = op.kind == OP_FINALIZE ? nullptr : op.gate;
+    const hipError_t e = exec_op_body(g, op);
+    g->op_ctrl = nullptr;
+    return e;
 }
 
 // Launch a step's operations in order; for the timing records, the
@@ -1693,8 +1779,8 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
     g->pdef = postdef_ok(g, o);   // fixed for the whole solve
     g->e_idx = vcycle_result_index(g->ctx, o);
     if (o.method == LAP_MG && o.precision == LAP_MIXED && o.inner > 1 && !g->l32.empty()) {
-        std::vector<Op> dry;   // where the step's last FP32 cycle leaves the correction
-        g->e_idx = plan_inner_cycles(g, o, view32(g), dry);
+        std::vector<Op> dry;   // where the step's first and last FP32 cycles leave the correction
+        g->e_idx = plan_inner_cycles(g, o, view32(g), dry, nullptr, nullptr, &g->e1_idx);
     }
     // the two-buffer methods need both buffers equal when they start
     if (g->psi1_stale && o.method != LAP_ADI) {
@@ -2215,7 +2301,8 @@ lap_status lap_grid_create_ex(lap_ctx* c, int32_t m, int32_t n, double dx, doubl
         g->adi_maxk = std::max(m, n);
         g->adi_tab = (double*)A(((size_t)4 * g->adi_maxk + 2 * kSegTab) * 8);
     }
-    g->ctrl = (Ctrl*)A(sizeof(Ctrl));
+    g->ctrl = (Ctrl*)A(5 * sizeof(Ctrl));
+    g->cyc = g->ctrl + 1;
     g->max_partials = (int)max_tiles(m, n);
     g->partials = (double*)A((size_t)g->max_partials * 16);
     g->norm_out = (double*)A(16);

@@ -66,25 +66,31 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int flags, hipStream_t s) {
 template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, hipStream_t);
 template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, hipStream_t);
 
-template <typename T, int V>
+template <typename T, int V, typename RT>
 __global__ __launch_bounds__(kBlock) void k_restrict(RestrictArgs<T> A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = b * kWavesPerBlock + wave_in_block();
     if (tile >= A.tl.ntiles) return;
-    restrict_tile<T, V>(A, tile, threadIdx.x & 63);
+    restrict_tile<T, V, RT>(A, tile, threadIdx.x & 63);
+}
+
+template <typename T, typename RT>
+hipError_t launch_restrict_rt(const RestrictArgs<T>& a, hipStream_t s) {
+    const dim3 grid(blocks_for(a.tl)), block(kBlock);
+    switch (a.tl.V) {
+        case 1: k_restrict<T, 1, RT><<<grid, block, 0, s>>>(a); break;
+        case 2: k_restrict<T, 2, RT><<<grid, block, 0, s>>>(a); break;
+        case 4: k_restrict<T, 4, RT><<<grid, block, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_restrict(const RestrictArgs<T>& a, hipStream_t s) {
-    const dim3 grid(blocks_for(a.tl)), block(kBlock);
-    switch (a.tl.V) {
-        case 1: k_restrict<T, 1><<<grid, block, 0, s>>>(a); break;
-        case 2: k_restrict<T, 2><<<grid, block, 0, s>>>(a); break;
-        case 4: k_restrict<T, 4><<<grid, block, 0, s>>>(a); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (sizeof(T) == 4 && a.r64) return launch_restrict_rt<T, double>(a, s);
+    return launch_restrict_rt<T, T>(a, s);
 }
 template hipError_t launch_restrict<double>(const RestrictArgs<double>&, hipStream_t);
 template hipError_t launch_restrict<float>(const RestrictArgs<float>&, hipStream_t);
@@ -148,11 +154,50 @@ hipError_t launch_coarse(const CoarseArgs<T>& a, hipStream_t s) {
 template hipError_t launch_coarse<double>(const CoarseArgs<double>&, hipStream_t);
 template hipError_t launch_coarse<float>(const CoarseArgs<float>&, hipStream_t);
 
+// Safety factor of the one-cycle prediction of a mixed step (the factor of a
+// cycle grows by about 10-15% between steps as the FP32 rounding floor nears).
+constexpr double kOneCycleMargin = 1.5;
+
+// After the test of a mixed step (thread 0; ctrl already updated): the FP32
+// cycles the step runs, as the gate pair cyc[2 p], cyc[2 p + 1].  q_prev,
+// checks0 and ran are the control block's test quantity, finalisation count
+// and cycle count before this test.
+__device__ void choose_cycles(Ctrl* ctrl, Ctrl* cyc, int cycles, double q_prev, int checks0, int ran) {
+    if (ctrl->done) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cyc[k].done = 1;
+        return;
+    }
+    const int inner = cycles & 255, p = (cycles >> 8) & 1;
+    bool one = false;
+    if (checks0 >= 1 && q_prev > 0.0) {
+        // 1.5 q (q / q_prev)^(1 / ran) < tol, as q / q_prev < (tol / (1.5 q))^ran
+        const double q = ctrl->stop == 0 ? ctrl->rel : ctrl->res_inf;
+        const double x = ctrl->tol / (kOneCycleMargin * q);
+        double pw = 1.0;
+        for (int k = 0; k < ran; ++k) pw *= x;
+        one = q / q_prev < pw;
+    }
+    cyc[2 * p].done = one ? 1 : 0;
+    cyc[2 * p + 1].done = one ? 0 : 1;
+    ctrl->cycles = one ? 1 : inner;
+}
+
 __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* partials, int ntiles, Ctrl* ctrl,
-                                                     double* out2, int mode) {
+                                                     double* out2, int mode, const Ctrl* gate, Ctrl* cyc,
+                                                     int cycles) {
     if (mode != 1 && ctrl->done) return;
+    if (gate != nullptr && gate->done) return;
+    double q_prev = 0.0;
+    int checks0 = 0, ran = 0;
+    if (cyc != nullptr && threadIdx.x == 0) {
+        q_prev = ctrl->stop == 0 ? ctrl->rel : ctrl->res_inf;
+        checks0 = ctrl->checks;
+        ran = ctrl->cycles;
+    }
     __shared__ double ss[kFinBlock / 64], sm[kFinBlock / 64];
     finalize_block(partials, ntiles, ctrl, out2, mode, ss, sm);
+    if (cyc != nullptr && mode == 0 && threadIdx.x == 0) choose_cycles(ctrl, cyc, cycles, q_prev, checks0, ran);
 }
 
 __global__ void k_ctrl_init(Ctrl* c, double tol, int stop, int max_iter, int step) {
@@ -168,7 +213,7 @@ __global__ void k_ctrl_init(Ctrl* c, double tol, int stop, int max_iter, int ste
     c->done = 0;
     c->status = 0;
     c->step = step;
-    c->pad = 0;
+    c->cycles = 0;
 }
 
 hipError_t launch_ctrl_init(Ctrl* ctrl, double tol, int stop, int max_iter, int step, hipStream_t s) {
@@ -195,8 +240,8 @@ hipError_t launch_ctrl_init_many(Ctrl* const* ctrls, int count, double tol, int 
 }
 
 hipError_t launch_finalize(const double* partials, int ntiles, Ctrl* ctrl, double* out2, int mode,
-                           hipStream_t s) {
-    k_finalize<<<1, kFinBlock, 0, s>>>(partials, ntiles, ctrl, out2, mode);
+                           hipStream_t s, const Ctrl* gate, Ctrl* cyc, int cycles) {
+    k_finalize<<<1, kFinBlock, 0, s>>>(partials, ntiles, ctrl, out2, mode, gate, cyc, cycles);
     return hipGetLastError();
 }
 
