@@ -64,6 +64,26 @@ def residual(u: np.ndarray, f: np.ndarray | None, dx: float, dy: float,
     return r
 
 
+def residual_diff(u: np.ndarray, f: np.ndarray | None, dx: float, dy: float,
+                  dtype=np.float64) -> np.ndarray:
+    """The same residual with L_h in difference form,
+        cx ((u_{i-1,j} - u_ij) + (u_{i+1,j} - u_ij)) + cy ((u_{i,j-1} - u_ij) + (u_{i,j+1} - u_ij)),
+    algebraically equal to apply_L (d = 2 (cx + cy)).  In floating point the
+    neighbour differences are formed first, so for a smooth u of large values
+    the result keeps the accuracy of the second differences instead of that
+    of terms of size 8|u|/h^2."""
+    cx, cy, _, _ = coefficients(dx, dy, dtype)
+    W = u[1:-1, :-2]
+    E = u[1:-1, 2:]
+    S = u[:-2, 1:-1]
+    N = u[2:, 1:-1]
+    C = u[1:-1, 1:-1]
+    Lu = cx * ((W - C) + (E - C)) + cy * ((S - C) + (N - C))
+    r = np.zeros_like(u)
+    r[1:-1, 1:-1] = -Lu if f is None else f[1:-1, 1:-1].astype(u.dtype) - Lu
+    return r
+
+
 def interior(a: np.ndarray) -> np.ndarray:
     return a[1:-1, 1:-1]
 

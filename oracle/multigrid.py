@@ -28,8 +28,8 @@ Readings (the V-cycle figure is not available):
 Mixed precision (not in the paper): psi and the residual stay FP64; each
 outer step solves the error equation approximately by one FP32 V-cycle from
 a zero start (or `inner` cycles, each next from the previous correction,
-forming its level-0 residual in FP64 arithmetic) and adds the FP32
-correction to the FP64 iterate.  How many cycles a step runs
+forming its level-0 residual with the operator in difference form) and adds
+the FP32 correction to the FP64 iterate.  How many cycles a step runs
 is the driver's choice (oracle.solve.mixed_solve).
 
 Pins (tests/test_oracle_multigrid.py): full weighting and bilinear
@@ -41,7 +41,9 @@ below 0.15 and its cycle count to 1e-10 does not grow with the grid
 FP32 cycles per defect correction its residual after each step follows the
 FP64 cycle history at the cycles run so far, and one step of two cycles
 lands within FP32 storage noise of two FP64 cycles (with the later cycle's
-level-0 residual in FP32 it is 20x farther on 513^2); a last step shortened to one
+level-0 residual in the standard form it is 20x farther on 513^2); the
+difference form equals the standard one in FP64 and is the more accurate in
+FP32 for a smooth field; a last step shortened to one
 cycle (oracle.solve.one_cycle_suffices, pinned against its closed form)
 lands on the history one cycle further, with no more steps than without it.
 """
@@ -49,7 +51,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .grid import coefficients, residual, norm2
+from .grid import coefficients, residual, residual_diff, norm2
 from .relax import rb_sweep, gs_lex_sweep
 from .lines import adi_zebra_iteration
 from .direct import dense_solve
@@ -113,15 +115,14 @@ def coarse_solve(u: np.ndarray, b: np.ndarray | None, dx: float, dy: float) -> N
 
 
 def vcycle(levels, l: int, u: np.ndarray, b: np.ndarray | None, nu1: int = 2, nu2: int = 2,
-           omega_s: float = 1.0, dtype=np.float64, smoother: str = "rb", top_residual64: bool = False) -> None:
+           omega_s: float = 1.0, dtype=np.float64, smoother: str = "rb", top_residual_diff: bool = False) -> None:
     """One V-cycle on level l, in place on u (u's perimeter is the boundary:
     g on level 0, zero on coarse levels; b is the right-hand side):
         nu1 smoothing sweeps; r = b - L u; b' = FW(r); e' = 0;
         V(l+1, e', b'); u += P e'; nu2 smoothing sweeps.
-    The coarsest level is solved exactly.  With top_residual64 the residual
-    of level l and its full weighting are evaluated in FP64 arithmetic on the
-    (FP32) values of u and b, and b' is rounded to dtype (the coarser levels
-    as usual)."""
+    The coarsest level is solved exactly.  With top_residual_diff the
+    residual of level l is formed with L_h in difference form
+    (grid.residual_diff; the coarser levels as usual)."""
     m, n, dx, dy = levels[l]
     if l == len(levels) - 1:
         coarse_solve(u, b, dx, dy)
@@ -139,12 +140,8 @@ def vcycle(levels, l: int, u: np.ndarray, b: np.ndarray | None, nu1: int = 2, nu
 
     for _ in range(nu1):
         smooth()
-    if top_residual64:
-        r = residual(u.astype(np.float64), None if b is None else b.astype(np.float64), dx, dy, np.float64)
-        bc = restrict_fw(r).astype(dtype)
-    else:
-        r = residual(u, b, dx, dy, dtype)
-        bc = restrict_fw(r)
+    r = (residual_diff if top_residual_diff else residual)(u, b, dx, dy, dtype)
+    bc = restrict_fw(r)
     mc, nc, _, _ = levels[l + 1]
     ec = np.zeros((nc, mc), dtype=u.dtype)
     vcycle(levels, l + 1, ec, bc, nu1, nu2, omega_s, dtype, smoother)
@@ -161,19 +158,19 @@ def mixed_step(psi: np.ndarray, f: np.ndarray | None, levels, nu1=2, nu2=2, omeg
         psi64 += fl64(e32).
     (Eqs. (13)-(15) solve the error equation with the cycle; more cycles per
     correction solve it more accurately before the FP64 update.)  A cycle
-    after the first starts from a smooth correction whose level-0 residual
-    b32 - L_h e32 is a small difference of terms of size 8|e|/h^2: in FP32
-    its rounding swamps the smooth part the coarse levels must see (on 8193^2
-    the second cycle then no longer reduces smooth error), so those cycles
-    form their level-0 residual and its full weighting in FP64 arithmetic
-    (vcycle's top_residual64; storage and the rest stay FP32).  Returns the
-    FP64 residual taken at the start of the step."""
+    after the first starts from a smooth correction of large values: the
+    standard form of its level-0 residual b32 - L_h e32 adds terms of size
+    8|e|/h^2 whose FP32 rounding swamps the smooth part the coarse levels must
+    see (on 8193^2 the second cycle then no longer reduces smooth error), so
+    those cycles form it with L_h in difference form (vcycle's
+    top_residual_diff), still in FP32.  Returns the FP64 residual taken at
+    the start of the step."""
     m, n, dx, dy = levels[0]
     r = residual(psi, f, dx, dy)
     b32 = r.astype(np.float32)
     e32 = np.zeros_like(b32)
     for c in range(inner):
-        vcycle(levels, 0, e32, b32, nu1, nu2, omega_s, np.float32, smoother, top_residual64=c > 0)
+        vcycle(levels, 0, e32, b32, nu1, nu2, omega_s, np.float32, smoother, top_residual_diff=c > 0)
     psi += e32.astype(np.float64)
     return r
 

@@ -67,6 +67,35 @@ def test_operator_matches_dense_assembly():
     assert np.allclose(-grid.apply_L(u, dx, dy)[1:-1, 1:-1].ravel(), A @ x, rtol=1e-13, atol=1e-12)
 
 
+def test_difference_form_residual():
+    """residual_diff equals the assembled operator (as residual does) in FP64,
+    reproduces the exact Laplacian of a cubic, and in FP32 on a smooth field
+    of large values on a fine grid (h = 1/8192) stays within 1e-3 of the FP64
+    residual of the stored values relative to its size, where the standard
+    form is off by a quarter of the residual or more."""
+    rng = np.random.default_rng(0)
+    m, n, dx, dy = 8, 6, 0.3, 0.2
+    A, _ = direct.assemble(m, n, dx, dy, np.zeros((n, m)), None)
+    x = rng.standard_normal((n - 2) * (m - 2))
+    u = np.zeros((n, m))
+    u[1:-1, 1:-1] = x.reshape(n - 2, m - 2)
+    assert np.allclose(grid.residual_diff(u, None, dx, dy)[1:-1, 1:-1].ravel(), A @ x, rtol=1e-13, atol=1e-12)
+    dx, dy = 0.2, 0.35
+    uc, lap = W.harmonic_field("x3", 17, 13, dx, dy, x0=0.4)
+    assert np.max(np.abs(grid.residual_diff(uc, lap, dx, dy))) < 1e-10
+    h = 1.0 / 8192
+    i = np.arange(40)
+    X, Y = np.meshgrid(0.3 + h * i, 0.6 + h * i)
+    us = np.sin(np.pi * X) * np.sin(np.pi * Y)           # smooth, values near 0.8
+    u32 = us.astype(np.float32)
+    ref = grid.residual(u32.astype(np.float64), None, h, h)[1:-1, 1:-1]   # exact for the stored values
+    scale = np.max(np.abs(ref))                            # about 2 pi^2 |u|
+    d32 = grid.residual_diff(u32, None, h, h, np.float32)[1:-1, 1:-1]
+    s32 = grid.residual(u32, None, h, h, np.float32)[1:-1, 1:-1]
+    assert np.max(np.abs(d32 - ref)) < 1e-3 * scale
+    assert np.max(np.abs(s32 - ref)) > 0.25 * scale
+
+
 def test_norms_against_numpy():
     rng = np.random.default_rng(1)
     r = rng.standard_normal((11, 13))

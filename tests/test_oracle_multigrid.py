@@ -180,12 +180,12 @@ def test_mixed_inner_cycles(inner):
     assert np.max(np.abs(um - ex)) <= 1e-8 * np.max(np.abs(ex))
 
 
-def test_continuing_cycle_has_fp64_residual():
+def test_continuing_cycle_residual_in_difference_form():
     """A mixed step of two FP32 cycles on 513^2 lands within FP32 storage
     noise (2e-7) of two FP64 V-cycles from the same iterate.  The second
     cycle starts from the first one's smooth correction: with its level-0
-    residual in FP32 arithmetic the step is 20x farther (4e-6; on 8193^2 the
-    smooth error of the step is then that of one cycle)."""
+    residual in the standard form the step is 20x farther (4e-6; on 8193^2
+    the smooth error of the step is then that of one cycle)."""
     p = W.square_problem(513, seed=2, bumps=True, bump_seed=3)
     lv = multigrid.hierarchy(p.m, p.n, p.dx, p.dy)
     u64 = p.psi0.copy()
@@ -199,7 +199,7 @@ def test_continuing_cycle_has_fp64_residual():
     assert np.max(np.abs(um - u64)) < 1e-6
     b32 = grid.residual(p.psi0, p.f, p.dx, p.dy).astype(np.float32)
     e32 = np.zeros_like(b32)
-    for _ in range(2):   # both cycles with the FP32 residual
+    for _ in range(2):   # both cycles with the standard form
         multigrid.vcycle(lv, 0, e32, b32, 2, 2, 1.0, np.float32)
     assert np.max(np.abs(p.psi0 + e32.astype(np.float64) - u64)) > 2e-6
 
