@@ -39,7 +39,7 @@ void k_fused(SweepArgs<T> A) {
     X(SW_PROBE | SW_RESTRICT | SW_TWO | SW_NORM) X(SW_PROBE | SW_RESTRICT | SW_TWO | SW_NORM | SW_F)  \
     X(SW_PROBE | SW_RESTRICT | SW_NORM) X(SW_PROBE | SW_RESTRICT | SW_NORM | SW_F)                \
     X(SW_PROBE | SW_TWO | SW_NORM) X(SW_PROBE | SW_TWO | SW_NORM | SW_F)                          \
-    X(SW_R64 | SW_RESTRICT | SW_TWO | SW_F) X(SW_R64 | SW_RESTRICT | SW_F)
+    X(SW_RDIFF | SW_RESTRICT | SW_TWO | SW_F) X(SW_RDIFF | SW_RESTRICT | SW_F)
 
 template <typename T, int V>
 static hipError_t launch_fused_v(const SweepArgs<T>& a, int flags, hipStream_t s) {

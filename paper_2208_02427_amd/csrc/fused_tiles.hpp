@@ -102,18 +102,13 @@ constexpr bool fused_full_turns() {
     return (FL & SW_PROLONG) == 0;
 }
 
-// Type of the residual + full weighting arithmetic of a pass (SW_R64: FP64
-// on FP32 values).
-template <typename T, int FL>
-using fused_rt = std::conditional_t<(FL & SW_R64) != 0, double, T>;
-
-template <typename T, int V, int NS, bool RS, int PF, typename RT = T>
+template <typename T, int V, int NS, bool RS, int PF>
 struct FusedRegs {
     RBStage<T, V> st[NS];
     T ring[PF][V], fring[PF][V];        // input rows j+1 .. j+PF (slot = step phase)
     T bo[V];                            // input row j-1 (norm of the input)
-    RT ru0[V], ru1[V], rf1[V];          // final rows q-2, q-1 and f of row q-1
-    RT r2[V], r1[V];                    // residual rows q-3, q-2
+    T ru0[V], ru1[V], rf1[V];           // final rows q-2, q-1 and f of row q-1
+    T r2[V], r1[V];                     // residual rows q-3, q-2
     double pring[PF][V], qring[PF][V];  // SW_DEF: FP64 iterate and source rows q .. q+PF-1
     double pm[V], pc[V], fm[V];         // SW_DEF: updated rows q-2, q-1 and the source of row q-1
     double s2, mx;
@@ -124,7 +119,7 @@ struct FusedRegs {
 // slot is refilled with row j+1+PF, and the last stage emits final row
 // q = j + 1 - 2 * NS.
 template <typename T, int V, int FL, int NS, bool RS, int JP, int PH>
-__device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS, fused_pf<T, FL>(), fused_rt<T, FL>>& R,
+__device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS, fused_pf<T, FL>()>& R,
                                            const Cols<V>& c, int j, int j0, int j1, int Lend,
                                            const OmegaMask<T, V>& wm) {
     constexpr int PF = fused_pf<T, FL>();
@@ -217,21 +212,18 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
     }
 
     if constexpr (RS) {
-        // residual of the result at row q-1, then full weighting at the even row q-2
-        // (SW_R64: in FP64 on the FP32 rows, which enter converted)
-        using RT = fused_rt<T, FL>;
-        RT r0[V], ov[V];
-        copy_as<RT, T, V>(ov, o);
-        if constexpr (std::is_same_v<RT, T>)
-            residual_row<T, V>(r0, R.ru0, R.ru1, o, R.rf1, (q - 1 >= 1) && (q - 1 <= A.n - 2), c, cx, cy, A.d);
+        // residual of the result at row q-1 (SW_RDIFF: in difference form), then
+        // full weighting at the even row q-2
+        T r0[V];
+        if constexpr ((FL & SW_RDIFF) != 0)
+            residual_row_diff<T, V>(r0, R.ru0, R.ru1, o, R.rf1, (q - 1 >= 1) && (q - 1 <= A.n - 2), c, cx, cy);
         else
-            residual_row<RT, V>(r0, R.ru0, R.ru1, ov, R.rf1, (q - 1 >= 1) && (q - 1 <= A.n - 2), c, A.dcx, A.dcy,
-                                A.dd);
+            residual_row<T, V>(r0, R.ru0, R.ru1, o, R.rf1, (q - 1 >= 1) && (q - 1 <= A.n - 2), c, cx, cy, A.d);
         // q - 2 is even exactly on steps with j odd
         if (JP == 1 && q - 2 >= j0 && q - 2 <= j1) {
             const int J = (q - 2) >> 1;
-            const RT w2 = lane_prev(R.r2[V - 1]), w1 = lane_prev(R.r1[V - 1]), w0 = lane_prev(r0[V - 1]);
-            const RT e2 = lane_next(R.r2[0]), e1 = lane_next(R.r1[0]), e0 = lane_next(r0[0]);
+            const T w2 = lane_prev(R.r2[V - 1]), w1 = lane_prev(R.r1[V - 1]), w0 = lane_prev(r0[V - 1]);
+            const T e2 = lane_next(R.r2[0]), e1 = lane_next(R.r1[0]), e0 = lane_next(r0[0]);
             if (J >= 1 && J <= A.nc - 2) {
                 T* brow = A.bc + (ptrdiff_t)J * A.Pcs;
 #pragma unroll
@@ -240,30 +232,29 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
                     if ((i & 1) || !c.cout[e]) continue;
                     const int I = i >> 1;
                     if (I < 1 || I > A.mc - 2) continue;
-                    const RT C = R.r1[e];
-                    const RT W = e > 0 ? R.r1[e - 1] : w1;
-                    const RT E = e < V - 1 ? R.r1[e + 1] : e1;
-                    const RT S = R.r2[e], N = r0[e];
-                    const RT SW = e > 0 ? R.r2[e - 1] : w2;
-                    const RT SE = e < V - 1 ? R.r2[e + 1] : e2;
-                    const RT NW = e > 0 ? r0[e - 1] : w0;
-                    const RT NE = e < V - 1 ? r0[e + 1] : e0;
-                    brow[I] = (T)((fma(RT(4), C, RT(2) * ((W + E) + (S + N))) + ((SW + SE) + (NW + NE))) *
-                                  RT(0.0625));
+                    const T C = R.r1[e];
+                    const T W = e > 0 ? R.r1[e - 1] : w1;
+                    const T E = e < V - 1 ? R.r1[e + 1] : e1;
+                    const T S = R.r2[e], N = r0[e];
+                    const T SW = e > 0 ? R.r2[e - 1] : w2;
+                    const T SE = e < V - 1 ? R.r2[e + 1] : e2;
+                    const T NW = e > 0 ? r0[e - 1] : w0;
+                    const T NE = e < V - 1 ? r0[e + 1] : e0;
+                    brow[I] = (fma(T(4), C, T(2) * ((W + E) + (S + N))) + ((SW + SE) + (NW + NE))) * T(0.0625);
                 }
             }
         }
-        copy<RT, V>(R.r2, R.r1);
-        copy<RT, V>(R.r1, r0);
-        copy<RT, V>(R.ru0, R.ru1);
-        copy<RT, V>(R.ru1, ov);
-        copy_as<RT, T, V>(R.rf1, fo);
+        copy<T, V>(R.r2, R.r1);
+        copy<T, V>(R.r1, r0);
+        copy<T, V>(R.ru0, R.ru1);
+        copy<T, V>(R.ru1, o);
+        copy<T, V>(R.rf1, fo);
     }
 }
 
 // Steps PH, PH+1, ... of one turn of the ring, starting at row j + PH.
 template <typename T, int V, int FL, int NS, bool RS, int JP0, int PH>
-__device__ __forceinline__ void fused_turn(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS, fused_pf<T, FL>(), fused_rt<T, FL>>& R,
+__device__ __forceinline__ void fused_turn(const SweepArgs<T>& A, FusedRegs<T, V, NS, RS, fused_pf<T, FL>()>& R,
                                            const Cols<V>& c, int j, int j0, int j1, int Lend,
                                            const OmegaMask<T, V>& wm) {
     if constexpr (PH < fused_pf<T, FL>()) {
@@ -279,7 +270,7 @@ __device__ __forceinline__ void fused_turn(const SweepArgs<T>& A, FusedRegs<T, V
 // renaming instead of copies.
 template <typename T, int V, int FL, int NS, bool RS, int JP0, int PH>
 __device__ __forceinline__ void fused_turn_full(const SweepArgs<T>& A,
-                                                FusedRegs<T, V, NS, RS, fused_pf<T, FL>(), fused_rt<T, FL>>& R, const Cols<V>& c,
+                                                FusedRegs<T, V, NS, RS, fused_pf<T, FL>()>& R, const Cols<V>& c,
                                                 int j, int j0, int j1, int Lend, const OmegaMask<T, V>& wm) {
     if constexpr (PH < fused_pf<T, FL>()) {
         fused_step<T, V, FL, NS, RS, (JP0 + PH) & 1, PH>(A, R, c, j + PH, j0, j1, Lend, wm);
@@ -339,18 +330,17 @@ __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int
     if (((L0 + 1) & 1) != JP0) --L0;
     const int Lend = (RS ? e1 + 2 : j1 + DX) + 2 * NS;
 
-    FusedRegs<T, V, NS, RS, fused_pf<T, FL>(), fused_rt<T, FL>> R;
+    FusedRegs<T, V, NS, RS, fused_pf<T, FL>()> R;
     R.s2 = 0.0;
     R.mx = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) stage_zero<T, V>(R.st[s]);
     if constexpr (RS) {
-        using RT = fused_rt<T, FL>;
-        zero<RT, V>(R.ru0);
-        zero<RT, V>(R.ru1);
-        zero<RT, V>(R.rf1);
-        zero<RT, V>(R.r2);
-        zero<RT, V>(R.r1);
+        zero<T, V>(R.ru0);
+        zero<T, V>(R.ru1);
+        zero<T, V>(R.rf1);
+        zero<T, V>(R.r2);
+        zero<T, V>(R.r1);
     }
     if constexpr (FL & SW_PROLONG) R.pr.init(A.ec, L0, A.nc, A.Pc, A.Pcs, c.i0);
     sweep_load<T, V, FL>(R.st[0].b, A, L0, c, R.pr);

@@ -176,9 +176,9 @@ enum : int {
                      // step when the smoother is zebra line relaxation
     SW_PROBE = 256,  // with SW_NORM: the input's residual norms only, exactly as the pass with the
                      // other flags computes them (same tiles, walk and order); nothing is stored
-    SW_R64 = 512,    // with SW_RESTRICT, FP32: the residual and its full weighting in FP64 arithmetic
-                     // on the FP32 values (coefficients dcx, dcy, dd), the coarse right-hand side
-                     // rounded to FP32 (a cycle that continues from a smooth correction)
+    SW_RDIFF = 512,  // with SW_RESTRICT: the residual in difference form, cx ((W - C) + (E - C)) +
+                     // cy ((S - C) + (N - C)), accurate for a smooth iterate of large values (an FP32
+                     // cycle that continues from a correction)
 };
 
 template <typename T>
@@ -222,8 +222,7 @@ struct RestrictArgs {
     int mc, nc, Pc;
     T cx, cy, d;
     Tiling tl;
-    int r64;            // FP32: residual and full weighting in FP64 arithmetic (as SW_R64)
-    double dcx, dcy, dd;
+    int rdiff;          // nonzero: the residual in difference form (as SW_RDIFF)
 };
 
 template <typename T>

@@ -654,9 +654,6 @@ SweepArgs<T> sweep_args(lap_grid* g, int l, const T* in, T* out, const T* f, con
     a.d = (T)c.d;
     a.inv_d = (T)c.inv_d;
     a.omega = (T)omega;
-    a.dcx = c.cx;
-    a.dcy = c.cy;
-    a.dd = c.d;
     a.tl = norm ? norm_tiling(L.m, L.n) : g->ctx->tiling(L.m, L.n, ec ? KC_SWEEP_PROLONG : KC_SWEEP, dt_of<T>());
     return a;
 }
@@ -725,7 +722,7 @@ hipError_t enq_finalize(lap_grid* g, int ntiles, int mode = 0, const Ctrl* gate 
 }
 
 template <typename T>
-hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc, T* uc0 = nullptr, bool r64 = false) {
+hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc, T* uc0 = nullptr, bool rdiff = false) {
     const LevelGeo& L = g->geo[l];
     const LevelGeo& C = g->geo[l + 1];
     const Coef c = coef(L.dx, L.dy);
@@ -744,10 +741,7 @@ hipError_t enq_restrict(lap_grid* g, int l, const T* u, const T* f, T* bc, T* uc
     a.cx = (T)c.cx;
     a.cy = (T)c.cy;
     a.d = (T)c.d;
-    a.r64 = r64 ? 1 : 0;
-    a.dcx = c.cx;
-    a.dcy = c.cy;
-    a.dd = c.d;
+    a.rdiff = rdiff ? 1 : 0;
     a.tl = g->ctx->tiling(L.m, L.n, KC_RESTRICT, dt_of<T>());
     const double per = (u ? 1.0 : 0.0) + (f ? 1.0 : 0.0) + (uc0 ? 0.5 : 0.25);
     return g->ctx->timed(KC_RESTRICT, l == 0, per * sizeof(T) * nint(L),
@@ -1225,11 +1219,11 @@ int plan_inner_cycles(lap_grid* g, const lap_opts& o, HierView<float> H, std::ve
             for (size_t k = mark; k < ops.size(); ++k) {
                 Op& op = ops[k];
                 op.gate = later;
-                // the residual of level 0's correction in FP64 arithmetic: in FP32 it is a
-                // small difference of terms of size 8|e|/h^2 whose rounding swamps its
-                // smooth part (the part the coarse levels must see)
+                // the residual of level 0's correction in difference form: in the standard
+                // form it adds terms of size 8|e|/h^2 whose FP32 rounding swamps its smooth
+                // part (the part the coarse levels must see)
                 if (op.level == 0 && ((op.kind == OP_SWEEP && (op.flags & SW_RESTRICT)) || op.kind == OP_RESTRICT))
-                    op.flags |= SW_R64;
+                    op.flags |= SW_RDIFF;
             }
         res = r == 0 ? base : 1 - base;
         if (c == 0 && first != nullptr) *first = res;
@@ -1502,7 +1496,7 @@ hipError_t exec_op_body(lap_grid* g, const Op& op) {
                 return enq_restrict<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.bc,
                                             (double*)op.out);
             return enq_restrict<float>(g, l, (const float*)op.in, (const float*)op.f, (float*)op.bc, (float*)op.out,
-                                       (op.flags & SW_R64) != 0);
+                                       (op.flags & SW_RDIFF) != 0);
         case OP_COARSE:
             if (op.dt == 0)
                 return enq_coarse<double>(g, l, (const double*)op.in, (const double*)op.f, (double*)op.out);

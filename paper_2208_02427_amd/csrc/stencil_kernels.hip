@@ -66,22 +66,22 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int flags, hipStream_t s) {
 template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, hipStream_t);
 template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, hipStream_t);
 
-template <typename T, int V, typename RT>
+template <typename T, int V, bool DIFF>
 __global__ __launch_bounds__(kBlock) void k_restrict(RestrictArgs<T> A) {
     if (A.ctrl != nullptr && A.ctrl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = b * kWavesPerBlock + wave_in_block();
     if (tile >= A.tl.ntiles) return;
-    restrict_tile<T, V, RT>(A, tile, threadIdx.x & 63);
+    restrict_tile<T, V, DIFF>(A, tile, threadIdx.x & 63);
 }
 
-template <typename T, typename RT>
-hipError_t launch_restrict_rt(const RestrictArgs<T>& a, hipStream_t s) {
+template <typename T, bool DIFF>
+hipError_t launch_restrict_as(const RestrictArgs<T>& a, hipStream_t s) {
     const dim3 grid(blocks_for(a.tl)), block(kBlock);
     switch (a.tl.V) {
-        case 1: k_restrict<T, 1, RT><<<grid, block, 0, s>>>(a); break;
-        case 2: k_restrict<T, 2, RT><<<grid, block, 0, s>>>(a); break;
-        case 4: k_restrict<T, 4, RT><<<grid, block, 0, s>>>(a); break;
+        case 1: k_restrict<T, 1, DIFF><<<grid, block, 0, s>>>(a); break;
+        case 2: k_restrict<T, 2, DIFF><<<grid, block, 0, s>>>(a); break;
+        case 4: k_restrict<T, 4, DIFF><<<grid, block, 0, s>>>(a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -89,8 +89,7 @@ hipError_t launch_restrict_rt(const RestrictArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_restrict(const RestrictArgs<T>& a, hipStream_t s) {
-    if (sizeof(T) == 4 && a.r64) return launch_restrict_rt<T, double>(a, s);
-    return launch_restrict_rt<T, T>(a, s);
+    return a.rdiff ? launch_restrict_as<T, true>(a, s) : launch_restrict_as<T, false>(a, s);
 }
 template hipError_t launch_restrict<double>(const RestrictArgs<double>&, hipStream_t);
 template hipError_t launch_restrict<float>(const RestrictArgs<float>&, hipStream_t);

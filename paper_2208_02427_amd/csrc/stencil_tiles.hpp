@@ -7,8 +7,6 @@
 
 #include "lap_kernels.hpp"
 
-#include <type_traits>
-
 namespace lap {
 
 // ------------------------------------------------------------------ helpers
@@ -58,13 +56,6 @@ template <typename T, int V>
 __device__ __forceinline__ void copy(T (&dst)[V], const T (&src)[V]) {
 #pragma unroll
     for (int e = 0; e < V; ++e) dst[e] = src[e];
-}
-
-// dst = src converted to dst's type (exact from FP32 to FP64)
-template <typename D, typename S, int V>
-__device__ __forceinline__ void copy_as(D (&dst)[V], const S (&src)[V]) {
-#pragma unroll
-    for (int e = 0; e < V; ++e) dst[e] = (D)src[e];
 }
 
 // Index of the calling wavefront in its workgroup, as a wave-uniform value
@@ -458,8 +449,28 @@ __device__ __forceinline__ void residual_row(T (&r)[V], const T (&um)[V], const 
     }
 }
 
-// RT: the type of the residual arithmetic (double on FP32 data: RestrictArgs::r64)
-template <typename T, int V, typename RT = T>
+// The same residual in difference form: cx ((W - C) + (E - C)) + cy ((S - C)
+// + (N - C)) forms each neighbour difference first.  For a smooth u the
+// standard form adds terms of size 8|u|/h^2 whose rounding, in FP32 on a fine
+// grid, swamps the small smooth residual; the differences are exact or
+// nearly so, and the result keeps the accuracy of the second differences.
+template <typename T, int V>
+__device__ __forceinline__ void residual_row_diff(T (&r)[V], const T (&um)[V], const T (&uc)[V], const T (&up)[V],
+                                                  const T (&f)[V], bool rowint, const Cols<V>& c, T cx, T cy) {
+    const T W0 = lane_prev(uc[V - 1]);
+    const T E0 = lane_next(uc[0]);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+        const T W = e > 0 ? uc[e - 1] : W0;
+        const T E = e < V - 1 ? uc[e + 1] : E0;
+        const T C = uc[e];
+        const T L = cx * ((W - C) + (E - C)) + cy * ((um[e] - C) + (up[e] - C));
+        r[e] = (rowint && c.cint[e]) ? (f[e] - L) : T(0);
+    }
+}
+
+// DIFF: the residual in difference form (RestrictArgs::rdiff)
+template <typename T, int V, bool DIFF = false>
 __device__ __forceinline__ void restrict_tile(const RestrictArgs<T>& A, int tile, int lane) {
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
     const Cols<V> c(win, lane, A.m, A.P, A.tl.H);
@@ -467,9 +478,9 @@ __device__ __forceinline__ void restrict_tile(const RestrictArgs<T>& A, int tile
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
 
     T um[V], uc[V], up[V], q1[V], q2[V], fr[V], fq1[V], fq2[V];
-    RT r2[V], r1[V], r0[V];
-    zero<RT, V>(r2);
-    zero<RT, V>(r1);
+    T r2[V], r1[V], r0[V];
+    zero<T, V>(r2);
+    zero<T, V>(r1);
     load_row<T, V>(um, A.u, j0 - 1, A.n, A.P, c.i0, c.vin);
     load_row<T, V>(uc, A.u, j0, A.n, A.P, c.i0, c.vin);
     load_row<T, V>(q1, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
@@ -484,20 +495,14 @@ __device__ __forceinline__ void restrict_tile(const RestrictArgs<T>& A, int tile
         copy<T, V>(fq1, fq2);
         if (j + 3 <= j1 + 2) load_row<T, V>(q2, A.u, j + 3, A.n, A.P, c.i0, c.vin);
         if (j + 2 <= j1 + 1) load_row<T, V>(fq2, A.f, j + 2, A.n, A.P, c.i0, c.vin);
-        if constexpr (std::is_same_v<RT, T>) {
+        if constexpr (DIFF)
+            residual_row_diff<T, V>(r0, um, uc, up, fr, (j >= 1) && (j <= A.n - 2), c, A.cx, A.cy);
+        else
             residual_row<T, V>(r0, um, uc, up, fr, (j >= 1) && (j <= A.n - 2), c, A.cx, A.cy, A.d);
-        } else {
-            RT xm[V], xc[V], xp[V], xf[V];
-            copy_as<RT, T, V>(xm, um);
-            copy_as<RT, T, V>(xc, uc);
-            copy_as<RT, T, V>(xp, up);
-            copy_as<RT, T, V>(xf, fr);
-            residual_row<RT, V>(r0, xm, xc, xp, xf, (j >= 1) && (j <= A.n - 2), c, A.dcx, A.dcy, A.dd);
-        }
         if ((j & 1) && j >= j0 + 2) {
             const int J = (j - 1) >> 1;               // coarse row at fine row j-1
-            const RT w2 = lane_prev(r2[V - 1]), w1 = lane_prev(r1[V - 1]), w0 = lane_prev(r0[V - 1]);
-            const RT e2 = lane_next(r2[0]), e1 = lane_next(r1[0]), e0 = lane_next(r0[0]);
+            const T w2 = lane_prev(r2[V - 1]), w1 = lane_prev(r1[V - 1]), w0 = lane_prev(r0[V - 1]);
+            const T e2 = lane_next(r2[0]), e1 = lane_next(r1[0]), e0 = lane_next(r0[0]);
             if (J >= 1 && J <= A.nc - 2) {
                 T* brow = A.bc + (size_t)J * A.Pc;
 #pragma unroll
@@ -506,23 +511,22 @@ __device__ __forceinline__ void restrict_tile(const RestrictArgs<T>& A, int tile
                     if ((i & 1) || !c.cout[e]) continue;
                     const int I = i >> 1;
                     if (I < 1 || I > A.mc - 2) continue;
-                    const RT C = r1[e];
-                    const RT W = e > 0 ? r1[e - 1] : w1;
-                    const RT E = e < V - 1 ? r1[e + 1] : e1;
-                    const RT S = r2[e], N = r0[e];
-                    const RT SW = e > 0 ? r2[e - 1] : w2;
-                    const RT SE = e < V - 1 ? r2[e + 1] : e2;
-                    const RT NW = e > 0 ? r0[e - 1] : w0;
-                    const RT NE = e < V - 1 ? r0[e + 1] : e0;
-                    const RT v =
-                        (fma(RT(4), C, RT(2) * ((W + E) + (S + N))) + ((SW + SE) + (NW + NE))) * RT(0.0625);
-                    brow[I] = (T)v;
+                    const T C = r1[e];
+                    const T W = e > 0 ? r1[e - 1] : w1;
+                    const T E = e < V - 1 ? r1[e + 1] : e1;
+                    const T S = r2[e], N = r0[e];
+                    const T SW = e > 0 ? r2[e - 1] : w2;
+                    const T SE = e < V - 1 ? r2[e + 1] : e2;
+                    const T NW = e > 0 ? r0[e - 1] : w0;
+                    const T NE = e < V - 1 ? r0[e + 1] : e0;
+                    const T v = (fma(T(4), C, T(2) * ((W + E) + (S + N))) + ((SW + SE) + (NW + NE))) * T(0.0625);
+                    brow[I] = v;
                     if (A.uc0 != nullptr) A.uc0[(size_t)J * A.Pc + I] = T(0);
                 }
             }
         }
-        copy<RT, V>(r2, r1);
-        copy<RT, V>(r1, r0);
+        copy<T, V>(r2, r1);
+        copy<T, V>(r1, r0);
         copy<T, V>(um, uc);
         copy<T, V>(uc, up);
     }
