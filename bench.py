@@ -206,11 +206,13 @@ def run_residual_leg(ctx, g, reps=20):
             "achieved_GB/s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 
-def run_mixed_leg(N, ctx, torch, lap, dev, keep=None, reps=3):
+def run_mixed_leg(N, ctx, torch, lap, dev, keep=None, reps=3, others=(1, 3)):
     """Mixed precision vs FP64 multigrid on the N x N grid with the 32-bump
     source: time to a 1e-10 relative residual (median of `reps` graph-replay
-    solves per precision, each grid holding one precision's graph), outer
-    steps / cycles, and the largest difference of the two results."""
+    solves per configuration, each grid holding one configuration's graph),
+    outer steps / cycles, and the largest difference of the two results.
+    "mixed" runs MIXED_INNER FP32 cycles per defect correction; the counts in
+    `others` are timed beside it as "mixed_inner<k>"."""
     pb = W.square_problem(N, seed=2, bumps=True, bump_seed=3)
     psib = torch.as_tensor(pb.psi0, device=dev)
     fb = torch.as_tensor(pb.f, device=dev)
@@ -219,7 +221,7 @@ def run_mixed_leg(N, ctx, torch, lap, dev, keep=None, reps=3):
     for key, prec, inner, alloc in (("fp64", "fp64", 1, lap.LAP_ALLOC_FP64),
                                     ("mixed", "mixed", MIXED_INNER, lap.LAP_ALLOC_MIXED),
                                     *[(f"mixed_inner{k}", "mixed", k, lap.LAP_ALLOC_MIXED)
-                                      for k in (1, 2, 3) if k != MIXED_INNER]):
+                                      for k in others if k != MIXED_INNER]):
         g = ctx.grid(psib, fb, pb.dx, pb.dy, alloc=alloc)
         t, info = timed_solves(g, lambda: g.write(psib), reps, method="mg", precision=prec, inner=inner,
                                tol=1e-10, max_iter=60)
@@ -687,6 +689,8 @@ def main():
     ap.add_argument("--measure-only", action="store_true",
                     help="only measured-mode solves (for profiler runs: no graph replay leg)")
     ap.add_argument("--no-batch", dest="batch", action="store_false", help="skip the ragged-batch leg")
+    ap.add_argument("--mixed-inner", type=int, nargs="*", default=[1, 3],
+                    help="FP32 cycles per correction timed in the mixed leg besides the default")
     ap.add_argument("--mixed-only", action="store_true",
                     help="run only the mixed-vs-FP64 leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--batch-only", action="store_true",
@@ -711,7 +715,7 @@ def main():
     dev = "cuda:0"
     if args.mixed_only or args.batch_only:
         ctx = lap.Context(arena_bytes=16 << 30, device=dev)
-        res = {"mixed": run_mixed_leg(args.size, ctx, torch, lap, dev)} if args.mixed_only else \
+        res = {"mixed": run_mixed_leg(args.size, ctx, torch, lap, dev, others=args.mixed_inner)} if args.mixed_only else \
               {"ragged_batch": run_batch_leg(args, ctx, torch, lap, dev)}
         if args.copy_probe:
             res["copy_probe"] = run_copy_probe(torch, lap, dev)
@@ -745,10 +749,10 @@ def main():
     d.update(run_headline(args, ctx, torch, lap, dev, keep))
     if not args.quick:
         say("mixed", N)
-        d["mixed"] = run_mixed_leg(N, ctx, torch, lap, dev, keep)
+        d["mixed"] = run_mixed_leg(N, ctx, torch, lap, dev, keep, others=args.mixed_inner)
         if N > 4097:
             say("mixed", 4097)
-            d["mixed_4097"] = run_mixed_leg(4097, ctx, torch, lap, dev)
+            d["mixed_4097"] = run_mixed_leg(4097, ctx, torch, lap, dev, others=args.mixed_inner)
         say("sor")
         d["sor"] = run_sor_leg(ctx, torch, lap, dev, sorted({4097, N}))
         d["mg_4097"] = run_mg4097_leg(ctx, torch, lap, dev)
