@@ -50,7 +50,7 @@ import workloads as W  # noqa: E402
 METRIC = "GLUP/s + time to 1e-10 residual (FP32+FP64 refine vs FP64); p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 # FP32 V-cycles per FP64 defect correction in the mixed-precision leg
-MIXED_INNER = 2
+MIXED_INNER = 3
 # HBM bytes per launch of the finest-level kernels (8193^2, f = 0) measured
 # with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by the counts of a
 # 1 GiB stream copy (summaries under profiles/); keyed by kernel class and the
@@ -66,7 +66,7 @@ FINE_LABELS = {
     "pre": "k_fused<double,2,56> pre pass: input norms, 2 RB sweeps, residual, full weighting",
     "two": "k_fused<double,V,36> post pass: bilinear correction, 2 RB sweeps",
 }
-ALL_CLASSES = range(13)
+ALL_CLASSES = range(15)
 KC_RESIDUAL = 8
 
 
@@ -206,7 +206,7 @@ def run_residual_leg(ctx, g, reps=20):
             "achieved_GB/s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 
-def run_mixed_leg(N, ctx, torch, lap, dev, keep=None, reps=3, others=(1, 3)):
+def run_mixed_leg(N, ctx, torch, lap, dev, keep=None, reps=3, others=(1, 2)):
     """Mixed precision vs FP64 multigrid on the N x N grid with the 32-bump
     source: time to a 1e-10 relative residual (median of `reps` graph-replay
     solves per configuration, each grid holding one configuration's graph),
@@ -689,7 +689,7 @@ def main():
     ap.add_argument("--measure-only", action="store_true",
                     help="only measured-mode solves (for profiler runs: no graph replay leg)")
     ap.add_argument("--no-batch", dest="batch", action="store_false", help="skip the ragged-batch leg")
-    ap.add_argument("--mixed-inner", type=int, nargs="*", default=[1, 3],
+    ap.add_argument("--mixed-inner", type=int, nargs="*", default=[1, 2],
                     help="FP32 cycles per correction timed in the mixed leg besides the default")
     ap.add_argument("--mixed-only", action="store_true",
                     help="run only the mixed-vs-FP64 leg and print its JSON (profiling aid; not the benchmark line)")

@@ -186,7 +186,10 @@ lap_status lap_ctx_usage(lap_ctx* ctx, size_t* used, size_t* largest_free);
  * weighting), 11 fused two-sweep pass with the prolongation (post-smoothing),
  * 12 fused two-sweep pass without a transfer (red-black SOR, further
  * smoothing passes), 13 one whole solve of a paper-order method
- * (LAP_JACOBI .. LAP_ADI_LEX; no algorithmic bytes).  Class 3 also holds the mixed loop's fused FP32
+ * (LAP_JACOBI .. LAP_ADI_LEX; no algorithmic bytes), 14 fused four-sweep pass
+ * (a mixed step's FP32 cycle: the level-0 post-smoothing after the bilinear
+ * correction, then the next cycle's pre-smoothing, residual and full
+ * weighting).  Class 3 also holds the mixed loop's fused FP32
  * post-smoothing + FP64 defect pass.  `fine_only` selects the finest-level
  * bucket.
  * lap_ctx_kernel_stats synchronises the stream. */

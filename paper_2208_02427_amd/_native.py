@@ -28,7 +28,7 @@ LAP_ALLOC_FP64, LAP_ALLOC_MIXED, LAP_ALLOC_ADI, LAP_ALLOC_ALL = 1, 2, 4, 7
 
 # kernel classes of lap_ctx_kernel_stats
 KC_SWEEP, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE, KC_ADI_ROWS, KC_ADI_COLS, \
-    KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_TWO_PLAIN, KC_PAPER = range(14)
+    KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_TWO_PLAIN, KC_PAPER, KC_FOUR = range(15)
 
 
 class LapInfo(ctypes.Structure):

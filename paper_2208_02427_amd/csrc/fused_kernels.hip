@@ -39,7 +39,8 @@ void k_fused(SweepArgs<T> A) {
     X(SW_PROBE | SW_RESTRICT | SW_TWO | SW_NORM) X(SW_PROBE | SW_RESTRICT | SW_TWO | SW_NORM | SW_F)  \
     X(SW_PROBE | SW_RESTRICT | SW_NORM) X(SW_PROBE | SW_RESTRICT | SW_NORM | SW_F)                \
     X(SW_PROBE | SW_TWO | SW_NORM) X(SW_PROBE | SW_TWO | SW_NORM | SW_F)                          \
-    X(SW_RDIFF | SW_RESTRICT | SW_TWO | SW_F) X(SW_RDIFF | SW_RESTRICT | SW_F)
+    X(SW_RDIFF | SW_RESTRICT | SW_TWO | SW_F) X(SW_RDIFF | SW_RESTRICT | SW_F)                   \
+    X(SW_FOUR | SW_PROLONG | SW_RESTRICT | SW_RDIFF | SW_F)
 
 template <typename T, int V>
 static hipError_t launch_fused_v(const SweepArgs<T>& a, int flags, hipStream_t s) {
@@ -59,7 +60,7 @@ static hipError_t launch_fused_v(const SweepArgs<T>& a, int flags, hipStream_t s
 template <typename T>
 hipError_t launch_fused(const SweepArgs<T>& a, int flags, hipStream_t s) {
     // the halo must cover every fused stage
-    const int need = ((flags & SW_TWO) ? 4 : 2) + ((flags & (SW_RESTRICT | SW_DEF)) ? 2 : 0);
+    const int need = ((flags & SW_FOUR) ? 8 : (flags & SW_TWO) ? 4 : 2) + ((flags & (SW_RESTRICT | SW_DEF)) ? 2 : 0);
     if (a.tl.H < need) return hipErrorInvalidValue;
     switch (a.tl.V) {
         case 1: return launch_fused_v<T, 1>(a, flags, s);

@@ -161,9 +161,11 @@ __device__ __forceinline__ void fused_step(const SweepArgs<T>& A, FusedRegs<T, V
 
     T o[V], fo[V];
     rb_push<T, V, JP>(R.st[0], d, fd, o, fo, j, A.n, wm, cx, cy, inv_d);
-    if constexpr (NS == 2) {
+#pragma unroll
+    for (int s = 1; s < NS; ++s) {
+        // stage s works two rows behind stage s - 1 (same row parity)
         T o2[V], fo2[V];
-        rb_push<T, V, JP>(R.st[1], o, fo, o2, fo2, j - 2, A.n, wm, cx, cy, inv_d);
+        rb_push<T, V, JP>(R.st[s], o, fo, o2, fo2, j - 2 * s, A.n, wm, cx, cy, inv_d);
         copy<T, V>(o, o2);
         copy<T, V>(fo, fo2);
     }
@@ -288,7 +290,7 @@ __device__ __forceinline__ void fused_turn_full(const SweepArgs<T>& A,
 // south operands swapped in a commutative sum: the values are unchanged.
 template <typename T, int V, int FL>
 __device__ __forceinline__ void fused_tile(const SweepArgs<T>& A0, int tile, int lane) {
-    constexpr int NS = (FL & SW_TWO) ? 2 : 1;
+    constexpr int NS = (FL & SW_FOUR) ? 4 : (FL & SW_TWO) ? 2 : 1;
     constexpr bool RS = (FL & SW_RESTRICT) != 0;
     SweepArgs<T> A = A0;
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;

@@ -179,6 +179,9 @@ enum : int {
     SW_RDIFF = 512,  // with SW_RESTRICT: the residual in difference form, cx ((W - C) + (E - C)) +
                      // cy ((S - C) + (N - C)), accurate for a smooth iterate of large values (an FP32
                      // cycle that continues from a correction)
+    SW_FOUR = 1024,  // fused pass: four sweeps (a cycle's two post-smoothing sweeps after its bilinear
+                     // correction, then the next cycle's two pre-smoothing sweeps, residual and full
+                     // weighting: SW_PROLONG | SW_RESTRICT)
 };
 
 template <typename T>

@@ -270,7 +270,8 @@ size_t coarse_bytes(const LevelGeo& C) {
 enum Part { PART_ALL = 0, PART_HEAD = 1, PART_TAIL = 2 };
 
 enum KClass { KC_SWEEP = 0, KC_SWEEP_PROLONG, KC_RESTRICT, KC_DEFECT, KC_COARSE, KC_FINALIZE,
-              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_TWO_PLAIN, KC_PAPER, KC_COUNT };
+              KC_ADI_ROWS, KC_ADI_COLS, KC_RESIDUAL, KC_SUBTREE, KC_PRE, KC_TWO, KC_TWO_PLAIN, KC_PAPER, KC_FOUR,
+              KC_COUNT };
 
 // Size classes for tilings, by interior node count.
 // One class per factor 4 of interior nodes from 2^12 to 2^24, so each level
@@ -671,15 +672,18 @@ hipError_t enq_sweep(lap_grid* g, int l, const T* in, T* out, const T* f, const 
 }
 
 // Halo, kernel class and tiling of a fused pass with these flags.
-int fused_halo(int flags) { return ((flags & SW_TWO) ? 4 : 2) + ((flags & SW_RESTRICT) ? 2 : 0); }
+int fused_halo(int flags) {
+    return ((flags & SW_FOUR) ? 8 : (flags & SW_TWO) ? 4 : 2) + ((flags & SW_RESTRICT) ? 2 : 0);
+}
 // (two-sweep passes with the prolongation and without any transfer, as red-black
 // SOR runs them, are tuned apart: their best tilings differ)
 int fused_class(int flags) {
     if (flags & SW_PROBE) return KC_RESIDUAL;   // norms only: timed with the residual-norm kernels
+    if (flags & SW_FOUR) return KC_FOUR;
     if (flags & SW_RESTRICT) return KC_PRE;
     return (flags & SW_PROLONG) ? KC_TWO : KC_TWO_PLAIN;
 }
-bool is_fused(int flags) { return (flags & (SW_TWO | SW_RESTRICT)) != 0; }
+bool is_fused(int flags) { return (flags & (SW_TWO | SW_FOUR | SW_RESTRICT)) != 0; }
 
 // Algorithmic bytes per interior node of a sweep or fused pass.
 double sweep_bytes_per_node(int flags, int sz) {
@@ -1197,27 +1201,49 @@ bool postdef_ok(lap_grid* g, const lap_opts& o) {
 // its two buffers the previous cycle left it).  With dp the last cycle stops
 // before its level-0 post-smoothing, described in *dp.  The operations of
 // the cycles after the first are gated by `later` (a step that runs one
-// cycle skips them).  Returns the level-0 buffer (0/1 of g->l32[0].u)
-// holding the correction; dp->in is given the same way, and *first the
-// buffer holding the first cycle's correction.
+// cycle skips them); `one` is the complementary gate (set when all cycles
+// run).  With fusion, a cycle's level-0 post-smoothing pass and the next
+// cycle's level-0 pre-smoothing pass (one two-sweep pass each) run as one
+// four-sweep pass that reads the post pass's input and writes the other
+// buffer; the next cycle is planned on the buffers swapped so that its
+// pre pass reads and writes exactly those.  The post pass it replaces stays,
+// gated by `one`, when it belongs to the first cycle.  Returns the level-0
+// buffer (0/1 of g->l32[0].u) holding the correction; dp->in is given the
+// same way, and *first the buffer holding the first cycle's correction.
 int plan_inner_cycles(lap_grid* g, const lap_opts& o, HierView<float> H, std::vector<Op>& ops,
-                      DeferredPost* dp = nullptr, Ctrl* later = nullptr, int* first = nullptr) {
+                      DeferredPost* dp = nullptr, Ctrl* later = nullptr, Ctrl* one = nullptr,
+                      int* first = nullptr) {
     float* B[2] = {g->l32[0].u[0], g->l32[0].u[1]};
+    const int fb = H.b[0] ? SW_F : 0;
     int base = 0;   // buffer of g->l32[0].u that H.u0[0] is
     int res = 0;
+    long post_at = -1;   // index in ops of the previous cycle's level-0 post pass (a fusable one)
     for (int c = 0; c < o.inner; ++c) {
         const bool last = c == o.inner - 1;
+        std::vector<Op> cyc;
+        int r = 0;
+        bool four = false;
         if (c > 0) {
             H.zero_start0 = false;
-            H.u0[0] = B[res];
-            H.u1[0] = B[1 - res];
-            base = res;
+            if (post_at >= 0) {
+                // on the swapped buffers the cycle's first pass must be the level-0
+                // two-sweep pre pass on exactly the post pass's input and output
+                HierView<float> Hs = H;
+                Hs.u0[0] = B[1 - res];
+                Hs.u1[0] = B[res];
+                r = plan_vcycle<float>(g, Hs, 0, o, false, PART_ALL, cyc, last ? dp : nullptr);
+                const Op& post = ops[(size_t)post_at];
+                four = !cyc.empty() && cyc[0].kind == OP_SWEEP && cyc[0].level == 0 &&
+                       cyc[0].flags == (SW_TWO | SW_RESTRICT | fb) && cyc[0].in == post.in && cyc[0].out == post.out;
+                if (!four) cyc.clear();
+            }
+            base = four ? 1 - res : res;
+            H.u0[0] = B[base];
+            H.u1[0] = B[1 - base];
         }
-        const size_t mark = ops.size();
-        const int r = plan_vcycle<float>(g, H, 0, o, false, PART_ALL, ops, last ? dp : nullptr);
+        if (!four) r = plan_vcycle<float>(g, H, 0, o, false, PART_ALL, cyc, last ? dp : nullptr);
         if (c > 0)
-            for (size_t k = mark; k < ops.size(); ++k) {
-                Op& op = ops[k];
+            for (Op& op : cyc) {
                 op.gate = later;
                 // the residual of level 0's correction in difference form: in the standard
                 // form it adds terms of size 8|e|/h^2 whose FP32 rounding swamps its smooth
@@ -1225,6 +1251,23 @@ int plan_inner_cycles(lap_grid* g, const lap_opts& o, HierView<float> H, std::ve
                 if (op.level == 0 && ((op.kind == OP_SWEEP && (op.flags & SW_RESTRICT)) || op.kind == OP_RESTRICT))
                     op.flags |= SW_RDIFF;
             }
+        if (four) {
+            Op& pre = cyc[0];
+            pre.flags |= SW_FOUR | SW_PROLONG;
+            pre.flags &= ~SW_TWO;
+            pre.ec = ops[(size_t)post_at].ec;
+            if (c == 1)
+                ops[(size_t)post_at].gate = one;   // the first cycle's post pass, when only it runs
+            else
+                ops.erase(ops.begin() + post_at);  // gated by `later` as the four-sweep pass is
+        }
+        ops.insert(ops.end(), cyc.begin(), cyc.end());
+        post_at = -1;
+        if (!last && g->ctx->fuse && !ops.empty()) {
+            const Op& q = ops.back();
+            if (q.kind == OP_SWEEP && q.level == 0 && q.dt == 1 && q.flags == (SW_PROLONG | SW_TWO | fb) && o.nu1 == 2)
+                post_at = (long)ops.size() - 1;
+        }
         res = r == 0 ? base : 1 - base;
         if (c == 0 && first != nullptr) *first = res;
         if (last && dp != nullptr && dp->in >= 0) dp->in = dp->in == 0 ? base : 1 - base;
@@ -1240,6 +1283,7 @@ struct StepGates {
     Ctrl* after_all = nullptr;
     Ctrl* after_one = nullptr;
     Ctrl* later = nullptr;
+    Ctrl* one = nullptr;
     int cycles = -1;
 };
 StepGates step_gates(lap_grid* g, const lap_opts& o, int s) {
@@ -1249,6 +1293,7 @@ StepGates step_gates(lap_grid* g, const lap_opts& o, int s) {
     G.after_all = g->cyc + 2 * p;
     G.after_one = g->cyc + 2 * p + 1;
     G.later = g->cyc + 2 * q;
+    G.one = g->cyc + 2 * q + 1;
     G.cycles = o.inner | (q << 8);
     return G;
 }
@@ -1275,7 +1320,7 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
                 std::vector<Op> prev;
                 H.b[0] = R[1 - par];
                 int e1 = 0;
-                plan_inner_cycles(g, o, H, prev, &dp, nullptr, &e1);
+                plan_inner_cycles(g, o, H, prev, &dp, nullptr, nullptr, &e1);
                 push_op<float>(ops, KEY_HEAD, OP_POSTDEF, 0, kPostDefFlags, pin, pout, R[1 - par], dp.ec, R[par],
                                o.omega, dp.in);
                 ops.back().gate = G.after_all;
@@ -1298,7 +1343,7 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
         }
         if (part == PART_HEAD) return;
         H.b[0] = R[par];
-        plan_inner_cycles(g, o, H, ops, &dp, G.later);
+        plan_inner_cycles(g, o, H, ops, &dp, G.later, G.one);
         return;
     }
     if (o.smoother == LAP_SMOOTH_ZEBRA) {
@@ -1335,7 +1380,7 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
     }
     if (part == PART_HEAD) return;
     HierView<float> H = view32(g);
-    plan_inner_cycles(g, o, H, ops, nullptr, G.later);
+    plan_inner_cycles(g, o, H, ops, nullptr, G.later, G.one);
 }
 
 // Full multigrid start (FP64): the source full-weighted down the hierarchy
@@ -1774,7 +1819,7 @@ lap_status prepare(lap_grid* g, const lap_opts& o, bool init = true) {
     g->e_idx = vcycle_result_index(g->ctx, o);
     if (o.method == LAP_MG && o.precision == LAP_MIXED && o.inner > 1 && !g->l32.empty()) {
         std::vector<Op> dry;   // where the step's first and last FP32 cycles leave the correction
-        g->e_idx = plan_inner_cycles(g, o, view32(g), dry, nullptr, nullptr, &g->e1_idx);
+        g->e_idx = plan_inner_cycles(g, o, view32(g), dry, nullptr, nullptr, nullptr, &g->e1_idx);
     }
     // the two-buffer methods need both buffers equal when they start
     if (g->psi1_stale && o.method != LAP_ADI) {
@@ -3447,7 +3492,7 @@ hipError_t tune_launch(lap_ctx* c, int cls, const Tiling& t, int m, int n, int P
         a.tl = t;
         return launch_sweep<T>(a, flags | (cls == KC_SWEEP_PROLONG ? SW_PROLONG : 0), c->stream);
     }
-    if (cls == KC_PRE || cls == KC_TWO || cls == KC_TWO_PLAIN) {
+    if (cls == KC_PRE || cls == KC_TWO || cls == KC_TWO_PLAIN || cls == KC_FOUR) {
         SweepArgs<T> a{};
         a.uin = (const T*)B.u[0];
         a.uout = (T*)B.u[1];
@@ -3556,8 +3601,9 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
     }
     std::string js = "{\"m\": " + std::to_string(m) + ", \"n\": " + std::to_string(n) + ", \"size_class\": " +
                      std::to_string(sc) + ", \"wave_cap\": " + std::to_string(c->wave_cap) + ", \"best\": [";
-    const char* names[KC_COUNT] = {"sweep",    "sweep_prolong", "restrict", "defect", "coarse", "finalize", "adi_rows",
-                                   "adi_cols", "residual",      "subtree",  "pre",    "two",    "two_plain"};
+    const char* names[KC_COUNT] = {"sweep",    "sweep_prolong", "restrict", "defect", "coarse",    "finalize",
+                                   "adi_rows", "adi_cols",      "residual", "subtree", "pre",      "two",
+                                   "two_plain", "paper",        "four"};
     // the variant each class is timed on: pre-smoothing from zero with the
     // restriction (coarse levels, FP32 level 0), post-smoothing with the
     // prolongation (with and without a right-hand side, as the one-sweep kernel)
@@ -3565,23 +3611,27 @@ extern "C" lap_status lap_autotune(lap_ctx* c, int32_t m, int32_t n, int32_t rep
         if (cls == KC_PRE) return (int)(SW_RESTRICT | SW_TWO | SW_ZERO);
         if (cls == KC_TWO) return (int)(SW_TWO | SW_PROLONG);
         if (cls == KC_TWO_PLAIN) return (int)SW_TWO;
+        if (cls == KC_FOUR) return (int)(SW_FOUR | SW_PROLONG | SW_RESTRICT | SW_RDIFF);
         return 0;
     };
     bool first = true;
     lap_status result = LAP_OK;
     for (int cls : {(int)KC_SWEEP, (int)KC_SWEEP_PROLONG, (int)KC_RESTRICT, (int)KC_RESIDUAL, (int)KC_DEFECT,
-                    (int)KC_PRE, (int)KC_TWO, (int)KC_TWO_PLAIN}) {
+                    (int)KC_PRE, (int)KC_TWO, (int)KC_TWO_PLAIN, (int)KC_FOUR}) {
         for (int dt = 0; dt < 2; ++dt) {
             if ((cls == KC_DEFECT || cls == KC_TWO_PLAIN) && dt == 1) continue;   // FP64 only
+            if (cls == KC_FOUR && dt == 0) continue;                              // FP32 only
             double best = 1e30;
             Cand bc{2, 0, c->wave_cap};
             for (const Cand& cd : cands) {
-                const int H = (cls == KC_PRE || cls == KC_TWO || cls == KC_TWO_PLAIN) ? fused_halo(base_flags(cls)) : 2;
+                const int H = (cls == KC_PRE || cls == KC_TWO || cls == KC_TWO_PLAIN || cls == KC_FOUR)
+                                  ? fused_halo(base_flags(cls))
+                                  : 2;
                 const Tiling t = make_tiling(m, n, cd.V, cd.ty, cd.tgt, H);
                 double total = 0.0;
                 for (int fl0 : {0, (int)SW_F}) {
                     if (fl0 == 0 && cls != KC_SWEEP && cls != KC_TWO && cls != KC_TWO_PLAIN) continue;
-                    if (fl0 == 0 && cls == KC_PRE) continue;
+                    if (fl0 == 0 && (cls == KC_PRE || cls == KC_FOUR)) continue;
                     const int fl = fl0 | base_flags(cls);
                     auto go = [&]() {
                         return dt == 0 ? tune_launch<double>(c, cls, t, m, n, P, Pc, B, fl)

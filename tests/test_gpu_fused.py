@@ -23,7 +23,7 @@ def _run(lap, torch, prob, fuse, sub=-1, tiling=None, **kw):
     if tiling is not None:
         V, ty, tgt = tiling
         for sc in range(8):
-            for cls in range(13):
+            for cls in range(15):
                 for dt in (0, 1):
                     ctx.set_tiling(cls, dt, sc, V, ty, tgt)
     ctx.set_timing(True)

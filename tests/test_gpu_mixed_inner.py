@@ -134,3 +134,32 @@ def test_two_cycle_step_keeps_fp64_smooth_accuracy():
     assert maxabs(um, u64) < 2e-6, maxabs(um, u64)
     g.destroy()
     ctx.close()
+
+
+@pytest.mark.parametrize("m,n", [(257, 193), (513, 257)])
+@pytest.mark.parametrize("inner", [2, 3])
+def test_inner_cycles_fused_vs_unfused_bitwise(m, n, inner):
+    """The fused schedule (the post-smoothing + defect pass, a cycle's level-0
+    post pass merged with the next cycle's pre pass as one four-sweep pass,
+    the in-LDS subtree) against one launch per sweep: 1, 2, 3 steps and a
+    solve to 1e-10 whose last step runs one cycle.  Fields bitwise, with the
+    same step counts; the residual norms agree to rounding (each schedule sums
+    its own tiles' partials)."""
+    torch, lap = need_gpu()
+    psi, f, dx, dy = rand_problem(m, n, 7 * m + inner, dx=1.0 / (m - 1), dy=1.0 / (n - 1), source=True)
+    res = {}
+    for fuse in (False, True):
+        ctx = _ctx(lap, fuse)
+        g = ctx.grid(to_dev(torch, psi), to_dev(torch, f), dx, dy)
+        out = []
+        for k, tol in ((1, 0.0), (2, 0.0), (3, 0.0), (40, 1e-10)):
+            say("inner fused vs unfused", m, n, inner, fuse, k, tol)
+            g.write(to_dev(torch, psi))
+            info = g.solve("mg", precision="mixed", inner=inner, tol=tol, max_iter=k)
+            out.append((info["iterations"], info["rel_res_l2"], g.read().cpu().numpy()))
+        res[fuse] = out
+        g.destroy()
+        ctx.close()
+    for a, b in zip(res[False], res[True]):
+        assert a[0] == b[0] and a[1] == pytest.approx(b[1], rel=1e-12)
+        assert np.array_equal(a[2], b[2])

@@ -21,7 +21,7 @@ def test_solution_bitwise_identical_across_tilings(precision):
         say("tiling", precision, V, ty, tgt)
         ctx = lap.Context(arena_bytes=256 << 20)
         for sc in range(8):
-            for cls in range(13):
+            for cls in range(15):
                 for dt in (0, 1):
                     ctx.set_tiling(cls, dt, sc, V, ty, tgt)
         g = ctx.grid(to_dev(torch, p.psi0), to_dev(torch, p.f), p.dx, p.dy)
