@@ -96,10 +96,13 @@ constexpr int fused_pf() {
 // row test) save the register copies of the rotating pipeline: 14% fewer
 // VALU instructions in the FP64 restricting pass.  Passes that prolong hold
 // the coarse rows as well and would need more registers, costing a wave of
-// occupancy, so they keep the tested turn.
+// occupancy, so they keep the tested turn; the four-sweep pass, bound by
+// vector issue (its four stages rotate 20 rows per step), takes the whole
+// turns anyway (8193^2 FP32: 132 instead of 118 registers, 242 instead of
+// 265 us as tuned).
 template <typename T, int FL>
 constexpr bool fused_full_turns() {
-    return (FL & SW_PROLONG) == 0;
+    return (FL & SW_PROLONG) == 0 || (FL & SW_FOUR) != 0;
 }
 
 template <typename T, int V, int NS, bool RS, int PF>
