@@ -28,7 +28,7 @@ def _ctx(lap, fuse):
 
 
 @pytest.mark.parametrize("m,n", [(257, 193), (129, 65)])
-@pytest.mark.parametrize("inner", [2, 3])
+@pytest.mark.parametrize("inner", [2, 3, 4])
 @pytest.mark.parametrize("fuse", [True, False])
 def test_inner_cycle_steps_vs_oracle(m, n, inner, fuse):
     torch, lap = need_gpu()
@@ -137,7 +137,7 @@ def test_two_cycle_step_keeps_fp64_smooth_accuracy():
 
 
 @pytest.mark.parametrize("m,n", [(257, 193), (513, 257)])
-@pytest.mark.parametrize("inner", [2, 3])
+@pytest.mark.parametrize("inner", [2, 3, 4])
 def test_inner_cycles_fused_vs_unfused_bitwise(m, n, inner):
     """The fused schedule (the post-smoothing + defect pass, a cycle's level-0
     post pass merged with the next cycle's pre pass as one four-sweep pass,
