@@ -163,3 +163,41 @@ def test_inner_cycles_fused_vs_unfused_bitwise(m, n, inner):
     for a, b in zip(res[False], res[True]):
         assert a[0] == b[0] and a[1] == pytest.approx(b[1], rel=1e-12)
         assert np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("m,n,nu1,nu2", [(129, 97, 1, 1), (129, 97, 3, 1), (129, 97, 0, 2), (129, 97, 2, 4),
+                                         (17, 17, 2, 2), (33, 17, 1, 3), (5, 5, 2, 2)])
+@pytest.mark.parametrize("fuse", [True, False])
+def test_inner_cycles_other_schedules(m, n, nu1, nu2, fuse):
+    """Two FP32 cycles per correction with other smoothing counts (one-sweep
+    and sweep-less pre-smoothing, the restrict kernel, a post-smoothing that
+    ends with one sweep), on grids whose whole first cycle is one in-LDS
+    subtree and on a single-level grid: steps 1..3 against the oracle within
+    3x its own FP32 rounding effect, and a converged solve."""
+    torch, lap = need_gpu()
+    psi, f, dx, dy = rand_problem(m, n, 31 * m + n + nu1, dx=1.0 / (m - 1), dy=1.1 / (n - 1), source=True)
+    ctx = _ctx(lap, fuse)
+    g = ctx.grid(to_dev(torch, psi), to_dev(torch, f), dx, dy)
+    lv = omg.hierarchy(m, n, dx, dy)
+    ref, ref64 = psi.copy(), psi.copy()
+    for k in (1, 2, 3):
+        say("inner schedules", m, n, nu1, nu2, fuse, k)
+        g.write(to_dev(torch, psi))
+        info = g.solve("mg", precision="mixed", inner=2, nu1=nu1, nu2=nu2, tol=0.0, max_iter=k)
+        assert info["iterations"] == k
+        omg.mixed_step(ref, f, lv, nu1, nu2, inner=2)
+        r = ogrid.residual(ref64, f, dx, dy)
+        e = np.zeros_like(r)
+        for _ in range(2):
+            omg.vcycle(lv, 0, e, r, nu1, nu2, 1.0, np.float64, "rb")
+        ref64 += e
+        scale = float(np.max(np.abs(ref)))
+        got = maxabs(g.read().cpu().numpy(), ref)
+        assert got <= 3.0 * maxabs(ref, ref64) + 1e-12 * scale, (k, got)
+    g.write(to_dev(torch, psi))
+    info = g.solve("mg", precision="mixed", inner=2, nu1=nu1, nu2=nu2, tol=1e-10, max_iter=60)
+    assert info["status"] == 0
+    r0 = ogrid.norm2(ogrid.residual(psi, f, dx, dy))
+    assert ogrid.norm2(ogrid.residual(g.read().cpu().numpy(), f, dx, dy)) / r0 < 1e-10 * 1.0001
+    g.destroy()
+    ctx.close()
