@@ -49,6 +49,12 @@ import workloads as W  # noqa: E402
 
 METRIC = "GLUP/s + time to 1e-10 residual (FP32+FP64 refine vs FP64); p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+# Relaxation of the red-black multigrid smoother in the "relaxed" leg: the
+# legs above keep the paper's Gauss-Seidel smoother (omega 1); over-relaxed
+# red-black Gauss-Seidel cuts the V(2,2) cycles to 1e-10 on the unit square
+# from 7 to 5 (oracle, 513^2 and 1025^2, with and without a source;
+# anisotropic grids 13 -> 9).
+MG_OMEGA = 1.15
 # FP32 V-cycles per FP64 defect correction timed in the mixed-precision leg
 # (the fastest is reported as "mixed")
 MIXED_INNERS = (1, 2, 3, 4)
@@ -207,14 +213,14 @@ def run_residual_leg(ctx, g, reps=20):
             "achieved_GB/s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 
-def run_mixed_leg(N, ctx, torch, lap, dev, keep=None, reps=3, inners=MIXED_INNERS):
+def run_mixed_leg(N, ctx, torch, lap, dev, keep=None, reps=3, inners=MIXED_INNERS, omega=1.0):
     """Mixed precision vs FP64 multigrid on the N x N grid with the 32-bump
     source: time to a 1e-10 relative residual (median of `reps` graph-replay
     solves per configuration, each grid holding one configuration's graph),
     outer steps / cycles, and the largest difference of the two results.
     Each count of FP32 cycles per defect correction in `inners` is timed
     ("mixed_inner<k>"); "mixed" is the fastest of them (its count in
-    "inner_fp32_cycles")."""
+    "inner_fp32_cycles").  `omega`: the smoother's relaxation."""
     pb = W.square_problem(N, seed=2, bumps=True, bump_seed=3)
     psib = torch.as_tensor(pb.psi0, device=dev)
     fb = torch.as_tensor(pb.f, device=dev)
@@ -225,12 +231,13 @@ def run_mixed_leg(N, ctx, torch, lap, dev, keep=None, reps=3, inners=MIXED_INNER
                                     *[(f"mixed_inner{k}", "mixed", k, lap.LAP_ALLOC_MIXED) for k in inners]):
         g = ctx.grid(psib, fb, pb.dx, pb.dy, alloc=alloc)
         t, info = timed_solves(g, lambda: g.write(psib), reps, method="mg", precision=prec, inner=inner,
-                               tol=1e-10, max_iter=60)
+                               omega=omega, tol=1e-10, max_iter=60)
         res[key] = {"time_to_tol_s": t, "iterations": info["iterations"], "rel_res": info["rel_res_l2"],
                     "status": info["status"], "graph_replay": True}
         if prec == "fp64":
             u64 = g.read()
-            res["residual_kernel_with_f"] = run_residual_leg(ctx, g)
+            if omega == 1.0:
+                res["residual_kernel_with_f"] = run_residual_leg(ctx, g)
         else:
             res[key]["inner_fp32_cycles"] = inner
             res[key]["speedup_over_fp64"] = res["fp64"]["time_to_tol_s"] / t
@@ -276,6 +283,44 @@ def run_mg4097_leg(ctx, torch, lap, dev):
     out = {"time_to_tol_s": t4, "cycles": i4["iterations"],
            "GLUP/s": i4["iterations"] * lup_per_cycle(g4.levels()) / t4 / 1e9}
     g4.destroy()
+    return out
+
+
+def run_relaxed_leg(args, ctx, torch, lap, dev, N):
+    """The large-grid multigrid solves with the over-relaxed red-black
+    smoother (omega MG_OMEGA) beside the Gauss-Seidel one: FP64 to 1e-10 on
+    the N x N headline grid (graph replay, median of 3 per smoother), FP64 vs
+    mixed on the 32-bump problem, and the ragged batch (mixed)."""
+    p = W.square_problem(N, seed=2)
+    psi = torch.as_tensor(p.psi0, device=dev)
+    g = ctx.grid(psi, None, p.dx, p.dy, alloc=lap.LAP_ALLOC_FP64)
+    out = {"omega": MG_OMEGA}
+    for w in (1.0, MG_OMEGA):
+        t, info = timed_solves(g, lambda: g.write(psi), 3, method="mg", precision="fp64", omega=w, tol=1e-10,
+                               max_iter=60)
+        out[f"fp64_w{w:g}"] = {"time_to_tol_s": t, "cycles": info["iterations"], "rel_res": info["rel_res_l2"],
+                               "status": info["status"]}
+    g.destroy()
+    del psi
+    out["mixed"] = run_mixed_leg(N, ctx, torch, lap, dev, inners=args.mixed_inner, omega=MG_OMEGA)
+    if args.batch:
+        probs = W.ragged_batch(count=args.batch_count, lo=33, hi=1025, seed=4)
+        grids = [ctx.grid(torch.as_tensor(q.psi0, device=dev), None, q.dx, q.dy, alloc=lap.LAP_ALLOC_MIXED)
+                 for q in probs]
+        kw = dict(method="mg", precision="mixed", omega=MG_OMEGA, tol=1e-10, max_iter=200)
+        ctx.solve_batch(grids, **kw)
+        for gg, q in zip(grids, probs):
+            gg.write(torch.as_tensor(q.psi0, device=dev))
+        sync()
+        t0 = time.perf_counter()
+        infos = ctx.solve_batch(grids, **kw)
+        sync()
+        t = time.perf_counter() - t0
+        its = [i["iterations"] for i in infos]
+        out["batch_mixed"] = {"seconds": t, "cycles_min": min(its), "cycles_max": max(its),
+                              "all_converged": all(i["status"] == 0 for i in infos)}
+        for gg in grids:
+            gg.destroy()
     return out
 
 
@@ -629,6 +674,21 @@ def compact(line_full, d):
         legs["sor"]["cols"] = "sweeps,s,GLUP/s"
     if "mg_4097" in d:
         legs["mg_4097_ms"] = sig(d["mg_4097"]["time_to_tol_s"] * 1e3)
+    if "relaxed" in d:
+        r = d["relaxed"]
+        w1, w2 = r["fp64_w1"], r[f"fp64_w{r['omega']:g}"]
+        m = r["mixed"]
+        legs["relaxed_w" + f"{r['omega']:g}"] = {
+            "mg_ms": [sig(w1["time_to_tol_s"] * 1e3), sig(w2["time_to_tol_s"] * 1e3)],
+            "cycles": [w1["cycles"], w2["cycles"]],
+            "mixed": {"fp64_ms": sig(m["fp64"]["time_to_tol_s"] * 1e3), "mixed_ms": sig(m["mixed"]["time_to_tol_s"] * 1e3),
+                      "speedup": sig(m["speedup_mixed_over_fp64"], 3), "inner": m["mixed"]["inner_fp32_cycles"],
+                      "steps": [m["fp64"]["iterations"], m["mixed"]["iterations"]],
+                      "err": sig(m["max_abs_mixed_vs_fp64"], 2)}}
+        if "batch_mixed" in r:
+            b = r["batch_mixed"]
+            legs["relaxed_w" + f"{r['omega']:g}"]["batch512_ms"] = sig(b["seconds"] * 1e3)
+            legs["relaxed_w" + f"{r['omega']:g}"]["batch512_cycles"] = [b["cycles_min"], b["cycles_max"]]
     if "chamber" in d:
         c = d["chamber"]
         wb = f"{c['sor_best_omega']:.2f}"
@@ -760,6 +820,8 @@ def main():
         say("sor")
         d["sor"] = run_sor_leg(ctx, torch, lap, dev, sorted({4097, N}))
         d["mg_4097"] = run_mg4097_leg(ctx, torch, lap, dev)
+        say("relaxed smoother")
+        d["relaxed"] = run_relaxed_leg(args, ctx, torch, lap, dev, N)
         say("chamber")
         d["chamber"] = run_chamber_leg(ctx, torch, lap, dev)
         if args.batch:
