@@ -321,6 +321,9 @@ def run_relaxed_leg(args, ctx, torch, lap, dev, N):
                               "all_converged": all(i["status"] == 0 for i in infos)}
         for gg in grids:
             gg.destroy()
+    if args.serve:
+        out["serving"] = run_serving_leg(args, ctx, torch, lap, dev, omega=MG_OMEGA, rates=[1000, 3000],
+                                         baseline_rates=[1000])
     return out
 
 
@@ -523,14 +526,17 @@ def run_batch_leg(args, ctx, torch, lap, dev):
     return out
 
 
-def run_serving_leg(args, ctx, torch, lap, dev):
+def run_serving_leg(args, ctx, torch, lap, dev, omega=1.0, rates=None, baseline_rates=None):
     """Poisson arrivals; m, n log-uniform in [17, 4097] snapped, beta = 1,
     32-bump source, tol 1e-8 or 1e-10; continuous batching (mixed) vs
     one-at-a-time FP64 solves.  Every rate serves warm-up + count requests
     (the request sizes, seeds and tolerances are the same at every rate, only
     the arrival times scale); latency percentiles, solves/s and GLUP/s cover
     the `count` requests after the warm-up, over the span from the first of
-    them arriving to the last finishing."""
+    them arriving to the last finishing.  `omega`: the multigrid smoother's
+    relaxation (served and one-at-a-time solves alike)."""
+    rates = args.rates if rates is None else rates
+    baseline_rates = args.baseline_rates if baseline_rates is None else baseline_rates
     from paper_2208_02427_amd.serving import Job, Server, DeviceBackend, serve_sequential
     warm, count = args.serve_warmup, args.serve_count
     total = warm + count
@@ -571,11 +577,11 @@ def run_serving_leg(args, ctx, torch, lap, dev):
 
     res = {"warmup_requests": warm, "measured_requests": count}
     errs = []
-    for rate in args.rates:
-        say("serving", rate, "requests/s")
+    for rate in rates:
+        say("serving", rate, "requests/s", "omega", omega)
         jobs = [Job(r.rid, r.arrival / rate, r.m, r.n, r.tol, payload=payload[r.rid]) for r in base]
         sync()
-        server = Server(Backend(ctx, precision="mixed"), max_active=256, burst=args.burst,
+        server = Server(Backend(ctx, precision="mixed", omega=omega), max_active=256, burst=args.burst,
                         solo_max_nodes=args.solo_max_nodes)
         stats = server.run(jobs)
         sm = stats_of(jobs)
@@ -588,18 +594,18 @@ def run_serving_leg(args, ctx, torch, lap, dev):
                 if j.rid in sample and j.result is not None:
                     psi0, f, dx, dy = j.payload
                     g = ctx.grid(psi0, f, dx, dy, alloc=lap.LAP_ALLOC_FP64)
-                    g.solve("mg", precision="fp64", tol=j.tol, max_iter=100)
+                    g.solve("mg", precision="fp64", omega=omega, tol=j.tol, max_iter=100)
                     errs.append(float((g.read() - j.result).abs().max().item()))
                     g.destroy()
             res["max_abs_served_vs_fp64_sampled"] = max(errs) if errs else None
             res["sampled_requests"] = len(errs)
         for j in jobs:
             j.result = None
-        if rate in args.baseline_rates:
+        if rate in baseline_rates:
             def solve_one(job):
                 psi0, f, dx, dy = job.payload
                 g = ctx.grid(psi0, f, dx, dy, alloc=lap.LAP_ALLOC_FP64)
-                info = g.solve("mg", precision="fp64", tol=job.tol, max_iter=100)
+                info = g.solve("mg", precision="fp64", omega=omega, tol=job.tol, max_iter=100)
                 lpc[(job.m, job.n)] = lup_per_cycle(g.levels())
                 g.destroy()
                 return info
@@ -649,6 +655,22 @@ def cpu_baseline_leg(headline, keep, N):
     return base, errors
 
 
+def serve_rows(s):
+    """The serving record as one row per rate."""
+    sv = {}
+    for rate, v in s.items():
+        if not isinstance(v, dict) or "batched_mixed" not in v:
+            continue
+        bm = v["batched_mixed"]
+        row = [sig(bm["p50_ms"], 3), sig(bm["p99_ms"], 3), sig(bm["solves_per_s"], 4), sig(bm["GLUP/s"], 3)]
+        if "one_at_a_time_fp64" in v:
+            o = v["one_at_a_time_fp64"]
+            row += [sig(o["p50_ms"], 3), sig(o["p99_ms"], 3), sig(o["solves_per_s"], 4)]
+        sv[rate] = row
+    sv["cols"] = "p50,p99 ms,solves/s,GLUP/s[,FP64 1-by-1 p50,p99,solves/s]"
+    return sv
+
+
 def compact(line_full, d):
     """The per-leg figures that go on the stdout line."""
     legs = {}
@@ -689,6 +711,8 @@ def compact(line_full, d):
             b = r["batch_mixed"]
             legs["relaxed_w" + f"{r['omega']:g}"]["batch512_ms"] = sig(b["seconds"] * 1e3)
             legs["relaxed_w" + f"{r['omega']:g}"]["batch512_cycles"] = [b["cycles_min"], b["cycles_max"]]
+        if "serving" in r:
+            legs["relaxed_w" + f"{r['omega']:g}"]["serve"] = serve_rows(r["serving"])
     if "chamber" in d:
         c = d["chamber"]
         wb = f"{c['sor_best_omega']:.2f}"
@@ -714,19 +738,8 @@ def compact(line_full, d):
                             "zebra_cycles": [b["mg_mixed_zebra"]["cycles_min"], b["mg_mixed_zebra"]["cycles_max"]],
                             "adi20_ms": sig(b["adi"]["seconds"] * 1e3), "adi_GB/s": sig(b["adi"]["alg_GB/s"])}
     if "serving" in d:
-        s = d["serving"]
-        sv = {}
-        for rate, v in s.items():
-            if not isinstance(v, dict) or "batched_mixed" not in v:
-                continue
-            bm = v["batched_mixed"]
-            row = [sig(bm["p50_ms"], 3), sig(bm["p99_ms"], 3), sig(bm["solves_per_s"], 4), sig(bm["GLUP/s"], 3)]
-            if "one_at_a_time_fp64" in v:
-                o = v["one_at_a_time_fp64"]
-                row += [sig(o["p50_ms"], 3), sig(o["p99_ms"], 3), sig(o["solves_per_s"], 4)]
-            sv[rate] = row
-        sv["cols"] = "p50,p99 ms,solves/s,GLUP/s[,FP64 1-by-1 p50,p99,solves/s]"
-        sv["err"] = sig(s.get("max_abs_served_vs_fp64_sampled"), 2)
+        sv = serve_rows(d["serving"])
+        sv["err"] = sig(d["serving"].get("max_abs_served_vs_fp64_sampled"), 2)
         legs["serve"] = sv
     if "errors_vs_exact" in d:
         short = {"fp64_mg_vs_exact": "mg", "bumps_fp64_vs_exact": "bumps_fp64", "bumps_mixed_vs_exact": "bumps_mixed",

@@ -327,11 +327,17 @@ lap_status lap_solve_batch(lap_ctx* ctx, lap_grid* const* grids, int32_t count,
  * (its later launches exit on the device), so each grid's iterate sequence
  * is the same for any `steps`; more steps per tick mean fewer host round
  * trips.  A grid already done is left unchanged and reports done.  tol per
- * grid is taken from lap_grid_set_tol (default 1e-10).  done_host[k] (host
- * array) is set to 1 when grid k has converged or failed. */
+ * grid is taken from lap_grid_set_tol (default 1e-10), the smoother's
+ * relaxation from lap_grid_set_omega (default 1).  done_host[k] (host array)
+ * is set to 1 when grid k has converged or failed. */
 lap_status lap_batch_step(lap_ctx* ctx, lap_grid* const* grids, int32_t count,
                           int32_t precision, int32_t steps, int32_t* done_host, lap_info* infos);
 lap_status lap_grid_set_tol(lap_grid* g, double tol);
+/* Relaxation of the red-black multigrid smoother in the grid's batched steps
+ * (the omega of LAP_MG, as in "Successive over relaxation", Eq. (7)): default 1
+ * (Gauss-Seidel); LAP_EINVAL unless 0 < omega < 2.  Takes effect when the
+ * grid's batched solve starts (after lap_grid_reset or a finished solve). */
+lap_status lap_grid_set_omega(lap_grid* g, double omega);
 /* Restart the stopping test of a grid (r_0 is re-taken at its next step). */
 lap_status lap_grid_reset(lap_grid* g);
 

@@ -312,6 +312,10 @@ class Grid:
     def set_tol(self, tol: float):
         _check(lib().lap_grid_set_tol(self.handle, float(tol)))
 
+    def set_omega(self, omega: float):
+        """Smoother relaxation of the grid's batched steps (lap_batch_step)."""
+        _check(lib().lap_grid_set_omega(self.handle, float(omega)))
+
     def reset(self):
         _check(lib().lap_grid_reset(self.handle))
 

@@ -74,6 +74,7 @@ SIGNATURES = {
     "lap_solve_batch": (_S, [_P, _PS(_P), c_int32, _PS(LapOpts), _PS(LapInfo)]),
     "lap_batch_step": (_S, [_P, _PS(_P), c_int32, c_int32, c_int32, _PS(c_int32), _PS(LapInfo)]),
     "lap_grid_set_tol": (_S, [_P, c_double]),
+    "lap_grid_set_omega": (_S, [_P, c_double]),
     "lap_grid_reset": (_S, [_P]),
     "lap_op_rb_sweep": (_S, [c_int32, c_int32, c_int32, c_int32, c_double, c_double, c_double,
                              _P, _P, _P, c_int32, _P, _P]),

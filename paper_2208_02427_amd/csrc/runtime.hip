@@ -445,6 +445,7 @@ struct lap_grid {
     double* norm_out = nullptr;
     double last_r0 = -1.0;
     double tol = 1e-10;
+    double batch_omega = 1.0;        // smoother relaxation of batched steps (lap_grid_set_omega)
     bool batch_started = false;
     bool batch_done = false;
     double batch_t0 = 0.0;
@@ -2493,6 +2494,13 @@ lap_status lap_grid_set_tol(lap_grid* g, double tol) {
     return LAP_OK;
 }
 
+lap_status lap_grid_set_omega(lap_grid* g, double omega) {
+    if (!g) return fail(LAP_EINVAL, "grid is NULL");
+    if (!(omega > 0.0 && omega < 2.0)) return fail(LAP_EINVAL, "omega must lie in (0, 2)");
+    g->batch_omega = omega;
+    return LAP_OK;
+}
+
 lap_status lap_grid_reset(lap_grid* g) {
     if (!g) return fail(LAP_EINVAL, "grid is NULL");
     g->batch_started = false;
@@ -2967,8 +2975,10 @@ int kclass_of(const Op& op) {
 
 // Build (or fetch) the merged-launch plan of one step of `gs`; steps[k] is
 // grid k's step number (its buffer parity).
+// grid_omega: each grid's smoother relaxation is its own (lap_grid_set_omega)
+// instead of o.omega.
 lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vector<int>& steps, const lap_opts& o,
-                    lap_ctx::Plan** out) {
+                    lap_ctx::Plan** out, bool grid_omega = false) {
     std::string key;
     {
         char buf[96];
@@ -2982,6 +2992,10 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
                                                           : 0);
             snprintf(buf, sizeof buf, "%p:%d%s,", (void*)gs[k], par, gs[k]->pdef ? "d" : "");
             key += buf;
+            if (grid_omega) {
+                snprintf(buf, sizeof buf, "w%.17g,", gs[k]->batch_omega);
+                key += buf;
+            }
         }
     }
     for (size_t k = 0; k < c->plans.size(); ++k)
@@ -2993,7 +3007,9 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
     std::map<long, std::vector<std::pair<lap_grid*, Op>>> groups;
     for (size_t k = 0; k < gs.size(); ++k) {
         std::vector<Op> ops;
-        plan_step(gs[k], o, steps[k], PART_ALL, ops);
+        lap_opts ok = o;
+        if (grid_omega) ok.omega = gs[k]->batch_omega;
+        plan_step(gs[k], ok, steps[k], PART_ALL, ops);
         for (size_t q = 1; q < ops.size(); ++q)
             if (ops[q].key <= ops[q - 1].key)   // merging by key must keep each grid's own order
                 return fail(LAP_EINVAL, "internal error: operation keys out of order");
@@ -3347,6 +3363,7 @@ extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t
         if (!g->batch_started) {
             lap_opts go = o;
             go.tol = g->tol;
+            go.omega = g->batch_omega;
             go.use_graph = 0;
             lap_status st = validate_opts(g, go);
             if (st != LAP_OK) return st;
@@ -3364,7 +3381,7 @@ extern "C" lap_status lap_batch_step(lap_ctx* c, lap_grid* const* grids, int32_t
         // the stopping tolerance lives in each grid's control block, so grids
         // with different tolerances share one plan
         lap_ctx::Plan* p = nullptr;
-        lap_status st = get_plan(c, active, steps, o, &p);
+        lap_status st = get_plan(c, active, steps, o, &p, true);
         if (st != LAP_OK) return st;
         hipError_t e = run_plan(c, p, true);
         if (e != hipSuccess) return fail(LAP_EHIP, std::string("batch launch: ") + hipGetErrorString(e));

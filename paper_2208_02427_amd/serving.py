@@ -276,10 +276,11 @@ class DeviceBackend:
     """liblap backend: grids with the mixed-precision hierarchy only, ticks
     through lap_batch_step.  job.payload = (psi0, f, dx, dy) device tensors."""
 
-    def __init__(self, ctx, precision: str = "mixed", keep_results: bool = False):
+    def __init__(self, ctx, precision: str = "mixed", keep_results: bool = False, omega: float = 1.0):
         from . import LAP_ALLOC_MIXED, LAP_ALLOC_FP64
         self.ctx = ctx
         self.precision = precision
+        self.omega = omega          # relaxation of the multigrid smoother
         self.alloc = LAP_ALLOC_MIXED if precision == "mixed" else LAP_ALLOC_FP64
         self.keep_results = keep_results
 
@@ -306,6 +307,7 @@ class DeviceBackend:
         psi0, f, dx, dy = job.payload
         g = self.ctx.grid(psi0, f, dx, dy, alloc=self.alloc)
         g.set_tol(job.tol)
+        g.set_omega(self.omega)
         return g
 
     def tick(self, grids, steps=1):
@@ -319,7 +321,7 @@ class DeviceBackend:
             raise
 
     def solve_alone(self, g, job):
-        return g.solve("mg", precision=self.precision, tol=job.tol, max_iter=1000)
+        return g.solve("mg", precision=self.precision, omega=self.omega, tol=job.tol, max_iter=1000)
 
     def retire(self, g):
         out = g.read() if self.keep_results else None

@@ -107,3 +107,40 @@ def test_batch_vs_alone_bitwise(precision):
         assert info["status"] == 0 and info["iterations"] == alone["iterations"]
         assert np.array_equal(u, g.read().cpu().numpy())
     ctx.close()
+
+
+def test_batch_step_with_grid_omega():
+    """Continuous batching with lap_grid_set_omega: ticks of a mixed batch
+    whose grids carry omega_s = 1.15 (two of them 1) end each grid where it
+    ends solved alone with its own omega, bitwise; omega outside (0, 2) is
+    refused."""
+    torch, lap = need_gpu()
+    from paper_2208_02427_amd import LapError
+    probs = W.ragged_batch(count=5, lo=33, hi=129, seed=8, bumps=True)
+    ctx = lap.Context(arena_bytes=1 << 30)
+    gs = [ctx.grid(to_dev(torch, q.psi0), None if q.f is None else to_dev(torch, q.f), q.dx, q.dy) for q in probs]
+    omegas = [W_S, 1.0, W_S, W_S, 1.0]
+    for g, w in zip(gs, omegas):
+        g.set_omega(w)
+    for bad in (0.0, 2.0, -1.0):
+        with pytest.raises(LapError):
+            gs[0].set_omega(bad)
+    say("batch step omega", [(q.m, q.n) for q in probs])
+    active, finished, tick = list(range(len(gs))), {}, 0
+    while active:
+        done, infos = ctx.batch_step([gs[k] for k in active], precision="mixed", steps=2)
+        still = []
+        for k, d, info in zip(active, done, infos):
+            if d:
+                finished[k] = (info, gs[k].read().cpu().numpy())
+            else:
+                still.append(k)
+        active = still
+        tick += 1
+        assert tick < 200
+    for k, (q, g, w) in enumerate(zip(probs, gs, omegas)):
+        g.write(to_dev(torch, q.psi0))
+        alone = g.solve("mg", precision="mixed", omega=w, tol=1e-10, max_iter=200)
+        assert finished[k][0]["status"] == 0 and finished[k][0]["iterations"] == alone["iterations"]
+        assert np.array_equal(finished[k][1], g.read().cpu().numpy())
+    ctx.close()
