@@ -143,11 +143,11 @@ typedef struct lap_opts {
                            * coarsest solve, bilinear interpolation of each coarse solution,
                            * one V-cycle per level); it counts as the first iteration, the
                            * stopping test's r_0 is the residual of the incoming field      */
-    int32_t inner;        /* MIXED, red-black smoother, one grid (lap_solve): FP32 V-cycles
-                           * per FP64 defect correction, 1..8 (default 1); the first starts
-                           * from zero, each next from the previous correction.  LAP_EINVAL
-                           * outside 1..8, for inner > 1 with FP64 or zebra smoothing, and
-                           * for inner != 1 in lap_solve_batch                              */
+    int32_t inner;        /* MIXED, red-black smoother (lap_solve, lap_solve_batch): FP32
+                           * V-cycles per FP64 defect correction, 1..8 (default 1); the first
+                           * starts from zero, each next from the previous correction.
+                           * LAP_EINVAL outside 1..8 and for inner > 1 with FP64 or zebra
+                           * smoothing (lap_batch_step always runs one cycle per step)      */
 } lap_opts;
 
 /* Fill *o with the defaults: MG, FP64, omega 1, tol 1e-10, max_iter 100,
@@ -311,8 +311,10 @@ lap_status lap_residual_ex(lap_grid* g, double* l2, double* linf);
 /* ------------------------------------------------------------------ batch */
 
 /* Solve `count` grids of one context together.  Grids are advanced in
- * lockstep: each step runs one cycle (MG) or one iteration (ADI/SOR) of every
- * grid that has not yet met its stopping rule, with the launches of all grids
+ * lockstep: each step runs one cycle (MG; a mixed step its opts->inner FP32
+ * cycles, or one where the step's test predicts one is enough, chosen per
+ * grid on the device) or one iteration (ADI/SOR) of every grid that has not
+ * yet met its stopping rule, with the launches of all grids
  * of one level merged into one persistent launch over a tile table.  Each
  * grid's arithmetic is the same as in a lap_solve_ex of that grid alone.
  * infos[k] (may be NULL) receives grid k's result.  Returns LAP_OK if all

@@ -71,6 +71,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(const BatchItem* items, 
     X(SW_TWO) X(SW_TWO | SW_ZERO) X(SW_TWO | SW_NORM) X(SW_TWO | SW_PROLONG) X(SW_RESTRICT) \
     X(SW_RESTRICT | SW_ZERO) X(SW_RESTRICT | SW_NORM) X(SW_RESTRICT | SW_TWO)              \
     X(SW_RESTRICT | SW_TWO | SW_ZERO) X(SW_RESTRICT | SW_TWO | SW_NORM) X(SW_DEF | SW_PROLONG | SW_TWO)
+// FP32 only: the level-0 passes of the cycles after the first of a mixed step
+// of several cycles (residual in difference form; four-sweep passes)
+#define LAP_BATCH_FUSED_FLAGS32(X) \
+    X(SW_RDIFF | SW_RESTRICT | SW_TWO) X(SW_RDIFF | SW_RESTRICT) X(SW_FOUR | SW_PROLONG | SW_RESTRICT | SW_RDIFF)
 
 template <typename T, int V>
 static hipError_t launch_batch_fused_v(int fl, const BatchItem* items, const int* tmap, int total, int blocks,
@@ -82,8 +86,16 @@ static hipError_t launch_batch_fused_v(int fl, const BatchItem* items, const int
         k_batch_fused<T, (F), V><<<g, b, 0, s>>>(items, tmap, total);     \
         break;
         LAP_BATCH_FUSED_FLAGS(LAP_CASE)
+        default:
+            if constexpr (sizeof(T) == 4) {
+                switch (fl) {
+                    LAP_BATCH_FUSED_FLAGS32(LAP_CASE)
+                    default: return hipErrorInvalidValue;
+                }
+            } else {
+                return hipErrorInvalidValue;
+            }
 #undef LAP_CASE
-        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

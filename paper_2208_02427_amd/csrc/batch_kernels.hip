@@ -86,10 +86,18 @@ __global__ __launch_bounds__(kBlock) void k_batch_restrict(const BatchItem* item
         A.d = (T)it.d;
         A.tl = item_tiling(it);
         const int lt = t - it.tile0;
-        switch (it.V) {
-            case 1: restrict_tile<T, 1>(A, lt, lane); break;
-            case 2: restrict_tile<T, 2>(A, lt, lane); break;
-            default: restrict_tile<T, 4>(A, lt, lane); break;
+        if (it.flags & SW_RDIFF) {
+            switch (it.V) {
+                case 1: restrict_tile<T, 1, true>(A, lt, lane); break;
+                case 2: restrict_tile<T, 2, true>(A, lt, lane); break;
+                default: restrict_tile<T, 4, true>(A, lt, lane); break;
+            }
+        } else {
+            switch (it.V) {
+                case 1: restrict_tile<T, 1>(A, lt, lane); break;
+                case 2: restrict_tile<T, 2>(A, lt, lane); break;
+                default: restrict_tile<T, 4>(A, lt, lane); break;
+            }
         }
     }
 }
@@ -173,8 +181,8 @@ __global__ __launch_bounds__(kFinBlock) void k_batch_finalize(const BatchItem* i
     __shared__ double ss[kFinBlock / 64], sm[kFinBlock / 64];
     for (int k = blockIdx.x; k < count; k += gridDim.x) {
         const BatchItem& it = items[k];
-        if (it.ctrl->done) continue;
-        finalize_block(it.partials, it.ntiles, it.ctrl, nullptr, 0, ss, sm);
+        if (it.ctrl->done || (it.gate != nullptr && it.gate->done)) continue;
+        finalize_step(it.partials, it.ntiles, it.ctrl, nullptr, 0, it.cyc, it.cycles, ss, sm);
         __syncthreads();
     }
 }

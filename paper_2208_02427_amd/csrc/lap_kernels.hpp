@@ -485,7 +485,7 @@ struct BatchItem {
     double cx, cy, d, inv_d, omega, a_off;
     int V, ty, nwin, nchunk, H;
     int ntiles, tile0;       // tiles (or line blocks) of this item; prefix offset in the launch
-    int flags;               // SW_F for sweeps; ADI relaxation form
+    int flags;               // SW_F for sweeps; SW_RDIFF for restrictions; ADI relaxation form
     int parity;              // ADI line parity
     const void* sub;         // BK_SUBTREE: device SubtreeArgs<T> of this grid
     // fused post-smoothing + defect pass (SW_DEF; in / out: the FP64 iterate,
@@ -494,6 +494,13 @@ struct BatchItem {
                              // defect: the FP32 buffer it sets to zero (nullable)
     const double* f64;       // FP64 source (nullable)
     int rowpart;             // norm partials per (window, row block) (see SweepArgs)
+    // finalisation of a mixed step of several FP32 cycles (see launch_finalize):
+    // the item is skipped while gate->done is set (nullable); after the test
+    // the cycle choice goes to the gate pair of cyc (nullable) by `cycles`.
+    // The other kinds take a gated operation's gate as ctrl.
+    const Ctrl* gate;
+    Ctrl* cyc;
+    int cycles;
 };
 
 enum BatchKind { BK_SWEEP = 0, BK_RESTRICT, BK_COARSE, BK_FINALIZE, BK_RESNORM, BK_DEFECT, BK_ADI_ROWS, BK_ADI_COLS,

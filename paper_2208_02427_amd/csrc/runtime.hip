@@ -834,6 +834,9 @@ inline long key_norm_fin(int l) { return 1000 + 100L * l + 1; }
 inline long key_restrict(int l) { return 1000 + 100L * l + 99; }
 constexpr long KEY_COARSE = 20000;
 inline long key_post(int l, int k) { return 30000 + 100L * (99 - l) + k; }
+// the keys of a mixed step's FP32 cycle c (one V-cycle's keys lie below it)
+// are offset by c * KEY_CYCLE
+constexpr long KEY_CYCLE = 40000;
 
 template <typename T>
 void push_op(std::vector<Op>& ops, long key, int kind, int level, int flags, const void* in, void* out,
@@ -1245,6 +1248,7 @@ int plan_inner_cycles(lap_grid* g, const lap_opts& o, HierView<float> H, std::ve
         if (!four) r = plan_vcycle<float>(g, H, 0, o, false, PART_ALL, cyc, last ? dp : nullptr);
         if (c > 0)
             for (Op& op : cyc) {
+                op.key += c * KEY_CYCLE;
                 op.gate = later;
                 // the residual of level 0's correction in difference form: in the standard
                 // form it adds terms of size 8|e|/h^2 whose FP32 rounding swamps its smooth
@@ -1368,15 +1372,16 @@ void plan_mixed_step(lap_grid* g, const lap_opts& o, int s, int e_idx, int part,
     if (part != PART_TAIL) {
         const float* e = first ? nullptr : (e_idx == 0 ? g->l32[0].u[0] : g->l32[0].u[1]);
         push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, pin, pout, g->f64, e, g->l32[0].b, 0.0);
-        if (!first && o.inner > 1) {
+        const bool alt = !first && o.inner > 1;
+        if (alt) {
             // after a step of all cycles its last correction, after a one-cycle step its first
             ops.back().gate = G.after_all;
-            push_op<double>(ops, KEY_HEAD, OP_DEFECT, 0, 0, pin, pout, g->f64, g->l32[0].u[g->e1_idx],
+            push_op<double>(ops, KEY_HEAD + 1, OP_DEFECT, 0, 0, pin, pout, g->f64, g->l32[0].u[g->e1_idx],
                             g->l32[0].b, 0.0);
             ops.back().gate = G.after_one;
         }
-        push_op<double>(ops, KEY_HEAD + 1, OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr, nullptr,
-                        0.0);
+        push_op<double>(ops, KEY_HEAD + (alt ? 2 : 1), OP_FINALIZE, 0, NORM_DEFECT, nullptr, nullptr, nullptr, nullptr,
+                        nullptr, 0.0);
         ops.back().cycles = G.cycles;
     }
     if (part == PART_HEAD) return;
@@ -2822,6 +2827,10 @@ int batch_kind(const Op& op) {
 }
 
 constexpr int kBatchMinRows = 32;
+// Four-sweep passes (halo 10) in plans of many grids: chunks of >= 64 rows
+// (512-grid ragged batch, four FP32 cycles per correction: 12.3 ms with 32,
+// 11.0 with 64, 11.2 with 128; four columns per lane 11.1-11.3)
+constexpr int kBatchFourMinRows = 64;
 constexpr size_t kBatchManyGrids = 4;
 constexpr int kBatchV = 2;
 
@@ -2841,7 +2850,9 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
     it.cbw = g->coarse_bw;
     it.cifast = g->coarse_ifast;
     it.partials = g->partials;
-    it.ctrl = g->ctrl;
+    // a gated operation's items skip at its gate (set, like the control
+    // block's done flag, once the solve has ended)
+    it.ctrl = op.gate != nullptr && op.kind != OP_FINALIZE ? op.gate : g->ctrl;
     it.m = L.m;
     it.n = L.n;
     it.P = L.P;
@@ -2866,7 +2877,10 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
             else
                 t = c->tiling(L.m, L.n, (op.flags & SW_PROLONG) ? KC_SWEEP_PROLONG : KC_SWEEP, op.dt);
             break;
-        case OP_RESTRICT: t = c->tiling(L.m, L.n, KC_RESTRICT, op.dt); break;
+        case OP_RESTRICT:
+            t = c->tiling(L.m, L.n, KC_RESTRICT, op.dt);
+            it.flags = op.flags & SW_RDIFF;
+            break;
         case OP_RESNORM: t = norm_tiling(g->geo[0].m, g->geo[0].n); break;
         case OP_DEFECT:
             t = norm_tiling(g->geo[0].m, g->geo[0].n, NORM_DEFECT);
@@ -2879,7 +2893,14 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
             it.f64 = g->f64;
             it.flags = SW_F;
             break;
-        case OP_FINALIZE: t.ntiles = norm_partials(g->geo[0].m, g->geo[0].n, op.flags); break;
+        case OP_FINALIZE:
+            t.ntiles = norm_partials(g->geo[0].m, g->geo[0].n, op.flags);
+            it.gate = op.gate;
+            if (op.cycles >= 0) {
+                it.cyc = g->cyc;
+                it.cycles = op.cycles;
+            }
+            break;
         case OP_ADI_ROWS:
         case OP_ADI_COLS: {
             const int dir = op.kind == OP_ADI_ROWS ? 0 : 1;
@@ -2918,16 +2939,19 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
     // The table's short row chunks (down to 2 rows) and narrow windows
     // minimise the latency of one grid's small level.  Inside a merged launch
     // over several grids a chunk's halo rows (up to 11 for a fused pass)
-    // weigh more, so plans of 4 or more grids use chunks of >= 32 rows, and
+    // weigh more, so plans of 4 or more grids use chunks of >= 32 rows (>= 64
+    // for four-sweep passes), and
     // every plan of 2 or more grids 2 columns per lane (one launch per key;
     // a 512-grid ragged batch of 33..1025 points a side: 13.8 ms with 4
     // columns per lane and >= 64 rows, 11.7 ms with 2 and >= 32; 15.4 ms with
     // the table's chunks).
     const bool tile_op = (op.kind == OP_SWEEP || op.kind == OP_RESTRICT) && !(op.flags & SW_NORM);
-    if (tile_op && nplan >= kBatchManyGrids)
-        t = make_tiling(L.m, L.n, kBatchV, std::max(t.ty, kBatchMinRows), 0, t.H);
-    else if (tile_op && nplan >= 2)
+    if (tile_op && nplan >= kBatchManyGrids) {
+        const bool four = (op.flags & SW_FOUR) != 0;
+        t = make_tiling(L.m, L.n, kBatchV, std::max(t.ty, four ? kBatchFourMinRows : kBatchMinRows), 0, t.H);
+    } else if (tile_op && nplan >= 2) {
         t = make_tiling(L.m, L.n, kBatchV, t.ty, 0, t.H);
+    }
     it.V = t.V;
     it.ty = t.ty;
     it.nwin = t.nwin;
@@ -2982,8 +3006,8 @@ lap_status get_plan(lap_ctx* c, const std::vector<lap_grid*>& gs, const std::vec
     std::string key;
     {
         char buf[96];
-        snprintf(buf, sizeof buf, "%d:%d:%d:%d:%d:%d:%d:%.17g|", o.method, o.precision, o.smoother, o.nu1, o.nu2,
-                 o.check_every, o.adi_form, o.omega);
+        snprintf(buf, sizeof buf, "%d:%d:%d:%d:%d:%d:%d:%d:%.17g|", o.method, o.precision, o.smoother, o.nu1, o.nu2,
+                 o.check_every, o.adi_form, o.inner, o.omega);
         key = buf;
         for (size_t k = 0; k < gs.size(); ++k) {
             const int par = (o.method == LAP_MG && o.precision == LAP_MIXED)
@@ -3232,7 +3256,6 @@ extern "C" lap_status lap_solve_batch(lap_ctx* c, lap_grid* const* grids, int32_
     if (is_paper_method(o->method))
         return fail(LAP_EINVAL, "the paper-order methods solve one grid at a time (lap_solve)");
     if (o->fmg) return fail(LAP_EINVAL, "the full multigrid start runs on one grid at a time (lap_solve)");
-    if (o->inner != 1) return fail(LAP_EINVAL, "batches take one FP32 cycle per defect correction (inner = 1)");
     const double t0 = now_s();
     for (int k = 0; k < count; ++k) {
         if (!grids[k] || grids[k]->ctx != c) return fail(LAP_EINVAL, "grid does not belong to this context");

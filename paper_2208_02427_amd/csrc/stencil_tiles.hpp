@@ -915,4 +915,48 @@ __device__ __forceinline__ void finalize_block(const double* partials, int ntile
     }
 }
 
+// Safety factor of the one-cycle prediction of a mixed step (the factor of a
+// cycle grows by about 10-15% between steps as the FP32 rounding floor nears).
+constexpr double kOneCycleMargin = 1.5;
+
+// After the test of a mixed step (thread 0; ctrl already updated): the FP32
+// cycles the step runs, as the gate pair cyc[2 p], cyc[2 p + 1].  q_prev,
+// checks0 and ran are the control block's test quantity, finalisation count
+// and cycle count before this test.
+__device__ __forceinline__ void choose_cycles(Ctrl* ctrl, Ctrl* cyc, int cycles, double q_prev, int checks0, int ran) {
+    if (ctrl->done) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cyc[k].done = 1;
+        return;
+    }
+    const int inner = cycles & 255, p = (cycles >> 8) & 1;
+    bool one = false;
+    if (checks0 >= 1 && q_prev > 0.0) {
+        // 1.5 q (q / q_prev)^(1 / ran) < tol, as q / q_prev < (tol / (1.5 q))^ran
+        const double q = ctrl->stop == 0 ? ctrl->rel : ctrl->res_inf;
+        const double x = ctrl->tol / (kOneCycleMargin * q);
+        double pw = 1.0;
+        for (int k = 0; k < ran; ++k) pw *= x;
+        one = q / q_prev < pw;
+    }
+    cyc[2 * p].done = one ? 1 : 0;
+    cyc[2 * p + 1].done = one ? 0 : 1;
+    ctrl->cycles = one ? 1 : inner;
+}
+
+// The stopping test, followed (cyc not null, mode 0) by the cycle choice of
+// a mixed step of several FP32 cycles.
+__device__ __forceinline__ void finalize_step(const double* partials, int ntiles, Ctrl* ctrl, double* out2, int mode,
+                                              Ctrl* cyc, int cycles, double* ss, double* sm) {
+    double q_prev = 0.0;
+    int checks0 = 0, ran = 0;
+    if (cyc != nullptr && threadIdx.x == 0) {
+        q_prev = ctrl->stop == 0 ? ctrl->rel : ctrl->res_inf;
+        checks0 = ctrl->checks;
+        ran = ctrl->cycles;
+    }
+    finalize_block(partials, ntiles, ctrl, out2, mode, ss, sm);
+    if (cyc != nullptr && mode == 0 && threadIdx.x == 0) choose_cycles(ctrl, cyc, cycles, q_prev, checks0, ran);
+}
+
 }  // namespace lap

@@ -110,8 +110,9 @@ def test_inner_cycle_argument_errors():
         say("inner errors", kw)
         with pytest.raises(LapError):
             g.solve("mg", raise_on_fail=True, **kw)
-    with pytest.raises(LapError):
-        ctx.solve_batch([g], method="mg", precision="mixed", inner=2)
+    for kw in (dict(precision="mixed", inner=9), dict(precision="fp64", inner=2)):
+        with pytest.raises(LapError):
+            ctx.solve_batch([g], method="mg", **kw)
     g.destroy()
     ctx.close()
 
