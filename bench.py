@@ -59,6 +59,7 @@ MG_OMEGA = 1.15
 # (the fastest is reported as "mixed")
 MIXED_INNERS = (1, 2, 3, 4)
 BATCH_INNERS = (1, 2, 3, 4)
+BATCH_INNER_MARGIN = 0.03
 # HBM bytes per launch of the finest-level kernels (8193^2, f = 0) measured
 # with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by the counts of a
 # 1 GiB stream copy (summaries under profiles/); keyed by kernel class and the
@@ -318,7 +319,8 @@ def run_relaxed_leg(args, ctx, torch, lap, dev, N):
             its = [i["iterations"] for i in infos]
             r = {"seconds": t, "inner_fp32_cycles": inner, "steps_min": min(its), "steps_max": max(its),
                  "all_converged": all(i["status"] == 0 for i in infos)}
-            if "batch_mixed" not in out or t < out["batch_mixed"]["seconds"]:
+            b = out.get("batch_mixed")
+            if b is None or t < b["seconds"] * (1.0 if b["inner_fp32_cycles"] != 1 else 1.0 - BATCH_INNER_MARGIN):
                 out["batch_mixed"] = r
             out[f"batch_mixed_inner{inner}"] = r
         for gg in grids:
@@ -457,7 +459,9 @@ def run_batch_leg(args, ctx, torch, lap, dev):
     """Ragged batch: 512 grids, m, n log-uniform in [33, 1025] (snapped to
     c*2^k+1), aspect <= 3, beta in [0.5, 2], U[0,1) boundary, f = 0.  The
     mixed solve is timed for each count of FP32 cycles per defect correction
-    in args.batch_inner ("mg_mixed_inner<k>"); "mg_mixed" is the fastest."""
+    in args.batch_inner ("mg_mixed_inner<k>"); "mg_mixed" is the fastest, one
+    cycle per correction unless another count is faster by BATCH_INNER_MARGIN
+    (batch times vary by ~2% between runs)."""
     count = args.batch_count
     probs = W.ragged_batch(count=count, lo=33, hi=1025, seed=4)
     grids = [ctx.grid(torch.as_tensor(p.psi0, device=dev), None, p.dx, p.dy,
@@ -483,7 +487,7 @@ def run_batch_leg(args, ctx, torch, lap, dev):
             r["GLUP/s"] = sum(k * l for k, l in zip(its, lpc)) / t / 1e9
             r["cycles_min"], r["cycles_max"] = min(its), max(its)
         out[f"mg_mixed_inner{inner}"] = r
-        if best is None or t < best[0]:
+        if best is None or t < best[0] * (1.0 if best[1] != 1 else 1.0 - BATCH_INNER_MARGIN):
             best = (t, inner, its, mkw)
     t, best_inner, its, mkw = best
     out["mg_mixed"] = dict(out[f"mg_mixed_inner{best_inner}"])
