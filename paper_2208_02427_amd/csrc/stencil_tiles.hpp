@@ -533,6 +533,12 @@ __device__ __forceinline__ void restrict_tile(const RestrictArgs<T>& A, int tile
 }
 
 // ------------------------------------------------------------------ residual
+// Rows in the residual kernel's ring (see residual_tile).  8193^2 FP64, the
+// canonical 18-row chunks, HIP events: f = 0 106 us with two rows ahead, 95 us
+// with a ring of 6 (66 registers, 7 waves per SIMD), 99-104 with 8 or 9; with
+// a source 185 -> 178 us.
+constexpr int kResRing = 6;
+
 template <typename T, int V>
 __device__ __forceinline__ void residual_tile(const ResidualArgs<T>& A, int tile, int lane) {
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
@@ -540,22 +546,21 @@ __device__ __forceinline__ void residual_tile(const ResidualArgs<T>& A, int tile
     const int j0 = 1 + chunk * A.tl.ty;
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
 
-    T um[V], uc[V], up[V], q1[V], q2[V], fr[V], fq1[V], fq2[V], r[V];
+    // A ring of R rows: row q of u sits in slot (q - j0 + 1) % R and is
+    // loaded R - 2 rows before its first use, row q of f in slot (q - j0) % R,
+    // R rows ahead.  The row loop is unrolled by R, so every slot index is a
+    // compile-time constant (no register copies that would wait for a load),
+    // and the loads are unconditional (rows past the chunk are clamped to its
+    // last neighbour row and never used), so the compiler counts them exactly.
+    constexpr int R = kResRing;
+    T u[R][V], fq[R][V], r[V];
     double s2 = 0.0, mx = 0.0;
-    load_row<T, V>(um, A.u, j0 - 1, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(uc, A.u, j0, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(q1, A.u, j0 + 1, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(q2, A.u, j0 + 2, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(fq1, A.f, j0, A.n, A.P, c.i0, c.vin);
-    load_row<T, V>(fq2, A.f, j0 + 1, A.n, A.P, c.i0, c.vin);
-    for (int j = j0; j <= j1; ++j) {
-        copy<T, V>(up, q1);
-        copy<T, V>(fr, fq1);
-        copy<T, V>(q1, q2);
-        copy<T, V>(fq1, fq2);
-        if (j + 3 <= j1 + 1) load_row<T, V>(q2, A.u, j + 3, A.n, A.P, c.i0, c.vin);
-        if (j + 2 <= j1) load_row<T, V>(fq2, A.f, j + 2, A.n, A.P, c.i0, c.vin);
-        residual_row<T, V>(r, um, uc, up, fr, true, c, A.cx, A.cy, A.d);
+#pragma unroll
+    for (int k = 0; k < R; ++k) load_row<T, V>(u[k], A.u, min(j0 - 1 + k, j1 + 1), A.n, A.P, c.i0, c.vin);
+#pragma unroll
+    for (int k = 0; k < R; ++k) load_row<T, V>(fq[k], A.f, min(j0 + k, j1), A.n, A.P, c.i0, c.vin);
+    auto row = [&](int k, int j) {
+        residual_row<T, V>(r, u[k], u[(k + 1) % R], u[(k + 2) % R], fq[k], true, c, A.cx, A.cy, A.d);
         if (A.r != nullptr) store_row<T, V>(A.r, r, j, A.P, c);
         if (A.partials != nullptr) {
 #pragma unroll
@@ -566,8 +571,16 @@ __device__ __forceinline__ void residual_tile(const ResidualArgs<T>& A, int tile
                 mx = fmax(mx, fabs(v));
             }
         }
-        copy<T, V>(um, uc);
-        copy<T, V>(uc, up);
+    };
+    for (int jb = j0; jb <= j1; jb += R) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int j = jb + k;
+            if (j <= j1) row(k, j);
+            // slot k of u (row j - 1) and of f (row j) are free now
+            load_row<T, V>(u[k], A.u, min(j - 1 + R, j1 + 1), A.n, A.P, c.i0, c.vin);
+            load_row<T, V>(fq[k], A.f, min(j + R, j1), A.n, A.P, c.i0, c.vin);
+        }
     }
     if (A.partials != nullptr) {
         const double s = wave_sum(s2);
