@@ -594,57 +594,65 @@ __device__ __forceinline__ void residual_tile(const ResidualArgs<T>& A, int tile
 
 // ---------------------------------------------------- FP64 defect correction
 template <int V>
-__device__ __forceinline__ void defect_load(double (&x)[V], const DefectArgs& A, int j, const Cols<V>& c) {
-    load_row<double, V>(x, A.psi_in, j, A.n, A.P, c.i0, c.vin);
-    if (A.e != nullptr && c.vin && j >= 0 && j < A.n) {
-        float ev[V];
-        ldv<float, V>(ev, A.e + (size_t)j * A.P + c.i0);
-#pragma unroll
-        for (int e = 0; e < V; ++e) x[e] = x[e] + (double)ev[e];
-    }
-}
-
-template <int V>
 __device__ __forceinline__ void defect_tile(const DefectArgs& A, int tile, int lane) {
     const int win = tile % A.tl.nwin, chunk = tile / A.tl.nwin;
     const Cols<V> c(win, lane, A.m, A.P, A.tl.H);
     const int j0 = 1 + chunk * A.tl.ty;
     const int j1 = min(j0 + A.tl.ty - 1, A.n - 2);
 
-    double um[V], uc[V], up[V], q1[V], q2[V], fr[V], fq1[V], fq2[V], r[V];
-    float r32[V];
+    // The ring of residual_tile: row q of psi (and of the FP32 correction e)
+    // in slot (q - j0 + 1) % R, of f in slot (q - j0) % R.  e is added to a
+    // row when the row first enters the stencil (one iteration before it is
+    // the centre row), not right after its load, so the loads ahead are not
+    // waited for.
+    constexpr int R = kResRing;
+    double u[R][V], fq[R][V], r[V];
+    float ev[R][V], r32[V];
     double s2 = 0.0, mx = 0.0;
-    defect_load<V>(um, A, j0 - 1, c);
-    defect_load<V>(uc, A, j0, c);
-    defect_load<V>(q1, A, j0 + 1, c);
-    defect_load<V>(q2, A, j0 + 2, c);
-    load_row<double, V>(fq1, A.f, j0, A.n, A.P, c.i0, c.vin);
-    load_row<double, V>(fq2, A.f, j0 + 1, A.n, A.P, c.i0, c.vin);
-    for (int j = j0; j <= j1; ++j) {
-        copy<double, V>(up, q1);
-        copy<double, V>(fr, fq1);
-        copy<double, V>(q1, q2);
-        copy<double, V>(fq1, fq2);
-        if (j + 3 <= j1 + 1) defect_load<V>(q2, A, j + 3, c);
-        if (j + 2 <= j1) load_row<double, V>(fq2, A.f, j + 2, A.n, A.P, c.i0, c.vin);
-        residual_row<double, V>(r, um, uc, up, fr, true, c, A.cx, A.cy, A.d);
-        if (A.psi_out != A.psi_in || A.e != nullptr) store_row<double, V>(A.psi_out, uc, j, A.P, c);
+    auto load_u = [&](int k, int q) {
+        load_row<double, V>(u[k], A.psi_in, q, A.n, A.P, c.i0, c.vin);
+        load_row<float, V>(ev[k], A.e, q, A.n, A.P, c.i0, c.vin);
+    };
+    auto add_e = [&](int k) {
+        if (A.e != nullptr) {
 #pragma unroll
-        for (int e = 0; e < V; ++e) r32[e] = (float)r[e];
-        store_row<float, V>(A.rhs, r32, j, A.P, c);
-        if (A.ezero != nullptr) {
-            float z[V];
-            zero<float, V>(z);
-            store_row<float, V>(A.ezero, z, j, A.P, c);
+            for (int e = 0; e < V; ++e) u[k][e] = u[k][e] + (double)ev[k][e];
         }
+    };
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            if (!c.cout[e]) continue;
-            s2 = fma(r[e], r[e], s2);
-            mx = fmax(mx, fabs(r[e]));
+    for (int k = 0; k < R; ++k) load_u(k, min(j0 - 1 + k, j1 + 1));
+#pragma unroll
+    for (int k = 0; k < R; ++k) load_row<double, V>(fq[k], A.f, min(j0 + k, j1), A.n, A.P, c.i0, c.vin);
+    add_e(0);
+    add_e(1);
+    for (int jb = j0; jb <= j1; jb += R) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int j = jb + k;
+            if (j <= j1) {
+                add_e((k + 2) % R);
+                const double (&uc)[V] = u[(k + 1) % R];
+                residual_row<double, V>(r, u[k], uc, u[(k + 2) % R], fq[k], true, c, A.cx, A.cy, A.d);
+                if (A.psi_out != A.psi_in || A.e != nullptr) store_row<double, V>(A.psi_out, uc, j, A.P, c);
+#pragma unroll
+                for (int e = 0; e < V; ++e) r32[e] = (float)r[e];
+                store_row<float, V>(A.rhs, r32, j, A.P, c);
+                if (A.ezero != nullptr) {
+                    float z[V];
+                    zero<float, V>(z);
+                    store_row<float, V>(A.ezero, z, j, A.P, c);
+                }
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    if (!c.cout[e]) continue;
+                    s2 = fma(r[e], r[e], s2);
+                    mx = fmax(mx, fabs(r[e]));
+                }
+            }
+            // slot k of psi (row j - 1) and of f (row j) are free now
+            load_u(k, min(j - 1 + R, j1 + 1));
+            load_row<double, V>(fq[k], A.f, min(j + R, j1), A.n, A.P, c.i0, c.vin);
         }
-        copy<double, V>(um, uc);
-        copy<double, V>(uc, up);
     }
     const double s = wave_sum(s2);
     const double m2 = wave_max(mx);
