@@ -2940,11 +2940,10 @@ BatchItem make_item(lap_grid* g, const Op& op, const lap_opts& o, size_t nplan) 
     // minimise the latency of one grid's small level.  Inside a merged launch
     // over several grids a chunk's halo rows (up to 11 for a fused pass)
     // weigh more, so plans of 4 or more grids use chunks of >= 32 rows (>= 64
-    // for four-sweep passes), and
-    // every plan of 2 or more grids 2 columns per lane (one launch per key;
-    // a 512-grid ragged batch of 33..1025 points a side: 13.8 ms with 4
-    // columns per lane and >= 64 rows, 11.7 ms with 2 and >= 32; 15.4 ms with
-    // the table's chunks).
+    // for four-sweep passes), and every plan of 2 or more grids 2 columns per
+    // lane (one launch per key; a 512-grid ragged batch of 33..1025 points a
+    // side: 13.8 ms with 4 columns per lane and >= 64 rows, 11.7 ms with 2 and
+    // >= 32; 15.4 ms with the table's chunks).
     const bool tile_op = (op.kind == OP_SWEEP || op.kind == OP_RESTRICT) && !(op.flags & SW_NORM);
     if (tile_op && nplan >= kBatchManyGrids) {
         const bool four = (op.flags & SW_FOUR) != 0;
