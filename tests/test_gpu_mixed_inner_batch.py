@@ -82,3 +82,27 @@ def test_batch_inner_cycles_with_relaxed_smoother():
     say("batch inner omega", [(q.m, q.n) for q in probs])
     _batch_vs_alone(torch, lap, probs, True, method="mg", precision="mixed", inner=3, omega=1.15, tol=1e-10,
                     max_iter=60)
+
+
+@pytest.mark.parametrize("max_iter", [1, 2, 3])
+def test_batch_inner_cycles_stopped_by_max_iter(max_iter):
+    """Grids that reach max_iter before the tolerance stop with LAP_ENOTCONV
+    (their gates set like a converged grid's, so their later launches exit),
+    each exactly where it stops alone with the same limit."""
+    torch, lap = need_gpu()
+    probs = W.ragged_batch(count=8, lo=33, hi=257, seed=14, bumps=True)
+    say("batch inner max_iter", max_iter)
+    ctx = lap.Context(arena_bytes=1 << 30)
+    gs = _grids(torch, ctx, probs)
+    kw = dict(method="mg", precision="mixed", inner=3, tol=1e-10, max_iter=max_iter)
+    infos = ctx.solve_batch(gs, **kw)
+    mix = [g.read().cpu().numpy() for g in gs]
+    for q, g, info, u in zip(probs, gs, infos, mix):
+        g.write(to_dev(torch, q.psi0))
+        alone = g.solve(**kw)
+        assert info["status"] == alone["status"] and info["iterations"] == alone["iterations"], (q.m, q.n)
+        assert info["rel_res_l2"] == alone["rel_res_l2"], (q.m, q.n)
+        assert np.array_equal(u, g.read().cpu().numpy()), (q.m, q.n)
+    if max_iter < 3:
+        assert all(i["status"] != 0 for i in infos)
+    ctx.close()
